@@ -1,0 +1,266 @@
+/*
+ * itn.h -- C ABI of libitn, a gfx950 (MI355X) implementation of the hot path
+ * of two-site DMRG: the effective-Hamiltonian matvec H_eff*psi in dense and
+ * quantum-number (QN) block-sparse form, the environment update, the labelled
+ * contraction it is built from, and a sweep driver around them.
+ *
+ * Conventions shared by every call
+ *  - Every call returns an itn_status and never throws.  Arguments are
+ *    validated before any device work is queued; on a validation error no
+ *    output is written.  itn_last_error() returns a message for the last
+ *    failing call on a handle.
+ *  - Tensors are row-major in the index order the call states (last index
+ *    fastest).  Device data is caller-owned: the library never frees it and
+ *    keeps no pointer to it after a call returns.
+ *  - Launches are asynchronous and ordered on the hip stream passed in
+ *    (NULL = the null stream).  Faults of queued kernels surface as
+ *    ITN_E_HIP at the next call that synchronises, or at itn_sync().
+ *  - The library owns its workspace (device scratch reused across calls and
+ *    grown on demand), its QN plans and their captured hipGraphs.  A handle is
+ *    not thread-safe; calls on one handle are serialised by the caller.
+ *
+ * Notation (the paper's MPS formula in Sec. 7.3, the operator element
+ * convention op[s', s] of the hard-core boson example in Sec. 8.3):
+ *   MPS site  A[a_{i-1}, s, a_i]           MPO site  W[m_{i-1}, m_i, s', s]
+ *   left env  L[a', m, a]                   right env R[b', m, b]
+ *   two-site  psi[a, s1, s2, b]
+ *   (H_eff psi)[a', s1', s2', b'] =
+ *      sum L[a', m0, a] W1[m0, m1, s1', s1] W2[m1, m2, s2', s2] R[b', m2, b] psi[a, s1, s2, b]
+ * This is the local problem of the DMRG algorithm of Sec. 7.2 ("forming the
+ * environment tensors and diagonalizing the local effective Hamiltonian");
+ * the contraction strategy of Sec. 9.4 (permute to matrices, then GEMM) is
+ * replaced here by MFMA kernels with the permutations folded into their
+ * address maps.
+ */
+#ifndef ITN_H
+#define ITN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ITN_OK = 0,
+  ITN_E_ARG = 1,           /* null pointer, bad enum, bad count                         */
+  ITN_E_SHAPE = 2,         /* extents inconsistent between operands                     */
+  ITN_E_LABEL = 3,         /* labels repeated, or output labels != uncontracted labels  */
+  ITN_E_ARROW = 4,         /* contracted QN indices with equal arrows (Sec. 8.2)        */
+  ITN_E_FLUX = 5,          /* a block violating the flux rule, or flux mismatch (Sec. 8)*/
+  ITN_E_DTYPE = 6,         /* dtype / precision combination not supported               */
+  ITN_E_WORKSPACE = 7,     /* workspace allocation failed                               */
+  ITN_E_HIP = 8,           /* a HIP / rocSOLVER call failed                             */
+  ITN_E_NOT_CONVERGED = 9, /* eigensolver stopped above its tolerance (result kept)     */
+  ITN_E_UNSUPPORTED = 10,  /* valid request this build does not implement               */
+  ITN_E_NODEVICE = 11      /* compute call on a host-only handle                        */
+} itn_status;
+
+typedef enum { ITN_F64 = 0, ITN_F32 = 1, ITN_BF16 = 2 } itn_dtype; /* storage type */
+
+/* Operand precision of the matrix-core contractions.  Accumulation is FP64
+ * for ITN_P_F64 and FP32 otherwise; every operand is rounded to this type
+ * before it enters an MFMA tile. */
+typedef enum { ITN_P_F64 = 0, ITN_P_F32 = 1, ITN_P_BF16 = 2 } itn_prec;
+
+typedef enum { ITN_LEFT = 0, ITN_RIGHT = 1 } itn_dir;
+
+typedef struct itn_handle itn_handle;
+typedef struct itn_plan itn_plan;
+typedef struct itn_mps itn_mps;
+typedef struct itn_mpo itn_mpo;
+
+/* One QN index (Sec. 8.2): an ordered list of sectors, each a QN of nq
+ * integer components and a dimension, and an arrow.  Host memory, read
+ * during the call only.  Sectors with equal QNs may repeat. */
+typedef struct {
+  int32_t nsec;
+  int32_t nq;
+  const int32_t* qn;  /* nsec*nq, sector-major */
+  const int32_t* dim; /* nsec */
+  int8_t arrow;       /* +1 Out (QNs add to the flux), -1 In (subtract) */
+} itn_space;
+
+/* A tensor argument.
+ *  dense   : nblocks == 0; dims[rank] gives the extents; data row-major.
+ *  QN      : space[rank] gives the indices; blocks are the sector tuples
+ *            block_sec[nblocks*rank] (0-based), sorted lexicographically with
+ *            the first index most significant; block b starts at element
+ *            block_off[b] of data and is row-major within itself; flux[nq] is
+ *            the tensor's flux.  (Sec. 9.2 keeps one array plus a
+ *            block->offset map; this layout fixes that map.)
+ *  label   : integer index labels, used by itn_contract only (Sec. 9.1:
+ *            equal labels are contracted, the rest survive).
+ *  data    : device pointer (host pointer where a call says so). */
+typedef struct {
+  int32_t rank;
+  const int64_t* dims;
+  const int32_t* label;
+  const itn_space* space;
+  itn_dtype dtype;
+  void* data;
+  int64_t nblocks;
+  const int32_t* block_sec;
+  const int64_t* block_off;
+  const int32_t* flux;
+} itn_tensor;
+
+/* ---------------------------------------------------------------- handle */
+
+/* Create a handle on HIP device `device`.  device = -1 gives a host-only
+ * handle that can validate arguments and build QN plans but returns
+ * ITN_E_NODEVICE from any call that would launch work. */
+itn_status itn_create(itn_handle** h, int device);
+itn_status itn_destroy(itn_handle* h);
+const char* itn_last_error(const itn_handle* h);
+/* Wait for all work queued by the library on `hip_stream`; reports faults. */
+itn_status itn_sync(itn_handle* h, void* hip_stream);
+/* Library version string (static storage). */
+const char* itn_version(void);
+
+/* --------------------------------------------------------------- contract */
+
+/* C = A * B over labels (the product operator of Sec. 4 with the label
+ * interface of Sec. 9.1): labels shared by A and B are summed; C's labels
+ * must be exactly the remaining ones, in any order (the caller fixes the
+ * output order).  No shared label is an outer product, all shared (rank-0
+ * C) an inner product.  Dense operands only; dtypes F64 or F32 for A, B, C
+ * (ITN_P_BF16 rounds operands to bf16).  Errors: ITN_E_LABEL,
+ * ITN_E_SHAPE, ITN_E_DTYPE. */
+itn_status itn_contract(itn_handle* h, const itn_tensor* A, const itn_tensor* B, itn_tensor* C,
+                        itn_prec prec, void* hip_stream);
+
+/* ------------------------------------------------------------ dense H_eff */
+
+/* out = H_eff * psi for nv vectors (dense).
+ *  L   [chi_l, w, chi_l]   device, F64 / F32 / BF16
+ *  W1  [w, w, d, d]        HOST, F64 (the MPO site tensors are tiny; the
+ *  W2  [w, w, d, d]        HOST, F64  library derives per-pair tables)
+ *  R   [chi_r, w, chi_r]   device, F64 / F32 / BF16
+ *  psi [chi_l, d, d, chi_r] device, F64 / F32: nv vectors stored one after
+ *       another (vector stride chi_l*d*d*chi_r elements)
+ *  out same shape and stride as psi, F64 / F32, must not alias psi.
+ * The contraction order is L first, then W1 W2 (fused into the first
+ * stage's epilogue when w*d*d <= 48), then R.  Operands whose dtype differs
+ * from `prec` are converted in workspace each call; pass L and R already in
+ * the compute type to avoid it.  Errors: ITN_E_SHAPE, ITN_E_DTYPE, ITN_E_ARG. */
+itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
+                          const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
+                          int32_t nv, itn_tensor* out, itn_prec prec, void* hip_stream);
+
+/* Bytes of library workspace itn_heff_apply uses for these extents. */
+itn_status itn_heff_workspace_size(itn_handle* h, int64_t chi_l, int64_t chi_r, int32_t d,
+                                   int32_t w, int32_t nv, itn_prec prec, size_t* bytes);
+
+/* -------------------------------------------------------------- QN H_eff */
+
+/* Build the plan of a block-sparse H_eff*psi (Sec. 8, Sec. 9.4): from the
+ * sector tables of L[a':Out, m:In, a:In], W1/W2[m_in:Out, m_out:In, s':Out,
+ * s:In], R[b':In, m:Out, b:Out] and psi[a:Out, s1:Out, s2:Out, b:In] it
+ * enumerates the allowed blocks by the flux rule, checks that every given
+ * block is allowed (ITN_E_FLUX) and that contracted indices have opposite
+ * arrows and equal sectors (ITN_E_ARROW, ITN_E_SHAPE), groups the block
+ * products by contracted sector pair, and fixes the order in which
+ * contributions to one output block are summed.  Integer host work only: a
+ * host-only handle may plan.  W1/W2 data are HOST F64 dense [w,w,d,d].
+ * The plan stores copies of everything it needs. */
+itn_status itn_qn_heff_plan(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
+                            const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
+                            int32_t nv, itn_prec prec, itn_plan** plan);
+itn_status itn_plan_destroy(itn_plan* plan);
+
+/* Plan queries (host).  Output block structure of H_eff*psi: the sector
+ * tuples and offsets (same layout as itn_tensor), and the work figures. */
+typedef struct {
+  int64_t out_nblocks;     /* number of output blocks (equals psi's)              */
+  int64_t out_elems;       /* elements per vector                                 */
+  int64_t n_pairs_stage1;  /* block pairs L x psi                                 */
+  int64_t n_groups_stage1; /* GEMM groups after combining by (q_a, q_m0)          */
+  int64_t n_pairs_stage4;  /* block pairs Z x R                                   */
+  int64_t n_tiles;         /* work items of the grouped launches                  */
+  double flops;            /* 2*M*N*K summed over contributing block products, x nv */
+} itn_plan_info;
+itn_status itn_plan_query(const itn_plan* plan, itn_plan_info* info);
+/* Copy the output block table: block_sec[out_nblocks*4], block_off[out_nblocks]. */
+itn_status itn_plan_out_blocks(const itn_plan* plan, int32_t* block_sec, int64_t* block_off);
+
+/* Apply a plan.  Tensors must carry the same sector tables and block lists
+ * the plan was built from (checked by signature: ITN_E_SHAPE otherwise);
+ * data pointers may change between calls.  psi/out hold nv vectors at stride
+ * out_elems.  The first call on a stream captures the launches into a
+ * hipGraph that later calls replay. */
+itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* plan, const itn_tensor* L,
+                             const itn_tensor* R, const itn_tensor* psi, itn_tensor* out,
+                             void* hip_stream);
+
+/* ------------------------------------------------------- environment step */
+
+/* One environment step (Sec. 7.2, "forming the environment tensors").
+ *  dir = ITN_LEFT :  E_out[a', m', a] = sum E[a'', m, a'''] A[a'', s', a'] W[m, m', s', s] A[a''', s, a]
+ *  dir = ITN_RIGHT:  E_out[b', m, b]  = sum A[b', s', b''] W[m, m', s', s] A[b, s, b'''] E[b'', m', b''']
+ *  E [chi, w, chi] device; A [chi_l, d, chi_r] device; W [w, w, d, d] HOST F64;
+ *  E_out device.  Dense; dtypes F64 / F32 (E, A, E_out). */
+itn_status itn_env_update(itn_handle* h, const itn_tensor* E, const itn_tensor* A,
+                          const itn_tensor* W, itn_dir dir, itn_tensor* E_out, itn_prec prec,
+                          void* hip_stream);
+
+/* ------------------------------------------------------------ DMRG sweeps */
+
+/* MPO of N sites, all with the same w and d: W_host holds N tensors
+ * [w, w, d, d] (F64) back to back.  Lower-triangular boundary convention:
+ * the left boundary selects channel w-1, the right boundary channel 0. */
+itn_status itn_mpo_create(itn_handle* h, int32_t N, int32_t w, int32_t d, const double* W_host,
+                          itn_mpo** mpo);
+itn_status itn_mpo_destroy(itn_mpo* mpo);
+
+/* MPS of N sites (F64, device-resident inside the object).  bond[N+1] gives
+ * the link dimensions (bond[0] = bond[N] = 1); sites_host holds the N site
+ * tensors [bond[i], d, bond[i+1]] back to back.  The state must be
+ * right-canonical with its norm on site 0 (a normalised product state is). */
+itn_status itn_mps_create(itn_handle* h, int32_t N, int32_t d, const int32_t* bond,
+                          const double* sites_host, itn_mps** mps);
+itn_status itn_mps_destroy(itn_mps* mps);
+/* Current link dimensions (N+1 entries). */
+itn_status itn_mps_bonds(const itn_mps* mps, int32_t* bond);
+/* Copy site i to host ([bond[i], d, bond[i+1]] doubles). */
+itn_status itn_mps_get_site(itn_handle* h, const itn_mps* mps, int32_t i, double* host);
+
+typedef struct {
+  int32_t nsweeps;
+  const int32_t* maxdim;  /* nsweeps entries (the Sweeps schedule of Sec. 7.2) */
+  const double* cutoff;   /* nsweeps entries (truncation of Sec. 5)            */
+  int32_t mindim;         /* >= 1                                              */
+  int32_t krylovdim;      /* Davidson basis size before restart (>= 2)        */
+  int32_t maxiter;        /* matvecs per local eigensolve                      */
+  double eig_tol;         /* residual tolerance, relative to |theta|           */
+  itn_prec prec;          /* matvec precision of the Davidson expansion        */
+  int32_t refine;         /* 1: finish every local solve with FP64 matvecs     */
+  double energy_tol;      /* stop early when |dE| < energy_tol*|E| (0: never)  */
+} itn_sweep_params;
+
+/* Per-sweep results, arrays of nsweeps entries owned by the caller (any may
+ * be NULL).  sweeps_done is set to the number of sweeps actually run. */
+typedef struct {
+  int32_t sweeps_done;
+  double* energy;       /* eigenvalue at the last bond of the sweep            */
+  double* max_trunc;    /* largest discarded weight of the sweep               */
+  int32_t* max_bond;    /* largest link dimension after the sweep              */
+  double* seconds;      /* wall time of the sweep                              */
+  int64_t* matvecs;     /* H_eff applications in the sweep (all precisions)    */
+  double* residual;     /* largest final FP64 residual norm of a local solve   */
+} itn_sweep_result;
+
+/* Run the schedule: per sweep, left->right over bonds (0,1)..(N-2,N-1) then
+ * right->left back (two-site updates, truncated split of Sec. 5, FP64
+ * eigensolver).  The MPS and its environments are updated in place, so a
+ * later call continues where this one stopped.  Returns
+ * ITN_E_NOT_CONVERGED (after finishing the sweeps) if a local solve ended
+ * above its tolerance. */
+itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
+                          const itn_sweep_params* params, itn_sweep_result* result);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ITN_H */

@@ -1,0 +1,170 @@
+"""Python binding of libitn (two-site DMRG H_eff on MI355X / gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libitn.so.  Device tensors are torch tensors on a ROCm device;
+MPO tensors are host float64 numpy arrays.  Importing the package does not
+load the library; the first call does, and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+__all__ = ["ItnError", "Handle", "PREC", "load"]
+
+PREC = {"f64": L.ITN_P_F64, "f32": L.ITN_P_F32, "bf16": L.ITN_P_BF16}
+
+
+def load():
+    return L.load()
+
+
+class ItnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (L.STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+        self.name = L.STATUS_NAMES.get(status, str(status))
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if isinstance(t, np.ndarray):
+        if t.dtype == np.float64:
+            return L.ITN_F64
+        if t.dtype == np.float32:
+            return L.ITN_F32
+        raise TypeError("unsupported numpy dtype %s" % t.dtype)
+    m = {torch.float64: L.ITN_F64, torch.float32: L.ITN_F32, torch.bfloat16: L.ITN_BF16}
+    if t.dtype not in m:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    return m[t.dtype]
+
+
+class _Keep:
+    """Holds ctypes buffers alive for the duration of a call."""
+
+    def __init__(self):
+        self.items = []
+
+    def arr(self, ctype, values):
+        a = (ctype * max(1, len(values)))(*values)
+        self.items.append(a)
+        return a
+
+
+def _dense(keep: _Keep, t, labels: Optional[Sequence[int]] = None, shape=None) -> L.itn_tensor:
+    """itn_tensor for a dense torch tensor (device) or numpy array (host)."""
+    if isinstance(t, np.ndarray):
+        if not t.flags.c_contiguous:
+            raise ValueError("host arrays must be C-contiguous")
+        ptr = t.ctypes.data
+    else:
+        if not t.is_contiguous():
+            raise ValueError("device tensors must be contiguous")
+        ptr = t.data_ptr()
+    dims = list(shape if shape is not None else t.shape)
+    tt = L.itn_tensor()
+    tt.rank = len(dims)
+    tt.dims = keep.arr(C.c_int64, dims)
+    if labels is not None:
+        tt.label = keep.arr(C.c_int32, list(labels))
+    tt.dtype = _dtype_code(t)
+    tt.data = C.c_void_p(ptr)
+    tt.nblocks = 0
+    return tt
+
+
+def _stream_ptr(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Handle:
+    """An itn_handle on one device (device=-1: host-only, planning and
+    validation only)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = L.load()
+        h = C.c_void_p()
+        st = self.lib.itn_create(C.byref(h), int(device))
+        if st != L.ITN_OK:
+            raise ItnError(st, "itn_create(device=%d) failed" % device)
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.itn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != L.ITN_OK:
+            msg = self.lib.itn_last_error(self.h)
+            raise ItnError(st, msg.decode() if msg else "")
+
+    def _sp(self, stream):
+        if self.device < 0:
+            return C.c_void_p(None)
+        return _stream_ptr(stream)
+
+    def last_error(self) -> str:
+        return self.lib.itn_last_error(self.h).decode()
+
+    def sync(self, stream=None):
+        self._check(self.lib.itn_sync(self.h, self._sp(stream)))
+
+    # ---------------------------------------------------------------- calls
+    def contract(self, A, la, B, lb, Cout, lc, prec: str = "f64", stream=None):
+        k = _Keep()
+        ta, tb, tc = _dense(k, A, la), _dense(k, B, lb), _dense(k, Cout, lc)
+        self._check(self.lib.itn_contract(self.h, C.byref(ta), C.byref(tb), C.byref(tc),
+                                          PREC[prec], self._sp(stream)))
+        return Cout
+
+    def heff_apply(self, Lenv, W1: np.ndarray, W2: np.ndarray, Renv, psi, out, nv: int = 1,
+                   prec: str = "f64", stream=None):
+        """psi/out: contiguous device tensors holding nv vectors
+        [chi_l, d, d, chi_r] back to back (any leading shape)."""
+        cl, cr = Lenv.shape[0], Renv.shape[0]
+        d = W1.shape[2]
+        shp = (cl, d, d, cr)
+        k = _Keep()
+        tl, tr = _dense(k, Lenv), _dense(k, Renv)
+        W1c = np.ascontiguousarray(W1, np.float64)
+        W2c = np.ascontiguousarray(W2, np.float64)
+        k.items += [W1c, W2c]
+        t1, t2 = _dense(k, W1c), _dense(k, W2c)
+        tp, to = _dense(k, psi, shape=shp), _dense(k, out, shape=shp)
+        self._check(self.lib.itn_heff_apply(self.h, C.byref(tl), C.byref(t1), C.byref(t2),
+                                            C.byref(tr), C.byref(tp), int(nv), C.byref(to),
+                                            PREC[prec], self._sp(stream)))
+        return out
+
+    def heff_workspace_size(self, chi_l, chi_r, d, w, nv=1, prec="f64") -> int:
+        b = C.c_size_t()
+        self._check(self.lib.itn_heff_workspace_size(self.h, chi_l, chi_r, d, w, nv, PREC[prec],
+                                                     C.byref(b)))
+        return b.value
+
+    def env_update(self, E, A, W: np.ndarray, direction: str, out, prec: str = "f64",
+                   stream=None):
+        k = _Keep()
+        Wc = np.ascontiguousarray(W, np.float64)
+        k.items.append(Wc)
+        te, ta, tw, to = _dense(k, E), _dense(k, A), _dense(k, Wc), _dense(k, out)
+        dr = L.ITN_LEFT if direction == "left" else L.ITN_RIGHT
+        self._check(self.lib.itn_env_update(self.h, C.byref(te), C.byref(ta), C.byref(tw), dr,
+                                            C.byref(to), PREC[prec], self._sp(stream)))
+        return out

@@ -1,0 +1,296 @@
+// Memory-bound kernels of libitn: layout changes with dtype conversion, the
+// sparse W-stage, and the FP64 vector operations of the eigensolver.
+#include "common.h"
+#include "kernels.h"
+
+namespace itn {
+
+// ------------------------------------------------------------------ helpers
+template <typename T> struct DT;
+template <> struct DT<double> { static constexpr int code = D_F64; };
+template <> struct DT<float> { static constexpr int code = D_F32; };
+template <> struct DT<bf16_t> { static constexpr int code = D_BF16; };
+
+#define ITN_DISPATCH2(IN_DT, OUT_DT, FN, ...)                                         \
+  do {                                                                                \
+    if ((IN_DT) == D_F64 && (OUT_DT) == D_F64) return FN<double, double>(__VA_ARGS__);  \
+    if ((IN_DT) == D_F64 && (OUT_DT) == D_F32) return FN<double, float>(__VA_ARGS__);   \
+    if ((IN_DT) == D_F64 && (OUT_DT) == D_BF16) return FN<double, bf16_t>(__VA_ARGS__); \
+    if ((IN_DT) == D_F32 && (OUT_DT) == D_F64) return FN<float, double>(__VA_ARGS__);   \
+    if ((IN_DT) == D_F32 && (OUT_DT) == D_F32) return FN<float, float>(__VA_ARGS__);    \
+    if ((IN_DT) == D_F32 && (OUT_DT) == D_BF16) return FN<float, bf16_t>(__VA_ARGS__);  \
+    if ((IN_DT) == D_BF16 && (OUT_DT) == D_F64) return FN<bf16_t, double>(__VA_ARGS__); \
+    if ((IN_DT) == D_BF16 && (OUT_DT) == D_F32) return FN<bf16_t, float>(__VA_ARGS__);  \
+    if ((IN_DT) == D_BF16 && (OUT_DT) == D_BF16) return FN<bf16_t, bf16_t>(__VA_ARGS__);\
+    return hipErrorInvalidValue;                                                      \
+  } while (0)
+
+template <typename To, typename From> __device__ __forceinline__ To conv(From x) {
+  return (To)(float)x;
+}
+template <> __device__ __forceinline__ double conv<double, double>(double x) { return x; }
+template <> __device__ __forceinline__ double conv<double, float>(float x) { return (double)x; }
+template <> __device__ __forceinline__ float conv<float, double>(double x) { return (float)x; }
+template <> __device__ __forceinline__ bf16_t conv<bf16_t, double>(double x) { return (bf16_t)(float)x; }
+
+static unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// -------------------------------------------------------------------- cast
+template <typename TI, typename TO>
+__global__ void cast_kernel(const TI* __restrict__ in, TO* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = conv<TO, TI>(in[i]);
+}
+template <typename TI, typename TO>
+static hipError_t cast_t(const void* in, void* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((cast_kernel<TI, TO>), dim3(grid_for(n, 256)), dim3(256), 0, s,
+                     static_cast<const TI*>(in), static_cast<TO*>(out), n);
+  return hipGetLastError();
+}
+hipError_t cast(int in_dtype, const void* in, int out_dtype, void* out, int64_t n, hipStream_t s) {
+  ITN_DISPATCH2(in_dtype, out_dtype, cast_t, in, out, n, s);
+}
+
+// ----------------------------------------------------------------- permute
+struct PermArgs {
+  int rank;
+  int64_t dims[8];
+  int64_t istr[8];
+  int64_t n;
+};
+template <typename TI, typename TO>
+__global__ void permute_kernel(const TI* __restrict__ in, TO* __restrict__ out, PermArgs a) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = i, off = 0;
+    for (int k = a.rank - 1; k >= 0; --k) {
+      const int64_t c = rem % a.dims[k];
+      rem /= a.dims[k];
+      off += c * a.istr[k];
+    }
+    out[i] = conv<TO, TI>(in[off]);
+  }
+}
+template <typename TI, typename TO>
+static hipError_t permute_t(const void* in, void* out, const PermArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL((permute_kernel<TI, TO>), dim3(grid_for(a.n, 256)), dim3(256), 0, s,
+                     static_cast<const TI*>(in), static_cast<TO*>(out), a);
+  return hipGetLastError();
+}
+hipError_t permute_cast(int in_dtype, const void* in, int out_dtype, void* out, int rank,
+                        const int64_t* out_dims, const int64_t* in_strides, hipStream_t s) {
+  if (rank < 0 || rank > 8) return hipErrorInvalidValue;
+  PermArgs a;
+  a.rank = rank;
+  a.n = 1;
+  for (int k = 0; k < 8; ++k) {
+    a.dims[k] = k < rank ? out_dims[k] : 1;
+    a.istr[k] = k < rank ? in_strides[k] : 0;
+    if (k < rank) a.n *= out_dims[k];
+  }
+  ITN_DISPATCH2(in_dtype, out_dtype, permute_t, in, out, a, s);
+}
+
+// --------------------------------------------------------------- transpose
+// 64x64 tiles through LDS: coalesced reads along c, coalesced writes along r.
+constexpr int TT = 64;
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ in,
+                                                         TO* __restrict__ out, TransposeArgs t,
+                                                         int64_t tiles_r, int64_t tiles_c) {
+  __shared__ float tile[TT][TT + 1];
+  __shared__ double tile64[(sizeof(TI) == 8) ? TT : 1][TT + 1];
+  const int64_t z = blockIdx.y;
+  const int64_t zb = z / t.nzc, zc = z % t.nzc;
+  const int64_t tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
+  const int64_t r0 = tr * TT, c0 = tc * TT;
+  const TI* ip = in + zb * t.in_zb + zc * t.in_zc;
+  TO* op = out + zb * t.out_zb + zc * t.out_zc;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  for (int i = ty; i < TT; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    if (r < t.rows && c < t.cols) {
+      if constexpr (sizeof(TI) == 8) tile64[i][tx] = (double)ip[r * t.in_r + c * t.in_c];
+      else tile[i][tx] = (float)ip[r * t.in_r + c * t.in_c];
+    }
+  }
+  __syncthreads();
+  for (int i = ty; i < TT; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (r < t.rows && c < t.cols) {
+      if constexpr (sizeof(TI) == 8) op[c * t.out_c + r * t.out_r] = conv<TO, double>(tile64[tx][i]);
+      else op[c * t.out_c + r * t.out_r] = conv<TO, float>(tile[tx][i]);
+    }
+  }
+}
+template <typename TI, typename TO>
+static hipError_t transpose_t(const void* in, void* out, const TransposeArgs& t, hipStream_t s) {
+  const int64_t tr = (t.rows + TT - 1) / TT, tc = (t.cols + TT - 1) / TT;
+  const int64_t nz = t.nzb * t.nzc;
+  if (tr == 0 || tc == 0 || nz == 0) return hipSuccess;
+  hipLaunchKernelGGL((transpose_kernel<TI, TO>), dim3((unsigned)(tr * tc), (unsigned)nz),
+                     dim3(256), 0, s, static_cast<const TI*>(in), static_cast<TO*>(out), t, tr, tc);
+  return hipGetLastError();
+}
+hipError_t transpose_cast(int in_dtype, const void* in, int out_dtype, void* out,
+                          const TransposeArgs& t, hipStream_t s) {
+  ITN_DISPATCH2(in_dtype, out_dtype, transpose_t, in, out, t, s);
+}
+
+// ------------------------------------------------------------------ W-stage
+// One thread per position y (fastest, coalesced), grid over (y-chunk, x, z).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void wstage_kernel(const TI* __restrict__ in, TO* __restrict__ out,
+                                                      WStageArgs a, const int32_t* __restrict__ row_ptr,
+                                                      const int64_t* __restrict__ row_off,
+                                                      const int64_t* __restrict__ col_off,
+                                                      const double* __restrict__ coef) {
+  using A = typename std::conditional<sizeof(TI) == 8, double, float>::type;
+  const int64_t y = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t x = blockIdx.y, z = blockIdx.z;
+  if (y >= a.Y) return;
+  const TI* ip = in + x * a.isx + z * a.isz + y * a.isy;
+  TO* op = out + x * a.osx + z * a.osz + y * a.osy;
+  for (int r = 0; r < a.nrows; ++r) {
+    A acc = 0;
+    for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) acc += (A)coef[e] * (A)ip[col_off[e]];
+    op[row_off[r]] = conv<TO, A>(acc);
+  }
+}
+template <typename TI, typename TO>
+static hipError_t wstage_t(const void* in, void* out, const WStageArgs& a, const int32_t* rp,
+                           const int64_t* ro, const int64_t* co, const double* cf, hipStream_t s) {
+  if (a.X == 0 || a.Y == 0 || a.Z == 0) return hipSuccess;
+  dim3 grid((unsigned)((a.Y + 255) / 256), (unsigned)a.X, (unsigned)a.Z);
+  hipLaunchKernelGGL((wstage_kernel<TI, TO>), grid, dim3(256), 0, s, static_cast<const TI*>(in),
+                     static_cast<TO*>(out), a, rp, ro, co, cf);
+  return hipGetLastError();
+}
+hipError_t wstage(int in_dtype, const void* in, int out_dtype, void* out, const WStageArgs& a,
+                  const int32_t* row_ptr, const int64_t* row_off, const int64_t* col_off,
+                  const double* coef, hipStream_t s) {
+  if (in_dtype == D_BF16) return hipErrorInvalidValue;
+  ITN_DISPATCH2(in_dtype, out_dtype, wstage_t, in, out, a, row_ptr, row_off, col_off, coef, s);
+}
+
+// ------------------------------------------------------------------ BLAS-1
+constexpr int DOT_THREADS = 256;
+constexpr int64_t DOT_CHUNK = 8192;  // elements per block
+
+int64_t dot_blocks(int64_t n) {
+  int64_t b = (n + DOT_CHUNK - 1) / DOT_CHUNK;
+  return b < 1 ? 1 : b;
+}
+
+// partial[j * nb + blockIdx.x] = sum over the block's chunk of V_j * w.
+__global__ __launch_bounds__(DOT_THREADS) void multi_dot_partial(const double* __restrict__ V,
+                                                                  int64_t ldv, int k,
+                                                                  const double* __restrict__ w,
+                                                                  int64_t n, double* partial) {
+  __shared__ double red[DOT_THREADS / 64];
+  const int64_t nb = gridDim.x;
+  const int64_t lo = blockIdx.x * DOT_CHUNK;
+  int64_t hi = lo + DOT_CHUNK;
+  if (hi > n) hi = n;
+  for (int j = 0; j < k; ++j) {
+    const double* v = V + j * ldv;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += DOT_THREADS) acc += v[i] * w[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < DOT_THREADS / 64; ++q) t += red[q];
+      partial[j * nb + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+// out[j] = sum_b partial[j * nb + b], fixed order.
+__global__ void multi_dot_final(const double* __restrict__ partial, int64_t nb, int k,
+                                double* out) {
+  const int j = blockIdx.x;
+  if (j >= k) return;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[j * nb + b];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+hipError_t multi_dot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
+                     double* partial, double* out, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  const int64_t nb = dot_blocks(n);
+  hipLaunchKernelGGL(multi_dot_partial, dim3((unsigned)nb), dim3(DOT_THREADS), 0, s, V, ldv, k, w,
+                     n, partial);
+  hipLaunchKernelGGL(multi_dot_final, dim3((unsigned)k), dim3(256), 0, s, partial, nb, k, out);
+  return hipGetLastError();
+}
+
+struct Coefs {
+  double c[64];
+};
+__global__ void lincomb_kernel(const double* __restrict__ V, int64_t ldv, int k, Coefs c,
+                               double beta, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = (beta != 0.0) ? beta * y[i] : 0.0;
+    for (int j = 0; j < k; ++j) acc += c.c[j] * V[j * ldv + i];
+    y[i] = acc;
+  }
+}
+hipError_t lincomb(const double* V, int64_t ldv, int k, const double* c, double beta, double* y,
+                   int64_t n, hipStream_t s) {
+  if (k > 64 || k < 0) return hipErrorInvalidValue;
+  Coefs cc;
+  for (int j = 0; j < 64; ++j) cc.c[j] = j < k ? c[j] : 0.0;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, V, ldv, k, cc,
+                     beta, y, n);
+  return hipGetLastError();
+}
+
+__global__ void scale_kernel(double* x, double a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] *= a;
+}
+hipError_t scale(double* x, double a, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, x, a, n);
+  return hipGetLastError();
+}
+
+template <typename T> __global__ void fill_kernel(T* x, T v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+hipError_t fill(void* x, int dtype, double v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned g = grid_for(n, 256, 8192);
+  if (dtype == D_F64)
+    hipLaunchKernelGGL(fill_kernel<double>, dim3(g), dim3(256), 0, s, (double*)x, v, n);
+  else if (dtype == D_F32)
+    hipLaunchKernelGGL(fill_kernel<float>, dim3(g), dim3(256), 0, s, (float*)x, (float)v, n);
+  else
+    hipLaunchKernelGGL(fill_kernel<bf16_t>, dim3(g), dim3(256), 0, s, (bf16_t*)x,
+                       (bf16_t)(float)v, n);
+  return hipGetLastError();
+}
+
+}  // namespace itn

@@ -1,0 +1,172 @@
+// Plain and grouped NT GEMM kernels (MFMA, gfx950).
+#include "gemm_core.h"
+#include "kernels.h"
+
+namespace itn {
+
+template <int P, int BM, int BN, bool ALIGNED, typename TOut>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_nt_kernel(GemmArgs g, int64_t tiles_m,
+                                                                 int64_t tiles_n) {
+  using Cfg = TileCfg<P, BM, BN>;
+  using T = typename Cfg::T;
+  extern __shared__ __align__(16) char lds[];
+  int64_t tm, tn;
+  tile_coords(blockIdx.x, tiles_m * tiles_n, tiles_m, tiles_n, tm, tn);
+  const int64_t b = blockIdx.y;
+  const T* A = static_cast<const T*>(g.A) + b * g.sA;
+  const T* B = static_cast<const T*>(g.B) + b * g.sB;
+  TOut* Cp = static_cast<TOut*>(g.C) + b * g.sC;
+  typename Cfg::AccV acc[BM / 32][BN / 32];
+  zero_acc<P, BM, BN>(acc);
+  gemm_accum<P, BM, BN, ALIGNED>(A, g.lda, g.M, B, g.ldb, g.N, g.K, tm * BM, tn * BN, acc, lds);
+  store_tile<P, BM, BN, TOut>(acc, Cp, g.ldc, g.M, g.N, tm * BM, tn * BN, g.accumulate != 0);
+}
+
+template <int P, int BM, int BN, typename TOut>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(
+    const typename PT<P>::T* __restrict__ Abase, const typename PT<P>::T* __restrict__ Bbase,
+    TOut* __restrict__ Cbase, const GProb* __restrict__ probs, const GSeg* __restrict__ segs,
+    const GTile* __restrict__ tiles, int64_t a_bs, int64_t b_bs, int64_t c_bs) {
+  using Cfg = TileCfg<P, BM, BN>;
+  using T = typename Cfg::T;
+  constexpr int E16 = Cfg::E16;
+  extern __shared__ __align__(16) char lds[];
+  const GTile t = tiles[blockIdx.x];
+  const GProb pr = probs[t.prob];
+  const int64_t batch = blockIdx.y;
+  typename Cfg::AccV acc[BM / 32][BN / 32];
+  zero_acc<P, BM, BN>(acc);
+  for (int s = 0; s < pr.nseg; ++s) {
+    const GSeg sg = segs[pr.seg0 + s];
+    const T* A = Abase + sg.a_off + batch * a_bs;
+    const T* B = Bbase + sg.b_off + batch * b_bs;
+    // The choice is uniform over the workgroup (it depends on the segment only).
+    const bool al = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 &&
+                    sg.lda % E16 == 0 && sg.ldb % E16 == 0;
+    if (al)
+      gemm_accum<P, BM, BN, true>(A, sg.lda, pr.M, B, sg.ldb, pr.N, sg.K, (int64_t)t.tm * BM,
+                                  (int64_t)t.tn * BN, acc, lds);
+    else
+      gemm_accum<P, BM, BN, false>(A, sg.lda, pr.M, B, sg.ldb, pr.N, sg.K, (int64_t)t.tm * BM,
+                                   (int64_t)t.tn * BN, acc, lds);
+  }
+  store_tile<P, BM, BN, TOut>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc, pr.M, pr.N,
+                              (int64_t)t.tm * BM, (int64_t)t.tn * BN, false);
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Tiles above 64 KiB of LDS need the per-kernel dynamic-LDS limit raised
+// (gfx950 has 160 KiB per workgroup).
+template <typename K> static hipError_t allow_lds(K kernel, int bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <int P, int BM, int BN, typename TOut>
+static hipError_t launch_nt(const GemmArgs& g, hipStream_t s) {
+  using Cfg = TileCfg<P, BM, BN>;
+  const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  if (tiles_m == 0 || tiles_n == 0 || g.batch == 0) return hipSuccess;
+  const int es = (int)sizeof(typename Cfg::T);
+  const bool al = aligned16(g.A) && aligned16(g.B) && (g.lda * es) % 16 == 0 &&
+                  (g.ldb * es) % 16 == 0 && (g.sA * es) % 16 == 0 && (g.sB * es) % 16 == 0;
+  dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)g.batch);
+  static const hipError_t attr =
+      allow_lds(gemm_nt_kernel<P, BM, BN, true, TOut>, Cfg::LDS_BYTES) != hipSuccess
+          ? hipErrorInvalidValue
+          : allow_lds(gemm_nt_kernel<P, BM, BN, false, TOut>, Cfg::LDS_BYTES);
+  if (attr != hipSuccess) return attr;
+  if (al)
+    hipLaunchKernelGGL((gemm_nt_kernel<P, BM, BN, true, TOut>), grid, dim3(GEMM_THREADS),
+                       Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<P, BM, BN, false, TOut>), grid, dim3(GEMM_THREADS),
+                       Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+template <int P, typename TOut>
+static hipError_t dispatch_nt(const GemmArgs& g, hipStream_t s) {
+  // Small problems use 64x64 tiles so that the launch still spreads over the CUs.
+  const int64_t big_tiles = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+  if (g.M >= 128 && g.N >= 128 && big_tiles >= 256) return launch_nt<P, 128, 128, TOut>(g, s);
+  return launch_nt<P, 64, 64, TOut>(g, s);
+}
+
+template <int P>
+static hipError_t dispatch_out(int c_dtype, const GemmArgs& g, hipStream_t s) {
+  switch (c_dtype) {
+    case D_F64: return dispatch_nt<P, double>(g, s);
+    case D_F32: return dispatch_nt<P, float>(g, s);
+    case D_BF16: return dispatch_nt<P, bf16_t>(g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t gemm_nt(int prec, int c_dtype, const GemmArgs& g, hipStream_t s) {
+  switch (prec) {
+    case P_F64: return dispatch_out<P_F64>(c_dtype, g, s);
+    case P_F32: return dispatch_out<P_F32>(c_dtype, g, s);
+    case P_BF16: return dispatch_out<P_BF16>(c_dtype, g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P, int BM, int BN, typename TOut>
+static hipError_t launch_grouped(const void* Ab, const void* Bb, void* Cb, const GProb* probs,
+                                 const GSeg* segs, const GTile* tiles, int64_t ntiles,
+                                 int64_t a_bs, int64_t b_bs, int64_t c_bs, int nbatch,
+                                 hipStream_t s) {
+  using Cfg = TileCfg<P, BM, BN>;
+  using T = typename Cfg::T;
+  if (ntiles == 0 || nbatch == 0) return hipSuccess;
+  dim3 grid((unsigned)ntiles, (unsigned)nbatch);
+  static const hipError_t attr = allow_lds(gemm_grouped_kernel<P, BM, BN, TOut>, Cfg::LDS_BYTES);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((gemm_grouped_kernel<P, BM, BN, TOut>), grid, dim3(GEMM_THREADS),
+                     Cfg::LDS_BYTES, s, static_cast<const T*>(Ab), static_cast<const T*>(Bb),
+                     static_cast<TOut*>(Cb), probs, segs, tiles, a_bs, b_bs, c_bs);
+  return hipGetLastError();
+}
+
+#define ITN_GROUPED_ARGS Ab, Bb, Cb, probs, segs, tiles, ntiles, a_bs, b_bs, c_bs, nbatch, s
+
+template <int P, typename TOut>
+static hipError_t grouped_cfg(int cfg, const void* Ab, const void* Bb, void* Cb,
+                              const GProb* probs, const GSeg* segs, const GTile* tiles,
+                              int64_t ntiles, int64_t a_bs, int64_t b_bs, int64_t c_bs, int nbatch,
+                              hipStream_t s) {
+  if (cfg == 1) return launch_grouped<P, 128, 128, TOut>(ITN_GROUPED_ARGS);
+  return launch_grouped<P, 64, 64, TOut>(ITN_GROUPED_ARGS);
+}
+
+template <int P>
+static hipError_t grouped_out(int c_dtype, int cfg, const void* Ab, const void* Bb, void* Cb,
+                              const GProb* probs, const GSeg* segs, const GTile* tiles,
+                              int64_t ntiles, int64_t a_bs, int64_t b_bs, int64_t c_bs, int nbatch,
+                              hipStream_t s) {
+  switch (c_dtype) {
+    case D_F64: return grouped_cfg<P, double>(cfg, ITN_GROUPED_ARGS);
+    case D_F32: return grouped_cfg<P, float>(cfg, ITN_GROUPED_ARGS);
+    case D_BF16: return grouped_cfg<P, bf16_t>(cfg, ITN_GROUPED_ARGS);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const void* Ab, const void* Bb,
+                        void* Cb, const GProb* probs, const GSeg* segs, const GTile* tiles,
+                        int64_t ntiles, int64_t a_bs, int64_t b_bs, int64_t c_bs, int nbatch,
+                        hipStream_t s) {
+  const int cfg = tile_cfg;
+  switch (prec) {
+    case P_F64: return grouped_out<P_F64>(c_dtype, cfg, ITN_GROUPED_ARGS);
+    case P_F32: return grouped_out<P_F32>(c_dtype, cfg, ITN_GROUPED_ARGS);
+    case P_BF16: return grouped_out<P_BF16>(c_dtype, cfg, ITN_GROUPED_ARGS);
+  }
+  return hipErrorInvalidValue;
+}
+#undef ITN_GROUPED_ARGS
+
+}  // namespace itn

@@ -1,0 +1,210 @@
+// MFMA tile engine shared by the GEMM-shaped kernels of libitn.
+//
+// One workgroup of 256 threads (four wave64s in a 2x2 grid) computes a
+// BM x BN tile of C = A * B^T, where both operands are K-contiguous rows
+// ("NT").  K advances in steps of 128 bytes (16 f64 / 32 f32 / 64 bf16
+// elements) through a double-buffered LDS stage; each LDS row is padded to
+// 144 bytes so that the 16-byte fragment reads of 16 consecutive rows fall
+// in distinct banks.  Every lane reads 16-byte fragments and feeds 16x16
+// MFMAs: for bf16 one v_mfma_f32_16x16x32_bf16 per fragment pair, for f32
+// four v_mfma_f32_16x16x4_f32, for f64 two v_mfma_f64_16x16x4_f64.  The
+// K index order inside a step is a fixed permutation shared by A and B, so
+// the sum is the plain sum over K.
+#pragma once
+
+#include "common.h"
+
+namespace itn {
+
+constexpr int GEMM_THREADS = 256;
+constexpr int ROW_BYTES = 128;
+constexpr int LDS_STRIDE = 144;
+
+template <int P, int BM, int BN> struct TileCfg {
+  using T = typename PT<P>::T;
+  using Acc = typename PT<P>::Acc;
+  using AccV = typename PT<P>::AccV;
+  static constexpr int E16 = PT<P>::E16;
+  static constexpr int BK = ROW_BYTES / (int)sizeof(T);
+  static constexpr int FM = BM / 32;  // 16-row blocks per wave (two waves along M)
+  static constexpr int FN = BN / 32;
+  static constexpr int A_PASSES = BM / 32;  // 32 rows x 8 chunks per pass of 256 threads
+  static constexpr int B_PASSES = BN / 32;
+  static constexpr int STAGE_BYTES = (BM + BN) * LDS_STRIDE;
+  static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
+};
+
+template <typename T> __device__ __forceinline__ T zero_of() { return (T)0.0f; }
+
+// 16 bytes of row `row` starting at element k; zero outside [0, nrows) x [0, K).
+template <typename T, int E16, bool ALIGNED>
+__device__ __forceinline__ uint4 load16(const T* __restrict__ base, int64_t ld, int64_t row,
+                                        int64_t nrows, int64_t k, int64_t K) {
+  uint4 v = {0u, 0u, 0u, 0u};
+  if (row < nrows) {
+    const T* p = base + row * ld + k;
+    if (ALIGNED && k + E16 <= K) {
+      v = *reinterpret_cast<const uint4*>(p);
+    } else {
+      T tmp[E16];
+#pragma unroll
+      for (int e = 0; e < E16; ++e) tmp[e] = (k + e < K) ? p[e] : zero_of<T>();
+      __builtin_memcpy(&v, tmp, 16);
+    }
+  }
+  return v;
+}
+
+template <int P> struct Mfma;
+template <> struct Mfma<P_BF16> {
+  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, floatx4& c) {
+    bf16x8 av, bv;
+    __builtin_memcpy(&av, &a, 16);
+    __builtin_memcpy(&bv, &b, 16);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<P_F32> {
+  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, floatx4& c) {
+    float av[4], bv[4];
+    __builtin_memcpy(av, &a, 16);
+    __builtin_memcpy(bv, &b, 16);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[e], c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<P_F64> {
+  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, doublex4& c) {
+    double av[2], bv[2];
+    __builtin_memcpy(av, &a, 16);
+    __builtin_memcpy(bv, &b, 16);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], bv[e], c, 0, 0, 0);
+  }
+};
+
+template <int P, int BM, int BN>
+__device__ __forceinline__ void zero_acc(typename TileCfg<P, BM, BN>::AccV (&acc)[BM / 32][BN / 32]) {
+#pragma unroll
+  for (int i = 0; i < BM / 32; ++i)
+#pragma unroll
+    for (int j = 0; j < BN / 32; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+}
+
+// acc += A[m0:m0+BM, 0:K] * B[n0:n0+BN, 0:K]^T.  A and B point at row 0 of
+// their operand; rows >= M (resp. N) and k >= K read as zero.  Ends with a
+// barrier, so it may be called again on the same LDS.
+template <int P, int BM, int BN, bool ALIGNED>
+__device__ __forceinline__ void gemm_accum(
+    const typename PT<P>::T* __restrict__ A, int64_t lda, int64_t M,
+    const typename PT<P>::T* __restrict__ B, int64_t ldb, int64_t N, int64_t K, int64_t m0,
+    int64_t n0, typename TileCfg<P, BM, BN>::AccV (&acc)[BM / 32][BN / 32], char* lds) {
+  using C = TileCfg<P, BM, BN>;
+  using T = typename C::T;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = tid >> 3, lchunk = tid & 7;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int64_t nk = (K + C::BK - 1) / C::BK;
+  if (nk <= 0) return;
+  uint4 ra[C::A_PASSES], rb[C::B_PASSES];
+
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < C::A_PASSES; ++p)
+      ra[p] = load16<T, C::E16, ALIGNED>(A, lda, m0 + p * 32 + lrow, M, k0 + lchunk * C::E16, K);
+#pragma unroll
+    for (int p = 0; p < C::B_PASSES; ++p)
+      rb[p] = load16<T, C::E16, ALIGNED>(B, ldb, n0 + p * 32 + lrow, N, k0 + lchunk * C::E16, K);
+  };
+  auto sstore = [&](int buf) {
+    char* a = lds + buf * C::STAGE_BYTES;
+    char* b = a + BM * LDS_STRIDE;
+#pragma unroll
+    for (int p = 0; p < C::A_PASSES; ++p)
+      *reinterpret_cast<uint4*>(a + (p * 32 + lrow) * LDS_STRIDE + lchunk * 16) = ra[p];
+#pragma unroll
+    for (int p = 0; p < C::B_PASSES; ++p)
+      *reinterpret_cast<uint4*>(b + (p * 32 + lrow) * LDS_STRIDE + lchunk * 16) = rb[p];
+  };
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) gload((kt + 1) * C::BK);
+    const char* As = lds + cur * C::STAGE_BYTES;
+    const char* Bs = As + BM * LDS_STRIDE;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      uint4 af[C::FM], bfr[C::FN];
+#pragma unroll
+      for (int i = 0; i < C::FM; ++i)
+        af[i] = *reinterpret_cast<const uint4*>(As + (wm * (BM / 2) + i * 16 + r16) * LDS_STRIDE +
+                                                ks * 64 + q * 16);
+#pragma unroll
+      for (int j = 0; j < C::FN; ++j)
+        bfr[j] = *reinterpret_cast<const uint4*>(Bs + (wn * (BN / 2) + j * 16 + r16) * LDS_STRIDE +
+                                                 ks * 64 + q * 16);
+#pragma unroll
+      for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) Mfma<P>::run(af[i], bfr[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+}
+
+// Write (or add to) the BM x BN tile at (m0, n0) of C (rows >= M or cols >= N skipped).
+template <int P, int BM, int BN, typename TOut>
+__device__ __forceinline__ void store_tile(
+    const typename TileCfg<P, BM, BN>::AccV (&acc)[BM / 32][BN / 32], TOut* __restrict__ Cp,
+    int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0, bool accumulate) {
+  using Acc = typename PT<P>::Acc;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int i = 0; i < BM / 32; ++i)
+#pragma unroll
+    for (int j = 0; j < BN / 32; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + wm * (BM / 2) + i * 16 + acc_row<P>(lane, e);
+        const int64_t col = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          Acc v = acc[i][j][e];
+          TOut* p = Cp + row * ldc + col;
+          if (accumulate) v += cvt<Acc>(*p);
+          *p = cvt<TOut>(v);
+        }
+      }
+}
+
+// Tile order: spread consecutive logical tiles over the 8 XCDs' own
+// dispatch slots (workgroup i runs on XCD i % 8), then walk tiles in groups
+// of 8 tile-rows so that tiles resident on one XCD share A and B panels.
+__device__ __forceinline__ void tile_coords(int64_t bid, int64_t ntiles, int64_t tiles_m,
+                                            int64_t tiles_n, int64_t& tm, int64_t& tn) {
+  int64_t logical = bid;
+  const int64_t per = ntiles / 8;
+  if (per > 0 && bid < per * 8) logical = (bid % 8) * per + bid / 8;
+  const int64_t G = 8;
+  const int64_t width = G * tiles_n;
+  const int64_t group = logical / width;
+  const int64_t first_m = group * G;
+  int64_t gsize = tiles_m - first_m;
+  if (gsize > G) gsize = G;
+  const int64_t in_group = logical % width;
+  tm = first_m + in_group % gsize;
+  tn = in_group / gsize;
+}
+
+}  // namespace itn

@@ -1,0 +1,94 @@
+// Host-side internals of libitn: the handle, workspace, error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/itn.h"
+#include "kernels.h"
+
+namespace itn {
+
+// Device CSR table of a W-stage (rows = outputs, entries = inputs).
+struct WTable {
+  int32_t nrows = 0;
+  int64_t nnz = 0;
+  int32_t* row_ptr = nullptr;
+  int64_t* row_off = nullptr;
+  int64_t* col_off = nullptr;
+  double* coef = nullptr;
+  void release();
+};
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t size = 0;
+};
+
+}  // namespace itn
+
+struct itn_handle {
+  int device = -1;
+  std::string err;
+  itn::Workspace ws;
+  std::map<std::string, std::unique_ptr<itn::WTable>> wtables;
+  void* solver = nullptr;  // rocblas_handle for rocSOLVER, created on first use
+};
+
+namespace itn {
+
+// Status with message recorded on the handle.
+itn_status fail(itn_handle* h, itn_status st, const char* fmt, ...);
+itn_status hip_fail(itn_handle* h, hipError_t e, const char* where);
+
+#define ITN_HIP(h, expr)                                   \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return ::itn::hip_fail(h, _e, #expr); \
+  } while (0)
+
+#define ITN_TRY(expr)                  \
+  do {                                 \
+    itn_status _s = (expr);            \
+    if (_s != ITN_OK) return _s;       \
+  } while (0)
+
+// Grow the handle's workspace to at least `bytes` (waits for the device).
+itn_status ensure_workspace(itn_handle* h, size_t bytes);
+
+// Carve 256-byte-aligned regions out of a workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t bytes) {
+    void* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  }
+};
+
+inline size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Look up or build (and upload) a W-stage table keyed by its content.
+itn_status get_wtable(itn_handle* h, const std::string& key, const std::vector<int32_t>& row_ptr,
+                      const std::vector<int64_t>& row_off, const std::vector<int64_t>& col_off,
+                      const std::vector<double>& coef, const WTable** out);
+
+// Host-side CSR builders.
+struct CSR {
+  std::vector<int32_t> row_ptr{0};
+  std::vector<int64_t> row_off;
+  std::vector<int64_t> col_off;
+  std::vector<double> coef;
+  std::string key() const;
+};
+
+}  // namespace itn

@@ -1,0 +1,121 @@
+// Host-side launch interface of the libitn device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace itn {
+
+// Storage dtypes (same codes as itn_dtype).
+enum DType { D_F64 = 0, D_F32 = 1, D_BF16 = 2 };
+inline int dtype_size(int dt) { return dt == D_F64 ? 8 : (dt == D_F32 ? 4 : 2); }
+
+// C[b][m][n] = sum_k A[b][m][k] * B[b][n][k]  (both operands K-contiguous,
+// "NT").  A, B hold the operand precision's type; C is written as c_dtype.
+// If accumulate != 0 the result is added to C (read in c_dtype).
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  void* C;
+  int64_t M, N, K;
+  int64_t lda, ldb, ldc;
+  int64_t sA, sB, sC;  // batch strides (elements)
+  int32_t batch;
+  int32_t accumulate;
+};
+hipError_t gemm_nt(int prec, int c_dtype, const GemmArgs& g, hipStream_t s);
+
+// Grouped NT GEMM over a device work table: every work item is one output
+// tile of one problem; a problem's K is the concatenation of `nseg`
+// segments, each with its own A/B base pointers and leading dimensions, and
+// is summed in segment order by the single workgroup that owns the tile.
+struct GSeg {      // one K segment of one problem
+  int64_t a_off;   // element offset of the segment's A block (row 0, k 0)
+  int64_t b_off;   // element offset of the segment's B block
+  int32_t lda, ldb;
+  int32_t K;
+  int32_t pad;
+};
+struct GProb {     // one output problem (an output block, or a group of them)
+  int64_t c_off;   // element offset of C (row 0, col 0)
+  int32_t M, N;
+  int32_t ldc;
+  int32_t seg0;    // first segment index
+  int32_t nseg;
+  int32_t tiles_n; // column tiles
+};
+struct GTile {     // one work item
+  int32_t prob;
+  int32_t tm, tn;  // tile coordinates within the problem
+  int32_t pad;
+};
+// Tile config codes for the grouped launch: 0 = 64x64, 1 = 128x128.
+// Batch b (grid.y) offsets A, B and C by b times their batch strides.
+hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const void* Abase, const void* Bbase,
+                        void* Cbase, const GProb* probs, const GSeg* segs, const GTile* tiles,
+                        int64_t ntiles, int64_t a_batch_stride, int64_t b_batch_stride,
+                        int64_t c_batch_stride, int nbatch, hipStream_t s);
+
+// Generic strided permutation with dtype conversion (rank <= 8):
+// out[i_0..i_{r-1}] (row-major over out_dims) = in[sum_k i_k * in_strides[k]].
+hipError_t permute_cast(int in_dtype, const void* in, int out_dtype, void* out, int rank,
+                        const int64_t* out_dims, const int64_t* in_strides, hipStream_t s);
+
+// Batched 2-D transpose with conversion: for each batch z (two levels zb, zc):
+//   out[zb][zc][c][r] = in[zb][zc][r][c]  with explicit strides.
+struct TransposeArgs {
+  int64_t rows, cols;
+  int64_t nzb, nzc;
+  int64_t in_zb, in_zc, in_r, in_c;     // input strides
+  int64_t out_zb, out_zc, out_c, out_r; // output strides
+};
+hipError_t transpose_cast(int in_dtype, const void* in, int out_dtype, void* out,
+                          const TransposeArgs& t, hipStream_t s);
+
+// Sparse "W-stage": for every position (x, z, y)
+//   out[x*osx + z*osz + y*osy + row_off[r]] = sum_{e in row r} coef[e] * in[x*isx + z*isz + y*isy + col_off[e]]
+// row_ptr has nrows+1 entries.  Inputs are FP64 or FP32 (in_dtype), output
+// out_dtype; arithmetic in FP64 for FP64 input, FP32 otherwise.
+struct WStageArgs {
+  int64_t X, Z, Y;
+  int64_t isx, isz, isy;
+  int64_t osx, osz, osy;
+  int32_t nrows;
+};
+hipError_t wstage(int in_dtype, const void* in, int out_dtype, void* out, const WStageArgs& a,
+                  const int32_t* row_ptr, const int64_t* row_off, const int64_t* col_off,
+                  const double* coef, hipStream_t s);
+
+// Fused first stage of H_eff for small w*d^2: X = L psi (MFMA) with the
+// W-stage applied in the epilogue, writing Z directly.  See heff.hip.
+struct HeffFusedArgs {
+  const void* L;     // [chi_l, w, chi_l]
+  const void* psiT;  // [d2, nv, chi_r, chi_l]
+  void* Z;           // [nv, chi_l, d2, w, chi_r]
+  int64_t chi_l, chi_r;
+  int32_t w, d2, nv;
+  int32_t nrows;     // CSR rows = d2*w (output (c', m2))
+  const int32_t* row_ptr;
+  const int32_t* col_idx;  // input index m0*d2 + c
+  const float* coef32;
+  const double* coef64;
+};
+bool heff_fused_supported(int prec, int w, int d2);
+hipError_t heff_stage1_fused(int prec, const HeffFusedArgs& a, hipStream_t s);
+
+// Element-wise conversion of a contiguous buffer.
+hipError_t cast(int in_dtype, const void* in, int out_dtype, void* out, int64_t n, hipStream_t s);
+
+// FP64 BLAS-1 helpers for the eigensolver (deterministic reductions).
+// out[j] = <V_j, w> for k vectors V_j = V + j*ldv, length n.  `partial`
+// must hold k * dot_blocks(n) doubles.
+int64_t dot_blocks(int64_t n);
+hipError_t multi_dot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
+                     double* partial, double* out, hipStream_t s);
+// y = sum_j c[j] * V_j  (+ beta*y if beta != 0); c on host, k <= 64.
+hipError_t lincomb(const double* V, int64_t ldv, int k, const double* c, double beta, double* y,
+                   int64_t n, hipStream_t s);
+hipError_t scale(double* x, double a, int64_t n, hipStream_t s);
+hipError_t fill(void* x, int dtype, double v, int64_t n, hipStream_t s);
+
+}  // namespace itn

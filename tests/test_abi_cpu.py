@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+include/itn.h declares, and rejects bad arguments before any launch."""
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2007_14822_amd as itn
+from paper_2007_14822_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "itn.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:itn_status|const char\*)\s+(itn_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_symbols_exported_and_bound():
+    lib = L.load()
+    syms = _declared_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in L.SIGNATURES, "binding lacks %s" % s
+    assert lib.itn_version().decode().startswith("libitn")
+
+
+@pytest.fixture(scope="module")
+def host():
+    return itn.Handle(-1)
+
+
+def _t(*shape, dtype=torch.float64):
+    return torch.zeros(*shape, dtype=dtype)
+
+
+def test_host_handle_refuses_work(host):
+    with pytest.raises(itn.ItnError) as e:
+        host.contract(_t(2, 3), [1, 2], _t(3, 4), [2, 3], _t(2, 4), [1, 3])
+    assert e.value.name == "ITN_E_NODEVICE"
+
+
+def test_contract_label_errors(host):
+    with pytest.raises(itn.ItnError) as e:
+        host.contract(_t(2, 3), [1, 2], _t(4, 4), [2, 3], _t(2, 4), [1, 3])
+    assert e.value.name == "ITN_E_SHAPE"
+    with pytest.raises(itn.ItnError) as e:
+        host.contract(_t(2, 3), [1, 2], _t(3, 4), [2, 3], _t(2, 4), [1, 4])
+    assert e.value.name == "ITN_E_LABEL"
+    with pytest.raises(itn.ItnError) as e:
+        host.contract(_t(2, 3), [1, 1], _t(3, 4), [2, 3], _t(2, 4), [1, 3])
+    assert e.value.name == "ITN_E_LABEL"
+    with pytest.raises(itn.ItnError) as e:
+        host.contract(_t(2, 3), [1, 2], _t(3, 4), [2, 3], _t(2, 5), [1, 3])
+    assert e.value.name == "ITN_E_SHAPE"
+
+
+def test_heff_shape_errors(host):
+    W = np.zeros((5, 5, 2, 2))
+    with pytest.raises(itn.ItnError) as e:  # L not square in its bonds
+        host.heff_apply(_t(4, 5, 3), W, W, _t(4, 5, 4), _t(4, 2, 2, 4), _t(4, 2, 2, 4))
+    assert e.value.name == "ITN_E_SHAPE"
+    with pytest.raises(itn.ItnError) as e:  # W with the wrong d
+        host.heff_apply(_t(4, 5, 4), np.zeros((5, 5, 3, 3)), W, _t(4, 5, 4), _t(4, 2, 2, 4),
+                        _t(4, 2, 2, 4))
+    assert e.value.name == "ITN_E_SHAPE"
+    with pytest.raises(itn.ItnError) as e:  # bf16 psi
+        host.heff_apply(_t(4, 5, 4), W, W, _t(4, 5, 4), _t(4, 2, 2, 4, dtype=torch.bfloat16),
+                        _t(4, 2, 2, 4))
+    assert e.value.name == "ITN_E_DTYPE"
+    with pytest.raises(itn.ItnError) as e:  # valid request, no device
+        host.heff_apply(_t(4, 5, 4), W, W, _t(4, 5, 4), _t(4, 2, 2, 4), _t(4, 2, 2, 4))
+    assert e.value.name == "ITN_E_NODEVICE"
+
+
+def test_env_update_errors(host):
+    W = np.zeros((5, 5, 2, 2))
+    with pytest.raises(itn.ItnError) as e:
+        host.env_update(_t(3, 5, 3), _t(4, 2, 6), W, "left", _t(6, 5, 6))
+    assert e.value.name == "ITN_E_SHAPE"
+    with pytest.raises(itn.ItnError) as e:
+        host.env_update(_t(3, 5, 3), _t(3, 2, 6), W, "left", _t(6, 5, 5))
+    assert e.value.name == "ITN_E_SHAPE"
+    with pytest.raises(itn.ItnError) as e:
+        host.env_update(_t(3, 5, 3), _t(3, 2, 6), W, "left", _t(6, 5, 6))
+    assert e.value.name == "ITN_E_NODEVICE"
+
+
+def test_workspace_query(host):
+    b = host.heff_workspace_size(2048, 2048, 2, 5, 1, "bf16")
+    assert b > 2048 * 2048 * 4 * 2

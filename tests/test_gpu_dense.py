@@ -1,0 +1,192 @@
+"""GPU parity of the dense path (contract, H_eff, environment step) against
+the oracle, through the C ABI.
+
+Tolerances (relative Frobenius error against the FP64 oracle):
+  f64  1e-10  (the FP64 target)
+  f32  1e-5   (unit roundoff 6e-8 times sqrt(K)-type growth for K <= 1e4)
+  bf16 2e-2   (operands rounded to 8 significant bits, u = 2^-9 = 2e-3)
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2007_14822_amd as itn
+from paper_2007_14822_amd import inputs as inp
+from oracle import heff as hf
+from oracle.tensor import contract as ocontract
+from tests.workloads import c1_operands, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 2e-2}
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def h():
+    return itn.Handle(0)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+# ------------------------------------------------------------------ contract
+CONTRACT_CASES = [
+    # (A dims by label, A labels, B labels, C labels)
+    ({1: 3, 2: 2, 3: 4, 4: 5}, [1, 2, 4, 3], [5, 4, 6], [1, 2, 3, 5, 6]),  # App. A shapes
+    ({1: 37, 2: 29, 3: 41}, [1, 2], [2, 3], [1, 3]),                       # ragged matrix
+    ({1: 37, 2: 29, 3: 41}, [1, 2], [2, 3], [3, 1]),                       # transposed output
+    ({1: 3, 2: 7, 3: 2, 4: 4}, [-1, 1, -2], [2, -2, -1], [1, 2]),          # label example
+    ({1: 6, 2: 5}, [1], [2], [1, 2]),                                      # outer product
+    ({1: 6, 2: 5, 3: 4}, [1, 2, 3], [3, 1, 2], []),                        # inner product
+    ({1: 130, 2: 70, 3: 129, 4: 3}, [1, 4, 2], [2, 3, 4], [3, 1]),         # several tiles
+]
+
+
+@pytest.mark.parametrize("case", range(len(CONTRACT_CASES)))
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_contract_parity(h, case, prec):
+    dims, la, lb, lc = CONTRACT_CASES[case]
+    dims = dict(dims)
+    dims.setdefault(-1, 3)
+    dims.setdefault(-2, 2)
+    dims.setdefault(5, 2)
+    dims.setdefault(6, 6)
+    rng = np.random.default_rng(100 + case)
+    A = rng.standard_normal([dims[l] for l in la])
+    B = rng.standard_normal([dims[l] for l in lb])
+    ref = ocontract(A, la, B, lb, lc)
+    for cdt in (torch.float64, torch.float32):
+        Cg = torch.zeros([dims[l] for l in lc], dtype=cdt, device=DEV)
+        h.contract(dev(A), la, dev(B), lb, Cg, lc, prec=prec)
+        assert rel_err(host(Cg), ref) <= max(TOL[prec], 1e-6 if cdt == torch.float32 else 0)
+
+
+def test_contract_f32_operands(h):
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((33, 65))
+    B = rng.standard_normal((65, 17))
+    Cg = torch.zeros((33, 17), dtype=torch.float64, device=DEV)
+    h.contract(dev(A, torch.float32), [1, 2], dev(B, torch.float32), [2, 3], Cg, [1, 3], "f32")
+    ref = A.astype(np.float32).astype(np.float64) @ B.astype(np.float32).astype(np.float64)
+    assert rel_err(host(Cg), ref) <= 1e-6
+
+
+def test_contract_zero_extent(h):
+    Cg = torch.full((3, 4), 7.0, dtype=torch.float64, device=DEV)
+    h.contract(dev(np.zeros((3, 0))), [1, 2], dev(np.zeros((0, 4))), [2, 3], Cg, [1, 3])
+    assert np.all(host(Cg) == 0.0)
+
+
+# --------------------------------------------------------------------- H_eff
+def _heff_case(cl, cr, d, w, nv, seed, mpo="heis"):
+    rng = np.random.default_rng(seed)
+    L = rng.standard_normal((cl, w, cl))
+    R = rng.standard_normal((cr, w, cr))
+    if mpo == "heis":
+        W = inp.heisenberg_mpo(3, d - 1)[1]
+        W1, W2 = W, W
+    else:
+        W1 = rng.standard_normal((w, w, d, d)) * (rng.random((w, w, 1, 1)) < 0.4)
+        W2 = rng.standard_normal((w, w, d, d)) * (rng.random((w, w, 1, 1)) < 0.4)
+    psi = rng.standard_normal((nv, cl, d, d, cr))
+    return L, W1, W2, R, psi
+
+
+HEFF_CASES = [
+    # cl, cr, d, w, nv, mpo
+    (1, 1, 2, 5, 1, "heis"),       # boundary-sized
+    (7, 3, 2, 5, 1, "heis"),       # ragged, below one tile
+    (37, 29, 2, 5, 2, "heis"),     # ragged, batched
+    (64, 64, 2, 5, 1, "heis"),
+    (96, 80, 3, 5, 1, "heis"),     # spin-1
+    (40, 52, 3, 11, 1, "rand"),    # AKLT-sized MPO, random sparse W
+    (24, 20, 4, 18, 2, "rand"),    # Hubbard-sized MPO
+    (150, 140, 2, 5, 1, "heis"),   # several tiles + tail
+]
+
+
+@pytest.mark.parametrize("case", range(len(HEFF_CASES)))
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_heff_parity(h, case, prec):
+    cl, cr, d, w, nv, mpo = HEFF_CASES[case]
+    L, W1, W2, R, psi = _heff_case(cl, cr, d, w, nv, 200 + case, mpo)
+    ref = np.stack([hf.heff_apply(L, W1, W2, R, psi[v]) for v in range(nv)])
+    for ldt in (torch.float64, torch.float32):
+        out = torch.zeros(psi.shape, dtype=torch.float64, device=DEV)
+        h.heff_apply(dev(L, ldt), W1, W2, dev(R, ldt), dev(psi), out, nv=nv, prec=prec)
+        tol = TOL[prec] if ldt == torch.float64 else max(TOL[prec], 1e-6)
+        assert rel_err(host(out), ref) <= tol, (case, prec, ldt)
+
+
+def test_heff_bf16_operands_and_f32_output(h):
+    L, W1, W2, R, psi = _heff_case(64, 48, 2, 5, 1, 5)
+    ref = hf.heff_apply(L, W1, W2, R, psi[0])
+    out = torch.zeros(psi.shape, dtype=torch.float32, device=DEV)
+    h.heff_apply(dev(L, torch.bfloat16), W1, W2, dev(R, torch.bfloat16), dev(psi, torch.float32),
+                 out, nv=1, prec="bf16")
+    assert rel_err(host(out)[0], ref) <= TOL["bf16"]
+
+
+def test_heff_deterministic(h):
+    L, W1, W2, R, psi = _heff_case(96, 96, 2, 5, 2, 9)
+    outs = []
+    for _ in range(2):
+        out = torch.zeros(psi.shape, dtype=torch.float64, device=DEV)
+        h.heff_apply(dev(L, torch.bfloat16), W1, W2, dev(R, torch.bfloat16), dev(psi), out, nv=2,
+                     prec="bf16")
+        outs.append(host(out))
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("chi", [64, 128])
+def test_heff_on_canonical_envs(h, chi):
+    """C1 operands at small chi (environments of a random canonical MPS)."""
+    L, W1, W2, R, psi = c1_operands(chi)
+    ref = hf.heff_apply(L, W1, W2, R, psi)
+    for prec in ("f64", "f32", "bf16"):
+        out = torch.zeros(psi.shape, dtype=torch.float64, device=DEV)
+        h.heff_apply(dev(L), W1, W2, dev(R), dev(psi), out, prec=prec)
+        assert rel_err(host(out), ref) <= TOL[prec], prec
+
+
+# ----------------------------------------------------------- environment step
+@pytest.mark.parametrize("direction", ["left", "right"])
+@pytest.mark.parametrize("shape", [(1, 2, 2), (5, 2, 9), (33, 3, 47), (64, 2, 128), (130, 2, 70)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_env_update_parity(h, direction, shape, prec):
+    chi_in, d, chi_out = shape
+    rng = np.random.default_rng(sum(shape) + (direction == "left"))
+    w = 5
+    W = inp.heisenberg_mpo(3, d - 1)[1]
+    E = rng.standard_normal((chi_in, w, chi_in))
+    if direction == "left":
+        A = rng.standard_normal((chi_in, d, chi_out))
+        ref = hf.env_left(E, A, W)
+    else:
+        A = rng.standard_normal((chi_out, d, chi_in))
+        ref = hf.env_right(E, A, W)
+    out = torch.zeros(ref.shape, dtype=torch.float64, device=DEV)
+    h.env_update(dev(E), dev(A), W, direction, out, prec=prec)
+    assert rel_err(host(out), ref) <= TOL[prec]
+
+
+def test_env_chain_matches_oracle(h):
+    """Environments built site by site on the GPU equal the oracle's."""
+    As, Ws = inp.random_canonical_mps(10, 2, 16, center=5, rng=np.random.default_rng(3)), \
+        inp.heisenberg_mpo(10)
+    Lg = dev(hf.left_boundary(5))
+    for k in range(5):
+        nxt = torch.zeros((As[k].shape[2], 5, As[k].shape[2]), dtype=torch.float64, device=DEV)
+        h.env_update(Lg, dev(As[k]), Ws[k], "left", nxt)
+        Lg = nxt
+    Lref = hf.left_envs(As[:5], Ws[:5])[-1]
+    assert rel_err(host(Lg), Lref) <= 1e-12
+    # identity channel of a left-canonical chain
+    np.testing.assert_allclose(host(Lg)[:, 4, :], np.eye(Lref.shape[0]), atol=1e-12)
