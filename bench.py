@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-site DMRG effective-Hamiltonian matvec on one MI355X.
+
+One step = one dense H_eff*psi (stage-1 MFMA GEMM with L, the sparse
+W-stage, stage-4 MFMA GEMM with R, including the conversion/transposition of
+the FP64 input vector) at chi = 2048, d = 2, w = 5 (Heisenberg MPO), the
+environments built on the GPU from a seeded random canonical MPS.  The
+headline `value` is the mixed-precision (bf16 operands, fp32 accumulation)
+throughput in TFLOP/s of algorithmic work; f32 and the plain FP64 GPU form of
+the same path are timed beside it, with their error against FP64.
+
+    python bench.py [--steps K] [--warmup W] [--chi 2048] [--no-cpu-baseline]
+
+Prints one JSON line.  Only one GPU is used; --gpus > 1 is refused.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = ("H_eff·psi TFLOP/s (% MFMA peak), mixed vs FP64; DMRG sweep time at 1e-8 ΔE")
+PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
+KERNEL_SOURCES = ["paper_2007_14822_amd/csrc/gemm_core.h", "paper_2007_14822_amd/csrc/gemm.hip",
+                  "paper_2007_14822_amd/csrc/heff_fused.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    hsh = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        fp = os.path.join(ROOT, p)
+        if os.path.exists(fp):
+            hsh.update(open(fp, "rb").read())
+    return hsh.hexdigest()[:16]
+
+
+def heff_flops(chi_l, chi_r, d, w, nv=1):
+    """Algorithmic flops of one H_eff*psi: 4 w d^2 chi^3 (two GEMM stages)
+    plus 4 w^2 d^3 chi^2 (the W-stage as two K = w d contractions)."""
+    return nv * (2.0 * w * d * d * chi_l * chi_l * chi_r + 2.0 * w * d * d * chi_l * chi_r * chi_r
+                 + 4.0 * w * w * d ** 3 * chi_l * chi_r)
+
+
+def build_workload(h, chi, d, torch, np, inp):
+    """Random canonical MPS of N_c = 2 log2 chi + 2 sites, Heisenberg MPO;
+    L = environment of the sites left of the centre bond, R of those right
+    of it, both built on the GPU (FP64 environment steps); psi unit Gaussian."""
+    n = int(round(math.log2(chi)))
+    Nc = 2 * n + 2
+    c = Nc // 2 - 1
+    rng = inp.rng_for(1, chi)
+    As = inp.random_canonical_mps(Nc, d, chi, center=c, rng=rng)
+    Ws = inp.heisenberg_mpo(Nc, d - 1)
+    w = Ws[0].shape[0]
+    dev = "cuda:0"
+    Lg = torch.zeros((1, w, 1), dtype=torch.float64, device=dev)
+    Lg[0, w - 1, 0] = 1.0
+    for k in range(c):
+        A = torch.as_tensor(np.ascontiguousarray(As[k]), device=dev)
+        nxt = torch.empty((A.shape[2], w, A.shape[2]), dtype=torch.float64, device=dev)
+        h.env_update(Lg, A, Ws[k], "left", nxt)
+        Lg = nxt
+    Rg = torch.zeros((1, w, 1), dtype=torch.float64, device=dev)
+    Rg[0, 0, 0] = 1.0
+    for k in range(Nc - 1, c + 1, -1):
+        A = torch.as_tensor(np.ascontiguousarray(As[k]), device=dev)
+        nxt = torch.empty((A.shape[0], w, A.shape[0]), dtype=torch.float64, device=dev)
+        h.env_update(Rg, A, Ws[k], "right", nxt)
+        Rg = nxt
+    psi = inp.unit_gaussian((Lg.shape[0], d, d, Rg.shape[0]), rng)
+    torch.cuda.synchronize()
+    return Lg, Ws[c], Ws[c + 1], Rg, torch.as_tensor(np.ascontiguousarray(psi), device=dev)
+
+
+def time_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, steps, warmup):
+    for _ in range(warmup):
+        h.heff_apply(Lp, W1, W2, Rp, psi, out, prec=prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        h.heff_apply(Lp, W1, W2, Rp, psi, out, prec=prec)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def profile_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, steps):
+    h.profile(True)
+    for _ in range(steps):
+        h.heff_apply(Lp, W1, W2, Rp, psi, out, prec=prec)
+    rep = h.profile_report()
+    h.profile(False)
+    return {k: {"avg_ms": v[0] / max(1, v[1]), "launches": v[1]} for k, v in rep.items()}
+
+
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch measured by rocprofv3 --pmc (FETCH_SIZE,
+    WRITE_SIZE) and calibrated with a plain copy, stored with the hash of
+    the kernel sources it was taken on; None if absent or stale."""
+    fp = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(fp):
+        return None
+    rec = json.load(open(fp))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(L, W1, W2, R, psi, chi, d, w, budget_s):
+    """The oracle (plain einsum, one thread) on a bounded sample: the first k
+    output rows a' of the same matvec; throughput scaled by k/chi."""
+    import numpy as np
+    from oracle import heff as hf
+    t0 = time.perf_counter()
+    hf.heff_apply_rows(L, W1, W2, R, psi, [0])
+    t1 = time.perf_counter() - t0
+    k = int(max(1, min(chi, budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    hf.heff_apply_rows(L, W1, W2, R, psi, list(range(k)))
+    dt = time.perf_counter() - t0
+    fl = heff_flops(chi, chi, d, w) * k / chi
+    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d output rows a' of the chi=%d matvec (oracle heff_apply_rows, "
+                      "numpy einsum optimize=False, single thread), %.1f s" % (k, chi, chi, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--chi", type=int, default=2048)
+    ap.add_argument("--d", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--only", choices=["bf16", "f32", "f64"], default=None,
+                    help="time one precision only (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding design in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2007_14822_amd as itn
+    from paper_2007_14822_amd import inputs as inp
+
+    chi, d = args.chi, args.d
+    h = itn.Handle(0)
+    log("[bench] building chi=%d workload" % chi)
+    t0 = time.perf_counter()
+    L64, W1, W2, R64, psi = build_workload(h, chi, d, torch, np, inp)
+    w = W1.shape[0]
+    log("[bench] workload ready in %.1f s" % (time.perf_counter() - t0))
+    flops = heff_flops(chi, chi, d, w)
+    gemm_flops = 2.0 * w * d * d * chi ** 3  # one GEMM stage
+    precs = [args.only] if args.only else ["bf16", "f32", "f64"]
+    tdt = {"bf16": torch.bfloat16, "f32": torch.float32, "f64": torch.float64}
+    results = {}
+    outs = {}
+    for prec in precs:
+        if prec == "f64":
+            Lp, Rp = L64, R64
+        else:
+            Lp = torch.empty(L64.shape, dtype=tdt[prec], device="cuda:0")
+            Rp = torch.empty(R64.shape, dtype=tdt[prec], device="cuda:0")
+            h.cast(L64, Lp)
+            h.cast(R64, Rp)
+        out = torch.zeros_like(psi)
+        steps = args.steps if prec != "f64" else max(2, args.steps // 4)
+        log("[bench] %s: %d warmup + %d timed steps" % (prec, args.warmup, steps))
+        ms = time_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, steps, args.warmup)
+        prof = profile_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, max(2, steps // 2))
+        outs[prec] = out.clone()
+        results[prec] = {"ms_per_step": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                         "frac_of_peak": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+                         "steps": steps, "kernels": prof}
+        log("[bench] %s: %.3f ms/step, %.1f TFLOP/s" % (prec, ms, results[prec]["tflops"]))
+        del Lp, Rp
+    if "f64" in outs:
+        ref = outs["f64"]
+        for prec in precs:
+            if prec != "f64":
+                results[prec]["rel_err_vs_f64"] = float(
+                    torch.linalg.vector_norm(outs[prec] - ref) / torch.linalg.vector_norm(ref))
+    head = precs[0]
+    r = results[head]
+    # dominant kernel and its roofline
+    kern = max(r["kernels"].items(), key=lambda kv: kv[1]["avg_ms"])
+    kname, kst = kern[0], kern[1]
+    achieved = gemm_flops / (kst["avg_ms"] * 1e-3) / 1e12 if "gemm" in kname else None
+    roof = {"bound": "mfma", "kernel": kname, "achieved": achieved, "peak": PEAK_TFLOPS[head],
+            "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS[head]) if achieved else None,
+            "avg_ms": kst["avg_ms"], "flop_per_launch": gemm_flops,
+            "traffic": traffic_record(kname, "c1_chi%d_%s" % (chi, head))}
+    line = {
+        "metric": METRIC, "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": r["steps"], "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": "dense two-site H_eff*psi, chi=%d, d=%d, w=%d (S=1/2 Heisenberg "
+                               "MPO), nv=1, environments of a seeded random canonical MPS" %
+                               (chi, d, w),
+                   "chi": chi, "d": d, "w": w, "nv": 1, "flop_per_step": flops,
+                   "precision": "%s operands, %s accumulation" %
+                                (head, "fp64" if head == "f64" else "fp32")},
+        "roofline": roof,
+        "by_precision": {k: {kk: vv for kk, vv in v.items() if kk != "kernels"} for k, v in
+                         results.items()},
+        "kernels": {k: v["kernels"] for k, v in results.items()},
+    }
+    if "f64" in results and head != "f64":
+        line["speedup_vs_fp64_gpu"] = results["f64"]["ms_per_step"] / r["ms_per_step"]
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(L64.cpu().numpy(), W1, W2, R64.cpu().numpy(),
+                                            psi.cpu().numpy(), chi, d, w, args.cpu_budget)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

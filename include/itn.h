@@ -119,6 +119,21 @@ itn_status itn_sync(itn_handle* h, void* hip_stream);
 /* Library version string (static storage). */
 const char* itn_version(void);
 
+/* Per-kernel timing with hip events recorded on the launch stream around
+ * each internal launch (small overhead per launch; off by default). */
+itn_status itn_profile_enable(itn_handle* h, int32_t on);
+/* Synchronise the device and report the launches timed since the last
+ * report, aggregated by kernel name in first-seen order: names[32*i] (NUL-
+ * terminated), total_ms[i], count[i] for i < min(*n_entries, max_entries).
+ * Clears the record. */
+itn_status itn_profile_report(itn_handle* h, int32_t max_entries, char* names, double* total_ms,
+                              int64_t* count, int32_t* n_entries);
+
+/* dst = src converted element-wise to dst's dtype (dense, equal extents;
+ * F64 / F32 / BF16 both ways, rounding to nearest).  Used to prepare
+ * environments in the matrix-core operand type once per bond. */
+itn_status itn_cast(itn_handle* h, const itn_tensor* src, itn_tensor* dst, void* hip_stream);
+
 /* --------------------------------------------------------------- contract */
 
 /* C = A * B over labels (the product operator of Sec. 4 with the label

@@ -125,7 +125,30 @@ class Handle:
     def sync(self, stream=None):
         self._check(self.lib.itn_sync(self.h, self._sp(stream)))
 
+    def profile(self, on: bool = True):
+        self._check(self.lib.itn_profile_enable(self.h, 1 if on else 0))
+
+    def profile_report(self):
+        """{kernel name: (total ms, launches)} since the last report."""
+        mx = 64
+        names = C.create_string_buffer(32 * mx)
+        tot = (C.c_double * mx)()
+        cnt = (C.c_int64 * mx)()
+        n = C.c_int32()
+        self._check(self.lib.itn_profile_report(self.h, mx, names, tot, cnt, C.byref(n)))
+        out = {}
+        for i in range(min(n.value, mx)):
+            nm = names.raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (tot[i], cnt[i])
+        return out
+
     # ---------------------------------------------------------------- calls
+    def cast(self, src, dst, stream=None):
+        k = _Keep()
+        ts, td = _dense(k, src), _dense(k, dst)
+        self._check(self.lib.itn_cast(self.h, C.byref(ts), C.byref(td), self._sp(stream)))
+        return dst
+
     def contract(self, A, la, B, lb, Cout, lc, prec: str = "f64", stream=None):
         k = _Keep()
         ta, tb, tc = _dense(k, A, la), _dense(k, B, lb), _dense(k, Cout, lc)

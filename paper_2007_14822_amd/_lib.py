@@ -63,6 +63,10 @@ SIGNATURES = {
     "itn_last_error": (C.c_char_p, [P]),
     "itn_sync": (S, [P, P]),
     "itn_version": (C.c_char_p, []),
+    "itn_profile_enable": (S, [P, C.c_int32]),
+    "itn_profile_report": (S, [P, C.c_int32, C.c_char_p, C.POINTER(C.c_double),
+                               C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "itn_cast": (S, [P, T, T, P]),
     "itn_contract": (S, [P, T, T, T, C.c_int, P]),
     "itn_heff_apply": (S, [P, T, T, T, T, T, C.c_int32, T, C.c_int, P]),
     "itn_heff_workspace_size": (S, [P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,

@@ -17,6 +17,10 @@ void WTable::release() {
   if (row_off) (void)hipFree(row_off);
   if (col_off) (void)hipFree(col_off);
   if (coef) (void)hipFree(coef);
+  if (col_idx) (void)hipFree(col_idx);
+  if (coef32) (void)hipFree(coef32);
+  col_idx = nullptr;
+  coef32 = nullptr;
   row_ptr = nullptr;
   row_off = col_off = nullptr;
   coef = nullptr;
@@ -55,6 +59,30 @@ itn_status ensure_workspace(itn_handle* h, size_t bytes) {
   return ITN_OK;
 }
 
+static hipEvent_t pool_event(itn_handle* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+Prof::Prof(itn_handle* h_, const char* n, hipStream_t s_) : h(h_), name(n), s(s_) {
+  if (!h->prof_on) return;
+  a = pool_event(h);
+  b = pool_event(h);
+  if (a) (void)hipEventRecord(a, s);
+}
+
+Prof::~Prof() {
+  if (!h->prof_on || !a || !b) return;
+  (void)hipEventRecord(b, s);
+  h->prof.push_back(ProfRec{name, a, b});
+}
+
 std::string CSR::key() const {
   std::string k;
   auto app = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
@@ -91,9 +119,15 @@ itn_status get_wtable(itn_handle* h, const std::string& key, const std::vector<i
   ITN_HIP(h, hipMemcpy(t->row_ptr, row_ptr.data(), row_ptr.size() * 4, hipMemcpyHostToDevice));
   if (!row_off.empty())
     ITN_HIP(h, hipMemcpy(t->row_off, row_off.data(), row_off.size() * 8, hipMemcpyHostToDevice));
+  ITN_HIP(h, hipMalloc(&t->col_idx, nz * 4));
+  ITN_HIP(h, hipMalloc(&t->coef32, nz * 4));
   if (!coef.empty()) {
     ITN_HIP(h, hipMemcpy(t->col_off, col_off.data(), col_off.size() * 8, hipMemcpyHostToDevice));
     ITN_HIP(h, hipMemcpy(t->coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice));
+    std::vector<int32_t> ci(col_off.begin(), col_off.end());
+    std::vector<float> cf(coef.begin(), coef.end());
+    ITN_HIP(h, hipMemcpy(t->col_idx, ci.data(), ci.size() * 4, hipMemcpyHostToDevice));
+    ITN_HIP(h, hipMemcpy(t->coef32, cf.data(), cf.size() * 4, hipMemcpyHostToDevice));
   }
   *out = t.get();
   h->wtables.emplace(key, std::move(t));
@@ -219,6 +253,8 @@ itn_status itn_destroy(itn_handle* h) {
   if (!h) return ITN_E_ARG;
   if (h->device >= 0) {
     (void)hipDeviceSynchronize();
+    for (auto& r : h->prof) (void)hipEventDestroy(r.a), (void)hipEventDestroy(r.b);
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     for (auto& kv : h->wtables) kv.second->release();
     if (h->ws.ptr) (void)hipFree(h->ws.ptr);
     itn_release_solver(h);
@@ -229,10 +265,65 @@ itn_status itn_destroy(itn_handle* h) {
 
 const char* itn_last_error(const itn_handle* h) { return h ? h->err.c_str() : "null handle"; }
 
+itn_status itn_profile_enable(itn_handle* h, int32_t on) {
+  if (!h) return ITN_E_ARG;
+  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle has no launches to time");
+  h->prof_on = on != 0;
+  return ITN_OK;
+}
+
+itn_status itn_profile_report(itn_handle* h, int32_t max_entries, char* names, double* total_ms,
+                              int64_t* count, int32_t* n_entries) {
+  if (!h || !n_entries || (max_entries > 0 && (!names || !total_ms || !count))) return ITN_E_ARG;
+  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle has no launches to time");
+  ITN_HIP(h, hipDeviceSynchronize());
+  std::vector<std::string> order;
+  std::map<std::string, std::pair<double, int64_t>> agg;
+  for (auto& r : h->prof) {
+    float ms = 0.f;
+    ITN_HIP(h, hipEventElapsedTime(&ms, r.a, r.b));
+    auto it = agg.find(r.name);
+    if (it == agg.end()) {
+      order.push_back(r.name);
+      agg[r.name] = {ms, 1};
+    } else {
+      it->second.first += ms;
+      it->second.second += 1;
+    }
+    h->ev_pool.push_back(r.a);
+    h->ev_pool.push_back(r.b);
+  }
+  h->prof.clear();
+  const int n = (int)order.size();
+  *n_entries = n;
+  for (int i = 0; i < n && i < max_entries; ++i) {
+    std::snprintf(names + 32 * i, 32, "%s", order[i].c_str());
+    total_ms[i] = agg[order[i]].first;
+    count[i] = agg[order[i]].second;
+  }
+  return ITN_OK;
+}
+
 itn_status itn_sync(itn_handle* h, void* hip_stream) {
   if (!h) return ITN_E_ARG;
   if (h->device < 0) return ITN_OK;
   ITN_HIP(h, hipStreamSynchronize(as_stream(hip_stream)));
+  return ITN_OK;
+}
+
+itn_status itn_cast(itn_handle* h, const itn_tensor* src, itn_tensor* dst, void* hip_stream) {
+  if (!h) return ITN_E_ARG;
+  ITN_TRY(check_dense(h, src, "src", -1));
+  ITN_TRY(check_dense(h, dst, "dst", -1));
+  if (src->rank != dst->rank) return fail(h, ITN_E_SHAPE, "src and dst ranks differ");
+  for (int k = 0; k < src->rank; ++k)
+    if (src->dims[k] != dst->dims[k]) return fail(h, ITN_E_SHAPE, "src and dst extents differ");
+  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
+  const int64_t n = numel(src);
+  if (n == 0) return ITN_OK;
+  hipStream_t s = as_stream(hip_stream);
+  Prof pf(h, "cast", s);
+  ITN_HIP(h, cast(src->dtype, src->data, dst->dtype, dst->data, n, s));
   return ITN_OK;
 }
 
@@ -444,17 +535,31 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
   const void* Rp = R->data;
   if (castL) {
     void* t = cv.take((size_t)(cl * w * cl) * es);
+    Prof pf(h, "cast_env", s);
     ITN_HIP(h, cast(L->dtype, L->data, pt, t, cl * w * cl, s));
     Lp = t;
   }
   if (castR) {
     void* t = cv.take((size_t)(cr * w * cr) * es);
+    Prof pf(h, "cast_env", s);
     ITN_HIP(h, cast(R->dtype, R->data, pt, t, cr * w * cr, s));
     Rp = t;
   }
   void* psiT = cv.take((size_t)(d2 * nv * cr * cl) * es);
-  void* X = cv.take((size_t)(cl * w * d2 * nv * cr) * dtype_size(xt));
   void* Z = cv.take((size_t)(nv * cl * d2 * w * cr) * es);
+  // The fused stage-1 kernel loads L rows straight into LDS: whole 128-byte
+  // K steps and 16-byte aligned rows.
+  const int64_t bk = 128 / es;
+  CSR fcsr;
+  bool fused = heff_fused_supported(P, (int)w, (int)d2) && cl % bk == 0 && cl > 0 &&
+               (reinterpret_cast<uintptr_t>(Lp) & 15) == 0;
+  if (fused) {
+    // CSR with input index m0*d2 + c and output row c'*w + m2.
+    fcsr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),
+                      (int)w, (int)d, d2, 1, w, 1);
+    fused = heff_fused_table_fits((int)fcsr.row_off.size(), (int64_t)fcsr.coef.size());
+  }
+  void* X = fused ? nullptr : cv.take((size_t)(cl * w * d2 * nv * cr) * dtype_size(xt));
   // psi[v][a][c][b] -> psiT[c][v][b][a]
   TransposeArgs ta{};
   ta.rows = cl;
@@ -469,9 +574,35 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
   ta.out_zc = (int64_t)nv * cr * cl;
   ta.out_c = cl;
   ta.out_r = 1;
-  ITN_HIP(h, transpose_cast(psi->dtype, psi->data, pt, psiT, ta, s));
-  // Stage 1: X[(a' m0), (c v b)] = L[(a' m0), a] . psiT[(c v b), a]
+  {
+    Prof pf(h, "heff_psi_transpose", s);
+    ITN_HIP(h, transpose_cast(psi->dtype, psi->data, pt, psiT, ta, s));
+  }
   const int64_t N1 = d2 * nv * cr;
+  if (fused) {
+    const CSR& csr = fcsr;
+    const WTable* tab = nullptr;
+    ITN_TRY(get_wtable(h, "fused" + csr.key(), csr.row_ptr, csr.row_off, csr.col_off, csr.coef, &tab));
+    HeffFusedArgs fa{};
+    fa.L = Lp;
+    fa.psiT = psiT;
+    fa.Z = Z;
+    fa.chi_l = cl;
+    fa.chi_r = cr;
+    fa.w = (int)w;
+    fa.d2 = (int)d2;
+    fa.nv = nv;
+    fa.nrows = tab->nrows;
+    fa.row_ptr = tab->row_ptr;
+    fa.col_idx = tab->col_idx;
+    fa.coef32 = tab->coef32;
+    fa.coef64 = tab->coef;
+    {
+      Prof pf(h, "heff_stage1_fused", s);
+      ITN_HIP(h, heff_stage1_fused(P, fa, s));
+    }
+  } else {
+  // Stage 1: X[(a' m0), (c v b)] = L[(a' m0), a] . psiT[(c v b), a]
   GemmArgs g1{};
   g1.A = Lp;
   g1.B = psiT;
@@ -483,7 +614,10 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
   g1.ldb = cl;
   g1.ldc = N1;
   g1.batch = 1;
-  ITN_HIP(h, gemm_nt(P, xt, g1, s));
+  {
+    Prof pf(h, "heff_stage1_gemm", s);
+    ITN_HIP(h, gemm_nt(P, xt, g1, s));
+  }
   // W-stage: Z[v][a'][c'][m2][b] = sum W12 X[a'][m0][c][v][b]
   CSR csr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),
                        (int)w, (int)d, /*in_m*/ N1, /*in_c*/ (int64_t)nv * cr,
@@ -501,7 +635,11 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
   wa.osz = cl * d2 * w * cr;
   wa.osy = 1;
   wa.nrows = tab->nrows;
-  ITN_HIP(h, wstage(xt, X, pt, Z, wa, tab->row_ptr, tab->row_off, tab->col_off, tab->coef, s));
+  {
+    Prof pf(h, "heff_wstage", s);
+    ITN_HIP(h, wstage(xt, X, pt, Z, wa, tab->row_ptr, tab->row_off, tab->col_off, tab->coef, s));
+  }
+  }  // unfused
   // Stage 4: out[(v a' c'), b'] = Z[(v a' c'), (m2 b)] . R[b', (m2 b)]
   GemmArgs g4{};
   g4.A = Z;
@@ -514,7 +652,10 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
   g4.ldb = w * cr;
   g4.ldc = cr;
   g4.batch = 1;
-  ITN_HIP(h, gemm_nt(P, out->dtype, g4, s));
+  {
+    Prof pf(h, "heff_stage4_gemm", s);
+    ITN_HIP(h, gemm_nt(P, out->dtype, g4, s));
+  }
   return ITN_OK;
 }
 

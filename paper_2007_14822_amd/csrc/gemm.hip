@@ -22,6 +22,29 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_nt_kernel(GemmArgs g, int64
   store_tile<P, BM, BN, TOut>(acc, Cp, g.ldc, g.M, g.N, tm * BM, tn * BN, g.accumulate != 0);
 }
 
+template <int P, int BM, int BN, int WM, int WN, typename TOut, bool ACCUM>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_nt_direct_kernel(GemmArgs g, int64_t tiles_m,
+                                                                        int64_t tiles_n) {
+  using Cfg = DirectCfg<P, BM, BN, WM, WN>;
+  using T = typename Cfg::T;
+  extern __shared__ __align__(16) char lds[];
+  int64_t tm, tn;
+  tile_coords(blockIdx.x, tiles_m * tiles_n, tiles_m, tiles_n, tm, tn);
+  const int64_t b = blockIdx.y;
+  const T* A = static_cast<const T*>(g.A) + b * g.sA;
+  const T* B = static_cast<const T*>(g.B) + b * g.sB;
+  TOut* Cp = static_cast<TOut*>(g.C) + b * g.sC;
+  typename Cfg::AccV acc[Cfg::FM][Cfg::FN];
+#pragma unroll
+  for (int i = 0; i < Cfg::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+  gemm_accum_direct<P, BM, BN, WM, WN>(A, g.lda, g.M, B, g.ldb, g.N, g.K, tm * BM, tn * BN, acc, lds);
+  store_tile_direct<P, BM, BN, WM, WN, TOut, ACCUM>(acc, Cp, g.ldc, g.M, g.N, tm * BM, tn * BN);
+}
+
 template <int P, int BM, int BN, typename TOut>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(
     const typename PT<P>::T* __restrict__ Abase, const typename PT<P>::T* __restrict__ Bbase,
@@ -87,11 +110,44 @@ static hipError_t launch_nt(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int P, int BM, int BN, int WM, int WN, typename TOut>
+static hipError_t launch_nt_direct(const GemmArgs& g, hipStream_t s) {
+  using Cfg = DirectCfg<P, BM, BN, WM, WN>;
+  const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)g.batch);
+  static const hipError_t attr =
+      allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, false>, Cfg::LDS_BYTES) != hipSuccess
+          ? hipErrorInvalidValue
+          : allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, true>, Cfg::LDS_BYTES);
+  if (attr != hipSuccess) return attr;
+  if (g.accumulate)
+    hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, true>), grid,
+                       dim3(Cfg::THREADS), Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, false>), grid,
+                       dim3(Cfg::THREADS), Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+// Direct-to-LDS tiles need 16-byte aligned rows and whole K steps.
+template <int P> static bool direct_ok(const GemmArgs& g) {
+  using T = typename PT<P>::T;
+  const int es = (int)sizeof(T);
+  const int64_t bk = ROW_BYTES / es;
+  return aligned16(g.A) && aligned16(g.B) && (g.lda * es) % 16 == 0 && (g.ldb * es) % 16 == 0 &&
+         (g.sA * es) % 16 == 0 && (g.sB * es) % 16 == 0 && g.K % bk == 0 && g.K > 0;
+}
+
 template <int P, typename TOut>
 static hipError_t dispatch_nt(const GemmArgs& g, hipStream_t s) {
-  // Small problems use 64x64 tiles so that the launch still spreads over the CUs.
-  const int64_t big_tiles = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-  if (g.M >= 128 && g.N >= 128 && big_tiles >= 256) return launch_nt<P, 128, 128, TOut>(g, s);
+  // Largest tile that still gives every CU at least one workgroup; small
+  // problems use 64x64 tiles so that the launch spreads over the CUs.
+  auto ntiles = [&](int bm, int bn) { return ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.batch; };
+  if constexpr (P == P_BF16) {
+    if (g.M >= 256 && g.N >= 256 && ntiles(256, 256) >= 256 && direct_ok<P>(g))
+      return launch_nt_direct<P, 256, 256, 2, 4, TOut>(g, s);
+  }
+  if (g.M >= 128 && g.N >= 128 && ntiles(128, 128) >= 256) return launch_nt<P, 128, 128, TOut>(g, s);
   return launch_nt<P, 64, 64, TOut>(g, s);
 }
 

@@ -161,6 +161,141 @@ __device__ __forceinline__ void gemm_accum(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Direct-to-LDS variant.  gfx950's global_load_lds_dwordx4 writes the 16
+// bytes each lane loads straight into LDS, lane i at (wave-uniform base +
+// 16*i), so no registers stage the tiles.  One wave fills 8 rows x 128 bytes
+// per instruction; LDS rows are 128 bytes wide and their eight 16-byte chunks
+// are XOR-swizzled by (row % 8), which keeps the fragment reads of 8
+// consecutive rows in distinct banks.  The chunk a lane writes is fixed by
+// its lane id, so the swizzle is applied by choosing which global chunk the
+// lane loads.  Requires 16-byte aligned rows and K % BK == 0; rows past M
+// (or N) are clamped to the last row (their results are never stored).
+
+__device__ __forceinline__ void lds_direct16(const void* g, void* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(
+      (const __attribute__((address_space(1))) void*)g,
+      (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+}
+
+template <int P, int BM, int BN, int WM, int WN> struct DirectCfg {
+  using T = typename PT<P>::T;
+  using AccV = typename PT<P>::AccV;
+  static constexpr int THREADS = 64 * WM * WN;
+  static constexpr int NW = WM * WN;
+  static constexpr int E16 = PT<P>::E16;
+  static constexpr int BK = ROW_BYTES / (int)sizeof(T);
+  static constexpr int TM = BM / WM, TN = BN / WN;  // wave tile
+  static constexpr int FM = TM / 16, FN = TN / 16;
+  static constexpr int STAGE_BYTES = (BM + BN) * ROW_BYTES;
+  static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
+  static constexpr int ROWS_PER_PASS = 8 * NW;
+  static constexpr int A_PASSES = BM / ROWS_PER_PASS;
+  static constexpr int B_PASSES = BN / ROWS_PER_PASS;
+  static_assert(BM % ROWS_PER_PASS == 0 && BN % ROWS_PER_PASS == 0, "tile vs waves");
+};
+
+// acc += A[m0:m0+BM, 0:K] * B[n0:n0+BN, 0:K]^T with direct-to-LDS staging.
+template <int P, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void gemm_accum_direct(
+    const typename PT<P>::T* __restrict__ A, int64_t lda, int64_t M,
+    const typename PT<P>::T* __restrict__ B, int64_t ldb, int64_t N, int64_t K, int64_t m0,
+    int64_t n0,
+    typename PT<P>::AccV (&acc)[DirectCfg<P, BM, BN, WM, WN>::FM][DirectCfg<P, BM, BN, WM, WN>::FN],
+    char* lds) {
+  using C = DirectCfg<P, BM, BN, WM, WN>;
+  using T = typename C::T;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int64_t nk = K / C::BK;
+  if (nk <= 0) return;
+  const int lrow = lane >> 3;  // row within the wave's 8-row slab
+  const int lpos = lane & 7;   // LDS chunk slot this lane fills
+  const int slab = wave * 8 + lrow;
+  // The swizzle (lpos ^ row%8) only depends on lrow since slab starts are multiples of 8.
+  const int64_t chunk = (int64_t)((lpos ^ lrow) * C::E16);
+  const bool fullA = m0 + BM <= M, fullB = n0 + BN <= N;
+  auto rowA = [&](int p) -> const T* {
+    int64_t gr = m0 + p * C::ROWS_PER_PASS + slab;
+    if (!fullA && gr >= M) gr = M - 1;
+    return A + gr * lda + chunk;
+  };
+  auto rowB = [&](int p) -> const T* {
+    int64_t gr = n0 + p * C::ROWS_PER_PASS + slab;
+    if (!fullB && gr >= N) gr = N - 1;
+    return B + gr * ldb + chunk;
+  };
+  auto issue = [&](int buf, int64_t k0) {
+    char* a = lds + buf * C::STAGE_BYTES + wave * 8 * ROW_BYTES;
+    char* b = lds + buf * C::STAGE_BYTES + BM * ROW_BYTES + wave * 8 * ROW_BYTES;
+#pragma unroll
+    for (int p = 0; p < C::A_PASSES; ++p) lds_direct16(rowA(p) + k0, a + p * C::ROWS_PER_PASS * ROW_BYTES);
+#pragma unroll
+    for (int p = 0; p < C::B_PASSES; ++p) lds_direct16(rowB(p) + k0, b + p * C::ROWS_PER_PASS * ROW_BYTES);
+  };
+
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) issue(cur ^ 1, (kt + 1) * C::BK);
+    const char* As = lds + cur * C::STAGE_BYTES;
+    const char* Bs = As + BM * ROW_BYTES;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int c = ks * 4 + q;
+      uint4 bfr[C::FN];
+#pragma unroll
+      for (int j = 0; j < C::FN; ++j) {
+        const int R = wn * C::TN + j * 16 + r16;
+        bfr[j] = *reinterpret_cast<const uint4*>(Bs + R * ROW_BYTES + ((c ^ (R & 7)) << 4));
+      }
+#pragma unroll
+      for (int i = 0; i < C::FM; ++i) {
+        const int R = wm * C::TM + i * 16 + r16;
+        const uint4 af = *reinterpret_cast<const uint4*>(As + R * ROW_BYTES + ((c ^ (R & 7)) << 4));
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) Mfma<P>::run(af, bfr[j], acc[i][j]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next tile have landed in LDS
+    __syncthreads();
+  }
+}
+
+// Store the wave's FM x FN accumulator blocks of a direct tile.
+template <int P, int BM, int BN, int WM, int WN, typename TOut, bool ACCUM>
+__device__ __forceinline__ void store_tile_direct(
+    const typename PT<P>::AccV (&acc)[DirectCfg<P, BM, BN, WM, WN>::FM][DirectCfg<P, BM, BN, WM, WN>::FN],
+    TOut* __restrict__ Cp, int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0) {
+  using C = DirectCfg<P, BM, BN, WM, WN>;
+  using Acc = typename PT<P>::Acc;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const bool full = m0 + BM <= M && n0 + BN <= N;
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + wm * C::TM + i * 16 + acc_row<P>(lane, e);
+        const int64_t col = n0 + wn * C::TN + j * 16 + (lane & 15);
+        if (full || (row < M && col < N)) {
+          Acc v = acc[i][j][e];
+          TOut* p = Cp + row * ldc + col;
+          if (ACCUM) v += cvt<Acc>(*p);
+          *p = cvt<TOut>(v);
+        }
+      }
+}
+
 // Write (or add to) the BM x BN tile at (m0, n0) of C (rows >= M or cols >= N skipped).
 template <int P, int BM, int BN, typename TOut>
 __device__ __forceinline__ void store_tile(

@@ -24,12 +24,20 @@ struct WTable {
   int64_t* row_off = nullptr;
   int64_t* col_off = nullptr;
   double* coef = nullptr;
+  int32_t* col_idx = nullptr;  // col_off as int32 (fused epilogue tables)
+  float* coef32 = nullptr;     // coef as float
   void release();
 };
 
 struct Workspace {
   void* ptr = nullptr;
   size_t size = 0;
+};
+
+// One timed launch (events recorded on the launch stream).
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
 };
 
 }  // namespace itn
@@ -40,6 +48,9 @@ struct itn_handle {
   itn::Workspace ws;
   std::map<std::string, std::unique_ptr<itn::WTable>> wtables;
   void* solver = nullptr;  // rocblas_handle for rocSOLVER, created on first use
+  bool prof_on = false;
+  std::vector<itn::ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
 };
 
 namespace itn {
@@ -81,6 +92,17 @@ inline size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 itn_status get_wtable(itn_handle* h, const std::string& key, const std::vector<int32_t>& row_ptr,
                       const std::vector<int64_t>& row_off, const std::vector<int64_t>& col_off,
                       const std::vector<double>& coef, const WTable** out);
+
+// Scoped per-kernel timer: records a pair of events around the launches in
+// its scope when profiling is enabled on the handle.
+struct Prof {
+  itn_handle* h;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Prof(itn_handle* h_, const char* n, hipStream_t s_);
+  ~Prof();
+};
 
 // Host-side CSR builders.
 struct CSR {

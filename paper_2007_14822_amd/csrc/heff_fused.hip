@@ -1,7 +1,265 @@
-// Fused first stage of the dense H_eff (placeholder until the fused kernel lands).
+// Fused first stage of the dense two-site H_eff:
+//
+//   X[a', m0, c, y] = sum_a L[a', m0, a] psiT[c, y, a]          (MFMA)
+//   Z[v, a', c', m2, b] = sum_{m0, c} W12[(c', m2), (m0, c)] X[a', m0, c, y]   (epilogue)
+//
+// with c = (s1, s2), y = (v, b), W12 = sum_m1 W1 W2 (sparse, CSR by output).
+// The tile of one workgroup covers a block of a' and a block of y for *all*
+// (m0, c) pairs: its A rows are (m0, a') and its B rows (c, y), and every
+// wave owns complete (m0, c) sets for its 16 x 16 (a', y) sub-blocks, so the
+// MFMA accumulators of one lane hold every X value its positions need.  The
+// epilogue writes them to a per-wave LDS area (input-major, lane-minor, so
+// that the gather below is bank-conflict free), then applies W12 row by row
+// from a CSR table and writes Z straight to HBM.  X never leaves the chip.
+#include "gemm_core.h"
 #include "kernels.h"
 
 namespace itn {
-bool heff_fused_supported(int, int, int) { return false; }
-hipError_t heff_stage1_fused(int, const HeffFusedArgs&, hipStream_t) { return hipErrorInvalidValue; }
+
+template <int P, int W, int C, int WM, int WN, int RA, int RB> struct FusedCfg {
+  using T = typename PT<P>::T;
+  using Acc = typename PT<P>::Acc;
+  using AccV = typename PT<P>::AccV;
+  static constexpr int NW = WM * WN;
+  static constexpr int THREADS = 64 * NW;
+  static constexpr int E16 = PT<P>::E16;
+  static constexpr int BK = ROW_BYTES / (int)sizeof(T);
+  static constexpr int TA = WM * 16 * RA;  // a' per workgroup
+  static constexpr int TY = WN * 16 * RB;  // y per workgroup
+  static constexpr int AROWS = W * TA;
+  static constexpr int BROWS = C * TY;
+  static constexpr int STAGE_BYTES = (AROWS + BROWS) * ROW_BYTES;
+  static constexpr int RPP = 8 * NW;  // rows per direct-load pass
+  static constexpr int A_PASSES = (AROWS + RPP - 1) / RPP;
+  static constexpr int B_PASSES = (BROWS + RPP - 1) / RPP;
+  // epilogue: GP position groups per pass, each W*C inputs x 64 lanes
+  static constexpr int GROUPS = RA * RB * 4;
+  static constexpr int GP_MAX = (2 * STAGE_BYTES) / (NW * W * C * 64 * (int)sizeof(Acc));
+  static constexpr int GP = GP_MAX >= 2 && GROUPS % 2 == 0 ? 2 : 1;
+  static constexpr int EPI_BYTES = NW * GP * W * C * 64 * (int)sizeof(Acc);
+  static constexpr int MAIN_BYTES = (2 * STAGE_BYTES > EPI_BYTES) ? 2 * STAGE_BYTES : EPI_BYTES;
+  // CSR table staged in LDS after the main area: row_ptr (<= 64 rows + 1)
+  // then entries {byte offset of the input in a group's area, coefficient}.
+  static constexpr int TAB_ROWS_MAX = 64;
+  static constexpr int TAB_NNZ_MAX = 480;
+  static constexpr int TAB_BYTES = (TAB_ROWS_MAX + 1) * 4 + TAB_NNZ_MAX * 16;
+  static constexpr int LDS_BYTES = MAIN_BYTES + TAB_BYTES;
+};
+
+// One CSR entry in LDS.
+template <typename Acc> struct alignas(sizeof(Acc) == 8 ? 16 : 8) TabEnt {
+  int32_t off;  // (input index) * 64 * sizeof(Acc)
+  Acc coef;
+};
+
+template <int P, int W, int C, int WM, int WN, int RA, int RB, typename TZ>
+__global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs a, int64_t tiles_a,
+                                                                   int64_t tiles_y) {
+  using Cfg = FusedCfg<P, W, C, WM, WN, RA, RB>;
+  using T = typename Cfg::T;
+  using Acc = typename Cfg::Acc;
+  extern __shared__ __align__(16) char lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int q = lane >> 4, r16 = lane & 15;
+  int64_t ta, ty;
+  tile_coords(blockIdx.x, tiles_a * tiles_y, tiles_a, tiles_y, ta, ty);
+  const int64_t a0 = ta * Cfg::TA, y0 = ty * Cfg::TY;
+  const int64_t cl = a.chi_l, Y = (int64_t)a.nv * a.chi_r;
+  const T* Lp = static_cast<const T*>(a.L);
+  const T* Bp = static_cast<const T*>(a.psiT);
+  const int64_t nk = cl / Cfg::BK;
+
+  // Stage the W12 CSR table in LDS (read by every wave in the epilogue).
+  int32_t* tab_rp = reinterpret_cast<int32_t*>(lds + Cfg::MAIN_BYTES);
+  TabEnt<Acc>* tab_e = reinterpret_cast<TabEnt<Acc>*>(lds + Cfg::MAIN_BYTES + (Cfg::TAB_ROWS_MAX + 1) * 4);
+  {
+    const int nnz = a.row_ptr[a.nrows];
+    for (int i = tid; i <= a.nrows; i += Cfg::THREADS) tab_rp[i] = a.row_ptr[i];
+    for (int i = tid; i < nnz; i += Cfg::THREADS) {
+      TabEnt<Acc> t;
+      t.off = a.col_idx[i] * 64 * (int)sizeof(Acc);
+      t.coef = (P == P_F64) ? (Acc)a.coef64[i] : (Acc)a.coef32[i];
+      tab_e[i] = t;
+    }
+  }
+
+  typename Cfg::AccV acc[W][RA][C][RB];
+#pragma unroll
+  for (int m = 0; m < W; ++m)
+#pragma unroll
+    for (int i = 0; i < RA; ++i)
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[m][i][c][j][e] = 0;
+
+  // direct-to-LDS row sources (see gemm_core.h for the swizzle)
+  const int lrow = lane >> 3, lpos = lane & 7;
+  const int slab = wave * 8 + lrow;
+  const int64_t chunk = (int64_t)((lpos ^ lrow) * Cfg::E16);
+  auto srcA = [&](int p) -> const T* {
+    const int r = p * Cfg::RPP + slab;                 // tile row (m0, a')
+    const int m0 = r / Cfg::TA;
+    int64_t ap = a0 + r % Cfg::TA;
+    if (ap >= cl) ap = cl - 1;
+    return Lp + (ap * W + m0) * cl + chunk;
+  };
+  auto srcB = [&](int p) -> const T* {
+    const int r = p * Cfg::RPP + slab;                 // tile row (c, y)
+    const int c = r / Cfg::TY;
+    int64_t y = y0 + r % Cfg::TY;
+    if (y >= Y) y = Y - 1;
+    return Bp + ((int64_t)c * Y + y) * cl + chunk;
+  };
+  auto issue = [&](int buf, int64_t k0) {
+    char* base = lds + buf * Cfg::STAGE_BYTES + wave * 8 * ROW_BYTES;
+#pragma unroll
+    for (int p = 0; p < Cfg::A_PASSES; ++p)
+      if (p * Cfg::RPP + wave * 8 < Cfg::AROWS)
+        lds_direct16(srcA(p) + k0, base + p * Cfg::RPP * ROW_BYTES);
+#pragma unroll
+    for (int p = 0; p < Cfg::B_PASSES; ++p)
+      if (p * Cfg::RPP + wave * 8 < Cfg::BROWS)
+        lds_direct16(srcB(p) + k0, base + (Cfg::AROWS + p * Cfg::RPP) * ROW_BYTES);
+  };
+
+  if (nk > 0) {
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) issue(cur ^ 1, (kt + 1) * Cfg::BK);
+    const char* As = lds + cur * Cfg::STAGE_BYTES;
+    const char* Bs = As + Cfg::AROWS * ROW_BYTES;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int ch = ks * 4 + q;
+      uint4 bfr[C][RB];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          const int R = c * Cfg::TY + wn * 16 * RB + j * 16 + r16;
+          bfr[c][j] = *reinterpret_cast<const uint4*>(Bs + R * ROW_BYTES + ((ch ^ (R & 7)) << 4));
+        }
+#pragma unroll
+      for (int m = 0; m < W; ++m)
+#pragma unroll
+        for (int i = 0; i < RA; ++i) {
+          const int R = m * Cfg::TA + wm * 16 * RA + i * 16 + r16;
+          const uint4 af = *reinterpret_cast<const uint4*>(As + R * ROW_BYTES + ((ch ^ (R & 7)) << 4));
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int j = 0; j < RB; ++j) Mfma<P>::run(af, bfr[c][j], acc[m][i][c][j]);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+
+  // ------------------------------------------------------------ W epilogue
+  // The table writes above are ordered before these reads by the K loop's
+  // barriers (nk >= 1 is guaranteed by the dispatcher).
+  char* ep = lds + (int64_t)wave * (Cfg::GP * W * C * 64 * (int)sizeof(Acc));
+  const int64_t zs_v = cl * (int64_t)(C * W) * a.chi_r;  // Z stride of v
+  const int64_t zs_a = (int64_t)(C * W) * a.chi_r;       // Z stride of a'
+  TZ* Zp = static_cast<TZ*>(a.Z);
+  constexpr int GB = W * C * 64 * (int)sizeof(Acc);  // bytes of one group's area
+  const int nrows = a.nrows;
+#pragma unroll
+  for (int g0 = 0; g0 < Cfg::GROUPS; g0 += Cfg::GP) {
+    TZ* zrow[Cfg::GP];
+    bool ok[Cfg::GP];
+#pragma unroll
+    for (int gg = 0; gg < Cfg::GP; ++gg) {
+      const int g = g0 + gg;
+      const int i = g / (RB * 4), j = (g / 4) % RB, e = g % 4;
+#pragma unroll
+      for (int m = 0; m < W; ++m)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          *reinterpret_cast<Acc*>(ep + gg * GB + ((m * C + c) * 64 + lane) * (int)sizeof(Acc)) =
+              acc[m][i][c][j][e];
+      const int64_t ap = a0 + wm * 16 * RA + i * 16 + acc_row<P>(lane, e);
+      const int64_t y = y0 + wn * 16 * RB + j * 16 + (lane & 15);
+      ok[gg] = ap < cl && y < Y;
+      const int64_t v = ok[gg] ? y / a.chi_r : 0, b = ok[gg] ? y % a.chi_r : 0;
+      zrow[gg] = Zp + v * zs_v + ap * zs_a + b;
+    }
+    // each lane reads back only its own column: no barrier needed
+    const char* mine = ep + lane * (int)sizeof(Acc);
+    int k = tab_rp[0];
+    for (int o = 0; o < nrows; ++o) {
+      Acc z[Cfg::GP];
+#pragma unroll
+      for (int gg = 0; gg < Cfg::GP; ++gg) z[gg] = 0;
+      const int e1 = tab_rp[o + 1];
+      for (; k < e1; ++k) {
+        const TabEnt<Acc> t = tab_e[k];
+#pragma unroll
+        for (int gg = 0; gg < Cfg::GP; ++gg)
+          z[gg] += t.coef * *reinterpret_cast<const Acc*>(mine + gg * GB + t.off);
+      }
+#pragma unroll
+      for (int gg = 0; gg < Cfg::GP; ++gg)
+        if (ok[gg]) zrow[gg][(int64_t)o * a.chi_r] = cvt<TZ>(z[gg]);
+    }
+  }
+}
+
+template <int P> struct FusedPick;  // configuration per precision and (w, d^2)
+
+template <int P, int W, int C, int WM, int WN, int RA, int RB>
+static hipError_t launch_fused(const HeffFusedArgs& a, hipStream_t s) {
+  using Cfg = FusedCfg<P, W, C, WM, WN, RA, RB>;
+  using T = typename Cfg::T;
+  const int64_t Y = (int64_t)a.nv * a.chi_r;
+  const int64_t tiles_a = (a.chi_l + Cfg::TA - 1) / Cfg::TA, tiles_y = (Y + Cfg::TY - 1) / Cfg::TY;
+  if (tiles_a == 0 || tiles_y == 0) return hipSuccess;
+  auto kern = heff_fused_kernel<P, W, C, WM, WN, RA, RB, T>;
+  static const hipError_t attr =
+      Cfg::LDS_BYTES > 65536
+          ? hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, Cfg::LDS_BYTES)
+          : hipSuccess;
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(tiles_a * tiles_y)), dim3(Cfg::THREADS),
+                     Cfg::LDS_BYTES, s, a, tiles_a, tiles_y);
+  return hipGetLastError();
+}
+
+bool heff_fused_supported(int prec, int w, int d2) {
+  if (w != 5) return false;
+  if (d2 == 4) return true;
+  if (d2 == 9) return prec != P_F64;
+  return false;
+}
+
+bool heff_fused_table_fits(int nrows, int64_t nnz) {
+  return nrows <= 64 && nnz <= 480;
+}
+
+hipError_t heff_stage1_fused(int prec, const HeffFusedArgs& a, hipStream_t s) {
+  if (!heff_fused_supported(prec, a.w, a.d2)) return hipErrorInvalidValue;
+  switch (prec) {
+    case P_BF16:
+      if (a.d2 == 4) return launch_fused<P_BF16, 5, 4, 2, 4, 2, 1>(a, s);
+      return launch_fused<P_BF16, 5, 9, 4, 2, 1, 1>(a, s);
+    case P_F32:
+      if (a.d2 == 4) return launch_fused<P_F32, 5, 4, 2, 4, 2, 1>(a, s);
+      return launch_fused<P_F32, 5, 9, 4, 2, 1, 1>(a, s);
+    case P_F64:
+      return launch_fused<P_F64, 5, 4, 2, 4, 1, 1>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace itn

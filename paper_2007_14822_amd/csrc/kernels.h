@@ -101,6 +101,7 @@ struct HeffFusedArgs {
   const double* coef64;
 };
 bool heff_fused_supported(int prec, int w, int d2);
+bool heff_fused_table_fits(int nrows, int64_t nnz);
 hipError_t heff_stage1_fused(int prec, const HeffFusedArgs& a, hipStream_t s);
 
 // Element-wise conversion of a contiguous buffer.

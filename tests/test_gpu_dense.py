@@ -46,6 +46,7 @@ CONTRACT_CASES = [
     ({1: 6, 2: 5}, [1], [2], [1, 2]),                                      # outer product
     ({1: 6, 2: 5, 3: 4}, [1, 2, 3], [3, 1, 2], []),                        # inner product
     ({1: 130, 2: 70, 3: 129, 4: 3}, [1, 4, 2], [2, 3, 4], [3, 1]),         # several tiles
+    ({1: 4000, 2: 192, 3: 4100}, [1, 2], [3, 2], [1, 3]),                  # 256x256 tiles, ragged
 ]
 
 
@@ -109,6 +110,9 @@ HEFF_CASES = [
     (40, 52, 3, 11, 1, "rand"),    # AKLT-sized MPO, random sparse W
     (24, 20, 4, 18, 2, "rand"),    # Hubbard-sized MPO
     (150, 140, 2, 5, 1, "heis"),   # several tiles + tail
+    (128, 96, 2, 5, 2, "heis"),    # fused first stage (all precisions), ragged chi_r
+    (192, 70, 3, 5, 1, "heis"),    # fused first stage for d = 3 (bf16, f32)
+    (64, 200, 2, 5, 3, "rand"),    # fused, random sparse W, y tiles straddle vectors
 ]
 
 
@@ -154,6 +158,29 @@ def test_heff_on_canonical_envs(h, chi):
         out = torch.zeros(psi.shape, dtype=torch.float64, device=DEV)
         h.heff_apply(dev(L), W1, W2, dev(R), dev(psi), out, prec=prec)
         assert rel_err(host(out), ref) <= TOL[prec], prec
+
+
+def test_heff_full_size_sampled_rows(h):
+    """chi = 2048, the benchmark's workload and launch configuration: the
+    environments are built on the GPU (FP64 environment steps, checked
+    against the oracle at smaller sizes) and 6 output rows a' are compared
+    with the oracle."""
+    import torch as _t
+    from bench import build_workload
+    L64, W1, W2, R64, psi = build_workload(h, 2048, 2, _t, np, inp)
+    rows = [0, 1, 777, 1024, 2046, 2047]
+    Lh, Rh, ph = host(L64), host(R64), host(psi)
+    ref = hf.heff_apply_rows(Lh, W1, W2, Rh, ph, rows)
+    for prec, dt in (("bf16", _t.bfloat16), ("f32", _t.float32), ("f64", _t.float64)):
+        Lp = _t.empty(L64.shape, dtype=dt, device=DEV)
+        Rp = _t.empty(R64.shape, dtype=dt, device=DEV)
+        h.cast(L64, Lp)
+        h.cast(R64, Rp)
+        out = _t.zeros_like(psi)
+        h.heff_apply(Lp, W1, W2, Rp, psi, out, prec=prec)
+        got = host(out)[rows]
+        assert rel_err(got, ref) <= TOL[prec], prec
+        del Lp, Rp
 
 
 # ----------------------------------------------------------- environment step
