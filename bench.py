@@ -50,6 +50,16 @@ def heff_flops(chi_l, chi_r, d, w, nv=1):
                  + 4.0 * w * w * d ** 3 * chi_l * chi_r)
 
 
+def kernel_work(chi_l, chi_r, d, w, nv=1):
+    """Algorithmic work per launch of each kernel of one H_eff*psi:
+    flops for the matrix-core stages, HBM bytes for the memory-bound ones
+    (operand sizes at the precision in use are filled in by the caller)."""
+    s1 = 2.0 * w * d * d * chi_l * chi_l * chi_r * nv
+    sw = 4.0 * w * w * d ** 3 * chi_l * chi_r * nv
+    s4 = 2.0 * w * d * d * chi_l * chi_r * chi_r * nv
+    return {"heff_stage1_fused": s1 + sw, "heff_stage1_gemm": s1, "heff_stage4_gemm": s4}
+
+
 def build_workload(h, chi, d, torch, np, inp):
     """Random canonical MPS of N_c = 2 log2 chi + 2 sites, Heisenberg MPO;
     L = environment of the sites left of the centre bond, R of those right
@@ -145,6 +155,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--only", choices=["bf16", "f32", "f64"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after the timed work, copy a buffer of this many bytes 3 times "
+                         "(a plain copy kernel of known size, to calibrate HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -198,13 +211,18 @@ def main():
     head = precs[0]
     r = results[head]
     # dominant kernel and its roofline
+    work = kernel_work(chi, chi, d, w)
     kern = max(r["kernels"].items(), key=lambda kv: kv[1]["avg_ms"])
     kname, kst = kern[0], kern[1]
-    achieved = gemm_flops / (kst["avg_ms"] * 1e-3) / 1e12 if "gemm" in kname else None
+    fl = work.get(kname)
+    achieved = fl / (kst["avg_ms"] * 1e-3) / 1e12 if fl else None
     roof = {"bound": "mfma", "kernel": kname, "achieved": achieved, "peak": PEAK_TFLOPS[head],
             "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS[head]) if achieved else None,
-            "avg_ms": kst["avg_ms"], "flop_per_launch": gemm_flops,
-            "traffic": traffic_record(kname, "c1_chi%d_%s" % (chi, head))}
+            "traffic": traffic_record(kname, "c1_chi%d_%s" % (chi, head)),
+            "avg_ms": kst["avg_ms"], "flop_per_launch": fl}
+    for k, v in r["kernels"].items():
+        if k in work:
+            v["tflops"] = work[k] / (v["avg_ms"] * 1e-3) / 1e12
     line = {
         "metric": METRIC, "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1,
         "steps": r["steps"], "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
@@ -229,6 +247,14 @@ def main():
                                             psi.cpu().numpy(), chi, d, w, args.cpu_budget)
     else:
         line["cpu_baseline"] = None
+    if args.copy_probe > 0:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = n * 4
     print(json.dumps(line), flush=True)
 
 
