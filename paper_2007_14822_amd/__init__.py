@@ -191,3 +191,79 @@ class Handle:
         self._check(self.lib.itn_env_update(self.h, C.byref(te), C.byref(ta), C.byref(tw), dr,
                                             C.byref(to), PREC[prec], self._sp(stream)))
         return out
+
+    # ------------------------------------------------------------- sweeps
+    def mpo(self, Ws):
+        """Upload an MPO given as a list of N host arrays [w, w, d, d]."""
+        W = np.ascontiguousarray(np.stack([np.asarray(x, np.float64) for x in Ws]))
+        N, w, _, d, _ = W.shape
+        out = C.c_void_p()
+        self._check(self.lib.itn_mpo_create(self.h, N, w, d,
+                                            W.ctypes.data_as(C.POINTER(C.c_double)),
+                                            C.byref(out)))
+        return _Owned(self.lib.itn_mpo_destroy, out, N=N, w=w, d=d)
+
+    def mps(self, As):
+        """Upload an MPS given as a list of N host arrays [bond_l, d, bond_r]
+        (right-canonical, norm on site 0)."""
+        N = len(As)
+        d = As[0].shape[1]
+        bond = [As[0].shape[0]] + [A.shape[2] for A in As]
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(A, np.float64).ravel() for A in As]))
+        bd = (C.c_int32 * (N + 1))(*bond)
+        out = C.c_void_p()
+        self._check(self.lib.itn_mps_create(self.h, N, d, bd,
+                                            flat.ctypes.data_as(C.POINTER(C.c_double)),
+                                            C.byref(out)))
+        return _Owned(self.lib.itn_mps_destroy, out, N=N, d=d)
+
+    def mps_bonds(self, mps):
+        b = (C.c_int32 * (mps.N + 1))()
+        self._check(self.lib.itn_mps_bonds(mps.ptr, b))
+        return list(b)
+
+    def mps_sites(self, mps):
+        bond = self.mps_bonds(mps)
+        out = []
+        for i in range(mps.N):
+            a = np.zeros((bond[i], mps.d, bond[i + 1]))
+            self._check(self.lib.itn_mps_get_site(self.h, mps.ptr, i,
+                                                  a.ctypes.data_as(C.POINTER(C.c_double))))
+            out.append(a)
+        return out
+
+    def dmrg_sweep(self, mps, mpo, sweeps, prec="f64", mindim=1, krylovdim=8, maxiter=100,
+                   eig_tol=1e-10, refine=True, energy_tol=0.0, allow_unconverged=False):
+        """Run a schedule [(maxdim, cutoff), ...]; returns per-sweep records."""
+        ns = len(sweeps)
+        md = (C.c_int32 * max(1, ns))(*[int(m) for m, _ in sweeps])
+        co = (C.c_double * max(1, ns))(*[float(c) for _, c in sweeps])
+        prm = L.itn_sweep_params(ns, md, co, int(mindim), int(krylovdim), int(maxiter),
+                                 float(eig_tol), PREC[prec], 1 if refine else 0, float(energy_tol))
+        arrs = {k: (t * max(1, ns))() for k, t in (("energy", C.c_double), ("max_trunc", C.c_double),
+                                                   ("max_bond", C.c_int32), ("seconds", C.c_double),
+                                                   ("matvecs", C.c_int64), ("residual", C.c_double))}
+        res = L.itn_sweep_result(0, arrs["energy"], arrs["max_trunc"], arrs["max_bond"],
+                                 arrs["seconds"], arrs["matvecs"], arrs["residual"])
+        st = self.lib.itn_dmrg_sweep(self.h, mps.ptr, mpo.ptr, C.byref(prm), C.byref(res))
+        if not (allow_unconverged and st == 9):
+            self._check(st)
+        return [{k: arrs[k][i] for k in arrs} for i in range(res.sweeps_done)]
+
+
+class _Owned:
+    """An opaque library object freed with its destroy call."""
+
+    def __init__(self, destroy, ptr, **info):
+        self._destroy = destroy
+        self.ptr = ptr
+        for k, v in info.items():
+            setattr(self, k, v)
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                self._destroy(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass

@@ -1,0 +1,630 @@
+// Two-site DMRG sweep driver of libitn: FP64 Davidson eigensolver with
+// matrix-core matvecs, FP64 truncated bond split on rocSOLVER, environment
+// updates, sweep schedule (the DMRG algorithm of Sec. 7.2 with the
+// truncation of Sec. 5).
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "handle.h"
+
+using namespace itn;
+
+struct itn_mpo {
+  int32_t N = 0, w = 0, d = 0;
+  std::vector<double> W;  // host, N * w*w*d*d
+  const double* site(int i) const { return W.data() + (size_t)i * w * w * d * d; }
+};
+
+namespace {
+
+// Device buffer that only grows.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  itn_status ensure(itn_handle* h, size_t b) {
+    if (b <= bytes) return ITN_OK;
+    if (p) {
+      ITN_HIP(h, hipDeviceSynchronize());
+      ITN_HIP(h, hipFree(p));
+    }
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      return fail(h, ITN_E_WORKSPACE, "allocation of %zu bytes failed", b);
+    }
+    bytes = b;
+    return ITN_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  double* d() const { return static_cast<double*>(p); }
+};
+
+}  // namespace
+
+struct itn_mps {
+  int32_t N = 0, d = 0;
+  std::vector<int32_t> bond;   // N+1
+  std::vector<DBuf> site;      // N, FP64 [bond[i], d, bond[i+1]]
+  std::vector<DBuf> Lenv;      // N+1: Lenv[k] = environment of sites [0, k)
+  std::vector<DBuf> Renv;      // N+1: Renv[k] = environment of sites [k, N)
+  bool envs = false;
+  int mpo_w = 0;
+  // driver scratch
+  DBuf psi, tmp, rho, evec, eval, einfo, V, AV, Lp, Rp, partial, dots, ev_host_stage;
+  ~itn_mps() {
+    for (auto& b : site) b.release();
+    for (auto& b : Lenv) b.release();
+    for (auto& b : Renv) b.release();
+    for (DBuf* b : {&psi, &tmp, &rho, &evec, &eval, &einfo, &V, &AV, &Lp, &Rp, &partial, &dots,
+                    &ev_host_stage})
+      b->release();
+  }
+};
+
+extern "C" void itn_release_solver(itn_handle* h) {
+  if (h && h->solver) {
+    rocblas_destroy_handle(static_cast<rocblas_handle>(h->solver));
+    h->solver = nullptr;
+  }
+}
+
+namespace {
+
+// ------------------------------------------------------------ small eigh
+// Cyclic Jacobi for a symmetric k x k matrix (row-major); eigenvalues
+// ascending in w, eigenvectors as the columns of V (row-major k x k).
+void jacobi_eigh(int k, std::vector<double> A, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) V[i * k + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        tot += A[i * k + j] * A[i * k + j];
+        if (i != j) off += A[i * k + j] * A[i * k + j];
+      }
+    if (off <= 1e-32 * std::max(tot, 1e-300)) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[p * k + q];
+        if (apq == 0.0) continue;
+        const double app = A[p * k + p], aqq = A[q * k + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < k; ++r) {  // A <- A J (columns p, q)
+          const double arp = A[r * k + p], arq = A[r * k + q];
+          A[r * k + p] = c * arp - s * arq;
+          A[r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {  // A <- J^T A (rows p, q)
+          const double apr = A[p * k + r], aqr = A[q * k + r];
+          A[p * k + r] = c * apr - s * aqr;
+          A[q * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = V[r * k + p], vrq = V[r * k + q];
+          V[r * k + p] = c * vrp - s * vrq;
+          V[r * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  std::vector<int> idx(k);
+  for (int i = 0; i < k; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[a * k + a] < A[b * k + b]; });
+  w.resize(k);
+  std::vector<double> V2((size_t)k * k);
+  for (int j = 0; j < k; ++j) {
+    w[j] = A[idx[j] * k + idx[j]];
+    for (int r = 0; r < k; ++r) V2[r * k + j] = V[r * k + idx[j]];
+  }
+  V.swap(V2);
+}
+
+itn_tensor dense_t(int rank, const int64_t* dims, itn_dtype dt, void* data) {
+  itn_tensor t{};
+  t.rank = rank;
+  t.dims = dims;
+  t.dtype = dt;
+  t.data = data;
+  return t;
+}
+
+// C[M,N] = A[M,K] * B[N,K]^T, FP64 operands and output.
+hipError_t gemm64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                  int64_t M, int64_t N, int64_t K, hipStream_t s) {
+  GemmArgs g{};
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.batch = 1;
+  return gemm_nt(P_F64, D_F64, g, s);
+}
+
+// out[c][r] = in[r][c] for an rows x cols FP64 matrix.
+hipError_t transpose64(const double* in, double* out, int64_t rows, int64_t cols, hipStream_t s) {
+  TransposeArgs t{};
+  t.rows = rows;
+  t.cols = cols;
+  t.nzb = 1;
+  t.nzc = 1;
+  t.in_r = cols;
+  t.in_c = 1;
+  t.out_c = rows;
+  t.out_r = 1;
+  return transpose_cast(D_F64, in, D_F64, out, t, s);
+}
+
+struct Ctx {
+  itn_handle* h;
+  itn_mps* m;
+  const itn_mpo* mpo;
+  const itn_sweep_params* p;
+  hipStream_t s = nullptr;
+  int64_t matvecs = 0;
+  double max_resid = 0.0;
+  bool unconverged = false;
+};
+
+// y = H_eff x at precision `prec` (FP64 vectors), through the public entry point.
+itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl, int64_t cr) {
+  const int w = c.mpo->w, d = c.mpo->d;
+  const int64_t dl[3] = {cl, w, cl}, dr[3] = {cr, w, cr}, dw[4] = {w, w, d, d};
+  const int64_t dp[4] = {cl, d, d, cr};
+  const bool low = prec != ITN_P_F64;
+  const itn_dtype et = prec == ITN_P_BF16 ? ITN_BF16 : (prec == ITN_P_F32 ? ITN_F32 : ITN_F64);
+  itn_tensor L = dense_t(3, dl, et, low ? c.m->Lp.p : c.m->Lenv[i].p);
+  itn_tensor R = dense_t(3, dr, et, low ? c.m->Rp.p : c.m->Renv[i + 2].p);
+  itn_tensor W1 = dense_t(4, dw, ITN_F64, const_cast<double*>(c.mpo->site(i)));
+  itn_tensor W2 = dense_t(4, dw, ITN_F64, const_cast<double*>(c.mpo->site(i + 1)));
+  itn_tensor P = dense_t(4, dp, ITN_F64, const_cast<double*>(x));
+  itn_tensor O = dense_t(4, dp, ITN_F64, y);
+  c.matvecs++;
+  return itn_heff_apply(c.h, &L, &W1, &W2, &R, &P, 1, &O, (itn_prec)prec, c.s);
+}
+
+// <V_j, w> for j < k, to host.
+itn_status dots(Ctx& c, const double* V, int64_t n, int k, const double* w, double* out) {
+  ITN_TRY(c.m->partial.ensure(c.h, (size_t)k * dot_blocks(n) * 8));
+  ITN_TRY(c.m->dots.ensure(c.h, (size_t)k * 8 + 8));
+  ITN_HIP(c.h, multi_dot(V, n, k, w, n, c.m->partial.d(), c.m->dots.d(), c.s));
+  ITN_HIP(c.h, hipMemcpyAsync(out, c.m->dots.p, (size_t)k * 8, hipMemcpyDeviceToHost, c.s));
+  ITN_HIP(c.h, hipStreamSynchronize(c.s));
+  return ITN_OK;
+}
+
+// Lowest eigenpair of H_eff at bond i by Davidson (identity preconditioner,
+// full re-orthogonalisation, restart from the Ritz vector), FP64 vectors.
+// psi (in/out, length n) is the start vector and the result.
+// *converged is false only when maxiter matvecs ended above the tolerance; a
+// residual already inside the Krylov space (no new direction) is at the
+// arithmetic's noise floor and counts as converged.
+itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* psi, int64_t n,
+                    int64_t cl, int64_t cr, double* energy, double* resid, bool* converged) {
+  const int kmax = std::max(4, std::min(c.p->krylovdim, 32));
+  constexpr int KEEP = 3;  // Ritz vectors kept at a restart (thick restart)
+  ITN_TRY(c.m->V.ensure(c.h, (size_t)(kmax + KEEP) * n * 8));
+  ITN_TRY(c.m->AV.ensure(c.h, (size_t)(kmax + KEEP) * n * 8));
+  double* V = c.m->V.d();
+  double* AV = c.m->AV.d();
+  std::vector<double> Hk((size_t)kmax * kmax, 0.0), tmp(kmax + 1);
+  double nrm2;
+  ITN_TRY(dots(c, psi, n, 1, psi, &nrm2));
+  if (!(nrm2 > 0)) return fail(c.h, ITN_E_ARG, "zero start vector at bond %d", i);
+  ITN_HIP(c.h, hipMemcpyAsync(V, psi, n * 8, hipMemcpyDeviceToDevice, c.s));
+  ITN_HIP(c.h, scale(V, 1.0 / std::sqrt(nrm2), n, c.s));
+  ITN_TRY(heff(c, i, prec, V, AV, cl, cr));
+  int k = 1;
+  double theta = 0.0, rn = 0.0;
+  bool conv = false;
+  std::vector<double> w, Y;
+  for (int it = 0;; ++it) {
+    // new column k-1 of the projected matrix
+    ITN_TRY(dots(c, V, n, k, AV + (size_t)(k - 1) * n, tmp.data()));
+    for (int a = 0; a < k; ++a) {
+      Hk[a * kmax + (k - 1)] = tmp[a];
+      Hk[(k - 1) * kmax + a] = tmp[a];
+    }
+    std::vector<double> Hs((size_t)k * k);
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) Hs[a * k + b] = 0.5 * (Hk[a * kmax + b] + Hk[b * kmax + a]);
+    jacobi_eigh(k, Hs, w, Y);
+    theta = w[0];
+    std::vector<double> y(k);
+    for (int a = 0; a < k; ++a) y[a] = Y[a * k + 0];
+    // x = V y (slot kmax), r = AV y - theta x (into psi as scratch)
+    double* x = V + (size_t)kmax * n;
+    double* ax = AV + (size_t)kmax * n;
+    ITN_HIP(c.h, lincomb(V, n, k, y.data(), 0.0, x, n, c.s));
+    ITN_HIP(c.h, lincomb(AV, n, k, y.data(), 0.0, ax, n, c.s));
+    double cf[2] = {1.0, -theta};
+    // psi <- ax - theta x   (lincomb over the two contiguous slots)
+    ITN_HIP(c.h, lincomb(x, n, 1, &cf[1], 0.0, psi, n, c.s));
+    ITN_HIP(c.h, lincomb(ax, n, 1, &cf[0], 1.0, psi, n, c.s));
+    double r2;
+    ITN_TRY(dots(c, psi, n, 1, psi, &r2));
+    rn = std::sqrt(std::max(r2, 0.0));
+    if (rn <= tol * std::max(1.0, std::fabs(theta))) {
+      conv = true;
+      break;
+    }
+    if (it + 1 >= maxiter) break;
+    if (k == kmax) {  // thick restart from the lowest KEEP Ritz vectors
+      const int keep = std::min(KEEP, k - 1);
+      for (int j = 0; j < keep; ++j) {
+        std::vector<double> yj(k);
+        for (int a = 0; a < k; ++a) yj[a] = Y[a * k + j];
+        ITN_HIP(c.h, lincomb(V, n, k, yj.data(), 0.0, V + (size_t)(kmax + j) * n, n, c.s));
+        ITN_HIP(c.h, lincomb(AV, n, k, yj.data(), 0.0, AV + (size_t)(kmax + j) * n, n, c.s));
+      }
+      ITN_HIP(c.h, hipMemcpyAsync(V, V + (size_t)kmax * n, (size_t)keep * n * 8,
+                                  hipMemcpyDeviceToDevice, c.s));
+      ITN_HIP(c.h, hipMemcpyAsync(AV, AV + (size_t)kmax * n, (size_t)keep * n * 8,
+                                  hipMemcpyDeviceToDevice, c.s));
+      std::fill(Hk.begin(), Hk.end(), 0.0);
+      for (int j = 0; j < keep; ++j) Hk[j * kmax + j] = w[j];
+      k = keep;
+    }
+    // t = r orthogonalised twice against V, normalised
+    for (int rep = 0; rep < 2; ++rep) {
+      ITN_TRY(dots(c, V, n, k, psi, tmp.data()));
+      for (int a = 0; a < k; ++a) tmp[a] = -tmp[a];
+      ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, psi, n, c.s));
+    }
+    double t2;
+    ITN_TRY(dots(c, psi, n, 1, psi, &t2));
+    if (!(t2 > 1e-28 * std::max(1.0, r2))) {  // no new direction
+      conv = true;
+      break;
+    }
+    ITN_HIP(c.h, hipMemcpyAsync(V + (size_t)k * n, psi, n * 8, hipMemcpyDeviceToDevice, c.s));
+    ITN_HIP(c.h, scale(V + (size_t)k * n, 1.0 / std::sqrt(t2), n, c.s));
+    ITN_TRY(heff(c, i, prec, V + (size_t)k * n, AV + (size_t)k * n, cl, cr));
+    ++k;
+  }
+  ITN_HIP(c.h, hipMemcpyAsync(psi, V + (size_t)kmax * n, n * 8, hipMemcpyDeviceToDevice, c.s));
+  *energy = theta;
+  *resid = rn;
+  *converged = conv;
+  return ITN_OK;
+}
+
+rocblas_handle solver(Ctx& c) {
+  if (!c.h->solver) {
+    rocblas_handle r = nullptr;
+    if (rocblas_create_handle(&r) != rocblas_status_success) return nullptr;
+    c.h->solver = r;
+  }
+  rocblas_handle r = static_cast<rocblas_handle>(c.h->solver);
+  rocblas_set_stream(r, c.s);
+  return r;
+}
+
+// Keep count per Sec. 5: discard the smallest weights while their running sum
+// stays within the cutoff, cap at maxdim, keep at least mindim (and one).
+int truncation_keep(const std::vector<double>& p_desc, double cutoff, int maxdim, int mindim,
+                    double* discarded) {
+  const int n = (int)p_desc.size();
+  int keep = n;
+  double disc = 0.0;
+  while (keep > 1 && disc + p_desc[keep - 1] <= cutoff) {
+    disc += p_desc[keep - 1];
+    --keep;
+  }
+  keep = std::min(keep, maxdim);
+  keep = std::max(keep, std::min(std::max(mindim, 1), n));
+  double d = 0.0;
+  for (int j = keep; j < n; ++j) d += p_desc[j];
+  *discarded = d;
+  return keep;
+}
+
+// Split psi [cl, d, d, cr] at bond i and store the new sites i, i+1.
+itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdim, double cutoff,
+                 double* trunc) {
+  itn_mps* m = c.m;
+  const int d = c.m->d;
+  const int64_t nl = cl * d, nr = cr * d;  // M is nl x nr
+  const int64_t n = to_right ? nl : nr;    // density-matrix dimension
+  double* M = m->psi.d();
+  ITN_TRY(m->tmp.ensure(c.h, (size_t)nl * nr * 8));
+  ITN_TRY(m->rho.ensure(c.h, (size_t)n * n * 8));
+  ITN_TRY(m->eval.ensure(c.h, (size_t)n * 2 * 8));
+  ITN_TRY(m->einfo.ensure(c.h, 64));
+  double* MT = m->tmp.d();
+  ITN_HIP(c.h, transpose64(M, MT, nl, nr, c.s));  // MT [nr][nl]
+  double* rho = m->rho.d();
+  if (to_right) ITN_HIP(c.h, gemm64(M, nr, M, nr, rho, n, n, n, nr, c.s));      // M M^T
+  else ITN_HIP(c.h, gemm64(MT, nl, MT, nl, rho, n, n, n, nl, c.s));             // M^T M
+  rocblas_handle rb = solver(c);
+  if (!rb) return fail(c.h, ITN_E_HIP, "rocblas handle creation failed");
+  double* D = m->eval.d();
+  double* E = D + n;
+  rocblas_status st = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+                                       rho, (rocblas_int)n, D, E,
+                                       static_cast<rocblas_int*>(m->einfo.p));
+  if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd failed (%d)", (int)st);
+  std::vector<double> ev(n);
+  rocblas_int info = 0;
+  ITN_HIP(c.h, hipMemcpyAsync(ev.data(), D, n * 8, hipMemcpyDeviceToHost, c.s));
+  ITN_HIP(c.h, hipMemcpyAsync(&info, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
+  ITN_HIP(c.h, hipStreamSynchronize(c.s));
+  if (info != 0) return fail(c.h, ITN_E_NOT_CONVERGED, "rocsolver_dsyevd info=%d at bond %d", (int)info, i);
+  // weights, descending
+  std::vector<double> pd(n);
+  double tot = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    pd[j] = std::max(ev[n - 1 - j], 0.0);
+    tot += pd[j];
+  }
+  if (!(tot > 0)) return fail(c.h, ITN_E_ARG, "zero two-site state at bond %d", i);
+  for (auto& x : pd) x /= tot;
+  const int k = truncation_keep(pd, cutoff, maxdim, c.p->mindim, trunc);
+  double kept = 0.0;
+  for (int j = 0; j < k; ++j) kept += pd[j] * tot;
+  const double inv = 1.0 / std::sqrt(kept);
+  // Uk^T: rows = eigenvectors n-1, n-2, ..., n-k (column j of rho holds eigenvector j)
+  ITN_TRY(m->evec.ensure(c.h, (size_t)k * n * 8));
+  double* Ukt = m->evec.d();
+  ITN_HIP(c.h, hipMemcpy2DAsync(Ukt, n * 8, rho + (size_t)(n - k) * n, n * 8, n * 8, k,
+                                hipMemcpyDeviceToDevice, c.s));
+  // reverse row order so row 0 is the largest weight
+  {
+    const int64_t dims[2] = {k, n};
+    const int64_t strides[2] = {-n, 1};
+    ITN_TRY(m->Lp.ensure(c.h, (size_t)k * n * 8));  // scratch before the next bond
+    ITN_HIP(c.h, permute_cast(D_F64, Ukt + (size_t)(k - 1) * n, D_F64, m->Lp.p, 2, dims, strides, c.s));
+    ITN_HIP(c.h, hipMemcpyAsync(Ukt, m->Lp.p, (size_t)k * n * 8, hipMemcpyDeviceToDevice, c.s));
+  }
+  DBuf& Sa = m->site[i];
+  DBuf& Sb = m->site[i + 1];
+  ITN_TRY(Sa.ensure(c.h, (size_t)cl * d * k * 8));
+  ITN_TRY(Sb.ensure(c.h, (size_t)k * d * cr * 8));
+  if (to_right) {
+    // A_i[(a s1), j] = U[(a s1), j];  A_{i+1}[j, (s2 b)] = (U^T M)[j, (s2 b)] / |S_k|
+    ITN_HIP(c.h, transpose64(Ukt, Sa.d(), k, nl, c.s));
+    ITN_HIP(c.h, gemm64(Ukt, nl, MT, nl, Sb.d(), nr, k, nr, nl, c.s));
+    ITN_HIP(c.h, scale(Sb.d(), inv, (int64_t)k * nr, c.s));
+  } else {
+    // A_{i+1}[j, (s2 b)] = V^T[j, (s2 b)];  A_i[(a s1), j] = (M V)[(a s1), j] / |S_k|
+    ITN_HIP(c.h, hipMemcpyAsync(Sb.p, Ukt, (size_t)k * nr * 8, hipMemcpyDeviceToDevice, c.s));
+    ITN_HIP(c.h, gemm64(M, nr, Ukt, nr, Sa.d(), k, nl, k, nr, c.s));
+    ITN_HIP(c.h, scale(Sa.d(), inv, nl * (int64_t)k, c.s));
+  }
+  m->bond[i + 1] = k;
+  return ITN_OK;
+}
+
+itn_status env_step(Ctx& c, int i, bool left) {
+  itn_mps* m = c.m;
+  const int w = c.mpo->w, d = m->d;
+  const int64_t dw[4] = {w, w, d, d};
+  itn_tensor Wt = dense_t(4, dw, ITN_F64, const_cast<double*>(c.mpo->site(i)));
+  if (left) {  // Lenv[i+1] from Lenv[i] and site i
+    const int64_t a = m->bond[i], b = m->bond[i + 1];
+    const int64_t de[3] = {a, w, a}, da[3] = {a, d, b}, doo[3] = {b, w, b};
+    ITN_TRY(m->Lenv[i + 1].ensure(c.h, (size_t)b * w * b * 8));
+    itn_tensor E = dense_t(3, de, ITN_F64, m->Lenv[i].p);
+    itn_tensor A = dense_t(3, da, ITN_F64, m->site[i].p);
+    itn_tensor O = dense_t(3, doo, ITN_F64, m->Lenv[i + 1].p);
+    return itn_env_update(c.h, &E, &A, &Wt, ITN_LEFT, &O, ITN_P_F64, c.s);
+  }
+  // Renv[i] from Renv[i+1] and site i
+  const int64_t a = m->bond[i], b = m->bond[i + 1];
+  const int64_t de[3] = {b, w, b}, da[3] = {a, d, b}, doo[3] = {a, w, a};
+  ITN_TRY(m->Renv[i].ensure(c.h, (size_t)a * w * a * 8));
+  itn_tensor E = dense_t(3, de, ITN_F64, m->Renv[i + 1].p);
+  itn_tensor A = dense_t(3, da, ITN_F64, m->site[i].p);
+  itn_tensor O = dense_t(3, doo, ITN_F64, m->Renv[i].p);
+  return itn_env_update(c.h, &E, &A, &Wt, ITN_RIGHT, &O, ITN_P_F64, c.s);
+}
+
+itn_status boundary(Ctx& c, DBuf& b, int channel) {
+  const int w = c.mpo->w;
+  ITN_TRY(b.ensure(c.h, (size_t)w * 8));
+  std::vector<double> v(w, 0.0);
+  v[channel] = 1.0;
+  ITN_HIP(c.h, hipMemcpy(b.p, v.data(), w * 8, hipMemcpyHostToDevice));
+  return ITN_OK;
+}
+
+// One bond: form psi, eigensolve, split, extend the environment.
+itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, double* energy,
+                     double* trunc) {
+  itn_mps* m = c.m;
+  const int d = m->d;
+  const int64_t cl = m->bond[i], cm = m->bond[i + 1], cr = m->bond[i + 2];
+  const int64_t n = cl * d * d * cr;
+  ITN_TRY(m->psi.ensure(c.h, (size_t)n * 8));
+  ITN_TRY(m->tmp.ensure(c.h, (size_t)std::max<int64_t>(n, cm * d * cr) * 8));
+  // psi[(a s1), (s2 b)] = A_i[(a s1), m] A_{i+1}[m, (s2 b)]
+  ITN_HIP(c.h, transpose64(m->site[i + 1].d(), m->tmp.d(), cm, d * cr, c.s));
+  ITN_HIP(c.h, gemm64(m->site[i].d(), cm, m->tmp.d(), cm, m->psi.d(), d * cr, cl * d, d * cr, cm, c.s));
+  // operands in the matvec precision, once per bond
+  const int prec = c.p->prec;
+  if (prec != ITN_P_F64) {
+    const int dt = prec == ITN_P_BF16 ? D_BF16 : D_F32;
+    const int w = c.mpo->w;
+    ITN_TRY(m->Lp.ensure(c.h, (size_t)cl * w * cl * 4 + 256));
+    ITN_TRY(m->Rp.ensure(c.h, (size_t)cr * w * cr * 4 + 256));
+    ITN_HIP(c.h, cast(D_F64, m->Lenv[i].p, dt, m->Lp.p, cl * w * cl, c.s));
+    ITN_HIP(c.h, cast(D_F64, m->Renv[i + 2].p, dt, m->Rp.p, cr * w * cr, c.s));
+  }
+  const double tol = c.p->eig_tol > 0 ? c.p->eig_tol : 1e-10;
+  const int maxiter = c.p->maxiter > 0 ? c.p->maxiter : 100;
+  double e = 0.0, r = 0.0;
+  bool conv = true;
+  if (prec == ITN_P_F64) {
+    ITN_TRY(davidson(c, i, ITN_P_F64, tol, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
+  } else {
+    // low-precision phase to its own noise floor, then FP64 refinement
+    const double tol_lo = std::max(tol, prec == ITN_P_BF16 ? 2e-2 : 2e-5);
+    ITN_TRY(davidson(c, i, prec, tol_lo, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
+    if (c.p->refine)
+      ITN_TRY(davidson(c, i, ITN_P_F64, tol, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
+  }
+  c.max_resid = std::max(c.max_resid, r);
+  if (!conv && (prec == ITN_P_F64 || c.p->refine)) c.unconverged = true;
+  *energy = e;
+  ITN_TRY(split(c, i, to_right, cl, cr, maxdim, cutoff, trunc));
+  if (to_right) ITN_TRY(env_step(c, i, true));
+  else ITN_TRY(env_step(c, i + 1, false));
+  return ITN_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- ABI
+extern "C" {
+
+itn_status itn_mpo_create(itn_handle* h, int32_t N, int32_t w, int32_t d, const double* W_host,
+                          itn_mpo** mpo) {
+  if (!h || !mpo || !W_host) return h ? fail(h, ITN_E_ARG, "null argument") : ITN_E_ARG;
+  *mpo = nullptr;
+  if (N < 2 || w < 1 || d < 1) return fail(h, ITN_E_ARG, "need N >= 2, w >= 1, d >= 1");
+  auto* o = new itn_mpo();
+  o->N = N;
+  o->w = w;
+  o->d = d;
+  o->W.assign(W_host, W_host + (size_t)N * w * w * d * d);
+  *mpo = o;
+  return ITN_OK;
+}
+
+itn_status itn_mpo_destroy(itn_mpo* mpo) {
+  delete mpo;
+  return ITN_OK;
+}
+
+itn_status itn_mps_create(itn_handle* h, int32_t N, int32_t d, const int32_t* bond,
+                          const double* sites_host, itn_mps** mps) {
+  if (!h || !mps || !bond || !sites_host) return h ? fail(h, ITN_E_ARG, "null argument") : ITN_E_ARG;
+  *mps = nullptr;
+  if (N < 2 || d < 1) return fail(h, ITN_E_ARG, "need N >= 2, d >= 1");
+  if (bond[0] != 1 || bond[N] != 1) return fail(h, ITN_E_SHAPE, "bond[0] and bond[N] must be 1");
+  for (int i = 0; i <= N; ++i)
+    if (bond[i] < 1) return fail(h, ITN_E_SHAPE, "bond dimensions must be >= 1");
+  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot hold an MPS");
+  auto* m = new itn_mps();
+  m->N = N;
+  m->d = d;
+  m->bond.assign(bond, bond + N + 1);
+  m->site.resize(N);
+  m->Lenv.resize(N + 1);
+  m->Renv.resize(N + 1);
+  size_t off = 0;
+  for (int i = 0; i < N; ++i) {
+    const size_t n = (size_t)bond[i] * d * bond[i + 1];
+    itn_status st = m->site[i].ensure(h, n * 8);
+    if (st == ITN_OK && hipMemcpy(m->site[i].p, sites_host + off, n * 8, hipMemcpyHostToDevice) != hipSuccess)
+      st = fail(h, ITN_E_HIP, "upload of site %d failed", i);
+    if (st != ITN_OK) {
+      delete m;
+      return st;
+    }
+    off += n;
+  }
+  *mps = m;
+  return ITN_OK;
+}
+
+itn_status itn_mps_destroy(itn_mps* mps) {
+  if (mps) (void)hipDeviceSynchronize();
+  delete mps;
+  return ITN_OK;
+}
+
+itn_status itn_mps_bonds(const itn_mps* mps, int32_t* bond) {
+  if (!mps || !bond) return ITN_E_ARG;
+  std::copy(mps->bond.begin(), mps->bond.end(), bond);
+  return ITN_OK;
+}
+
+itn_status itn_mps_get_site(itn_handle* h, const itn_mps* mps, int32_t i, double* host) {
+  if (!h || !mps || !host) return ITN_E_ARG;
+  if (i < 0 || i >= mps->N) return fail(h, ITN_E_ARG, "site index out of range");
+  const size_t n = (size_t)mps->bond[i] * mps->d * mps->bond[i + 1];
+  ITN_HIP(h, hipDeviceSynchronize());
+  ITN_HIP(h, hipMemcpy(host, mps->site[i].p, n * 8, hipMemcpyDeviceToHost));
+  return ITN_OK;
+}
+
+itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
+                          const itn_sweep_params* p, itn_sweep_result* res) {
+  if (!h || !mps || !mpo || !p) return h ? fail(h, ITN_E_ARG, "null argument") : ITN_E_ARG;
+  if (mpo->N != mps->N || mpo->d != mps->d)
+    return fail(h, ITN_E_SHAPE, "MPO (N=%d, d=%d) does not match the MPS (N=%d, d=%d)", mpo->N,
+                mpo->d, mps->N, mps->d);
+  if (p->nsweeps < 0 || (p->nsweeps > 0 && (!p->maxdim || !p->cutoff)))
+    return fail(h, ITN_E_ARG, "bad sweep schedule");
+  if (p->prec != ITN_P_F64 && p->prec != ITN_P_F32 && p->prec != ITN_P_BF16)
+    return fail(h, ITN_E_ARG, "unknown precision");
+  for (int k = 0; k < p->nsweeps; ++k)
+    if (p->maxdim[k] < 1 || p->cutoff[k] < 0) return fail(h, ITN_E_ARG, "bad maxdim/cutoff");
+  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot run sweeps");
+  Ctx c;
+  c.h = h;
+  c.m = mps;
+  c.mpo = mpo;
+  c.p = p;
+  const int N = mps->N;
+  if (!mps->envs || mps->mpo_w != mpo->w) {
+    ITN_TRY(boundary(c, mps->Lenv[0], mpo->w - 1));
+    ITN_TRY(boundary(c, mps->Renv[N], 0));
+    for (int i = N - 1; i >= 2; --i) ITN_TRY(env_step(c, i, false));
+    mps->envs = true;
+    mps->mpo_w = mpo->w;
+  }
+  if (res) res->sweeps_done = 0;
+  double prevE = 0.0;
+  for (int sw = 0; sw < p->nsweeps; ++sw) {
+    auto t0 = std::chrono::steady_clock::now();
+    c.matvecs = 0;
+    c.max_resid = 0.0;
+    double E = 0.0, maxtr = 0.0, tr = 0.0;
+    for (int i = 0; i <= N - 2; ++i) {
+      ITN_TRY(bond_step(c, i, true, p->maxdim[sw], p->cutoff[sw], &E, &tr));
+      maxtr = std::max(maxtr, tr);
+    }
+    for (int i = N - 2; i >= 0; --i) {
+      ITN_TRY(bond_step(c, i, false, p->maxdim[sw], p->cutoff[sw], &E, &tr));
+      maxtr = std::max(maxtr, tr);
+    }
+    ITN_HIP(h, hipStreamSynchronize(c.s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (res) {
+      if (res->energy) res->energy[sw] = E;
+      if (res->max_trunc) res->max_trunc[sw] = maxtr;
+      if (res->max_bond) res->max_bond[sw] = *std::max_element(mps->bond.begin(), mps->bond.end());
+      if (res->seconds) res->seconds[sw] = secs;
+      if (res->matvecs) res->matvecs[sw] = c.matvecs;
+      if (res->residual) res->residual[sw] = c.max_resid;
+      res->sweeps_done = sw + 1;
+    }
+    if (sw > 0 && p->energy_tol > 0 && std::fabs(E - prevE) < p->energy_tol * std::fabs(E)) break;
+    prevE = E;
+  }
+  if (c.unconverged)
+    return fail(h, ITN_E_NOT_CONVERGED, "a local eigensolve ended above its tolerance (max residual %.3e)",
+                c.max_resid);
+  return ITN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+"""GPU two-site DMRG sweeps (FP64 Davidson, rocSOLVER bond split) through
+the C ABI, against exact diagonalisation and the oracle."""
+import numpy as np
+import pytest
+
+import paper_2007_14822_amd as itn
+from paper_2007_14822_amd import inputs as inp
+from oracle import dmrg as odmrg, ed, heff as hf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    return itn.Handle(0)
+
+
+@pytest.fixture(scope="module")
+def e_ed10():
+    return float(np.linalg.eigvalsh(ed.heisenberg_dense(10))[0])
+
+
+def run(h, Ws, As0, sweeps, **kw):
+    mpo = h.mpo(Ws)
+    mps = h.mps(As0)
+    recs = h.dmrg_sweep(mps, mpo, sweeps, **kw)
+    return recs, mps
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_c0_heisenberg_matches_ed(h, e_ed10, prec):
+    """N=10 S=1/2, maxdim 32 (an exact representation), 5 sweeps, random
+    product start: |E - E_ED| / |E_ED| <= 1e-10 (FP64), and the same for the
+    mixed-precision runs after their FP64 refinement."""
+    N = 10
+    As0 = inp.random_product_state(N, 2, inp.rng_for(0, 32))
+    recs, mps = run(h, inp.heisenberg_mpo(N), As0, [(32, 1e-14)] * 5, prec=prec, eig_tol=1e-12,
+                    krylovdim=12, maxiter=400)
+    E = recs[-1]["energy"]
+    assert abs(E - e_ed10) / abs(e_ed10) <= 1e-10, (prec, E, e_ed10)
+    bonds = h.mps_bonds(mps)
+    assert max(bonds) <= 32
+    # the returned state carries that energy
+    sites = h.mps_sites(mps)
+    assert abs(hf.mps_energy(sites, inp.heisenberg_mpo(N)) - E) / abs(E) <= 1e-9
+    if prec != "f64":
+        assert recs[-1]["matvecs"] > 0
+
+
+def test_c0_matches_oracle_dmrg_per_converged_sweep(h):
+    N = 10
+    As0 = inp.random_product_state(N, 2, inp.rng_for(0, 32))
+    ref = odmrg.dmrg(inp.heisenberg_mpo(N), As0, [(32, 1e-14)] * 5)
+    recs, _ = run(h, inp.heisenberg_mpo(N), As0, [(32, 1e-14)] * 5, eig_tol=1e-12, krylovdim=12,
+                  maxiter=400)
+    assert abs(recs[-1]["energy"] - ref.energy) / abs(ref.energy) <= 1e-10
+
+
+def test_aklt_exact_energy(h):
+    N = 8
+    As0 = inp.random_product_state(N, 3, np.random.default_rng(8))
+    recs, _ = run(h, inp.aklt_mpo(N), As0, [(16, 1e-12)] * 4, eig_tol=1e-11, krylovdim=12,
+                  maxiter=400)
+    assert abs(recs[-1]["energy"] + 2.0 / 3.0 * (N - 1)) < 1e-9
+
+
+def test_spin1_chain_matches_ed(h):
+    N = 6
+    e = float(np.linalg.eigvalsh(ed.heisenberg_dense(N, 2))[0])
+    As0 = inp.random_product_state(N, 3, np.random.default_rng(6))
+    recs, _ = run(h, inp.heisenberg_mpo(N, 2), As0, [(27, 1e-14)] * 4, eig_tol=1e-12,
+                  krylovdim=12, maxiter=400)
+    assert abs(recs[-1]["energy"] - e) / abs(e) <= 1e-10
+
+
+def test_hubbard_2x2_matches_ed(h):
+    Lx, Ly = 2, 2
+    e = float(np.linalg.eigvalsh(ed.hubbard_dense(Lx, Ly, U=8.0))[0])
+    As0 = inp.neel_product_state(Lx * Ly, 4, up=1, dn=2)
+    recs, _ = run(h, inp.hubbard_mpo(Lx, Ly, U=8.0), As0, [(64, 1e-14)] * 4, eig_tol=1e-12,
+                  krylovdim=12, maxiter=400)
+    assert abs(recs[-1]["energy"] - e) / abs(e) <= 1e-10
+
+
+def test_truncation_respects_maxdim(h):
+    N = 12
+    As0 = inp.random_product_state(N, 2, np.random.default_rng(3))
+    recs, mps = run(h, inp.heisenberg_mpo(N), As0, [(4, 0.0), (8, 0.0)], eig_tol=1e-10,
+                    krylovdim=8, maxiter=200)
+    assert max(h.mps_bonds(mps)) <= 8
+    assert recs[0]["max_bond"] <= 4
+    assert recs[-1]["max_trunc"] > 0.0
+
+
+def test_mismatched_mpo_rejected(h):
+    As0 = inp.random_product_state(6, 2, np.random.default_rng(1))
+    mps = h.mps(As0)
+    mpo = h.mpo(inp.heisenberg_mpo(7))
+    with pytest.raises(itn.ItnError) as e:
+        h.dmrg_sweep(mps, mpo, [(8, 0.0)])
+    assert e.value.name == "ITN_E_SHAPE"
