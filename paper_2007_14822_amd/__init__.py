@@ -251,6 +251,101 @@ class Handle:
         return [{k: arrs[k][i] for k in arrs} for i in range(res.sweeps_done)]
 
 
+def _qn(keep: _Keep, desc) -> L.itn_tensor:
+    """itn_tensor for a QN tensor described as a dict:
+      spaces : [(qns, dims, arrow), ...]  qns = list of QN tuples per sector
+      blocks : [sector tuple, ...] sorted (absent for a dense host MPO tensor)
+      offsets: [element offset per block]
+      data   : device torch tensor (flat) / host numpy array / None (planning)
+    """
+    spaces = desc["spaces"]
+    rank = len(spaces)
+    sp = (L.itn_space * rank)()
+    for i, (qns, dims, arrow) in enumerate(spaces):
+        qns = [tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,))) for q in qns]
+        nq = len(qns[0])
+        sp[i].nsec = len(dims)
+        sp[i].nq = nq
+        sp[i].qn = keep.arr(C.c_int32, [x for q in qns for x in q])
+        sp[i].dim = keep.arr(C.c_int32, [int(x) for x in dims])
+        sp[i].arrow = int(arrow)
+    keep.items.append(sp)
+    tt = L.itn_tensor()
+    tt.rank = rank
+    totals = [int(sum(dims)) for _, dims, _ in spaces]
+    tt.dims = keep.arr(C.c_int64, totals)
+    tt.space = C.cast(sp, C.POINTER(L.itn_space))
+    data = desc.get("data")
+    if data is None:
+        tt.dtype = desc.get("dtype", L.ITN_F64)
+        tt.data = C.c_void_p(None)
+    else:
+        if isinstance(data, np.ndarray):
+            data = np.ascontiguousarray(data)
+            keep.items.append(data)
+            tt.data = C.c_void_p(data.ctypes.data)
+        else:
+            tt.data = C.c_void_p(data.data_ptr())
+        tt.dtype = _dtype_code(data)
+    blocks = desc.get("blocks")
+    if blocks is not None:
+        tt.nblocks = len(blocks)
+        tt.block_sec = keep.arr(C.c_int32, [int(x) for b in blocks for x in b])
+        tt.block_off = keep.arr(C.c_int64, [int(x) for x in desc["offsets"]])
+        nq = len(spaces[0][0][0]) if isinstance(spaces[0][0][0], (tuple, list)) else 1
+        tt.flux = keep.arr(C.c_int32, [0] * nq)
+    return tt
+
+
+def _qn_handle_methods():
+    def qn_plan(self, Ld, W1d, W2d, Rd, Pd, nv: int = 1, prec: str = "f64"):
+        k = _Keep()
+        ts = [_qn(k, x) for x in (Ld, W1d, W2d, Rd, Pd)]
+        out = C.c_void_p()
+        self._check(self.lib.itn_qn_heff_plan(self.h, *[C.byref(t) for t in ts], int(nv),
+                                              PREC[prec], C.byref(out)))
+        return Plan(self, out)
+
+    def qn_apply(self, plan, Ld, Rd, Pd, Od, stream=None):
+        k = _Keep()
+        ts = [_qn(k, x) for x in (Ld, Rd, Pd, Od)]
+        self._check(self.lib.itn_qn_heff_apply(self.h, plan.ptr, *[C.byref(t) for t in ts],
+                                               self._sp(stream)))
+    return qn_plan, qn_apply
+
+
+class Plan:
+    """A QN H_eff plan (owned by the library)."""
+
+    def __init__(self, handle, ptr):
+        self.handle = handle
+        self.lib = handle.lib
+        self.ptr = ptr
+
+    def info(self):
+        i = L.itn_plan_info()
+        self.handle._check(self.lib.itn_plan_query(self.ptr, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in L.itn_plan_info._fields_}
+
+    def out_blocks(self):
+        n = self.info()["out_nblocks"]
+        sec = (C.c_int32 * (4 * max(1, n)))()
+        off = (C.c_int64 * max(1, n))()
+        self.handle._check(self.lib.itn_plan_out_blocks(self.ptr, sec, off))
+        return [tuple(sec[4 * b:4 * b + 4]) for b in range(n)], list(off[:n])
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                self.lib.itn_plan_destroy(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
+
+
+Handle.qn_plan, Handle.qn_apply = _qn_handle_methods()
+
+
 class _Owned:
     """An opaque library object freed with its destroy call."""
 

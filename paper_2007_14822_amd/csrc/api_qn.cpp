@@ -1,0 +1,820 @@
+// Block-sparse (quantum-number) H_eff*psi: the integer host planner and the
+// grouped, graph-captured execution.
+//
+// Sec. 8 fixes the rules the planner applies: an index is a list of QN
+// sectors with an arrow; a block is stored iff Out QNs minus In QNs equal
+// the tensor's flux; contracted indices need opposite arrows.  Sec. 9.4
+// describes block-sparse contraction as dense contractions of block pairs,
+// with several pairs possibly landing on one output block, and the option
+// of combining blocks before contracting.  Here:
+//   stage 1  one GEMM per (a-sector, m0-sector) group: the L block times all
+//            psi blocks with that a-sector, concatenated along N (combine-
+//            then-contract);
+//   W-stage  per (a'-sector, b-sector) pair, a sparse map from the X blocks
+//            to the Z blocks stage 4 needs;
+//   stage 4  one problem per output block, its K the concatenation of the
+//            (m2, b) segments of every contributing (Z block, R block) pair,
+//            summed in ascending m2-sector order by the workgroup that owns
+//            the output tile (no atomics: run-to-run deterministic).
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+#include "handle.h"
+
+using namespace itn;
+
+namespace {
+
+struct QSpace {
+  int nsec = 0, nq = 0;
+  std::vector<int32_t> qn;   // nsec*nq
+  std::vector<int32_t> dim;  // nsec
+  std::vector<int64_t> off;  // element offset of each sector
+  int8_t arrow = 0;
+  int64_t total = 0;
+  const int32_t* q(int k) const { return qn.data() + (size_t)k * nq; }
+  bool same_sectors(const QSpace& o) const { return nq == o.nq && qn == o.qn && dim == o.dim; }
+  // sector with exactly this QN, or -1 (sectors with distinct QNs only)
+  int find(const std::vector<int32_t>& want) const {
+    for (int k = 0; k < nsec; ++k)
+      if (std::equal(want.begin(), want.end(), q(k))) return k;
+    return -1;
+  }
+};
+
+struct QTensor {
+  int rank = 0;
+  std::vector<QSpace> sp;
+  std::vector<std::vector<int32_t>> blocks;  // sector tuples
+  std::vector<int64_t> off;
+  std::map<std::vector<int32_t>, int> index;
+  int64_t elems = 0;
+};
+
+itn_status read_space(itn_handle* h, const itn_space& s, QSpace& out, const char* what) {
+  if (s.nsec < 1 || s.nq < 1 || !s.qn || !s.dim)
+    return fail(h, ITN_E_ARG, "%s: a QN index needs nsec >= 1, nq >= 1, qn and dim", what);
+  if (s.arrow != 1 && s.arrow != -1) return fail(h, ITN_E_ARROW, "%s: arrow must be +1 or -1", what);
+  out.nsec = s.nsec;
+  out.nq = s.nq;
+  out.qn.assign(s.qn, s.qn + (size_t)s.nsec * s.nq);
+  out.dim.assign(s.dim, s.dim + s.nsec);
+  out.arrow = s.arrow;
+  out.off.resize(s.nsec);
+  out.total = 0;
+  for (int k = 0; k < s.nsec; ++k) {
+    if (out.dim[k] < 1) return fail(h, ITN_E_SHAPE, "%s: sector dimensions must be >= 1", what);
+    out.off[k] = out.total;
+    out.total += out.dim[k];
+  }
+  return ITN_OK;
+}
+
+std::vector<int32_t> block_flux(const QTensor& t, const std::vector<int32_t>& blk) {
+  const int nq = t.sp[0].nq;
+  std::vector<int32_t> f(nq, 0);
+  for (int i = 0; i < t.rank; ++i)
+    for (int c = 0; c < nq; ++c) f[c] += t.sp[i].arrow * t.sp[i].q(blk[i])[c];
+  return f;
+}
+
+// Read a QN tensor: spaces, expected arrows, block list (validated).
+itn_status read_qtensor(itn_handle* h, const itn_tensor* t, int rank, const int* arrows,
+                        QTensor& out, const char* what, bool need_blocks) {
+  if (!t) return fail(h, ITN_E_ARG, "%s is NULL", what);
+  if (t->rank != rank) return fail(h, ITN_E_SHAPE, "%s must have rank %d", what, rank);
+  if (!t->space) return fail(h, ITN_E_ARG, "%s needs QN index spaces", what);
+  out.rank = rank;
+  out.sp.resize(rank);
+  for (int i = 0; i < rank; ++i) {
+    ITN_TRY(read_space(h, t->space[i], out.sp[i], what));
+    if (out.sp[i].arrow != arrows[i])
+      return fail(h, ITN_E_ARROW, "%s index %d has arrow %d, expected %d", what, i, out.sp[i].arrow,
+                  arrows[i]);
+    if (out.sp[i].nq != out.sp[0].nq) return fail(h, ITN_E_SHAPE, "%s: mixed QN lengths", what);
+  }
+  if (!need_blocks) return ITN_OK;
+  if (t->nblocks < 0 || (t->nblocks > 0 && (!t->block_sec || !t->block_off)))
+    return fail(h, ITN_E_ARG, "%s: block list missing", what);
+  const int nq = out.sp[0].nq;
+  std::vector<int32_t> flux(nq, 0);
+  if (t->flux) flux.assign(t->flux, t->flux + nq);
+  for (int c = 0; c < nq; ++c)
+    if (flux[c] != 0) return fail(h, ITN_E_FLUX, "%s must have zero flux", what);
+  int64_t expect = 0;
+  for (int64_t b = 0; b < t->nblocks; ++b) {
+    std::vector<int32_t> blk(t->block_sec + b * rank, t->block_sec + (b + 1) * rank);
+    int64_t sz = 1;
+    for (int i = 0; i < rank; ++i) {
+      if (blk[i] < 0 || blk[i] >= out.sp[i].nsec)
+        return fail(h, ITN_E_ARG, "%s block %lld: sector out of range", what, (long long)b);
+      sz *= out.sp[i].dim[blk[i]];
+    }
+    if (b > 0 && !(out.blocks.back() < blk))
+      return fail(h, ITN_E_ARG, "%s blocks must be sorted and unique", what);
+    if (block_flux(out, blk) != flux)
+      return fail(h, ITN_E_FLUX, "%s block %lld violates the flux rule", what, (long long)b);
+    if (t->block_off[b] != expect)
+      return fail(h, ITN_E_SHAPE, "%s block offsets must be the exclusive prefix sum of block sizes",
+                  what);
+    expect += sz;
+    out.index[blk] = (int)out.blocks.size();
+    out.blocks.push_back(blk);
+    out.off.push_back(t->block_off[b]);
+  }
+  out.elems = expect;
+  return ITN_OK;
+}
+
+// Every allowed (zero-flux) sector tuple of a tensor's indices, lexicographic.
+std::vector<std::vector<int32_t>> allowed_blocks(const QTensor& t) {
+  std::vector<std::vector<int32_t>> out;
+  std::vector<int32_t> blk(t.rank, 0);
+  const int nq = t.sp[0].nq;
+  std::function<void(int)> rec = [&](int i) {
+    if (i == t.rank) {
+      auto f = block_flux(t, blk);
+      bool zero = true;
+      for (int c = 0; c < nq; ++c) zero &= f[c] == 0;
+      if (zero) out.push_back(blk);
+      return;
+    }
+    for (int k = 0; k < t.sp[i].nsec; ++k) {
+      blk[i] = k;
+      rec(i + 1);
+    }
+  };
+  rec(0);
+  return out;
+}
+
+std::vector<int32_t> qadd(const int32_t* a, const int32_t* b, int nq, int sb) {
+  std::vector<int32_t> r(nq);
+  for (int c = 0; c < nq; ++c) r[c] = a[c] + sb * b[c];
+  return r;
+}
+
+bool distinct_qns(const QSpace& s) {
+  for (int i = 0; i < s.nsec; ++i)
+    for (int j = i + 1; j < s.nsec; ++j)
+      if (std::equal(s.q(i), s.q(i) + s.nq, s.q(j))) return false;
+  return true;
+}
+
+std::string sig_of(const QTensor& t) {
+  std::ostringstream o;
+  for (auto& s : t.sp) {
+    o << "[" << (int)s.arrow;
+    for (size_t k = 0; k < s.qn.size(); ++k) o << "," << s.qn[k];
+    o << ";";
+    for (auto dd : s.dim) o << dd << ",";
+    o << "]";
+  }
+  o << "B" << t.blocks.size() << ":";
+  for (auto& b : t.blocks)
+    for (auto k : b) o << k << ",";
+  return o.str();
+}
+
+// process-wide autotune cache: plan signature -> (stage-1 cfg, stage-4 cfg)
+std::mutex g_tune_mu;
+std::map<size_t, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("ITN_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  size_t k;
+  int a, b;
+  while (f >> k >> a >> b) g_tune[k] = {a, b};
+}
+
+void tune_store(size_t key, int a, int b) {
+  g_tune[key] = {a, b};
+  const char* path = std::getenv("ITN_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << a << " " << b << "\n";
+}
+
+}  // namespace
+
+struct itn_plan {
+  int prec = 0, pt = 0, xt = 0;
+  int psi_dt = 0, out_dt = 0;
+  int nv = 1;
+  int64_t out_elems = 0;
+  std::string sig;  // operand structure signature (L, R, psi)
+  size_t sig_hash = 0;
+  // host tables
+  std::vector<std::vector<int32_t>> out_blocks;
+  std::vector<int64_t> out_off;
+  std::vector<GProb> p1, p4;
+  std::vector<GSeg> s1, s4;
+  std::vector<GTile> t1[2], t4[2];
+  std::vector<QnTBlock> tb;
+  int64_t tb_tiles = 0;
+  std::vector<QnWPair> wp;
+  std::vector<QnWRow> wr;
+  std::vector<QnWEnt> we;
+  std::vector<QnWItem> wi;
+  std::vector<int64_t> zoff, zsize;
+  int64_t psiT_elems = 0, X_elems = 0, Z_elems = 0;
+  int64_t pairs1 = 0;
+  double flops_gemm = 0.0, flops_w = 0.0;
+  // device state
+  int device = -1;
+  char* dtab = nullptr;  // all tables
+  QnDevPtrs* dptrs = nullptr;
+  GProb *dp1 = nullptr, *dp4 = nullptr;
+  GSeg *ds1 = nullptr, *ds4 = nullptr;
+  GTile *dt1[2] = {nullptr, nullptr}, *dt4[2] = {nullptr, nullptr};
+  QnTBlock* dtb = nullptr;
+  QnWPair* dwp = nullptr;
+  QnWRow* dwr = nullptr;
+  QnWEnt* dwe = nullptr;
+  QnWItem* dwi = nullptr;
+  int64_t* dzoff = nullptr;
+  int64_t* dzsize = nullptr;
+  void* psiT = nullptr;
+  void* X = nullptr;
+  void* Z = nullptr;
+  int cfg1 = 0, cfg4 = 0;
+  bool tuned = false;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~itn_plan() {
+    if (device >= 0) {
+      (void)hipDeviceSynchronize();
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (cap) (void)hipStreamDestroy(cap);
+      for (void* p : {(void*)dtab, psiT, X, Z})
+        if (p) (void)hipFree(p);
+    }
+  }
+};
+
+namespace {
+
+// Tile lists for tile size `bt` (square), largest K-work first.
+std::vector<GTile> make_tiles(const std::vector<GProb>& probs, const std::vector<GSeg>& segs, int bt) {
+  struct W {
+    GTile t;
+    int64_t work;
+  };
+  std::vector<W> v;
+  for (size_t p = 0; p < probs.size(); ++p) {
+    const GProb& pr = probs[p];
+    int64_t k = 0;
+    for (int s = 0; s < pr.nseg; ++s) k += segs[pr.seg0 + s].K;
+    const int tm = (pr.M + bt - 1) / bt, tn = (pr.N + bt - 1) / bt;
+    for (int i = 0; i < tm; ++i)
+      for (int j = 0; j < tn; ++j) v.push_back({GTile{(int32_t)p, i, j, 0}, k});
+  }
+  std::stable_sort(v.begin(), v.end(), [](const W& a, const W& b) { return a.work > b.work; });
+  std::vector<GTile> out;
+  out.reserve(v.size());
+  for (auto& x : v) out.push_back(x.t);
+  return out;
+}
+
+itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t,
+                      const itn_tensor* W2t, const itn_tensor* Rt, const itn_tensor* Pt, int nv,
+                      int prec, itn_plan& pl) {
+  static const int aL[3] = {+1, -1, -1}, aR[3] = {-1, +1, +1}, aP[4] = {+1, +1, +1, -1},
+                   aW[4] = {+1, -1, +1, -1};
+  QTensor L, R, P, W1, W2;
+  ITN_TRY(read_qtensor(h, Lt, 3, aL, L, "L", true));
+  ITN_TRY(read_qtensor(h, Rt, 3, aR, R, "R", true));
+  ITN_TRY(read_qtensor(h, Pt, 4, aP, P, "psi", true));
+  ITN_TRY(read_qtensor(h, W1t, 4, aW, W1, "W1", false));
+  ITN_TRY(read_qtensor(h, W2t, 4, aW, W2, "W2", false));
+  const int nq = P.sp[0].nq;
+  for (QTensor* t : {&L, &R, &W1, &W2})
+    if (t->sp[0].nq != nq) return fail(h, ITN_E_SHAPE, "all operands need the same QN length");
+  // contracted pairs: equal sectors (arrows already checked opposite)
+  if (!L.sp[2].same_sectors(P.sp[0])) return fail(h, ITN_E_SHAPE, "L's a and psi's a differ");
+  if (!L.sp[0].same_sectors(P.sp[0])) return fail(h, ITN_E_SHAPE, "L's a' and psi's a differ");
+  if (!R.sp[2].same_sectors(P.sp[3])) return fail(h, ITN_E_SHAPE, "R's b and psi's b differ");
+  if (!R.sp[0].same_sectors(P.sp[3])) return fail(h, ITN_E_SHAPE, "R's b' and psi's b differ");
+  if (!L.sp[1].same_sectors(W1.sp[0])) return fail(h, ITN_E_SHAPE, "L's m and W1's m_in differ");
+  if (!W1.sp[1].same_sectors(W2.sp[0])) return fail(h, ITN_E_SHAPE, "W1's m_out and W2's m_in differ");
+  if (!W2.sp[1].same_sectors(R.sp[1])) return fail(h, ITN_E_SHAPE, "W2's m_out and R's m differ");
+  if (!W1.sp[2].same_sectors(P.sp[1]) || !W1.sp[3].same_sectors(P.sp[1]))
+    return fail(h, ITN_E_SHAPE, "W1's site indices and psi's s1 differ");
+  if (!W2.sp[2].same_sectors(P.sp[2]) || !W2.sp[3].same_sectors(P.sp[2]))
+    return fail(h, ITN_E_SHAPE, "W2's site indices and psi's s2 differ");
+  if (!distinct_qns(P.sp[0]) || !distinct_qns(P.sp[3]))
+    return fail(h, ITN_E_UNSUPPORTED, "bond indices must have distinct sector QNs");
+  // psi must hold every allowed block (the output block set is psi's)
+  if (allowed_blocks(P) != P.blocks)
+    return fail(h, ITN_E_SHAPE, "psi must store every flux-allowed block");
+  const int w = (int)W1.sp[0].total, d1 = (int)P.sp[1].total, d2 = (int)P.sp[2].total;
+  if (W2.sp[0].total != w) return fail(h, ITN_E_SHAPE, "W1 and W2 bond dimensions differ");
+  if (!W1t->data || !W2t->data || W1t->dtype != ITN_F64 || W2t->dtype != ITN_F64)
+    return fail(h, ITN_E_DTYPE, "W1, W2 must be host F64 dense arrays");
+  const double* w1 = static_cast<const double*>(W1t->data);
+  const double* w2 = static_cast<const double*>(W2t->data);
+  // the MPO tensors must respect their own charges
+  auto sector_of = [](const QSpace& s, int g) {
+    int k = 0;
+    while (k + 1 < s.nsec && s.off[k + 1] <= g) ++k;
+    return k;
+  };
+  for (int which = 0; which < 2; ++which) {
+    const QTensor& Wt = which ? W2 : W1;
+    const double* wd = which ? w2 : w1;
+    const int d = which ? d2 : d1;
+    for (int a = 0; a < w; ++a)
+      for (int b = 0; b < w; ++b)
+        for (int sp = 0; sp < d; ++sp)
+          for (int s = 0; s < d; ++s) {
+            if (wd[((a * w + b) * d + sp) * d + s] == 0.0) continue;
+            std::vector<int32_t> blk = {sector_of(Wt.sp[0], a), sector_of(Wt.sp[1], b),
+                                        sector_of(Wt.sp[2], sp), sector_of(Wt.sp[3], s)};
+            for (int c = 0; c < nq; ++c)
+              if (block_flux(Wt, blk)[c] != 0)
+                return fail(h, ITN_E_FLUX, "W%d has a nonzero entry outside its allowed blocks",
+                            which + 1);
+          }
+  }
+  const QSpace& SA = P.sp[0];
+  const QSpace& S1 = P.sp[1];
+  const QSpace& S2 = P.sp[2];
+  const QSpace& SB = P.sp[3];
+  const QSpace& SM = L.sp[1];   // m0 sectors
+  const QSpace& SM2 = R.sp[1];  // m2 sectors
+  pl.prec = prec;
+  pl.pt = prec == ITN_P_F64 ? D_F64 : (prec == ITN_P_F32 ? D_F32 : D_BF16);
+  pl.xt = prec == ITN_P_F64 ? D_F64 : D_F32;
+  pl.psi_dt = Pt->dtype;
+  pl.nv = nv;
+  pl.out_elems = P.elems;
+  pl.out_blocks = P.blocks;
+  pl.out_off = P.off;
+  pl.sig = sig_of(L) + "|" + sig_of(R) + "|" + sig_of(P) + "|" + std::to_string(nv) + "|" +
+           std::to_string(prec);
+  pl.sig_hash = std::hash<std::string>()(pl.sig);
+
+  // ---- psiT layout: groups by a-sector (psi blocks are a-major already)
+  const int nA = SA.nsec;
+  std::vector<int64_t> N_ia(nA, 0), psiT_off(nA, 0), colbase(P.blocks.size(), 0);
+  for (size_t b = 0; b < P.blocks.size(); ++b) {
+    const auto& k = P.blocks[b];
+    colbase[b] = N_ia[k[0]];
+    N_ia[k[0]] += (int64_t)S1.dim[k[1]] * S2.dim[k[2]] * SB.dim[k[3]];
+  }
+  int64_t acc = 0;
+  for (int ia = 0; ia < nA; ++ia) {
+    psiT_off[ia] = acc;
+    acc += N_ia[ia] * SA.dim[ia];
+  }
+  pl.psiT_elems = acc;
+  int64_t tiles = 0;
+  for (size_t b = 0; b < P.blocks.size(); ++b) {
+    const auto& k = P.blocks[b];
+    QnTBlock t{};
+    t.in_off = P.off[b];
+    t.rows = SA.dim[k[0]];
+    t.cols = S1.dim[k[1]] * S2.dim[k[2]] * SB.dim[k[3]];
+    t.ld_out = SA.dim[k[0]];
+    t.out_off = psiT_off[k[0]] + colbase[b] * SA.dim[k[0]];
+    t.tiles_c = (t.cols + 63) / 64;
+    t.tile0 = (int32_t)tiles;
+    tiles += (int64_t)((t.rows + 63) / 64) * t.tiles_c;
+    pl.tb.push_back(t);
+  }
+  pl.tb_tiles = tiles;
+
+  // ---- stage 1 groups (a-sector, m0-sector)
+  std::map<std::pair<int, int>, std::pair<int64_t, int>> xgroup;  // -> (X offset, a'-sector)
+  int64_t xacc = 0;
+  for (int ia = 0; ia < nA; ++ia) {
+    if (N_ia[ia] == 0) continue;
+    for (int im = 0; im < SM.nsec; ++im) {
+      // L[a':Out, m:In, a:In], zero flux: q(a') = q(m) + q(a)
+      const int iap = SA.find(qadd(SM.q(im), SA.q(ia), nq, +1));
+      if (iap < 0) continue;
+      auto it = L.index.find({iap, im, ia});
+      if (it == L.index.end()) continue;
+      const int64_t M = (int64_t)SA.dim[iap] * SM.dim[im];
+      GSeg sg{};
+      sg.a_off = L.off[it->second];
+      sg.b_off = psiT_off[ia];
+      sg.lda = SA.dim[ia];
+      sg.ldb = SA.dim[ia];
+      sg.K = SA.dim[ia];
+      GProb pr{};
+      pr.c_off = xacc;
+      pr.M = (int32_t)M;
+      pr.N = (int32_t)N_ia[ia];
+      pr.ldc = (int32_t)N_ia[ia];
+      pr.seg0 = (int32_t)pl.s1.size();
+      pr.nseg = 1;
+      pl.s1.push_back(sg);
+      pl.p1.push_back(pr);
+      xgroup[{ia, im}] = {xacc, iap};
+      xacc += M * N_ia[ia];
+      pl.flops_gemm += 2.0 * M * N_ia[ia] * SA.dim[ia];
+      for (size_t b = 0; b < P.blocks.size(); ++b) pl.pairs1 += P.blocks[b][0] == ia;
+    }
+  }
+  pl.X_elems = xacc;
+
+  // ---- stage 4 problems and the Z blocks they need
+  std::map<std::vector<int32_t>, int64_t> zblock;  // (ia', is1', is2', im2, ib) -> Z offset
+  int64_t zacc = 0;
+  for (size_t ob = 0; ob < P.blocks.size(); ++ob) {
+    const auto& k = P.blocks[ob];
+    const int iap = k[0], i1 = k[1], i2 = k[2], ibp = k[3];
+    GProb pr{};
+    pr.c_off = P.off[ob];
+    pr.M = SA.dim[iap] * S1.dim[i1] * S2.dim[i2];
+    pr.N = SB.dim[ibp];
+    pr.ldc = SB.dim[ibp];
+    pr.seg0 = (int32_t)pl.s4.size();
+    pr.nseg = 0;
+    for (int im2 = 0; im2 < SM2.nsec; ++im2) {
+      // R[b':In, m:Out, b:Out], zero flux: q(b) = q(b') - q(m)
+      const int ib = SB.find(qadd(SB.q(ibp), SM2.q(im2), nq, -1));
+      if (ib < 0) continue;
+      auto it = R.index.find({ibp, im2, ib});
+      if (it == R.index.end()) continue;
+      std::vector<int32_t> zk = {iap, i1, i2, im2, ib};
+      const int64_t K = (int64_t)SM2.dim[im2] * SB.dim[ib];
+      if (!zblock.count(zk)) {
+        zblock[zk] = zacc;
+        zacc += (int64_t)pr.M * K;
+      }
+      GSeg sg{};
+      sg.a_off = zblock[zk];
+      sg.lda = (int32_t)K;
+      sg.b_off = R.off[it->second];
+      sg.ldb = (int32_t)K;
+      sg.K = (int32_t)K;
+      pl.s4.push_back(sg);
+      pr.nseg++;
+      pl.flops_gemm += 2.0 * pr.M * pr.N * K;
+    }
+    if (pr.nseg == 0) {
+      pl.zoff.push_back(P.off[ob]);
+      pl.zsize.push_back((int64_t)pr.M * pr.N);
+    } else {
+      pl.p4.push_back(pr);
+    }
+  }
+  pl.Z_elems = zacc;
+
+  // ---- W-stage: pairs (a'-sector, b-sector) over the Z blocks needed
+  // W12[m0, m2, s1', s2', s1, s2] = sum_m1 W1[m0, m1, s1', s1] W2[m1, m2, s2', s2]
+  const size_t nW12 = (size_t)w * w * d1 * d1 * d2 * d2;
+  std::vector<double> W12(nW12, 0.0);
+  auto w12 = [&](int m0, int m2, int s1p, int s2p, int s1, int s2) -> double& {
+    return W12[((((((size_t)m0 * w + m2) * d1 + s1p) * d2 + s2p) * d1 + s1) * d2) + s2];
+  };
+  for (int m0 = 0; m0 < w; ++m0)
+    for (int m1 = 0; m1 < w; ++m1)
+      for (int s1p = 0; s1p < d1; ++s1p)
+        for (int s1 = 0; s1 < d1; ++s1) {
+          const double a = w1[((m0 * w + m1) * d1 + s1p) * d1 + s1];
+          if (a == 0.0) continue;
+          for (int m2 = 0; m2 < w; ++m2)
+            for (int s2p = 0; s2p < d2; ++s2p)
+              for (int s2 = 0; s2 < d2; ++s2) {
+                const double b = w2[((m1 * w + m2) * d2 + s2p) * d2 + s2];
+                if (b != 0.0) w12(m0, m2, s1p, s2p, s1, s2) += a * b;
+              }
+        }
+  std::map<std::pair<int, int>, std::vector<std::vector<int32_t>>> pairs;
+  for (auto& kv : zblock) pairs[{kv.first[0], kv.first[4]}].push_back(kv.first);
+  for (auto& kv : pairs) {
+    const int iap = kv.first.first, ib = kv.first.second;
+    QnWPair wpair{};
+    wpair.row0 = (int32_t)pl.wr.size();
+    wpair.da = SA.dim[iap];
+    wpair.db = SB.dim[ib];
+    const int64_t db = SB.dim[ib];
+    for (auto& zk : kv.second) {
+      const int i1p = zk[1], i2p = zk[2], im2 = zk[3];
+      const int64_t zoff = zblock[zk];
+      const int64_t ds1p = S1.dim[i1p], ds2p = S2.dim[i2p], dm2 = SM2.dim[im2];
+      for (int s1l = 0; s1l < ds1p; ++s1l)
+        for (int s2l = 0; s2l < ds2p; ++s2l)
+          for (int m2l = 0; m2l < dm2; ++m2l) {
+            QnWRow row{};
+            row.off = zoff + (s1l * ds2p + s2l) * dm2 * db + m2l * db;
+            row.astride = ds1p * ds2p * dm2 * db;
+            row.e0 = (int32_t)pl.we.size();
+            const int g_m2 = (int)SM2.off[im2] + m2l;
+            const int g_s1p = (int)S1.off[i1p] + s1l, g_s2p = (int)S2.off[i2p] + s2l;
+            for (int im0 = 0; im0 < SM.nsec; ++im0) {
+              // X group (ia, im0) with q(a) = q(a') - q(m0)
+              const int ia = SA.find(qadd(SA.q(iap), SM.q(im0), nq, -1));
+              if (ia < 0) continue;
+              auto xg = xgroup.find({ia, im0});
+              if (xg == xgroup.end() || xg->second.second != iap) continue;
+              for (int i1 = 0; i1 < S1.nsec; ++i1)
+                for (int i2 = 0; i2 < S2.nsec; ++i2) {
+                  auto pb = P.index.find({ia, i1, i2, ib});
+                  if (pb == P.index.end()) continue;
+                  const int64_t ds1 = S1.dim[i1], ds2 = S2.dim[i2];
+                  for (int m0l = 0; m0l < SM.dim[im0]; ++m0l)
+                    for (int s1l2 = 0; s1l2 < ds1; ++s1l2)
+                      for (int s2l2 = 0; s2l2 < ds2; ++s2l2) {
+                        const double cf = w12((int)SM.off[im0] + m0l, g_m2, g_s1p, g_s2p,
+                                              (int)S1.off[i1] + s1l2, (int)S2.off[i2] + s2l2);
+                        if (cf == 0.0) continue;
+                        QnWEnt e{};
+                        e.off = xg->second.first + m0l * N_ia[ia] + colbase[pb->second] +
+                                (s1l2 * ds2 + s2l2) * db;
+                        e.astride = (int64_t)SM.dim[im0] * N_ia[ia];
+                        e.coef = cf;
+                        pl.we.push_back(e);
+                      }
+                }
+            }
+            row.ne = (int32_t)(pl.we.size() - row.e0);
+            pl.flops_w += 2.0 * row.ne * wpair.da * db;
+            pl.wr.push_back(row);
+          }
+    }
+    wpair.nrows = (int32_t)(pl.wr.size() - wpair.row0);
+    const int pid = (int)pl.wp.size();
+    pl.wp.push_back(wpair);
+    for (int a = 0; a < wpair.da; ++a)
+      for (int b0 = 0; b0 < wpair.db; b0 += 256) pl.wi.push_back(QnWItem{pid, a, b0, 0});
+  }
+  for (int c = 0; c < 2; ++c) {
+    pl.t1[c] = make_tiles(pl.p1, pl.s1, grouped_tile_rows(c));
+    pl.t4[c] = make_tiles(pl.p4, pl.s4, grouped_tile_rows(c));
+  }
+  return ITN_OK;
+}
+
+template <typename T> T* carve(char*& p, size_t n) {
+  T* r = reinterpret_cast<T*>(p);
+  p += (n * sizeof(T) + 255) & ~size_t(255);
+  return r;
+}
+
+itn_status upload(itn_handle* h, itn_plan& pl) {
+  pl.device = h->device;
+  size_t bytes = 0;
+  auto add = [&](size_t n) { bytes += (n + 255) & ~size_t(255); };
+  add(sizeof(QnDevPtrs));
+  add(pl.p1.size() * sizeof(GProb));
+  add(pl.p4.size() * sizeof(GProb));
+  add(pl.s1.size() * sizeof(GSeg));
+  add(pl.s4.size() * sizeof(GSeg));
+  for (int c = 0; c < 2; ++c) {
+    add(pl.t1[c].size() * sizeof(GTile));
+    add(pl.t4[c].size() * sizeof(GTile));
+  }
+  add(pl.tb.size() * sizeof(QnTBlock));
+  add(pl.wp.size() * sizeof(QnWPair));
+  add(pl.wr.size() * sizeof(QnWRow));
+  add(pl.we.size() * sizeof(QnWEnt));
+  add(pl.wi.size() * sizeof(QnWItem));
+  add(pl.zoff.size() * 8);
+  add(pl.zsize.size() * 8);
+  ITN_HIP(h, hipMalloc(&pl.dtab, bytes + 256));
+  char* p = pl.dtab;
+  pl.dptrs = carve<QnDevPtrs>(p, 1);
+  auto put = [&](auto*& dst, const auto& vec) -> hipError_t {
+    using E = typename std::remove_reference<decltype(vec)>::type::value_type;
+    dst = carve<E>(p, vec.size());
+    if (vec.empty()) return hipSuccess;
+    return hipMemcpy(dst, vec.data(), vec.size() * sizeof(E), hipMemcpyHostToDevice);
+  };
+  ITN_HIP(h, put(pl.dp1, pl.p1));
+  ITN_HIP(h, put(pl.dp4, pl.p4));
+  ITN_HIP(h, put(pl.ds1, pl.s1));
+  ITN_HIP(h, put(pl.ds4, pl.s4));
+  for (int c = 0; c < 2; ++c) {
+    ITN_HIP(h, put(pl.dt1[c], pl.t1[c]));
+    ITN_HIP(h, put(pl.dt4[c], pl.t4[c]));
+  }
+  ITN_HIP(h, put(pl.dtb, pl.tb));
+  ITN_HIP(h, put(pl.dwp, pl.wp));
+  ITN_HIP(h, put(pl.dwr, pl.wr));
+  ITN_HIP(h, put(pl.dwe, pl.we));
+  ITN_HIP(h, put(pl.dwi, pl.wi));
+  ITN_HIP(h, put(pl.dzoff, pl.zoff));
+  ITN_HIP(h, put(pl.dzsize, pl.zsize));
+  const int es = dtype_size(pl.pt), xs = dtype_size(pl.xt);
+  ITN_HIP(h, hipMalloc(&pl.psiT, std::max<size_t>(256, (size_t)pl.nv * pl.psiT_elems * es)));
+  ITN_HIP(h, hipMalloc(&pl.X, std::max<size_t>(256, (size_t)pl.nv * pl.X_elems * xs)));
+  ITN_HIP(h, hipMalloc(&pl.Z, std::max<size_t>(256, (size_t)pl.nv * pl.Z_elems * es)));
+  return ITN_OK;
+}
+
+constexpr int MAX_WG = 1024;  // persistent grouped launches: at most 4 workgroups per CU
+
+// The launches of one apply (after the operand pointers are set).
+itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int cfg4) {
+  QnPtrs* ptrs = &pl.dptrs->p;
+  {
+    Prof pf(h, "qn_psi_transpose", s);
+    ITN_HIP(h, qn_block_transpose(pl.psi_dt, ptrs, pl.pt, pl.psiT, pl.dtb, (int)pl.tb.size(),
+                                  pl.tb_tiles, pl.out_elems, pl.psiT_elems, pl.nv, s));
+  }
+  {
+    Prof pf(h, "qn_stage1_grouped", s);
+    ITN_HIP(h, gemm_grouped(pl.prec, pl.xt, cfg1, &pl.dptrs->g1, pl.dp1, pl.ds1, pl.dt1[cfg1],
+                            (int64_t)pl.t1[cfg1].size(), 0, pl.psiT_elems, pl.X_elems, pl.nv, MAX_WG, s));
+  }
+  {
+    Prof pf(h, "qn_wstage", s);
+    ITN_HIP(h, qn_wstage(pl.xt, pl.X, pl.pt, pl.Z, pl.dwp, pl.dwr, pl.dwe, pl.dwi,
+                         (int64_t)pl.wi.size(), pl.X_elems, pl.Z_elems, pl.nv, s));
+  }
+  if (!pl.zoff.empty()) {
+    Prof pf(h, "qn_zero_blocks", s);
+    ITN_HIP(h, qn_zero_blocks(pl.out_dt, ptrs, pl.dzoff, pl.dzsize, (int)pl.zoff.size(),
+                              pl.out_elems, pl.nv, s));
+  }
+  {
+    Prof pf(h, "qn_stage4_grouped", s);
+    ITN_HIP(h, gemm_grouped(pl.prec, pl.out_dt, cfg4, &pl.dptrs->g4, pl.dp4, pl.ds4, pl.dt4[cfg4],
+                            (int64_t)pl.t4[cfg4].size(), pl.Z_elems, 0, pl.out_elems, pl.nv, MAX_WG, s));
+  }
+  return ITN_OK;
+}
+
+// Pick the faster tile per grouped stage by timing both on the real operands.
+itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    auto it = g_tune.find(pl.sig_hash);
+    if (it != g_tune.end()) {
+      pl.cfg1 = it->second.first;
+      pl.cfg4 = it->second.second;
+      pl.tuned = true;
+      return ITN_OK;
+    }
+  }
+  hipEvent_t e0, e1;
+  ITN_HIP(h, hipEventCreate(&e0));
+  ITN_HIP(h, hipEventCreate(&e1));
+  float best1 = 1e30f, best4 = 1e30f;
+  for (int c = 0; c < 2; ++c) {
+    for (int stage = 0; stage < 2; ++stage) {
+      float tot = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        ITN_HIP(h, hipEventRecord(e0, s));
+        if (stage == 0)
+          ITN_HIP(h, gemm_grouped(pl.prec, pl.xt, c, &pl.dptrs->g1, pl.dp1, pl.ds1, pl.dt1[c],
+                                  (int64_t)pl.t1[c].size(), 0, pl.psiT_elems, pl.X_elems, pl.nv,
+                                  MAX_WG, s));
+        else
+          ITN_HIP(h, gemm_grouped(pl.prec, pl.out_dt, c, &pl.dptrs->g4, pl.dp4, pl.ds4, pl.dt4[c],
+                                  (int64_t)pl.t4[c].size(), pl.Z_elems, 0, pl.out_elems, pl.nv,
+                                  MAX_WG, s));
+        ITN_HIP(h, hipEventRecord(e1, s));
+        ITN_HIP(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        ITN_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tot += ms;
+      }
+      if (stage == 0 && tot < best1) best1 = tot, pl.cfg1 = c;
+      if (stage == 1 && tot < best4) best4 = tot, pl.cfg4 = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  pl.tuned = true;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_store(pl.sig_hash, pl.cfg1, pl.cfg4);
+  return ITN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+itn_status itn_qn_heff_plan(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
+                            const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
+                            int32_t nv, itn_prec prec, itn_plan** plan) {
+  if (!h) return ITN_E_ARG;
+  if (!plan) return fail(h, ITN_E_ARG, "plan is NULL");
+  *plan = nullptr;
+  if (nv < 1) return fail(h, ITN_E_ARG, "nv must be >= 1");
+  if (prec != ITN_P_F64 && prec != ITN_P_F32 && prec != ITN_P_BF16)
+    return fail(h, ITN_E_ARG, "unknown precision");
+  if (psi && psi->dtype != ITN_F64 && psi->dtype != ITN_F32)
+    return fail(h, ITN_E_DTYPE, "psi must be F64 or F32");
+  auto* pl = new itn_plan();
+  itn_status st = build_plan(h, L, W1, W2, R, psi, nv, prec, *pl);
+  if (st != ITN_OK) {
+    delete pl;
+    return st;
+  }
+  *plan = pl;
+  return ITN_OK;
+}
+
+itn_status itn_plan_destroy(itn_plan* plan) {
+  delete plan;
+  return ITN_OK;
+}
+
+itn_status itn_plan_query(const itn_plan* pl, itn_plan_info* info) {
+  if (!pl || !info) return ITN_E_ARG;
+  info->out_nblocks = (int64_t)pl->out_blocks.size();
+  info->out_elems = pl->out_elems;
+  info->n_pairs_stage1 = pl->pairs1;
+  info->n_groups_stage1 = (int64_t)pl->p1.size();
+  info->n_pairs_stage4 = (int64_t)pl->s4.size();
+  info->n_tiles = (int64_t)(pl->t1[pl->cfg1].size() + pl->t4[pl->cfg4].size());
+  info->flops = pl->flops_gemm * pl->nv;
+  return ITN_OK;
+}
+
+itn_status itn_plan_out_blocks(const itn_plan* pl, int32_t* block_sec, int64_t* block_off) {
+  if (!pl || !block_sec || !block_off) return ITN_E_ARG;
+  for (size_t b = 0; b < pl->out_blocks.size(); ++b) {
+    for (int i = 0; i < 4; ++i) block_sec[b * 4 + i] = pl->out_blocks[b][i];
+    block_off[b] = pl->out_off[b];
+  }
+  return ITN_OK;
+}
+
+itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, const itn_tensor* R,
+                             const itn_tensor* psi, itn_tensor* out, void* hip_stream) {
+  if (!h) return ITN_E_ARG;
+  if (!pl || !L || !R || !psi || !out) return fail(h, ITN_E_ARG, "null argument");
+  // operands must carry the structure the plan was built from
+  {
+    static const int aL[3] = {+1, -1, -1}, aR[3] = {-1, +1, +1}, aP[4] = {+1, +1, +1, -1};
+    QTensor Lq, Rq, Pq, Oq;
+    ITN_TRY(read_qtensor(h, L, 3, aL, Lq, "L", true));
+    ITN_TRY(read_qtensor(h, R, 3, aR, Rq, "R", true));
+    ITN_TRY(read_qtensor(h, psi, 4, aP, Pq, "psi", true));
+    ITN_TRY(read_qtensor(h, out, 4, aP, Oq, "out", true));
+    const std::string sg = sig_of(Lq) + "|" + sig_of(Rq) + "|" + sig_of(Pq) + "|" +
+                           std::to_string(pl->nv) + "|" + std::to_string(pl->prec);
+    if (sg != pl->sig) return fail(h, ITN_E_SHAPE, "operands differ from the plan's structure");
+    if (sig_of(Oq) != sig_of(Pq)) return fail(h, ITN_E_SHAPE, "out must have psi's structure");
+  }
+  if (L->dtype != pl->pt || R->dtype != pl->pt)
+    return fail(h, ITN_E_DTYPE, "L and R must be stored in the plan's compute type");
+  if (psi->dtype != pl->psi_dt) return fail(h, ITN_E_DTYPE, "psi dtype differs from the plan's");
+  if (out->dtype != ITN_F64 && out->dtype != ITN_F32)
+    return fail(h, ITN_E_DTYPE, "out must be F64 or F32");
+  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (pl->device < 0) {
+    pl->out_dt = out->dtype;
+    ITN_TRY(upload(h, *pl));
+  } else if (pl->device != h->device) {
+    return fail(h, ITN_E_ARG, "plan was uploaded to another device");
+  }
+  if (out->dtype != pl->out_dt) return fail(h, ITN_E_DTYPE, "out dtype differs from the first apply");
+  QnDevPtrs v{};
+  v.p.L = L->data;
+  v.p.R = R->data;
+  v.p.psi = psi->data;
+  v.p.out = out->data;
+  v.g1 = GBases{L->data, pl->psiT, pl->X};
+  v.g4 = GBases{pl->Z, R->data, out->data};
+  {
+    Prof pf(h, "qn_set_ptrs", s);
+    ITN_HIP(h, qn_set_ptrs(pl->dptrs, v, s));
+  }
+  if (!pl->tuned) ITN_TRY(autotune(h, *pl, s));
+  if (h->prof_on) {  // per-kernel timing: run the launches directly
+    ITN_TRY(launch_all(h, *pl, s, pl->cfg1, pl->cfg4));
+    return ITN_OK;
+  }
+  if (!pl->exec) {
+    ITN_HIP(h, hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+    ITN_HIP(h, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+    const itn_status st = launch_all(h, *pl, pl->cap, pl->cfg1, pl->cfg4);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(pl->cap, &g);
+    if (st != ITN_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    ITN_HIP(h, e);
+    pl->graph = g;
+    ITN_HIP(h, hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+  }
+  ITN_HIP(h, hipGraphLaunch(pl->exec, s));
+  return ITN_OK;
+}
+
+}  // extern "C"

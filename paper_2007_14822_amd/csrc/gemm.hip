@@ -45,36 +45,43 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_nt_direct_kernel(GemmArgs g
   store_tile_direct<P, BM, BN, WM, WN, TOut, ACCUM>(acc, Cp, g.ldc, g.M, g.N, tm * BM, tn * BN);
 }
 
+// Persistent grouped GEMM: gridDim.x workgroups stride over the tile list
+// (ordered by the planner, largest work first); base pointers are read from
+// device memory so that a captured graph can be replayed with new operands.
 template <int P, int BM, int BN, typename TOut>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(
-    const typename PT<P>::T* __restrict__ Abase, const typename PT<P>::T* __restrict__ Bbase,
-    TOut* __restrict__ Cbase, const GProb* __restrict__ probs, const GSeg* __restrict__ segs,
-    const GTile* __restrict__ tiles, int64_t a_bs, int64_t b_bs, int64_t c_bs) {
+    const GBases* __restrict__ bases, const GProb* __restrict__ probs, const GSeg* __restrict__ segs,
+    const GTile* __restrict__ tiles, int64_t ntiles, int64_t a_bs, int64_t b_bs, int64_t c_bs) {
   using Cfg = TileCfg<P, BM, BN>;
   using T = typename Cfg::T;
   constexpr int E16 = Cfg::E16;
   extern __shared__ __align__(16) char lds[];
-  const GTile t = tiles[blockIdx.x];
-  const GProb pr = probs[t.prob];
+  const T* Abase = static_cast<const T*>(bases->A);
+  const T* Bbase = static_cast<const T*>(bases->B);
+  TOut* Cbase = static_cast<TOut*>(bases->C);
   const int64_t batch = blockIdx.y;
-  typename Cfg::AccV acc[BM / 32][BN / 32];
-  zero_acc<P, BM, BN>(acc);
-  for (int s = 0; s < pr.nseg; ++s) {
-    const GSeg sg = segs[pr.seg0 + s];
-    const T* A = Abase + sg.a_off + batch * a_bs;
-    const T* B = Bbase + sg.b_off + batch * b_bs;
-    // The choice is uniform over the workgroup (it depends on the segment only).
-    const bool al = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 &&
-                    sg.lda % E16 == 0 && sg.ldb % E16 == 0;
-    if (al)
-      gemm_accum<P, BM, BN, true>(A, sg.lda, pr.M, B, sg.ldb, pr.N, sg.K, (int64_t)t.tm * BM,
-                                  (int64_t)t.tn * BN, acc, lds);
-    else
-      gemm_accum<P, BM, BN, false>(A, sg.lda, pr.M, B, sg.ldb, pr.N, sg.K, (int64_t)t.tm * BM,
-                                   (int64_t)t.tn * BN, acc, lds);
+  for (int64_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const GTile t = tiles[ti];
+    const GProb pr = probs[t.prob];
+    typename Cfg::AccV acc[BM / 32][BN / 32];
+    zero_acc<P, BM, BN>(acc);
+    for (int s = 0; s < pr.nseg; ++s) {
+      const GSeg sg = segs[pr.seg0 + s];
+      const T* A = Abase + sg.a_off + batch * a_bs;
+      const T* B = Bbase + sg.b_off + batch * b_bs;
+      // uniform over the workgroup (depends on the segment only)
+      const bool al = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 &&
+                      sg.lda % E16 == 0 && sg.ldb % E16 == 0;
+      if (al)
+        gemm_accum<P, BM, BN, true>(A, sg.lda, pr.M, B, sg.ldb, pr.N, sg.K, (int64_t)t.tm * BM,
+                                    (int64_t)t.tn * BN, acc, lds);
+      else
+        gemm_accum<P, BM, BN, false>(A, sg.lda, pr.M, B, sg.ldb, pr.N, sg.K, (int64_t)t.tm * BM,
+                                     (int64_t)t.tn * BN, acc, lds);
+    }
+    store_tile<P, BM, BN, TOut>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc, pr.M, pr.N,
+                                (int64_t)t.tm * BM, (int64_t)t.tn * BN, false);
   }
-  store_tile<P, BM, BN, TOut>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc, pr.M, pr.N,
-                              (int64_t)t.tm * BM, (int64_t)t.tn * BN, false);
 }
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -171,38 +178,35 @@ hipError_t gemm_nt(int prec, int c_dtype, const GemmArgs& g, hipStream_t s) {
 }
 
 template <int P, int BM, int BN, typename TOut>
-static hipError_t launch_grouped(const void* Ab, const void* Bb, void* Cb, const GProb* probs,
-                                 const GSeg* segs, const GTile* tiles, int64_t ntiles,
-                                 int64_t a_bs, int64_t b_bs, int64_t c_bs, int nbatch,
-                                 hipStream_t s) {
+static hipError_t launch_grouped(const GBases* bases, const GProb* probs, const GSeg* segs,
+                                 const GTile* tiles, int64_t ntiles, int64_t a_bs, int64_t b_bs,
+                                 int64_t c_bs, int nbatch, int max_wg, hipStream_t s) {
   using Cfg = TileCfg<P, BM, BN>;
-  using T = typename Cfg::T;
   if (ntiles == 0 || nbatch == 0) return hipSuccess;
-  dim3 grid((unsigned)ntiles, (unsigned)nbatch);
+  int64_t g = ntiles;
+  if (max_wg > 0 && g > max_wg) g = max_wg;
+  dim3 grid((unsigned)g, (unsigned)nbatch);
   static const hipError_t attr = allow_lds(gemm_grouped_kernel<P, BM, BN, TOut>, Cfg::LDS_BYTES);
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL((gemm_grouped_kernel<P, BM, BN, TOut>), grid, dim3(GEMM_THREADS),
-                     Cfg::LDS_BYTES, s, static_cast<const T*>(Ab), static_cast<const T*>(Bb),
-                     static_cast<TOut*>(Cb), probs, segs, tiles, a_bs, b_bs, c_bs);
+                     Cfg::LDS_BYTES, s, bases, probs, segs, tiles, ntiles, a_bs, b_bs, c_bs);
   return hipGetLastError();
 }
 
-#define ITN_GROUPED_ARGS Ab, Bb, Cb, probs, segs, tiles, ntiles, a_bs, b_bs, c_bs, nbatch, s
+#define ITN_GROUPED_ARGS bases, probs, segs, tiles, ntiles, a_bs, b_bs, c_bs, nbatch, max_wg, s
 
 template <int P, typename TOut>
-static hipError_t grouped_cfg(int cfg, const void* Ab, const void* Bb, void* Cb,
-                              const GProb* probs, const GSeg* segs, const GTile* tiles,
-                              int64_t ntiles, int64_t a_bs, int64_t b_bs, int64_t c_bs, int nbatch,
-                              hipStream_t s) {
+static hipError_t grouped_cfg(int cfg, const GBases* bases, const GProb* probs, const GSeg* segs,
+                              const GTile* tiles, int64_t ntiles, int64_t a_bs, int64_t b_bs,
+                              int64_t c_bs, int nbatch, int max_wg, hipStream_t s) {
   if (cfg == 1) return launch_grouped<P, 128, 128, TOut>(ITN_GROUPED_ARGS);
   return launch_grouped<P, 64, 64, TOut>(ITN_GROUPED_ARGS);
 }
 
 template <int P>
-static hipError_t grouped_out(int c_dtype, int cfg, const void* Ab, const void* Bb, void* Cb,
-                              const GProb* probs, const GSeg* segs, const GTile* tiles,
-                              int64_t ntiles, int64_t a_bs, int64_t b_bs, int64_t c_bs, int nbatch,
-                              hipStream_t s) {
+static hipError_t grouped_out(int c_dtype, int cfg, const GBases* bases, const GProb* probs,
+                              const GSeg* segs, const GTile* tiles, int64_t ntiles, int64_t a_bs,
+                              int64_t b_bs, int64_t c_bs, int nbatch, int max_wg, hipStream_t s) {
   switch (c_dtype) {
     case D_F64: return grouped_cfg<P, double>(cfg, ITN_GROUPED_ARGS);
     case D_F32: return grouped_cfg<P, float>(cfg, ITN_GROUPED_ARGS);
@@ -211,10 +215,9 @@ static hipError_t grouped_out(int c_dtype, int cfg, const void* Ab, const void* 
   return hipErrorInvalidValue;
 }
 
-hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const void* Ab, const void* Bb,
-                        void* Cb, const GProb* probs, const GSeg* segs, const GTile* tiles,
-                        int64_t ntiles, int64_t a_bs, int64_t b_bs, int64_t c_bs, int nbatch,
-                        hipStream_t s) {
+hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const GBases* bases, const GProb* probs,
+                        const GSeg* segs, const GTile* tiles, int64_t ntiles, int64_t a_bs,
+                        int64_t b_bs, int64_t c_bs, int nbatch, int max_wg, hipStream_t s) {
   const int cfg = tile_cfg;
   switch (prec) {
     case P_F64: return grouped_out<P_F64>(c_dtype, cfg, ITN_GROUPED_ARGS);
@@ -224,5 +227,7 @@ hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const void* Ab, con
   return hipErrorInvalidValue;
 }
 #undef ITN_GROUPED_ARGS
+
+int grouped_tile_rows(int tile_cfg) { return tile_cfg == 1 ? 128 : 64; }
 
 }  // namespace itn

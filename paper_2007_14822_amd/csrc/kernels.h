@@ -49,12 +49,78 @@ struct GTile {     // one work item
   int32_t tm, tn;  // tile coordinates within the problem
   int32_t pad;
 };
-// Tile config codes for the grouped launch: 0 = 64x64, 1 = 128x128.
-// Batch b (grid.y) offsets A, B and C by b times their batch strides.
-hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const void* Abase, const void* Bbase,
-                        void* Cbase, const GProb* probs, const GSeg* segs, const GTile* tiles,
-                        int64_t ntiles, int64_t a_batch_stride, int64_t b_batch_stride,
-                        int64_t c_batch_stride, int nbatch, hipStream_t s);
+// Base pointers of a grouped launch, read by the kernel from device memory.
+struct GBases {
+  const void* A;
+  const void* B;
+  void* C;
+};
+// Persistent grouped launch: at most max_wg workgroups (0: one per tile)
+// stride over the tile list.  Tile config: 0 = 64x64, 1 = 128x128.  Batch b
+// (grid.y) offsets A, B and C by b times their batch strides.
+hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const GBases* bases, const GProb* probs,
+                        const GSeg* segs, const GTile* tiles, int64_t ntiles, int64_t a_batch_stride,
+                        int64_t b_batch_stride, int64_t c_batch_stride, int nbatch, int max_wg,
+                        hipStream_t s);
+int grouped_tile_rows(int tile_cfg);
+
+// ------------------------------------------------------------- QN helpers
+// Pointers of the caller's operands for one block-sparse H_eff apply, read
+// by the kernels from device memory (set by qn_set_ptrs before a replay).
+struct QnPtrs {
+  const void* L;
+  const void* R;
+  const void* psi;
+  void* out;
+};
+struct QnDevPtrs {
+  QnPtrs p;
+  GBases g1;  // stage 1: A = L, B = psiT, C = X
+  GBases g4;  // stage 4: A = Z, B = R, C = out
+};
+hipError_t qn_set_ptrs(QnDevPtrs* dst, QnDevPtrs v, hipStream_t s);
+// Per-block transpose with conversion: item i moves block `in` [rows][cols]
+// (row-major at in_off of psi + v * in_bs) to out_off of `out` + v * out_bs
+// as [cols][rows] with row stride ld_out (elements).
+struct QnTBlock {
+  int64_t in_off, out_off;
+  int32_t rows, cols;
+  int32_t ld_out;
+  int32_t tiles_c;  // column tiles of 64
+  int32_t tile0;    // first tile index of this block in the flat tile space
+  int32_t pad;
+};
+hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, void* out,
+                              const QnTBlock* blocks, int nblocks, int64_t ntiles, int64_t in_bs,
+                              int64_t out_bs, int nv, hipStream_t s);
+// Block-sparse W-stage: work item = (pair, a', b chunk of 256); rows and
+// entries carry their own offsets and a'-strides.
+struct QnWPair {
+  int32_t row0, nrows;  // CSR rows of this pair
+  int32_t da, db;       // positions a' < da, b < db
+};
+struct QnWRow {
+  int64_t off;          // Z offset of (a' = 0, b = 0)
+  int64_t astride;
+  int32_t e0, ne;       // entries
+};
+struct QnWEnt {
+  int64_t off;          // X offset of (a' = 0, b = 0)
+  int64_t astride;
+  double coef;
+};
+struct QnWItem {
+  int32_t pair;
+  int32_t a;
+  int32_t b0;
+  int32_t pad;
+};
+hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnWPair* pairs,
+                     const QnWRow* rows, const QnWEnt* ents, const QnWItem* items, int64_t nitems,
+                     int64_t x_bs, int64_t z_bs, int nv, hipStream_t s);
+// Zero the listed output blocks (offsets, sizes) of out + v * bs.
+hipError_t qn_zero_blocks(int dtype, const QnPtrs* ptrs, const int64_t* offs, const int64_t* sizes,
+                          int nblocks, int64_t bs, int nv, hipStream_t s);
 
 // Generic strided permutation with dtype conversion (rank <= 8):
 // out[i_0..i_{r-1}] (row-major over out_dims) = in[sum_k i_k * in_strides[k]].

@@ -1,0 +1,120 @@
+"""GPU parity of the block-sparse (QN) H_eff against the oracle's blockwise
+route, through the C ABI (planner + grouped launches + hipGraph replay)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2007_14822_amd as itn
+from oracle import qn as Q
+from tests import qn_util as U
+from tests.workloads import rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 2e-2}
+TDT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+
+
+@pytest.fixture(scope="module")
+def h():
+    return itn.Handle(0)
+
+
+def _gpu_desc(bt, dtype):
+    d, flat = U.desc(bt, with_data=False)
+    d["data"] = torch.as_tensor(flat, dtype=dtype, device=DEV)
+    return d
+
+
+def _run(h, ops, W1, W2, prec, nv, psis):
+    """psis: list of nv oracle psi BlockTensors (same structure)."""
+    L, w1, w2, R, psi = ops
+    Ld, Rd = _gpu_desc(L, TDT[prec]), _gpu_desc(R, TDT[prec])
+    Pd, _ = U.desc(psi, with_data=False)
+    flat = np.concatenate([p.packed()[2] for p in psis])
+    Pd["data"] = torch.as_tensor(flat, device=DEV)
+    Od = dict(Pd)
+    Od["data"] = torch.zeros_like(Pd["data"])
+    plan = h.qn_plan(Ld, U.mpo_desc(W1, w1), U.mpo_desc(W2, w2), Rd, Pd, nv=nv, prec=prec)
+    h.qn_apply(plan, Ld, Rd, Pd, Od)
+    torch.cuda.synchronize()
+    return plan, (Ld, Rd, Pd, Od), Od["data"].cpu().numpy()
+
+
+def _ref(ops, psis):
+    L, w1, w2, R, _ = ops
+    return np.concatenate([Q.heff_apply_blocks(L, w1, w2, R, p).packed()[2] for p in psis])
+
+
+def _perturbed(psi, seed):
+    rng = np.random.default_rng(seed)
+    out = Q.BlockTensor(psi.inds, psi.flux)
+    for k, v in psi.blocks.items():
+        out.blocks[k] = rng.standard_normal(v.shape)
+    return out
+
+
+@pytest.mark.parametrize("make", [U.small_u1, U.small_u1u1])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nv", [1, 3])
+def test_qn_heff_parity(h, make, prec, nv):
+    ops, W1, W2 = make()
+    psis = [ops[4]] + [_perturbed(ops[4], 10 + v) for v in range(nv - 1)]
+    _, _, got = _run(h, ops, W1, W2, prec, nv, psis)
+    assert rel_err(got, _ref(ops, psis)) <= TOL[prec]
+
+
+def test_qn_graph_replay_new_operands(h):
+    """The captured graph is replayed with new psi/out buffers."""
+    ops, W1, W2 = U.small_u1u1()
+    plan, (Ld, Rd, Pd, Od), got = _run(h, ops, W1, W2, "f64", 1, [ops[4]])
+    assert rel_err(got, _ref(ops, [ops[4]])) <= 1e-10
+    for seed in (1, 2, 3):
+        p2 = _perturbed(ops[4], seed)
+        P2 = dict(Pd)
+        P2["data"] = torch.as_tensor(p2.packed()[2], device=DEV)
+        O2 = dict(Od)
+        O2["data"] = torch.full_like(P2["data"], float("nan"))
+        h.qn_apply(plan, Ld, Rd, P2, O2)
+        torch.cuda.synchronize()
+        assert rel_err(O2["data"].cpu().numpy(), _ref(ops, [p2])) <= 1e-10
+
+
+def test_qn_deterministic(h):
+    ops, W1, W2 = U.small_u1()
+    plan, (Ld, Rd, Pd, Od), a = _run(h, ops, W1, W2, "bf16", 2, [ops[4], _perturbed(ops[4], 4)])
+    h.qn_apply(plan, Ld, Rd, Pd, Od)
+    torch.cuda.synchronize()
+    b = Od["data"].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_qn_structure_mismatch_rejected(h):
+    ops, W1, W2 = U.small_u1()
+    plan, (Ld, Rd, Pd, Od), _ = _run(h, ops, W1, W2, "f64", 1, [ops[4]])
+    bad = dict(Rd)
+    bad["blocks"] = Rd["blocks"][:-1]
+    bad["offsets"] = Rd["offsets"][:-1]
+    with pytest.raises(itn.ItnError) as e:
+        h.qn_apply(plan, Ld, bad, Pd, Od)
+    assert e.value.name == "ITN_E_SHAPE"
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_c3_full_size_sampled_sectors(h, prec):
+    """U(1) chi=4096 in 25 sectors (the benchmark workload): every output
+    block of three a'-sectors against the oracle restricted to those rows."""
+    ops, W1, W2 = U.c3_operands()
+    L, w1, w2, R, psi = ops
+    _, _, got = _run(h, ops, W1, W2, prec, 1, [psi])
+    keys, offs, _ = psi.packed()
+    chosen = {0, 7, 17}  # dims 8, 35, 107
+    Lr = Q.BlockTensor(L.inds, L.flux, {k: v for k, v in L.blocks.items() if k[0] in chosen})
+    ref = Q.heff_apply_blocks(Lr, w1, w2, R, psi)
+    for k, o in zip(keys, offs):
+        if k[0] not in chosen:
+            continue
+        n = psi.blocks[k].size
+        r = ref.blocks[k].ravel() if k in ref.blocks else np.zeros(n)
+        assert rel_err(got[o:o + n], r) <= TOL[prec], (k, prec)

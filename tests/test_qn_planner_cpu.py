@@ -1,0 +1,90 @@
+"""The QN planner through the C ABI on a host-only handle: output block
+structure bit-exact against the oracle, and argument validation."""
+import copy
+
+import numpy as np
+import pytest
+
+import paper_2007_14822_amd as itn
+from oracle import qn as Q
+from tests import qn_util as U
+
+
+@pytest.fixture(scope="module")
+def host():
+    return itn.Handle(-1)
+
+
+def _plan(host, ops, W1, W2, nv=1):
+    L, w1, w2, R, psi = ops
+    Ld, _ = U.desc(L, with_data=False)
+    Rd, _ = U.desc(R, with_data=False)
+    Pd, _ = U.desc(psi, with_data=False)
+    return host.qn_plan(Ld, U.mpo_desc(W1, w1), U.mpo_desc(W2, w2), Rd, Pd, nv=nv)
+
+
+@pytest.mark.parametrize("make", [U.small_u1, U.small_u1u1])
+def test_output_blocks_bit_exact(host, make):
+    ops, W1, W2 = make()
+    plan = _plan(host, ops, W1, W2)
+    blocks, offs = plan.out_blocks()
+    L, w1, w2, R, psi = ops
+    ref = Q.heff_apply_blocks(L, w1, w2, R, psi)
+    keys, roffs, flat = ref.packed()
+    assert blocks == [tuple(k) for k in keys]
+    assert offs == roffs
+    info = plan.info()
+    assert info["out_nblocks"] == len(keys) and info["out_elems"] == flat.size
+
+
+def test_c3_structure(host):
+    ops, W1, W2 = U.c3_operands()
+    L, w1, w2, R, psi = ops
+    plan = _plan(host, ops, W1, W2)
+    blocks, offs = plan.out_blocks()
+    keys, roffs, flat = psi.packed()
+    assert len(blocks) == 98
+    assert blocks == [tuple(k) for k in keys] and offs == roffs
+    info = plan.info()
+    assert info["n_groups_stage1"] > 0 and info["flops"] > 0
+    # algorithmic flops: sum of 2 M N K over contributing block products
+    assert abs(info["flops"] - 1.101e11) / 1.101e11 < 0.02
+
+
+def test_arrow_flux_and_shape_errors(host):
+    ops, W1, W2 = U.small_u1()
+    L, w1, w2, R, psi = ops
+    Ld, _ = U.desc(L, with_data=False)
+    Rd, _ = U.desc(R, with_data=False)
+    Pd, _ = U.desc(psi, with_data=False)
+    m1, m2 = U.mpo_desc(W1, w1), U.mpo_desc(W2, w2)
+    bad = copy.deepcopy(Ld)
+    q, d, a = bad["spaces"][2]
+    bad["spaces"][2] = (q, d, +1)  # L's a must be In
+    with pytest.raises(itn.ItnError) as e:
+        host.qn_plan(bad, m1, m2, Rd, Pd)
+    assert e.value.name == "ITN_E_ARROW"
+    bad = copy.deepcopy(Pd)
+    bad["blocks"] = bad["blocks"][1:]  # psi must hold every allowed block
+    bad["offsets"] = list(np.cumsum([0] + [1] * 0))  # wrong layout as well
+    with pytest.raises(itn.ItnError) as e:
+        host.qn_plan(Ld, m1, m2, Rd, bad)
+    assert e.value.name in ("ITN_E_SHAPE", "ITN_E_ARG")
+    bad = copy.deepcopy(Ld)
+    blk = list(bad["blocks"][0])
+    blk[0] = (blk[0] + 1) % len(bad["spaces"][0][1])
+    bad["blocks"] = [tuple(blk)] + bad["blocks"][1:]
+    with pytest.raises(itn.ItnError) as e:
+        host.qn_plan(bad, m1, m2, Rd, Pd)
+    assert e.value.name in ("ITN_E_FLUX", "ITN_E_ARG")
+    Wbad = W1.copy()
+    Wbad[4, 1] = 1.0  # S- channel fed with the identity breaks charge conservation
+    with pytest.raises(itn.ItnError) as e:
+        host.qn_plan(Ld, U.mpo_desc(Wbad, w1), m2, Rd, Pd)
+    assert e.value.name == "ITN_E_FLUX"
+    bad = copy.deepcopy(Rd)
+    q, d, a = bad["spaces"][2]
+    bad["spaces"][2] = (q, [x + 1 for x in d], a)  # R's b sectors differ from psi's
+    with pytest.raises(itn.ItnError) as e:
+        host.qn_plan(Ld, m1, m2, bad, Pd)
+    assert e.value.name in ("ITN_E_SHAPE", "ITN_E_FLUX")
