@@ -144,17 +144,129 @@ def cpu_baseline(L, W1, W2, R, psi, chi, d, w, budget_s):
                       "numpy einsum optimize=False, single thread), %.1f s" % (k, chi, chi, dt)}
 
 
+# ----------------------------------------------------------------- QN legs
+def qn_workload(h, torch, np, inp, which, prec, nv):
+    """Block-sparse H_eff operands.  Structure from the library's block
+    enumeration, values from the seeded per-block generator.
+      c3: U(1) S=1/2 chain bond, chi=4096 in 25 binomial-shaped sectors, w=5
+      c4: U(1)xU(1) Hubbard 4x32 cylinder bond, chi=4096 in 81 sectors,
+          w=18 (column-major snake) or the synthetic w=38 shape"""
+    if which == "c3":
+        bond = [((q,), n) for q, n in inp.c3_sector_dims()]
+        site_q = inp.heisenberg_site_qn(1)
+        W = inp.heisenberg_mpo(3)[1]
+        W1 = W2 = W
+        link_q = inp.heisenberg_mpo_link_qn()
+        seed = inp.seed_for(3, 4096)
+    else:
+        bond = list(inp.c4_sector_dims())
+        site_q = inp.hubbard_site_qn()
+        if which == "c4":
+            Ws = inp.hubbard_mpo(32, 4)
+            W1, W2 = Ws[62], Ws[63]
+        else:  # c4w38
+            Ws = inp.long_range_hubbard_mpo(8, 9)
+            W1, W2 = Ws[6], Ws[7]
+        link_q = [None] * W1.shape[0]
+        # channel charges: kinds 0..3 follow c+up, c+dn, cup, cdn
+        rmax = (W1.shape[0] - 2) // 4
+        kind_q = [(1, 1), (1, -1), (-1, -1), (-1, 1)]
+        link_q = [(0, 0)] + [kind_q[k] for k in range(4) for _ in range(rmax)] + [(0, 0)]
+        seed = inp.seed_for(4, 4096)
+    bq = [tuple(q) if isinstance(q, tuple) else (q,) for q, _ in bond]
+    bd = [n for _, n in bond]
+    sq, sd = inp.sectors_from_basis_qns(site_q)
+    lq, ld = inp.sectors_from_basis_qns(link_q)
+    spaces = {
+        "L": [(bq, bd, +1), (lq, ld, -1), (bq, bd, -1)],
+        "R": [(bq, bd, -1), (lq, ld, +1), (bq, bd, +1)],
+        "psi": [(bq, bd, +1), (sq, sd, +1), (sq, sd, +1), (bq, bd, -1)],
+        "W": [(lq, ld, +1), (lq, ld, -1), (sq, sd, +1), (sq, sd, -1)],
+    }
+    tdt = {"bf16": torch.bfloat16, "f32": torch.float32, "f64": torch.float64}[prec]
+    dev = "cuda:0"
+
+    def fill(name, tag, nvec=1):
+        blocks, offs, tot = h.qn_allowed_blocks(spaces[name])
+        sizes = [int(np.prod([spaces[name][i][1][k] for i, k in enumerate(b)])) for b in blocks]
+        flat = np.empty(nvec * tot)
+        for v in range(nvec):
+            for b, o, sz in zip(blocks, offs, sizes):
+                flat[v * tot + o:v * tot + o + sz] = inp.block_values(seed + tag, (v,) + tuple(b),
+                                                                     (sz,))
+        return {"spaces": spaces[name], "blocks": blocks, "offsets": offs}, flat, tot
+
+    Ld, Lf, _ = fill("L", 1)
+    Rd, Rf, _ = fill("R", 2)
+    Pd, Pf, tot = fill("psi", 3, nv)
+    for v in range(nv):
+        Pf[v * tot:(v + 1) * tot] /= np.linalg.norm(Pf[v * tot:(v + 1) * tot])
+    Ld["data"] = torch.as_tensor(Lf, dtype=tdt, device=dev)
+    Rd["data"] = torch.as_tensor(Rf, dtype=tdt, device=dev)
+    Pd["data"] = torch.as_tensor(Pf, device=dev)
+    Od = dict(Pd)
+    Od["data"] = torch.zeros_like(Pd["data"])
+    W1d = {"spaces": spaces["W"], "data": np.ascontiguousarray(W1)}
+    W2d = {"spaces": spaces["W"], "data": np.ascontiguousarray(W2)}
+    return Ld, W1d, W2d, Rd, Pd, Od
+
+
+def time_qn(h, torch, np, inp, which, prec, nv, steps, warmup):
+    Ld, W1d, W2d, Rd, Pd, Od = qn_workload(h, torch, np, inp, which, prec, nv)
+    t0 = time.perf_counter()
+    plan = h.qn_plan(Ld, W1d, W2d, Rd, Pd, nv=nv, prec=prec)
+    tplan = time.perf_counter() - t0
+    for _ in range(warmup):
+        h.qn_apply(plan, Ld, Rd, Pd, Od)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        h.qn_apply(plan, Ld, Rd, Pd, Od)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    info = plan.info()
+    h.profile(True)
+    for _ in range(max(2, steps // 4)):
+        h.qn_apply(plan, Ld, Rd, Pd, Od)
+    rep = h.profile_report()
+    h.profile(False)
+    out = Od["data"].clone()
+    del Ld, Rd, Pd, Od
+    return {"ms_per_apply": ms, "tflops": info["flops"] / (ms * 1e-3) / 1e12,
+            "flop_per_apply": info["flops"], "out_blocks": info["out_nblocks"],
+            "stage1_groups": info["n_groups_stage1"], "stage4_segments": info["n_pairs_stage4"],
+            "plan_seconds": tplan, "nv": nv,
+            "kernels": {k: {"avg_ms": v[0] / max(1, v[1]), "launches": v[1]} for k, v in rep.items()}}, out
+
+
+# ---------------------------------------------------------------- DMRG leg
+def dmrg_leg(h, np, inp, prec, sweeps, N=100):
+    """Spin-1 Heisenberg chain (d=3, w=5), random product start, the given
+    (maxdim, cutoff) schedule; per-sweep time, energy, matvecs."""
+    mpo = h.mpo(inp.heisenberg_mpo(N, 2))
+    mps = h.mps(inp.random_product_state(N, 3, inp.rng_for(2, 64)))
+    t0 = time.perf_counter()
+    recs = h.dmrg_sweep(mps, mpo, sweeps, prec=prec, eig_tol=1e-9, krylovdim=8, maxiter=60,
+                        refine=True, allow_unconverged=True)
+    return {"total_seconds": time.perf_counter() - t0, "sweeps": recs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--chi", type=int, default=2048)
     ap.add_argument("--d", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--only", choices=["bf16", "f32", "f64"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--no-qn", action="store_true")
+    ap.add_argument("--no-dmrg", action="store_true")
+    ap.add_argument("--dmrg-maxdim", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed work, copy a buffer of this many bytes 3 times "
                          "(a plain copy kernel of known size, to calibrate HBM counters)")
@@ -241,6 +353,44 @@ def main():
     }
     if "f64" in results and head != "f64":
         line["speedup_vs_fp64_gpu"] = results["f64"]["ms_per_step"] / r["ms_per_step"]
+    if not args.no_qn and not args.only:
+        qn = {}
+        for which, nv in (("c3", 1), ("c4", 4), ("c4w38", 4)):
+            for prec in ("bf16", "f64"):
+                log("[bench] QN %s %s nv=%d" % (which, prec, nv))
+                r_qn, out = time_qn(h, torch, np, inp, which, prec, nv, 10, 3)
+                qn["%s_%s" % (which, prec)] = r_qn
+                if prec == "f64":
+                    ref = out
+                    lo = qn["%s_bf16" % which]
+                    lo["rel_err_vs_f64"] = float(torch.linalg.vector_norm(lo_out - ref) /
+                                                 torch.linalg.vector_norm(ref))
+                else:
+                    lo_out = out
+                log("[bench]   %.3f ms, %.1f TFLOP/s" % (r_qn["ms_per_apply"], r_qn["tflops"]))
+        line["qn"] = qn
+    if not args.no_dmrg and not args.only:
+        md = args.dmrg_maxdim
+        sched = [(min(64, md), 1e-10), (min(128, md), 1e-10)] + [(md, 1e-10)] * 4
+        dm = {}
+        for prec in ("f64", "bf16"):
+            log("[bench] DMRG spin-1 N=100 %s, maxdim up to %d" % (prec, md))
+            dm[prec] = dmrg_leg(h, np, inp, prec, sched)
+            log("[bench]   %.1f s, E=%.12f" % (dm[prec]["total_seconds"],
+                                               dm[prec]["sweeps"][-1]["energy"]))
+        e64 = dm["f64"]["sweeps"][-1]["energy"]
+        for prec in dm:
+            ss = dm[prec]["sweeps"]
+            t = 0.0
+            reached = None
+            for k, rec in enumerate(ss):
+                t += rec["seconds"]
+                if k > 0 and abs(rec["energy"] - ss[k - 1]["energy"]) < 1e-8 * abs(rec["energy"]):
+                    reached = t if reached is None else reached
+            dm[prec]["seconds_to_dE_1e-8"] = reached
+            dm[prec]["rel_err_vs_f64_run"] = abs(ss[-1]["energy"] - e64) / abs(e64)
+        line["dmrg"] = {"model": "spin-1 Heisenberg chain, N=100, d=3, w=5",
+                        "schedule": sched, **dm}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(L64.cpu().numpy(), W1, W2, R64.cpu().numpy(),

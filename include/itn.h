@@ -200,6 +200,15 @@ itn_status itn_plan_query(const itn_plan* plan, itn_plan_info* info);
 /* Copy the output block table: block_sec[out_nblocks*4], block_off[out_nblocks]. */
 itn_status itn_plan_out_blocks(const itn_plan* plan, int32_t* block_sec, int64_t* block_off);
 
+/* Enumerate the allowed blocks of a QN tensor's indices (t->space, t->rank,
+ * t->flux; NULL flux = zero): the sector tuples whose Out QNs minus In QNs
+ * equal the flux (Sec. 8), in the packing order of itn_tensor, with their
+ * offsets.  Call with block_sec == NULL to get *nblocks and *total only;
+ * otherwise block_sec[*nblocks * rank] and block_off[*nblocks] are filled
+ * (their capacity is the *nblocks passed in).  Host-only handles may call. */
+itn_status itn_qn_allowed_blocks(itn_handle* h, const itn_tensor* t, int64_t* nblocks,
+                                 int32_t* block_sec, int64_t* block_off, int64_t* total);
+
 /* Apply a plan.  Tensors must carry the same sector tables and block lists
  * the plan was built from (checked by signature: ITN_E_SHAPE otherwise);
  * data pointers may change between calls.  psi/out hold nv vectors at stride

@@ -64,11 +64,15 @@ def hubbard_dense(Lx: int, Ly: int, t: float = 1.0, U: float = 8.0) -> np.ndarra
     """Full Fock-space Hubbard Hamiltonian on the cylinder (column-major
     sites), modes ordered up-then-down on each site, returned in the site
     basis (|0>, |up>, |dn>, |up dn>) of the MPO inputs."""
-    N = Lx * Ly
+    return hubbard_dense_bonds(Lx * Ly, cylinder_bonds(Lx, Ly), t, U)
+
+
+def hubbard_dense_bonds(N: int, bonds, t: float = 1.0, U: float = 8.0) -> np.ndarray:
+    """As hubbard_dense for an explicit list of hopping bonds (i < j)."""
     c = _mode_annihilators(2 * N)
     dim = 4 ** N
     H = np.zeros((dim, dim))
-    for (i, j) in cylinder_bonds(Lx, Ly):
+    for (i, j) in bonds:
         for s in range(2):
             ci, cj = c[2 * i + s], c[2 * j + s]
             H += -t * (ci.T @ cj + cj.T @ ci)

@@ -306,12 +306,29 @@ def _qn_handle_methods():
                                               PREC[prec], C.byref(out)))
         return Plan(self, out)
 
+    def qn_allowed_blocks(self, spaces, flux=None):
+        """(blocks, offsets, total) of the zero-flux (or `flux`) blocks."""
+        k = _Keep()
+        t = _qn(k, {"spaces": spaces})
+        if flux is not None:
+            t.flux = k.arr(C.c_int32, list(flux))
+        n, tot = C.c_int64(0), C.c_int64(0)
+        self._check(self.lib.itn_qn_allowed_blocks(self.h, C.byref(t), C.byref(n), None, None,
+                                                   C.byref(tot)))
+        sec = (C.c_int32 * max(1, n.value * len(spaces)))()
+        off = (C.c_int64 * max(1, n.value))()
+        self._check(self.lib.itn_qn_allowed_blocks(self.h, C.byref(t), C.byref(n), sec, off,
+                                                   C.byref(tot)))
+        r = len(spaces)
+        return ([tuple(sec[b * r:(b + 1) * r]) for b in range(n.value)], list(off[:n.value]),
+                tot.value)
+
     def qn_apply(self, plan, Ld, Rd, Pd, Od, stream=None):
         k = _Keep()
         ts = [_qn(k, x) for x in (Ld, Rd, Pd, Od)]
         self._check(self.lib.itn_qn_heff_apply(self.h, plan.ptr, *[C.byref(t) for t in ts],
                                                self._sp(stream)))
-    return qn_plan, qn_apply
+    return qn_plan, qn_allowed_blocks, qn_apply
 
 
 class Plan:
@@ -343,7 +360,7 @@ class Plan:
             pass
 
 
-Handle.qn_plan, Handle.qn_apply = _qn_handle_methods()
+Handle.qn_plan, Handle.qn_allowed_blocks, Handle.qn_apply = _qn_handle_methods()
 
 
 class _Owned:

@@ -73,6 +73,8 @@ SIGNATURES = {
                                     C.c_int, C.POINTER(C.c_size_t)]),
     "itn_qn_heff_plan": (S, [P, T, T, T, T, T, C.c_int32, C.c_int, C.POINTER(P)]),
     "itn_plan_destroy": (S, [P]),
+    "itn_qn_allowed_blocks": (S, [P, T, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "itn_plan_query": (S, [P, C.POINTER(itn_plan_info)]),
     "itn_plan_out_blocks": (S, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "itn_qn_heff_apply": (S, [P, P, T, T, T, T, P]),

@@ -726,6 +726,56 @@ itn_status itn_qn_heff_plan(itn_handle* h, const itn_tensor* L, const itn_tensor
   return ITN_OK;
 }
 
+itn_status itn_qn_allowed_blocks(itn_handle* h, const itn_tensor* t, int64_t* nblocks,
+                                 int32_t* block_sec, int64_t* block_off, int64_t* total) {
+  if (!h) return ITN_E_ARG;
+  if (!t || !nblocks || !total) return fail(h, ITN_E_ARG, "null argument");
+  if (t->rank < 1 || t->rank > 8 || !t->space) return fail(h, ITN_E_ARG, "need 1..8 QN indices");
+  QTensor q;
+  q.rank = t->rank;
+  q.sp.resize(t->rank);
+  for (int i = 0; i < t->rank; ++i) {
+    ITN_TRY(read_space(h, t->space[i], q.sp[i], "t"));
+    if (q.sp[i].nq != q.sp[0].nq) return fail(h, ITN_E_SHAPE, "mixed QN lengths");
+  }
+  const int nq = q.sp[0].nq;
+  std::vector<int32_t> flux(nq, 0);
+  if (t->flux) flux.assign(t->flux, t->flux + nq);
+  std::vector<std::vector<int32_t>> out;
+  std::vector<int32_t> blk(q.rank, 0);
+  std::function<void(int)> rec = [&](int i) {
+    if (i == q.rank) {
+      if (block_flux(q, blk) == flux) out.push_back(blk);
+      return;
+    }
+    for (int k = 0; k < q.sp[i].nsec; ++k) {
+      blk[i] = k;
+      rec(i + 1);
+    }
+  };
+  rec(0);
+  int64_t acc = 0;
+  std::vector<int64_t> offs;
+  for (auto& b : out) {
+    offs.push_back(acc);
+    int64_t sz = 1;
+    for (int i = 0; i < q.rank; ++i) sz *= q.sp[i].dim[b[i]];
+    acc += sz;
+  }
+  if (block_sec) {
+    if (!block_off) return fail(h, ITN_E_ARG, "block_off is NULL");
+    if (*nblocks < (int64_t)out.size()) return fail(h, ITN_E_ARG, "capacity %lld < %zu blocks",
+                                                    (long long)*nblocks, out.size());
+    for (size_t b = 0; b < out.size(); ++b) {
+      for (int i = 0; i < q.rank; ++i) block_sec[b * q.rank + i] = out[b][i];
+      block_off[b] = offs[b];
+    }
+  }
+  *nblocks = (int64_t)out.size();
+  *total = acc;
+  return ITN_OK;
+}
+
 itn_status itn_plan_destroy(itn_plan* plan) {
   delete plan;
   return ITN_OK;

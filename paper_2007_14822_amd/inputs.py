@@ -316,6 +316,49 @@ def c4_sector_dims(total: int = 4096, sigma: float = 2.0) -> List[Tuple[Tuple[in
     return out
 
 
+def sectors_from_basis_qns(qns: Sequence) -> Tuple[List[Tuple[int, ...]], List[int]]:
+    """Run-length encoding of a basis' QN list into (sector QNs, sector dims):
+    maximal runs of equal QN in basis order (equal QNs may repeat)."""
+    q_out: List[Tuple[int, ...]] = []
+    d_out: List[int] = []
+    for q in qns:
+        q = tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,)))
+        if q_out and q_out[-1] == q:
+            d_out[-1] += 1
+        else:
+            q_out.append(q)
+            d_out.append(1)
+    return q_out, d_out
+
+
+def long_range_hubbard_mpo(N: int, rmax: int, t: float = 1.0, U: float = 8.0) -> List[np.ndarray]:
+    """Synthetic Hubbard chain with equal hopping at every distance 1..rmax
+    (a charge-conserving MPO of w = 2 + 4 rmax, used as a shape)."""
+    o = hubbard_ops()
+    w = 2 + 4 * rmax
+    start = [o["Cdagup"] @ o["F"], o["Cdagdn"] @ o["F"], o["F"] @ o["Cup"], o["F"] @ o["Cdn"]]
+    close = [o["Cup"], o["Cdn"], o["Cdagup"], o["Cdagdn"]]
+
+    def ch(kind: int, r: int) -> int:
+        return 1 + kind * rmax + (r - 1)
+
+    Ws = []
+    for i in range(N):
+        W = np.zeros((w, w, 4, 4))
+        W[0, 0] = o["Id"]
+        W[w - 1, w - 1] = o["Id"]
+        W[w - 1, 0] = U * o["Nupdn"]
+        for k in range(4):
+            W[w - 1, ch(k, 1)] = start[k]
+            for r in range(1, rmax):
+                W[ch(k, r), ch(k, r + 1)] = o["F"]
+            for r in range(1, rmax + 1):
+                if i - r >= 0:
+                    W[ch(k, r), 0] = -t * close[k]
+        Ws.append(W)
+    return Ws
+
+
 def heisenberg_site_qn(two_s: int = 1) -> List[int]:
     """2Sz of each basis state (highest first)."""
     return [two_s - 2 * k for k in range(two_s + 1)]

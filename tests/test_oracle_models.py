@@ -120,3 +120,17 @@ def test_c4_sector_table():
     dims = [n for _, n in secs]
     assert sum(dims) == 4096
     assert len(secs) == 81 and max(dims) == 324 and min(dims) == 1
+
+
+def test_long_range_hubbard_mpo_equals_fock_space():
+    N, rmax = 5, 3
+    bonds = [(i, j) for i in range(N) for j in range(i + 1, min(N, i + rmax + 1))]
+    H_mpo = hf.mpo_to_dense(inp.long_range_hubbard_mpo(N, rmax, t=0.7, U=3.0))
+    H_ed = ed.hubbard_dense_bonds(N, bonds, t=0.7, U=3.0)
+    np.testing.assert_allclose(H_mpo, H_ed, atol=1e-12)
+    assert inp.long_range_hubbard_mpo(4, 9)[0].shape[0] == 38
+
+
+def test_sector_runs():
+    q, d = inp.sectors_from_basis_qns(inp.heisenberg_mpo_link_qn())
+    assert q == [(0,), (-2,), (2,), (0,)] and d == [1, 1, 1, 2]

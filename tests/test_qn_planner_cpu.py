@@ -88,3 +88,22 @@ def test_arrow_flux_and_shape_errors(host):
     with pytest.raises(itn.ItnError) as e:
         host.qn_plan(Ld, m1, m2, bad, Pd)
     assert e.value.name in ("ITN_E_SHAPE", "ITN_E_FLUX")
+
+
+@pytest.mark.parametrize("make", [U.small_u1, U.small_u1u1, U.c3_operands])
+def test_allowed_blocks_match_oracle(host, make):
+    ops, W1, W2 = make()
+    for bt in ops:
+        spaces = [U.space(i) for i in bt.inds]
+        blocks, offs, tot = host.qn_allowed_blocks(spaces)
+        ref = Q.allowed_blocks(bt.inds, bt.flux)
+        assert blocks == [tuple(b) for b in ref]
+        sizes = [int(np.prod([bt.inds[i].sdim(k) for i, k in enumerate(b)])) for b in ref]
+        assert offs == list(np.cumsum([0] + sizes)[:-1]) and tot == sum(sizes)
+
+
+def test_allowed_blocks_paper_flux_example(host):
+    # Sec. 8: i = (QN(0)=>2, QN(1)=>3), j = (QN(1)=>2, QN(2)=>1), flux QN(2)
+    spaces = [([(0,), (1,)], [2, 3], +1), ([(1,), (2,)], [2, 1], +1)]
+    blocks, offs, tot = host.qn_allowed_blocks(spaces, flux=[2])
+    assert blocks == [(0, 1), (1, 0)] and offs == [0, 2] and tot == 2 + 6
