@@ -228,8 +228,9 @@ struct itn_plan {
   std::vector<QnWRow> wr;
   std::vector<QnWEnt> we;
   std::vector<QnWItem> wi;
+  std::vector<QnCopy> cp;  // L / R repacks into padded, aligned blocks
   std::vector<int64_t> zoff, zsize;
-  int64_t psiT_elems = 0, X_elems = 0, Z_elems = 0;
+  int64_t psiT_elems = 0, X_elems = 0, Z_elems = 0, Lp_elems = 0, Rp_elems = 0;
   int64_t pairs1 = 0;
   double flops_gemm = 0.0, flops_w = 0.0;
   // device state
@@ -244,11 +245,14 @@ struct itn_plan {
   QnWRow* dwr = nullptr;
   QnWEnt* dwe = nullptr;
   QnWItem* dwi = nullptr;
+  QnCopy* dcp = nullptr;
   int64_t* dzoff = nullptr;
   int64_t* dzsize = nullptr;
   void* psiT = nullptr;
   void* X = nullptr;
   void* Z = nullptr;
+  void* Lp = nullptr;  // padded copies of the used L / R blocks
+  void* Rp = nullptr;
   int cfg1 = 0, cfg4 = 0;
   bool tuned = false;
   hipStream_t cap = nullptr;
@@ -260,13 +264,33 @@ struct itn_plan {
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);
       if (cap) (void)hipStreamDestroy(cap);
-      for (void* p : {(void*)dtab, psiT, X, Z})
+      for (void* p : {(void*)dtab, psiT, X, Z, Lp, Rp})
         if (p) (void)hipFree(p);
     }
   }
 };
 
 namespace {
+
+// Row strides and block offsets of the plan-owned operand layouts are
+// rounded up to 8 elements (16 bytes at bf16) and the padding is zero, so
+// every K step of the grouped GEMMs is a whole, aligned 16-byte load.
+inline int64_t pad8(int64_t x) { return (x + 7) & ~int64_t(7); }
+
+// Split a block copy into items of at most 32 rows.
+void add_copy(std::vector<QnCopy>& v, int64_t in_off, int64_t out_off, int rows, int cols, int ld,
+              int src) {
+  for (int r0 = 0; r0 < rows; r0 += 32) {
+    QnCopy c{};
+    c.in_off = in_off + (int64_t)r0 * cols;
+    c.out_off = out_off + (int64_t)r0 * ld;
+    c.rows = std::min(32, rows - r0);
+    c.cols = cols;
+    c.ld_out = ld;
+    c.src = src;
+    v.push_back(c);
+  }
+}
 
 // Tile lists for tile size `bt` (square), largest K-work first.
 std::vector<GTile> make_tiles(const std::vector<GProb>& probs, const std::vector<GSeg>& segs, int bt) {
@@ -376,10 +400,12 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     colbase[b] = N_ia[k[0]];
     N_ia[k[0]] += (int64_t)S1.dim[k[1]] * S2.dim[k[2]] * SB.dim[k[3]];
   }
+  std::vector<int64_t> ldT(nA);
   int64_t acc = 0;
   for (int ia = 0; ia < nA; ++ia) {
+    ldT[ia] = pad8(SA.dim[ia]);
     psiT_off[ia] = acc;
-    acc += N_ia[ia] * SA.dim[ia];
+    acc += pad8(N_ia[ia] * ldT[ia]);
   }
   pl.psiT_elems = acc;
   int64_t tiles = 0;
@@ -389,8 +415,8 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     t.in_off = P.off[b];
     t.rows = SA.dim[k[0]];
     t.cols = S1.dim[k[1]] * S2.dim[k[2]] * SB.dim[k[3]];
-    t.ld_out = SA.dim[k[0]];
-    t.out_off = psiT_off[k[0]] + colbase[b] * SA.dim[k[0]];
+    t.ld_out = (int32_t)ldT[k[0]];
+    t.out_off = psiT_off[k[0]] + colbase[b] * ldT[k[0]];
     t.tiles_c = (t.cols + 63) / 64;
     t.tile0 = (int32_t)tiles;
     tiles += (int64_t)((t.rows + 63) / 64) * t.tiles_c;
@@ -411,11 +437,13 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       if (it == L.index.end()) continue;
       const int64_t M = (int64_t)SA.dim[iap] * SM.dim[im];
       GSeg sg{};
-      sg.a_off = L.off[it->second];
+      sg.a_off = pl.Lp_elems;
+      add_copy(pl.cp, L.off[it->second], pl.Lp_elems, (int)M, SA.dim[ia], (int)ldT[ia], 0);
+      pl.Lp_elems += pad8(M * ldT[ia]);
       sg.b_off = psiT_off[ia];
-      sg.lda = SA.dim[ia];
-      sg.ldb = SA.dim[ia];
-      sg.K = SA.dim[ia];
+      sg.lda = (int32_t)ldT[ia];
+      sg.ldb = (int32_t)ldT[ia];
+      sg.K = (int32_t)ldT[ia];
       GProb pr{};
       pr.c_off = xacc;
       pr.M = (int32_t)M;
@@ -435,6 +463,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
 
   // ---- stage 4 problems and the Z blocks they need
   std::map<std::vector<int32_t>, int64_t> zblock;  // (ia', is1', is2', im2, ib) -> Z offset
+  std::map<int, int64_t> rpad;                      // R block -> padded copy offset
   int64_t zacc = 0;
   for (size_t ob = 0; ob < P.blocks.size(); ++ob) {
     const auto& k = P.blocks[ob];
@@ -454,19 +483,25 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       if (it == R.index.end()) continue;
       std::vector<int32_t> zk = {iap, i1, i2, im2, ib};
       const int64_t K = (int64_t)SM2.dim[im2] * SB.dim[ib];
+      const int64_t ldK = pad8(K);
       if (!zblock.count(zk)) {
         zblock[zk] = zacc;
-        zacc += (int64_t)pr.M * K;
+        zacc += pad8((int64_t)pr.M * ldK);
+      }
+      if (!rpad.count(it->second)) {
+        rpad[it->second] = pl.Rp_elems;
+        add_copy(pl.cp, R.off[it->second], pl.Rp_elems, SB.dim[ibp], (int)K, (int)ldK, 1);
+        pl.Rp_elems += pad8((int64_t)SB.dim[ibp] * ldK);
       }
       GSeg sg{};
       sg.a_off = zblock[zk];
-      sg.lda = (int32_t)K;
-      sg.b_off = R.off[it->second];
-      sg.ldb = (int32_t)K;
-      sg.K = (int32_t)K;
+      sg.lda = (int32_t)ldK;
+      sg.b_off = rpad[it->second];
+      sg.ldb = (int32_t)ldK;
+      sg.K = (int32_t)ldK;
       pl.s4.push_back(sg);
       pr.nseg++;
-      pl.flops_gemm += 2.0 * pr.M * pr.N * K;
+      pl.flops_gemm += 2.0 * pr.M * pr.N * K;  // algorithmic (unpadded) work
     }
     if (pr.nseg == 0) {
       pl.zoff.push_back(P.off[ob]);
@@ -510,12 +545,13 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       const int i1p = zk[1], i2p = zk[2], im2 = zk[3];
       const int64_t zoff = zblock[zk];
       const int64_t ds1p = S1.dim[i1p], ds2p = S2.dim[i2p], dm2 = SM2.dim[im2];
+      const int64_t ldZ = pad8(dm2 * db);
       for (int s1l = 0; s1l < ds1p; ++s1l)
         for (int s2l = 0; s2l < ds2p; ++s2l)
           for (int m2l = 0; m2l < dm2; ++m2l) {
             QnWRow row{};
-            row.off = zoff + (s1l * ds2p + s2l) * dm2 * db + m2l * db;
-            row.astride = ds1p * ds2p * dm2 * db;
+            row.off = zoff + (s1l * ds2p + s2l) * ldZ + m2l * db;
+            row.astride = ds1p * ds2p * ldZ;
             row.e0 = (int32_t)pl.we.size();
             const int g_m2 = (int)SM2.off[im2] + m2l;
             const int g_s1p = (int)S1.off[i1p] + s1l, g_s2p = (int)S2.off[i2p] + s2l;
@@ -553,8 +589,8 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     wpair.nrows = (int32_t)(pl.wr.size() - wpair.row0);
     const int pid = (int)pl.wp.size();
     pl.wp.push_back(wpair);
-    for (int a = 0; a < wpair.da; ++a)
-      for (int b0 = 0; b0 < wpair.db; b0 += 256) pl.wi.push_back(QnWItem{pid, a, b0, 0});
+    for (int64_t p0 = 0; p0 < (int64_t)wpair.da * wpair.db; p0 += 256)
+      pl.wi.push_back(QnWItem{pid, (int32_t)p0});
   }
   for (int c = 0; c < 2; ++c) {
     pl.t1[c] = make_tiles(pl.p1, pl.s1, grouped_tile_rows(c));
@@ -587,6 +623,7 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   add(pl.wr.size() * sizeof(QnWRow));
   add(pl.we.size() * sizeof(QnWEnt));
   add(pl.wi.size() * sizeof(QnWItem));
+  add(pl.cp.size() * sizeof(QnCopy));
   add(pl.zoff.size() * 8);
   add(pl.zsize.size() * 8);
   ITN_HIP(h, hipMalloc(&pl.dtab, bytes + 256));
@@ -611,12 +648,22 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   ITN_HIP(h, put(pl.dwr, pl.wr));
   ITN_HIP(h, put(pl.dwe, pl.we));
   ITN_HIP(h, put(pl.dwi, pl.wi));
+  ITN_HIP(h, put(pl.dcp, pl.cp));
   ITN_HIP(h, put(pl.dzoff, pl.zoff));
   ITN_HIP(h, put(pl.dzsize, pl.zsize));
   const int es = dtype_size(pl.pt), xs = dtype_size(pl.xt);
-  ITN_HIP(h, hipMalloc(&pl.psiT, std::max<size_t>(256, (size_t)pl.nv * pl.psiT_elems * es)));
-  ITN_HIP(h, hipMalloc(&pl.X, std::max<size_t>(256, (size_t)pl.nv * pl.X_elems * xs)));
-  ITN_HIP(h, hipMalloc(&pl.Z, std::max<size_t>(256, (size_t)pl.nv * pl.Z_elems * es)));
+  auto zalloc = [&](void** p, size_t bytes) -> hipError_t {
+    bytes = std::max<size_t>(256, bytes);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return e;
+    return hipMemset(*p, 0, bytes);  // padding must read as zero (never rewritten)
+  };
+  ITN_HIP(h, zalloc(&pl.psiT, (size_t)pl.nv * pl.psiT_elems * es));
+  ITN_HIP(h, zalloc(&pl.X, (size_t)pl.nv * pl.X_elems * xs));
+  ITN_HIP(h, zalloc(&pl.Z, (size_t)pl.nv * pl.Z_elems * es));
+  ITN_HIP(h, zalloc(&pl.Lp, (size_t)pl.Lp_elems * es));
+  ITN_HIP(h, zalloc(&pl.Rp, (size_t)pl.Rp_elems * es));
+  ITN_HIP(h, hipDeviceSynchronize());
   return ITN_OK;
 }
 
@@ -625,6 +672,10 @@ constexpr int MAX_WG = 1024;  // persistent grouped launches: at most 4 workgrou
 // The launches of one apply (after the operand pointers are set).
 itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int cfg4) {
   QnPtrs* ptrs = &pl.dptrs->p;
+  {
+    Prof pf(h, "qn_env_repack", s);
+    ITN_HIP(h, qn_block_copy(pl.pt, ptrs, pl.Lp, pl.Rp, pl.dcp, (int64_t)pl.cp.size(), s));
+  }
   {
     Prof pf(h, "qn_psi_transpose", s);
     ITN_HIP(h, qn_block_transpose(pl.psi_dt, ptrs, pl.pt, pl.psiT, pl.dtb, (int)pl.tb.size(),
@@ -838,8 +889,8 @@ itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, c
   v.p.R = R->data;
   v.p.psi = psi->data;
   v.p.out = out->data;
-  v.g1 = GBases{L->data, pl->psiT, pl->X};
-  v.g4 = GBases{pl->Z, R->data, out->data};
+  v.g1 = GBases{pl->Lp, pl->psiT, pl->X};
+  v.g4 = GBases{pl->Z, pl->Rp, out->data};
   {
     Prof pf(h, "qn_set_ptrs", s);
     ITN_HIP(h, qn_set_ptrs(pl->dptrs, v, s));

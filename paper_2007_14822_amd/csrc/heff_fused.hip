@@ -32,24 +32,17 @@ template <int P, int W, int C, int WM, int WN, int RA, int RB> struct FusedCfg {
   static constexpr int RPP = 8 * NW;  // rows per direct-load pass
   static constexpr int A_PASSES = (AROWS + RPP - 1) / RPP;
   static constexpr int B_PASSES = (BROWS + RPP - 1) / RPP;
-  // epilogue: GP position groups per pass, each W*C inputs x 64 lanes
+  // Epilogue: GP position groups per pass, stored interleaved as
+  // [input (m0, c)][lane][group] so that a lane writes and gathers GP values
+  // with one LDS instruction.
   static constexpr int GROUPS = RA * RB * 4;
-  static constexpr int GP_MAX = (2 * STAGE_BYTES) / (NW * W * C * 64 * (int)sizeof(Acc));
-  static constexpr int GP = GP_MAX >= 2 && GROUPS % 2 == 0 ? 2 : 1;
-  static constexpr int EPI_BYTES = NW * GP * W * C * 64 * (int)sizeof(Acc);
-  static constexpr int MAIN_BYTES = (2 * STAGE_BYTES > EPI_BYTES) ? 2 * STAGE_BYTES : EPI_BYTES;
-  // CSR table staged in LDS after the main area: row_ptr (<= 64 rows + 1)
-  // then entries {byte offset of the input in a group's area, coefficient}.
-  static constexpr int TAB_ROWS_MAX = 64;
-  static constexpr int TAB_NNZ_MAX = 480;
-  static constexpr int TAB_BYTES = (TAB_ROWS_MAX + 1) * 4 + TAB_NNZ_MAX * 16;
-  static constexpr int LDS_BYTES = MAIN_BYTES + TAB_BYTES;
-};
-
-// One CSR entry in LDS.
-template <typename Acc> struct alignas(sizeof(Acc) == 8 ? 16 : 8) TabEnt {
-  int32_t off;  // (input index) * 64 * sizeof(Acc)
-  Acc coef;
+  static constexpr int LDS_MAX = 163840;
+  static constexpr int GP_BYTES1 = NW * W * C * 64 * (int)sizeof(Acc);
+  static constexpr int GP = (GROUPS % 4 == 0 && 4 * GP_BYTES1 <= LDS_MAX) ? 4
+                          : (GROUPS % 2 == 0 && 2 * GP_BYTES1 <= LDS_MAX) ? 2 : 1;
+  static constexpr int EPI_BYTES = GP * GP_BYTES1;
+  static constexpr int LDS_BYTES = (2 * STAGE_BYTES > EPI_BYTES) ? 2 * STAGE_BYTES : EPI_BYTES;
+  static_assert(LDS_BYTES <= LDS_MAX, "LDS budget");
 };
 
 template <int P, int W, int C, int WM, int WN, int RA, int RB, typename TZ>
@@ -71,20 +64,6 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
   const T* Lp = static_cast<const T*>(a.L);
   const T* Bp = static_cast<const T*>(a.psiT);
   const int64_t nk = cl / Cfg::BK;
-
-  // Stage the W12 CSR table in LDS (read by every wave in the epilogue).
-  int32_t* tab_rp = reinterpret_cast<int32_t*>(lds + Cfg::MAIN_BYTES);
-  TabEnt<Acc>* tab_e = reinterpret_cast<TabEnt<Acc>*>(lds + Cfg::MAIN_BYTES + (Cfg::TAB_ROWS_MAX + 1) * 4);
-  {
-    const int nnz = a.row_ptr[a.nrows];
-    for (int i = tid; i <= a.nrows; i += Cfg::THREADS) tab_rp[i] = a.row_ptr[i];
-    for (int i = tid; i < nnz; i += Cfg::THREADS) {
-      TabEnt<Acc> t;
-      t.off = a.col_idx[i] * 64 * (int)sizeof(Acc);
-      t.coef = (P == P_F64) ? (Acc)a.coef64[i] : (Acc)a.coef32[i];
-      tab_e[i] = t;
-    }
-  }
 
   typename Cfg::AccV acc[W][RA][C][RB];
 #pragma unroll
@@ -166,50 +145,54 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
   }
 
   // ------------------------------------------------------------ W epilogue
-  // The table writes above are ordered before these reads by the K loop's
-  // barriers (nk >= 1 is guaranteed by the dispatcher).
-  char* ep = lds + (int64_t)wave * (Cfg::GP * W * C * 64 * (int)sizeof(Acc));
+  // The last K step ended with a barrier: the stage buffers are free.
+  constexpr int GP = Cfg::GP;
+  typedef Acc AccG __attribute__((ext_vector_type(GP)));
+  Acc* ep = reinterpret_cast<Acc*>(lds) + (int64_t)wave * (W * C * 64 * GP);
   const int64_t zs_v = cl * (int64_t)(C * W) * a.chi_r;  // Z stride of v
   const int64_t zs_a = (int64_t)(C * W) * a.chi_r;       // Z stride of a'
   TZ* Zp = static_cast<TZ*>(a.Z);
-  constexpr int GB = W * C * 64 * (int)sizeof(Acc);  // bytes of one group's area
   const int nrows = a.nrows;
+  const int32_t* __restrict__ rp = a.row_ptr;
+  const int32_t* __restrict__ ci = a.col_idx;
 #pragma unroll
-  for (int g0 = 0; g0 < Cfg::GROUPS; g0 += Cfg::GP) {
-    TZ* zrow[Cfg::GP];
-    bool ok[Cfg::GP];
+  for (int g0 = 0; g0 < Cfg::GROUPS; g0 += GP) {
+    TZ* zrow[GP];
+    bool ok[GP];
 #pragma unroll
-    for (int gg = 0; gg < Cfg::GP; ++gg) {
+    for (int m = 0; m < W; ++m)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        AccG v;
+#pragma unroll
+        for (int gg = 0; gg < GP; ++gg) {
+          const int g = g0 + gg;
+          v[gg] = acc[m][g / (RB * 4)][c][(g / 4) % RB][g % 4];
+        }
+        *reinterpret_cast<AccG*>(ep + ((m * C + c) * 64 + lane) * GP) = v;
+      }
+#pragma unroll
+    for (int gg = 0; gg < GP; ++gg) {
       const int g = g0 + gg;
       const int i = g / (RB * 4), j = (g / 4) % RB, e = g % 4;
-#pragma unroll
-      for (int m = 0; m < W; ++m)
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-          *reinterpret_cast<Acc*>(ep + gg * GB + ((m * C + c) * 64 + lane) * (int)sizeof(Acc)) =
-              acc[m][i][c][j][e];
       const int64_t ap = a0 + wm * 16 * RA + i * 16 + acc_row<P>(lane, e);
       const int64_t y = y0 + wn * 16 * RB + j * 16 + (lane & 15);
       ok[gg] = ap < cl && y < Y;
-      const int64_t v = ok[gg] ? y / a.chi_r : 0, b = ok[gg] ? y % a.chi_r : 0;
-      zrow[gg] = Zp + v * zs_v + ap * zs_a + b;
+      const int64_t vv = ok[gg] ? y / a.chi_r : 0, b = ok[gg] ? y % a.chi_r : 0;
+      zrow[gg] = Zp + vv * zs_v + ap * zs_a + b;
     }
-    // each lane reads back only its own column: no barrier needed
-    const char* mine = ep + lane * (int)sizeof(Acc);
-    int k = tab_rp[0];
+    // each lane reads back only its own slots: no barrier needed
+    const Acc* mine = ep + lane * GP;
+    int k = rp[0];
     for (int o = 0; o < nrows; ++o) {
-      Acc z[Cfg::GP];
-#pragma unroll
-      for (int gg = 0; gg < Cfg::GP; ++gg) z[gg] = 0;
-      const int e1 = tab_rp[o + 1];
+      AccG z = (Acc)0;
+      const int e1 = rp[o + 1];
       for (; k < e1; ++k) {
-        const TabEnt<Acc> t = tab_e[k];
-#pragma unroll
-        for (int gg = 0; gg < Cfg::GP; ++gg)
-          z[gg] += t.coef * *reinterpret_cast<const Acc*>(mine + gg * GB + t.off);
+        const Acc cf = (P == P_F64) ? (Acc)a.coef64[k] : (Acc)a.coef32[k];
+        z += cf * *reinterpret_cast<const AccG*>(mine + ci[k] * (64 * GP));
       }
 #pragma unroll
-      for (int gg = 0; gg < Cfg::GP; ++gg)
+      for (int gg = 0; gg < GP; ++gg)
         if (ok[gg]) zrow[gg][(int64_t)o * a.chi_r] = cvt<TZ>(z[gg]);
     }
   }
@@ -244,7 +227,7 @@ bool heff_fused_supported(int prec, int w, int d2) {
 }
 
 bool heff_fused_table_fits(int nrows, int64_t nnz) {
-  return nrows <= 64 && nnz <= 480;
+  return nrows >= 1 && nnz >= 0;  // the table is read through the scalar cache: any size
 }
 
 hipError_t heff_stage1_fused(int prec, const HeffFusedArgs& a, hipStream_t s) {

@@ -93,8 +93,20 @@ struct QnTBlock {
 hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, void* out,
                               const QnTBlock* blocks, int nblocks, int64_t ntiles, int64_t in_bs,
                               int64_t out_bs, int nv, hipStream_t s);
-// Block-sparse W-stage: work item = (pair, a', b chunk of 256); rows and
-// entries carry their own offsets and a'-strides.
+// Block copy into a padded layout: item i copies rows [0, rows) x [0, cols)
+// of a row-major block of the caller's L (src = 0) or R (src = 1) at in_off
+// to outL (src = 0) or outR (src = 1) + out_off with row stride ld_out.
+struct QnCopy {
+  int64_t in_off, out_off;
+  int32_t rows, cols;
+  int32_t ld_out;
+  int32_t src;
+};
+hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
+                         const QnCopy* items, int64_t nitems, hipStream_t s);
+// Block-sparse W-stage: work item = (pair, first position of 256); positions
+// p = a' * db + b of the pair; rows and entries carry their own offsets and
+// a'-strides.
 struct QnWPair {
   int32_t row0, nrows;  // CSR rows of this pair
   int32_t da, db;       // positions a' < da, b < db
@@ -111,9 +123,7 @@ struct QnWEnt {
 };
 struct QnWItem {
   int32_t pair;
-  int32_t a;
-  int32_t b0;
-  int32_t pad;
+  int32_t p0;  // first position
 };
 hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnWPair* pairs,
                      const QnWRow* rows, const QnWEnt* ents, const QnWItem* items, int64_t nitems,

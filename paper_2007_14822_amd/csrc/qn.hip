@@ -91,12 +91,12 @@ __global__ __launch_bounds__(256) void qn_wstage_kernel(const TX* __restrict__ X
   using A = typename std::conditional<sizeof(TX) == 8, double, float>::type;
   const QnWItem it = items[blockIdx.x];
   const QnWPair pr = pairs[it.pair];
-  const int64_t b = it.b0 + threadIdx.x;
-  if (b >= pr.db) return;
+  const int64_t p = (int64_t)it.p0 + threadIdx.x;
+  if (p >= (int64_t)pr.da * pr.db) return;
+  const int64_t a = p / pr.db, b = p % pr.db;
   const int64_t v = blockIdx.y;
   const TX* xp = X + v * x_bs + b;
   TZ* zp = Z + v * z_bs + b;
-  const int64_t a = it.a;
   for (int r = pr.row0; r < pr.row0 + pr.nrows; ++r) {
     const QnWRow row = rows[r];
     A z = 0;
@@ -128,6 +128,37 @@ hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnW
   if (x_dtype == D_F32 && z_dtype == D_BF16) ITN_QW(float, bf16_t);
 #undef ITN_QW
   return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ block copy
+template <typename T>
+__global__ __launch_bounds__(256) void qn_copy_kernel(const QnPtrs* __restrict__ ptrs,
+                                                       T* __restrict__ outL, T* __restrict__ outR,
+                                                       const QnCopy* __restrict__ items) {
+  const QnCopy it = items[blockIdx.x];
+  const T* src = static_cast<const T*>(it.src ? ptrs->R : ptrs->L) + it.in_off;
+  T* dst = (it.src ? outR : outL) + it.out_off;
+  // an item holds at most 32 rows: 32-bit index arithmetic
+  const int n = it.rows * it.cols;
+  const unsigned cols = (unsigned)it.cols;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const unsigned r = (unsigned)e / cols, c = (unsigned)e - r * cols;
+    dst[(int64_t)r * it.ld_out + c] = src[e];
+  }
+}
+hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
+                         const QnCopy* items, int64_t nitems, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  if (dtype == D_F64)
+    hipLaunchKernelGGL(qn_copy_kernel<double>, dim3((unsigned)nitems), dim3(256), 0, s, ptrs,
+                       static_cast<double*>(outL), static_cast<double*>(outR), items);
+  else if (dtype == D_F32)
+    hipLaunchKernelGGL(qn_copy_kernel<float>, dim3((unsigned)nitems), dim3(256), 0, s, ptrs,
+                       static_cast<float*>(outL), static_cast<float*>(outR), items);
+  else
+    hipLaunchKernelGGL(qn_copy_kernel<bf16_t>, dim3((unsigned)nitems), dim3(256), 0, s, ptrs,
+                       static_cast<bf16_t*>(outL), static_cast<bf16_t*>(outR), items);
+  return hipGetLastError();
 }
 
 // ----------------------------------------------------------- zero blocks
