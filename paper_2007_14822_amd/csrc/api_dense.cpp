@@ -593,6 +593,7 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
     fa.d2 = (int)d2;
     fa.nv = nv;
     fa.nrows = tab->nrows;
+    fa.nnz = (int32_t)tab->nnz;
     fa.row_ptr = tab->row_ptr;
     fa.col_idx = tab->col_idx;
     fa.coef32 = tab->coef32;

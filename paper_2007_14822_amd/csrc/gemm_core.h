@@ -228,22 +228,22 @@ __device__ __forceinline__ void gemm_accum_direct(
     if (!fullB && gr >= N) gr = N - 1;
     return B + gr * ldb + chunk;
   };
-  auto issue = [&](int buf, int64_t k0) {
-    char* a = lds + buf * C::STAGE_BYTES + wave * 8 * ROW_BYTES;
-    char* b = lds + buf * C::STAGE_BYTES + BM * ROW_BYTES + wave * 8 * ROW_BYTES;
+  auto issue = [&](char* __restrict__ stage, int64_t k0) {
+    char* a = stage + wave * 8 * ROW_BYTES;
+    char* b = stage + BM * ROW_BYTES + wave * 8 * ROW_BYTES;
 #pragma unroll
     for (int p = 0; p < C::A_PASSES; ++p) lds_direct16(rowA(p) + k0, a + p * C::ROWS_PER_PASS * ROW_BYTES);
 #pragma unroll
     for (int p = 0; p < C::B_PASSES; ++p) lds_direct16(rowB(p) + k0, b + p * C::ROWS_PER_PASS * ROW_BYTES);
   };
-
-  issue(0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) issue(cur ^ 1, (kt + 1) * C::BK);
-    const char* As = lds + cur * C::STAGE_BYTES;
+  // One K step: the direct loads of the next stage into `nxt` overlap the
+  // MFMAs on `cur`.  The stages never alias; the restrict-qualified
+  // parameters let the compiler see that, so it does not wait for the
+  // loads before its LDS reads of `cur` (the wait at the end of the step
+  // is explicit).
+  auto kstep = [&](const char* __restrict__ cur, char* __restrict__ nxt, bool more, int64_t k0) {
+    if (more) issue(nxt, k0);
+    const char* As = cur;
     const char* Bs = As + BM * ROW_BYTES;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
@@ -264,6 +264,15 @@ __device__ __forceinline__ void gemm_accum_direct(
     }
     __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next tile have landed in LDS
     __syncthreads();
+  };
+
+  issue(lds, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    kstep(lds + cur * C::STAGE_BYTES, lds + (cur ^ 1) * C::STAGE_BYTES, kt + 1 < nk,
+          (kt + 1) * C::BK);
   }
 }
 

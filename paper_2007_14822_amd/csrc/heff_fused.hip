@@ -11,6 +11,10 @@
 // epilogue writes them to a per-wave LDS area (input-major, lane-minor, so
 // that the gather below is bank-conflict free), then applies W12 row by row
 // from a CSR table and writes Z straight to HBM.  X never leaves the chip.
+// The CSR table (at most 63 rows and 128 entries) is loaded into lane
+// registers when the kernel starts, under the main loop, and read back
+// with readlane: the epilogue issues no memory loads besides its LDS
+// gathers.
 #include "gemm_core.h"
 #include "kernels.h"
 
@@ -65,6 +69,21 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
   const T* Bp = static_cast<const T*>(a.psiT);
   const int64_t nk = cl / Cfg::BK;
 
+  // W12 table in lane registers: lane l holds row_ptr[l] and entries l and
+  // 64 + l (LDS byte offset of the gathered input and coefficient).
+  constexpr int GP = Cfg::GP;
+  constexpr int IN_BYTES = 64 * GP * (int)sizeof(Acc);  // LDS bytes per input
+  const int tab_rp = lane <= a.nrows ? a.row_ptr[lane] : 0;
+  int tab_off[2];
+  Acc tab_cf[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = h * 64 + lane;
+    const bool in = e < a.nnz;
+    tab_off[h] = in ? a.col_idx[e] * IN_BYTES : 0;
+    tab_cf[h] = in ? ((P == P_F64) ? (Acc)a.coef64[e] : (Acc)a.coef32[e]) : (Acc)0;
+  }
+
   typename Cfg::AccV acc[W][RA][C][RB];
 #pragma unroll
   for (int m = 0; m < W; ++m)
@@ -112,10 +131,22 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) issue(cur ^ 1, (kt + 1) * Cfg::BK);
-    const char* As = lds + cur * Cfg::STAGE_BYTES;
+  // One K step: direct loads of the next stage into `nxt` overlap the MFMAs
+  // on `cur`.  The two stages never alias; restrict-qualified parameters let
+  // the compiler see that and not wait for the loads before reading `cur`.
+  auto kstep = [&](const char* __restrict__ cur, char* __restrict__ nxt, bool more, int64_t k0) {
+    if (more) {
+      char* base = nxt + wave * 8 * ROW_BYTES;
+#pragma unroll
+      for (int p = 0; p < Cfg::A_PASSES; ++p)
+        if (p * Cfg::RPP + wave * 8 < Cfg::AROWS)
+          lds_direct16(srcA(p) + k0, base + p * Cfg::RPP * ROW_BYTES);
+#pragma unroll
+      for (int p = 0; p < Cfg::B_PASSES; ++p)
+        if (p * Cfg::RPP + wave * 8 < Cfg::BROWS)
+          lds_direct16(srcB(p) + k0, base + (Cfg::AROWS + p * Cfg::RPP) * ROW_BYTES);
+    }
+    const char* As = cur;
     const char* Bs = As + Cfg::AROWS * ROW_BYTES;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
@@ -142,19 +173,36 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+  };
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    kstep(lds + cur * Cfg::STAGE_BYTES, lds + (cur ^ 1) * Cfg::STAGE_BYTES, kt + 1 < nk,
+          (kt + 1) * Cfg::BK);
   }
 
   // ------------------------------------------------------------ W epilogue
   // The last K step ended with a barrier: the stage buffers are free.
-  constexpr int GP = Cfg::GP;
   typedef Acc AccG __attribute__((ext_vector_type(GP)));
-  Acc* ep = reinterpret_cast<Acc*>(lds) + (int64_t)wave * (W * C * 64 * GP);
+  char* ep = lds + wave * (W * C * IN_BYTES);
   const int64_t zs_v = cl * (int64_t)(C * W) * a.chi_r;  // Z stride of v
   const int64_t zs_a = (int64_t)(C * W) * a.chi_r;       // Z stride of a'
   TZ* Zp = static_cast<TZ*>(a.Z);
-  const int nrows = a.nrows;
-  const int32_t* __restrict__ rp = a.row_ptr;
-  const int32_t* __restrict__ ci = a.col_idx;
+  // entry k of the table, broadcast from the lane that holds it
+  auto entry = [&](int k, int& off, Acc& cf) {
+    const int h = k >> 6, l = k & 63;
+    const int ov = h ? tab_off[1] : tab_off[0];
+    off = __builtin_amdgcn_readlane(ov, l);
+    if constexpr (sizeof(Acc) == 8) {
+      const double cv = h ? tab_cf[1] : tab_cf[0];
+      const int64_t bits = __builtin_bit_cast(int64_t, cv);
+      const int lo = __builtin_amdgcn_readlane((int)bits, l);
+      const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+      cf = __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
+    } else {
+      const float cv = h ? tab_cf[1] : tab_cf[0];
+      cf = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, cv), l));
+    }
+  };
 #pragma unroll
   for (int g0 = 0; g0 < Cfg::GROUPS; g0 += GP) {
     TZ* zrow[GP];
@@ -169,7 +217,7 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
           const int g = g0 + gg;
           v[gg] = acc[m][g / (RB * 4)][c][(g / 4) % RB][g % 4];
         }
-        *reinterpret_cast<AccG*>(ep + ((m * C + c) * 64 + lane) * GP) = v;
+        *reinterpret_cast<AccG*>(ep + (m * C + c) * IN_BYTES + lane * (GP * (int)sizeof(Acc))) = v;
       }
 #pragma unroll
     for (int gg = 0; gg < GP; ++gg) {
@@ -181,20 +229,33 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
       const int64_t vv = ok[gg] ? y / a.chi_r : 0, b = ok[gg] ? y % a.chi_r : 0;
       zrow[gg] = Zp + vv * zs_v + ap * zs_a + b;
     }
-    // each lane reads back only its own slots: no barrier needed
-    const Acc* mine = ep + lane * GP;
-    int k = rp[0];
-    for (int o = 0; o < nrows; ++o) {
+    // Each lane reads back only its own slots: no barrier needed.  All
+    // W*C output rows are formed in registers first, then stored together.
+    const char* mine = ep + lane * (GP * (int)sizeof(Acc));
+    int k = __builtin_amdgcn_readlane(tab_rp, 0);
+    AccG zz[W * C];
+#pragma unroll
+    for (int o = 0; o < W * C; ++o) {
       AccG z = (Acc)0;
-      const int e1 = rp[o + 1];
-      for (; k < e1; ++k) {
-        const Acc cf = (P == P_F64) ? (Acc)a.coef64[k] : (Acc)a.coef32[k];
-        z += cf * *reinterpret_cast<const AccG*>(mine + ci[k] * (64 * GP));
+      const int e1 = __builtin_amdgcn_readlane(tab_rp, o + 1);
+      for (; k < e1; k += 2) {
+        int o0, o1;
+        Acc c0, c1;
+        entry(k, o0, c0);
+        entry(k + 1 < e1 ? k + 1 : k, o1, c1);
+        if (k + 1 >= e1) c1 = (Acc)0;
+        const AccG x0 = *reinterpret_cast<const AccG*>(mine + o0);
+        const AccG x1 = *reinterpret_cast<const AccG*>(mine + o1);
+        z += c0 * x0 + c1 * x1;
       }
+      k = e1;
+      zz[o] = z;
+    }
+#pragma unroll
+    for (int o = 0; o < W * C; ++o)
 #pragma unroll
       for (int gg = 0; gg < GP; ++gg)
-        if (ok[gg]) zrow[gg][(int64_t)o * a.chi_r] = cvt<TZ>(z[gg]);
-    }
+        if (ok[gg]) zrow[gg][(int64_t)o * a.chi_r] = cvt<TZ>(zz[o][gg]);
   }
 }
 
@@ -227,11 +288,13 @@ bool heff_fused_supported(int prec, int w, int d2) {
 }
 
 bool heff_fused_table_fits(int nrows, int64_t nnz) {
-  return nrows >= 1 && nnz >= 0;  // the table is read through the scalar cache: any size
+  return nrows >= 1 && nrows <= 63 && nnz >= 0 && nnz <= 128;  // lane-register table
 }
 
 hipError_t heff_stage1_fused(int prec, const HeffFusedArgs& a, hipStream_t s) {
   if (!heff_fused_supported(prec, a.w, a.d2)) return hipErrorInvalidValue;
+  // the epilogue unrolls over all w*d2 output rows of W12
+  if (a.nrows != a.w * a.d2 || !heff_fused_table_fits(a.nrows, a.nnz)) return hipErrorInvalidValue;
   switch (prec) {
     case P_BF16:
       if (a.d2 == 4) return launch_fused<P_BF16, 5, 4, 2, 4, 2, 1>(a, s);

@@ -170,7 +170,8 @@ struct HeffFusedArgs {
   void* Z;           // [nv, chi_l, d2, w, chi_r]
   int64_t chi_l, chi_r;
   int32_t w, d2, nv;
-  int32_t nrows;     // CSR rows = d2*w (output (c', m2))
+  int32_t nrows;     // CSR rows = d2*w (output (c', m2)), at most 63
+  int32_t nnz;       // CSR entries, at most 128
   const int32_t* row_ptr;
   const int32_t* col_idx;  // input index m0*d2 + c
   const float* coef32;
