@@ -101,13 +101,18 @@ hipError_t permute_cast(int in_dtype, const void* in, int out_dtype, void* out, 
 
 // --------------------------------------------------------------- transpose
 // 64x64 tiles through LDS: coalesced reads along c, coalesced writes along r.
+// The tile holds FP64 only for FP64 output (bf16 conversion from FP64 goes
+// through FP32 either way), which keeps the LDS footprint, and so the
+// number of resident tiles, up for the common FP64 -> bf16/FP32 case.  Each
+// lane writes two consecutive r of an output row.
 constexpr int TT = 64;
+template <typename TO> struct alignas(2 * sizeof(TO)) Pair { TO v[2]; };
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ in,
                                                          TO* __restrict__ out, TransposeArgs t,
                                                          int64_t tiles_r, int64_t tiles_c) {
-  __shared__ float tile[TT][TT + 1];
-  __shared__ double tile64[(sizeof(TI) == 8) ? TT : 1][TT + 1];
+  using TS = typename std::conditional<sizeof(TO) == 8, double, float>::type;
+  __shared__ TS tile[TT][TT + 1];
   const int64_t z = blockIdx.y;
   const int64_t zb = z / t.nzc, zc = z % t.nzc;
   const int64_t tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
@@ -115,19 +120,30 @@ __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ i
   const TI* ip = in + zb * t.in_zb + zc * t.in_zc;
   TO* op = out + zb * t.out_zb + zc * t.out_zc;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+#pragma unroll 4
   for (int i = ty; i < TT; i += 4) {
     const int64_t r = r0 + i, c = c0 + tx;
-    if (r < t.rows && c < t.cols) {
-      if constexpr (sizeof(TI) == 8) tile64[i][tx] = (double)ip[r * t.in_r + c * t.in_c];
-      else tile[i][tx] = (float)ip[r * t.in_r + c * t.in_c];
-    }
+    using TW = typename std::conditional<sizeof(TI) == 8, double, float>::type;  // exact widening of TI
+    if (r < t.rows && c < t.cols) tile[i][tx] = (TS)(TW)ip[r * t.in_r + c * t.in_c];
   }
   __syncthreads();
-  for (int i = ty; i < TT; i += 4) {
-    const int64_t c = c0 + i, r = r0 + tx;
-    if (r < t.rows && c < t.cols) {
-      if constexpr (sizeof(TI) == 8) op[c * t.out_c + r * t.out_r] = conv<TO, double>(tile64[tx][i]);
-      else op[c * t.out_c + r * t.out_r] = conv<TO, float>(tile[tx][i]);
+  const int px = threadIdx.x & 31, py = threadIdx.x >> 5;  // 32 pairs x 8 rows
+  const int64_t r = r0 + 2 * px;
+  const bool pair_ok = t.out_r == 1 && r + 1 < t.rows;
+#pragma unroll 4
+  for (int i = py; i < TT; i += 8) {
+    const int64_t c = c0 + i;
+    if (c >= t.cols || r >= t.rows) continue;
+    TO* p = op + c * t.out_c + r * t.out_r;
+    const TO v0 = conv<TO, TS>(tile[2 * px][i]);
+    if (pair_ok && (reinterpret_cast<uintptr_t>(p) % sizeof(Pair<TO>)) == 0) {
+      Pair<TO> pr;
+      pr.v[0] = v0;
+      pr.v[1] = conv<TO, TS>(tile[2 * px + 1][i]);
+      *reinterpret_cast<Pair<TO>*>(p) = pr;
+    } else {
+      p[0] = v0;
+      if (r + 1 < t.rows) p[t.out_r] = conv<TO, TS>(tile[2 * px + 1][i]);
     }
   }
 }

@@ -150,7 +150,13 @@ static hipError_t dispatch_nt(const GemmArgs& g, hipStream_t s) {
   // Largest tile that still gives every CU at least one workgroup; small
   // problems use 64x64 tiles so that the launch spreads over the CUs.
   auto ntiles = [&](int bm, int bn) { return ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.batch; };
-  if constexpr (P == P_BF16) {
+  // Direct-to-LDS tiles of 8 waves: 256 x 256 for 4-byte accumulators
+  // (128 accumulator registers per lane); FP64 accumulators are twice as
+  // wide, so FP64 uses 256 x 128.
+  if constexpr (P == P_F64) {
+    if (g.M >= 256 && g.N >= 128 && ntiles(256, 128) >= 256 && direct_ok<P>(g))
+      return launch_nt_direct<P, 256, 128, 2, 4, TOut>(g, s);
+  } else {
     if (g.M >= 256 && g.N >= 256 && ntiles(256, 256) >= 256 && direct_ok<P>(g))
       return launch_nt_direct<P, 256, 256, 2, 4, TOut>(g, s);
   }
