@@ -195,6 +195,9 @@ typedef struct {
   int64_t n_pairs_stage4;  /* block pairs Z x R                                   */
   int64_t n_tiles;         /* work items of the grouped launches                  */
   double flops;            /* 2*M*N*K summed over contributing block products, x nv */
+  int64_t x_elems;         /* stage-1 intermediate X, elements per vector         */
+  int64_t z_elems;         /* W-stage output Z (stage-4 operand), per vector      */
+  double flops_wstage;     /* 2 * W12 terms * positions, x nv (not in flops)      */
 } itn_plan_info;
 itn_status itn_plan_query(const itn_plan* plan, itn_plan_info* info);
 /* Copy the output block table: block_sec[out_nblocks*4], block_off[out_nblocks]. */

@@ -223,14 +223,15 @@ struct itn_plan {
   std::vector<GSeg> s1, s4;
   std::vector<GTile> t1[2], t4[2];
   std::vector<QnTBlock> tb;
+  std::vector<int32_t> tbi;  // block of every transpose tile
   int64_t tb_tiles = 0;
   std::vector<QnWPair> wp;
-  std::vector<QnWRow> wr;
   std::vector<QnWEnt> we;
   std::vector<QnWItem> wi;
   std::vector<QnCopy> cp;  // L / R repacks into padded, aligned blocks
   std::vector<int64_t> zoff, zsize;
   int64_t psiT_elems = 0, X_elems = 0, Z_elems = 0, Lp_elems = 0, Rp_elems = 0;
+  int64_t max_db = 0;  // widest right bond sector
   int64_t pairs1 = 0;
   double flops_gemm = 0.0, flops_w = 0.0;
   // device state
@@ -241,8 +242,8 @@ struct itn_plan {
   GSeg *ds1 = nullptr, *ds4 = nullptr;
   GTile *dt1[2] = {nullptr, nullptr}, *dt4[2] = {nullptr, nullptr};
   QnTBlock* dtb = nullptr;
+  int32_t* dtbi = nullptr;
   QnWPair* dwp = nullptr;
-  QnWRow* dwr = nullptr;
   QnWEnt* dwe = nullptr;
   QnWItem* dwi = nullptr;
   QnCopy* dcp = nullptr;
@@ -419,7 +420,9 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     t.out_off = psiT_off[k[0]] + colbase[b] * ldT[k[0]];
     t.tiles_c = (t.cols + 63) / 64;
     t.tile0 = (int32_t)tiles;
-    tiles += (int64_t)((t.rows + 63) / 64) * t.tiles_c;
+    const int64_t nt = (int64_t)((t.rows + 63) / 64) * t.tiles_c;
+    tiles += nt;
+    pl.tbi.insert(pl.tbi.end(), (size_t)nt, (int32_t)pl.tb.size());
     pl.tb.push_back(t);
   }
   pl.tb_tiles = tiles;
@@ -537,10 +540,11 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   for (auto& kv : pairs) {
     const int iap = kv.first.first, ib = kv.first.second;
     QnWPair wpair{};
-    wpair.row0 = (int32_t)pl.wr.size();
+    wpair.e0 = (int32_t)pl.we.size();
     wpair.da = SA.dim[iap];
     wpair.db = SB.dim[ib];
     const int64_t db = SB.dim[ib];
+    pl.max_db = std::max<int64_t>(pl.max_db, db);
     for (auto& zk : kv.second) {
       const int i1p = zk[1], i2p = zk[2], im2 = zk[3];
       const int64_t zoff = zblock[zk];
@@ -549,10 +553,9 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       for (int s1l = 0; s1l < ds1p; ++s1l)
         for (int s2l = 0; s2l < ds2p; ++s2l)
           for (int m2l = 0; m2l < dm2; ++m2l) {
-            QnWRow row{};
-            row.off = zoff + (s1l * ds2p + s2l) * ldZ + m2l * db;
-            row.astride = ds1p * ds2p * ldZ;
-            row.e0 = (int32_t)pl.we.size();
+            const int64_t row_off = zoff + (s1l * ds2p + s2l) * ldZ + m2l * db;
+            const int64_t row_astride = ds1p * ds2p * ldZ;
+            const size_t row_e0 = pl.we.size();
             const int g_m2 = (int)SM2.off[im2] + m2l;
             const int g_s1p = (int)S1.off[i1p] + s1l, g_s2p = (int)S2.off[i2p] + s2l;
             for (int im0 = 0; im0 < SM.nsec; ++im0) {
@@ -581,15 +584,22 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
                       }
                 }
             }
-            row.ne = (int32_t)(pl.we.size() - row.e0);
-            pl.flops_w += 2.0 * row.ne * wpair.da * db;
-            pl.wr.push_back(row);
+            pl.flops_w += 2.0 * (double)(pl.we.size() - row_e0) * wpair.da * db;
+            if (pl.we.size() == row_e0) {
+              // no W12 term reaches this row: a zero-weight read of X[b] writes the zeros
+              QnWEnt e{};
+              pl.we.push_back(e);
+            }
+            QnWEnt& last = pl.we.back();
+            last.zoff = row_off;
+            last.zastride = row_astride;
+            last.end = 1;
           }
     }
-    wpair.nrows = (int32_t)(pl.wr.size() - wpair.row0);
+    wpair.ne = (int32_t)(pl.we.size() - wpair.e0);
     const int pid = (int)pl.wp.size();
     pl.wp.push_back(wpair);
-    for (int64_t p0 = 0; p0 < (int64_t)wpair.da * wpair.db; p0 += 256)
+    for (int64_t p0 = 0; p0 < (int64_t)wpair.da * wpair.db; p0 += QN_WSTAGE_POS)
       pl.wi.push_back(QnWItem{pid, (int32_t)p0});
   }
   for (int c = 0; c < 2; ++c) {
@@ -619,8 +629,8 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
     add(pl.t4[c].size() * sizeof(GTile));
   }
   add(pl.tb.size() * sizeof(QnTBlock));
+  add(pl.tbi.size() * sizeof(int32_t));
   add(pl.wp.size() * sizeof(QnWPair));
-  add(pl.wr.size() * sizeof(QnWRow));
   add(pl.we.size() * sizeof(QnWEnt));
   add(pl.wi.size() * sizeof(QnWItem));
   add(pl.cp.size() * sizeof(QnCopy));
@@ -644,8 +654,8 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
     ITN_HIP(h, put(pl.dt4[c], pl.t4[c]));
   }
   ITN_HIP(h, put(pl.dtb, pl.tb));
+  ITN_HIP(h, put(pl.dtbi, pl.tbi));
   ITN_HIP(h, put(pl.dwp, pl.wp));
-  ITN_HIP(h, put(pl.dwr, pl.wr));
   ITN_HIP(h, put(pl.dwe, pl.we));
   ITN_HIP(h, put(pl.dwi, pl.wi));
   ITN_HIP(h, put(pl.dcp, pl.cp));
@@ -659,7 +669,8 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
     return hipMemset(*p, 0, bytes);  // padding must read as zero (never rewritten)
   };
   ITN_HIP(h, zalloc(&pl.psiT, (size_t)pl.nv * pl.psiT_elems * es));
-  ITN_HIP(h, zalloc(&pl.X, (size_t)pl.nv * pl.X_elems * xs));
+  // + max b-sector width: zero-weight W-stage entries read X[v * X_elems + b]
+  ITN_HIP(h, zalloc(&pl.X, ((size_t)pl.nv * pl.X_elems + (size_t)pl.max_db) * xs));
   ITN_HIP(h, zalloc(&pl.Z, (size_t)pl.nv * pl.Z_elems * es));
   ITN_HIP(h, zalloc(&pl.Lp, (size_t)pl.Lp_elems * es));
   ITN_HIP(h, zalloc(&pl.Rp, (size_t)pl.Rp_elems * es));
@@ -678,8 +689,8 @@ itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int 
   }
   {
     Prof pf(h, "qn_psi_transpose", s);
-    ITN_HIP(h, qn_block_transpose(pl.psi_dt, ptrs, pl.pt, pl.psiT, pl.dtb, (int)pl.tb.size(),
-                                  pl.tb_tiles, pl.out_elems, pl.psiT_elems, pl.nv, s));
+    ITN_HIP(h, qn_block_transpose(pl.psi_dt, ptrs, pl.pt, pl.psiT, pl.dtb, pl.dtbi, pl.tb_tiles,
+                                  pl.out_elems, pl.psiT_elems, pl.nv, s));
   }
   {
     Prof pf(h, "qn_stage1_grouped", s);
@@ -688,8 +699,8 @@ itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int 
   }
   {
     Prof pf(h, "qn_wstage", s);
-    ITN_HIP(h, qn_wstage(pl.xt, pl.X, pl.pt, pl.Z, pl.dwp, pl.dwr, pl.dwe, pl.dwi,
-                         (int64_t)pl.wi.size(), pl.X_elems, pl.Z_elems, pl.nv, s));
+    ITN_HIP(h, qn_wstage(pl.xt, pl.X, pl.pt, pl.Z, pl.dwp, pl.dwe, pl.dwi, (int64_t)pl.wi.size(),
+                         pl.X_elems, pl.Z_elems, pl.nv, s));
   }
   if (!pl.zoff.empty()) {
     Prof pf(h, "qn_zero_blocks", s);
@@ -841,6 +852,9 @@ itn_status itn_plan_query(const itn_plan* pl, itn_plan_info* info) {
   info->n_pairs_stage4 = (int64_t)pl->s4.size();
   info->n_tiles = (int64_t)(pl->t1[pl->cfg1].size() + pl->t4[pl->cfg4].size());
   info->flops = pl->flops_gemm * pl->nv;
+  info->x_elems = pl->X_elems;
+  info->z_elems = pl->Z_elems;
+  info->flops_wstage = pl->flops_w * pl->nv;
   return ITN_OK;
 }
 

@@ -91,8 +91,8 @@ struct QnTBlock {
   int32_t pad;
 };
 hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, void* out,
-                              const QnTBlock* blocks, int nblocks, int64_t ntiles, int64_t in_bs,
-                              int64_t out_bs, int nv, hipStream_t s);
+                              const QnTBlock* blocks, const int32_t* tile_block, int64_t ntiles,
+                              int64_t in_bs, int64_t out_bs, int nv, hipStream_t s);
 // Block copy into a padded layout: item i copies rows [0, rows) x [0, cols)
 // of a row-major block of the caller's L (src = 0) or R (src = 1) at in_off
 // to outL (src = 0) or outR (src = 1) + out_off with row stride ld_out.
@@ -107,27 +107,31 @@ hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
 // Block-sparse W-stage: work item = (pair, first position of 256); positions
 // p = a' * db + b of the pair; rows and entries carry their own offsets and
 // a'-strides.
+// Block-sparse W-stage.  The entries of one (a'-sector, b-sector) pair are
+// stored row after row; the last entry of a row carries the row's Z offset,
+// and rows without W12 terms have one zero-weight entry, so every Z element
+// of the pair is written.
 struct QnWPair {
-  int32_t row0, nrows;  // CSR rows of this pair
+  int32_t e0, ne;       // entries of this pair
   int32_t da, db;       // positions a' < da, b < db
-};
-struct QnWRow {
-  int64_t off;          // Z offset of (a' = 0, b = 0)
-  int64_t astride;
-  int32_t e0, ne;       // entries
 };
 struct QnWEnt {
   int64_t off;          // X offset of (a' = 0, b = 0)
   int64_t astride;
   double coef;
+  int64_t zoff;         // Z offset of (a' = 0, b = 0) of the row (last entry of a row)
+  int64_t zastride;     // 0 on entries that do not end a row
+  int32_t end;          // 1 on the last entry of a row
+  int32_t pad;
 };
+constexpr int QN_WSTAGE_POS = 512;  // positions per item (2 per thread)
 struct QnWItem {
   int32_t pair;
   int32_t p0;  // first position
 };
 hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnWPair* pairs,
-                     const QnWRow* rows, const QnWEnt* ents, const QnWItem* items, int64_t nitems,
-                     int64_t x_bs, int64_t z_bs, int nv, hipStream_t s);
+                     const QnWEnt* ents, const QnWItem* items, int64_t nitems, int64_t x_bs,
+                     int64_t z_bs, int nv, hipStream_t s);
 // Zero the listed output blocks (offsets, sizes) of out + v * bs.
 hipError_t qn_zero_blocks(int dtype, const QnPtrs* ptrs, const int64_t* offs, const int64_t* sizes,
                           int nblocks, int64_t bs, int nv, hipStream_t s);

@@ -20,53 +20,52 @@ hipError_t qn_set_ptrs(QnDevPtrs* dst, QnDevPtrs v, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ transpose
+// One 64 x 64 tile per workgroup; tile -> block from a table built by the
+// planner.  The LDS tile holds FP64 only for FP64 output (bf16 from FP64
+// goes through FP32 either way).
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restrict__ ptrs,
                                                             TO* __restrict__ out,
                                                             const QnTBlock* __restrict__ blocks,
-                                                            int nblocks, int64_t in_bs,
-                                                            int64_t out_bs) {
-  __shared__ double tile[64][65];
-  // locate the block owning this tile (blocks sorted by tile0)
+                                                            const int32_t* __restrict__ tile_block,
+                                                            int64_t in_bs, int64_t out_bs) {
+  using TS = typename std::conditional<sizeof(TO) == 8, double, float>::type;
+  __shared__ TS tile[64][65];
   const int t = blockIdx.x;
-  int lo = 0, hi = nblocks - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (blocks[mid].tile0 <= t) lo = mid;
-    else hi = mid - 1;
-  }
-  const QnTBlock bk = blocks[lo];
+  const QnTBlock bk = blocks[tile_block[t]];
   const int local = t - bk.tile0;
   const int64_t r0 = (int64_t)(local / bk.tiles_c) * 64, c0 = (int64_t)(local % bk.tiles_c) * 64;
   const int64_t v = blockIdx.y;
   const TI* ip = static_cast<const TI*>(ptrs->psi) + bk.in_off + v * in_bs;
   TO* op = out + bk.out_off + v * out_bs;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
   for (int i = ty; i < 64; i += 4) {
     const int64_t r = r0 + i, c = c0 + tx;
-    if (r < bk.rows && c < bk.cols) tile[i][tx] = (double)ip[r * bk.cols + c];
+    if (r < bk.rows && c < bk.cols) tile[i][tx] = (TS)ip[r * bk.cols + c];
   }
   __syncthreads();
+#pragma unroll 4
   for (int i = ty; i < 64; i += 4) {
     const int64_t c = c0 + i, r = r0 + tx;
-    if (r < bk.rows && c < bk.cols) op[c * bk.ld_out + r] = qconv<TO>(tile[tx][i]);
+    if (r < bk.rows && c < bk.cols) op[c * bk.ld_out + r] = qconv<TO>((double)tile[tx][i]);
   }
 }
 
 template <typename TI, typename TO>
-static hipError_t qn_transpose_t(const QnPtrs* ptrs, void* out, const QnTBlock* blocks, int nblocks,
-                                 int64_t ntiles, int64_t in_bs, int64_t out_bs, int nv,
-                                 hipStream_t s) {
+static hipError_t qn_transpose_t(const QnPtrs* ptrs, void* out, const QnTBlock* blocks,
+                                 const int32_t* tile_block, int64_t ntiles, int64_t in_bs,
+                                 int64_t out_bs, int nv, hipStream_t s) {
   if (ntiles == 0 || nv == 0) return hipSuccess;
   hipLaunchKernelGGL((qn_transpose_kernel<TI, TO>), dim3((unsigned)ntiles, (unsigned)nv), dim3(256),
-                     0, s, ptrs, static_cast<TO*>(out), blocks, nblocks, in_bs, out_bs);
+                     0, s, ptrs, static_cast<TO*>(out), blocks, tile_block, in_bs, out_bs);
   return hipGetLastError();
 }
 
 hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, void* out,
-                              const QnTBlock* blocks, int nblocks, int64_t ntiles, int64_t in_bs,
-                              int64_t out_bs, int nv, hipStream_t s) {
-#define ITN_QT(TI, TO) return qn_transpose_t<TI, TO>(ptrs, out, blocks, nblocks, ntiles, in_bs, out_bs, nv, s)
+                              const QnTBlock* blocks, const int32_t* tile_block, int64_t ntiles,
+                              int64_t in_bs, int64_t out_bs, int nv, hipStream_t s) {
+#define ITN_QT(TI, TO) return qn_transpose_t<TI, TO>(ptrs, out, blocks, tile_block, ntiles, in_bs, out_bs, nv, s)
   if (in_dtype == D_F64) {
     if (out_dtype == D_F64) ITN_QT(double, double);
     if (out_dtype == D_F32) ITN_QT(double, float);
@@ -81,48 +80,79 @@ hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, v
 }
 
 // -------------------------------------------------------------- W-stage
+// One workgroup per item of QN_WSTAGE_POS positions (a', b) of a pair, two
+// per thread; the pair's entries are taken four at a time, so every thread
+// has eight independent X loads in flight before it accumulates.
 template <typename TX, typename TZ>
 __global__ __launch_bounds__(256) void qn_wstage_kernel(const TX* __restrict__ X, TZ* __restrict__ Z,
                                                          const QnWPair* __restrict__ pairs,
-                                                         const QnWRow* __restrict__ rows,
                                                          const QnWEnt* __restrict__ ents,
                                                          const QnWItem* __restrict__ items,
                                                          int64_t x_bs, int64_t z_bs) {
   using A = typename std::conditional<sizeof(TX) == 8, double, float>::type;
+  constexpr int NP = QN_WSTAGE_POS / 256;
+  constexpr int NE = 4;
   const QnWItem it = items[blockIdx.x];
   const QnWPair pr = pairs[it.pair];
-  const int64_t p = (int64_t)it.p0 + threadIdx.x;
-  if (p >= (int64_t)pr.da * pr.db) return;
-  const int64_t a = p / pr.db, b = p % pr.db;
+  const int npos = pr.da * pr.db;
+  int64_t a[NP], b[NP];
+  bool ok[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int p = it.p0 + k * 256 + (int)threadIdx.x;
+    ok[k] = p < npos;
+    const int pp = ok[k] ? p : 0;  // position (0, 0) exists in every pair
+    a[k] = pp / pr.db;
+    b[k] = pp - a[k] * pr.db;
+  }
   const int64_t v = blockIdx.y;
-  const TX* xp = X + v * x_bs + b;
-  TZ* zp = Z + v * z_bs + b;
-  for (int r = pr.row0; r < pr.row0 + pr.nrows; ++r) {
-    const QnWRow row = rows[r];
-    A z = 0;
-    for (int e = row.e0; e < row.e0 + row.ne; ++e) {
-      const QnWEnt en = ents[e];
-      z += (A)en.coef * (A)xp[en.off + a * en.astride];
+  const TX* xv = X + v * x_bs;
+  TZ* zv = Z + v * z_bs;
+  const QnWEnt* en = ents + pr.e0;
+  const int ne = pr.ne;
+  A z[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) z[k] = 0;
+  for (int e0 = 0; e0 < ne; e0 += NE) {
+    QnWEnt ec[NE];
+    A x[NE][NP];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) ec[j] = en[e0 + j < ne ? e0 + j : ne - 1];
+#pragma unroll
+    for (int j = 0; j < NE; ++j)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) x[j][k] = (A)xv[ec[j].off + a[k] * ec[j].astride + b[k]];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      if (e0 + j >= ne) break;
+      if (ec[j].coef != 0.0)  // zero-weight entries of rows without W12 terms add nothing
+#pragma unroll
+        for (int k = 0; k < NP; ++k) z[k] += (A)ec[j].coef * x[j][k];
+      if (ec[j].end) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          if (ok[k]) zv[ec[j].zoff + a[k] * ec[j].zastride + b[k]] = qconv<TZ>((double)z[k]);
+          z[k] = 0;
+        }
+      }
     }
-    zp[row.off + a * row.astride] = qconv<TZ>((double)z);
   }
 }
 
 template <typename TX, typename TZ>
-static hipError_t qn_wstage_t(const void* X, void* Z, const QnWPair* pairs, const QnWRow* rows,
-                              const QnWEnt* ents, const QnWItem* items, int64_t nitems, int64_t x_bs,
-                              int64_t z_bs, int nv, hipStream_t s) {
+static hipError_t qn_wstage_t(const void* X, void* Z, const QnWPair* pairs, const QnWEnt* ents,
+                              const QnWItem* items, int64_t nitems, int64_t x_bs, int64_t z_bs, int nv,
+                              hipStream_t s) {
   if (nitems == 0 || nv == 0) return hipSuccess;
   hipLaunchKernelGGL((qn_wstage_kernel<TX, TZ>), dim3((unsigned)nitems, (unsigned)nv), dim3(256), 0,
-                     s, static_cast<const TX*>(X), static_cast<TZ*>(Z), pairs, rows, ents, items,
-                     x_bs, z_bs);
+                     s, static_cast<const TX*>(X), static_cast<TZ*>(Z), pairs, ents, items, x_bs, z_bs);
   return hipGetLastError();
 }
 
 hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnWPair* pairs,
-                     const QnWRow* rows, const QnWEnt* ents, const QnWItem* items, int64_t nitems,
-                     int64_t x_bs, int64_t z_bs, int nv, hipStream_t s) {
-#define ITN_QW(TX, TZ) return qn_wstage_t<TX, TZ>(X, Z, pairs, rows, ents, items, nitems, x_bs, z_bs, nv, s)
+                     const QnWEnt* ents, const QnWItem* items, int64_t nitems, int64_t x_bs,
+                     int64_t z_bs, int nv, hipStream_t s) {
+#define ITN_QW(TX, TZ) return qn_wstage_t<TX, TZ>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, s)
   if (x_dtype == D_F64 && z_dtype == D_F64) ITN_QW(double, double);
   if (x_dtype == D_F32 && z_dtype == D_F32) ITN_QW(float, float);
   if (x_dtype == D_F32 && z_dtype == D_BF16) ITN_QW(float, bf16_t);
@@ -131,6 +161,8 @@ hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnW
 }
 
 // ------------------------------------------------------------ block copy
+// Rows of an item (at most 32) are spread over the four waves, columns over
+// the lanes; narrow blocks use a flat index instead.
 template <typename T>
 __global__ __launch_bounds__(256) void qn_copy_kernel(const QnPtrs* __restrict__ ptrs,
                                                        T* __restrict__ outL, T* __restrict__ outR,
@@ -138,12 +170,21 @@ __global__ __launch_bounds__(256) void qn_copy_kernel(const QnPtrs* __restrict__
   const QnCopy it = items[blockIdx.x];
   const T* src = static_cast<const T*>(it.src ? ptrs->R : ptrs->L) + it.in_off;
   T* dst = (it.src ? outR : outL) + it.out_off;
-  // an item holds at most 32 rows: 32-bit index arithmetic
-  const int n = it.rows * it.cols;
-  const unsigned cols = (unsigned)it.cols;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const unsigned r = (unsigned)e / cols, c = (unsigned)e - r * cols;
-    dst[(int64_t)r * it.ld_out + c] = src[e];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (it.cols >= 48) {
+    for (int r = wave; r < it.rows; r += 4) {
+      const T* sr = src + (int64_t)r * it.cols;
+      T* dr = dst + (int64_t)r * it.ld_out;
+#pragma unroll 4
+      for (int c = lane; c < it.cols; c += 64) dr[c] = sr[c];
+    }
+  } else {
+    const int n = it.rows * it.cols;
+    const unsigned cols = (unsigned)it.cols;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      const unsigned r = (unsigned)e / cols, c = (unsigned)e - r * cols;
+      dst[(int64_t)r * it.ld_out + c] = src[e];
+    }
   }
 }
 hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
