@@ -242,14 +242,15 @@ def time_qn(h, torch, np, inp, which, prec, nv, steps, warmup):
 
 
 # ---------------------------------------------------------------- DMRG leg
-def dmrg_leg(h, np, inp, prec, sweeps, N=100):
+def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False):
     """Spin-1 Heisenberg chain (d=3, w=5), random product start, the given
-    (maxdim, cutoff) schedule; per-sweep time, energy, matvecs."""
+    (maxdim, cutoff) schedule; per-sweep time, energy, matvecs (and, with
+    timing, the per-phase split, which adds stream waits)."""
     mpo = h.mpo(inp.heisenberg_mpo(N, 2))
     mps = h.mps(inp.random_product_state(N, 3, inp.rng_for(2, 64)))
     t0 = time.perf_counter()
     recs = h.dmrg_sweep(mps, mpo, sweeps, prec=prec, eig_tol=1e-9, krylovdim=8, maxiter=60,
-                        refine=True, allow_unconverged=True)
+                        refine=True, allow_unconverged=True, timing=timing)
     return {"total_seconds": time.perf_counter() - t0, "sweeps": recs}
 
 
@@ -389,8 +390,13 @@ def main():
                     reached = t if reached is None else reached
             dm[prec]["seconds_to_dE_1e-8"] = reached
             dm[prec]["rel_err_vs_f64_run"] = abs(ss[-1]["energy"] - e64) / abs(e64)
+        # time split of the last sweep, from a separate run with phase timers
+        log("[bench] DMRG bf16 time split (phase-timed run)")
+        sp = dmrg_leg(h, np, inp, "bf16", sched, timing=True)["sweeps"][-1]
+        split = {k: sp[k] for k in ("seconds", "t_matvec", "t_solver", "t_split", "t_env", "matvecs",
+                                    "max_bond")}
         line["dmrg"] = {"model": "spin-1 Heisenberg chain, N=100, d=3, w=5",
-                        "schedule": sched, **dm}
+                        "schedule": sched, **dm, "bf16_last_sweep_split": split}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(L64.cpu().numpy(), W1, W2, R64.cpu().numpy(),

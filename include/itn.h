@@ -264,6 +264,8 @@ typedef struct {
   itn_prec prec;          /* matvec precision of the Davidson expansion        */
   int32_t refine;         /* 1: finish every local solve with FP64 matvecs     */
   double energy_tol;      /* stop early when |dE| < energy_tol*|E| (0: never)  */
+  int32_t timing;         /* 1: synchronise at phase boundaries and report the
+                             per-phase times below (adds host waits)           */
 } itn_sweep_params;
 
 /* Per-sweep results, arrays of nsweeps entries owned by the caller (any may
@@ -276,6 +278,13 @@ typedef struct {
   double* seconds;      /* wall time of the sweep                              */
   int64_t* matvecs;     /* H_eff applications in the sweep (all precisions)    */
   double* residual;     /* largest final FP64 residual norm of a local solve   */
+  /* Per-phase seconds of the sweep, filled when params->timing is 1 (any may
+   * be NULL): H_eff applications; the rest of the local eigensolves (basis
+   * BLAS-1, projected problem, restarts); bond splits; environment updates. */
+  double* t_matvec;
+  double* t_solver;
+  double* t_split;
+  double* t_env;
 } itn_sweep_result;
 
 /* Run the schedule: per sweep, left->right over bonds (0,1)..(N-2,N-1) then

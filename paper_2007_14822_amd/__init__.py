@@ -233,18 +233,25 @@ class Handle:
         return out
 
     def dmrg_sweep(self, mps, mpo, sweeps, prec="f64", mindim=1, krylovdim=8, maxiter=100,
-                   eig_tol=1e-10, refine=True, energy_tol=0.0, allow_unconverged=False):
-        """Run a schedule [(maxdim, cutoff), ...]; returns per-sweep records."""
+                   eig_tol=1e-10, refine=True, energy_tol=0.0, allow_unconverged=False,
+                   timing=False):
+        """Run a schedule [(maxdim, cutoff), ...]; returns per-sweep records
+        (with per-phase seconds t_matvec/t_solver/t_split/t_env if timing)."""
         ns = len(sweeps)
         md = (C.c_int32 * max(1, ns))(*[int(m) for m, _ in sweeps])
         co = (C.c_double * max(1, ns))(*[float(c) for _, c in sweeps])
         prm = L.itn_sweep_params(ns, md, co, int(mindim), int(krylovdim), int(maxiter),
-                                 float(eig_tol), PREC[prec], 1 if refine else 0, float(energy_tol))
-        arrs = {k: (t * max(1, ns))() for k, t in (("energy", C.c_double), ("max_trunc", C.c_double),
-                                                   ("max_bond", C.c_int32), ("seconds", C.c_double),
-                                                   ("matvecs", C.c_int64), ("residual", C.c_double))}
-        res = L.itn_sweep_result(0, arrs["energy"], arrs["max_trunc"], arrs["max_bond"],
-                                 arrs["seconds"], arrs["matvecs"], arrs["residual"])
+                                 float(eig_tol), PREC[prec], 1 if refine else 0, float(energy_tol),
+                                 1 if timing else 0)
+        fields = [("energy", C.c_double), ("max_trunc", C.c_double), ("max_bond", C.c_int32),
+                  ("seconds", C.c_double), ("matvecs", C.c_int64), ("residual", C.c_double)]
+        if timing:
+            fields += [(k, C.c_double) for k in ("t_matvec", "t_solver", "t_split", "t_env")]
+        arrs = {k: (t * max(1, ns))() for k, t in fields}
+        res = L.itn_sweep_result(0, *[arrs[k] for k, _ in fields[:6]])
+        if timing:
+            res.t_matvec, res.t_solver, res.t_split, res.t_env = (arrs[k] for k in
+                                                                   ("t_matvec", "t_solver", "t_split", "t_env"))
         st = self.lib.itn_dmrg_sweep(self.h, mps.ptr, mpo.ptr, C.byref(prm), C.byref(res))
         if not (allow_unconverged and st == 9):
             self._check(st)

@@ -43,14 +43,17 @@ class itn_sweep_params(C.Structure):
     _fields_ = [("nsweeps", C.c_int32), ("maxdim", C.POINTER(C.c_int32)),
                 ("cutoff", C.POINTER(C.c_double)), ("mindim", C.c_int32),
                 ("krylovdim", C.c_int32), ("maxiter", C.c_int32), ("eig_tol", C.c_double),
-                ("prec", C.c_int), ("refine", C.c_int32), ("energy_tol", C.c_double)]
+                ("prec", C.c_int), ("refine", C.c_int32), ("energy_tol", C.c_double),
+                ("timing", C.c_int32)]
 
 
 class itn_sweep_result(C.Structure):
     _fields_ = [("sweeps_done", C.c_int32), ("energy", C.POINTER(C.c_double)),
                 ("max_trunc", C.POINTER(C.c_double)), ("max_bond", C.POINTER(C.c_int32)),
                 ("seconds", C.POINTER(C.c_double)), ("matvecs", C.POINTER(C.c_int64)),
-                ("residual", C.POINTER(C.c_double))]
+                ("residual", C.POINTER(C.c_double)), ("t_matvec", C.POINTER(C.c_double)),
+                ("t_solver", C.POINTER(C.c_double)), ("t_split", C.POINTER(C.c_double)),
+                ("t_env", C.POINTER(C.c_double))]
 
 
 P = C.c_void_p

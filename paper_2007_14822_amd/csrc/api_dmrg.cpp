@@ -181,10 +181,33 @@ struct Ctx {
   int64_t matvecs = 0;
   double max_resid = 0.0;
   bool unconverged = false;
+  // per-phase seconds of the current sweep (params->timing only)
+  double t_mv = 0.0, t_solve = 0.0, t_split = 0.0, t_env = 0.0;
+};
+
+// Adds the wall time of a scope to *acc when timing is on; the stream is
+// drained at both ends so that the time belongs to the phase.
+struct PhaseTimer {
+  Ctx& c;
+  double* acc;
+  std::chrono::steady_clock::time_point t0;
+  PhaseTimer(Ctx& ctx, double* a) : c(ctx), acc(a) {
+    if (c.p->timing) {
+      (void)hipStreamSynchronize(c.s);
+      t0 = std::chrono::steady_clock::now();
+    }
+  }
+  ~PhaseTimer() {
+    if (c.p->timing) {
+      (void)hipStreamSynchronize(c.s);
+      *acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+  }
 };
 
 // y = H_eff x at precision `prec` (FP64 vectors), through the public entry point.
 itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl, int64_t cr) {
+  PhaseTimer pt(c, &c.t_mv);
   const int w = c.mpo->w, d = c.mpo->d;
   const int64_t dl[3] = {cl, w, cl}, dr[3] = {cr, w, cr}, dw[4] = {w, w, d, d};
   const int64_t dp[4] = {cl, d, d, cr};
@@ -211,11 +234,17 @@ itn_status dots(Ctx& c, const double* V, int64_t n, int k, const double* w, doub
 }
 
 // Lowest eigenpair of H_eff at bond i by Davidson (identity preconditioner,
-// full re-orthogonalisation, restart from the Ritz vector), FP64 vectors.
-// psi (in/out, length n) is the start vector and the result.
-// *converged is false only when maxiter matvecs ended above the tolerance; a
-// residual already inside the Krylov space (no new direction) is at the
-// arithmetic's noise floor and counts as converged.
+// full re-orthogonalisation, thick restart), FP64 vectors.  psi (in/out,
+// length n) is the start vector and the result.  *converged is false only
+// when maxiter matvecs ended above the tolerance; a residual already inside
+// the Krylov space (no new direction) is at the arithmetic's noise floor and
+// counts as converged.
+//
+// Host round trips per expansion step: three.  (1) the new column V^T A v_k
+// of the projected matrix; (2) V^T r and r.r in one reduction, the residual
+// being formed in the next basis slot; (3) the same pair after the first
+// Gram-Schmidt pass, from which the norm after the second pass follows as
+// |r'|^2 - |c2|^2 (V orthonormal).
 itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* psi, int64_t n,
                     int64_t cl, int64_t cr, double* energy, double* resid, bool* converged) {
   const int kmax = std::max(4, std::min(c.p->krylovdim, 32));
@@ -224,7 +253,7 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
   ITN_TRY(c.m->AV.ensure(c.h, (size_t)(kmax + KEEP) * n * 8));
   double* V = c.m->V.d();
   double* AV = c.m->AV.d();
-  std::vector<double> Hk((size_t)kmax * kmax, 0.0), tmp(kmax + 1);
+  std::vector<double> Hk((size_t)kmax * kmax, 0.0), tmp(kmax + 2);
   double nrm2;
   ITN_TRY(dots(c, psi, n, 1, psi, &nrm2));
   if (!(nrm2 > 0)) return fail(c.h, ITN_E_ARG, "zero start vector at bond %d", i);
@@ -234,9 +263,9 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
   int k = 1;
   double theta = 0.0, rn = 0.0;
   bool conv = false;
-  std::vector<double> w, Y;
+  std::vector<double> w, Y, y;
   for (int it = 0;; ++it) {
-    // new column k-1 of the projected matrix
+    // (1) new column k-1 of the projected matrix
     ITN_TRY(dots(c, V, n, k, AV + (size_t)(k - 1) * n, tmp.data()));
     for (int a = 0; a < k; ++a) {
       Hk[a * kmax + (k - 1)] = tmp[a];
@@ -247,25 +276,8 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
       for (int b = 0; b < k; ++b) Hs[a * k + b] = 0.5 * (Hk[a * kmax + b] + Hk[b * kmax + a]);
     jacobi_eigh(k, Hs, w, Y);
     theta = w[0];
-    std::vector<double> y(k);
+    y.assign(k, 0.0);
     for (int a = 0; a < k; ++a) y[a] = Y[a * k + 0];
-    // x = V y (slot kmax), r = AV y - theta x (into psi as scratch)
-    double* x = V + (size_t)kmax * n;
-    double* ax = AV + (size_t)kmax * n;
-    ITN_HIP(c.h, lincomb(V, n, k, y.data(), 0.0, x, n, c.s));
-    ITN_HIP(c.h, lincomb(AV, n, k, y.data(), 0.0, ax, n, c.s));
-    double cf[2] = {1.0, -theta};
-    // psi <- ax - theta x   (lincomb over the two contiguous slots)
-    ITN_HIP(c.h, lincomb(x, n, 1, &cf[1], 0.0, psi, n, c.s));
-    ITN_HIP(c.h, lincomb(ax, n, 1, &cf[0], 1.0, psi, n, c.s));
-    double r2;
-    ITN_TRY(dots(c, psi, n, 1, psi, &r2));
-    rn = std::sqrt(std::max(r2, 0.0));
-    if (rn <= tol * std::max(1.0, std::fabs(theta))) {
-      conv = true;
-      break;
-    }
-    if (it + 1 >= maxiter) break;
     if (k == kmax) {  // thick restart from the lowest KEEP Ritz vectors
       const int keep = std::min(KEEP, k - 1);
       for (int j = 0; j < keep; ++j) {
@@ -281,25 +293,45 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
       std::fill(Hk.begin(), Hk.end(), 0.0);
       for (int j = 0; j < keep; ++j) Hk[j * kmax + j] = w[j];
       k = keep;
+      y.assign(k, 0.0);
+      y[0] = 1.0;
     }
-    // t = r orthogonalised twice against V, normalised
-    for (int rep = 0; rep < 2; ++rep) {
-      ITN_TRY(dots(c, V, n, k, psi, tmp.data()));
-      for (int a = 0; a < k; ++a) tmp[a] = -tmp[a];
-      ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, psi, n, c.s));
+    // r = AV y - theta V y, in slot k (the next basis vector if r is kept)
+    double* r = V + (size_t)k * n;
+    std::vector<double> ny(k);
+    for (int a = 0; a < k; ++a) ny[a] = -theta * y[a];
+    ITN_HIP(c.h, lincomb(AV, n, k, y.data(), 0.0, r, n, c.s));
+    ITN_HIP(c.h, lincomb(V, n, k, ny.data(), 1.0, r, n, c.s));
+    // (2) V^T r and r.r
+    ITN_TRY(dots(c, V, n, k + 1, r, tmp.data()));
+    const double r2 = tmp[k];
+    rn = std::sqrt(std::max(r2, 0.0));
+    if (rn <= tol * std::max(1.0, std::fabs(theta))) {
+      conv = true;
+      break;
     }
-    double t2;
-    ITN_TRY(dots(c, psi, n, 1, psi, &t2));
+    if (it + 1 >= maxiter) break;
+    // Gram-Schmidt, two passes
+    for (int a = 0; a < k; ++a) tmp[a] = -tmp[a];
+    ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, r, n, c.s));
+    ITN_TRY(dots(c, V, n, k + 1, r, tmp.data()));  // (3)
+    double c2 = 0.0;
+    for (int a = 0; a < k; ++a) {
+      c2 += tmp[a] * tmp[a];
+      tmp[a] = -tmp[a];
+    }
+    const double t2 = tmp[k] - c2;
     if (!(t2 > 1e-28 * std::max(1.0, r2))) {  // no new direction
       conv = true;
       break;
     }
-    ITN_HIP(c.h, hipMemcpyAsync(V + (size_t)k * n, psi, n * 8, hipMemcpyDeviceToDevice, c.s));
-    ITN_HIP(c.h, scale(V + (size_t)k * n, 1.0 / std::sqrt(t2), n, c.s));
-    ITN_TRY(heff(c, i, prec, V + (size_t)k * n, AV + (size_t)k * n, cl, cr));
+    ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, r, n, c.s));
+    ITN_HIP(c.h, scale(r, 1.0 / std::sqrt(t2), n, c.s));
+    ITN_TRY(heff(c, i, prec, r, AV + (size_t)k * n, cl, cr));
     ++k;
   }
-  ITN_HIP(c.h, hipMemcpyAsync(psi, V + (size_t)kmax * n, n * 8, hipMemcpyDeviceToDevice, c.s));
+  // the Ritz vector of the last projected problem
+  ITN_HIP(c.h, lincomb(V, n, k, y.data(), 0.0, psi, n, c.s));
   *energy = theta;
   *resid = rn;
   *converged = conv;
@@ -471,19 +503,26 @@ itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, do
   const int maxiter = c.p->maxiter > 0 ? c.p->maxiter : 100;
   double e = 0.0, r = 0.0;
   bool conv = true;
-  if (prec == ITN_P_F64) {
-    ITN_TRY(davidson(c, i, ITN_P_F64, tol, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
-  } else {
-    // low-precision phase to its own noise floor, then FP64 refinement
-    const double tol_lo = std::max(tol, prec == ITN_P_BF16 ? 2e-2 : 2e-5);
-    ITN_TRY(davidson(c, i, prec, tol_lo, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
-    if (c.p->refine)
+  {
+    PhaseTimer pt(c, &c.t_solve);
+    if (prec == ITN_P_F64) {
       ITN_TRY(davidson(c, i, ITN_P_F64, tol, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
+    } else {
+      // low-precision phase to its own noise floor, then FP64 refinement
+      const double tol_lo = std::max(tol, prec == ITN_P_BF16 ? 2e-2 : 2e-5);
+      ITN_TRY(davidson(c, i, prec, tol_lo, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
+      if (c.p->refine)
+        ITN_TRY(davidson(c, i, ITN_P_F64, tol, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
+    }
   }
   c.max_resid = std::max(c.max_resid, r);
   if (!conv && (prec == ITN_P_F64 || c.p->refine)) c.unconverged = true;
   *energy = e;
-  ITN_TRY(split(c, i, to_right, cl, cr, maxdim, cutoff, trunc));
+  {
+    PhaseTimer pt(c, &c.t_split);
+    ITN_TRY(split(c, i, to_right, cl, cr, maxdim, cutoff, trunc));
+  }
+  PhaseTimer pt(c, &c.t_env);
   if (to_right) ITN_TRY(env_step(c, i, true));
   else ITN_TRY(env_step(c, i + 1, false));
   return ITN_OK;
@@ -598,6 +637,7 @@ itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
     auto t0 = std::chrono::steady_clock::now();
     c.matvecs = 0;
     c.max_resid = 0.0;
+    c.t_mv = c.t_solve = c.t_split = c.t_env = 0.0;
     double E = 0.0, maxtr = 0.0, tr = 0.0;
     for (int i = 0; i <= N - 2; ++i) {
       ITN_TRY(bond_step(c, i, true, p->maxdim[sw], p->cutoff[sw], &E, &tr));
@@ -616,6 +656,12 @@ itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
       if (res->seconds) res->seconds[sw] = secs;
       if (res->matvecs) res->matvecs[sw] = c.matvecs;
       if (res->residual) res->residual[sw] = c.max_resid;
+      if (p->timing) {
+        if (res->t_matvec) res->t_matvec[sw] = c.t_mv;
+        if (res->t_solver) res->t_solver[sw] = c.t_solve - c.t_mv;
+        if (res->t_split) res->t_split[sw] = c.t_split;
+        if (res->t_env) res->t_env[sw] = c.t_env;
+      }
       res->sweeps_done = sw + 1;
     }
     if (sw > 0 && p->energy_tol > 0 && std::fabs(E - prevE) < p->energy_tol * std::fabs(E)) break;

@@ -99,3 +99,20 @@ def test_mismatched_mpo_rejected(h):
     with pytest.raises(itn.ItnError) as e:
         h.dmrg_sweep(mps, mpo, [(8, 0.0)])
     assert e.value.name == "ITN_E_SHAPE"
+
+
+def test_sweep_phase_timing(h):
+    """With timing on, the per-phase seconds are filled, non-negative and
+    within the sweep's wall time; the energy is unaffected."""
+    N = 10
+    As0 = inp.random_product_state(N, 2, inp.rng_for(0, 32))
+    kw = dict(eig_tol=1e-12, krylovdim=12, maxiter=400)
+    recs_t, _ = run(h, inp.heisenberg_mpo(N), As0, [(32, 1e-14)] * 2, timing=True, **kw)
+    recs, _ = run(h, inp.heisenberg_mpo(N), As0, [(32, 1e-14)] * 2, **kw)
+    for r in recs_t:
+        parts = [r[k] for k in ("t_matvec", "t_solver", "t_split", "t_env")]
+        assert all(x >= 0.0 for x in parts)
+        assert r["t_matvec"] > 0.0 and r["t_split"] > 0.0
+        assert sum(parts) <= r["seconds"] * 1.01 + 1e-3
+    assert "t_matvec" not in recs[0]
+    assert abs(recs_t[-1]["energy"] - recs[-1]["energy"]) <= 1e-12 * abs(recs[-1]["energy"])
