@@ -216,7 +216,12 @@ itn_status itn_qn_allowed_blocks(itn_handle* h, const itn_tensor* t, int64_t* nb
  * the plan was built from (checked by signature: ITN_E_SHAPE otherwise);
  * data pointers may change between calls.  psi/out hold nv vectors at stride
  * out_elems.  The first call on a stream captures the launches into a
- * hipGraph that later calls replay. */
+ * hipGraph that later calls replay.
+ * The first apply also picks, per grouped stage, the fastest launch mode by
+ * timing them on the real operands (0: 64x64 tiles; 1: 128x128; 2, 3: block
+ * products with both extents >= 192 on 256-row direct-to-LDS tiles, the rest
+ * on 64 / 128).  The choice is cached per operand structure (in the file
+ * ITN_AUTOTUNE_CACHE if set); ITN_QN_TILE_MODE="m1,m4" fixes it instead. */
 itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* plan, const itn_tensor* L,
                              const itn_tensor* R, const itn_tensor* psi, itn_tensor* out,
                              void* hip_stream);

@@ -18,6 +18,7 @@
 //            the output tile (no atomics: run-to-run deterministic).
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -221,7 +222,17 @@ struct itn_plan {
   std::vector<int64_t> out_off;
   std::vector<GProb> p1, p4;
   std::vector<GSeg> s1, s4;
-  std::vector<GTile> t1[2], t4[2];
+  // Tile lists of a grouped stage.  all[c]: every problem with the
+  // register-staged tile c (0: 64x64, 1: 128x128); big: the problems large
+  // enough for the direct-to-LDS 8-wave tile; rest[c]: the others with tile c.
+  // Launch modes: 0, 1 = all[mode]; 2, 3 = big then rest[mode - 2].
+  struct Tiles {
+    std::vector<GTile> all[2], big, rest[2];
+    GTile *d_all[2] = {nullptr, nullptr}, *d_big = nullptr, *d_rest[2] = {nullptr, nullptr};
+    size_t count(int mode) const {
+      return mode < 2 ? all[mode].size() : big.size() + rest[mode - 2].size();
+    }
+  } tl1, tl4;
   std::vector<QnTBlock> tb;
   std::vector<int32_t> tbi;  // block of every transpose tile
   int64_t tb_tiles = 0;
@@ -240,7 +251,6 @@ struct itn_plan {
   QnDevPtrs* dptrs = nullptr;
   GProb *dp1 = nullptr, *dp4 = nullptr;
   GSeg *ds1 = nullptr, *ds4 = nullptr;
-  GTile *dt1[2] = {nullptr, nullptr}, *dt4[2] = {nullptr, nullptr};
   QnTBlock* dtb = nullptr;
   int32_t* dtbi = nullptr;
   QnWPair* dwp = nullptr;
@@ -254,6 +264,7 @@ struct itn_plan {
   void* Z = nullptr;
   void* Lp = nullptr;  // padded copies of the used L / R blocks
   void* Rp = nullptr;
+  void* zero = nullptr;  // zero page for K tails of direct-to-LDS tiles
   int cfg1 = 0, cfg4 = 0;
   bool tuned = false;
   hipStream_t cap = nullptr;
@@ -265,7 +276,7 @@ struct itn_plan {
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);
       if (cap) (void)hipStreamDestroy(cap);
-      for (void* p : {(void*)dtab, psiT, X, Z, Lp, Rp})
+      for (void* p : {(void*)dtab, psiT, X, Z, Lp, Rp, zero})
         if (p) (void)hipFree(p);
     }
   }
@@ -293,18 +304,21 @@ void add_copy(std::vector<QnCopy>& v, int64_t in_off, int64_t out_off, int rows,
   }
 }
 
-// Tile lists for tile size `bt` (square), largest K-work first.
-std::vector<GTile> make_tiles(const std::vector<GProb>& probs, const std::vector<GSeg>& segs, int bt) {
+// Tile list (bm x bn tiles) over the problems `use` selects, largest K-work
+// first.
+std::vector<GTile> make_tiles(const std::vector<GProb>& probs, const std::vector<GSeg>& segs, int bm,
+                              int bn, const std::vector<char>& use) {
   struct W {
     GTile t;
     int64_t work;
   };
   std::vector<W> v;
   for (size_t p = 0; p < probs.size(); ++p) {
+    if (!use[p]) continue;
     const GProb& pr = probs[p];
     int64_t k = 0;
     for (int s = 0; s < pr.nseg; ++s) k += segs[pr.seg0 + s].K;
-    const int tm = (pr.M + bt - 1) / bt, tn = (pr.N + bt - 1) / bt;
+    const int tm = (pr.M + bm - 1) / bm, tn = (pr.N + bn - 1) / bn;
     for (int i = 0; i < tm; ++i)
       for (int j = 0; j < tn; ++j) v.push_back({GTile{(int32_t)p, i, j, 0}, k});
   }
@@ -313,6 +327,32 @@ std::vector<GTile> make_tiles(const std::vector<GProb>& probs, const std::vector
   out.reserve(v.size());
   for (auto& x : v) out.push_back(x.t);
   return out;
+}
+
+// Problems that go to the direct-to-LDS tile: both extents at least 3/4 of
+// a 256 tile, and every segment 16-byte aligned (true of the padded plan
+// layouts; checked anyway).
+template <typename TL>
+void build_tiles(TL& tl, const std::vector<GProb>& probs, const std::vector<GSeg>& segs, int prec,
+                 int dtype) {
+  const int e16 = 16 / dtype_size(dtype);
+  std::vector<char> all(probs.size(), 1), big(probs.size(), 0), rest(probs.size(), 1);
+  for (size_t p = 0; p < probs.size(); ++p) {
+    const GProb& pr = probs[p];
+    bool ok = pr.M >= 192 && pr.N >= 192;
+    for (int s = 0; ok && s < pr.nseg; ++s) {
+      const GSeg& g = segs[pr.seg0 + s];
+      ok = g.a_off % e16 == 0 && g.b_off % e16 == 0 && g.lda % e16 == 0 && g.ldb % e16 == 0;
+    }
+    big[p] = ok;
+    rest[p] = !ok;
+  }
+  for (int c = 0; c < 2; ++c) {
+    const int t = grouped_tile_rows(c);
+    tl.all[c] = make_tiles(probs, segs, t, t, all);
+    tl.rest[c] = make_tiles(probs, segs, t, t, rest);
+  }
+  tl.big = make_tiles(probs, segs, grouped_tile_rows(2), grouped_tile_cols(prec, 2), big);
 }
 
 itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t,
@@ -602,10 +642,8 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     for (int64_t p0 = 0; p0 < (int64_t)wpair.da * wpair.db; p0 += QN_WSTAGE_POS)
       pl.wi.push_back(QnWItem{pid, (int32_t)p0});
   }
-  for (int c = 0; c < 2; ++c) {
-    pl.t1[c] = make_tiles(pl.p1, pl.s1, grouped_tile_rows(c));
-    pl.t4[c] = make_tiles(pl.p4, pl.s4, grouped_tile_rows(c));
-  }
+  build_tiles(pl.tl1, pl.p1, pl.s1, pl.prec, pl.pt);
+  build_tiles(pl.tl4, pl.p4, pl.s4, pl.prec, pl.pt);
   return ITN_OK;
 }
 
@@ -624,9 +662,12 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   add(pl.p4.size() * sizeof(GProb));
   add(pl.s1.size() * sizeof(GSeg));
   add(pl.s4.size() * sizeof(GSeg));
-  for (int c = 0; c < 2; ++c) {
-    add(pl.t1[c].size() * sizeof(GTile));
-    add(pl.t4[c].size() * sizeof(GTile));
+  for (auto* tl : {&pl.tl1, &pl.tl4}) {
+    for (int c = 0; c < 2; ++c) {
+      add(tl->all[c].size() * sizeof(GTile));
+      add(tl->rest[c].size() * sizeof(GTile));
+    }
+    add(tl->big.size() * sizeof(GTile));
   }
   add(pl.tb.size() * sizeof(QnTBlock));
   add(pl.tbi.size() * sizeof(int32_t));
@@ -649,9 +690,12 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   ITN_HIP(h, put(pl.dp4, pl.p4));
   ITN_HIP(h, put(pl.ds1, pl.s1));
   ITN_HIP(h, put(pl.ds4, pl.s4));
-  for (int c = 0; c < 2; ++c) {
-    ITN_HIP(h, put(pl.dt1[c], pl.t1[c]));
-    ITN_HIP(h, put(pl.dt4[c], pl.t4[c]));
+  for (auto* tl : {&pl.tl1, &pl.tl4}) {
+    for (int c = 0; c < 2; ++c) {
+      ITN_HIP(h, put(tl->d_all[c], tl->all[c]));
+      ITN_HIP(h, put(tl->d_rest[c], tl->rest[c]));
+    }
+    ITN_HIP(h, put(tl->d_big, tl->big));
   }
   ITN_HIP(h, put(pl.dtb, pl.tb));
   ITN_HIP(h, put(pl.dtbi, pl.tbi));
@@ -674,6 +718,7 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   ITN_HIP(h, zalloc(&pl.Z, (size_t)pl.nv * pl.Z_elems * es));
   ITN_HIP(h, zalloc(&pl.Lp, (size_t)pl.Lp_elems * es));
   ITN_HIP(h, zalloc(&pl.Rp, (size_t)pl.Rp_elems * es));
+  ITN_HIP(h, zalloc(&pl.zero, 256));
   ITN_HIP(h, hipDeviceSynchronize());
   return ITN_OK;
 }
@@ -681,6 +726,26 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
 constexpr int MAX_WG = 1024;  // persistent grouped launches: at most 4 workgroups per CU
 
 // The launches of one apply (after the operand pointers are set).
+// One grouped stage (0: stage 1, 1: stage 4) in launch mode `mode`.
+hipError_t stage_launch(itn_plan& pl, int stage, int mode, hipStream_t s) {
+  const bool s1 = stage == 0;
+  const GBases* b = s1 ? &pl.dptrs->g1 : &pl.dptrs->g4;
+  const GProb* P = s1 ? pl.dp1 : pl.dp4;
+  const GSeg* S = s1 ? pl.ds1 : pl.ds4;
+  const itn_plan::Tiles& T = s1 ? pl.tl1 : pl.tl4;
+  const int cdt = s1 ? pl.xt : pl.out_dt;
+  const int64_t a_bs = s1 ? 0 : pl.Z_elems, b_bs = s1 ? pl.psiT_elems : 0;
+  const int64_t c_bs = s1 ? pl.X_elems : pl.out_elems;
+  if (mode < 2)
+    return gemm_grouped(pl.prec, cdt, mode, b, P, S, T.d_all[mode], (int64_t)T.all[mode].size(), a_bs,
+                        b_bs, c_bs, pl.nv, MAX_WG, s);
+  hipError_t e = gemm_grouped(pl.prec, cdt, 2, b, P, S, T.d_big, (int64_t)T.big.size(), a_bs, b_bs,
+                              c_bs, pl.nv, MAX_WG, s);
+  if (e != hipSuccess) return e;
+  return gemm_grouped(pl.prec, cdt, mode - 2, b, P, S, T.d_rest[mode - 2],
+                      (int64_t)T.rest[mode - 2].size(), a_bs, b_bs, c_bs, pl.nv, MAX_WG, s);
+}
+
 itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int cfg4) {
   QnPtrs* ptrs = &pl.dptrs->p;
   {
@@ -694,8 +759,7 @@ itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int 
   }
   {
     Prof pf(h, "qn_stage1_grouped", s);
-    ITN_HIP(h, gemm_grouped(pl.prec, pl.xt, cfg1, &pl.dptrs->g1, pl.dp1, pl.ds1, pl.dt1[cfg1],
-                            (int64_t)pl.t1[cfg1].size(), 0, pl.psiT_elems, pl.X_elems, pl.nv, MAX_WG, s));
+    ITN_HIP(h, stage_launch(pl, 0, cfg1, s));
   }
   {
     Prof pf(h, "qn_wstage", s);
@@ -709,14 +773,24 @@ itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int 
   }
   {
     Prof pf(h, "qn_stage4_grouped", s);
-    ITN_HIP(h, gemm_grouped(pl.prec, pl.out_dt, cfg4, &pl.dptrs->g4, pl.dp4, pl.ds4, pl.dt4[cfg4],
-                            (int64_t)pl.t4[cfg4].size(), pl.Z_elems, 0, pl.out_elems, pl.nv, MAX_WG, s));
+    ITN_HIP(h, stage_launch(pl, 1, cfg4, s));
   }
   return ITN_OK;
 }
 
 // Pick the faster tile per grouped stage by timing both on the real operands.
 itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
+  // ITN_QN_TILE_MODE="m1,m4" fixes the launch modes (tests and experiments)
+  if (const char* fm = std::getenv("ITN_QN_TILE_MODE")) {
+    int a = -1, b = -1;
+    if (std::sscanf(fm, "%d,%d", &a, &b) == 2 && a >= 0 && a < 4 && b >= 0 && b < 4) {
+      pl.cfg1 = a;
+      pl.cfg4 = b;
+      pl.tuned = true;
+      return ITN_OK;
+    }
+    return fail(h, ITN_E_ARG, "ITN_QN_TILE_MODE must be \"m1,m4\" with modes 0..3");
+  }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load();
@@ -732,19 +806,13 @@ itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
   ITN_HIP(h, hipEventCreate(&e0));
   ITN_HIP(h, hipEventCreate(&e1));
   float best1 = 1e30f, best4 = 1e30f;
-  for (int c = 0; c < 2; ++c) {
+  for (int c = 0; c < 4; ++c) {
     for (int stage = 0; stage < 2; ++stage) {
+      if (c >= 2 && (stage == 0 ? pl.tl1 : pl.tl4).big.empty()) continue;
       float tot = 0.f;
       for (int rep = 0; rep < 3; ++rep) {
         ITN_HIP(h, hipEventRecord(e0, s));
-        if (stage == 0)
-          ITN_HIP(h, gemm_grouped(pl.prec, pl.xt, c, &pl.dptrs->g1, pl.dp1, pl.ds1, pl.dt1[c],
-                                  (int64_t)pl.t1[c].size(), 0, pl.psiT_elems, pl.X_elems, pl.nv,
-                                  MAX_WG, s));
-        else
-          ITN_HIP(h, gemm_grouped(pl.prec, pl.out_dt, c, &pl.dptrs->g4, pl.dp4, pl.ds4, pl.dt4[c],
-                                  (int64_t)pl.t4[c].size(), pl.Z_elems, 0, pl.out_elems, pl.nv,
-                                  MAX_WG, s));
+        ITN_HIP(h, stage_launch(pl, stage, c, s));
         ITN_HIP(h, hipEventRecord(e1, s));
         ITN_HIP(h, hipEventSynchronize(e1));
         float ms = 0.f;
@@ -850,7 +918,7 @@ itn_status itn_plan_query(const itn_plan* pl, itn_plan_info* info) {
   info->n_pairs_stage1 = pl->pairs1;
   info->n_groups_stage1 = (int64_t)pl->p1.size();
   info->n_pairs_stage4 = (int64_t)pl->s4.size();
-  info->n_tiles = (int64_t)(pl->t1[pl->cfg1].size() + pl->t4[pl->cfg4].size());
+  info->n_tiles = (int64_t)(pl->tl1.count(pl->cfg1) + pl->tl4.count(pl->cfg4));
   info->flops = pl->flops_gemm * pl->nv;
   info->x_elems = pl->X_elems;
   info->z_elems = pl->Z_elems;
@@ -903,8 +971,8 @@ itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, c
   v.p.R = R->data;
   v.p.psi = psi->data;
   v.p.out = out->data;
-  v.g1 = GBases{pl->Lp, pl->psiT, pl->X};
-  v.g4 = GBases{pl->Z, pl->Rp, out->data};
+  v.g1 = GBases{pl->Lp, pl->psiT, pl->X, pl->zero};
+  v.g4 = GBases{pl->Z, pl->Rp, out->data, pl->zero};
   {
     Prof pf(h, "qn_set_ptrs", s);
     ITN_HIP(h, qn_set_ptrs(pl->dptrs, v, s));

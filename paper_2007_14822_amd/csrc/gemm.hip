@@ -84,6 +84,42 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(
   }
 }
 
+// Persistent grouped GEMM on direct-to-LDS 8-wave tiles (large problems of a
+// grouped launch).  K segments may end inside a K step (zero page).
+template <int P, int BM, int BN, int WM, int WN, typename TOut>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_grouped_direct_kernel(
+    const GBases* __restrict__ bases, const GProb* __restrict__ probs, const GSeg* __restrict__ segs,
+    const GTile* __restrict__ tiles, int64_t ntiles, int64_t a_bs, int64_t b_bs, int64_t c_bs) {
+  using Cfg = DirectCfg<P, BM, BN, WM, WN>;
+  using T = typename Cfg::T;
+  extern __shared__ __align__(16) char lds[];
+  const T* Abase = static_cast<const T*>(bases->A);
+  const T* Bbase = static_cast<const T*>(bases->B);
+  const T* zero = static_cast<const T*>(bases->zero);
+  TOut* Cbase = static_cast<TOut*>(bases->C);
+  const int64_t batch = blockIdx.y;
+  for (int64_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const GTile t = tiles[ti];
+    const GProb pr = probs[t.prob];
+    typename Cfg::AccV acc[Cfg::FM][Cfg::FN];
+#pragma unroll
+    for (int i = 0; i < Cfg::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::FN; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+    for (int sgi = 0; sgi < pr.nseg; ++sgi) {
+      const GSeg sg = segs[pr.seg0 + sgi];
+      gemm_accum_direct<P, BM, BN, WM, WN, true>(Abase + sg.a_off + batch * a_bs, sg.lda, pr.M,
+                                                 Bbase + sg.b_off + batch * b_bs, sg.ldb, pr.N, sg.K,
+                                                 (int64_t)t.tm * BM, (int64_t)t.tn * BN, acc, lds, zero);
+    }
+    store_tile_direct<P, BM, BN, WM, WN, TOut, false>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc,
+                                                       pr.M, pr.N, (int64_t)t.tm * BM,
+                                                       (int64_t)t.tn * BN);
+  }
+}
+
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // Tiles above 64 KiB of LDS need the per-kernel dynamic-LDS limit raised
@@ -199,12 +235,33 @@ static hipError_t launch_grouped(const GBases* bases, const GProb* probs, const 
   return hipGetLastError();
 }
 
+template <int P, int BM, int BN, int WM, int WN, typename TOut>
+static hipError_t launch_grouped_direct(const GBases* bases, const GProb* probs, const GSeg* segs,
+                                        const GTile* tiles, int64_t ntiles, int64_t a_bs, int64_t b_bs,
+                                        int64_t c_bs, int nbatch, int max_wg, hipStream_t s) {
+  using Cfg = DirectCfg<P, BM, BN, WM, WN>;
+  if (ntiles == 0 || nbatch == 0) return hipSuccess;
+  int64_t g = ntiles;
+  if (max_wg > 0 && g > max_wg) g = max_wg;
+  dim3 grid((unsigned)g, (unsigned)nbatch);
+  static const hipError_t attr =
+      allow_lds(gemm_grouped_direct_kernel<P, BM, BN, WM, WN, TOut>, Cfg::LDS_BYTES);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((gemm_grouped_direct_kernel<P, BM, BN, WM, WN, TOut>), grid, dim3(Cfg::THREADS),
+                     Cfg::LDS_BYTES, s, bases, probs, segs, tiles, ntiles, a_bs, b_bs, c_bs);
+  return hipGetLastError();
+}
+
 #define ITN_GROUPED_ARGS bases, probs, segs, tiles, ntiles, a_bs, b_bs, c_bs, nbatch, max_wg, s
 
 template <int P, typename TOut>
 static hipError_t grouped_cfg(int cfg, const GBases* bases, const GProb* probs, const GSeg* segs,
                               const GTile* tiles, int64_t ntiles, int64_t a_bs, int64_t b_bs,
                               int64_t c_bs, int nbatch, int max_wg, hipStream_t s) {
+  if (cfg == 2) {
+    if constexpr (P == P_F64) return launch_grouped_direct<P, 256, 128, 2, 4, TOut>(ITN_GROUPED_ARGS);
+    else return launch_grouped_direct<P, 256, 256, 2, 4, TOut>(ITN_GROUPED_ARGS);
+  }
   if (cfg == 1) return launch_grouped<P, 128, 128, TOut>(ITN_GROUPED_ARGS);
   return launch_grouped<P, 64, 64, TOut>(ITN_GROUPED_ARGS);
 }
@@ -234,6 +291,10 @@ hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const GBases* bases
 }
 #undef ITN_GROUPED_ARGS
 
-int grouped_tile_rows(int tile_cfg) { return tile_cfg == 1 ? 128 : 64; }
+int grouped_tile_rows(int tile_cfg) { return tile_cfg == 2 ? 256 : tile_cfg == 1 ? 128 : 64; }
+int grouped_tile_cols(int prec, int tile_cfg) {
+  if (tile_cfg == 2) return prec == P_F64 ? 128 : 256;
+  return grouped_tile_rows(tile_cfg);
+}
 
 }  // namespace itn

@@ -196,13 +196,17 @@ template <int P, int BM, int BN, int WM, int WN> struct DirectCfg {
 };
 
 // acc += A[m0:m0+BM, 0:K] * B[n0:n0+BN, 0:K]^T with direct-to-LDS staging.
-template <int P, int BM, int BN, int WM, int WN>
+// Without KTAIL, K is a whole number of K steps.  With KTAIL, K may end
+// inside a step: rows must be readable (and zero) up to K rounded up to 16
+// bytes, and 16-byte chunks beyond that are loaded from `zero` (at least 16
+// zero bytes) instead of the row.
+template <int P, int BM, int BN, int WM, int WN, bool KTAIL = false>
 __device__ __forceinline__ void gemm_accum_direct(
     const typename PT<P>::T* __restrict__ A, int64_t lda, int64_t M,
     const typename PT<P>::T* __restrict__ B, int64_t ldb, int64_t N, int64_t K, int64_t m0,
     int64_t n0,
     typename PT<P>::AccV (&acc)[DirectCfg<P, BM, BN, WM, WN>::FM][DirectCfg<P, BM, BN, WM, WN>::FN],
-    char* lds) {
+    char* lds, const typename PT<P>::T* zero = nullptr) {
   using C = DirectCfg<P, BM, BN, WM, WN>;
   using T = typename C::T;
   const int tid = threadIdx.x;
@@ -210,8 +214,9 @@ __device__ __forceinline__ void gemm_accum_direct(
   const int wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int q = lane >> 4, r16 = lane & 15;
-  const int64_t nk = K / C::BK;
+  const int64_t nk = KTAIL ? (K + C::BK - 1) / C::BK : K / C::BK;
   if (nk <= 0) return;
+  const int64_t kpad = (K + C::E16 - 1) / C::E16 * C::E16;  // readable row length
   const int lrow = lane >> 3;  // row within the wave's 8-row slab
   const int lpos = lane & 7;   // LDS chunk slot this lane fills
   const int slab = wave * 8 + lrow;
@@ -231,10 +236,14 @@ __device__ __forceinline__ void gemm_accum_direct(
   auto issue = [&](char* __restrict__ stage, int64_t k0) {
     char* a = stage + wave * 8 * ROW_BYTES;
     char* b = stage + BM * ROW_BYTES + wave * 8 * ROW_BYTES;
+    // with KTAIL, chunks past the row's readable length come from the zero page
+    const bool tail = KTAIL && k0 + chunk >= kpad;
 #pragma unroll
-    for (int p = 0; p < C::A_PASSES; ++p) lds_direct16(rowA(p) + k0, a + p * C::ROWS_PER_PASS * ROW_BYTES);
+    for (int p = 0; p < C::A_PASSES; ++p)
+      lds_direct16(tail ? zero : rowA(p) + k0, a + p * C::ROWS_PER_PASS * ROW_BYTES);
 #pragma unroll
-    for (int p = 0; p < C::B_PASSES; ++p) lds_direct16(rowB(p) + k0, b + p * C::ROWS_PER_PASS * ROW_BYTES);
+    for (int p = 0; p < C::B_PASSES; ++p)
+      lds_direct16(tail ? zero : rowB(p) + k0, b + p * C::ROWS_PER_PASS * ROW_BYTES);
   };
   // One K step: the direct loads of the next stage into `nxt` overlap the
   // MFMAs on `cur`.  The stages never alias; the restrict-qualified

@@ -54,15 +54,20 @@ struct GBases {
   const void* A;
   const void* B;
   void* C;
+  const void* zero;  // >= 16 zero bytes (K tails of direct-to-LDS tiles)
 };
 // Persistent grouped launch: at most max_wg workgroups (0: one per tile)
-// stride over the tile list.  Tile config: 0 = 64x64, 1 = 128x128.  Batch b
-// (grid.y) offsets A, B and C by b times their batch strides.
+// stride over the tile list.  Tile config: 0 = 64x64, 1 = 128x128 (register
+// staged, any alignment); 2 = direct-to-LDS 8-wave tiles (256x256, FP64
+// 256x128), which need 16-byte aligned operand rows that are zero up to K
+// rounded to 16 bytes, and bases->zero.  Batch b (grid.y) offsets A, B and
+// C by b times their batch strides.
 hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const GBases* bases, const GProb* probs,
                         const GSeg* segs, const GTile* tiles, int64_t ntiles, int64_t a_batch_stride,
                         int64_t b_batch_stride, int64_t c_batch_stride, int nbatch, int max_wg,
                         hipStream_t s);
 int grouped_tile_rows(int tile_cfg);
+int grouped_tile_cols(int prec, int tile_cfg);
 
 // ------------------------------------------------------------- QN helpers
 // Pointers of the caller's operands for one block-sparse H_eff apply, read

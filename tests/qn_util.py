@@ -46,3 +46,14 @@ def c3_operands(seed=None):
     ops = Q.heff_qn_operands(secs, secs, inp.heisenberg_site_qn(1), inp.heisenberg_mpo_link_qn(),
                              W, W, seed, inp.block_values)
     return ops, W, W
+
+
+def large_u1(seed=31):
+    """Sectors of a few hundred states (none a multiple of 8): block GEMMs large
+    enough for the 256-tile path, with ragged M, N and K."""
+    bl = [((-2,), 197), ((0,), 301), ((2,), 229)]
+    br = [((-2,), 203), ((0,), 263), ((2,), 311), ((4,), 199)]
+    W = inp.heisenberg_mpo(3)[1]
+    ops = Q.heff_qn_operands(bl, br, inp.heisenberg_site_qn(1), inp.heisenberg_mpo_link_qn(), W, W,
+                             seed, inp.block_values)
+    return ops, W, W

@@ -118,3 +118,17 @@ def test_c3_full_size_sampled_sectors(h, prec):
         n = psi.blocks[k].size
         r = ref.blocks[k].ravel() if k in ref.blocks else np.zeros(n)
         assert rel_err(got[o:o + n], r) <= TOL[prec], (k, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_qn_launch_modes_parity(h, monkeypatch, prec):
+    """Every grouped launch mode, forced, against the oracle on sectors of a
+    few hundred states (ragged M, N, K: the 256-tile path with K tails)."""
+    ops, W1, W2 = U.large_u1()
+    ref = _ref(ops, [ops[4]])
+    for mode in ("0,0", "1,1", "2,2", "3,3", "2,3", "3,2"):
+        monkeypatch.setenv("ITN_QN_TILE_MODE", mode)
+        plan, _, got = _run(h, ops, W1, W2, prec, 1, [ops[4]])
+        assert plan.info()["n_tiles"] > 0
+        assert rel_err(got, ref) <= TOL[prec], (mode, prec)
+        del plan
