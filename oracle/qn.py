@@ -7,6 +7,11 @@ subtracts); contracted index pairs must have opposite arrows; the flux of a
 product is the sum of the operands' fluxes.  Sec. 9.2 stores a block-sparse
 tensor as one array plus a map from block to offset.
 
+A QN component may obey Z_N addition instead of integer addition (Sec. 8,
+fermion parity being the example, Z_2): its values are taken modulo N.  An
+index carries the modulus of every component (`mod`, 0 = integer addition,
+empty = all integer); QN values are stored reduced, in [0, N).
+
 Block layout used for packing (a reading; the paper's tuples are 1-based):
 blocks are 0-based sector tuples sorted lexicographically with the first
 index most significant, each block row-major, offsets the exclusive prefix
@@ -41,10 +46,18 @@ def qn_scale(a: QN, s: int) -> QN:
     return tuple(s * x for x in a)
 
 
+def qn_reduce(a: QN, mod: Sequence[int]) -> QN:
+    """Components with modulus N > 0 taken modulo N (into [0, N))."""
+    if not mod:
+        return tuple(a)
+    return tuple(x % m if m else x for x, m in zip(a, mod))
+
+
 @dataclass(frozen=True)
 class QNIndex:
     sectors: Tuple[Tuple[QN, int], ...]
     arrow: int = +1  # +1 Out, -1 In
+    mod: Tuple[int, ...] = ()  # per-component modulus, 0 = integer addition
 
     @property
     def dim(self) -> int:
@@ -62,7 +75,10 @@ class QNIndex:
         return out
 
     def dag(self) -> "QNIndex":
-        return QNIndex(self.sectors, -self.arrow)
+        return QNIndex(self.sectors, -self.arrow, self.mod)
+
+    def with_arrow(self, arrow: int) -> "QNIndex":
+        return QNIndex(self.sectors, arrow, self.mod)
 
     def qn(self, k: int) -> QN:
         return self.sectors[k][0]
@@ -71,21 +87,33 @@ class QNIndex:
         return self.sectors[k][1]
 
 
-def make_index(pairs: Sequence[Tuple[Sequence[int], int]], arrow: int = +1) -> QNIndex:
-    return QNIndex(tuple((tuple(int(x) for x in q), int(n)) for q, n in pairs), arrow)
+def make_index(pairs: Sequence[Tuple[Sequence[int], int]], arrow: int = +1,
+               mod: Sequence[int] = ()) -> QNIndex:
+    mod = tuple(int(m) for m in mod)
+    return QNIndex(tuple((qn_reduce(tuple(int(x) for x in q), mod), int(n)) for q, n in pairs), arrow,
+                   mod)
 
 
-def index_from_basis_qns(qns: Sequence[Sequence[int]], arrow: int = +1) -> QNIndex:
+def index_from_basis_qns(qns: Sequence[Sequence[int]], arrow: int = +1,
+                         mod: Sequence[int] = ()) -> QNIndex:
     """Sectors as maximal runs of equal QN in basis order (runs of the same
     QN need not be merged)."""
+    mod = tuple(int(m) for m in mod)
     pairs: List[Tuple[QN, int]] = []
     for q in qns:
-        q = tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,)))
+        q = qn_reduce(tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,))), mod)
         if pairs and pairs[-1][0] == q:
             pairs[-1] = (q, pairs[-1][1] + 1)
         else:
             pairs.append((q, 1))
-    return QNIndex(tuple(pairs), arrow)
+    return QNIndex(tuple(pairs), arrow, mod)
+
+
+def common_mod(inds: Sequence[QNIndex]) -> Tuple[int, ...]:
+    mods = {ind.mod for ind in inds}
+    if len(mods) != 1:
+        raise ValueError("indices of one tensor need the same QN moduli")
+    return mods.pop()
 
 
 def block_flux(inds: Sequence[QNIndex], blk: Sequence[int]) -> QN:
@@ -93,15 +121,16 @@ def block_flux(inds: Sequence[QNIndex], blk: Sequence[int]) -> QN:
     tot = (0,) * nq
     for ind, k in zip(inds, blk):
         tot = qn_add(tot, qn_scale(ind.qn(k), ind.arrow))
-    return tot
+    return qn_reduce(tot, common_mod(inds))
 
 
 def allowed_blocks(inds: Sequence[QNIndex], flux: QN) -> List[Tuple[int, ...]]:
     """Every sector tuple whose arrow-weighted QN sum equals the flux, in
     lexicographic order."""
+    want = qn_reduce(tuple(flux), common_mod(inds))
     out = []
     for blk in itertools.product(*[range(ind.nsec) for ind in inds]):
-        if block_flux(inds, blk) == tuple(flux):
+        if block_flux(inds, blk) == want:
             out.append(tuple(blk))
     return out
 
@@ -140,7 +169,7 @@ class BlockTensor:
 
 def from_dense(T: np.ndarray, inds: Sequence[QNIndex], flux: QN) -> BlockTensor:
     offs = [ind.offsets() for ind in inds]
-    out = BlockTensor(list(inds), tuple(flux))
+    out = BlockTensor(list(inds), qn_reduce(tuple(flux), common_mod(inds)))
     for blk in allowed_blocks(inds, flux):
         sl = tuple(slice(offs[i][k], offs[i][k] + inds[i].sdim(k)) for i, k in enumerate(blk))
         out.blocks[blk] = np.array(T[sl], dtype=np.float64)
@@ -159,7 +188,7 @@ def outside_blocks_max(T: np.ndarray, inds: Sequence[QNIndex], flux: QN) -> floa
 
 def random_blocks(inds: Sequence[QNIndex], flux: QN, seed: int, block_values) -> BlockTensor:
     """Fill every allowed block with `block_values(seed, key, shape)`."""
-    out = BlockTensor(list(inds), tuple(flux))
+    out = BlockTensor(list(inds), qn_reduce(tuple(flux), common_mod(inds)))
     for blk in allowed_blocks(inds, flux):
         out.blocks[blk] = block_values(seed, blk, out.block_shape(blk))
     return out
@@ -177,7 +206,7 @@ def contract_blocks(A: BlockTensor, la: Sequence[int], B: BlockTensor, lb: Seque
         ia, ib = A.inds[la.index(l)], B.inds[lb.index(l)]
         if ia.arrow == ib.arrow:
             raise ValueError("contracted QN indices need opposite arrows")
-        if ia.sectors != ib.sectors:
+        if ia.sectors != ib.sectors or ia.mod != ib.mod:
             raise ValueError("contracted QN indices have different sectors")
     free_a = [l for l in la if l not in lb]
     free_b = [l for l in lb if l not in la]
@@ -189,7 +218,8 @@ def contract_blocks(A: BlockTensor, la: Sequence[int], B: BlockTensor, lb: Seque
     for l, ind in zip(lb, B.inds):
         if l not in ind_of:
             ind_of[l] = ind
-    out = BlockTensor([ind_of[l] for l in lc], qn_add(A.flux, B.flux))
+    out = BlockTensor([ind_of[l] for l in lc],
+                      qn_reduce(qn_add(A.flux, B.flux), common_mod(list(A.inds) + list(B.inds))))
     letters = "abcdefghijklmnopqrstuvwxyz"
     allv = sorted(set(la) | set(lb))
     m = {l: letters[k] for k, l in enumerate(allv)}
@@ -232,8 +262,8 @@ def heff_apply_embedded(L: BlockTensor, W1: BlockTensor, W2: BlockTensor, R: Blo
 
 def mpo_blocks(W: np.ndarray, link_in: QNIndex, link_out: QNIndex, site: QNIndex) -> BlockTensor:
     """An MPO tensor W[m_in:Out, m_out:In, s':Out, s:In] with zero flux."""
-    inds = [QNIndex(link_in.sectors, +1), QNIndex(link_out.sectors, -1),
-            QNIndex(site.sectors, +1), QNIndex(site.sectors, -1)]
+    inds = [link_in.with_arrow(+1), link_out.with_arrow(-1), site.with_arrow(+1),
+            site.with_arrow(-1)]
     nq = len(site.qn(0))
     return from_dense(W, inds, (0,) * nq)
 
@@ -248,19 +278,40 @@ def heff_qn_operands(bond_l: Sequence[Tuple[QN, int]], bond_r: Sequence[Tuple[QN
     (seed + tensor tag, sector tuple)."""
     site = index_from_basis_qns(site_qns)
     link = index_from_basis_qns(link_qns)
-    nq = len(site.qn(0))
-    zero = (0,) * nq
     al = make_index(bond_l, +1)
     ar = make_index(bond_r, +1)
-    L = random_blocks([al, QNIndex(link.sectors, -1), QNIndex(al.sectors, -1)], zero,
-                      seed + 1, block_values)
-    R = random_blocks([QNIndex(ar.sectors, -1), QNIndex(link.sectors, +1), QNIndex(ar.sectors, +1)],
-                      zero, seed + 2, block_values)
-    psi = random_blocks([al, site, site, QNIndex(ar.sectors, -1)], psi_flux or zero, seed + 3,
-                        block_values)
-    nrm = psi.norm()
-    for k in psi.blocks:
-        psi.blocks[k] = psi.blocks[k] / nrm
+    L, R, psi = _env_and_psi(al, ar, site, link, seed, block_values, psi_flux)
     w1 = mpo_blocks(W1, link, link, site)
     w2 = mpo_blocks(W2, link, link, site)
     return L, w1, w2, R, psi
+
+
+def _env_and_psi(al: QNIndex, ar: QNIndex, site: QNIndex, link: QNIndex, seed: int, block_values,
+                 psi_flux):
+    zero = (0,) * len(site.qn(0))
+    L = random_blocks([al, link.with_arrow(-1), al.with_arrow(-1)], zero, seed + 1, block_values)
+    R = random_blocks([ar.with_arrow(-1), link.with_arrow(+1), ar.with_arrow(+1)], zero, seed + 2,
+                      block_values)
+    psi = random_blocks([al, site, site, ar.with_arrow(-1)], psi_flux or zero, seed + 3, block_values)
+    nrm = psi.norm()
+    for k in psi.blocks:
+        psi.blocks[k] = psi.blocks[k] / nrm
+    return L, R, psi
+
+
+def heff_qn_operands_random_w(bond_l: Sequence[Tuple[QN, int]], bond_r: Sequence[Tuple[QN, int]],
+                              site_qns: Sequence, link_qns: Sequence, mod: Sequence[int], seed: int,
+                              block_values, psi_flux: QN | None = None):
+    """As heff_qn_operands, for QNs with the given moduli, with the two MPO
+    tensors also Gaussian on every allowed block (a symmetric but otherwise
+    synthetic W).  Returns (L, w1, w2, R, psi, W1 dense, W2 dense)."""
+    site = index_from_basis_qns(site_qns, +1, mod)
+    link = index_from_basis_qns(link_qns, +1, mod)
+    al = make_index(bond_l, +1, mod)
+    ar = make_index(bond_r, +1, mod)
+    L, R, psi = _env_and_psi(al, ar, site, link, seed, block_values, psi_flux)
+    winds = [link.with_arrow(+1), link.with_arrow(-1), site.with_arrow(+1), site.with_arrow(-1)]
+    zero = (0,) * len(site.qn(0))
+    w1 = random_blocks(winds, zero, seed + 4, block_values)
+    w2 = random_blocks(winds, zero, seed + 5, block_values)
+    return L, w1, w2, R, psi, w1.to_dense(), w2.to_dense()

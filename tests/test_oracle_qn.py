@@ -148,3 +148,87 @@ def test_c3_block_counts():
     assert nb == 98
     assert abs(nel - 8.79e6) / 8.79e6 < 0.01
     assert abs(nl - 11.05e6) / 11.05e6 < 0.01
+
+
+# ------------------------------------------------------- Z_N quantum numbers
+def test_zn_paper_parity_example():
+    """Sec. 8: with Z_2 addition, P=1 plus P=1 is P=0; a combined (N, Sz, P)
+    QN adds componentwise with only P taken modulo 2."""
+    assert Q.qn_reduce(Q.qn_add((1,), (1,)), (2,)) == (0,)
+    a, b = (1, -1, 1), (2, 1, 1)
+    assert Q.qn_reduce(Q.qn_add(a, b), (0, 0, 2)) == (3, 0, 0)
+    assert Q.make_index([((5,), 1), ((-3,), 2)], +1, (4,)).sectors == (((1,), 1), ((1,), 2))
+
+
+def _group_average(T, inds, flux, n_u1=64):
+    """Projection of a dense array onto the tensors with the given flux under
+    the symmetry group of the indices' QNs, by averaging the group action
+    e^{i theta q} over the group (Z_N: its N elements; U(1): n_u1 equally
+    spaced angles, exact for charge sums of magnitude below n_u1)."""
+    mod = inds[0].mod or (0,) * len(inds[0].qn(0))
+    out = T.astype(complex)
+    for c, m in enumerate(mod):
+        n = m if m else n_u1
+        acc = np.zeros_like(out)
+        for g in range(n):
+            th = 2 * np.pi * g / n
+            G = out.copy()
+            for a, ind in enumerate(inds):
+                ph = np.concatenate([np.full(nk, np.exp(1j * th * ind.arrow * q[c]))
+                                     for q, nk in ind.sectors])
+                shape = [1] * T.ndim
+                shape[a] = -1
+                G = G * ph.reshape(shape)
+            acc += G * np.exp(-1j * th * flux[c])
+        out = acc / n
+    return out
+
+
+@pytest.mark.parametrize("mod,flux", [((4,), (0,)), ((4,), (3,)), ((0, 3), (1, 2)), ((2, 0, 4), (0, 1, 1))])
+def test_zn_allowed_blocks_match_group_projection(mod, flux):
+    """A random dense array projected onto the symmetric subspace by group
+    averaging equals its restriction to the allowed blocks (and nothing of it
+    lies outside them)."""
+    rng = np.random.default_rng(5)
+    nq = len(mod)
+    def idx(arrow, seed):
+        r = np.random.default_rng(seed)
+        return Q.make_index([(tuple(int(x) for x in r.integers(-3, 5, nq)), int(r.integers(1, 3)))
+                             for _ in range(4)], arrow, mod)
+    inds = [idx(+1, 1), idx(-1, 2), idx(+1, 3)]
+    # distinct QNs per index (merge duplicates by building from unique QNs)
+    inds = [Q.QNIndex(tuple({q: n for q, n in ind.sectors}.items()), ind.arrow, ind.mod) for ind in inds]
+    T = rng.standard_normal([ind.dim for ind in inds])
+    P = _group_average(T, inds, flux)
+    assert np.abs(P.imag).max() < 1e-12
+    B = Q.from_dense(T, inds, flux).to_dense()
+    assert np.allclose(P.real, B, atol=1e-12)
+    assert Q.outside_blocks_max(P.real, inds, flux) < 1e-12
+
+
+def test_zn_contract_matches_dense():
+    mod = (0, 4)
+    a = Q.make_index([((0, 0), 2), ((1, 1), 3), ((1, 3), 1), ((2, 2), 2)], +1, mod)
+    m = Q.make_index([((0, 0), 1), ((1, 1), 2), ((-1, 3), 1), ((0, 2), 2)], +1, mod)
+    A = Q.random_blocks([a, m.dag(), a.dag()], (0, 0), 11, inp.block_values)
+    B = Q.random_blocks([a, m, a.dag()], (1, 3), 12, inp.block_values)
+    C = Q.contract_blocks(A, [1, 2, 3], B, [3, 4, 5], [1, 2, 4, 5])
+    D = np.einsum("abc,cde->abde", A.to_dense(), B.to_dense())
+    assert C.flux == (1, 3)
+    assert np.allclose(C.to_dense(), D, atol=1e-12)
+    assert Q.outside_blocks_max(D, C.inds, C.flux) < 1e-12
+
+
+def test_zn_heff_blocks_match_embedded():
+    """U(1) x Z_4 operands with a synthetic symmetric W: the blockwise H_eff
+    equals the dense route, and the result keeps psi's flux."""
+    bond = [((0, 0), 2), ((1, 1), 3), ((1, 3), 2), ((2, 2), 2), ((0, 2), 1)]
+    site = [(0, 0), (1, 1), (1, 3), (2, 0)]
+    link = [(0, 0), (1, 1), (-1, 3), (0, 2), (0, 0)]
+    L, w1, w2, R, psi, W1, W2 = Q.heff_qn_operands_random_w(bond, bond, site, link, (0, 4), 21,
+                                                            inp.block_values)
+    yb = Q.heff_apply_blocks(L, w1, w2, R, psi)
+    yd, ye = Q.heff_apply_embedded(L, w1, w2, R, psi)
+    assert np.allclose(yb.to_dense(), yd, atol=1e-12)
+    assert Q.outside_blocks_max(yd, psi.inds, psi.flux) < 1e-12
+    assert len(psi.blocks) > 0 and W1.shape == (5, 5, 4, 4)
