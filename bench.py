@@ -158,6 +158,12 @@ def qn_workload(h, torch, np, inp, which, prec, nv):
         W1 = W2 = W
         link_q = inp.heisenberg_mpo_link_qn()
         seed = inp.seed_for(3, 4096)
+    elif which == "c4z4":
+        bond = list(inp.c4z4_sector_dims())
+        site_q = inp.hubbard_momentum_site_qn()
+        link_q = inp.hubbard_momentum_link_qn(18)
+        W1 = W2 = None  # Gaussian on the allowed blocks, built below
+        seed = inp.seed_for(5, 4096)
     else:
         bond = list(inp.c4_sector_dims())
         site_q = inp.hubbard_site_qn()
@@ -173,6 +179,7 @@ def qn_workload(h, torch, np, inp, which, prec, nv):
         kind_q = [(1, 1), (1, -1), (-1, -1), (-1, 1)]
         link_q = [(0, 0)] + [kind_q[k] for k in range(4) for _ in range(rmax)] + [(0, 0)]
         seed = inp.seed_for(4, 4096)
+    mod = (0, 0, 4) if which == "c4z4" else None
     bq = [tuple(q) if isinstance(q, tuple) else (q,) for q, _ in bond]
     bd = [n for _, n in bond]
     sq, sd = inp.sectors_from_basis_qns(site_q)
@@ -183,6 +190,8 @@ def qn_workload(h, torch, np, inp, which, prec, nv):
         "psi": [(bq, bd, +1), (sq, sd, +1), (sq, sd, +1), (bq, bd, -1)],
         "W": [(lq, ld, +1), (lq, ld, -1), (sq, sd, +1), (sq, sd, -1)],
     }
+    if mod:
+        spaces = {k: [sp + (mod,) for sp in v] for k, v in spaces.items()}
     tdt = {"bf16": torch.bfloat16, "f32": torch.float32, "f64": torch.float64}[prec]
     dev = "cuda:0"
 
@@ -206,6 +215,19 @@ def qn_workload(h, torch, np, inp, which, prec, nv):
     Pd["data"] = torch.as_tensor(Pf, device=dev)
     Od = dict(Pd)
     Od["data"] = torch.zeros_like(Pd["data"])
+    if W1 is None:  # synthetic symmetric MPO tensors: Gaussian on their allowed blocks
+        Wds = []
+        for tag in (4, 5):
+            blocks, offs, _ = h.qn_allowed_blocks(spaces["W"])
+            dims = [spaces["W"][i][1] for i in range(4)]
+            starts = [np.concatenate([[0], np.cumsum(dd)[:-1]]) for dd in dims]
+            Wd = np.zeros([int(sum(dd)) for dd in dims])
+            for b in blocks:
+                shp = tuple(int(dims[i][b[i]]) for i in range(4))
+                sl = tuple(slice(int(starts[i][b[i]]), int(starts[i][b[i]]) + shp[i]) for i in range(4))
+                Wd[sl] = inp.block_values(seed + tag, tuple(b), shp)
+            Wds.append(Wd)
+        W1, W2 = Wds
     W1d = {"spaces": spaces["W"], "data": np.ascontiguousarray(W1)}
     W2d = {"spaces": spaces["W"], "data": np.ascontiguousarray(W2)}
     return Ld, W1d, W2d, Rd, Pd, Od
@@ -356,7 +378,7 @@ def main():
         line["speedup_vs_fp64_gpu"] = results["f64"]["ms_per_step"] / r["ms_per_step"]
     if not args.no_qn and not args.only:
         qn = {}
-        for which, nv in (("c3", 1), ("c4", 4), ("c4w38", 4)):
+        for which, nv in (("c3", 1), ("c4", 4), ("c4w38", 4), ("c4z4", 4)):
             for prec in ("bf16", "f64"):
                 log("[bench] QN %s %s nv=%d" % (which, prec, nv))
                 r_qn, out = time_qn(h, torch, np, inp, which, prec, nv, 10, 3)

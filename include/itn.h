@@ -80,6 +80,10 @@ typedef struct {
   const int32_t* qn;  /* nsec*nq, sector-major */
   const int32_t* dim; /* nsec */
   int8_t arrow;       /* +1 Out (QNs add to the flux), -1 In (subtract) */
+  const int32_t* mod; /* nq addition rules, or NULL (all integer): 0 = integer
+                         addition, N >= 2 = Z_N addition (values taken mod N;
+                         Sec. 8).  Every index of every operand of one call
+                         must use the same rules. */
 } itn_space;
 
 /* A tensor argument.

@@ -268,7 +268,9 @@ def _qn(keep: _Keep, desc) -> L.itn_tensor:
     spaces = desc["spaces"]
     rank = len(spaces)
     sp = (L.itn_space * rank)()
-    for i, (qns, dims, arrow) in enumerate(spaces):
+    for i, spc in enumerate(spaces):
+        qns, dims, arrow = spc[:3]
+        mod = spc[3] if len(spc) > 3 else None
         qns = [tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,))) for q in qns]
         nq = len(qns[0])
         sp[i].nsec = len(dims)
@@ -276,10 +278,12 @@ def _qn(keep: _Keep, desc) -> L.itn_tensor:
         sp[i].qn = keep.arr(C.c_int32, [x for q in qns for x in q])
         sp[i].dim = keep.arr(C.c_int32, [int(x) for x in dims])
         sp[i].arrow = int(arrow)
+        if mod:
+            sp[i].mod = keep.arr(C.c_int32, [int(m) for m in mod])
     keep.items.append(sp)
     tt = L.itn_tensor()
     tt.rank = rank
-    totals = [int(sum(dims)) for _, dims, _ in spaces]
+    totals = [int(sum(spc[1])) for spc in spaces]
     tt.dims = keep.arr(C.c_int64, totals)
     tt.space = C.cast(sp, C.POINTER(L.itn_space))
     data = desc.get("data")

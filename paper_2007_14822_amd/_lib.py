@@ -21,7 +21,7 @@ ITN_LEFT, ITN_RIGHT = 0, 1
 
 class itn_space(C.Structure):
     _fields_ = [("nsec", C.c_int32), ("nq", C.c_int32), ("qn", C.POINTER(C.c_int32)),
-                ("dim", C.POINTER(C.c_int32)), ("arrow", C.c_int8)]
+                ("dim", C.POINTER(C.c_int32)), ("arrow", C.c_int8), ("mod", C.POINTER(C.c_int32))]
 
 
 class itn_tensor(C.Structure):

@@ -33,15 +33,21 @@ using namespace itn;
 
 namespace {
 
+// QN component c adds modulo mod[c] when mod[c] > 0 (Z_N), else as integers.
+inline int32_t qn_red(int64_t x, int32_t m) { return m > 0 ? (int32_t)(((x % m) + m) % m) : (int32_t)x; }
+
 struct QSpace {
   int nsec = 0, nq = 0;
-  std::vector<int32_t> qn;   // nsec*nq
+  std::vector<int32_t> qn;   // nsec*nq, Z_N components reduced into [0, N)
+  std::vector<int32_t> mod;  // nq addition rules (0 = integer)
   std::vector<int32_t> dim;  // nsec
   std::vector<int64_t> off;  // element offset of each sector
   int8_t arrow = 0;
   int64_t total = 0;
   const int32_t* q(int k) const { return qn.data() + (size_t)k * nq; }
-  bool same_sectors(const QSpace& o) const { return nq == o.nq && qn == o.qn && dim == o.dim; }
+  bool same_sectors(const QSpace& o) const {
+    return nq == o.nq && qn == o.qn && dim == o.dim && mod == o.mod;
+  }
   // sector with exactly this QN, or -1 (sectors with distinct QNs only)
   int find(const std::vector<int32_t>& want) const {
     for (int k = 0; k < nsec; ++k)
@@ -65,7 +71,16 @@ itn_status read_space(itn_handle* h, const itn_space& s, QSpace& out, const char
   if (s.arrow != 1 && s.arrow != -1) return fail(h, ITN_E_ARROW, "%s: arrow must be +1 or -1", what);
   out.nsec = s.nsec;
   out.nq = s.nq;
+  out.mod.assign(s.nq, 0);
+  if (s.mod) {
+    for (int c = 0; c < s.nq; ++c) {
+      if (s.mod[c] < 0 || s.mod[c] == 1)
+        return fail(h, ITN_E_ARG, "%s: a QN addition rule is 0 (integer) or N >= 2 (Z_N)", what);
+      out.mod[c] = s.mod[c];
+    }
+  }
   out.qn.assign(s.qn, s.qn + (size_t)s.nsec * s.nq);
+  for (size_t k = 0; k < out.qn.size(); ++k) out.qn[k] = qn_red(out.qn[k], out.mod[k % s.nq]);
   out.dim.assign(s.dim, s.dim + s.nsec);
   out.arrow = s.arrow;
   out.off.resize(s.nsec);
@@ -80,10 +95,12 @@ itn_status read_space(itn_handle* h, const itn_space& s, QSpace& out, const char
 
 std::vector<int32_t> block_flux(const QTensor& t, const std::vector<int32_t>& blk) {
   const int nq = t.sp[0].nq;
-  std::vector<int32_t> f(nq, 0);
+  std::vector<int64_t> f(nq, 0);
   for (int i = 0; i < t.rank; ++i)
     for (int c = 0; c < nq; ++c) f[c] += t.sp[i].arrow * t.sp[i].q(blk[i])[c];
-  return f;
+  std::vector<int32_t> r(nq);
+  for (int c = 0; c < nq; ++c) r[c] = qn_red(f[c], t.sp[0].mod[c]);
+  return r;
 }
 
 // Read a QN tensor: spaces, expected arrows, block list (validated).
@@ -100,6 +117,7 @@ itn_status read_qtensor(itn_handle* h, const itn_tensor* t, int rank, const int*
       return fail(h, ITN_E_ARROW, "%s index %d has arrow %d, expected %d", what, i, out.sp[i].arrow,
                   arrows[i]);
     if (out.sp[i].nq != out.sp[0].nq) return fail(h, ITN_E_SHAPE, "%s: mixed QN lengths", what);
+    if (out.sp[i].mod != out.sp[0].mod) return fail(h, ITN_E_SHAPE, "%s: mixed QN addition rules", what);
   }
   if (!need_blocks) return ITN_OK;
   if (t->nblocks < 0 || (t->nblocks > 0 && (!t->block_sec || !t->block_off)))
@@ -108,7 +126,8 @@ itn_status read_qtensor(itn_handle* h, const itn_tensor* t, int rank, const int*
   std::vector<int32_t> flux(nq, 0);
   if (t->flux) flux.assign(t->flux, t->flux + nq);
   for (int c = 0; c < nq; ++c)
-    if (flux[c] != 0) return fail(h, ITN_E_FLUX, "%s must have zero flux", what);
+    if (qn_red(flux[c], out.sp[0].mod[c]) != 0) return fail(h, ITN_E_FLUX, "%s must have zero flux", what);
+  flux.assign(nq, 0);
   int64_t expect = 0;
   for (int64_t b = 0; b < t->nblocks; ++b) {
     std::vector<int32_t> blk(t->block_sec + b * rank, t->block_sec + (b + 1) * rank);
@@ -156,9 +175,11 @@ std::vector<std::vector<int32_t>> allowed_blocks(const QTensor& t) {
   return out;
 }
 
-std::vector<int32_t> qadd(const int32_t* a, const int32_t* b, int nq, int sb) {
+// a + sb * b under the QN addition rules `mod`.
+std::vector<int32_t> qadd(const int32_t* a, const int32_t* b, const std::vector<int32_t>& mod, int sb) {
+  const int nq = (int)mod.size();
   std::vector<int32_t> r(nq);
-  for (int c = 0; c < nq; ++c) r[c] = a[c] + sb * b[c];
+  for (int c = 0; c < nq; ++c) r[c] = qn_red((int64_t)a[c] + sb * (int64_t)b[c], mod[c]);
   return r;
 }
 
@@ -174,6 +195,8 @@ std::string sig_of(const QTensor& t) {
   for (auto& s : t.sp) {
     o << "[" << (int)s.arrow;
     for (size_t k = 0; k < s.qn.size(); ++k) o << "," << s.qn[k];
+    o << "%";
+    for (auto m : s.mod) o << m << ",";
     o << ";";
     for (auto dd : s.dim) o << dd << ",";
     o << "]";
@@ -369,6 +392,9 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   const int nq = P.sp[0].nq;
   for (QTensor* t : {&L, &R, &W1, &W2})
     if (t->sp[0].nq != nq) return fail(h, ITN_E_SHAPE, "all operands need the same QN length");
+  for (QTensor* t : {&L, &R, &W1, &W2})
+    if (t->sp[0].mod != P.sp[0].mod) return fail(h, ITN_E_SHAPE, "all operands need the same QN rules");
+  const std::vector<int32_t>& qmod = P.sp[0].mod;
   // contracted pairs: equal sectors (arrows already checked opposite)
   if (!L.sp[2].same_sectors(P.sp[0])) return fail(h, ITN_E_SHAPE, "L's a and psi's a differ");
   if (!L.sp[0].same_sectors(P.sp[0])) return fail(h, ITN_E_SHAPE, "L's a' and psi's a differ");
@@ -474,7 +500,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     if (N_ia[ia] == 0) continue;
     for (int im = 0; im < SM.nsec; ++im) {
       // L[a':Out, m:In, a:In], zero flux: q(a') = q(m) + q(a)
-      const int iap = SA.find(qadd(SM.q(im), SA.q(ia), nq, +1));
+      const int iap = SA.find(qadd(SM.q(im), SA.q(ia), qmod, +1));
       if (iap < 0) continue;
       auto it = L.index.find({iap, im, ia});
       if (it == L.index.end()) continue;
@@ -520,7 +546,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     pr.nseg = 0;
     for (int im2 = 0; im2 < SM2.nsec; ++im2) {
       // R[b':In, m:Out, b:Out], zero flux: q(b) = q(b') - q(m)
-      const int ib = SB.find(qadd(SB.q(ibp), SM2.q(im2), nq, -1));
+      const int ib = SB.find(qadd(SB.q(ibp), SM2.q(im2), qmod, -1));
       if (ib < 0) continue;
       auto it = R.index.find({ibp, im2, ib});
       if (it == R.index.end()) continue;
@@ -600,7 +626,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
             const int g_s1p = (int)S1.off[i1p] + s1l, g_s2p = (int)S2.off[i2p] + s2l;
             for (int im0 = 0; im0 < SM.nsec; ++im0) {
               // X group (ia, im0) with q(a) = q(a') - q(m0)
-              const int ia = SA.find(qadd(SA.q(iap), SM.q(im0), nq, -1));
+              const int ia = SA.find(qadd(SA.q(iap), SM.q(im0), qmod, -1));
               if (ia < 0) continue;
               auto xg = xgroup.find({ia, im0});
               if (xg == xgroup.end() || xg->second.second != iap) continue;
@@ -867,10 +893,12 @@ itn_status itn_qn_allowed_blocks(itn_handle* h, const itn_tensor* t, int64_t* nb
   for (int i = 0; i < t->rank; ++i) {
     ITN_TRY(read_space(h, t->space[i], q.sp[i], "t"));
     if (q.sp[i].nq != q.sp[0].nq) return fail(h, ITN_E_SHAPE, "mixed QN lengths");
+    if (q.sp[i].mod != q.sp[0].mod) return fail(h, ITN_E_SHAPE, "mixed QN addition rules");
   }
   const int nq = q.sp[0].nq;
   std::vector<int32_t> flux(nq, 0);
   if (t->flux) flux.assign(t->flux, t->flux + nq);
+  for (int c = 0; c < nq; ++c) flux[c] = qn_red(flux[c], q.sp[0].mod[c]);
   std::vector<std::vector<int32_t>> out;
   std::vector<int32_t> blk(q.rank, 0);
   std::function<void(int)> rec = [&](int i) {

@@ -387,3 +387,32 @@ def hubbard_mpo_link_qn(w: int) -> List[Tuple[int, int]]:
 def hubbard_site_qn() -> List[Tuple[int, int]]:
     """(N, 2Sz) of the basis (|0>, |up>, |dn>, |up dn>)."""
     return [(0, 0), (1, 1), (1, -1), (2, 0)]
+
+
+# ---------------------------------------------------- Z_N momentum labels
+# A third QN component with Z_4 addition (a k_y-like momentum label around a
+# 4-leg cylinder).  Structure only: the operands built on it are synthetic.
+
+def c4z4_sector_dims(total: int = 4096, n: int = 4) -> List[Tuple[Tuple[int, int, int], int]]:
+    """Every (dN, 2Sz) sector of c4_sector_dims split into n momentum
+    sectors k = 0..n-1 of near-equal size (zero sizes dropped)."""
+    out = []
+    for (dn, sz), d in c4_sector_dims(total):
+        for k in range(n):
+            m = d // n + (1 if k < d % n else 0)
+            if m > 0:
+                out.append(((dn, sz, k), m))
+    return out
+
+
+def hubbard_momentum_site_qn(k: int = 1, n: int = 4) -> List[Tuple[int, int, int]]:
+    """(N, 2Sz, momentum mod n) of (|0>, |up>, |dn>, |up dn>) for an orbital
+    of momentum k."""
+    return [(0, 0, 0), (1, 1, k % n), (1, -1, k % n), (2, 0, (2 * k) % n)]
+
+
+def hubbard_momentum_link_qn(w: int, k: int = 1, n: int = 4) -> List[Tuple[int, int, int]]:
+    """hubbard_mpo_link_qn with a momentum component: creation channels carry
+    +k, annihilation channels -k (mod n)."""
+    kinds = {(1, 1): k, (1, -1): k, (-1, -1): -k, (-1, 1): -k, (0, 0): 0}
+    return [(a, b, kinds[(a, b)] % n) for a, b in hubbard_mpo_link_qn(w)]

@@ -6,7 +6,8 @@ from oracle import qn as Q
 
 
 def space(ind: Q.QNIndex):
-    return ([q for q, _ in ind.sectors], [n for _, n in ind.sectors], ind.arrow)
+    sp = ([q for q, _ in ind.sectors], [n for _, n in ind.sectors], ind.arrow)
+    return sp + (ind.mod,) if ind.mod else sp
 
 
 def desc(bt: Q.BlockTensor, data=None, with_data=True):
@@ -57,3 +58,16 @@ def large_u1(seed=31):
     ops = Q.heff_qn_operands(bl, br, inp.heisenberg_site_qn(1), inp.heisenberg_mpo_link_qn(), W, W,
                              seed, inp.block_values)
     return ops, W, W
+
+
+def zn_u1z4(seed=41, scale=1):
+    """U(1) x Z_4 operands (Z_4 as a momentum-like label) with a synthetic
+    symmetric W (Gaussian on every allowed block); sector sizes times
+    `scale`.  Returns (ops, W1 dense, W2 dense)."""
+    bond = [((0, 0), 2), ((1, 1), 3), ((1, 3), 2), ((2, 2), 2), ((0, 2), 1), ((2, 0), 3), ((1, 2), 2)]
+    bond = [(q, n * scale) for q, n in bond]
+    site = [(0, 0), (1, 1), (1, 3), (2, 0)]
+    link = [(0, 0), (1, 1), (-1, 3), (0, 2), (0, 0)]
+    L, w1, w2, R, psi, W1, W2 = Q.heff_qn_operands_random_w(bond, bond, site, link, (0, 4), seed,
+                                                            inp.block_values)
+    return (L, w1, w2, R, psi), W1, W2

@@ -132,3 +132,23 @@ def test_qn_launch_modes_parity(h, monkeypatch, prec):
         assert plan.info()["n_tiles"] > 0
         assert rel_err(got, ref) <= TOL[prec], (mode, prec)
         del plan
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nv", [1, 3])
+def test_zn_heff_parity(h, prec, nv):
+    """U(1) x Z_4 QNs (Z_N addition, Sec. 8) with a synthetic symmetric W."""
+    ops, W1, W2 = U.zn_u1z4()
+    psis = [ops[4]] + [_perturbed(ops[4], 30 + v) for v in range(nv - 1)]
+    _, _, got = _run(h, ops, W1, W2, prec, nv, psis)
+    assert rel_err(got, _ref(ops, psis)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("mode", ["0,0", "2,3"])
+def test_zn_large_sectors_parity(h, monkeypatch, mode):
+    """U(1) x Z_4 sectors of 100-300 states (the 256-row tiles, K tails)."""
+    monkeypatch.setenv("ITN_QN_TILE_MODE", mode)
+    ops, W1, W2 = U.zn_u1z4(scale=100)
+    for prec in ("f64", "bf16"):
+        _, _, got = _run(h, ops, W1, W2, prec, 1, [ops[4]])
+        assert rel_err(got, _ref(ops, [ops[4]])) <= TOL[prec], (mode, prec)

@@ -107,3 +107,42 @@ def test_allowed_blocks_paper_flux_example(host):
     spaces = [([(0,), (1,)], [2, 3], +1), ([(1,), (2,)], [2, 1], +1)]
     blocks, offs, tot = host.qn_allowed_blocks(spaces, flux=[2])
     assert blocks == [(0, 1), (1, 0)] and offs == [0, 2] and tot == 2 + 6
+
+
+def test_zn_allowed_blocks_match_oracle(host):
+    """Z_N addition rules: the library's block enumeration equals the
+    oracle's for U(1) x Z_4 and Z_2 x U(1) indices, any flux."""
+    nonempty = 0
+    for mod, flux in [((0, 4), (0, 0)), ((0, 4), (1, 3)), ((2, 0), (1, -1)), ((2, 0), (0, 0))]:
+        i1 = Q.make_index([((0, 0), 2), ((1, 1), 1), ((1, 3), 3), ((2, 2), 1)], +1, mod)
+        i2 = Q.make_index([((0, 1), 1), ((1, 0), 2), ((0, 3), 2)], -1, mod)
+        i3 = Q.make_index([((1, 1), 2), ((0, 0), 1), ((2, 3), 1)], +1, mod)
+        inds = [i1, i2, i3]
+        spaces = [U.space(i) for i in inds]
+        blocks, offs, tot = host.qn_allowed_blocks(spaces, flux)
+        ref = Q.allowed_blocks(inds, flux)
+        assert blocks == ref
+        sizes = [int(np.prod([inds[k].sdim(b[k]) for k in range(3)])) for b in ref]
+        assert offs == [int(x) for x in np.cumsum([0] + sizes)[:len(sizes)]] and tot == sum(sizes)
+        nonempty += len(ref) > 0
+    assert nonempty >= 2
+
+
+def test_zn_rules_validated(host):
+    from oracle import qn as Q
+    i1 = Q.make_index([((0, 0), 2), ((1, 1), 1)], +1, (0, 4))
+    bad = [([q for q, _ in i1.sectors], [n for _, n in i1.sectors], +1, (0, 1))]
+    with pytest.raises(itn.ItnError):
+        host.qn_allowed_blocks(bad)
+
+
+def test_zn_plan_out_blocks_match_oracle(host):
+    """Planning a U(1) x Z_4 H_eff on a host-only handle: output blocks equal
+    the oracle's psi blocks (structure, bit-exact)."""
+    ops, W1, W2 = U.zn_u1z4()
+    L, w1, w2, R, psi = ops
+    plan = host.qn_plan(U.desc(L, with_data=False)[0], U.mpo_desc(W1, w1), U.mpo_desc(W2, w2),
+                     U.desc(R, with_data=False)[0], U.desc(psi, with_data=False)[0], nv=1, prec="f64")
+    keys, offs = plan.out_blocks()
+    pk, po, _ = psi.packed()
+    assert [tuple(k) for k in keys] == [tuple(k) for k in pk] and offs == po
