@@ -362,6 +362,21 @@ class Plan:
         self.handle._check(self.lib.itn_plan_out_blocks(self.ptr, sec, off))
         return [tuple(sec[4 * b:4 * b + 4]) for b in range(n)], list(off[:n])
 
+    def bind(self, Ld, Rd, Pd, Od, stream=None):
+        """A callable applying the plan to these operands: the descriptors
+        are marshalled once (the tensors' current storage is used on every
+        call), so a loop of applies costs one library call each."""
+        k = _Keep()
+        ts = [_qn(k, x) for x in (Ld, Rd, Pd, Od)]
+        refs = [C.byref(t) for t in ts]
+        sp = self.handle._sp(stream)
+        lib, h, ptr, check = self.lib, self.handle.h, self.ptr, self.handle._check
+
+        def apply():
+            check(lib.itn_qn_heff_apply(h, ptr, *refs, sp))
+        apply.keep = (k, ts, Ld, Rd, Pd, Od)
+        return apply
+
     def __del__(self):
         try:
             if self.ptr:

@@ -17,6 +17,7 @@
 //            summed in ascending m2-sector order by the workgroup that owns
 //            the output tile (no atomics: run-to-run deterministic).
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -207,9 +208,10 @@ std::string sig_of(const QTensor& t) {
   return o.str();
 }
 
-// process-wide autotune cache: plan signature -> (stage-1 cfg, stage-4 cfg)
+// process-wide autotune cache: plan signature -> (stage-1 mode, stage-4
+// mode, W-stage kernel); lines "key m1 m4 w" in ITN_AUTOTUNE_CACHE if set
 std::mutex g_tune_mu;
-std::map<size_t, std::pair<int, int>> g_tune;
+std::map<size_t, std::array<int, 3>> g_tune;
 bool g_tune_loaded = false;
 
 void tune_load() {
@@ -218,17 +220,23 @@ void tune_load() {
   const char* path = std::getenv("ITN_AUTOTUNE_CACHE");
   if (!path) return;
   std::ifstream f(path);
-  size_t k;
-  int a, b;
-  while (f >> k >> a >> b) g_tune[k] = {a, b};
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    size_t k;
+    int a, b, c = 0;
+    if (!(is >> k >> a >> b)) continue;
+    is >> c;
+    g_tune[k] = {a, b, c};
+  }
 }
 
-void tune_store(size_t key, int a, int b) {
-  g_tune[key] = {a, b};
+void tune_store(size_t key, int a, int b, int c) {
+  g_tune[key] = {a, b, c};
   const char* path = std::getenv("ITN_AUTOTUNE_CACHE");
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << " " << a << " " << b << "\n";
+  f << key << " " << a << " " << b << " " << c << "\n";
 }
 
 }  // namespace
@@ -260,12 +268,20 @@ struct itn_plan {
   std::vector<int32_t> tbi;  // block of every transpose tile
   int64_t tb_tiles = 0;
   std::vector<QnWPair> wp;
+  std::vector<QnWIn> win;
   std::vector<QnWEnt> we;
-  std::vector<QnWItem> wi;
+  // W-stage kernel candidates: streaming, or inputs staged in LDS for
+  // chunks of 64 / 128 / 256 positions (if the largest pair's inputs fit);
+  // one item list each, the autotuner picks wsel.
+  static constexpr int kWCand[4] = {0, 64, 128, 256};
+  std::vector<QnWItem> wi[4];
+  bool wok[4] = {true, false, false, false};
+  int wsel = 0;
   std::vector<QnCopy> cp;  // L / R repacks into padded, aligned blocks
   std::vector<int64_t> zoff, zsize;
   int64_t psiT_elems = 0, X_elems = 0, Z_elems = 0, Lp_elems = 0, Rp_elems = 0;
   int64_t max_db = 0;  // widest right bond sector
+  int64_t max_nin = 0; // most distinct X inputs of one W-stage pair
   int64_t pairs1 = 0;
   double flops_gemm = 0.0, flops_w = 0.0;
   // device state
@@ -277,8 +293,9 @@ struct itn_plan {
   QnTBlock* dtb = nullptr;
   int32_t* dtbi = nullptr;
   QnWPair* dwp = nullptr;
+  QnWIn* dwin = nullptr;
   QnWEnt* dwe = nullptr;
-  QnWItem* dwi = nullptr;
+  QnWItem* dwi[4] = {nullptr, nullptr, nullptr, nullptr};
   QnCopy* dcp = nullptr;
   int64_t* dzoff = nullptr;
   int64_t* dzsize = nullptr;
@@ -606,6 +623,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   for (auto& kv : pairs) {
     const int iap = kv.first.first, ib = kv.first.second;
     QnWPair wpair{};
+    std::map<std::pair<int64_t, int64_t>, int32_t> pair_inputs;  // distinct X inputs -> index
     wpair.e0 = (int32_t)pl.we.size();
     wpair.da = SA.dim[iap];
     wpair.db = SB.dim[ib];
@@ -646,6 +664,8 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
                                 (s1l2 * ds2 + s2l2) * db;
                         e.astride = (int64_t)SM.dim[im0] * N_ia[ia];
                         e.coef = cf;
+                        e.in = pair_inputs.emplace(std::make_pair(e.off, e.astride),
+                                                   (int32_t)pair_inputs.size()).first->second;
                         pl.we.push_back(e);
                       }
                 }
@@ -663,10 +683,25 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
           }
     }
     wpair.ne = (int32_t)(pl.we.size() - wpair.e0);
-    const int pid = (int)pl.wp.size();
+    wpair.in0 = (int32_t)pl.win.size();
+    wpair.nin = (int32_t)pair_inputs.size();
+    pl.win.resize(pl.win.size() + pair_inputs.size());
+    for (auto& kv : pair_inputs) pl.win[wpair.in0 + kv.second] = QnWIn{kv.first.first, kv.first.second};
+    pl.max_nin = std::max<int64_t>(pl.max_nin, (int64_t)pair_inputs.size());
     pl.wp.push_back(wpair);
-    for (int64_t p0 = 0; p0 < (int64_t)wpair.da * wpair.db; p0 += QN_WSTAGE_POS)
-      pl.wi.push_back(QnWItem{pid, (int32_t)p0});
+  }
+  // W-stage item lists, one per kernel candidate
+  {
+    const int64_t xsz = pl.xt == D_F64 ? 8 : 4;
+    for (int c = 0; c < 4; ++c) {
+      const int t = itn_plan::kWCand[c];
+      pl.wok[c] = t == 0 || pl.max_nin * t * xsz <= 144 * 1024;
+      if (!pl.wok[c]) continue;
+      const int64_t chunk = t ? t : QN_WSTAGE_POS;
+      for (size_t pid = 0; pid < pl.wp.size(); ++pid)
+        for (int64_t p0 = 0; p0 < (int64_t)pl.wp[pid].da * pl.wp[pid].db; p0 += chunk)
+          pl.wi[c].push_back(QnWItem{(int32_t)pid, (int32_t)p0});
+    }
   }
   build_tiles(pl.tl1, pl.p1, pl.s1, pl.prec, pl.pt);
   build_tiles(pl.tl4, pl.p4, pl.s4, pl.prec, pl.pt);
@@ -698,8 +733,9 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   add(pl.tb.size() * sizeof(QnTBlock));
   add(pl.tbi.size() * sizeof(int32_t));
   add(pl.wp.size() * sizeof(QnWPair));
+  add(pl.win.size() * sizeof(QnWIn));
   add(pl.we.size() * sizeof(QnWEnt));
-  add(pl.wi.size() * sizeof(QnWItem));
+  for (int c = 0; c < 4; ++c) add(pl.wi[c].size() * sizeof(QnWItem));
   add(pl.cp.size() * sizeof(QnCopy));
   add(pl.zoff.size() * 8);
   add(pl.zsize.size() * 8);
@@ -726,8 +762,9 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   ITN_HIP(h, put(pl.dtb, pl.tb));
   ITN_HIP(h, put(pl.dtbi, pl.tbi));
   ITN_HIP(h, put(pl.dwp, pl.wp));
+  ITN_HIP(h, put(pl.dwin, pl.win));
   ITN_HIP(h, put(pl.dwe, pl.we));
-  ITN_HIP(h, put(pl.dwi, pl.wi));
+  for (int c = 0; c < 4; ++c) ITN_HIP(h, put(pl.dwi[c], pl.wi[c]));
   ITN_HIP(h, put(pl.dcp, pl.cp));
   ITN_HIP(h, put(pl.dzoff, pl.zoff));
   ITN_HIP(h, put(pl.dzsize, pl.zsize));
@@ -752,6 +789,12 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
 constexpr int MAX_WG = 1024;  // persistent grouped launches: at most 4 workgroups per CU
 
 // The launches of one apply (after the operand pointers are set).
+// The W-stage with kernel candidate c.
+hipError_t wstage_launch(itn_plan& pl, int c, hipStream_t s) {
+  return qn_wstage(pl.xt, pl.X, pl.pt, pl.Z, pl.dwp, pl.dwin, pl.dwe, pl.dwi[c], (int64_t)pl.wi[c].size(),
+                   pl.X_elems, pl.Z_elems, pl.nv, itn_plan::kWCand[c], (int)pl.max_nin, s);
+}
+
 // One grouped stage (0: stage 1, 1: stage 4) in launch mode `mode`.
 hipError_t stage_launch(itn_plan& pl, int stage, int mode, hipStream_t s) {
   const bool s1 = stage == 0;
@@ -789,8 +832,7 @@ itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int 
   }
   {
     Prof pf(h, "qn_wstage", s);
-    ITN_HIP(h, qn_wstage(pl.xt, pl.X, pl.pt, pl.Z, pl.dwp, pl.dwe, pl.dwi, (int64_t)pl.wi.size(),
-                         pl.X_elems, pl.Z_elems, pl.nv, s));
+    ITN_HIP(h, wstage_launch(pl, pl.wsel, s));
   }
   if (!pl.zoff.empty()) {
     Prof pf(h, "qn_zero_blocks", s);
@@ -806,12 +848,22 @@ itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int 
 
 // Pick the faster tile per grouped stage by timing both on the real operands.
 itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
+  // ITN_QN_WSTAGE=0|64|128|256 fixes the W-stage kernel (if it fits)
+  int wforce = -1;
+  if (const char* f = std::getenv("ITN_QN_WSTAGE")) {
+    const int t = std::atoi(f);
+    for (int c = 0; c < 4; ++c)
+      if (itn_plan::kWCand[c] == t && pl.wok[c]) wforce = c;
+    if (wforce < 0) return fail(h, ITN_E_ARG, "ITN_QN_WSTAGE=%s is not an applicable W-stage kernel", f);
+    pl.wsel = wforce;
+  }
   // ITN_QN_TILE_MODE="m1,m4" fixes the launch modes (tests and experiments)
   if (const char* fm = std::getenv("ITN_QN_TILE_MODE")) {
     int a = -1, b = -1;
     if (std::sscanf(fm, "%d,%d", &a, &b) == 2 && a >= 0 && a < 4 && b >= 0 && b < 4) {
       pl.cfg1 = a;
       pl.cfg4 = b;
+      if (wforce < 0) pl.wsel = 0;
       pl.tuned = true;
       return ITN_OK;
     }
@@ -821,9 +873,11 @@ itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load();
     auto it = g_tune.find(pl.sig_hash);
-    if (it != g_tune.end()) {
-      pl.cfg1 = it->second.first;
-      pl.cfg4 = it->second.second;
+    if (it != g_tune.end() && it->second[0] >= 0 && it->second[0] < 4 && it->second[1] >= 0 &&
+        it->second[1] < 4 && it->second[2] >= 0 && it->second[2] < 4 && pl.wok[it->second[2]]) {
+      pl.cfg1 = it->second[0];
+      pl.cfg4 = it->second[1];
+      if (wforce < 0) pl.wsel = it->second[2];
       pl.tuned = true;
       return ITN_OK;
     }
@@ -849,11 +903,28 @@ itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
       if (stage == 1 && tot < best4) best4 = tot, pl.cfg4 = c;
     }
   }
+  if (wforce < 0) {  // W-stage kernel candidates
+    float bestw = 1e30f;
+    for (int c = 0; c < 4; ++c) {
+      if (!pl.wok[c]) continue;
+      float tot = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        ITN_HIP(h, hipEventRecord(e0, s));
+        ITN_HIP(h, wstage_launch(pl, c, s));
+        ITN_HIP(h, hipEventRecord(e1, s));
+        ITN_HIP(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        ITN_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tot += ms;
+      }
+      if (tot < bestw) bestw = tot, pl.wsel = c;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   pl.tuned = true;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  tune_store(pl.sig_hash, pl.cfg1, pl.cfg4);
+  tune_store(pl.sig_hash, pl.cfg1, pl.cfg4, pl.wsel);
   return ITN_OK;
 }
 

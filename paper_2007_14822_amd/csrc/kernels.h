@@ -115,10 +115,16 @@ hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
 // Block-sparse W-stage.  The entries of one (a'-sector, b-sector) pair are
 // stored row after row; the last entry of a row carries the row's Z offset,
 // and rows without W12 terms have one zero-weight entry, so every Z element
-// of the pair is written.
+// of the pair is written.  Each entry names its X input both directly (off,
+// astride) and as an index into the pair's list of distinct inputs.
 struct QnWPair {
   int32_t e0, ne;       // entries of this pair
   int32_t da, db;       // positions a' < da, b < db
+  int32_t in0, nin;     // distinct X inputs of this pair
+};
+struct QnWIn {
+  int64_t off;          // X offset of (a' = 0, b = 0)
+  int64_t astride;
 };
 struct QnWEnt {
   int64_t off;          // X offset of (a' = 0, b = 0)
@@ -127,16 +133,19 @@ struct QnWEnt {
   int64_t zoff;         // Z offset of (a' = 0, b = 0) of the row (last entry of a row)
   int64_t zastride;     // 0 on entries that do not end a row
   int32_t end;          // 1 on the last entry of a row
-  int32_t pad;
+  int32_t in;           // index into the pair's inputs
 };
-constexpr int QN_WSTAGE_POS = 512;  // positions per item (2 per thread)
+constexpr int QN_WSTAGE_POS = 512;  // positions per item of the streaming kernel (2 per thread)
 struct QnWItem {
   int32_t pair;
   int32_t p0;  // first position
 };
+// staged = 64/128/256: items of that many positions; the pair's inputs for
+// them are loaded once into LDS (max_nin inputs at most); staged = 0: the
+// streaming kernel (QN_WSTAGE_POS positions per item, X read per entry).
 hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnWPair* pairs,
-                     const QnWEnt* ents, const QnWItem* items, int64_t nitems, int64_t x_bs,
-                     int64_t z_bs, int nv, hipStream_t s);
+                     const QnWIn* ins, const QnWEnt* ents, const QnWItem* items, int64_t nitems,
+                     int64_t x_bs, int64_t z_bs, int nv, int staged, int max_nin, hipStream_t s);
 // Zero the listed output blocks (offsets, sizes) of out + v * bs.
 hipError_t qn_zero_blocks(int dtype, const QnPtrs* ptrs, const int64_t* offs, const int64_t* sizes,
                           int nblocks, int64_t bs, int nv, hipStream_t s);

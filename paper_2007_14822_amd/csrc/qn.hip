@@ -80,7 +80,8 @@ hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, v
 }
 
 // -------------------------------------------------------------- W-stage
-// One workgroup per item of QN_WSTAGE_POS positions (a', b) of a pair, two
+// Streaming variant (pairs with too many inputs for LDS): one workgroup per
+// item of QN_WSTAGE_POS positions (a', b) of a pair, two
 // per thread; the pair's entries are taken four at a time, so every thread
 // has eight independent X loads in flight before it accumulates.
 template <typename TX, typename TZ>
@@ -139,20 +140,95 @@ __global__ __launch_bounds__(256) void qn_wstage_kernel(const TX* __restrict__ X
   }
 }
 
+// Staged variant: one workgroup of T threads per item of T positions.  The
+// pair's distinct X inputs for these positions are loaded once into LDS
+// ([input][position], each thread its own column, so no barrier), then the
+// entries index them; a dense W12 no longer re-reads X per entry.
+template <typename TX, typename TZ, int T>
+__global__ __launch_bounds__(T) void qn_wstage_staged_kernel(const TX* __restrict__ X,
+                                                              TZ* __restrict__ Z,
+                                                              const QnWPair* __restrict__ pairs,
+                                                              const QnWIn* __restrict__ ins,
+                                                              const QnWEnt* __restrict__ ents,
+                                                              const QnWItem* __restrict__ items,
+                                                              int64_t x_bs, int64_t z_bs) {
+  using A = typename std::conditional<sizeof(TX) == 8, double, float>::type;
+  constexpr int NE = 8;
+  extern __shared__ __align__(16) char lds_raw[];
+  A* xs = reinterpret_cast<A*>(lds_raw);
+  const int tid = threadIdx.x;
+  const QnWItem it = items[blockIdx.x];
+  const QnWPair pr = pairs[it.pair];
+  const int npos = pr.da * pr.db;
+  const int p = it.p0 + tid;
+  const bool ok = p < npos;
+  const int pp = ok ? p : 0;  // position (0, 0) exists in every pair
+  const int64_t a = pp / pr.db, b = pp - a * pr.db;
+  const int64_t v = blockIdx.y;
+  const TX* xv = X + v * x_bs;
+  TZ* zv = Z + v * z_bs;
+  const QnWIn* in = ins + pr.in0;
+#pragma unroll 4
+  for (int k = 0; k < pr.nin; ++k) xs[k * T + tid] = (A)xv[in[k].off + a * in[k].astride + b];
+  const QnWEnt* en = ents + pr.e0;
+  const int ne = pr.ne;
+  A z = 0;
+  for (int e0 = 0; e0 < ne; e0 += NE) {
+    QnWEnt ec[NE];
+    A x[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) ec[j] = en[e0 + j < ne ? e0 + j : ne - 1];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) x[j] = xs[ec[j].in * T + tid];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      if (e0 + j >= ne) break;
+      if (ec[j].coef != 0.0) z += (A)ec[j].coef * x[j];  // zero-weight entries add nothing
+      if (ec[j].end) {
+        if (ok) zv[ec[j].zoff + a * ec[j].zastride + b] = qconv<TZ>((double)z);
+        z = 0;
+      }
+    }
+  }
+}
+
+template <typename TX, typename TZ, int T>
+static hipError_t qn_wstage_staged_t(const void* X, void* Z, const QnWPair* pairs, const QnWIn* ins,
+                                     const QnWEnt* ents, const QnWItem* items, int64_t nitems,
+                                     int64_t x_bs, int64_t z_bs, int nv, int max_nin, hipStream_t s) {
+  const int lds = std::max(1, max_nin) * T * (int)sizeof(typename std::conditional<sizeof(TX) == 8, double, float>::type);
+  auto kern = qn_wstage_staged_kernel<TX, TZ, T>;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)nitems, (unsigned)nv), dim3(T), lds, s,
+                     static_cast<const TX*>(X), static_cast<TZ*>(Z), pairs, ins, ents, items, x_bs, z_bs);
+  return hipGetLastError();
+}
+
 template <typename TX, typename TZ>
-static hipError_t qn_wstage_t(const void* X, void* Z, const QnWPair* pairs, const QnWEnt* ents,
-                              const QnWItem* items, int64_t nitems, int64_t x_bs, int64_t z_bs, int nv,
-                              hipStream_t s) {
+static hipError_t qn_wstage_t(const void* X, void* Z, const QnWPair* pairs, const QnWIn* ins,
+                              const QnWEnt* ents, const QnWItem* items, int64_t nitems, int64_t x_bs,
+                              int64_t z_bs, int nv, int staged, int max_nin, hipStream_t s) {
   if (nitems == 0 || nv == 0) return hipSuccess;
+  switch (staged) {
+    case 256: return qn_wstage_staged_t<TX, TZ, 256>(X, Z, pairs, ins, ents, items, nitems, x_bs, z_bs, nv, max_nin, s);
+    case 128: return qn_wstage_staged_t<TX, TZ, 128>(X, Z, pairs, ins, ents, items, nitems, x_bs, z_bs, nv, max_nin, s);
+    case 64: return qn_wstage_staged_t<TX, TZ, 64>(X, Z, pairs, ins, ents, items, nitems, x_bs, z_bs, nv, max_nin, s);
+    case 0: break;
+    default: return hipErrorInvalidValue;
+  }
   hipLaunchKernelGGL((qn_wstage_kernel<TX, TZ>), dim3((unsigned)nitems, (unsigned)nv), dim3(256), 0,
                      s, static_cast<const TX*>(X), static_cast<TZ*>(Z), pairs, ents, items, x_bs, z_bs);
   return hipGetLastError();
 }
 
 hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnWPair* pairs,
-                     const QnWEnt* ents, const QnWItem* items, int64_t nitems, int64_t x_bs,
-                     int64_t z_bs, int nv, hipStream_t s) {
-#define ITN_QW(TX, TZ) return qn_wstage_t<TX, TZ>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, s)
+                     const QnWIn* ins, const QnWEnt* ents, const QnWItem* items, int64_t nitems,
+                     int64_t x_bs, int64_t z_bs, int nv, int staged, int max_nin, hipStream_t s) {
+#define ITN_QW(TX, TZ) return qn_wstage_t<TX, TZ>(X, Z, pairs, ins, ents, items, nitems, x_bs, z_bs, nv, staged, max_nin, s)
   if (x_dtype == D_F64 && z_dtype == D_F64) ITN_QW(double, double);
   if (x_dtype == D_F32 && z_dtype == D_F32) ITN_QW(float, float);
   if (x_dtype == D_F32 && z_dtype == D_BF16) ITN_QW(float, bf16_t);

@@ -152,3 +152,15 @@ def test_zn_large_sectors_parity(h, monkeypatch, mode):
     for prec in ("f64", "bf16"):
         _, _, got = _run(h, ops, W1, W2, prec, 1, [ops[4]])
         assert rel_err(got, _ref(ops, [ops[4]])) <= TOL[prec], (mode, prec)
+
+
+@pytest.mark.parametrize("wk", ["0", "64", "256"])
+@pytest.mark.parametrize("make", [U.small_u1u1, U.zn_u1z4])
+def test_qn_wstage_kernels_parity(h, monkeypatch, wk, make):
+    """Both W-stage kernels (streaming X per entry; inputs staged in LDS in
+    chunks of 64 / 256 positions) give the oracle's result."""
+    monkeypatch.setenv("ITN_QN_WSTAGE", wk)
+    ops, W1, W2 = make()
+    for prec in ("f64", "bf16"):
+        _, _, got = _run(h, ops, W1, W2, prec, 2, [ops[4], _perturbed(ops[4], 7)])
+        assert rel_err(got, _ref(ops, [ops[4], _perturbed(ops[4], 7)])) <= TOL[prec], (wk, prec)
