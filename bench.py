@@ -91,6 +91,44 @@ def build_workload(h, chi, d, torch, np, inp):
     return Lg, Ws[c], Ws[c + 1], Rg, torch.as_tensor(np.ascontiguousarray(psi), device=dev)
 
 
+def sum_leg(h, torch, np, inp, chi, steps, warmup):
+    """H = H_ff + H_zz: the S=1/2 Heisenberg chain as two MPOs (flip-flop,
+    w=4; ZZ, w=3) applied as a sum of H_eff terms at bond dimension chi (bf16
+    operands; environments Gaussian of the right shapes, as only the time is
+    taken here; the parity tests check the values)."""
+    ops = inp.spin_ops(1)
+    Sp, Sm, Sz, I = ops["S+"], ops["S-"], ops["Sz"], ops["Id"]
+    Wf = np.zeros((4, 4, 2, 2))
+    Wf[0, 0], Wf[1, 0], Wf[2, 0], Wf[3, 1], Wf[3, 2], Wf[3, 3] = I, Sp, Sm, 0.5 * Sm, 0.5 * Sp, I
+    Wz = np.zeros((3, 3, 2, 2))
+    Wz[0, 0], Wz[1, 0], Wz[2, 1], Wz[2, 2] = I, Sz, Sz, I
+    g = torch.Generator(device="cuda:0").manual_seed(inp.seed_for(1, chi) + 7)
+    terms = []
+    for W in (Wf, Wz):
+        w = W.shape[0]
+        Le = (torch.randn((chi, w, chi), generator=g, device="cuda:0") / chi).to(torch.bfloat16)
+        Re = (torch.randn((chi, w, chi), generator=g, device="cuda:0") / chi).to(torch.bfloat16)
+        terms.append((Le, W, W, Re))
+    psi = torch.randn((chi, 2, 2, chi), generator=g, device="cuda:0", dtype=torch.float64)
+    out = torch.empty_like(psi)
+    for _ in range(warmup):
+        h.heff_apply_sum(terms, psi, out, prec="bf16")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        h.heff_apply_sum(terms, psi, out, prec="bf16")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flops = 0.0
+    for W in (Wf, Wz):
+        kw = kernel_work(chi, chi, 2, W.shape[0])
+        flops += kw["heff_stage1_fused"] + kw["heff_stage4_gemm"]
+    return {"terms": "Heisenberg flip-flop (w=4) + ZZ (w=3)", "chi": chi, "ms_per_apply": ms,
+            "flop_per_apply": flops, "tflops": flops / (ms * 1e-3) / 1e12, "precision": "bf16"}
+
+
 def time_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, steps, warmup):
     for _ in range(warmup):
         h.heff_apply(Lp, W1, W2, Rp, psi, out, prec=prec)
@@ -290,6 +328,7 @@ def main():
                     help="time one precision only (profiling runs)")
     ap.add_argument("--no-qn", action="store_true")
     ap.add_argument("--no-dmrg", action="store_true")
+    ap.add_argument("--no-sum", action="store_true")
     ap.add_argument("--dmrg-maxdim", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed work, copy a buffer of this many bytes 3 times "
@@ -393,6 +432,8 @@ def main():
                     lo_out = out
                 log("[bench]   %.3f ms, %.1f TFLOP/s" % (r_qn["ms_per_apply"], r_qn["tflops"]))
         line["qn"] = qn
+    if not args.no_sum and not args.only:
+        line["mpo_sum"] = sum_leg(h, torch, np, inp, chi, args.steps, args.warmup)
     if not args.no_dmrg and not args.only:
         md = args.dmrg_maxdim
         sched = [(min(64, md), 1e-10), (min(128, md), 1e-10)] + [(md, 1e-10)] * 4

@@ -168,6 +168,19 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
                           const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
                           int32_t nv, itn_tensor* out, itn_prec prec, void* hip_stream);
 
+/* out = sum over k < nterms of H_eff,k * psi: the effective Hamiltonian of a
+ * sum of MPOs H = H_0 + H_1 + ... (Sec. 7.2, a Hamiltonian given as several
+ * MPOs summed implicitly).  L[k], W1[k], W2[k], R[k] are one term's operands
+ * with the layouts and dtypes of itn_heff_apply; each term may have its own
+ * MPO bond dimension w_k, all share chi_l, chi_r, d and psi.  psi is
+ * transposed once; every term's last stage adds into out (bit-identical to a
+ * single itn_heff_apply for nterms = 1).  Arrays of nterms pointers, owned by
+ * the caller.  Errors: as itn_heff_apply, and ITN_E_ARG for nterms < 1. */
+itn_status itn_heff_apply_sum(itn_handle* h, int32_t nterms, const itn_tensor* const* L,
+                              const itn_tensor* const* W1, const itn_tensor* const* W2,
+                              const itn_tensor* const* R, const itn_tensor* psi, int32_t nv,
+                              itn_tensor* out, itn_prec prec, void* hip_stream);
+
 /* Bytes of library workspace itn_heff_apply uses for these extents. */
 itn_status itn_heff_workspace_size(itn_handle* h, int64_t chi_l, int64_t chi_r, int32_t d,
                                    int32_t w, int32_t nv, itn_prec prec, size_t* bytes);

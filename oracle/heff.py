@@ -173,3 +173,14 @@ def canonicalize(As, center: int) -> List[np.ndarray]:
         As[i] = Q.T.reshape(Q.shape[1], d, b)
         As[i - 1] = np.einsum("asx,yx->asy", As[i - 1], Rm, optimize=False)
     return As
+
+
+def heff_apply_sum(terms, psi: np.ndarray) -> np.ndarray:
+    """Sec. 7.2: a Hamiltonian given as a sum of MPOs H = sum_k H_k acts on the
+    two-site wavefunction as the sum of the terms' effective Hamiltonians;
+    terms = [(L_k, W1_k, W2_k, R_k), ...] (each with its own MPO bond
+    dimension)."""
+    out = np.zeros_like(psi, dtype=np.float64)
+    for L, W1, W2, R in terms:
+        out = out + heff_apply(L, W1, W2, R, psi)
+    return out

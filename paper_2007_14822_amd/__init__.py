@@ -175,6 +175,28 @@ class Handle:
                                             PREC[prec], self._sp(stream)))
         return out
 
+    def heff_apply_sum(self, terms, psi, out, nv: int = 1, prec: str = "f64", stream=None):
+        """out = sum of H_eff,k psi over terms [(Lenv, W1, W2, Renv), ...]."""
+        cl, cr = terms[0][0].shape[0], terms[0][3].shape[0]
+        d = terms[0][1].shape[2]
+        shp = (cl, d, d, cr)
+        k = _Keep()
+        n = len(terms)
+        arrs = {x: (L.itn_tensor * n)() for x in "LABR"}
+        for i, (Le, W1, W2, Re) in enumerate(terms):
+            W1c = np.ascontiguousarray(W1, np.float64)
+            W2c = np.ascontiguousarray(W2, np.float64)
+            k.items += [W1c, W2c]
+            arrs["L"][i], arrs["A"][i] = _dense(k, Le), _dense(k, W1c)
+            arrs["B"][i], arrs["R"][i] = _dense(k, W2c), _dense(k, Re)
+        ptrs = {x: (C.c_void_p * n)(*[C.addressof(arrs[x][i]) for i in range(n)]) for x in arrs}
+        k.items += [arrs, ptrs]
+        tp, to = _dense(k, psi, shape=shp), _dense(k, out, shape=shp)
+        self._check(self.lib.itn_heff_apply_sum(self.h, n, ptrs["L"], ptrs["A"], ptrs["B"], ptrs["R"],
+                                                C.byref(tp), int(nv), C.byref(to), PREC[prec],
+                                                self._sp(stream)))
+        return out
+
     def heff_workspace_size(self, chi_l, chi_r, d, w, nv=1, prec="f64") -> int:
         b = C.c_size_t()
         self._check(self.lib.itn_heff_workspace_size(self.h, chi_l, chi_r, d, w, nv, PREC[prec],

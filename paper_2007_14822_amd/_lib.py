@@ -73,6 +73,7 @@ SIGNATURES = {
     "itn_cast": (S, [P, T, T, P]),
     "itn_contract": (S, [P, T, T, T, C.c_int, P]),
     "itn_heff_apply": (S, [P, T, T, T, T, T, C.c_int32, T, C.c_int, P]),
+    "itn_heff_apply_sum": (S, [P, C.c_int32, P, P, P, P, T, C.c_int32, T, C.c_int, P]),
     "itn_heff_workspace_size": (S, [P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_int, C.POINTER(C.c_size_t)]),
     "itn_qn_heff_plan": (S, [P, T, T, T, T, T, C.c_int32, C.c_int, C.POINTER(P)]),

@@ -490,32 +490,46 @@ itn_status itn_heff_workspace_size(itn_handle* h, int64_t chi_l, int64_t chi_r, 
   return ITN_OK;
 }
 
-itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
-                          const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
-                          int32_t nv, itn_tensor* out, itn_prec prec, void* hip_stream) {
-  if (!h) return ITN_E_ARG;
+// Shapes of one term of H_eff: L [chi_l, w, chi_l], R [chi_r, w, chi_r], W1 and
+// W2 [w, w, d, d] host F64, against psi [chi_l, d, d, chi_r].
+static itn_status check_term(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
+                             const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi) {
   ITN_TRY(check_dense(h, L, "L", 3));
   ITN_TRY(check_dense(h, R, "R", 3));
   ITN_TRY(check_dense(h, W1, "W1", 4));
   ITN_TRY(check_dense(h, W2, "W2", 4));
-  ITN_TRY(check_dense(h, psi, "psi", 4));
-  ITN_TRY(check_dense(h, out, "out", 4));
-  if (!valid_prec(prec)) return fail(h, ITN_E_ARG, "unknown precision");
-  if (nv < 1) return fail(h, ITN_E_ARG, "nv must be >= 1");
-  const int64_t cl = L->dims[0], w = L->dims[1], cr = R->dims[0];
-  const int64_t d = psi->dims[1];
-  if (L->dims[2] != cl) return fail(h, ITN_E_SHAPE, "L must be [chi_l, w, chi_l]");
-  if (R->dims[1] != w || R->dims[2] != cr) return fail(h, ITN_E_SHAPE, "R must be [chi_r, w, chi_r]");
+  const int64_t cl = psi->dims[0], cr = psi->dims[3], d = psi->dims[1], w = L->dims[1];
+  if (L->dims[0] != cl || L->dims[2] != cl) return fail(h, ITN_E_SHAPE, "L must be [chi_l, w, chi_l]");
+  if (R->dims[0] != cr || R->dims[1] != w || R->dims[2] != cr)
+    return fail(h, ITN_E_SHAPE, "R must be [chi_r, w, chi_r]");
   for (const itn_tensor* W : {W1, W2})
     if (W->dims[0] != w || W->dims[1] != w || W->dims[2] != d || W->dims[3] != d)
       return fail(h, ITN_E_SHAPE, "W must be [w, w, d, d] with w = %lld, d = %lld", (long long)w,
                   (long long)d);
-  if (psi->dims[0] != cl || psi->dims[2] != d || psi->dims[3] != cr)
-    return fail(h, ITN_E_SHAPE, "psi must be [chi_l, d, d, chi_r]");
-  for (int k = 0; k < 4; ++k)
-    if (out->dims[k] != psi->dims[k]) return fail(h, ITN_E_SHAPE, "out must have psi's shape");
   if (W1->dtype != ITN_F64 || W2->dtype != ITN_F64 || !W1->data || !W2->data)
     return fail(h, ITN_E_DTYPE, "W1, W2 must be host F64 arrays");
+  return ITN_OK;
+}
+
+// out = sum over the n terms of H_eff,k psi (Sec. 7.2 sums of MPOs).  psi is
+// transposed and cast once; every term runs stage 1 (+ W-stage) and its
+// stage-4 GEMM adds into out from the second term on.
+static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const* Ls,
+                                   const itn_tensor* const* W1s, const itn_tensor* const* W2s,
+                                   const itn_tensor* const* Rs, const itn_tensor* psi, int32_t nv,
+                                   itn_tensor* out, itn_prec prec, void* hip_stream) {
+  if (!h) return ITN_E_ARG;
+  if (n < 1 || !Ls || !W1s || !W2s || !Rs) return fail(h, ITN_E_ARG, "need at least one term");
+  ITN_TRY(check_dense(h, psi, "psi", 4));
+  ITN_TRY(check_dense(h, out, "out", 4));
+  if (!valid_prec(prec)) return fail(h, ITN_E_ARG, "unknown precision");
+  if (nv < 1) return fail(h, ITN_E_ARG, "nv must be >= 1");
+  if (psi->dims[1] != psi->dims[2]) return fail(h, ITN_E_SHAPE, "psi must be [chi_l, d, d, chi_r]");
+  for (int k = 0; k < n; ++k) ITN_TRY(check_term(h, Ls[k], W1s[k], W2s[k], Rs[k], psi));
+  const int64_t cl = psi->dims[0], cr = psi->dims[3];
+  const int64_t d = psi->dims[1];
+  for (int k = 0; k < 4; ++k)
+    if (out->dims[k] != psi->dims[k]) return fail(h, ITN_E_SHAPE, "out must have psi's shape");
   if (psi->dtype == ITN_BF16 || out->dtype == ITN_BF16)
     return fail(h, ITN_E_DTYPE, "psi and out must be F64 or F32");
   if (psi->data == out->data && cl * d * d * cr > 0) return fail(h, ITN_E_ARG, "out must not alias psi");
@@ -528,38 +542,20 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
   const int pt = P == ITN_P_F64 ? D_F64 : (P == ITN_P_F32 ? D_F32 : D_BF16);
   const int es = dtype_size(pt);
   const int xt = xtype_of(P);
-  const bool castL = L->dtype != pt, castR = R->dtype != pt;
-  ITN_TRY(ensure_workspace(h, heff_ws_bytes(cl, cr, (int)d, (int)w, nv, P, castL, castR)));
+  int64_t wmax = 0;
+  bool anyL = false, anyR = false;
+  for (int k = 0; k < n; ++k) {
+    wmax = std::max<int64_t>(wmax, Ls[k]->dims[1]);
+    anyL |= Ls[k]->dtype != pt;
+    anyR |= Rs[k]->dtype != pt;
+  }
+  ITN_TRY(ensure_workspace(h, heff_ws_bytes(cl, cr, (int)d, (int)wmax, nv, P, anyL, anyR)));
   Carver cv(h->ws.ptr);
-  const void* Lp = L->data;
-  const void* Rp = R->data;
-  if (castL) {
-    void* t = cv.take((size_t)(cl * w * cl) * es);
-    Prof pf(h, "cast_env", s);
-    ITN_HIP(h, cast(L->dtype, L->data, pt, t, cl * w * cl, s));
-    Lp = t;
-  }
-  if (castR) {
-    void* t = cv.take((size_t)(cr * w * cr) * es);
-    Prof pf(h, "cast_env", s);
-    ITN_HIP(h, cast(R->dtype, R->data, pt, t, cr * w * cr, s));
-    Rp = t;
-  }
+  void* Lcast = anyL ? cv.take((size_t)(cl * wmax * cl) * es) : nullptr;
+  void* Rcast = anyR ? cv.take((size_t)(cr * wmax * cr) * es) : nullptr;
   void* psiT = cv.take((size_t)(d2 * nv * cr * cl) * es);
-  void* Z = cv.take((size_t)(nv * cl * d2 * w * cr) * es);
-  // The fused stage-1 kernel loads L rows straight into LDS: whole 128-byte
-  // K steps and 16-byte aligned rows.
-  const int64_t bk = 128 / es;
-  CSR fcsr;
-  bool fused = heff_fused_supported(P, (int)w, (int)d2) && cl % bk == 0 && cl > 0 &&
-               (reinterpret_cast<uintptr_t>(Lp) & 15) == 0;
-  if (fused) {
-    // CSR with input index m0*d2 + c and output row c'*w + m2.
-    fcsr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),
-                      (int)w, (int)d, d2, 1, w, 1);
-    fused = heff_fused_table_fits((int)fcsr.row_off.size(), (int64_t)fcsr.coef.size());
-  }
-  void* X = fused ? nullptr : cv.take((size_t)(cl * w * d2 * nv * cr) * dtype_size(xt));
+  void* Z = cv.take((size_t)(nv * cl * d2 * wmax * cr) * es);
+  void* Xbuf = cv.take((size_t)(cl * wmax * d2 * nv * cr) * dtype_size(xt));
   // psi[v][a][c][b] -> psiT[c][v][b][a]
   TransposeArgs ta{};
   ta.rows = cl;
@@ -579,85 +575,124 @@ itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* 
     ITN_HIP(h, transpose_cast(psi->dtype, psi->data, pt, psiT, ta, s));
   }
   const int64_t N1 = d2 * nv * cr;
-  if (fused) {
-    const CSR& csr = fcsr;
-    const WTable* tab = nullptr;
-    ITN_TRY(get_wtable(h, "fused" + csr.key(), csr.row_ptr, csr.row_off, csr.col_off, csr.coef, &tab));
-    HeffFusedArgs fa{};
-    fa.L = Lp;
-    fa.psiT = psiT;
-    fa.Z = Z;
-    fa.chi_l = cl;
-    fa.chi_r = cr;
-    fa.w = (int)w;
-    fa.d2 = (int)d2;
-    fa.nv = nv;
-    fa.nrows = tab->nrows;
-    fa.nnz = (int32_t)tab->nnz;
-    fa.row_ptr = tab->row_ptr;
-    fa.col_idx = tab->col_idx;
-    fa.coef32 = tab->coef32;
-    fa.coef64 = tab->coef;
-    {
+  for (int term = 0; term < n; ++term) {
+    const itn_tensor* L = Ls[term];
+    const itn_tensor* R = Rs[term];
+    const itn_tensor* W1 = W1s[term];
+    const itn_tensor* W2 = W2s[term];
+    const int64_t w = L->dims[1];
+    const void* Lp = L->data;
+    const void* Rp = R->data;
+    if (L->dtype != pt) {
+      Prof pf(h, "cast_env", s);
+      ITN_HIP(h, cast(L->dtype, L->data, pt, Lcast, cl * w * cl, s));
+      Lp = Lcast;
+    }
+    if (R->dtype != pt) {
+      Prof pf(h, "cast_env", s);
+      ITN_HIP(h, cast(R->dtype, R->data, pt, Rcast, cr * w * cr, s));
+      Rp = Rcast;
+    }
+    // The fused stage-1 kernel loads L rows straight into LDS: whole 128-byte
+    // K steps and 16-byte aligned rows.
+    const int64_t bk = 128 / es;
+    CSR fcsr;
+    bool fused = heff_fused_supported(P, (int)w, (int)d2) && cl % bk == 0 && cl > 0 &&
+                 (reinterpret_cast<uintptr_t>(Lp) & 15) == 0;
+    if (fused) {
+      // CSR with input index m0*d2 + c and output row c'*w + m2.
+      fcsr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),
+                        (int)w, (int)d, d2, 1, w, 1);
+      fused = heff_fused_table_fits((int)fcsr.row_off.size(), (int64_t)fcsr.coef.size());
+    }
+    if (fused) {
+      const CSR& csr = fcsr;
+      const WTable* tab = nullptr;
+      ITN_TRY(get_wtable(h, "fused" + csr.key(), csr.row_ptr, csr.row_off, csr.col_off, csr.coef, &tab));
+      HeffFusedArgs fa{};
+      fa.L = Lp;
+      fa.psiT = psiT;
+      fa.Z = Z;
+      fa.chi_l = cl;
+      fa.chi_r = cr;
+      fa.w = (int)w;
+      fa.d2 = (int)d2;
+      fa.nv = nv;
+      fa.nrows = tab->nrows;
+      fa.nnz = (int32_t)tab->nnz;
+      fa.row_ptr = tab->row_ptr;
+      fa.col_idx = tab->col_idx;
+      fa.coef32 = tab->coef32;
+      fa.coef64 = tab->coef;
       Prof pf(h, "heff_stage1_fused", s);
       ITN_HIP(h, heff_stage1_fused(P, fa, s));
+    } else {
+      // Stage 1: X[(a' m0), (c v b)] = L[(a' m0), a] . psiT[(c v b), a]
+      GemmArgs g1{};
+      g1.A = Lp;
+      g1.B = psiT;
+      g1.C = Xbuf;
+      g1.M = cl * w;
+      g1.N = N1;
+      g1.K = cl;
+      g1.lda = cl;
+      g1.ldb = cl;
+      g1.ldc = N1;
+      g1.batch = 1;
+      {
+        Prof pf(h, "heff_stage1_gemm", s);
+        ITN_HIP(h, gemm_nt(P, xt, g1, s));
+      }
+      // W-stage: Z[v][a'][c'][m2][b] = sum W12 X[a'][m0][c][v][b]
+      CSR csr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),
+                           (int)w, (int)d, /*in_m*/ N1, /*in_c*/ (int64_t)nv * cr,
+                           /*out_c*/ w * cr, /*out_m*/ cr);
+      const WTable* tab = nullptr;
+      ITN_TRY(get_wtable(h, csr.key(), csr.row_ptr, csr.row_off, csr.col_off, csr.coef, &tab));
+      WStageArgs wa{};
+      wa.X = cl;
+      wa.Z = nv;
+      wa.Y = cr;
+      wa.isx = w * N1;
+      wa.isz = cr;
+      wa.isy = 1;
+      wa.osx = d2 * w * cr;
+      wa.osz = cl * d2 * w * cr;
+      wa.osy = 1;
+      wa.nrows = tab->nrows;
+      Prof pf(h, "heff_wstage", s);
+      ITN_HIP(h, wstage(xt, Xbuf, pt, Z, wa, tab->row_ptr, tab->row_off, tab->col_off, tab->coef, s));
     }
-  } else {
-  // Stage 1: X[(a' m0), (c v b)] = L[(a' m0), a] . psiT[(c v b), a]
-  GemmArgs g1{};
-  g1.A = Lp;
-  g1.B = psiT;
-  g1.C = X;
-  g1.M = cl * w;
-  g1.N = N1;
-  g1.K = cl;
-  g1.lda = cl;
-  g1.ldb = cl;
-  g1.ldc = N1;
-  g1.batch = 1;
-  {
-    Prof pf(h, "heff_stage1_gemm", s);
-    ITN_HIP(h, gemm_nt(P, xt, g1, s));
-  }
-  // W-stage: Z[v][a'][c'][m2][b] = sum W12 X[a'][m0][c][v][b]
-  CSR csr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),
-                       (int)w, (int)d, /*in_m*/ N1, /*in_c*/ (int64_t)nv * cr,
-                       /*out_c*/ w * cr, /*out_m*/ cr);
-  const WTable* tab = nullptr;
-  ITN_TRY(get_wtable(h, csr.key(), csr.row_ptr, csr.row_off, csr.col_off, csr.coef, &tab));
-  WStageArgs wa{};
-  wa.X = cl;
-  wa.Z = nv;
-  wa.Y = cr;
-  wa.isx = w * N1;
-  wa.isz = cr;
-  wa.isy = 1;
-  wa.osx = d2 * w * cr;
-  wa.osz = cl * d2 * w * cr;
-  wa.osy = 1;
-  wa.nrows = tab->nrows;
-  {
-    Prof pf(h, "heff_wstage", s);
-    ITN_HIP(h, wstage(xt, X, pt, Z, wa, tab->row_ptr, tab->row_off, tab->col_off, tab->coef, s));
-  }
-  }  // unfused
-  // Stage 4: out[(v a' c'), b'] = Z[(v a' c'), (m2 b)] . R[b', (m2 b)]
-  GemmArgs g4{};
-  g4.A = Z;
-  g4.B = Rp;
-  g4.C = out->data;
-  g4.M = (int64_t)nv * cl * d2;
-  g4.N = cr;
-  g4.K = w * cr;
-  g4.lda = w * cr;
-  g4.ldb = w * cr;
-  g4.ldc = cr;
-  g4.batch = 1;
-  {
+    // Stage 4: out[(v a' c'), b'] (+)= Z[(v a' c'), (m2 b)] . R[b', (m2 b)]
+    GemmArgs g4{};
+    g4.A = Z;
+    g4.B = Rp;
+    g4.C = out->data;
+    g4.M = (int64_t)nv * cl * d2;
+    g4.N = cr;
+    g4.K = w * cr;
+    g4.lda = w * cr;
+    g4.ldb = w * cr;
+    g4.ldc = cr;
+    g4.batch = 1;
+    g4.accumulate = term > 0;
     Prof pf(h, "heff_stage4_gemm", s);
     ITN_HIP(h, gemm_nt(P, out->dtype, g4, s));
   }
   return ITN_OK;
+}
+
+itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
+                          const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
+                          int32_t nv, itn_tensor* out, itn_prec prec, void* hip_stream) {
+  return heff_apply_terms(h, 1, &L, &W1, &W2, &R, psi, nv, out, prec, hip_stream);
+}
+
+itn_status itn_heff_apply_sum(itn_handle* h, int32_t nterms, const itn_tensor* const* L,
+                              const itn_tensor* const* W1, const itn_tensor* const* W2,
+                              const itn_tensor* const* R, const itn_tensor* psi, int32_t nv,
+                              itn_tensor* out, itn_prec prec, void* hip_stream) {
+  return heff_apply_terms(h, nterms, L, W1, W2, R, psi, nv, out, prec, hip_stream);
 }
 
 // --------------------------------------------------------- environment step

@@ -217,3 +217,54 @@ def test_env_chain_matches_oracle(h):
     assert rel_err(host(Lg), Lref) <= 1e-12
     # identity channel of a left-canonical chain
     np.testing.assert_allclose(host(Lg)[:, 4, :], np.eye(Lref.shape[0]), atol=1e-12)
+
+
+# ------------------------------------------------------------ sums of MPOs
+SUM_CASES = [
+    (37, 29, 2, [3, 5, 2], 1),     # ragged, unfused terms of different w
+    (128, 96, 2, [5, 5], 2),       # fused stage 1 for every term, stage-4 accumulation
+    (64, 40, 3, [4, 2, 5], 1),     # d = 3
+]
+
+
+@pytest.mark.parametrize("case", range(len(SUM_CASES)))
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_heff_apply_sum_parity(h, case, prec):
+    cl, cr, d, ws, nv = SUM_CASES[case]
+    rng = np.random.default_rng(300 + case)
+    terms = [(rng.standard_normal((cl, w, cl)) / cl, rng.standard_normal((w, w, d, d)),
+              rng.standard_normal((w, w, d, d)), rng.standard_normal((cr, w, cr)) / cr) for w in ws]
+    psi = rng.standard_normal((nv, cl, d, d, cr))
+    ref = np.stack([hf.heff_apply_sum(terms, psi[v]) for v in range(nv)])
+    out = torch.full(psi.shape, float("nan"), dtype=torch.float64, device=DEV)
+    h.heff_apply_sum([(dev(L), W1, W2, dev(R)) for L, W1, W2, R in terms], dev(psi), out, nv=nv,
+                     prec=prec)
+    assert rel_err(host(out), ref) <= TOL[prec], (case, prec)
+
+
+def test_heff_apply_sum_single_term_is_heff_apply(h):
+    L, W1, W2, R, psi = _heff_case(128, 128, 2, 5, 1, 77, "heis")
+    a = torch.zeros(psi.shape, dtype=torch.float64, device=DEV)
+    b = torch.zeros(psi.shape, dtype=torch.float64, device=DEV)
+    h.heff_apply(dev(L), W1, W2, dev(R), dev(psi), a, prec="bf16")
+    h.heff_apply_sum([(dev(L), W1, W2, dev(R))], dev(psi), b, prec="bf16")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_heff_sum_of_split_heisenberg_equals_full(h):
+    """Flip-flop + ZZ MPOs with their own environments of a canonical MPS:
+    the GPU sum equals the oracle's full-MPO H_eff."""
+    from tests.test_oracle_heff import _split_heisenberg
+    N, i = 12, 5
+    As = inp.random_canonical_mps(N, 2, 48, i, np.random.default_rng(12))
+    Wfull = inp.heisenberg_mpo(N)
+    Wf, Wz = _split_heisenberg(N)
+    def operands(Ws):
+        return hf.left_envs(As, Ws)[i], Ws[i], Ws[i + 1], hf.right_envs(As, Ws)[i + 2]
+    psi = np.einsum("asm,mtb->astb", As[i], As[i + 1])
+    ref = hf.heff_apply(*operands(Wfull), psi)
+    out = torch.zeros(psi.shape, dtype=torch.float64, device=DEV)
+    h.heff_apply_sum([(dev(L), W1, W2, dev(R)) for L, W1, W2, R in (operands(Wf), operands(Wz))],
+                     dev(psi), out, prec="f64")
+    assert rel_err(host(out), ref) <= TOL["f64"]

@@ -147,3 +147,58 @@ def test_stage_order_equals_matrix_definition():
     np.testing.assert_allclose(y, yb, rtol=1e-12, atol=1e-12)
     rows = [2, 0]
     np.testing.assert_allclose(hf.heff_apply_rows(L, W1, W2, R, psi, rows), y[rows], atol=1e-13)
+
+
+# ------------------------------------------------------------ sums of MPOs
+def _split_heisenberg(N):
+    """The S=1/2 Heisenberg chain as two MPOs: flip-flop (w=4) and ZZ (w=3),
+    same convention as the library's MPO (left boundary row w-1, right
+    boundary column 0)."""
+    ops = inp.spin_ops(1)
+    Sp, Sm, Sz, I = ops["S+"], ops["S-"], ops["Sz"], ops["Id"]
+    Wf = np.zeros((4, 4, 2, 2))
+    Wf[0, 0], Wf[1, 0], Wf[2, 0] = I, Sp, Sm
+    Wf[3, 1], Wf[3, 2], Wf[3, 3] = 0.5 * Sm, 0.5 * Sp, I
+    Wz = np.zeros((3, 3, 2, 2))
+    Wz[0, 0], Wz[1, 0], Wz[2, 1], Wz[2, 2] = I, Sz, Sz, I
+    return [Wf.copy() for _ in range(N)], [Wz.copy() for _ in range(N)]
+
+
+def test_heff_sum_of_split_mpos_equals_full_mpo():
+    """Sec. 7.2: H given as a sum of MPOs.  Projecting H = H_ff + H_zz onto the
+    two-site space of an MPS is linear, so the sum of the two terms' H_eff
+    (each with its own environments) equals the full MPO's H_eff."""
+    N, i = 8, 3
+    As = inp.random_canonical_mps(N, 2, 6, i, np.random.default_rng(4))
+    Wfull = inp.heisenberg_mpo(N)
+    Wf, Wz = _split_heisenberg(N)
+    def operands(Ws):
+        return hf.left_envs(As, Ws)[i], Ws[i], Ws[i + 1], hf.right_envs(As, Ws)[i + 2]
+    psi = np.einsum("asm,mtb->astb", As[i], As[i + 1])
+    full = hf.heff_apply(*operands(Wfull), psi)
+    summed = hf.heff_apply_sum([operands(Wf), operands(Wz)], psi)
+    assert np.allclose(summed, full, atol=1e-12)
+    # the split MPOs sum to the chain Hamiltonian (dense, small chain)
+    Hs = hf.mpo_to_dense(Wf[:6]) + hf.mpo_to_dense(Wz[:6])
+    assert np.allclose(Hs, ed.heisenberg_dense(6), atol=1e-12)
+
+
+def test_heff_sum_equals_direct_sum_mpo():
+    """A sum of terms equals one H_eff whose MPO tensors are the block-diagonal
+    direct sum of the terms' (environments concatenated along m)."""
+    rng = np.random.default_rng(9)
+    cl, cr, d = 5, 4, 3
+    ws = [3, 5, 2]
+    terms = [(rng.standard_normal((cl, w, cl)), rng.standard_normal((w, w, d, d)),
+              rng.standard_normal((w, w, d, d)), rng.standard_normal((cr, w, cr))) for w in ws]
+    psi = rng.standard_normal((cl, d, d, cr))
+    W = sum(ws)
+    Lds = np.concatenate([t[0] for t in terms], axis=1)
+    Rds = np.concatenate([t[3] for t in terms], axis=1)
+    W1ds, W2ds = np.zeros((W, W, d, d)), np.zeros((W, W, d, d))
+    o = 0
+    for (_, W1, W2, _), w in zip(terms, ws):
+        W1ds[o:o + w, o:o + w], W2ds[o:o + w, o:o + w] = W1, W2
+        o += w
+    assert np.allclose(hf.heff_apply_sum(terms, psi), hf.heff_apply(Lds, W1ds, W2ds, Rds, psi),
+                       atol=1e-10)
