@@ -281,7 +281,7 @@ static hipError_t launch_fused(const HeffFusedArgs& a, hipStream_t s) {
 }
 
 bool heff_fused_supported(int prec, int w, int d2) {
-  if (w != 5) return false;
+  if (w < 3 || w > 5) return false;
   if (d2 == 4) return true;
   if (d2 == 9) return prec != P_F64;
   return false;
@@ -291,19 +291,32 @@ bool heff_fused_table_fits(int nrows, int64_t nnz) {
   return nrows >= 1 && nrows <= 63 && nnz >= 0 && nnz <= 128;  // lane-register table
 }
 
+template <int P, int W> static hipError_t fused_w(const HeffFusedArgs& a, hipStream_t s) {
+  if constexpr (P == P_F64) {
+    return launch_fused<P, W, 4, 2, 4, 1, 1>(a, s);
+  } else {
+    if (a.d2 == 4) return launch_fused<P, W, 4, 2, 4, 2, 1>(a, s);
+    return launch_fused<P, W, 9, 4, 2, 1, 1>(a, s);
+  }
+}
+
+template <int P> static hipError_t fused_p(const HeffFusedArgs& a, hipStream_t s) {
+  switch (a.w) {
+    case 3: return fused_w<P, 3>(a, s);
+    case 4: return fused_w<P, 4>(a, s);
+    case 5: return fused_w<P, 5>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t heff_stage1_fused(int prec, const HeffFusedArgs& a, hipStream_t s) {
   if (!heff_fused_supported(prec, a.w, a.d2)) return hipErrorInvalidValue;
   // the epilogue unrolls over all w*d2 output rows of W12
   if (a.nrows != a.w * a.d2 || !heff_fused_table_fits(a.nrows, a.nnz)) return hipErrorInvalidValue;
   switch (prec) {
-    case P_BF16:
-      if (a.d2 == 4) return launch_fused<P_BF16, 5, 4, 2, 4, 2, 1>(a, s);
-      return launch_fused<P_BF16, 5, 9, 4, 2, 1, 1>(a, s);
-    case P_F32:
-      if (a.d2 == 4) return launch_fused<P_F32, 5, 4, 2, 4, 2, 1>(a, s);
-      return launch_fused<P_F32, 5, 9, 4, 2, 1, 1>(a, s);
-    case P_F64:
-      return launch_fused<P_F64, 5, 4, 2, 4, 1, 1>(a, s);
+    case P_BF16: return fused_p<P_BF16>(a, s);
+    case P_F32: return fused_p<P_F32>(a, s);
+    case P_F64: return fused_p<P_F64>(a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -224,6 +224,7 @@ SUM_CASES = [
     (37, 29, 2, [3, 5, 2], 1),     # ragged, unfused terms of different w
     (128, 96, 2, [5, 5], 2),       # fused stage 1 for every term, stage-4 accumulation
     (64, 40, 3, [4, 2, 5], 1),     # d = 3
+    (128, 64, 2, [4, 3], 1),       # fused stage 1 with w = 4 and w = 3
 ]
 
 
