@@ -128,14 +128,40 @@ def davidson(apply: Callable[[np.ndarray], np.ndarray], v0: np.ndarray,
     return theta, (x / np.linalg.norm(x)).reshape(shape)
 
 
-def local_ground_state(L, W1, W2, R, psi0):
+def overlap_env_left(LO, A, B):
+    """<psi|phi> environment one site further right: LO'[b', b] =
+    sum_{a', a, s} A[a', s, b'] LO[a', a] B[a, s, b] (A of psi, B of phi)."""
+    return np.einsum("xsy,xa,asb->yb", A, LO, B, optimize=False)
+
+
+def overlap_env_right(RO, A, B):
+    """The mirror image: RO'[a', a] = sum_{b', b, s} A[a', s, b'] RO[b', b] B[a, s, b]."""
+    return np.einsum("xsy,yb,asb->xa", A, RO, B, optimize=False)
+
+
+def projected_state(LO, B1, B2, RO):
+    """A previous state phi seen from the two-site space of psi at the bond:
+    v[a', s1, s2, b'] = sum LO[a', a] B1[a, s1, m] B2[m, s2, b] RO[b', b]."""
+    return np.einsum("xa,asm,mtb,yb->xsty", LO, B1, B2, RO, optimize=False)
+
+
+def local_ground_state(L, W1, W2, R, psi0, penalty=()):
+    """Lowest eigenpair of H_eff + sum_k w |v_k><v_k| (penalty = [(w, v_k)])."""
     n = psi0.size
     if n <= EXACT_EIGH_MAX:
         H = hf.heff_matrix(L, W1, W2, R)
+        for wt, v in penalty:
+            H = H + wt * np.outer(v.ravel(), v.ravel())
         H = 0.5 * (H + H.T)
         ev, evec = np.linalg.eigh(H)
         return float(ev[0]), evec[:, 0].reshape(psi0.shape)
-    return davidson(lambda v: hf.heff_apply(L, W1, W2, R, v), psi0)
+
+    def apply(x):
+        y = hf.heff_apply(L, W1, W2, R, x)
+        for wt, v in penalty:
+            y = y + wt * float(np.vdot(v, x)) * v
+        return y
+    return davidson(apply, psi0)
 
 
 @dataclass
@@ -154,9 +180,12 @@ class DMRGResult:
 
 
 def dmrg(Ws: Sequence[np.ndarray], As0: Sequence[np.ndarray],
-         sweeps: Sequence[Tuple[int, float]], mindim: int = 1) -> DMRGResult:
+         sweeps: Sequence[Tuple[int, float]], mindim: int = 1, ortho: Sequence = (),
+         weight: float = 0.0) -> DMRGResult:
     """Two-site DMRG.  `As0` must be right-canonical with its norm on site 0
-    (a normalised product state is)."""
+    (a normalised product state is).  `ortho`: previously found states (lists
+    of site tensors) whose projectors, times the energy penalty `weight`, are
+    added to the Hamiltonian (Sec. 7.2, excited states)."""
     As = [np.array(A, dtype=np.float64) for A in As0]
     N = len(As)
     w = Ws[0].shape[0]
@@ -166,21 +195,37 @@ def dmrg(Ws: Sequence[np.ndarray], As0: Sequence[np.ndarray],
     Renv[N] = hf.right_boundary(w)
     for k in range(N - 1, 0, -1):
         Renv[k] = hf.env_right(Renv[k + 1], As[k], Ws[k])
+    # overlap environments <psi|phi_j>, left and right of the bond
+    LO = [[None] * (N + 1) for _ in ortho]
+    RO = [[None] * (N + 1) for _ in ortho]
+    for j, Bs in enumerate(ortho):
+        LO[j][0] = np.ones((1, 1))
+        RO[j][N] = np.ones((1, 1))
+        for k in range(N - 1, 0, -1):
+            RO[j][k] = overlap_env_right(RO[j][k + 1], As[k], Bs[k])
+
+    def penalty(i):
+        return [(weight, projected_state(LO[j][i], Bs[i], Bs[i + 1], RO[j][i + 2]))
+                for j, Bs in enumerate(ortho)]
     records = []
     energy = 0.0
     for sw, (maxdim, cutoff) in enumerate(sweeps):
         maxtr = 0.0
         for i in range(0, N - 1):
             psi = np.einsum("asb,btc->astc", As[i], As[i + 1], optimize=False)
-            energy, psi = local_ground_state(Lenv[i], Ws[i], Ws[i + 1], Renv[i + 2], psi)
+            energy, psi = local_ground_state(Lenv[i], Ws[i], Ws[i + 1], Renv[i + 2], psi, penalty(i))
             As[i], As[i + 1], tw, _ = split_bond(psi, cutoff, maxdim, True, mindim)
             maxtr = max(maxtr, tw)
             Lenv[i + 1] = hf.env_left(Lenv[i], As[i], Ws[i])
+            for j, Bs in enumerate(ortho):
+                LO[j][i + 1] = overlap_env_left(LO[j][i], As[i], Bs[i])
         for i in range(N - 2, -1, -1):
             psi = np.einsum("asb,btc->astc", As[i], As[i + 1], optimize=False)
-            energy, psi = local_ground_state(Lenv[i], Ws[i], Ws[i + 1], Renv[i + 2], psi)
+            energy, psi = local_ground_state(Lenv[i], Ws[i], Ws[i + 1], Renv[i + 2], psi, penalty(i))
             As[i], As[i + 1], tw, _ = split_bond(psi, cutoff, maxdim, False, mindim)
             maxtr = max(maxtr, tw)
             Renv[i + 1] = hf.env_right(Renv[i + 2], As[i + 1], Ws[i + 1])
+            for j, Bs in enumerate(ortho):
+                RO[j][i + 1] = overlap_env_right(RO[j][i + 2], As[i + 1], Bs[i + 1])
         records.append(SweepRecord(sw, energy, max(A.shape[2] for A in As), maxtr))
     return DMRGResult(energy, As, records)

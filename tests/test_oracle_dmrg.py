@@ -93,3 +93,44 @@ def test_dmrg_hubbard_small_cylinder():
     As0 = inp.neel_product_state(Lx * Ly, 4, up=1, dn=2)
     res = dm.dmrg(inp.hubbard_mpo(Lx, Ly, U=8.0), As0, [(64, 1e-14)] * 4)
     assert abs(res.energy - e_ed) / abs(e_ed) <= 1e-10
+
+
+def test_excited_states_by_energy_penalty_match_ed():
+    """Sec. 7.2 excited states: with the ground state's projector added times
+    a penalty larger than the gap, DMRG finds the first excited level, and
+    with both found states penalised the next level (ED spectrum, N = 8)."""
+    N = 8
+    Ws = inp.heisenberg_mpo(N)
+    ev = np.linalg.eigvalsh(ed.heisenberg_dense(N))
+    levels = [ev[0]]
+    for e in ev[1:]:
+        if e > levels[-1] + 1e-8:
+            levels.append(e)
+    sweeps = [(16, 1e-14)] * 6
+    r0 = dm.dmrg(Ws, inp.random_product_state(N, 2, np.random.default_rng(1)), sweeps)
+    assert abs(r0.energy - levels[0]) < 1e-10
+    r1 = dm.dmrg(Ws, inp.random_product_state(N, 2, np.random.default_rng(2)), sweeps,
+                    ortho=[r0.mps], weight=10.0)
+    assert abs(r1.energy - levels[1]) < 1e-9
+    # the excited state is orthogonal to the ground state
+    v0 = hf.mps_to_dense(r0.mps).ravel()
+    v1 = hf.mps_to_dense(r1.mps).ravel()
+    assert abs(v0 @ v1) < 1e-6 and abs(np.linalg.norm(v1) - 1) < 1e-9
+
+
+def test_projected_state_is_the_overlap():
+    """<phi|psi> over the whole chain equals v . psi_bond at any bond, with v
+    the projected state built from the overlap environments."""
+    N, i = 6, 2
+    rng = np.random.default_rng(3)
+    As = inp.random_canonical_mps(N, 2, 4, i, rng)
+    Bs = inp.random_canonical_mps(N, 2, 3, 0, rng)
+    LO, RO = np.ones((1, 1)), np.ones((1, 1))
+    for k in range(i):
+        LO = dm.overlap_env_left(LO, As[k], Bs[k])
+    for k in range(N - 1, i + 1, -1):
+        RO = dm.overlap_env_right(RO, As[k], Bs[k])
+    v = dm.projected_state(LO, Bs[i], Bs[i + 1], RO)
+    psi = np.einsum("asb,btc->astc", As[i], As[i + 1])
+    full = hf.mps_to_dense(As).ravel() @ hf.mps_to_dense(Bs).ravel()
+    assert abs(float(np.vdot(v, psi)) - full) < 1e-12
