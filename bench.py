@@ -129,6 +129,28 @@ def sum_leg(h, torch, np, inp, chi, steps, warmup):
             "flop_per_apply": flops, "tflops": flops / (ms * 1e-3) / 1e12, "precision": "bf16"}
 
 
+def excited_leg(h, np, inp, N=40, maxdim=64):
+    """Ground state, then the first excited state with the ground state's
+    projector times an energy penalty added (bf16 matvecs, FP64 refinement):
+    energies, gap, wall time and matvecs of each run."""
+    mpo = h.mpo(inp.heisenberg_mpo(N))
+    sweeps = [(16, 1e-10), (32, 1e-10)] + [(maxdim, 1e-10)] * 4
+    kw = dict(prec="bf16", eig_tol=1e-9, krylovdim=8, maxiter=60, refine=True, allow_unconverged=True)
+    out = {"model": "S=1/2 Heisenberg chain, N=%d, maxdim %d, penalty weight 4" % (N, maxdim)}
+    gs = h.mps(inp.random_product_state(N, 2, inp.rng_for(2, 40)))
+    t0 = time.perf_counter()
+    r0 = h.dmrg_sweep(gs, mpo, sweeps, **kw)
+    out["ground"] = {"energy": r0[-1]["energy"], "seconds": time.perf_counter() - t0,
+                     "matvecs": int(sum(r["matvecs"] for r in r0))}
+    x1 = h.mps(inp.random_product_state(N, 2, inp.rng_for(2, 41)))
+    t0 = time.perf_counter()
+    r1 = h.dmrg_sweep(x1, mpo, sweeps, ortho=[gs], weight=4.0, **kw)
+    out["excited"] = {"energy": r1[-1]["energy"], "seconds": time.perf_counter() - t0,
+                      "matvecs": int(sum(r["matvecs"] for r in r1))}
+    out["gap"] = r1[-1]["energy"] - r0[-1]["energy"]
+    return out
+
+
 def time_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, steps, warmup):
     for _ in range(warmup):
         h.heff_apply(Lp, W1, W2, Rp, psi, out, prec=prec)
@@ -461,6 +483,9 @@ def main():
                                     "max_bond")}
         line["dmrg"] = {"model": "spin-1 Heisenberg chain, N=100, d=3, w=5",
                         "schedule": sched, **dm, "bf16_last_sweep_split": split}
+    if not args.no_dmrg and not args.only:
+        log("[bench] excited state by energy penalty, S=1/2 chain N=40")
+        line["excited_state"] = excited_leg(h, np, inp)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(L64.cpu().numpy(), W1, W2, R64.cpu().numpy(),

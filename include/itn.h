@@ -288,6 +288,14 @@ typedef struct {
   double energy_tol;      /* stop early when |dE| < energy_tol*|E| (0: never)  */
   int32_t timing;         /* 1: synchronise at phase boundaries and report the
                              per-phase times below (adds host waits)           */
+  /* Excited states (Sec. 7.2): previously found states whose projectors,
+   * times the energy penalty `weight`, are added to the Hamiltonian, so the
+   * sweep converges to the lowest state orthogonal to them when the weight
+   * exceeds the gap.  ortho: northo MPS handles with the same N and d (not
+   * the MPS being optimised), read only; northo = 0: none. */
+  int32_t northo;
+  const itn_mps* const* ortho;
+  double weight;
 } itn_sweep_params;
 
 /* Per-sweep results, arrays of nsweeps entries owned by the caller (any may

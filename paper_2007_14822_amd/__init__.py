@@ -256,15 +256,22 @@ class Handle:
 
     def dmrg_sweep(self, mps, mpo, sweeps, prec="f64", mindim=1, krylovdim=8, maxiter=100,
                    eig_tol=1e-10, refine=True, energy_tol=0.0, allow_unconverged=False,
-                   timing=False):
+                   timing=False, ortho=(), weight=0.0):
         """Run a schedule [(maxdim, cutoff), ...]; returns per-sweep records
-        (with per-phase seconds t_matvec/t_solver/t_split/t_env if timing)."""
+        (with per-phase seconds t_matvec/t_solver/t_split/t_env if timing).
+        ortho: previously found MPS whose projectors, times `weight`, are
+        added to H (excited states)."""
         ns = len(sweeps)
         md = (C.c_int32 * max(1, ns))(*[int(m) for m, _ in sweeps])
         co = (C.c_double * max(1, ns))(*[float(c) for _, c in sweeps])
         prm = L.itn_sweep_params(ns, md, co, int(mindim), int(krylovdim), int(maxiter),
                                  float(eig_tol), PREC[prec], 1 if refine else 0, float(energy_tol),
                                  1 if timing else 0)
+        optrs = (C.c_void_p * max(1, len(ortho)))(
+            *[o.ptr.value if isinstance(o.ptr, C.c_void_p) else o.ptr for o in ortho])
+        prm.northo = len(ortho)
+        prm.ortho = C.cast(optrs, C.POINTER(C.c_void_p)) if ortho else None
+        prm.weight = float(weight)
         fields = [("energy", C.c_double), ("max_trunc", C.c_double), ("max_bond", C.c_int32),
                   ("seconds", C.c_double), ("matvecs", C.c_int64), ("residual", C.c_double)]
         if timing:

@@ -44,7 +44,8 @@ class itn_sweep_params(C.Structure):
                 ("cutoff", C.POINTER(C.c_double)), ("mindim", C.c_int32),
                 ("krylovdim", C.c_int32), ("maxiter", C.c_int32), ("eig_tol", C.c_double),
                 ("prec", C.c_int), ("refine", C.c_int32), ("energy_tol", C.c_double),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("northo", C.c_int32), ("ortho", C.POINTER(C.c_void_p)),
+                ("weight", C.c_double)]
 
 
 class itn_sweep_result(C.Structure):

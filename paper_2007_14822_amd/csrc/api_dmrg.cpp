@@ -60,14 +60,21 @@ struct itn_mps {
   std::vector<DBuf> Renv;      // N+1: Renv[k] = environment of sites [k, N)
   bool envs = false;
   int mpo_w = 0;
+  // overlap environments with the states of an excited-state sweep:
+  // OL[j][k] = <psi|phi_j> over sites [0, k), OR[j][k] over [k, N)
+  std::vector<std::vector<DBuf>> OL, OR;
   // driver scratch
   DBuf psi, tmp, rho, evec, eval, einfo, V, AV, Lp, Rp, partial, dots, ev_host_stage;
+  DBuf ovec, ot1, ot2, ot3, odots;
   ~itn_mps() {
     for (auto& b : site) b.release();
     for (auto& b : Lenv) b.release();
     for (auto& b : Renv) b.release();
+    for (auto* v : {&OL, &OR})
+      for (auto& row : *v)
+        for (auto& b : row) b.release();
     for (DBuf* b : {&psi, &tmp, &rho, &evec, &eval, &einfo, &V, &AV, &Lp, &Rp, &partial, &dots,
-                    &ev_host_stage})
+                    &ev_host_stage, &ovec, &ot1, &ot2, &ot3, &odots})
       b->release();
   }
 };
@@ -183,6 +190,9 @@ struct Ctx {
   bool unconverged = false;
   // per-phase seconds of the current sweep (params->timing only)
   double t_mv = 0.0, t_solve = 0.0, t_split = 0.0, t_env = 0.0;
+  // excited states: projected previous states at the current bond
+  int northo = 0;
+  const double* pen_v = nullptr;  // northo vectors of the bond's length
 };
 
 // Adds the wall time of a scope to *acc when timing is on; the stream is
@@ -220,7 +230,15 @@ itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl,
   itn_tensor P = dense_t(4, dp, ITN_F64, const_cast<double*>(x));
   itn_tensor O = dense_t(4, dp, ITN_F64, y);
   c.matvecs++;
-  return itn_heff_apply(c.h, &L, &W1, &W2, &R, &P, 1, &O, (itn_prec)prec, c.s);
+  ITN_TRY(itn_heff_apply(c.h, &L, &W1, &W2, &R, &P, 1, &O, (itn_prec)prec, c.s));
+  if (c.northo > 0) {  // + weight * sum_j |v_j><v_j| x  (Sec. 7.2 energy penalty)
+    const int64_t n = cl * d * d * cr;
+    ITN_TRY(c.m->partial.ensure(c.h, (size_t)c.northo * dot_blocks(n) * 8));
+    ITN_TRY(c.m->odots.ensure(c.h, (size_t)c.northo * 8 + 8));
+    ITN_HIP(c.h, multi_dot(c.pen_v, n, c.northo, x, n, c.m->partial.d(), c.m->odots.d(), c.s));
+    ITN_HIP(c.h, lincomb_dev(c.pen_v, n, c.northo, c.m->odots.d(), c.p->weight, y, n, c.s));
+  }
+  return ITN_OK;
 }
 
 // <V_j, w> for j < k, to host.
@@ -477,6 +495,50 @@ itn_status boundary(Ctx& c, DBuf& b, int channel) {
   return ITN_OK;
 }
 
+// Overlap environment steps and projected states of the excited-state sweep
+// (previous state phi with bonds clp, crp; psi's site A with cl, cr).
+// Left:  out[b', b]  = sum_{a', s} A[a', s, b'] sum_a LO[a', a] B[a, s, b]
+itn_status ov_left(Ctx& c, const double* LO, const double* A, const double* B, int64_t cl, int64_t cr,
+                   int64_t clp, int64_t crp, double* out) {
+  itn_mps* m = c.m;
+  const int64_t d = m->d;
+  // ot1 holds Bt [(s b)][a], then Tt [b][(a' s)]
+  ITN_TRY(m->ot1.ensure(c.h, (size_t)std::max(d * crp * clp, cl * d * crp) * 8 + 8));
+  ITN_TRY(m->ot2.ensure(c.h, (size_t)(cl * d * crp) * 8 + 8));
+  ITN_TRY(m->ot3.ensure(c.h, (size_t)(cr * cl * d) * 8 + 8));
+  ITN_HIP(c.h, transpose64(B, m->ot1.d(), clp, d * crp, c.s));                       // Bt[(s b)][a]
+  ITN_HIP(c.h, gemm64(LO, clp, m->ot1.d(), clp, m->ot2.d(), d * crp, cl, d * crp, clp, c.s));  // T[a'][(s b)]
+  ITN_HIP(c.h, transpose64(m->ot2.d(), m->ot1.d(), cl * d, crp, c.s));              // Tt[b][(a' s)]
+  ITN_HIP(c.h, transpose64(A, m->ot3.d(), cl * d, cr, c.s));                        // At[b'][(a' s)]
+  ITN_HIP(c.h, gemm64(m->ot3.d(), cl * d, m->ot1.d(), cl * d, out, crp, cr, crp, cl * d, c.s));
+  return ITN_OK;
+}
+// Right: out[a', a] = sum_{s, b'} A[a', s, b'] sum_b RO[b', b] B[a, s, b]
+itn_status ov_right(Ctx& c, const double* RO, const double* A, const double* B, int64_t cl, int64_t cr,
+                    int64_t clp, int64_t crp, double* out) {
+  itn_mps* m = c.m;
+  const int64_t d = m->d;
+  ITN_TRY(m->ot1.ensure(c.h, (size_t)(clp * d * cr) * 8 + 8));
+  ITN_HIP(c.h, gemm64(B, crp, RO, crp, m->ot1.d(), cr, clp * d, cr, crp, c.s));     // U[(a s)][b']
+  ITN_HIP(c.h, gemm64(A, d * cr, m->ot1.d(), d * cr, out, clp, cl, clp, d * cr, c.s));
+  return ITN_OK;
+}
+// v[a', s1, s2, b'] = sum LO[a', a] B1[a, s1, m] B2[m, s2, b] RO[b', b]
+itn_status ov_project(Ctx& c, const double* LO, const double* B1, const double* B2, const double* RO,
+                      int64_t cl, int64_t cr, int64_t clp, int64_t mp, int64_t crp, double* out) {
+  itn_mps* m = c.m;
+  const int64_t d = m->d;
+  ITN_TRY(m->ot1.ensure(c.h, (size_t)std::max(d * mp * clp, d * crp * mp) * 8 + 8));
+  ITN_TRY(m->ot2.ensure(c.h, (size_t)(cl * d * mp) * 8 + 8));
+  ITN_TRY(m->ot3.ensure(c.h, (size_t)(cl * d * d * crp) * 8 + 8));
+  ITN_HIP(c.h, transpose64(B1, m->ot1.d(), clp, d * mp, c.s));                      // B1t[(s1 m)][a]
+  ITN_HIP(c.h, gemm64(LO, clp, m->ot1.d(), clp, m->ot2.d(), d * mp, cl, d * mp, clp, c.s));  // P1[(a' s1)][m]
+  ITN_HIP(c.h, transpose64(B2, m->ot1.d(), mp, d * crp, c.s));                      // B2t[(s2 b)][m]
+  ITN_HIP(c.h, gemm64(m->ot2.d(), mp, m->ot1.d(), mp, m->ot3.d(), d * crp, cl * d, d * crp, mp, c.s));
+  ITN_HIP(c.h, gemm64(m->ot3.d(), crp, RO, crp, out, cr, cl * d * d, cr, crp, c.s));
+  return ITN_OK;
+}
+
 // One bond: form psi, eigensolve, split, extend the environment.
 itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, double* energy,
                      double* trunc) {
@@ -498,6 +560,15 @@ itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, do
     ITN_TRY(m->Rp.ensure(c.h, (size_t)cr * w * cr * 4 + 256));
     ITN_HIP(c.h, cast(D_F64, m->Lenv[i].p, dt, m->Lp.p, cl * w * cl, c.s));
     ITN_HIP(c.h, cast(D_F64, m->Renv[i + 2].p, dt, m->Rp.p, cr * w * cr, c.s));
+  }
+  if (c.northo > 0) {  // previous states seen from this bond
+    ITN_TRY(m->ovec.ensure(c.h, (size_t)c.northo * n * 8));
+    for (int j = 0; j < c.northo; ++j) {
+      const itn_mps* o = c.p->ortho[j];
+      ITN_TRY(ov_project(c, m->OL[j][i].d(), o->site[i].d(), o->site[i + 1].d(), m->OR[j][i + 2].d(), cl,
+                         cr, o->bond[i], o->bond[i + 1], o->bond[i + 2], m->ovec.d() + (size_t)j * n));
+    }
+    c.pen_v = m->ovec.d();
   }
   const double tol = c.p->eig_tol > 0 ? c.p->eig_tol : 1e-10;
   const int maxiter = c.p->maxiter > 0 ? c.p->maxiter : 100;
@@ -525,6 +596,20 @@ itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, do
   PhaseTimer pt(c, &c.t_env);
   if (to_right) ITN_TRY(env_step(c, i, true));
   else ITN_TRY(env_step(c, i + 1, false));
+  for (int j = 0; j < c.northo; ++j) {  // overlap environments follow the new sites
+    const itn_mps* o = c.p->ortho[j];
+    const int k = to_right ? i : i + 1;
+    const int64_t ocl = m->bond[k], ocr = m->bond[k + 1], pcl = o->bond[k], pcr = o->bond[k + 1];
+    if (to_right) {
+      ITN_TRY(m->OL[j][k + 1].ensure(c.h, (size_t)(ocr * pcr) * 8));
+      ITN_TRY(ov_left(c, m->OL[j][k].d(), m->site[k].d(), o->site[k].d(), ocl, ocr, pcl, pcr,
+                      m->OL[j][k + 1].d()));
+    } else {
+      ITN_TRY(m->OR[j][k].ensure(c.h, (size_t)(ocl * pcl) * 8));
+      ITN_TRY(ov_right(c, m->OR[j][k + 1].d(), m->site[k].d(), o->site[k].d(), ocl, ocr, pcl, pcr,
+                       m->OR[j][k].d()));
+    }
+  }
   return ITN_OK;
 }
 
@@ -630,6 +715,35 @@ itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
     for (int i = N - 1; i >= 2; --i) ITN_TRY(env_step(c, i, false));
     mps->envs = true;
     mps->mpo_w = mpo->w;
+  }
+  if (p->northo < 0 || (p->northo > 0 && !p->ortho))
+    return fail(h, ITN_E_ARG, "northo > 0 needs the ortho array");
+  c.northo = p->northo;
+  if (c.northo > 0) {
+    for (int j = 0; j < c.northo; ++j) {
+      const itn_mps* o = p->ortho[j];
+      if (!o || o == mps) return fail(h, ITN_E_ARG, "ortho[%d] must be another MPS", j);
+      if (o->N != N || o->d != mps->d)
+        return fail(h, ITN_E_SHAPE, "ortho[%d] (N=%d, d=%d) does not match the MPS", j, o->N, o->d);
+    }
+    for (auto* v : {&mps->OL, &mps->OR}) {
+      for (auto& row : *v)
+        for (auto& b : row) b.release();
+      v->assign(c.northo, std::vector<DBuf>(N + 1));
+    }
+    const double one = 1.0;
+    for (int j = 0; j < c.northo; ++j) {
+      const itn_mps* o = p->ortho[j];
+      ITN_TRY(mps->OL[j][0].ensure(h, 8));
+      ITN_TRY(mps->OR[j][N].ensure(h, 8));
+      ITN_HIP(h, hipMemcpy(mps->OL[j][0].p, &one, 8, hipMemcpyHostToDevice));
+      ITN_HIP(h, hipMemcpy(mps->OR[j][N].p, &one, 8, hipMemcpyHostToDevice));
+      for (int k = N - 1; k >= 1; --k) {
+        ITN_TRY(mps->OR[j][k].ensure(h, (size_t)mps->bond[k] * o->bond[k] * 8));
+        ITN_TRY(ov_right(c, mps->OR[j][k + 1].d(), mps->site[k].d(), o->site[k].d(), mps->bond[k],
+                         mps->bond[k + 1], o->bond[k], o->bond[k + 1], mps->OR[j][k].d()));
+      }
+    }
   }
   if (res) res->sweeps_done = 0;
   double prevE = 0.0;

@@ -280,6 +280,25 @@ hipError_t lincomb(const double* V, int64_t ldv, int k, const double* c, double 
   return hipGetLastError();
 }
 
+// y += scale * sum_j c[j] * V_j with the coefficients in device memory.
+__global__ void lincomb_dev_kernel(const double* __restrict__ V, int64_t ldv, int k,
+                                   const double* __restrict__ c, double scale, double* __restrict__ y,
+                                   int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += c[j] * V[(int64_t)j * ldv + i];
+    y[i] += scale * acc;
+  }
+}
+hipError_t lincomb_dev(const double* V, int64_t ldv, int k, const double* c, double scale, double* y,
+                       int64_t n, hipStream_t s) {
+  if (n == 0 || k == 0) return hipSuccess;
+  hipLaunchKernelGGL(lincomb_dev_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, V, ldv, k, c,
+                     scale, y, n);
+  return hipGetLastError();
+}
+
 __global__ void scale_kernel(double* x, double a, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

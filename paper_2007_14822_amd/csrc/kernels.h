@@ -212,6 +212,9 @@ hipError_t multi_dot(const double* V, int64_t ldv, int k, const double* w, int64
 hipError_t lincomb(const double* V, int64_t ldv, int k, const double* c, double beta, double* y,
                    int64_t n, hipStream_t s);
 hipError_t scale(double* x, double a, int64_t n, hipStream_t s);
+// y += scale * sum_j c[j] * V_j, coefficients c (k of them) in device memory.
+hipError_t lincomb_dev(const double* V, int64_t ldv, int k, const double* c, double scale, double* y,
+                       int64_t n, hipStream_t s);
 hipError_t fill(void* x, int dtype, double v, int64_t n, hipStream_t s);
 
 }  // namespace itn

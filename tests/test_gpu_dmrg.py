@@ -116,3 +116,44 @@ def test_sweep_phase_timing(h):
         assert sum(parts) <= r["seconds"] * 1.01 + 1e-3
     assert "t_matvec" not in recs[0]
     assert abs(recs_t[-1]["energy"] - recs[-1]["energy"]) <= 1e-12 * abs(recs[-1]["energy"])
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_excited_state_by_energy_penalty(h, prec):
+    """Sec. 7.2: the ground state found first, the next sweep with its
+    projector times a penalty finds the first excited level (ED, N = 8), and
+    a third with both projectors the level after."""
+    N = 8
+    ev = np.linalg.eigvalsh(ed.heisenberg_dense(N))
+    levels = [ev[0]]
+    for e in ev[1:]:
+        if e > levels[-1] + 1e-8:
+            levels.append(e)
+    kw = dict(prec=prec, eig_tol=1e-12, krylovdim=12, maxiter=400)
+    sweeps = [(16, 1e-14)] * 6
+    mpo = h.mpo(inp.heisenberg_mpo(N))
+    gs = h.mps(inp.random_product_state(N, 2, np.random.default_rng(1)))
+    r0 = h.dmrg_sweep(gs, mpo, sweeps, **kw)
+    assert abs(r0[-1]["energy"] - levels[0]) < 1e-9
+    x1 = h.mps(inp.random_product_state(N, 2, np.random.default_rng(2)))
+    r1 = h.dmrg_sweep(x1, mpo, sweeps, ortho=[gs], weight=10.0, **kw)
+    assert abs(r1[-1]["energy"] - levels[1]) < 1e-8, (prec, r1[-1]["energy"], levels[:3])
+    v0 = hf.mps_to_dense(h.mps_sites(gs)).ravel()
+    v1 = hf.mps_to_dense(h.mps_sites(x1)).ravel()
+    assert abs(v0 @ v1) < 1e-5
+    # the oracle's penalty DMRG from the same states agrees
+    ref = odmrg.dmrg(inp.heisenberg_mpo(N), inp.random_product_state(N, 2, np.random.default_rng(2)),
+                     sweeps, ortho=[h.mps_sites(gs)], weight=10.0)
+    assert abs(ref.energy - r1[-1]["energy"]) < 1e-8
+
+
+def test_excited_state_rejects_bad_ortho(h):
+    mpo = h.mpo(inp.heisenberg_mpo(6))
+    a = h.mps(inp.random_product_state(6, 2, np.random.default_rng(1)))
+    b = h.mps(inp.random_product_state(7, 2, np.random.default_rng(1)))
+    with pytest.raises(itn.ItnError) as e:
+        h.dmrg_sweep(a, mpo, [(8, 0.0)], ortho=[b], weight=1.0)
+    assert e.value.name == "ITN_E_SHAPE"
+    with pytest.raises(itn.ItnError) as e:
+        h.dmrg_sweep(a, mpo, [(8, 0.0)], ortho=[a], weight=1.0)
+    assert e.value.name == "ITN_E_ARG"
