@@ -186,6 +186,48 @@ def traffic_record(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def ttgt(tensordot, L, W1, W2, R, psi):
+    """H_eff psi as the paper's TTGT contraction (Sec. 9.4): every pairwise
+    contraction a permutation plus one library GEMM (tensordot).  A comparator
+    only: W1[m0, m1, s1', s1], W2[m1, m2, s2', s2], R[b', m2, b]."""
+    T1 = tensordot(L, psi, ([2], [0]))              # [a', m0, s1, s2, b]
+    T2 = tensordot(T1, W1, ([1, 2], [0, 3]))        # [a', s2, b, m1, s1']
+    T3 = tensordot(T2, W2, ([1, 3], [3, 0]))        # [a', b, s1', m2, s2']
+    T4 = tensordot(T3, R, ([1, 3], [2, 1]))         # [a', s1', s2', b']
+    return T4
+
+
+def ttgt_gpu(torch, L, W1, W2, R, psi, flops, steps):
+    """TTGT with PyTorch FP64 (rocBLAS/hipBLASLt DGEMMs and permute copies)."""
+    W1t = torch.as_tensor(W1, device=L.device)
+    W2t = torch.as_tensor(W2, device=L.device)
+    td = lambda a, b, dims: torch.tensordot(a, b, dims=dims)
+    y = ttgt(td, L, W1t, W2t, R, psi)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        y = ttgt(td, L, W1t, W2t, R, psi)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"ms_per_step": ms, "tflops": flops / (ms * 1e-3) / 1e12, "steps": steps,
+            "method": "torch.tensordot chain L, W1, W2, R in FP64 (permute + library GEMM each)"}
+
+
+def ttgt_cpu(np, L, W1, W2, R, psi, flops):
+    """TTGT on the host BLAS with every core (numpy tensordot, FP64), one matvec."""
+    import os
+    Lh, Rh, ph = L.cpu().numpy(), R.cpu().numpy(), psi.cpu().numpy()
+    td = lambda a, b, dims: np.tensordot(a, b, axes=dims)
+    t0 = time.perf_counter()
+    ttgt(td, Lh, W1, W2, Rh, ph)
+    dt = time.perf_counter() - t0
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "seconds": dt,
+            "cores": len(os.sched_getaffinity(0)),
+            "method": "numpy.tensordot chain in FP64 on the host BLAS, one full matvec"}
+
+
 def cpu_baseline(L, W1, W2, R, psi, chi, d, w, budget_s):
     """The oracle (plain einsum, one thread) on a bounded sample: the first k
     output rows a' of the same matvec; throughput scaled by k/chi."""
@@ -438,6 +480,11 @@ def main():
     }
     if "f64" in results and head != "f64":
         line["speedup_vs_fp64_gpu"] = results["f64"]["ms_per_step"] / r["ms_per_step"]
+    if not args.only:
+        log("[bench] TTGT comparators (library GEMMs + permutes, FP64)")
+        line["ttgt_gpu_f64"] = ttgt_gpu(torch, L64, W1, W2, R64, psi, flops, args.steps // 4 + 2)
+        if not args.no_cpu_baseline:
+            line["ttgt_cpu_f64"] = ttgt_cpu(np, L64, W1, W2, R64, psi, flops)
     if not args.no_qn and not args.only:
         qn = {}
         for which, nv in (("c3", 1), ("c4", 4), ("c4w38", 4), ("c4z4", 4)):
