@@ -26,8 +26,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = ("H_eff·psi TFLOP/s (% MFMA peak), mixed vs FP64; DMRG sweep time at 1e-8 ΔE")
 PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
-KERNEL_SOURCES = ["paper_2007_14822_amd/csrc/gemm_core.h", "paper_2007_14822_amd/csrc/gemm.hip",
-                  "paper_2007_14822_amd/csrc/heff_fused.hip"]
+# the sources heff_stage1_fused is compiled from (its HBM-traffic record is
+# valid only for this code)
+KERNEL_SOURCES = ["paper_2007_14822_amd/csrc/heff_fused.hip", "paper_2007_14822_amd/csrc/gemm_core.h",
+                  "paper_2007_14822_amd/csrc/common.h", "paper_2007_14822_amd/csrc/kernels.h"]
 
 
 def log(*a):
@@ -363,6 +365,8 @@ def time_qn(h, torch, np, inp, which, prec, nv, steps, warmup):
             "flop_per_apply": info["flops"], "out_blocks": info["out_nblocks"],
             "stage1_groups": info["n_groups_stage1"], "stage4_segments": info["n_pairs_stage4"],
             "plan_seconds": tplan, "nv": nv,
+            "launch_modes": [info["mode_stage1"], info["mode_stage4"]],
+            "wstage_tile": info["wstage_tile"],
             "kernels": {k: {"avg_ms": v[0] / max(1, v[1]), "launches": v[1]} for k, v in rep.items()}}, out
 
 

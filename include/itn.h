@@ -215,6 +215,10 @@ typedef struct {
   int64_t x_elems;         /* stage-1 intermediate X, elements per vector         */
   int64_t z_elems;         /* W-stage output Z (stage-4 operand), per vector      */
   double flops_wstage;     /* 2 * W12 terms * positions, x nv (not in flops)      */
+  int32_t mode_stage1;     /* grouped launch modes of stages 1 and 4 (0..5, see   */
+  int32_t mode_stage4;     /* itn_qn_heff_apply); -1 before the first apply       */
+  int32_t wstage_tile;     /* W-stage kernel: 0 streaming, else LDS-staged with   */
+                           /* this many positions per block; -1 before the first apply */
 } itn_plan_info;
 itn_status itn_plan_query(const itn_plan* plan, itn_plan_info* info);
 /* Copy the output block table: block_sec[out_nblocks*4], block_off[out_nblocks]. */
@@ -237,8 +241,11 @@ itn_status itn_qn_allowed_blocks(itn_handle* h, const itn_tensor* t, int64_t* nb
  * The first apply also picks, per grouped stage, the fastest launch mode by
  * timing them on the real operands (0: 64x64 tiles; 1: 128x128; 2, 3: block
  * products with both extents >= 192 on 256-row direct-to-LDS tiles, the rest
- * on 64 / 128).  The choice is cached per operand structure (in the file
- * ITN_AUTOTUNE_CACHE if set); ITN_QN_TILE_MODE="m1,m4" fixes it instead. */
+ * on 64 / 128; 4: as 2, with the remaining products of both extents >= 96
+ * on 128x128 direct-to-LDS tiles; 5: products of both extents >= 96 on
+ * 128x128 direct-to-LDS tiles, the rest on 64).  The choice is cached per
+ * operand structure (in the file ITN_AUTOTUNE_CACHE if set);
+ * ITN_QN_TILE_MODE="m1,m4" (modes 0..5) fixes it instead. */
 itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* plan, const itn_tensor* L,
                              const itn_tensor* R, const itn_tensor* psi, itn_tensor* out,
                              void* hip_stream);

@@ -255,13 +255,31 @@ struct itn_plan {
   std::vector<GSeg> s1, s4;
   // Tile lists of a grouped stage.  all[c]: every problem with the
   // register-staged tile c (0: 64x64, 1: 128x128); big: the problems large
-  // enough for the direct-to-LDS 8-wave tile; rest[c]: the others with tile c.
-  // Launch modes: 0, 1 = all[mode]; 2, 3 = big then rest[mode - 2].
+  // enough for the 8-wave 256-row direct tile; rest[c]: the others with tile
+  // c; mid: problems with both extents >= 96 that are not big, on the
+  // 4-wave 128x128 direct tile, rest_mid: the remaining ones (64x64);
+  // midall: every problem with both extents >= 96 on the 128x128 direct
+  // tile, rest_midall: the others (64x64).  Launch modes: 0, 1 = all[mode];
+  // 2, 3 = big then rest[mode - 2]; 4 = big, mid, rest_mid; 5 = midall,
+  // rest_midall.
+  static constexpr int kModes = 6;
   struct Tiles {
-    std::vector<GTile> all[2], big, rest[2];
+    std::vector<GTile> all[2], big, rest[2], mid, rest_mid, midall, rest_midall;
     GTile *d_all[2] = {nullptr, nullptr}, *d_big = nullptr, *d_rest[2] = {nullptr, nullptr};
+    GTile *d_mid = nullptr, *d_rest_mid = nullptr, *d_midall = nullptr, *d_rest_midall = nullptr;
     size_t count(int mode) const {
-      return mode < 2 ? all[mode].size() : big.size() + rest[mode - 2].size();
+      switch (mode) {
+        case 0: case 1: return all[mode].size();
+        case 2: case 3: return big.size() + rest[mode - 2].size();
+        case 4: return big.size() + mid.size() + rest_mid.size();
+        default: return midall.size() + rest_midall.size();
+      }
+    }
+    bool usable(int mode) const {
+      if (mode == 2 || mode == 3) return !big.empty();
+      if (mode == 4) return !big.empty() && !mid.empty();
+      if (mode == 5) return !midall.empty();
+      return true;
     }
   } tl1, tl4;
   std::vector<QnTBlock> tb;
@@ -376,16 +394,25 @@ template <typename TL>
 void build_tiles(TL& tl, const std::vector<GProb>& probs, const std::vector<GSeg>& segs, int prec,
                  int dtype) {
   const int e16 = 16 / dtype_size(dtype);
-  std::vector<char> all(probs.size(), 1), big(probs.size(), 0), rest(probs.size(), 1);
-  for (size_t p = 0; p < probs.size(); ++p) {
+  const size_t np = probs.size();
+  std::vector<char> all(np, 1), big(np, 0), rest(np, 1), mid(np, 0), rest_mid(np, 1), midall(np, 0),
+      rest_midall(np, 1);
+  for (size_t p = 0; p < np; ++p) {
     const GProb& pr = probs[p];
-    bool ok = pr.M >= 192 && pr.N >= 192;
-    for (int s = 0; ok && s < pr.nseg; ++s) {
+    bool aligned = true;
+    for (int s = 0; aligned && s < pr.nseg; ++s) {
       const GSeg& g = segs[pr.seg0 + s];
-      ok = g.a_off % e16 == 0 && g.b_off % e16 == 0 && g.lda % e16 == 0 && g.ldb % e16 == 0;
+      aligned = g.a_off % e16 == 0 && g.b_off % e16 == 0 && g.lda % e16 == 0 && g.ldb % e16 == 0;
     }
-    big[p] = ok;
-    rest[p] = !ok;
+    // both extents at least 3/4 of the tile
+    const bool b = aligned && pr.M >= 192 && pr.N >= 192;
+    const bool m = aligned && pr.M >= 96 && pr.N >= 96;
+    big[p] = b;
+    rest[p] = !b;
+    mid[p] = m && !b;
+    rest_mid[p] = !m;
+    midall[p] = m;
+    rest_midall[p] = !m;
   }
   for (int c = 0; c < 2; ++c) {
     const int t = grouped_tile_rows(c);
@@ -393,6 +420,10 @@ void build_tiles(TL& tl, const std::vector<GProb>& probs, const std::vector<GSeg
     tl.rest[c] = make_tiles(probs, segs, t, t, rest);
   }
   tl.big = make_tiles(probs, segs, grouped_tile_rows(2), grouped_tile_cols(prec, 2), big);
+  tl.mid = make_tiles(probs, segs, 128, 128, mid);
+  tl.rest_mid = make_tiles(probs, segs, 64, 64, rest_mid);
+  tl.midall = make_tiles(probs, segs, 128, 128, midall);
+  tl.rest_midall = make_tiles(probs, segs, 64, 64, rest_midall);
 }
 
 itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t,
@@ -728,7 +759,8 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
       add(tl->all[c].size() * sizeof(GTile));
       add(tl->rest[c].size() * sizeof(GTile));
     }
-    add(tl->big.size() * sizeof(GTile));
+    for (auto* v : {&tl->big, &tl->mid, &tl->rest_mid, &tl->midall, &tl->rest_midall})
+      add(v->size() * sizeof(GTile));
   }
   add(pl.tb.size() * sizeof(QnTBlock));
   add(pl.tbi.size() * sizeof(int32_t));
@@ -758,6 +790,10 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
       ITN_HIP(h, put(tl->d_rest[c], tl->rest[c]));
     }
     ITN_HIP(h, put(tl->d_big, tl->big));
+    ITN_HIP(h, put(tl->d_mid, tl->mid));
+    ITN_HIP(h, put(tl->d_rest_mid, tl->rest_mid));
+    ITN_HIP(h, put(tl->d_midall, tl->midall));
+    ITN_HIP(h, put(tl->d_rest_midall, tl->rest_midall));
   }
   ITN_HIP(h, put(pl.dtb, pl.tb));
   ITN_HIP(h, put(pl.dtbi, pl.tbi));
@@ -805,14 +841,24 @@ hipError_t stage_launch(itn_plan& pl, int stage, int mode, hipStream_t s) {
   const int cdt = s1 ? pl.xt : pl.out_dt;
   const int64_t a_bs = s1 ? 0 : pl.Z_elems, b_bs = s1 ? pl.psiT_elems : 0;
   const int64_t c_bs = s1 ? pl.X_elems : pl.out_elems;
-  if (mode < 2)
-    return gemm_grouped(pl.prec, cdt, mode, b, P, S, T.d_all[mode], (int64_t)T.all[mode].size(), a_bs,
-                        b_bs, c_bs, pl.nv, MAX_WG, s);
-  hipError_t e = gemm_grouped(pl.prec, cdt, 2, b, P, S, T.d_big, (int64_t)T.big.size(), a_bs, b_bs,
-                              c_bs, pl.nv, MAX_WG, s);
-  if (e != hipSuccess) return e;
-  return gemm_grouped(pl.prec, cdt, mode - 2, b, P, S, T.d_rest[mode - 2],
-                      (int64_t)T.rest[mode - 2].size(), a_bs, b_bs, c_bs, pl.nv, MAX_WG, s);
+  auto run = [&](int cfg, const GTile* t, size_t n) {
+    return gemm_grouped(pl.prec, cdt, cfg, b, P, S, t, (int64_t)n, a_bs, b_bs, c_bs, pl.nv, MAX_WG, s);
+  };
+  hipError_t e = hipSuccess;
+  switch (mode) {
+    case 0: case 1: return run(mode, T.d_all[mode], T.all[mode].size());
+    case 2: case 3:
+      if ((e = run(2, T.d_big, T.big.size())) != hipSuccess) return e;
+      return run(mode - 2, T.d_rest[mode - 2], T.rest[mode - 2].size());
+    case 4:
+      if ((e = run(2, T.d_big, T.big.size())) != hipSuccess) return e;
+      if ((e = run(3, T.d_mid, T.mid.size())) != hipSuccess) return e;
+      return run(0, T.d_rest_mid, T.rest_mid.size());
+    case 5:
+      if ((e = run(3, T.d_midall, T.midall.size())) != hipSuccess) return e;
+      return run(0, T.d_rest_midall, T.rest_midall.size());
+  }
+  return hipErrorInvalidValue;
 }
 
 itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int cfg4) {
@@ -860,21 +906,23 @@ itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
   // ITN_QN_TILE_MODE="m1,m4" fixes the launch modes (tests and experiments)
   if (const char* fm = std::getenv("ITN_QN_TILE_MODE")) {
     int a = -1, b = -1;
-    if (std::sscanf(fm, "%d,%d", &a, &b) == 2 && a >= 0 && a < 4 && b >= 0 && b < 4) {
+    if (std::sscanf(fm, "%d,%d", &a, &b) == 2 && a >= 0 && a < itn_plan::kModes && b >= 0 &&
+        b < itn_plan::kModes) {
       pl.cfg1 = a;
       pl.cfg4 = b;
       if (wforce < 0) pl.wsel = 0;
       pl.tuned = true;
       return ITN_OK;
     }
-    return fail(h, ITN_E_ARG, "ITN_QN_TILE_MODE must be \"m1,m4\" with modes 0..3");
+    return fail(h, ITN_E_ARG, "ITN_QN_TILE_MODE must be \"m1,m4\" with modes 0..5");
   }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load();
     auto it = g_tune.find(pl.sig_hash);
-    if (it != g_tune.end() && it->second[0] >= 0 && it->second[0] < 4 && it->second[1] >= 0 &&
-        it->second[1] < 4 && it->second[2] >= 0 && it->second[2] < 4 && pl.wok[it->second[2]]) {
+    if (it != g_tune.end() && it->second[0] >= 0 && it->second[0] < itn_plan::kModes &&
+        it->second[1] >= 0 && it->second[1] < itn_plan::kModes && it->second[2] >= 0 &&
+        it->second[2] < 4 && pl.wok[it->second[2]]) {
       pl.cfg1 = it->second[0];
       pl.cfg4 = it->second[1];
       if (wforce < 0) pl.wsel = it->second[2];
@@ -886,9 +934,9 @@ itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
   ITN_HIP(h, hipEventCreate(&e0));
   ITN_HIP(h, hipEventCreate(&e1));
   float best1 = 1e30f, best4 = 1e30f;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < itn_plan::kModes; ++c) {
     for (int stage = 0; stage < 2; ++stage) {
-      if (c >= 2 && (stage == 0 ? pl.tl1 : pl.tl4).big.empty()) continue;
+      if (!(stage == 0 ? pl.tl1 : pl.tl4).usable(c)) continue;
       float tot = 0.f;
       for (int rep = 0; rep < 3; ++rep) {
         ITN_HIP(h, hipEventRecord(e0, s));
@@ -1022,6 +1070,9 @@ itn_status itn_plan_query(const itn_plan* pl, itn_plan_info* info) {
   info->x_elems = pl->X_elems;
   info->z_elems = pl->Z_elems;
   info->flops_wstage = pl->flops_w * pl->nv;
+  info->mode_stage1 = pl->tuned ? pl->cfg1 : -1;
+  info->mode_stage4 = pl->tuned ? pl->cfg4 : -1;
+  info->wstage_tile = pl->tuned ? itn_plan::kWCand[pl->wsel] : -1;
   return ITN_OK;
 }
 

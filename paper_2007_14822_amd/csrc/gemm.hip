@@ -262,6 +262,7 @@ static hipError_t grouped_cfg(int cfg, const GBases* bases, const GProb* probs, 
     if constexpr (P == P_F64) return launch_grouped_direct<P, 256, 128, 2, 4, TOut>(ITN_GROUPED_ARGS);
     else return launch_grouped_direct<P, 256, 256, 2, 4, TOut>(ITN_GROUPED_ARGS);
   }
+  if (cfg == 3) return launch_grouped_direct<P, 128, 128, 2, 2, TOut>(ITN_GROUPED_ARGS);
   if (cfg == 1) return launch_grouped<P, 128, 128, TOut>(ITN_GROUPED_ARGS);
   return launch_grouped<P, 64, 64, TOut>(ITN_GROUPED_ARGS);
 }
@@ -291,7 +292,7 @@ hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const GBases* bases
 }
 #undef ITN_GROUPED_ARGS
 
-int grouped_tile_rows(int tile_cfg) { return tile_cfg == 2 ? 256 : tile_cfg == 1 ? 128 : 64; }
+int grouped_tile_rows(int tile_cfg) { return tile_cfg == 2 ? 256 : (tile_cfg == 1 || tile_cfg == 3) ? 128 : 64; }
 int grouped_tile_cols(int prec, int tile_cfg) {
   if (tile_cfg == 2) return prec == P_F64 ? 128 : 256;
   return grouped_tile_rows(tile_cfg);

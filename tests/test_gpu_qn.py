@@ -126,7 +126,7 @@ def test_qn_launch_modes_parity(h, monkeypatch, prec):
     few hundred states (ragged M, N, K: the 256-tile path with K tails)."""
     ops, W1, W2 = U.large_u1()
     ref = _ref(ops, [ops[4]])
-    for mode in ("0,0", "1,1", "2,2", "3,3", "2,3", "3,2"):
+    for mode in ("0,0", "1,1", "2,2", "3,3", "2,3", "3,2", "4,4", "5,5", "4,5"):
         monkeypatch.setenv("ITN_QN_TILE_MODE", mode)
         plan, _, got = _run(h, ops, W1, W2, prec, 1, [ops[4]])
         assert plan.info()["n_tiles"] > 0
@@ -144,7 +144,7 @@ def test_zn_heff_parity(h, prec, nv):
     assert rel_err(got, _ref(ops, psis)) <= TOL[prec]
 
 
-@pytest.mark.parametrize("mode", ["0,0", "2,3"])
+@pytest.mark.parametrize("mode", ["0,0", "2,3", "4,5"])
 def test_zn_large_sectors_parity(h, monkeypatch, mode):
     """U(1) x Z_4 sectors of 100-300 states (the 256-row tiles, K tails)."""
     monkeypatch.setenv("ITN_QN_TILE_MODE", mode)
