@@ -27,9 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = ("H_eff·psi TFLOP/s (% MFMA peak), mixed vs FP64; DMRG sweep time at 1e-8 ΔE")
 PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
 # the sources heff_stage1_fused is compiled from (its HBM-traffic record is
-# valid only for this code)
+# valid only for this code); of the shared declarations header only the
+# kernel's argument struct counts
 KERNEL_SOURCES = ["paper_2007_14822_amd/csrc/heff_fused.hip", "paper_2007_14822_amd/csrc/gemm_core.h",
-                  "paper_2007_14822_amd/csrc/common.h", "paper_2007_14822_amd/csrc/kernels.h"]
+                  "paper_2007_14822_amd/csrc/common.h"]
+KERNEL_DECLS = ("paper_2007_14822_amd/csrc/kernels.h", "struct HeffFusedArgs")
 
 
 def log(*a):
@@ -42,6 +44,12 @@ def kernel_source_hash() -> str:
         fp = os.path.join(ROOT, p)
         if os.path.exists(fp):
             hsh.update(open(fp, "rb").read())
+    fp = os.path.join(ROOT, KERNEL_DECLS[0])
+    if os.path.exists(fp):
+        text = open(fp, "rb").read().decode()
+        i = text.find(KERNEL_DECLS[1])
+        if i >= 0:
+            hsh.update(text[i:text.index("};", i)].encode())
     return hsh.hexdigest()[:16]
 
 
