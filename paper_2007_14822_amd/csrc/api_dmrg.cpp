@@ -66,6 +66,7 @@ struct itn_mps {
   // driver scratch
   DBuf psi, tmp, rho, evec, eval, einfo, V, AV, Lp, Rp, partial, dots, ev_host_stage;
   DBuf ovec, ot1, ot2, ot3, odots;
+  DBuf hh, hscr;  // bond split: Householder reflectors [n][n]; tridiagonal and barrier scratch
   ~itn_mps() {
     for (auto& b : site) b.release();
     for (auto& b : Lenv) b.release();
@@ -74,7 +75,7 @@ struct itn_mps {
       for (auto& row : *v)
         for (auto& b : row) b.release();
     for (DBuf* b : {&psi, &tmp, &rho, &evec, &eval, &einfo, &V, &AV, &Lp, &Rp, &partial, &dots,
-                    &ev_host_stage, &ovec, &ot1, &ot2, &ot3, &odots})
+                    &ev_host_stage, &ovec, &ot1, &ot2, &ot3, &odots, &hh, &hscr})
       b->release();
   }
 };
@@ -329,21 +330,32 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
       break;
     }
     if (it + 1 >= maxiter) break;
-    // Gram-Schmidt, two passes
-    for (int a = 0; a < k; ++a) tmp[a] = -tmp[a];
-    ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, r, n, c.s));
-    ITN_TRY(dots(c, V, n, k + 1, r, tmp.data()));  // (3)
-    double c2 = 0.0;
+    // Gram-Schmidt against V.  With V orthonormal the projected norm is
+    // r.r - |V^T r|^2; a second pass (and its reduction) is needed only when
+    // the projection removed much of r (Daniel-Gragg-Kaufman-Stewart test:
+    // kept norm below 1/sqrt(2)).  The Galerkin residual is orthogonal to V
+    // up to rounding, so one pass is the common case.
+    double p2 = 0.0;
     for (int a = 0; a < k; ++a) {
-      c2 += tmp[a] * tmp[a];
+      p2 += tmp[a] * tmp[a];
       tmp[a] = -tmp[a];
     }
-    const double t2 = tmp[k] - c2;
-    if (!(t2 > 1e-28 * std::max(1.0, r2))) {  // no new direction
-      conv = true;
-      break;
-    }
     ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, r, n, c.s));
+    double t2 = r2 - p2;
+    if (!(t2 > 0.5 * r2)) {
+      ITN_TRY(dots(c, V, n, k + 1, r, tmp.data()));  // (3) second pass
+      double c2 = 0.0;
+      for (int a = 0; a < k; ++a) {
+        c2 += tmp[a] * tmp[a];
+        tmp[a] = -tmp[a];
+      }
+      t2 = tmp[k] - c2;
+      if (!(t2 > 1e-28 * std::max(1.0, r2))) {  // no new direction
+        conv = true;
+        break;
+      }
+      ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, r, n, c.s));
+    }
     ITN_HIP(c.h, scale(r, 1.0 / std::sqrt(t2), n, c.s));
     ITN_TRY(heff(c, i, prec, r, AV + (size_t)k * n, cl, cr));
     ++k;
@@ -386,6 +398,16 @@ int truncation_keep(const std::vector<double>& p_desc, double cutoff, int maxdim
   return keep;
 }
 
+// ITN_EIG=library selects rocSOLVER's full symmetric eigensolver for every
+// bond split (comparison runs); default is the cooperative tridiagonalisation.
+bool use_coop_sytrd() {
+  static const bool v = [] {
+    const char* e = std::getenv("ITN_EIG");
+    return !(e && std::string(e) == "library");
+  }();
+  return v;
+}
+
 // Split psi [cl, d, d, cr] at bond i and store the new sites i, i+1.
 itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdim, double cutoff,
                  double* trunc) {
@@ -407,16 +429,69 @@ itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdi
   if (!rb) return fail(c.h, ITN_E_HIP, "rocblas handle creation failed");
   double* D = m->eval.d();
   double* E = D + n;
-  rocblas_status st = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
-                                       rho, (rocblas_int)n, D, E,
-                                       static_cast<rocblas_int*>(m->einfo.p));
-  if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd failed (%d)", (int)st);
   std::vector<double> ev(n);
   rocblas_int info = 0;
-  ITN_HIP(c.h, hipMemcpyAsync(ev.data(), D, n * 8, hipMemcpyDeviceToHost, c.s));
-  ITN_HIP(c.h, hipMemcpyAsync(&info, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
-  ITN_HIP(c.h, hipStreamSynchronize(c.s));
-  if (info != 0) return fail(c.h, ITN_E_NOT_CONVERGED, "rocsolver_dsyevd info=%d at bond %d", (int)info, i);
+  // Eigen-decomposition of rho.  Householder tridiagonalisation in one
+  // cooperative launch, the tridiagonal eigenproblem by rocSOLVER's divide
+  // and conquer, the kept eigenvectors back-transformed; the library's full
+  // symmetric solver where n does not fit (or ITN_EIG=library).
+  const int nwg = use_coop_sytrd() ? sytrd_coop_groups((int)n) : 0;
+  bool coop = nwg > 0;
+  double *hhV = nullptr, *tau = nullptr;
+  int* coop_err = nullptr;
+  if (coop) {
+    ITN_TRY(m->hh.ensure(c.h, (size_t)n * n * 8));
+    ITN_TRY(m->hscr.ensure(c.h, (size_t)(5 * n + 2 * nwg + 8) * 8));
+    hhV = m->hh.d();
+    double* scr = m->hscr.d();
+    tau = scr;
+    SytrdArgs sa{};
+    sa.A = rho;
+    sa.lda = n;
+    sa.n = (int)n;
+    sa.nwg = nwg;
+    sa.d = D;
+    sa.e = E;
+    sa.tau = tau;
+    sa.V = hhV;
+    sa.pub = scr + n;
+    sa.pbuf = scr + 3 * n;
+    sa.dots = scr + 5 * n;
+    sa.bar = reinterpret_cast<unsigned*>(scr + 5 * n + 2 * nwg);
+    sa.err = reinterpret_cast<int*>(scr + 5 * n + 2 * nwg + 1);
+    sa.spin_limit = (int64_t)1 << 24;
+    coop_err = sa.err;
+    if (sytrd_coop(sa, c.s) != hipSuccess) {  // e.g. no cooperative launch: library path
+      (void)hipGetLastError();
+      coop = false;
+    }
+  }
+  if (coop) {
+    // eigenvectors of T into rho's storage (column j: eigenvalue j, ascending)
+    rocblas_status st = rocsolver_dstedc(rb, rocblas_evect_tridiagonal, (rocblas_int)n, D, E, rho,
+                                         (rocblas_int)n, static_cast<rocblas_int*>(m->einfo.p));
+    if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dstedc failed (%d)", (int)st);
+    int err = 0;
+    ITN_HIP(c.h, hipMemcpyAsync(ev.data(), D, n * 8, hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipMemcpyAsync(&info, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipMemcpyAsync(&err, coop_err, sizeof(err), hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipStreamSynchronize(c.s));
+    if (err != 0) {  // a grid barrier gave up: redo this bond with the library solver
+      coop = false;
+      if (to_right) ITN_HIP(c.h, gemm64(M, nr, M, nr, rho, n, n, n, nr, c.s));
+      else ITN_HIP(c.h, gemm64(MT, nl, MT, nl, rho, n, n, n, nl, c.s));
+    }
+  }
+  if (!coop) {
+    rocblas_status st = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
+                                         rho, (rocblas_int)n, D, E,
+                                         static_cast<rocblas_int*>(m->einfo.p));
+    if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd failed (%d)", (int)st);
+    ITN_HIP(c.h, hipMemcpyAsync(ev.data(), D, n * 8, hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipMemcpyAsync(&info, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipStreamSynchronize(c.s));
+  }
+  if (info != 0) return fail(c.h, ITN_E_NOT_CONVERGED, "symmetric eigensolver info=%d at bond %d", (int)info, i);
   // weights, descending
   std::vector<double> pd(n);
   double tot = 0.0;
@@ -430,13 +505,15 @@ itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdi
   double kept = 0.0;
   for (int j = 0; j < k; ++j) kept += pd[j] * tot;
   const double inv = 1.0 / std::sqrt(kept);
-  // Uk^T: rows = eigenvectors n-1, n-2, ..., n-k (column j of rho holds eigenvector j)
+  // Uk^T: row r = eigenvector of the r-th largest eigenvalue
   ITN_TRY(m->evec.ensure(c.h, (size_t)k * n * 8));
   double* Ukt = m->evec.d();
-  ITN_HIP(c.h, hipMemcpy2DAsync(Ukt, n * 8, rho + (size_t)(n - k) * n, n * 8, n * 8, k,
-                                hipMemcpyDeviceToDevice, c.s));
-  // reverse row order so row 0 is the largest weight
-  {
+  if (coop) {
+    ITN_HIP(c.h, tridiag_back(hhV, tau, rho, n, (int)n - 1, Ukt, (int)n, k, c.s));
+  } else {
+    // column j of rho holds eigenvector j: copy n-k .. n-1, then reverse the row order
+    ITN_HIP(c.h, hipMemcpy2DAsync(Ukt, n * 8, rho + (size_t)(n - k) * n, n * 8, n * 8, k,
+                                  hipMemcpyDeviceToDevice, c.s));
     const int64_t dims[2] = {k, n};
     const int64_t strides[2] = {-n, 1};
     ITN_TRY(m->Lp.ensure(c.h, (size_t)k * n * 8));  // scratch before the next bond

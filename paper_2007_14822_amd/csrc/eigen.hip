@@ -1,0 +1,266 @@
+// Symmetric eigensolver pieces for the FP64 bond split: Householder
+// tridiagonalisation in one cooperative launch, and the back-transformation
+// of selected tridiagonal eigenvectors.
+//
+// Tridiagonalisation Q^T A Q = T (Householder, one column per step): at step
+// k the reflector H_k = I - tau_k v_k v_k^T with v_k[j] = 0 for j <= k and
+// v_k[k+1] = 1 annihilates A[k+2:, k]; the trailing block is updated by the
+// symmetric rank-2 form A <- A - v w^T - w v^T with p = tau A v,
+// w = p - (tau/2)(p^T v) v.  The rows of A are spread cyclically over the
+// workgroups of one cooperative launch and stay in LDS for the whole
+// reduction; per step only row k+1 (the next pivot row) and p travel between
+// workgroups, through global memory and one grid barrier.  One launch
+// replaces the per-column launches of a library reduction, whose cost at
+// n of a few hundred is launch latency.
+#include "common.h"
+#include "kernels.h"
+
+namespace itn {
+
+namespace {
+
+constexpr int EIG_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Sum over the workgroup; every thread gets the result.  `red` holds one
+// double per wave.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  x = wave_sum(x);
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < EIG_THREADS / 64; ++w) s += red[w];
+  return s;
+}
+
+// Grid barrier over the cooperative launch: arrivals are counted on `bar`
+// (agent-scope atomics, so workgroups on different XCDs see each other);
+// a wait that exceeds `spin_limit` polls sets *err and gives up, so every
+// wave always reaches the end of the kernel.
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int* err,
+                                             int64_t spin_limit) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int64_t spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > spin_limit ||
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// Loads of data other workgroups wrote in this launch (not served from a
+// stale cache line).
+__device__ __forceinline__ double shared_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
+  extern __shared__ __align__(16) double lds_d[];
+  const int n = a.n, nwg = a.nwg, g = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int nrows = (n - g + nwg - 1) / nwg;  // rows g, g + nwg, ...
+  double* rows = lds_d;                        // [nrows][n]
+  double* v = rows + (int64_t)a.rows_per * n;  // [n]
+  double* w = v + n;                           // [n]
+  double* x = w + n;                           // [n] current row k (the pivot row)
+  double* red = x + n;                         // [EIG_THREADS / 64]
+  for (int64_t t = tid; t < (int64_t)nrows * n; t += EIG_THREADS) {
+    const int r = (int)(t / n), j = (int)(t % n);
+    rows[t] = a.A[(int64_t)(g + r * nwg) * a.lda + j];
+  }
+  for (int j = tid; j < n; j += EIG_THREADS) x[j] = a.A[j];  // row 0
+  __syncthreads();
+  // One grid barrier per step.  Every workgroup holds the pivot row k: it
+  // forms v_k itself, and after the barrier rebuilds row k+1 from the
+  // published pre-update copy and this step's rank-2 term.  Published data
+  // alternate between two buffers by step parity, so a workgroup that is
+  // one step ahead never overwrites what a slower one still reads.
+  unsigned epoch = 0;
+  for (int k = 0; k + 2 < n; ++k) {
+    const int par = k & 1;
+    double* pub = a.pub + par * n;
+    double* pbuf = a.pbuf + par * n;
+    double* dots = a.dots + par * nwg;
+    const double alpha = x[k + 1];
+    double ss = 0.0;
+    for (int j = k + 2 + tid; j < n; j += EIG_THREADS) ss += x[j] * x[j];
+    const double xnorm2 = block_sum(ss, red);
+    double tau = 0.0, beta = alpha;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      const double scal = 1.0 / (alpha - beta);
+      for (int j = k + 2 + tid; j < n; j += EIG_THREADS) v[j] = x[j] * scal;
+    } else {
+      for (int j = k + 2 + tid; j < n; j += EIG_THREADS) v[j] = 0.0;
+    }
+    if (tid == 0) v[k + 1] = 1.0;
+    __syncthreads();
+    if (g == 0) {
+      if (tid == 0) {
+        a.d[k] = x[k];
+        a.e[k] = beta;
+        a.tau[k] = tau;
+      }
+      double* vk = a.V + (int64_t)k * n;
+      for (int j = tid; j < n; j += EIG_THREADS) vk[j] = j > k ? v[j] : 0.0;
+    }
+    // row k+1 before this step's update, for every workgroup's next pivot
+    if ((k + 1) % nwg == g) {
+      const double* rk = rows + (int64_t)((k + 1) / nwg) * n;
+      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) pub[j] = rk[j];
+    }
+    // p = tau A v on this workgroup's rows i > k (one wave per row)
+    double part = 0.0;
+    for (int r = wave; r < nrows; r += EIG_THREADS / 64) {
+      const int i = g + r * nwg;
+      if (i <= k) continue;
+      const double* ri = rows + (int64_t)r * n;
+      double sacc = 0.0;
+      for (int j = k + 1 + lane; j < n; j += 64) sacc += ri[j] * v[j];
+      sacc = tau * wave_sum(sacc);
+      if (lane == 0) {
+        pbuf[i] = sacc;
+        part += sacc * v[i];
+      }
+    }
+    const double dot = block_sum(part, red);
+    if (tid == 0) dots[g] = dot;
+    grid_barrier(a.bar, (++epoch) * (unsigned)nwg, a.err, a.spin_limit);
+    double K = 0.0;
+    if (tau != 0.0) {
+      double pv = 0.0;
+      for (int q = 0; q < nwg; ++q) pv += shared_load(dots + q);  // fixed order: same in every workgroup
+      K = -0.5 * tau * pv;
+      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) w[j] = shared_load(pbuf + j) + K * v[j];
+    } else {
+      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) w[j] = 0.0;
+    }
+    __syncthreads();
+    // next pivot row: row k+1 after this step's update
+    {
+      const double vi = v[k + 1], wi = w[k + 1];
+      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) x[j] = shared_load(pub + j) - (vi * w[j] + wi * v[j]);
+    }
+    if (tau != 0.0) {
+      // A_ij -= v_i w_j + w_i v_j on this workgroup's rows i > k, columns j > k
+      for (int r = 0; r < nrows; ++r) {
+        const int i = g + r * nwg;
+        if (i <= k) continue;
+        double* ri = rows + (int64_t)r * n;
+        const double vi = v[i], wi = w[i];
+        for (int j = k + 1 + tid; j < n; j += EIG_THREADS) ri[j] -= vi * w[j] + wi * v[j];
+      }
+    }
+    __syncthreads();
+  }
+  // the last 2x2 block
+  const int i0 = n - 2, i1 = n - 1;
+  if (i0 % nwg == g && tid == 0) a.d[i0] = rows[(int64_t)(i0 / nwg) * n + i0];
+  if (i1 % nwg == g && tid == 0) {
+    a.d[i1] = rows[(int64_t)(i1 / nwg) * n + i1];
+    a.e[i0] = rows[(int64_t)(i1 / nwg) * n + i0];
+    a.tau[i0] = 0.0;
+  }
+}
+
+// out[r][:] = Q z with z = column cols0 - r of ZT (descending order when
+// cols0 = n - 1): reflectors applied last to first.  One wave per vector.
+__global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restrict__ V,
+                                                           const double* __restrict__ tau,
+                                                           const double* __restrict__ ZT, int64_t ldz,
+                                                           int cols0, double* __restrict__ out, int n,
+                                                           int k) {
+  extern __shared__ __align__(16) double zs[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * 4 + wave;
+  if (r >= k) return;
+  double* z = zs + (int64_t)wave * n;
+  const double* src = ZT + (int64_t)(cols0 - r) * ldz;
+  for (int j = lane; j < n; j += 64) z[j] = src[j];
+  for (int q = n - 3; q >= 0; --q) {
+    const double t = tau[q];
+    if (t == 0.0) continue;
+    const double* vq = V + (int64_t)q * n;
+    double s = 0.0;
+    for (int j = q + 1 + lane; j < n; j += 64) s += vq[j] * z[j];
+    s = t * wave_sum(s);
+    for (int j = q + 1 + lane; j < n; j += 64) z[j] -= s * vq[j];
+  }
+  double* dst = out + (int64_t)r * n;
+  for (int j = lane; j < n; j += 64) dst[j] = z[j];
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+}  // namespace
+
+int sytrd_coop_groups(int n) {
+  if (n < 3) return 0;
+  // rows of A plus three n-vectors must fit the LDS of one workgroup
+  for (int nwg = 8; nwg <= 256; nwg *= 2) {
+    const int64_t rows = (n + nwg - 1) / nwg;
+    if ((rows * n + 3 * (int64_t)n) * 8 + 64 <= 160 * 1024) return nwg;
+  }
+  return 0;
+}
+
+size_t sytrd_coop_lds(int n, int nwg) {
+  const int64_t rows = (n + nwg - 1) / nwg;
+  return (size_t)((rows * n + 3 * (int64_t)n) * 8 + (EIG_THREADS / 64) * 8);
+}
+
+hipError_t sytrd_coop(const SytrdArgs& a0, hipStream_t s) {
+  SytrdArgs a = a0;
+  if (a.n < 3 || a.nwg < 1) return hipErrorInvalidValue;
+  a.rows_per = (a.n + a.nwg - 1) / a.nwg;
+  const size_t lds = sytrd_coop_lds(a.n, a.nwg);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(sytrd_coop_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+      160 * 1024);
+  if (attr != hipSuccess) return attr;
+  // barrier counter and error flag start at zero (a kernel, not a memset)
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, a.bar, 1);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned*>(a.err), 1);
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(sytrd_coop_kernel), dim3(a.nwg),
+                                    dim3(EIG_THREADS), args, (unsigned)lds, s);
+}
+
+hipError_t tridiag_back(const double* V, const double* tau, const double* ZT, int64_t ldz, int cols0,
+                        double* out, int n, int k, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  if (n < 1 || cols0 - (k - 1) < 0 || cols0 >= n) return hipErrorInvalidValue;
+  const size_t lds = (size_t)4 * n * 8;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(tridiag_back_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+      160 * 1024);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(tridiag_back_kernel, dim3((unsigned)((k + 3) / 4)), dim3(256), lds, s, V, tau, ZT,
+                     ldz, cols0, out, n, k);
+  return hipGetLastError();
+}
+
+}  // namespace itn

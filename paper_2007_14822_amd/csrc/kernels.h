@@ -218,4 +218,26 @@ hipError_t lincomb_dev(const double* V, int64_t ldv, int k, const double* c, dou
                        int64_t n, hipStream_t s);
 hipError_t fill(void* x, int dtype, double v, int64_t n, hipStream_t s);
 
+// Householder tridiagonalisation of a symmetric FP64 n x n matrix A (rows of
+// length n at stride lda; read only) in one cooperative launch of nwg
+// workgroups: d[n], e[n-1] (T[k+1][k] = e[k]), tau[n-1], reflector k in row k
+// of V [n][n] (V[k][j] = 0 for j <= k, V[k][k+1] = 1).  Scratch: pub[2n],
+// pbuf[2n], dots[2 nwg], bar, err (zeroed by the call).  *err becomes non-zero
+// if a grid barrier waited more than spin_limit polls (results invalid).
+struct SytrdArgs {
+  const double* A;
+  int64_t lda;
+  int n, nwg, rows_per;
+  double *d, *e, *tau, *V, *pub, *pbuf, *dots;
+  unsigned* bar;
+  int* err;
+  int64_t spin_limit;
+};
+int sytrd_coop_groups(int n);  // workgroup count whose LDS holds A (0: n unsupported)
+size_t sytrd_coop_lds(int n, int nwg);
+hipError_t sytrd_coop(const SytrdArgs& a, hipStream_t s);
+// out[r][:] = Q ZT[:, cols0 - r] for r < k, Q = H_0 H_1 ... H_{n-3} from sytrd_coop.
+hipError_t tridiag_back(const double* V, const double* tau, const double* ZT, int64_t ldz, int cols0,
+                        double* out, int n, int k, hipStream_t s);
+
 }  // namespace itn
