@@ -401,11 +401,8 @@ int truncation_keep(const std::vector<double>& p_desc, double cutoff, int maxdim
 // ITN_EIG=library selects rocSOLVER's full symmetric eigensolver for every
 // bond split (comparison runs); default is the cooperative tridiagonalisation.
 bool use_coop_sytrd() {
-  static const bool v = [] {
-    const char* e = std::getenv("ITN_EIG");
-    return !(e && std::string(e) == "library");
-  }();
-  return v;
+  const char* e = std::getenv("ITN_EIG");
+  return !(e && std::strcmp(e, "library") == 0);
 }
 
 // Split psi [cl, d, d, cr] at bond i and store the new sites i, i+1.

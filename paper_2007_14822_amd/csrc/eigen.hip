@@ -41,34 +41,40 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
-// Grid barrier over the cooperative launch: arrivals are counted on `bar`
-// (agent-scope atomics, so workgroups on different XCDs see each other);
-// a wait that exceeds `spin_limit` polls sets *err and gives up, so every
-// wave always reaches the end of the kernel.
+// Data exchanged between workgroups inside the launch goes through
+// agent-scope atomic stores and loads: coherent across XCDs without
+// whole-cache write-back / invalidate fences (which cost several
+// microseconds per barrier).
+__device__ __forceinline__ void shared_store(double* p, double x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double shared_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier over the cooperative launch.  Every wave first waits for
+// its own stores to complete (so the shared_store data of the step are
+// performed before the arrival is counted); arrivals are counted on `bar`
+// with agent-scope atomics; the loads after the barrier are issued only
+// once the count is seen.  A wait that exceeds `spin_limit` polls sets
+// *err and gives up, so every wave always reaches the end of the kernel.
 __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int* err,
                                              int64_t spin_limit) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int64_t spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (++spins > spin_limit ||
           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();
   }
   __syncthreads();
-}
-
-// Loads of data other workgroups wrote in this launch (not served from a
-// stale cache line).
-__device__ __forceinline__ double shared_load(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
@@ -80,7 +86,7 @@ __global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
   double* v = rows + (int64_t)a.rows_per * n;  // [n]
   double* w = v + n;                           // [n]
   double* x = w + n;                           // [n] current row k (the pivot row)
-  double* red = x + n;                         // [EIG_THREADS / 64]
+  double* red = x + n;                         // [EIG_THREADS / 64 + nwg]
   for (int64_t t = tid; t < (int64_t)nrows * n; t += EIG_THREADS) {
     const int r = (int)(t / n), j = (int)(t % n);
     rows[t] = a.A[(int64_t)(g + r * nwg) * a.lda + j];
@@ -125,48 +131,84 @@ __global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
     // row k+1 before this step's update, for every workgroup's next pivot
     if ((k + 1) % nwg == g) {
       const double* rk = rows + (int64_t)((k + 1) / nwg) * n;
-      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) pub[j] = rk[j];
+      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) shared_store(pub + j, rk[j]);
     }
-    // p = tau A v on this workgroup's rows i > k (one wave per row)
+    // p = tau A v on this workgroup's rows i > k: a wave takes GR rows at a
+    // time and reduces their GR partial sums together, so the shuffle
+    // latencies overlap
     double part = 0.0;
-    for (int r = wave; r < nrows; r += EIG_THREADS / 64) {
-      const int i = g + r * nwg;
-      if (i <= k) continue;
-      const double* ri = rows + (int64_t)r * n;
-      double sacc = 0.0;
-      for (int j = k + 1 + lane; j < n; j += 64) sacc += ri[j] * v[j];
-      sacc = tau * wave_sum(sacc);
-      if (lane == 0) {
-        pbuf[i] = sacc;
-        part += sacc * v[i];
+    constexpr int GR = 8;
+    for (int r0 = wave * GR; r0 < nrows; r0 += (EIG_THREADS / 64) * GR) {
+      double sacc[GR];
+#pragma unroll
+      for (int q = 0; q < GR; ++q) sacc[q] = 0.0;
+      for (int j = k + 1 + lane; j < n; j += 64) {
+        const double vj = v[j];
+#pragma unroll
+        for (int q = 0; q < GR; ++q)
+          if (r0 + q < nrows) sacc[q] += rows[(int64_t)(r0 + q) * n + j] * vj;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int q = 0; q < GR; ++q) sacc[q] += __shfl_xor(sacc[q], off, 64);
+      if (lane < GR && r0 + lane < nrows) {
+        double sv = sacc[0];
+#pragma unroll
+        for (int q = 1; q < GR; ++q)
+          if (lane == q) sv = sacc[q];
+        const int i = g + (r0 + lane) * nwg;
+        if (i > k) {
+          sv *= tau;
+          shared_store(pbuf + i, sv);
+          part += sv * v[i];
+        }
       }
     }
     const double dot = block_sum(part, red);
-    if (tid == 0) dots[g] = dot;
+    if (tid == 0) shared_store(dots + g, dot);
     grid_barrier(a.bar, (++epoch) * (unsigned)nwg, a.err, a.spin_limit);
-    double K = 0.0;
-    if (tau != 0.0) {
-      double pv = 0.0;
-      for (int q = 0; q < nwg; ++q) pv += shared_load(dots + q);  // fixed order: same in every workgroup
-      K = -0.5 * tau * pv;
-      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) w[j] = shared_load(pbuf + j) + K * v[j];
-    } else {
-      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) w[j] = 0.0;
+    // everything published this step, fetched in one batch
+    constexpr int MJ = 8;  // n <= 1 + 8 * EIG_THREADS
+    double pb[MJ], pu[MJ];
+#pragma unroll
+    for (int m = 0; m < MJ; ++m) {
+      const int j = k + 1 + tid + m * EIG_THREADS;
+      pb[m] = j < n && tau != 0.0 ? shared_load(pbuf + j) : 0.0;
+      pu[m] = j < n ? shared_load(pub + j) : 0.0;
+    }
+    if (tid < nwg) red[EIG_THREADS / 64 + tid] = tau != 0.0 ? shared_load(dots + tid) : 0.0;
+    __syncthreads();
+    double pv = 0.0;
+    for (int q = 0; q < nwg; ++q) pv += red[EIG_THREADS / 64 + q];  // fixed order: same in every workgroup
+    const double K = -0.5 * tau * pv;
+#pragma unroll
+    for (int m = 0; m < MJ; ++m) {
+      const int j = k + 1 + tid + m * EIG_THREADS;
+      if (j < n) w[j] = pb[m] + K * v[j];
     }
     __syncthreads();
     // next pivot row: row k+1 after this step's update
     {
       const double vi = v[k + 1], wi = w[k + 1];
-      for (int j = k + 1 + tid; j < n; j += EIG_THREADS) x[j] = shared_load(pub + j) - (vi * w[j] + wi * v[j]);
+#pragma unroll
+      for (int m = 0; m < MJ; ++m) {
+        const int j = k + 1 + tid + m * EIG_THREADS;
+        if (j < n) x[j] = pu[m] - (vi * w[j] + wi * v[j]);
+      }
     }
     if (tau != 0.0) {
       // A_ij -= v_i w_j + w_i v_j on this workgroup's rows i > k, columns j > k
-      for (int r = 0; r < nrows; ++r) {
-        const int i = g + r * nwg;
-        if (i <= k) continue;
-        double* ri = rows + (int64_t)r * n;
-        const double vi = v[i], wi = w[i];
-        for (int j = k + 1 + tid; j < n; j += EIG_THREADS) ri[j] -= vi * w[j] + wi * v[j];
+      const int r0 = g > k ? 0 : (k - g) / nwg + 1;  // first row with i > k
+#pragma unroll
+      for (int m = 0; m < MJ; ++m) {
+        const int j = k + 1 + tid + m * EIG_THREADS;
+        if (j >= n) break;
+        const double vj = v[j], wj = w[j];
+        for (int r = r0; r < nrows; ++r) {
+          const int i = g + r * nwg;
+          rows[(int64_t)r * n + j] -= v[i] * wj + w[i] * vj;
+        }
       }
     }
     __syncthreads();
@@ -216,23 +258,23 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 }  // namespace
 
 int sytrd_coop_groups(int n) {
-  if (n < 3) return 0;
+  if (n < 3 || n > 1 + 8 * EIG_THREADS) return 0;
   // rows of A plus three n-vectors must fit the LDS of one workgroup
   for (int nwg = 8; nwg <= 256; nwg *= 2) {
     const int64_t rows = (n + nwg - 1) / nwg;
-    if ((rows * n + 3 * (int64_t)n) * 8 + 64 <= 160 * 1024) return nwg;
+    if ((rows * n + 3 * (int64_t)n) * 8 + (EIG_THREADS / 64 + 256) * 8 <= 160 * 1024) return nwg;
   }
   return 0;
 }
 
 size_t sytrd_coop_lds(int n, int nwg) {
   const int64_t rows = (n + nwg - 1) / nwg;
-  return (size_t)((rows * n + 3 * (int64_t)n) * 8 + (EIG_THREADS / 64) * 8);
+  return (size_t)((rows * n + 3 * (int64_t)n) * 8 + (EIG_THREADS / 64 + nwg) * 8);
 }
 
 hipError_t sytrd_coop(const SytrdArgs& a0, hipStream_t s) {
   SytrdArgs a = a0;
-  if (a.n < 3 || a.nwg < 1) return hipErrorInvalidValue;
+  if (a.n < 3 || a.n > 1 + 8 * EIG_THREADS || a.nwg < 1) return hipErrorInvalidValue;
   a.rows_per = (a.n + a.nwg - 1) / a.nwg;
   const size_t lds = sytrd_coop_lds(a.n, a.nwg);
   if (lds > 160 * 1024) return hipErrorInvalidValue;

@@ -157,3 +157,27 @@ def test_excited_state_rejects_bad_ortho(h):
     with pytest.raises(itn.ItnError) as e:
         h.dmrg_sweep(a, mpo, [(8, 0.0)], ortho=[a], weight=1.0)
     assert e.value.name == "ITN_E_ARG"
+
+
+@pytest.mark.parametrize("maxdim", [32, 200])
+def test_bond_split_eigensolvers_agree(h, monkeypatch, maxdim):
+    """The bond split's density-matrix eigensolver: the cooperative
+    Householder path (one launch over workgroups holding the matrix rows in
+    LDS; density matrices of 96 and 600 rows use 8 and 32 workgroups) and the
+    library's full symmetric solver give the same sweep energies, bond
+    dimensions and truncation weights (spin-1 chain, N=20, FP64)."""
+    N = 20
+    As0 = inp.random_product_state(N, 3, inp.rng_for(5, maxdim))
+    out = {}
+    for mode in ("library", "coop"):
+        if mode == "library":
+            monkeypatch.setenv("ITN_EIG", "library")
+        else:
+            monkeypatch.delenv("ITN_EIG", raising=False)
+        recs, _ = run(h, inp.heisenberg_mpo(N, 2), As0, [(maxdim, 1e-12)] * 3, prec="f64",
+                      eig_tol=1e-9, krylovdim=8, maxiter=200, allow_unconverged=True)
+        out[mode] = recs
+    for a, b in zip(out["library"], out["coop"]):
+        assert abs(a["energy"] - b["energy"]) <= 1e-10 * abs(a["energy"]), (a, b)
+        assert a["max_bond"] == b["max_bond"], (a, b)
+        assert abs(a["max_trunc"] - b["max_trunc"]) <= 1e-12, (a, b)
