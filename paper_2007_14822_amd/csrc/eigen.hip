@@ -81,15 +81,17 @@ __global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
   extern __shared__ __align__(16) double lds_d[];
   const int n = a.n, nwg = a.nwg, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int nrows = (n - g + nwg - 1) / nwg;  // rows g, g + nwg, ...
-  double* rows = lds_d;                        // [nrows][n]
-  double* v = rows + (int64_t)a.rows_per * n;  // [n]
+  const int nrows = (n - g + nwg - 1) / nwg;  // rows g, g + nwg, ... (at most 64)
+  const int ld = n | 1;                        // odd row stride: a lane per row hits distinct banks
+  double* rows = lds_d;                        // [nrows][ld]
+  double* v = rows + (int64_t)a.rows_per * ld; // [n]
   double* w = v + n;                           // [n]
   double* x = w + n;                           // [n] current row k (the pivot row)
-  double* red = x + n;                         // [EIG_THREADS / 64 + nwg]
+  double* part4 = x + n;                       // [EIG_THREADS] per-wave partial row sums
+  double* red = part4 + EIG_THREADS;           // [EIG_THREADS / 64 + nwg]
   for (int64_t t = tid; t < (int64_t)nrows * n; t += EIG_THREADS) {
     const int r = (int)(t / n), j = (int)(t % n);
-    rows[t] = a.A[(int64_t)(g + r * nwg) * a.lda + j];
+    rows[(int64_t)r * ld + j] = a.A[(int64_t)(g + r * nwg) * a.lda + j];
   }
   for (int j = tid; j < n; j += EIG_THREADS) x[j] = a.A[j];  // row 0
   __syncthreads();
@@ -130,43 +132,44 @@ __global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
     }
     // row k+1 before this step's update, for every workgroup's next pivot
     if ((k + 1) % nwg == g) {
-      const double* rk = rows + (int64_t)((k + 1) / nwg) * n;
+      const double* rk = rows + (int64_t)((k + 1) / nwg) * ld;
       for (int j = k + 1 + tid; j < n; j += EIG_THREADS) shared_store(pub + j, rk[j]);
     }
-    // p = tau A v on this workgroup's rows i > k: a wave takes GR rows at a
-    // time and reduces their GR partial sums together, so the shuffle
-    // latencies overlap
-    double part = 0.0;
-    constexpr int GR = 8;
-    for (int r0 = wave * GR; r0 < nrows; r0 += (EIG_THREADS / 64) * GR) {
-      double sacc[GR];
-#pragma unroll
-      for (int q = 0; q < GR; ++q) sacc[q] = 0.0;
-      for (int j = k + 1 + lane; j < n; j += 64) {
-        const double vj = v[j];
-#pragma unroll
-        for (int q = 0; q < GR; ++q)
-          if (r0 + q < nrows) sacc[q] += rows[(int64_t)(r0 + q) * n + j] * vj;
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int q = 0; q < GR; ++q) sacc[q] += __shfl_xor(sacc[q], off, 64);
-      if (lane < GR && r0 + lane < nrows) {
-        double sv = sacc[0];
-#pragma unroll
-        for (int q = 1; q < GR; ++q)
-          if (lane == q) sv = sacc[q];
-        const int i = g + (r0 + lane) * nwg;
-        if (i > k) {
-          sv *= tau;
-          shared_store(pbuf + i, sv);
-          part += sv * v[i];
+    // p = tau A v on this workgroup's rows i > k: lane r sums row r over a
+    // quarter of the columns (one quarter per wave); wave 0 adds the four
+    // quarters and forms this workgroup's part of p.v
+    {
+      const int cnt = n - (k + 1), q4 = (cnt + 3) / 4;
+      const int j0 = k + 1 + wave * q4, j1 = min(n, j0 + q4);
+      double sacc = 0.0;
+      if (lane < nrows) {  // four independent sums keep several LDS reads in flight
+        const double* ri = rows + (int64_t)lane * ld;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int j = j0;
+#pragma unroll 2
+        for (; j + 3 < j1; j += 4) {
+          s0 += ri[j] * v[j];
+          s1 += ri[j + 1] * v[j + 1];
+          s2 += ri[j + 2] * v[j + 2];
+          s3 += ri[j + 3] * v[j + 3];
         }
+        for (; j < j1; ++j) s0 += ri[j] * v[j];
+        sacc = (s0 + s1) + (s2 + s3);
       }
+      part4[tid] = sacc;
     }
-    const double dot = block_sum(part, red);
-    if (tid == 0) shared_store(dots + g, dot);
+    __syncthreads();
+    if (wave == 0) {
+      double part = 0.0;
+      const int i = g + lane * nwg;
+      if (lane < nrows && i > k) {
+        const double pi = tau * (((part4[lane] + part4[64 + lane]) + part4[128 + lane]) + part4[192 + lane]);
+        shared_store(pbuf + i, pi);
+        part = pi * v[i];
+      }
+      part = wave_sum(part);
+      if (lane == 0) shared_store(dots + g, part);
+    }
     grid_barrier(a.bar, (++epoch) * (unsigned)nwg, a.err, a.spin_limit);
     // everything published this step, fetched in one batch
     constexpr int MJ = 8;  // n <= 1 + 8 * EIG_THREADS
@@ -205,9 +208,10 @@ __global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
         const int j = k + 1 + tid + m * EIG_THREADS;
         if (j >= n) break;
         const double vj = v[j], wj = w[j];
+#pragma unroll 4
         for (int r = r0; r < nrows; ++r) {
           const int i = g + r * nwg;
-          rows[(int64_t)r * n + j] -= v[i] * wj + w[i] * vj;
+          rows[(int64_t)r * ld + j] -= v[i] * wj + w[i] * vj;
         }
       }
     }
@@ -215,10 +219,10 @@ __global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
   }
   // the last 2x2 block
   const int i0 = n - 2, i1 = n - 1;
-  if (i0 % nwg == g && tid == 0) a.d[i0] = rows[(int64_t)(i0 / nwg) * n + i0];
+  if (i0 % nwg == g && tid == 0) a.d[i0] = rows[(int64_t)(i0 / nwg) * ld + i0];
   if (i1 % nwg == g && tid == 0) {
-    a.d[i1] = rows[(int64_t)(i1 / nwg) * n + i1];
-    a.e[i0] = rows[(int64_t)(i1 / nwg) * n + i0];
+    a.d[i1] = rows[(int64_t)(i1 / nwg) * ld + i1];
+    a.e[i0] = rows[(int64_t)(i1 / nwg) * ld + i0];
     a.tau[i0] = 0.0;
   }
 }
@@ -260,22 +264,24 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 int sytrd_coop_groups(int n) {
   if (n < 3 || n > 1 + 8 * EIG_THREADS) return 0;
   // rows of A plus three n-vectors must fit the LDS of one workgroup
+  // (a lane per row in the row sums: at most 64 rows per workgroup)
   for (int nwg = 8; nwg <= 256; nwg *= 2) {
     const int64_t rows = (n + nwg - 1) / nwg;
-    if ((rows * n + 3 * (int64_t)n) * 8 + (EIG_THREADS / 64 + 256) * 8 <= 160 * 1024) return nwg;
+    if (rows <= 64 && sytrd_coop_lds(n, nwg) <= 160 * 1024) return nwg;
   }
   return 0;
 }
 
 size_t sytrd_coop_lds(int n, int nwg) {
   const int64_t rows = (n + nwg - 1) / nwg;
-  return (size_t)((rows * n + 3 * (int64_t)n) * 8 + (EIG_THREADS / 64 + nwg) * 8);
+  return (size_t)((rows * (n + 1) + 3 * (int64_t)n + EIG_THREADS + EIG_THREADS / 64 + nwg) * 8);
 }
 
 hipError_t sytrd_coop(const SytrdArgs& a0, hipStream_t s) {
   SytrdArgs a = a0;
   if (a.n < 3 || a.n > 1 + 8 * EIG_THREADS || a.nwg < 1) return hipErrorInvalidValue;
   a.rows_per = (a.n + a.nwg - 1) / a.nwg;
+  if (a.rows_per > 64) return hipErrorInvalidValue;
   const size_t lds = sytrd_coop_lds(a.n, a.nwg);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   static const hipError_t attr = hipFuncSetAttribute(
