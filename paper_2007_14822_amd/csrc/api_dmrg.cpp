@@ -432,7 +432,7 @@ itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdi
   // cooperative launch, the tridiagonal eigenproblem by rocSOLVER's divide
   // and conquer, the kept eigenvectors back-transformed; the library's full
   // symmetric solver where n does not fit (or ITN_EIG=library).
-  const int nwg = use_coop_sytrd() ? sytrd_coop_groups((int)n) : 0;
+  const int nwg = use_coop_sytrd() && tridiag_back_supported((int)n) ? sytrd_coop_groups((int)n) : 0;
   bool coop = nwg > 0;
   double *hhV = nullptr, *tau = nullptr;
   int* coop_err = nullptr;

@@ -228,30 +228,99 @@ __global__ __launch_bounds__(EIG_THREADS) void sytrd_coop_kernel(SytrdArgs a) {
 }
 
 // out[r][:] = Q z with z = column cols0 - r of ZT (descending order when
-// cols0 = n - 1): reflectors applied last to first.  One wave per vector.
+// cols0 = n - 1): reflectors applied last to first.  A workgroup holds VPW
+// vectors in LDS (256 / VPW lanes per vector) and streams the reflectors
+// through LDS in chunks of C rows of V, loading the next chunk into
+// registers while it applies the current one.
+template <int VPW, int C>
 __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restrict__ V,
                                                            const double* __restrict__ tau,
                                                            const double* __restrict__ ZT, int64_t ldz,
                                                            int cols0, double* __restrict__ out, int n,
                                                            int k) {
-  extern __shared__ __align__(16) double zs[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = blockIdx.x * 4 + wave;
-  if (r >= k) return;
-  double* z = zs + (int64_t)wave * n;
-  const double* src = ZT + (int64_t)(cols0 - r) * ldz;
-  for (int j = lane; j < n; j += 64) z[j] = src[j];
-  for (int q = n - 3; q >= 0; --q) {
-    const double t = tau[q];
-    if (t == 0.0) continue;
-    const double* vq = V + (int64_t)q * n;
-    double s = 0.0;
-    for (int j = q + 1 + lane; j < n; j += 64) s += vq[j] * z[j];
-    s = t * wave_sum(s);
-    for (int j = q + 1 + lane; j < n; j += 64) z[j] -= s * vq[j];
+  constexpr int L = 256 / VPW;  // lanes per vector
+  constexpr int PF = 24;        // prefetch registers per thread (C * n <= 256 * PF)
+  extern __shared__ __align__(16) double sh[];
+  double* z = sh;                          // [VPW][n]
+  double* vb = z + (int64_t)VPW * n;       // [2][C][n]
+  double* tb = vb + (int64_t)2 * C * n;    // [2][C]
+  const int tid = threadIdx.x, grp = tid / L, t = tid % L;
+  const int r = blockIdx.x * VPW + grp;
+  double* zr = z + (int64_t)grp * n;
+  if (r < k) {
+    const double* src = ZT + (int64_t)(cols0 - r) * ldz;
+    for (int j = t; j < n; j += L) zr[j] = src[j];
   }
-  double* dst = out + (int64_t)r * n;
-  for (int j = lane; j < n; j += 64) dst[j] = z[j];
+  const int nref = n - 2;  // reflectors 0 .. n-3
+  const int nchunk = (nref + C - 1) / C;
+  // chunk c holds reflectors q = nref-1-c*C-u for u < C (descending)
+  double pf[PF];
+  double pt = 0.0;
+  auto fetch = [&](int c) {
+#pragma unroll
+    for (int m = 0; m < PF; ++m) {
+      const int e = tid + m * 256;
+      const int u = e / n, j = e % n;
+      const int q = nref - 1 - c * C - u;
+      pf[m] = (u < C && q >= 0) ? V[(int64_t)q * n + j] : 0.0;
+    }
+    const int q = nref - 1 - c * C - tid;
+    pt = (tid < C && q >= 0) ? tau[q] : 0.0;
+  };
+  auto stash = [&](int buf) {
+    double* dst = vb + (int64_t)buf * C * n;
+#pragma unroll
+    for (int m = 0; m < PF; ++m) {
+      const int e = tid + m * 256;
+      if (e < C * n) dst[e] = pf[m];
+    }
+    if (tid < C) tb[buf * C + tid] = pt;
+  };
+  if (nchunk > 0) {
+    fetch(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunk) fetch(c + 1);
+    const double* vc = vb + (int64_t)buf * C * n;
+    if (r < k) {
+      for (int u = 0; u < C; ++u) {
+        const double tq = tb[buf * C + u];
+        if (tq == 0.0) continue;  // also the padding past reflector 0
+        const double* vq = vc + (int64_t)u * n;
+        double sacc = 0.0;
+        for (int j = t; j < n; j += L) sacc += vq[j] * zr[j];
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
+        sacc *= tq;
+        for (int j = t; j < n; j += L) zr[j] -= sacc * vq[j];
+      }
+    }
+    __syncthreads();
+    if (c + 1 < nchunk) stash(buf ^ 1);
+    __syncthreads();
+  }
+  if (r < k) {
+    double* dst = out + (int64_t)r * n;
+    for (int j = t; j < n; j += L) dst[j] = zr[j];
+  }
+}
+
+// Vectors per workgroup and reflector chunk for n (0: n too large).
+static void back_cfg(int n, int& vpw, int& c) {
+  vpw = 0;
+  c = 0;
+  const int cands[3][2] = {{4, 16}, {4, 8}, {4, 4}};  // a wave per vector: k / 4 workgroups
+  for (auto& cd : cands) {
+    const int64_t lds = ((int64_t)cd[0] * n + 2LL * cd[1] * n + 2 * cd[1]) * 8;
+    if (lds <= 160 * 1024 && (int64_t)cd[1] * n <= 256 * 24) {
+      vpw = cd[0];
+      c = cd[1];
+      return;
+    }
+  }
 }
 
 __global__ void zero_u32_kernel(unsigned* p, int n) {
@@ -296,19 +365,31 @@ hipError_t sytrd_coop(const SytrdArgs& a0, hipStream_t s) {
                                     dim3(EIG_THREADS), args, (unsigned)lds, s);
 }
 
+bool tridiag_back_supported(int n) {
+  int vpw, c;
+  back_cfg(n, vpw, c);
+  return n >= 3 && vpw > 0;
+}
+
 hipError_t tridiag_back(const double* V, const double* tau, const double* ZT, int64_t ldz, int cols0,
                         double* out, int n, int k, hipStream_t s) {
   if (k <= 0) return hipSuccess;
-  if (n < 1 || cols0 - (k - 1) < 0 || cols0 >= n) return hipErrorInvalidValue;
-  const size_t lds = (size_t)4 * n * 8;
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(tridiag_back_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-      160 * 1024);
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(tridiag_back_kernel, dim3((unsigned)((k + 3) / 4)), dim3(256), lds, s, V, tau, ZT,
-                     ldz, cols0, out, n, k);
-  return hipGetLastError();
+  if (n < 3 || cols0 - (k - 1) < 0 || cols0 >= n) return hipErrorInvalidValue;
+  int vpw, c;
+  back_cfg(n, vpw, c);
+  if (vpw == 0) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)vpw * n + 2 * (size_t)c * n + 2 * c) * 8;
+  auto go = [&](auto kern) -> hipError_t {
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((k + vpw - 1) / vpw)), dim3(256), lds, s, V, tau, ZT, ldz,
+                       cols0, out, n, k);
+    return hipGetLastError();
+  };
+  if (c == 16) return go(tridiag_back_kernel<4, 16>);
+  if (c == 8) return go(tridiag_back_kernel<4, 8>);
+  return go(tridiag_back_kernel<4, 4>);
 }
 
 }  // namespace itn

@@ -239,5 +239,6 @@ hipError_t sytrd_coop(const SytrdArgs& a, hipStream_t s);
 // out[r][:] = Q ZT[:, cols0 - r] for r < k, Q = H_0 H_1 ... H_{n-3} from sytrd_coop.
 hipError_t tridiag_back(const double* V, const double* tau, const double* ZT, int64_t ldz, int cols0,
                         double* out, int n, int k, hipStream_t s);
+bool tridiag_back_supported(int n);
 
 }  // namespace itn
