@@ -199,7 +199,7 @@ hipError_t wstage(int in_dtype, const void* in, int out_dtype, void* out, const 
 
 // ------------------------------------------------------------------ BLAS-1
 constexpr int DOT_THREADS = 256;
-constexpr int64_t DOT_CHUNK = 8192;  // elements per block
+constexpr int64_t DOT_CHUNK = 1024;  // elements per block
 
 int64_t dot_blocks(int64_t n) {
   int64_t b = (n + DOT_CHUNK - 1) / DOT_CHUNK;
@@ -211,22 +211,37 @@ __global__ __launch_bounds__(DOT_THREADS) void multi_dot_partial(const double* _
                                                                   int64_t ldv, int k,
                                                                   const double* __restrict__ w,
                                                                   int64_t n, double* partial) {
-  __shared__ double red[DOT_THREADS / 64];
+  // up to DG vectors per pass: w is read once per pass and the DG sums are
+  // reduced together
+  constexpr int DG = 16;
+  __shared__ double red[DOT_THREADS / 64][DG];
   const int64_t nb = gridDim.x;
   const int64_t lo = blockIdx.x * DOT_CHUNK;
   int64_t hi = lo + DOT_CHUNK;
   if (hi > n) hi = n;
-  for (int j = 0; j < k; ++j) {
-    const double* v = V + j * ldv;
-    double acc = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += DOT_THREADS) acc += v[i] * w[i];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < k; j0 += DG) {
+    double acc[DG];
+#pragma unroll
+    for (int q = 0; q < DG; ++q) acc[q] = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += DOT_THREADS) {
+      const double wi = w[i];
+#pragma unroll
+      for (int q = 0; q < DG; ++q)
+        if (j0 + q < k) acc[q] += V[(int64_t)(j0 + q) * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int q = 0; q < DG; ++q) acc[q] += __shfl_down(acc[q], off, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < DG; ++q) red[wave][q] = acc[q];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < DG && j0 + (int)threadIdx.x < k) {
       double t = 0.0;
-      for (int q = 0; q < DOT_THREADS / 64; ++q) t += red[q];
-      partial[j * nb + blockIdx.x] = t;
+      for (int q = 0; q < DOT_THREADS / 64; ++q) t += red[q][threadIdx.x];
+      partial[(int64_t)(j0 + threadIdx.x) * nb + blockIdx.x] = t;
     }
     __syncthreads();
   }
