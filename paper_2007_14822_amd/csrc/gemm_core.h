@@ -308,8 +308,13 @@ __device__ __forceinline__ void store_tile_direct(
         if (full || (row < M && col < N)) {
           Acc v = acc[i][j][e];
           TOut* p = Cp + row * ldc + col;
-          if (ACCUM) v += cvt<Acc>(*p);
-          *p = cvt<TOut>(v);
+          if (ACCUM) {
+            v += cvt<Acc>(*p);
+            *p = cvt<TOut>(v);
+          } else {
+            // the tile is written once and read by a later kernel: stream it
+            __builtin_nontemporal_store(cvt<TOut>(v), p);
+          }
         }
       }
 }
