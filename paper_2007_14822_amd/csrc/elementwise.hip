@@ -127,6 +127,26 @@ __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ i
     if (r < t.rows && c < t.cols) tile[i][tx] = (TS)(TW)ip[r * t.in_r + c * t.in_c];
   }
   __syncthreads();
+  if constexpr (sizeof(TO) == 2) {
+    // 16-bit outputs with unit stride along r: eight consecutive values
+    // (16 bytes) per thread on full tiles with aligned rows
+    const bool wide = t.out_r == 1 && r0 + TT <= t.rows && c0 + TT <= t.cols && (t.out_c % 8) == 0 &&
+                      (reinterpret_cast<uintptr_t>(op + r0) % 16) == 0;
+    if (wide) {
+      const int g8 = threadIdx.x & 7, cy = threadIdx.x >> 3;  // 8 groups of 8 rows x 32 columns
+#pragma unroll
+      for (int i = cy; i < TT; i += 32) {
+        union {
+          TO v[8];
+          uint4 u;
+        } pk;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pk.v[q] = conv<TO, TS>(tile[g8 * 8 + q][i]);
+        *reinterpret_cast<uint4*>(op + (c0 + i) * t.out_c + r0 + g8 * 8) = pk.u;
+      }
+      return;
+    }
+  }
   const int px = threadIdx.x & 31, py = threadIdx.x >> 5;  // 32 pairs x 8 rows
   const int64_t r = r0 + 2 * px;
   const bool pair_ok = t.out_r == 1 && r + 1 < t.rows;
