@@ -676,6 +676,7 @@ static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const
     g4.ldc = cr;
     g4.batch = 1;
     g4.accumulate = term > 0;
+    g4.stream = 1;  // H psi is read by the eigensolver's next pass, not by a resident kernel
     Prof pf(h, "heff_stage4_gemm", s);
     ITN_HIP(h, gemm_nt(P, out->dtype, g4, s));
   }

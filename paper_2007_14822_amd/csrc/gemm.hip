@@ -22,7 +22,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_nt_kernel(GemmArgs g, int64
   store_tile<P, BM, BN, TOut>(acc, Cp, g.ldc, g.M, g.N, tm * BM, tn * BN, g.accumulate != 0);
 }
 
-template <int P, int BM, int BN, int WM, int WN, typename TOut, bool ACCUM>
+template <int P, int BM, int BN, int WM, int WN, typename TOut, int MODE>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_nt_direct_kernel(GemmArgs g, int64_t tiles_m,
                                                                         int64_t tiles_n) {
   using Cfg = DirectCfg<P, BM, BN, WM, WN>;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_nt_direct_kernel(GemmArgs g
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
   gemm_accum_direct<P, BM, BN, WM, WN>(A, g.lda, g.M, B, g.ldb, g.N, g.K, tm * BM, tn * BN, acc, lds);
-  store_tile_direct<P, BM, BN, WM, WN, TOut, ACCUM>(acc, Cp, g.ldc, g.M, g.N, tm * BM, tn * BN);
+  store_tile_direct<P, BM, BN, WM, WN, TOut, MODE>(acc, Cp, g.ldc, g.M, g.N, tm * BM, tn * BN);
 }
 
 // Persistent grouped GEMM: gridDim.x workgroups stride over the tile list
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_grouped_direct_kernel(
                                                  Bbase + sg.b_off + batch * b_bs, sg.ldb, pr.N, sg.K,
                                                  (int64_t)t.tm * BM, (int64_t)t.tn * BN, acc, lds, zero);
     }
-    store_tile_direct<P, BM, BN, WM, WN, TOut, false>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc,
+    store_tile_direct<P, BM, BN, WM, WN, TOut, 0>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc,
                                                        pr.M, pr.N, (int64_t)t.tm * BM,
                                                        (int64_t)t.tn * BN);
   }
@@ -159,15 +159,19 @@ static hipError_t launch_nt_direct(const GemmArgs& g, hipStream_t s) {
   const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
   dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)g.batch);
   static const hipError_t attr =
-      allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, false>, Cfg::LDS_BYTES) != hipSuccess
+      (allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 0>, Cfg::LDS_BYTES) != hipSuccess ||
+       allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 1>, Cfg::LDS_BYTES) != hipSuccess)
           ? hipErrorInvalidValue
-          : allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, true>, Cfg::LDS_BYTES);
+          : allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 2>, Cfg::LDS_BYTES);
   if (attr != hipSuccess) return attr;
   if (g.accumulate)
-    hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, true>), grid,
+    hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 1>), grid,
+                       dim3(Cfg::THREADS), Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
+  else if (g.stream)
+    hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 2>), grid,
                        dim3(Cfg::THREADS), Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
   else
-    hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, false>), grid,
+    hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 0>), grid,
                        dim3(Cfg::THREADS), Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
   return hipGetLastError();
 }

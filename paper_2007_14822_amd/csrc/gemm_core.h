@@ -286,7 +286,9 @@ __device__ __forceinline__ void gemm_accum_direct(
 }
 
 // Store the wave's FM x FN accumulator blocks of a direct tile.
-template <int P, int BM, int BN, int WM, int WN, typename TOut, bool ACCUM>
+// MODE: 0 store, 1 accumulate into C, 2 store with nontemporal hints (C is
+// consumed by a later pass, not by the next kernel's cache-resident reads).
+template <int P, int BM, int BN, int WM, int WN, typename TOut, int MODE>
 __device__ __forceinline__ void store_tile_direct(
     const typename PT<P>::AccV (&acc)[DirectCfg<P, BM, BN, WM, WN>::FM][DirectCfg<P, BM, BN, WM, WN>::FN],
     TOut* __restrict__ Cp, int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0) {
@@ -308,12 +310,13 @@ __device__ __forceinline__ void store_tile_direct(
         if (full || (row < M && col < N)) {
           Acc v = acc[i][j][e];
           TOut* p = Cp + row * ldc + col;
-          if (ACCUM) {
+          if constexpr (MODE == 1) {
             v += cvt<Acc>(*p);
             *p = cvt<TOut>(v);
-          } else {
-            // the tile is written once and read by a later kernel: stream it
+          } else if constexpr (MODE == 2) {
             __builtin_nontemporal_store(cvt<TOut>(v), p);
+          } else {
+            *p = cvt<TOut>(v);
           }
         }
       }

@@ -22,6 +22,7 @@ struct GemmArgs {
   int64_t sA, sB, sC;  // batch strides (elements)
   int32_t batch;
   int32_t accumulate;
+  int32_t stream;  // non-zero: C is written with nontemporal stores (read only by a later pass)
 };
 hipError_t gemm_nt(int prec, int c_dtype, const GemmArgs& g, hipStream_t s);
 
