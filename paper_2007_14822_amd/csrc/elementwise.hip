@@ -182,7 +182,10 @@ hipError_t transpose_cast(int in_dtype, const void* in, int out_dtype, void* out
 }
 
 // ------------------------------------------------------------------ W-stage
-// One thread per position y (fastest, coalesced), grid over (y-chunk, x, z).
+// One thread per (output row r, position y): consecutive threads take
+// consecutive y of one row (coalesced); grid over ((r, y) chunks, x, z).
+// A thread per row rather than per position keeps small bond dimensions
+// (Y of a few dozen) from leaving most of the GPU idle.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void wstage_kernel(const TI* __restrict__ in, TO* __restrict__ out,
                                                       WStageArgs a, const int32_t* __restrict__ row_ptr,
@@ -190,22 +193,21 @@ __global__ __launch_bounds__(256) void wstage_kernel(const TI* __restrict__ in, 
                                                       const int64_t* __restrict__ col_off,
                                                       const double* __restrict__ coef) {
   using A = typename std::conditional<sizeof(TI) == 8, double, float>::type;
-  const int64_t y = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t r = t / a.Y, y = t % a.Y;
   const int64_t x = blockIdx.y, z = blockIdx.z;
-  if (y >= a.Y) return;
+  if (r >= a.nrows) return;
   const TI* ip = in + x * a.isx + z * a.isz + y * a.isy;
   TO* op = out + x * a.osx + z * a.osz + y * a.osy;
-  for (int r = 0; r < a.nrows; ++r) {
-    A acc = 0;
-    for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) acc += (A)coef[e] * (A)ip[col_off[e]];
-    op[row_off[r]] = conv<TO, A>(acc);
-  }
+  A acc = 0;
+  for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) acc += (A)coef[e] * (A)ip[col_off[e]];
+  op[row_off[r]] = conv<TO, A>(acc);
 }
 template <typename TI, typename TO>
 static hipError_t wstage_t(const void* in, void* out, const WStageArgs& a, const int32_t* rp,
                            const int64_t* ro, const int64_t* co, const double* cf, hipStream_t s) {
-  if (a.X == 0 || a.Y == 0 || a.Z == 0) return hipSuccess;
-  dim3 grid((unsigned)((a.Y + 255) / 256), (unsigned)a.X, (unsigned)a.Z);
+  if (a.X == 0 || a.Y == 0 || a.Z == 0 || a.nrows == 0) return hipSuccess;
+  dim3 grid((unsigned)((a.nrows * a.Y + 255) / 256), (unsigned)a.X, (unsigned)a.Z);
   hipLaunchKernelGGL((wstage_kernel<TI, TO>), grid, dim3(256), 0, s, static_cast<const TI*>(in),
                      static_cast<TO*>(out), a, rp, ro, co, cf);
   return hipGetLastError();
