@@ -50,6 +50,35 @@ struct DBuf {
   double* d() const { return static_cast<double*>(p); }
 };
 
+// Pinned host staging for the small device-to-host reads of the sweep
+// (Davidson reductions, eigenvalues of the bond split): a read into pinned
+// memory completes without the staging copy of a pageable destination.
+struct HostPin {
+  void* p = nullptr;
+  size_t bytes = 0;
+  itn_status ensure(itn_handle* h, size_t b) {
+    if (b <= bytes) return ITN_OK;
+    if (p) {
+      ITN_HIP(h, hipDeviceSynchronize());
+      ITN_HIP(h, hipHostFree(p));
+    }
+    p = nullptr;
+    bytes = 0;
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      return fail(h, ITN_E_WORKSPACE, "pinned allocation of %zu bytes failed", b);
+    }
+    bytes = b;
+    return ITN_OK;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  double* d() const { return static_cast<double*>(p); }
+};
+
 }  // namespace
 
 struct itn_mps {
@@ -67,6 +96,7 @@ struct itn_mps {
   DBuf psi, tmp, rho, evec, eval, einfo, V, AV, Lp, Rp, partial, dots, ev_host_stage;
   DBuf ovec, ot1, ot2, ot3, odots;
   DBuf hh, hscr;  // bond split: Householder reflectors [n][n]; tridiagonal and barrier scratch
+  HostPin pin;    // pinned host staging for small reads
   ~itn_mps() {
     for (auto& b : site) b.release();
     for (auto& b : Lenv) b.release();
@@ -77,6 +107,7 @@ struct itn_mps {
     for (DBuf* b : {&psi, &tmp, &rho, &evec, &eval, &einfo, &V, &AV, &Lp, &Rp, &partial, &dots,
                     &ev_host_stage, &ovec, &ot1, &ot2, &ot3, &odots, &hh, &hscr})
       b->release();
+    pin.release();
   }
 };
 
@@ -246,9 +277,11 @@ itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl,
 itn_status dots(Ctx& c, const double* V, int64_t n, int k, const double* w, double* out) {
   ITN_TRY(c.m->partial.ensure(c.h, (size_t)k * dot_blocks(n) * 8));
   ITN_TRY(c.m->dots.ensure(c.h, (size_t)k * 8 + 8));
+  ITN_TRY(c.m->pin.ensure(c.h, (size_t)k * 8 + 8));
   ITN_HIP(c.h, multi_dot(V, n, k, w, n, c.m->partial.d(), c.m->dots.d(), c.s));
-  ITN_HIP(c.h, hipMemcpyAsync(out, c.m->dots.p, (size_t)k * 8, hipMemcpyDeviceToHost, c.s));
+  ITN_HIP(c.h, hipMemcpyAsync(c.m->pin.p, c.m->dots.p, (size_t)k * 8, hipMemcpyDeviceToHost, c.s));
   ITN_HIP(c.h, hipStreamSynchronize(c.s));
+  std::memcpy(out, c.m->pin.p, (size_t)k * 8);
   return ITN_OK;
 }
 
@@ -259,10 +292,11 @@ itn_status dots(Ctx& c, const double* V, int64_t n, int k, const double* w, doub
 // the Krylov space (no new direction) is at the arithmetic's noise floor and
 // counts as converged.
 //
-// Host round trips per expansion step: three.  (1) the new column V^T A v_k
-// of the projected matrix; (2) V^T r and r.r in one reduction, the residual
-// being formed in the next basis slot; (3) the same pair after the first
-// Gram-Schmidt pass, from which the norm after the second pass follows as
+// Host round trips per expansion step: two, sometimes three.  (1) the new
+// column V^T A v_k of the projected matrix; (2) V^T r and r.r in one
+// reduction, the residual being formed in the next basis slot; (3) only when
+// the first Gram-Schmidt pass removed most of r (DGKS test): the same pair
+// after that pass, from which the norm after the second pass follows as
 // |r'|^2 - |c2|^2 (V orthonormal).
 itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* psi, int64_t n,
                     int64_t cl, int64_t cr, double* energy, double* resid, bool* converged) {
@@ -469,10 +503,15 @@ itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdi
                                          (rocblas_int)n, static_cast<rocblas_int*>(m->einfo.p));
     if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dstedc failed (%d)", (int)st);
     int err = 0;
-    ITN_HIP(c.h, hipMemcpyAsync(ev.data(), D, n * 8, hipMemcpyDeviceToHost, c.s));
-    ITN_HIP(c.h, hipMemcpyAsync(&info, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
-    ITN_HIP(c.h, hipMemcpyAsync(&err, coop_err, sizeof(err), hipMemcpyDeviceToHost, c.s));
+    ITN_TRY(m->pin.ensure(c.h, (size_t)(n + 2) * 8));
+    char* pin = static_cast<char*>(m->pin.p);
+    ITN_HIP(c.h, hipMemcpyAsync(pin, D, n * 8, hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipMemcpyAsync(pin + n * 8, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipMemcpyAsync(pin + (n + 1) * 8, coop_err, sizeof(err), hipMemcpyDeviceToHost, c.s));
     ITN_HIP(c.h, hipStreamSynchronize(c.s));
+    std::memcpy(ev.data(), pin, n * 8);
+    std::memcpy(&info, pin + n * 8, sizeof(info));
+    std::memcpy(&err, pin + (n + 1) * 8, sizeof(err));
     if (err != 0) {  // a grid barrier gave up: redo this bond with the library solver
       coop = false;
       if (to_right) ITN_HIP(c.h, gemm64(M, nr, M, nr, rho, n, n, n, nr, c.s));
@@ -484,9 +523,13 @@ itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdi
                                          rho, (rocblas_int)n, D, E,
                                          static_cast<rocblas_int*>(m->einfo.p));
     if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd failed (%d)", (int)st);
-    ITN_HIP(c.h, hipMemcpyAsync(ev.data(), D, n * 8, hipMemcpyDeviceToHost, c.s));
-    ITN_HIP(c.h, hipMemcpyAsync(&info, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
+    ITN_TRY(m->pin.ensure(c.h, (size_t)(n + 2) * 8));
+    char* pin = static_cast<char*>(m->pin.p);
+    ITN_HIP(c.h, hipMemcpyAsync(pin, D, n * 8, hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipMemcpyAsync(pin + n * 8, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
     ITN_HIP(c.h, hipStreamSynchronize(c.s));
+    std::memcpy(ev.data(), pin, n * 8);
+    std::memcpy(&info, pin + n * 8, sizeof(info));
   }
   if (info != 0) return fail(c.h, ITN_E_NOT_CONVERGED, "symmetric eigensolver info=%d at bond %d", (int)info, i);
   // weights, descending
