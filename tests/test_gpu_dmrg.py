@@ -159,11 +159,12 @@ def test_excited_state_rejects_bad_ortho(h):
     assert e.value.name == "ITN_E_ARG"
 
 
-@pytest.mark.parametrize("maxdim", [32, 200])
+@pytest.mark.parametrize("maxdim", [32, 100, 200])
 def test_bond_split_eigensolvers_agree(h, monkeypatch, maxdim):
     """The bond split's density-matrix eigensolver: the cooperative
     Householder path (one launch over workgroups holding the matrix rows in
-    LDS; density matrices of 96 and 600 rows use 8 and 32 workgroups) and the
+    LDS; density matrices of 96, 300 and 600 rows use 8, 16 and 32
+    workgroups) and the
     library's full symmetric solver give the same sweep energies, bond
     dimensions and truncation weights (spin-1 chain, N=20, FP64)."""
     N = 20
