@@ -245,10 +245,23 @@ itn_status itn_qn_allowed_blocks(itn_handle* h, const itn_tensor* t, int64_t* nb
  * on 128x128 direct-to-LDS tiles; 5: products of both extents >= 96 on
  * 128x128 direct-to-LDS tiles, the rest on 64).  The choice is cached per
  * operand structure (in the file ITN_AUTOTUNE_CACHE if set);
- * ITN_QN_TILE_MODE="m1,m4" (modes 0..5) fixes it instead. */
+ * ITN_QN_TILE_MODE="m1,m4" (modes 0..5) fixes it instead.
+ * L == NULL and R == NULL apply with the environments of the last
+ * itn_qn_prepare_env (or of the last apply that passed them) without
+ * repacking them again (ITN_E_ARG if there are none); passing only one of
+ * them is ITN_E_ARG. */
 itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* plan, const itn_tensor* L,
                              const itn_tensor* R, const itn_tensor* psi, itn_tensor* out,
                              void* hip_stream);
+
+/* Repack the environments L, R (the plan's structure and compute type:
+ * ITN_E_SHAPE / ITN_E_DTYPE otherwise) into the plan's layouts on
+ * hip_stream, for applies with L = R = NULL.  The eigensolver at a bond of
+ * a DMRG sweep (Sec. 7.2) applies H_eff many times with the same
+ * environments: their repack is then paid once per bond, not per apply.
+ * L and R must stay unchanged and allocated while such applies run. */
+itn_status itn_qn_prepare_env(itn_handle* h, itn_plan* plan, const itn_tensor* L,
+                              const itn_tensor* R, void* hip_stream);
 
 /* ------------------------------------------------------- environment step */
 

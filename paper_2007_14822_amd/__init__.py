@@ -364,10 +364,11 @@ def _qn_handle_methods():
                 tot.value)
 
     def qn_apply(self, plan, Ld, Rd, Pd, Od, stream=None):
+        """H_eff*psi into Od.  Ld = Rd = None uses the environments of the
+        plan's last prepare_env (or of its last apply that passed them)."""
         k = _Keep()
-        ts = [_qn(k, x) for x in (Ld, Rd, Pd, Od)]
-        self._check(self.lib.itn_qn_heff_apply(self.h, plan.ptr, *[C.byref(t) for t in ts],
-                                               self._sp(stream)))
+        refs = [None if x is None else C.byref(_qn(k, x)) for x in (Ld, Rd, Pd, Od)]
+        self._check(self.lib.itn_qn_heff_apply(self.h, plan.ptr, *refs, self._sp(stream)))
     return qn_plan, qn_allowed_blocks, qn_apply
 
 
@@ -391,13 +392,23 @@ class Plan:
         self.handle._check(self.lib.itn_plan_out_blocks(self.ptr, sec, off))
         return [tuple(sec[4 * b:4 * b + 4]) for b in range(n)], list(off[:n])
 
+    def prepare_env(self, Ld, Rd, stream=None):
+        """Repack the environments once for applies with Ld = Rd = None
+        (the environments must stay unchanged while those run)."""
+        k = _Keep()
+        refs = [C.byref(_qn(k, x)) for x in (Ld, Rd)]
+        self.handle._check(self.lib.itn_qn_prepare_env(self.handle.h, self.ptr, *refs,
+                                                       self.handle._sp(stream)))
+        self._env_keep = (k, Ld, Rd)
+
     def bind(self, Ld, Rd, Pd, Od, stream=None):
         """A callable applying the plan to these operands: the descriptors
         are marshalled once (the tensors' current storage is used on every
-        call), so a loop of applies costs one library call each."""
+        call), so a loop of applies costs one library call each.  Ld = Rd =
+        None binds to the prepared environments (prepare_env)."""
         k = _Keep()
-        ts = [_qn(k, x) for x in (Ld, Rd, Pd, Od)]
-        refs = [C.byref(t) for t in ts]
+        ts = [None if x is None else _qn(k, x) for x in (Ld, Rd, Pd, Od)]
+        refs = [None if t is None else C.byref(t) for t in ts]
         sp = self.handle._sp(stream)
         lib, h, ptr, check = self.lib, self.handle.h, self.ptr, self.handle._check
 

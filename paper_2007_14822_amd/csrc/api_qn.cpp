@@ -247,6 +247,7 @@ struct itn_plan {
   int nv = 1;
   int64_t out_elems = 0;
   std::string sig;  // operand structure signature (L, R, psi)
+  std::string sigL, sigR, sigP;  // the parts of sig
   size_t sig_hash = 0;
   // host tables
   std::vector<std::vector<int32_t>> out_blocks;
@@ -328,11 +329,21 @@ struct itn_plan {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // applies with prepared environments (itn_qn_prepare_env): their own graph
+  // without the L/R repack
+  hipGraph_t graph_pe = nullptr;
+  hipGraphExec_t exec_pe = nullptr;
+  bool env_ready = false;
+  bool out_set = false;
+  const void* envL = nullptr;  // environments of the last prepare
+  const void* envR = nullptr;
   ~itn_plan() {
     if (device >= 0) {
       (void)hipDeviceSynchronize();
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);
+      if (exec_pe) (void)hipGraphExecDestroy(exec_pe);
+      if (graph_pe) (void)hipGraphDestroy(graph_pe);
       if (cap) (void)hipStreamDestroy(cap);
       for (void* p : {(void*)dtab, psiT, X, Z, Lp, Rp, zero})
         if (p) (void)hipFree(p);
@@ -503,7 +514,10 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   pl.out_elems = P.elems;
   pl.out_blocks = P.blocks;
   pl.out_off = P.off;
-  pl.sig = sig_of(L) + "|" + sig_of(R) + "|" + sig_of(P) + "|" + std::to_string(nv) + "|" +
+  pl.sigL = sig_of(L);
+  pl.sigR = sig_of(R);
+  pl.sigP = sig_of(P);
+  pl.sig = pl.sigL + "|" + pl.sigR + "|" + pl.sigP + "|" + std::to_string(nv) + "|" +
            std::to_string(prec);
   pl.sig_hash = std::hash<std::string>()(pl.sig);
 
@@ -861,9 +875,10 @@ hipError_t stage_launch(itn_plan& pl, int stage, int mode, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int cfg4) {
+itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int cfg4,
+                      bool with_env = true) {
   QnPtrs* ptrs = &pl.dptrs->p;
-  {
+  if (with_env) {
     Prof pf(h, "qn_env_repack", s);
     ITN_HIP(h, qn_block_copy(pl.pt, ptrs, pl.Lp, pl.Rp, pl.dcp, (int64_t)pl.cp.size(), s));
   }
@@ -1085,40 +1100,83 @@ itn_status itn_plan_out_blocks(const itn_plan* pl, int32_t* block_sec, int64_t* 
   return ITN_OK;
 }
 
-itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, const itn_tensor* R,
-                             const itn_tensor* psi, itn_tensor* out, void* hip_stream) {
-  if (!h) return ITN_E_ARG;
-  if (!pl || !L || !R || !psi || !out) return fail(h, ITN_E_ARG, "null argument");
-  // operands must carry the structure the plan was built from
-  {
-    static const int aL[3] = {+1, -1, -1}, aR[3] = {-1, +1, +1}, aP[4] = {+1, +1, +1, -1};
-    QTensor Lq, Rq, Pq, Oq;
-    ITN_TRY(read_qtensor(h, L, 3, aL, Lq, "L", true));
-    ITN_TRY(read_qtensor(h, R, 3, aR, Rq, "R", true));
-    ITN_TRY(read_qtensor(h, psi, 4, aP, Pq, "psi", true));
-    ITN_TRY(read_qtensor(h, out, 4, aP, Oq, "out", true));
-    const std::string sg = sig_of(Lq) + "|" + sig_of(Rq) + "|" + sig_of(Pq) + "|" +
-                           std::to_string(pl->nv) + "|" + std::to_string(pl->prec);
-    if (sg != pl->sig) return fail(h, ITN_E_SHAPE, "operands differ from the plan's structure");
-    if (sig_of(Oq) != sig_of(Pq)) return fail(h, ITN_E_SHAPE, "out must have psi's structure");
-  }
+// Structure and dtype checks of environments against the plan.
+static itn_status check_env(itn_handle* h, const itn_plan* pl, const itn_tensor* L, const itn_tensor* R) {
+  static const int aL[3] = {+1, -1, -1}, aR[3] = {-1, +1, +1};
+  QTensor Lq, Rq;
+  ITN_TRY(read_qtensor(h, L, 3, aL, Lq, "L", true));
+  ITN_TRY(read_qtensor(h, R, 3, aR, Rq, "R", true));
+  if (sig_of(Lq) != pl->sigL || sig_of(Rq) != pl->sigR)
+    return fail(h, ITN_E_SHAPE, "operands differ from the plan's structure");
   if (L->dtype != pl->pt || R->dtype != pl->pt)
     return fail(h, ITN_E_DTYPE, "L and R must be stored in the plan's compute type");
-  if (psi->dtype != pl->psi_dt) return fail(h, ITN_E_DTYPE, "psi dtype differs from the plan's");
-  if (out->dtype != ITN_F64 && out->dtype != ITN_F32)
-    return fail(h, ITN_E_DTYPE, "out must be F64 or F32");
+  return ITN_OK;
+}
+
+static itn_status ensure_device(itn_handle* h, itn_plan* pl) {
   if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (pl->device < 0) {
-    pl->out_dt = out->dtype;
     ITN_TRY(upload(h, *pl));
   } else if (pl->device != h->device) {
     return fail(h, ITN_E_ARG, "plan was uploaded to another device");
   }
-  if (out->dtype != pl->out_dt) return fail(h, ITN_E_DTYPE, "out dtype differs from the first apply");
+  return ITN_OK;
+}
+
+itn_status itn_qn_prepare_env(itn_handle* h, itn_plan* pl, const itn_tensor* L, const itn_tensor* R,
+                              void* hip_stream) {
+  if (!h) return ITN_E_ARG;
+  if (!pl || !L || !R) return fail(h, ITN_E_ARG, "null argument");
+  ITN_TRY(check_env(h, pl, L, R));
+  ITN_TRY(ensure_device(h, pl));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   QnDevPtrs v{};
   v.p.L = L->data;
   v.p.R = R->data;
+  v.g1 = GBases{pl->Lp, pl->psiT, pl->X, pl->zero};
+  v.g4 = GBases{pl->Z, pl->Rp, nullptr, pl->zero};
+  ITN_HIP(h, qn_set_ptrs(pl->dptrs, v, s));
+  {
+    Prof pf(h, "qn_env_repack", s);
+    ITN_HIP(h, qn_block_copy(pl->pt, &pl->dptrs->p, pl->Lp, pl->Rp, pl->dcp, (int64_t)pl->cp.size(), s));
+  }
+  pl->envL = L->data;
+  pl->envR = R->data;
+  pl->env_ready = true;
+  return ITN_OK;
+}
+
+itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, const itn_tensor* R,
+                             const itn_tensor* psi, itn_tensor* out, void* hip_stream) {
+  if (!h) return ITN_E_ARG;
+  if (!pl || !psi || !out) return fail(h, ITN_E_ARG, "null argument");
+  const bool prepared = !L && !R;
+  if (!prepared && (!L || !R)) return fail(h, ITN_E_ARG, "pass both L and R, or neither (prepared)");
+  if (prepared && !pl->env_ready)
+    return fail(h, ITN_E_ARG, "no prepared environments: call itn_qn_prepare_env first");
+  // operands must carry the structure the plan was built from
+  {
+    static const int aP[4] = {+1, +1, +1, -1};
+    QTensor Pq, Oq;
+    if (!prepared) ITN_TRY(check_env(h, pl, L, R));
+    ITN_TRY(read_qtensor(h, psi, 4, aP, Pq, "psi", true));
+    ITN_TRY(read_qtensor(h, out, 4, aP, Oq, "out", true));
+    if (sig_of(Pq) != pl->sigP) return fail(h, ITN_E_SHAPE, "operands differ from the plan's structure");
+    if (sig_of(Oq) != sig_of(Pq)) return fail(h, ITN_E_SHAPE, "out must have psi's structure");
+  }
+  if (psi->dtype != pl->psi_dt) return fail(h, ITN_E_DTYPE, "psi dtype differs from the plan's");
+  if (out->dtype != ITN_F64 && out->dtype != ITN_F32)
+    return fail(h, ITN_E_DTYPE, "out must be F64 or F32");
+  ITN_TRY(ensure_device(h, pl));
+  if (!pl->out_set) {
+    pl->out_dt = out->dtype;
+    pl->out_set = true;
+  }
+  if (out->dtype != pl->out_dt) return fail(h, ITN_E_DTYPE, "out dtype differs from the first apply");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  QnDevPtrs v{};
+  v.p.L = prepared ? pl->envL : L->data;
+  v.p.R = prepared ? pl->envR : R->data;
   v.p.psi = psi->data;
   v.p.out = out->data;
   v.g1 = GBases{pl->Lp, pl->psiT, pl->X, pl->zero};
@@ -1127,15 +1185,23 @@ itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, c
     Prof pf(h, "qn_set_ptrs", s);
     ITN_HIP(h, qn_set_ptrs(pl->dptrs, v, s));
   }
+  // an apply with environments repacks them: later prepared applies use these
+  if (!prepared) {
+    pl->envL = L->data;
+    pl->envR = R->data;
+    pl->env_ready = true;
+  }
   if (!pl->tuned) ITN_TRY(autotune(h, *pl, s));
   if (h->prof_on) {  // per-kernel timing: run the launches directly
-    ITN_TRY(launch_all(h, *pl, s, pl->cfg1, pl->cfg4));
+    ITN_TRY(launch_all(h, *pl, s, pl->cfg1, pl->cfg4, !prepared));
     return ITN_OK;
   }
-  if (!pl->exec) {
-    ITN_HIP(h, hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+  hipGraph_t& graph = prepared ? pl->graph_pe : pl->graph;
+  hipGraphExec_t& exec = prepared ? pl->exec_pe : pl->exec;
+  if (!exec) {
+    if (!pl->cap) ITN_HIP(h, hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
     ITN_HIP(h, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-    const itn_status st = launch_all(h, *pl, pl->cap, pl->cfg1, pl->cfg4);
+    const itn_status st = launch_all(h, *pl, pl->cap, pl->cfg1, pl->cfg4, !prepared);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(pl->cap, &g);
     if (st != ITN_OK) {
@@ -1143,10 +1209,10 @@ itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, c
       return st;
     }
     ITN_HIP(h, e);
-    pl->graph = g;
-    ITN_HIP(h, hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+    graph = g;
+    ITN_HIP(h, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   }
-  ITN_HIP(h, hipGraphLaunch(pl->exec, s));
+  ITN_HIP(h, hipGraphLaunch(exec, s));
   return ITN_OK;
 }
 

@@ -164,3 +164,44 @@ def test_qn_wstage_kernels_parity(h, monkeypatch, wk, make):
     for prec in ("f64", "bf16"):
         _, _, got = _run(h, ops, W1, W2, prec, 2, [ops[4], _perturbed(ops[4], 7)])
         assert rel_err(got, _ref(ops, [ops[4], _perturbed(ops[4], 7)])) <= TOL[prec], (wk, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_qn_prepared_environments(h, prec):
+    """Applies with environments prepared once (itn_qn_prepare_env, L = R =
+    NULL) give the same output as applies that pass L and R, across new psi
+    buffers and a second environment pair; a prepared apply on a fresh plan,
+    or with only one environment, is an argument error."""
+    ops, W1, W2 = U.small_u1u1()
+    L, w1, w2, R, psi = ops
+    Ld, Rd = _gpu_desc(L, TDT[prec]), _gpu_desc(R, TDT[prec])
+    Pd, _ = U.desc(psi, with_data=False)
+    Pd["data"] = torch.as_tensor(psi.packed()[2], device=DEV)
+    Od = dict(Pd)
+    Od["data"] = torch.zeros_like(Pd["data"])
+    plan = h.qn_plan(Ld, U.mpo_desc(W1, w1), U.mpo_desc(W2, w2), Rd, Pd, nv=1, prec=prec)
+    with pytest.raises(itn.ItnError):
+        h.qn_apply(plan, None, None, Pd, Od)  # nothing prepared yet
+    with pytest.raises(itn.ItnError):
+        h.qn_apply(plan, Ld, None, Pd, Od)
+    # a second environment pair of the same structure (scaled values)
+    L2d, R2d = dict(Ld), dict(Rd)
+    L2d["data"] = Ld["data"] * 0.5
+    R2d["data"] = Rd["data"] * 2.0
+    for envs in ((Ld, Rd), (L2d, R2d)):
+        plan.prepare_env(*envs)
+        for seed in (1, 2):
+            p2 = _perturbed(psi, seed)
+            P2 = dict(Pd)
+            P2["data"] = torch.as_tensor(p2.packed()[2], device=DEV)
+            Oa, Ob = dict(Od), dict(Od)
+            Oa["data"] = torch.full_like(P2["data"], float("nan"))
+            Ob["data"] = torch.full_like(P2["data"], float("nan"))
+            h.qn_apply(plan, None, None, P2, Oa)
+            h.qn_apply(plan, envs[0], envs[1], P2, Ob)
+            torch.cuda.synchronize()
+            a, b = Oa["data"].cpu().numpy(), Ob["data"].cpu().numpy()
+            assert np.array_equal(a, b), (prec, seed)
+            # (0.5 L, 2 R): exact power-of-two scalings, the same H_eff
+            ref = Q.heff_apply_blocks(L, w1, w2, R, p2).packed()[2]
+            assert rel_err(a, ref) <= TOL[prec], (prec, seed)
