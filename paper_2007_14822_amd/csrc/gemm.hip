@@ -185,20 +185,45 @@ template <int P> static bool direct_ok(const GemmArgs& g) {
          (g.sA * es) % 16 == 0 && (g.sB * es) % 16 == 0 && g.K % bk == 0 && g.K > 0;
 }
 
+// Compute units of the current device (cached per device).
+static int64_t device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    cache[dev] = c;
+  }
+  return cache[dev];
+}
+
 template <int P, typename TOut>
 static hipError_t dispatch_nt(const GemmArgs& g, hipStream_t s) {
   // Largest tile that still gives every CU at least one workgroup; small
   // problems use 64x64 tiles so that the launch spreads over the CUs.
   auto ntiles = [&](int bm, int bn) { return ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.batch; };
+  const int64_t cus = device_cus();
   // Direct-to-LDS tiles of 8 waves: 256 x 256 for 4-byte accumulators
   // (128 accumulator registers per lane); FP64 accumulators are twice as
   // wide, so FP64 uses 256 x 128.
   if constexpr (P == P_F64) {
-    if (g.M >= 256 && g.N >= 128 && ntiles(256, 128) >= 256 && direct_ok<P>(g))
+    if (g.M >= 256 && g.N >= 128 && ntiles(256, 128) >= cus && direct_ok<P>(g))
       return launch_nt_direct<P, 256, 128, 2, 4, TOut>(g, s);
   } else {
-    if (g.M >= 256 && g.N >= 256 && ntiles(256, 256) >= 256 && direct_ok<P>(g))
+    if (g.M >= 256 && g.N >= 256 && ntiles(256, 256) >= cus && direct_ok<P>(g)) {
+      // Rounds of one tile per CU: a last round that fills a quarter of the
+      // CUs costs a whole round.  192 x 256 tiles run at about 0.85 of the
+      // 256 x 256 rate per flop (measured); take them when their rounds
+      // cost less, e.g. M = 9 * 2048 (576 tiles of 256 x 256 = 2.25 rounds
+      // against 768 of 192 x 256 = 3 full rounds).
+      auto rounds = [&](int bm, int bn) { return (ntiles(bm, bn) + cus - 1) / cus; };
+      const double c256 = (double)rounds(256, 256) * 256.0 * 256.0;
+      const double c192 = (double)rounds(192, 256) * 192.0 * 256.0 / 0.85;
+      if (c192 < c256) return launch_nt_direct<P, 192, 256, 2, 4, TOut>(g, s);
       return launch_nt_direct<P, 256, 256, 2, 4, TOut>(g, s);
+    }
   }
   if (g.M >= 128 && g.N >= 128 && ntiles(128, 128) >= 256) return launch_nt<P, 128, 128, TOut>(g, s);
   return launch_nt<P, 64, 64, TOut>(g, s);

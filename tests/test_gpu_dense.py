@@ -46,7 +46,8 @@ CONTRACT_CASES = [
     ({1: 6, 2: 5}, [1], [2], [1, 2]),                                      # outer product
     ({1: 6, 2: 5, 3: 4}, [1, 2, 3], [3, 1, 2], []),                        # inner product
     ({1: 130, 2: 70, 3: 129, 4: 3}, [1, 4, 2], [2, 3, 4], [3, 1]),         # several tiles
-    ({1: 4000, 2: 192, 3: 4100}, [1, 2], [3, 2], [1, 3]),                  # 256x256 tiles, ragged
+    ({1: 4000, 2: 192, 3: 4100}, [1, 2], [3, 2], [1, 3]),                  # 192x256 tiles, ragged
+    ({1: 4000, 2: 192, 3: 4096}, [1, 2], [3, 2], [1, 3]),                  # 256x256 tiles, ragged
 ]
 
 
@@ -160,14 +161,16 @@ def test_heff_on_canonical_envs(h, chi):
         assert rel_err(host(out), ref) <= TOL[prec], prec
 
 
-def test_heff_full_size_sampled_rows(h):
-    """chi = 2048, the benchmark's workload and launch configuration: the
-    environments are built on the GPU (FP64 environment steps, checked
-    against the oracle at smaller sizes) and 6 output rows a' are compared
-    with the oracle."""
+@pytest.mark.parametrize("d", [2, 3])
+def test_heff_full_size_sampled_rows(h, d):
+    """chi = 2048, the benchmark's workloads and launch configurations (d = 2:
+    256x256 stage-4 tiles; d = 3: the 45-channel fused kernel and 192x256
+    stage-4 tiles): the environments are built on the GPU (FP64 environment
+    steps, checked against the oracle at smaller sizes) and 6 output rows a'
+    are compared with the oracle."""
     import torch as _t
     from bench import build_workload
-    L64, W1, W2, R64, psi = build_workload(h, 2048, 2, _t, np, inp)
+    L64, W1, W2, R64, psi = build_workload(h, 2048, d, _t, np, inp)
     rows = [0, 1, 777, 1024, 2046, 2047]
     Lh, Rh, ph = host(L64), host(R64), host(psi)
     ref = hf.heff_apply_rows(Lh, W1, W2, Rh, ph, rows)
