@@ -107,6 +107,7 @@ hipError_t permute_cast(int in_dtype, const void* in, int out_dtype, void* out, 
 // lane writes two consecutive r of an output row.
 constexpr int TT = 64;
 template <typename TO> struct alignas(2 * sizeof(TO)) Pair { TO v[2]; };
+template <typename TI> struct alignas(16) TW2 { TI v[2]; };
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ in,
                                                          TO* __restrict__ out, TransposeArgs t,
@@ -120,11 +121,25 @@ __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ i
   const TI* ip = in + zb * t.in_zb + zc * t.in_zc;
   TO* op = out + zb * t.out_zb + zc * t.out_zc;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  using TW = typename std::conditional<sizeof(TI) == 8, double, float>::type;  // exact widening of TI
+  // 8-byte inputs, unit stride along c, full tile, 16-byte aligned rows:
+  // two consecutive c (16 bytes) per lane, 8 rows per pass.
+  const bool wide_in = sizeof(TI) == 8 && t.in_c == 1 && r0 + TT <= t.rows && c0 + TT <= t.cols &&
+                       (t.in_r % 2) == 0 && (reinterpret_cast<uintptr_t>(ip) % 16) == 0;
+  if (wide_in) {
+    const int c2 = (threadIdx.x & 31) * 2, ry = threadIdx.x >> 5;  // 32 pairs x 8 rows
+#pragma unroll
+    for (int i = ry; i < TT; i += 8) {
+      const TW2<TI> v2 = *reinterpret_cast<const TW2<TI>*>(ip + (r0 + i) * t.in_r + c0 + c2);
+      tile[i][c2] = (TS)(TW)v2.v[0];
+      tile[i][c2 + 1] = (TS)(TW)v2.v[1];
+    }
+  } else {
 #pragma unroll 4
-  for (int i = ty; i < TT; i += 4) {
-    const int64_t r = r0 + i, c = c0 + tx;
-    using TW = typename std::conditional<sizeof(TI) == 8, double, float>::type;  // exact widening of TI
-    if (r < t.rows && c < t.cols) tile[i][tx] = (TS)(TW)ip[r * t.in_r + c * t.in_c];
+    for (int i = ty; i < TT; i += 4) {
+      const int64_t r = r0 + i, c = c0 + tx;
+      if (r < t.rows && c < t.cols) tile[i][tx] = (TS)(TW)ip[r * t.in_r + c * t.in_c];
+    }
   }
   __syncthreads();
   if constexpr (sizeof(TO) == 2) {
