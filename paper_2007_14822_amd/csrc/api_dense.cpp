@@ -598,7 +598,8 @@ static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const
     const int64_t bk = 128 / es;
     CSR fcsr;
     bool fused = heff_fused_supported(P, (int)w, (int)d2) && cl % bk == 0 && cl > 0 &&
-                 (reinterpret_cast<uintptr_t>(Lp) & 15) == 0;
+                 (reinterpret_cast<uintptr_t>(Lp) & 15) == 0 &&
+                 heff_fused_fits(P, cl, cr, (int)w, (int)d2, (int)nv);
     if (fused) {
       // CSR with input index m0*d2 + c and output row c'*w + m2.
       fcsr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),

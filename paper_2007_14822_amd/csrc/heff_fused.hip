@@ -20,6 +20,18 @@
 
 namespace itn {
 
+// Raw buffer descriptor over [base, base + bytes) (bytes < 2^31); the third
+// descriptor word selects 32-bit data for untyped buffer loads.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+// 16 bytes per lane from base + voff + soff into LDS at lds_wave_base + 16 * lane.
+__device__ __forceinline__ void lds_buffer16(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff,
+                                             void* lds_wave_base) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds_wave_base, 16,
+                                           voff, soff, 0, 0);
+}
+
 template <int P, int W, int C, int WM, int WN, int RA, int RB> struct FusedCfg {
   using T = typename PT<P>::T;
   using Acc = typename PT<P>::Acc;
@@ -96,34 +108,43 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc[m][i][c][j][e] = 0;
 
-  // direct-to-LDS row sources (see gemm_core.h for the swizzle)
+  // Direct-to-LDS row sources (see gemm_core.h for the swizzle), through
+  // buffer descriptors: uniform 64-bit bases, one 32-bit lane offset per
+  // operand, and per pass a uniform byte offset.  Tile row r = p*RPP + slab
+  // of A is (m0, a') = (r / TA, a0 + r % TA); RPP is a multiple of TA and
+  // of TY, so the lane part of the row (r % TA, r / TA - p*RPP/TA) is the
+  // same in every pass and the pass adds p*(RPP/TA) rows of m0 (likewise
+  // for B's (c, y)).  Both operands are below 2^31 bytes (checked by the
+  // launcher).  Rows beyond chi_l (or Y) are clamped to the last row.
+  static_assert(Cfg::RPP % Cfg::TA == 0 && Cfg::RPP % Cfg::TY == 0, "pass stride vs tile rows");
   const int lrow = lane >> 3, lpos = lane & 7;
   const int slab = wave * 8 + lrow;
   const int64_t chunk = (int64_t)((lpos ^ lrow) * Cfg::E16);
-  auto srcA = [&](int p) -> const T* {
-    const int r = p * Cfg::RPP + slab;                 // tile row (m0, a')
-    const int m0 = r / Cfg::TA;
-    int64_t ap = a0 + r % Cfg::TA;
+  constexpr int ES = (int)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rsA = make_rsrc(Lp, cl * W * cl * ES);
+  const __amdgpu_buffer_rsrc_t rsB = make_rsrc(Bp, (int64_t)C * Y * cl * ES);
+  uint32_t voffA, voffB;
+  {
+    int64_t ap = a0 + slab % Cfg::TA;
     if (ap >= cl) ap = cl - 1;
-    return Lp + (ap * W + m0) * cl + chunk;
-  };
-  auto srcB = [&](int p) -> const T* {
-    const int r = p * Cfg::RPP + slab;                 // tile row (c, y)
-    const int c = r / Cfg::TY;
-    int64_t y = y0 + r % Cfg::TY;
+    voffA = (uint32_t)(((ap * W + slab / Cfg::TA) * cl + chunk) * ES);
+    int64_t y = y0 + slab % Cfg::TY;
     if (y >= Y) y = Y - 1;
-    return Bp + ((int64_t)c * Y + y) * cl + chunk;
-  };
+    voffB = (uint32_t)((((int64_t)(slab / Cfg::TY) * Y + y) * cl + chunk) * ES);
+  }
+  const uint32_t passA = (uint32_t)((Cfg::RPP / Cfg::TA) * cl * ES);      // one pass: RPP/TA more m0
+  const uint32_t passB = (uint32_t)((Cfg::RPP / Cfg::TY) * Y * cl * ES);  // RPP/TY more c
   auto issue = [&](int buf, int64_t k0) {
     char* base = lds + buf * Cfg::STAGE_BYTES + wave * 8 * ROW_BYTES;
+    const uint32_t kb = (uint32_t)(k0 * ES);
 #pragma unroll
     for (int p = 0; p < Cfg::A_PASSES; ++p)
       if (p * Cfg::RPP + wave * 8 < Cfg::AROWS)
-        lds_direct16(srcA(p) + k0, base + p * Cfg::RPP * ROW_BYTES);
+        lds_buffer16(rsA, voffA, p * passA + kb, base + p * Cfg::RPP * ROW_BYTES);
 #pragma unroll
     for (int p = 0; p < Cfg::B_PASSES; ++p)
       if (p * Cfg::RPP + wave * 8 < Cfg::BROWS)
-        lds_direct16(srcB(p) + k0, base + (Cfg::AROWS + p * Cfg::RPP) * ROW_BYTES);
+        lds_buffer16(rsB, voffB, p * passB + kb, base + (Cfg::AROWS + p * Cfg::RPP) * ROW_BYTES);
   };
 
   if (nk > 0) {
@@ -137,14 +158,15 @@ __global__ __launch_bounds__(64 * WM * WN) void heff_fused_kernel(HeffFusedArgs 
   auto kstep = [&](const char* __restrict__ cur, char* __restrict__ nxt, bool more, int64_t k0) {
     if (more) {
       char* base = nxt + wave * 8 * ROW_BYTES;
+      const uint32_t kb = (uint32_t)(k0 * ES);
 #pragma unroll
       for (int p = 0; p < Cfg::A_PASSES; ++p)
         if (p * Cfg::RPP + wave * 8 < Cfg::AROWS)
-          lds_direct16(srcA(p) + k0, base + p * Cfg::RPP * ROW_BYTES);
+          lds_buffer16(rsA, voffA, p * passA + kb, base + p * Cfg::RPP * ROW_BYTES);
 #pragma unroll
       for (int p = 0; p < Cfg::B_PASSES; ++p)
         if (p * Cfg::RPP + wave * 8 < Cfg::BROWS)
-          lds_direct16(srcB(p) + k0, base + (Cfg::AROWS + p * Cfg::RPP) * ROW_BYTES);
+          lds_buffer16(rsB, voffB, p * passB + kb, base + (Cfg::AROWS + p * Cfg::RPP) * ROW_BYTES);
     }
     const char* As = cur;
     const char* Bs = As + Cfg::AROWS * ROW_BYTES;
@@ -309,8 +331,15 @@ template <int P> static hipError_t fused_p(const HeffFusedArgs& a, hipStream_t s
   return hipErrorInvalidValue;
 }
 
+bool heff_fused_fits(int prec, int64_t chi_l, int64_t chi_r, int w, int d2, int nv) {
+  const int64_t es = prec == P_F64 ? 8 : prec == P_F32 ? 4 : 2;
+  const int64_t lim = (int64_t)1 << 31;  // buffer-descriptor range of each operand
+  return chi_l * w * chi_l * es < lim && (int64_t)d2 * nv * chi_r * chi_l * es < lim;
+}
+
 hipError_t heff_stage1_fused(int prec, const HeffFusedArgs& a, hipStream_t s) {
   if (!heff_fused_supported(prec, a.w, a.d2)) return hipErrorInvalidValue;
+  if (!heff_fused_fits(prec, a.chi_l, a.chi_r, a.w, a.d2, a.nv)) return hipErrorInvalidValue;
   // the epilogue unrolls over all w*d2 output rows of W12
   if (a.nrows != a.w * a.d2 || !heff_fused_table_fits(a.nrows, a.nnz)) return hipErrorInvalidValue;
   switch (prec) {

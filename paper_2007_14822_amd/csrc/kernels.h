@@ -199,6 +199,9 @@ struct HeffFusedArgs {
 };
 bool heff_fused_supported(int prec, int w, int d2);
 bool heff_fused_table_fits(int nrows, int64_t nnz);
+// L and psiT each below 2^31 bytes (the kernel addresses them through buffer
+// descriptors); larger problems take the unfused path.
+bool heff_fused_fits(int prec, int64_t chi_l, int64_t chi_r, int w, int d2, int nv);
 hipError_t heff_stage1_fused(int prec, const HeffFusedArgs& a, hipStream_t s);
 
 // Element-wise conversion of a contiguous buffer.
