@@ -82,8 +82,8 @@ hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, v
 // -------------------------------------------------------------- W-stage
 // Streaming variant (pairs with too many inputs for LDS): one workgroup per
 // item of QN_WSTAGE_POS positions (a', b) of a pair, two
-// per thread; the pair's entries are taken four at a time, so every thread
-// has eight independent X loads in flight before it accumulates.
+// per thread; the pair's entries are taken eight at a time, so every thread
+// has sixteen independent X loads in flight before it accumulates.
 template <typename TX, typename TZ>
 __global__ __launch_bounds__(256) void qn_wstage_kernel(const TX* __restrict__ X, TZ* __restrict__ Z,
                                                          const QnWPair* __restrict__ pairs,
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void qn_wstage_kernel(const TX* __restrict__ X
                                                          int64_t x_bs, int64_t z_bs) {
   using A = typename std::conditional<sizeof(TX) == 8, double, float>::type;
   constexpr int NP = QN_WSTAGE_POS / 256;
-  constexpr int NE = 4;
+  constexpr int NE = 8;
   const QnWItem it = items[blockIdx.x];
   const QnWPair pr = pairs[it.pair];
   const int npos = pr.da * pr.db;
