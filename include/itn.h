@@ -53,7 +53,7 @@ typedef enum {
   ITN_E_WORKSPACE = 7,     /* workspace allocation failed                               */
   ITN_E_HIP = 8,           /* a HIP / rocSOLVER call failed                             */
   ITN_E_NOT_CONVERGED = 9, /* eigensolver stopped above its tolerance (result kept)     */
-  ITN_E_UNSUPPORTED = 10,  /* valid request this build does not implement               */
+  ITN_E_UNSUPPORTED = 10,  /* valid request the library does not implement              */
   ITN_E_NODEVICE = 11      /* compute call on a host-only handle                        */
 } itn_status;
 
