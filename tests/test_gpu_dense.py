@@ -114,6 +114,8 @@ HEFF_CASES = [
     (128, 96, 2, 5, 2, "heis"),    # fused first stage (all precisions), ragged chi_r
     (192, 70, 3, 5, 1, "heis"),    # fused first stage for d = 3 (bf16, f32)
     (64, 200, 2, 5, 3, "rand"),    # fused, random sparse W, y tiles straddle vectors
+    (48, 40, 2, 5, 2, "heis"),     # fused f64 with a ragged a' tile (32-row tiles)
+    (96, 72, 2, 5, 2, "heis"),     # fused f32 with a ragged a' tile (64-row tiles)
 ]
 
 
