@@ -508,7 +508,10 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   const QSpace& SM2 = R.sp[1];  // m2 sectors
   pl.prec = prec;
   pl.pt = prec == ITN_P_F64 ? D_F64 : (prec == ITN_P_F32 ? D_F32 : D_BF16);
-  pl.xt = prec == ITN_P_F64 ? D_F64 : D_F32;
+  // X (stage 1's output) is the W-stage's operand: stored at the operand
+  // precision (bf16 for bf16 applies: half the bytes of the HBM-bound
+  // W-stage), accumulated in f32 by the W-stage.
+  pl.xt = pl.pt;
   pl.psi_dt = Pt->dtype;
   pl.nv = nv;
   pl.out_elems = P.elems;
@@ -737,7 +740,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   }
   // W-stage item lists, one per kernel candidate
   {
-    const int64_t xsz = pl.xt == D_F64 ? 8 : 4;
+    const int64_t xsz = pl.xt == D_F64 ? 8 : 4;  // LDS holds X in the accumulation type
     for (int c = 0; c < 4; ++c) {
       const int t = itn_plan::kWCand[c];
       pl.wok[c] = t == 0 || pl.max_nin * t * xsz <= 144 * 1024;

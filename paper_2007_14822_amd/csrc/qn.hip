@@ -232,6 +232,7 @@ hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnW
   if (x_dtype == D_F64 && z_dtype == D_F64) ITN_QW(double, double);
   if (x_dtype == D_F32 && z_dtype == D_F32) ITN_QW(float, float);
   if (x_dtype == D_F32 && z_dtype == D_BF16) ITN_QW(float, bf16_t);
+  if (x_dtype == D_BF16 && z_dtype == D_BF16) ITN_QW(bf16_t, bf16_t);
 #undef ITN_QW
   return hipErrorInvalidValue;
 }
