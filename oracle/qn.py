@@ -224,10 +224,14 @@ def contract_blocks(A: BlockTensor, la: Sequence[int], B: BlockTensor, lb: Seque
     allv = sorted(set(la) | set(lb))
     m = {l: letters[k] for k, l in enumerate(allv)}
     sub = "".join(m[l] for l in la) + "," + "".join(m[l] for l in lb) + "->" + "".join(m[l] for l in lc)
+    # B's blocks by their contracted sectors: the pairs visited, and their
+    # order (ascending ka, then ascending kb), are those of a full double loop
+    # that skips pairs whose contracted sectors differ.
+    by_sec: Dict[Tuple[int, ...], List[Tuple[int, ...]]] = {}
+    for kb in sorted(B.blocks):
+        by_sec.setdefault(tuple(kb[lb.index(l)] for l in common), []).append(kb)
     for ka in sorted(A.blocks):
-        for kb in sorted(B.blocks):
-            if any(ka[la.index(l)] != kb[lb.index(l)] for l in common):
-                continue
+        for kb in by_sec.get(tuple(ka[la.index(l)] for l in common), []):
             sec = {}
             for l, k in zip(la, ka):
                 sec[l] = k
