@@ -7,7 +7,10 @@ load the library; the first call does, and raises if it is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -78,6 +81,31 @@ def _dense(keep: _Keep, t, labels: Optional[Sequence[int]] = None, shape=None) -
     return tt
 
 
+# Library objects still alive at interpreter exit are freed by an atexit hook
+# (registered when the first handle is created, so it runs before torch's own
+# exit handlers and while the HIP runtime is still up): plans and MPS/MPO
+# objects first, then the handles that own their device resources.  After
+# that, and during interpreter finalisation, __del__ does nothing.
+_live_objects: "weakref.WeakSet" = weakref.WeakSet()
+_live_handles: "weakref.WeakSet" = weakref.WeakSet()
+_exit_hook = False
+
+
+def _close_all():
+    for o in list(_live_objects):
+        o.close()
+    for h in list(_live_handles):
+        h.close()
+
+
+def _register(obj, handle: bool = False):
+    global _exit_hook
+    if not _exit_hook:
+        atexit.register(_close_all)
+        _exit_hook = True
+    (_live_handles if handle else _live_objects).add(obj)
+
+
 def _stream_ptr(stream=None):
     import torch
     if stream is None:
@@ -97,13 +125,24 @@ class Handle:
             raise ItnError(st, "itn_create(device=%d) failed" % device)
         self.h = h
         self.device = device
+        _register(self, handle=True)
 
     def close(self):
+        """Free the handle (its workspace, tables and solver state).  Objects
+        made from it (plans, MPS, MPO) should be closed first."""
         if getattr(self, "h", None):
             self.lib.itn_destroy(self.h)
             self.h = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -156,6 +195,28 @@ class Handle:
                                           PREC[prec], self._sp(stream)))
         return Cout
 
+    def _check_vectors(self, psi, out, n1: int, nv: int):
+        """psi and out must each hold exactly nv vectors of n1 elements, be
+        contiguous tensors on this handle's device (any tensor on a host-only
+        handle, which validates and then refuses the work), and not overlap
+        (the library sees only their base pointers)."""
+        if nv < 1:
+            raise ValueError("nv must be >= 1")
+        for name, t in (("psi", psi), ("out", out)):
+            if isinstance(t, np.ndarray) or not hasattr(t, "data_ptr"):
+                raise TypeError("%s must be a device tensor" % name)
+            if self.device >= 0 and (t.device.type != "cuda" or (t.device.index or 0) != self.device):
+                raise ValueError("%s must live on cuda:%d" % (name, self.device))
+            if not t.is_contiguous():
+                raise ValueError("%s must be contiguous" % name)
+            if t.numel() != nv * n1:
+                raise ValueError("%s holds %d elements, expected nv * chi_l*d*d*chi_r = %d"
+                                 % (name, t.numel(), nv * n1))
+        pa, pb = psi.data_ptr(), out.data_ptr()
+        na, nb = psi.numel() * psi.element_size(), out.numel() * out.element_size()
+        if pa < pb + nb and pb < pa + na:
+            raise ValueError("out must not overlap psi")
+
     def heff_apply(self, Lenv, W1: np.ndarray, W2: np.ndarray, Renv, psi, out, nv: int = 1,
                    prec: str = "f64", stream=None):
         """psi/out: contiguous device tensors holding nv vectors
@@ -163,6 +224,7 @@ class Handle:
         cl, cr = Lenv.shape[0], Renv.shape[0]
         d = W1.shape[2]
         shp = (cl, d, d, cr)
+        self._check_vectors(psi, out, cl * d * d * cr, int(nv))
         k = _Keep()
         tl, tr = _dense(k, Lenv), _dense(k, Renv)
         W1c = np.ascontiguousarray(W1, np.float64)
@@ -180,6 +242,7 @@ class Handle:
         cl, cr = terms[0][0].shape[0], terms[0][3].shape[0]
         d = terms[0][1].shape[2]
         shp = (cl, d, d, cr)
+        self._check_vectors(psi, out, cl * d * d * cr, int(nv))
         k = _Keep()
         n = len(terms)
         arrs = {x: (L.itn_tensor * n)() for x in "LABR"}
@@ -223,7 +286,7 @@ class Handle:
         self._check(self.lib.itn_mpo_create(self.h, N, w, d,
                                             W.ctypes.data_as(C.POINTER(C.c_double)),
                                             C.byref(out)))
-        return _Owned(self.lib.itn_mpo_destroy, out, N=N, w=w, d=d)
+        return _Owned(self, self.lib.itn_mpo_destroy, out, N=N, w=w, d=d)
 
     def mps(self, As):
         """Upload an MPS given as a list of N host arrays [bond_l, d, bond_r]
@@ -237,7 +300,7 @@ class Handle:
         self._check(self.lib.itn_mps_create(self.h, N, d, bd,
                                             flat.ctypes.data_as(C.POINTER(C.c_double)),
                                             C.byref(out)))
-        return _Owned(self.lib.itn_mps_destroy, out, N=N, d=d)
+        return _Owned(self, self.lib.itn_mps_destroy, out, N=N, d=d)
 
     def mps_bonds(self, mps):
         b = (C.c_int32 * (mps.N + 1))()
@@ -379,6 +442,7 @@ class Plan:
         self.handle = handle
         self.lib = handle.lib
         self.ptr = ptr
+        _register(self)
 
     def info(self):
         i = L.itn_plan_info()
@@ -417,11 +481,16 @@ class Plan:
         apply.keep = (k, ts, Ld, Rd, Pd, Od)
         return apply
 
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.lib.itn_plan_destroy(self.ptr)
+            self.ptr = None
+
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
-            if self.ptr:
-                self.lib.itn_plan_destroy(self.ptr)
-                self.ptr = None
+            self.close()
         except Exception:
             pass
 
@@ -430,18 +499,26 @@ Handle.qn_plan, Handle.qn_allowed_blocks, Handle.qn_apply = _qn_handle_methods()
 
 
 class _Owned:
-    """An opaque library object freed with its destroy call."""
+    """An opaque library object (MPS, MPO) freed with its destroy call; it
+    keeps the handle it was made on alive."""
 
-    def __init__(self, destroy, ptr, **info):
+    def __init__(self, handle, destroy, ptr, **info):
+        self.handle = handle
         self._destroy = destroy
         self.ptr = ptr
         for k, v in info.items():
             setattr(self, k, v)
+        _register(self)
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self._destroy(self.ptr)
+            self.ptr = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
-            if self.ptr:
-                self._destroy(self.ptr)
-                self.ptr = None
+            self.close()
         except Exception:
             pass

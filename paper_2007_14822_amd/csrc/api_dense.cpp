@@ -532,11 +532,18 @@ static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const
     if (out->dims[k] != psi->dims[k]) return fail(h, ITN_E_SHAPE, "out must have psi's shape");
   if (psi->dtype == ITN_BF16 || out->dtype == ITN_BF16)
     return fail(h, ITN_E_DTYPE, "psi and out must be F64 or F32");
-  if (psi->data == out->data && cl * d * d * cr > 0) return fail(h, ITN_E_ARG, "out must not alias psi");
   if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
   const int64_t d2 = d * d;
   const int64_t n1 = cl * d2 * cr;  // one vector
   if (n1 == 0) return ITN_OK;
+  if (!psi->data || !out->data) return fail(h, ITN_E_ARG, "psi and out need data");
+  {  // the nv vectors of psi and of out occupy disjoint byte ranges
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(psi->data);
+    const uintptr_t pb = reinterpret_cast<uintptr_t>(out->data);
+    const uintptr_t na = (uintptr_t)(nv * n1) * dtype_size(psi->dtype);
+    const uintptr_t nb = (uintptr_t)(nv * n1) * dtype_size(out->dtype);
+    if (pa < pb + nb && pb < pa + na) return fail(h, ITN_E_ARG, "out must not overlap psi");
+  }
   hipStream_t s = as_stream(hip_stream);
   const int P = prec;
   const int pt = P == ITN_P_F64 ? D_F64 : (P == ITN_P_F32 ? D_F32 : D_BF16);

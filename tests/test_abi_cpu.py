@@ -63,10 +63,13 @@ def test_heff_shape_errors(host):
     with pytest.raises(itn.ItnError) as e:  # L not square in its bonds
         host.heff_apply(_t(4, 5, 3), W, W, _t(4, 5, 4), _t(4, 2, 2, 4), _t(4, 2, 2, 4))
     assert e.value.name == "ITN_E_SHAPE"
-    with pytest.raises(itn.ItnError) as e:  # W with the wrong d
-        host.heff_apply(_t(4, 5, 4), np.zeros((5, 5, 3, 3)), W, _t(4, 5, 4), _t(4, 2, 2, 4),
+    with pytest.raises(itn.ItnError) as e:  # W2 with the wrong d
+        host.heff_apply(_t(4, 5, 4), W, np.zeros((5, 5, 3, 3)), _t(4, 5, 4), _t(4, 2, 2, 4),
                         _t(4, 2, 2, 4))
     assert e.value.name == "ITN_E_SHAPE"
+    with pytest.raises(ValueError):  # W1's d does not fit psi's element count
+        host.heff_apply(_t(4, 5, 4), np.zeros((5, 5, 3, 3)), W, _t(4, 5, 4), _t(4, 2, 2, 4),
+                        _t(4, 2, 2, 4))
     with pytest.raises(itn.ItnError) as e:  # bf16 psi
         host.heff_apply(_t(4, 5, 4), W, W, _t(4, 5, 4), _t(4, 2, 2, 4, dtype=torch.bfloat16),
                         _t(4, 2, 2, 4))
@@ -92,3 +95,36 @@ def test_env_update_errors(host):
 def test_workspace_query(host):
     b = host.heff_workspace_size(2048, 2048, 2, 5, 1, "bf16")
     assert b > 2048 * 2048 * 4 * 2
+
+
+def test_heff_vector_count_and_overlap_checked(host):
+    """The binding checks psi / out against nv before the library sees only
+    base pointers: a short buffer, a wrong nv and overlapping ranges are
+    rejected on the host."""
+    W = np.zeros((5, 5, 2, 2))
+    L, R = _t(4, 5, 4), _t(4, 5, 4)
+    with pytest.raises(ValueError):  # nv = 2 but one vector of psi
+        host.heff_apply(L, W, W, R, _t(4, 2, 2, 4), _t(2, 4, 2, 2, 4), nv=2)
+    with pytest.raises(ValueError):  # out one element short
+        host.heff_apply(L, W, W, R, _t(4, 2, 2, 4), _t(63))
+    buf = _t(3, 64)
+    with pytest.raises(ValueError):  # out overlaps psi by one vector
+        host.heff_apply(L, W, W, R, buf[0:2].reshape(2, 4, 2, 2, 4), buf[1:3].reshape(2, 4, 2, 2, 4),
+                        nv=2)
+    with pytest.raises(ValueError):
+        host.heff_apply_sum([(L, W, W, R)], _t(4, 2, 2, 4), _t(2, 4, 2, 2, 4))
+
+
+def test_objects_close_and_exit_hook():
+    """Handles and plans can be closed explicitly (twice is harmless); the
+    module's exit hook closes whatever is still open."""
+    h2 = itn.Handle(-1)
+    h2.close()
+    h2.close()
+    assert h2.h is None
+    with itn.Handle(-1) as h3:
+        assert h3.h
+    assert h3.h is None
+    h4 = itn.Handle(-1)
+    itn._close_all()
+    assert h4.h is None
