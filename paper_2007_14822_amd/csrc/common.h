@@ -34,9 +34,27 @@ template <> struct PT<P_BF16> {
   static constexpr int E16 = 8;
 };
 
+// Nearest bf16 to a double (ties to even), rounded once.  Narrowing to float
+// first and then to bf16 rounds twice and can land one bf16 step off (a
+// value just above a bf16 midpoint becomes the midpoint in float, which then
+// ties to even).  Narrowing to float with round-to-odd instead (truncate
+// toward zero, set the last significand bit when anything was dropped) keeps
+// the information the second rounding needs, because float carries more
+// than two bits beyond bf16's 8 (Boldo and Melquiond's round-to-odd
+// theorem); the float -> bf16 step is the hardware's nearest-even rounding.
+__device__ __forceinline__ bf16_t bf16_from_double(double x) {
+  float f = (float)x;
+  if ((double)f != x && f == f) {
+    uint32_t u = __float_as_uint(f);
+    if (__builtin_fabs((double)f) > __builtin_fabs(x)) u -= 1u;  // toward zero
+    f = __uint_as_float(u | 1u);
+  }
+  return (bf16_t)f;
+}
+
 // Conversions used at load / store boundaries.
 template <typename To, typename From> __device__ __forceinline__ To cvt(From x) { return (To)x; }
-template <> __device__ __forceinline__ bf16_t cvt<bf16_t, double>(double x) { return (bf16_t)(float)x; }
+template <> __device__ __forceinline__ bf16_t cvt<bf16_t, double>(double x) { return bf16_from_double(x); }
 template <> __device__ __forceinline__ double cvt<double, bf16_t>(bf16_t x) { return (double)(float)x; }
 
 // Row of element j of lane `lane` in the 16x16 output block of a 16x16xK

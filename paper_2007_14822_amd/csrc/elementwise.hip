@@ -31,7 +31,7 @@ template <typename To, typename From> __device__ __forceinline__ To conv(From x)
 template <> __device__ __forceinline__ double conv<double, double>(double x) { return x; }
 template <> __device__ __forceinline__ double conv<double, float>(float x) { return (double)x; }
 template <> __device__ __forceinline__ float conv<float, double>(double x) { return (float)x; }
-template <> __device__ __forceinline__ bf16_t conv<bf16_t, double>(double x) { return (bf16_t)(float)x; }
+template <> __device__ __forceinline__ bf16_t conv<bf16_t, double>(double x) { return bf16_from_double(x); }
 
 static unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
   int64_t g = (n + threads - 1) / threads;

@@ -10,6 +10,7 @@ namespace itn {
 template <typename To> __device__ __forceinline__ To qconv(double x) { return (To)(float)x; }
 template <> __device__ __forceinline__ double qconv<double>(double x) { return x; }
 template <> __device__ __forceinline__ float qconv<float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ bf16_t qconv<bf16_t>(double x) { return bf16_from_double(x); }
 
 __global__ void qn_set_ptrs_kernel(QnDevPtrs* dst, QnDevPtrs v) {
   if (threadIdx.x == 0) *dst = v;

@@ -7,12 +7,13 @@ import torch
 import paper_2007_14822_amd as itn
 from oracle import qn as Q
 from tests import qn_util as U
-from tests.workloads import rel_err
+from tests.workloads import elementwise_ratio, group_rel_err, heff_error_factor, rel_err
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 2e-2}
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 1e-2}
+GTOL = {"f64": 1e-9, "f32": 1e-4, "bf16": 3e-2}
 TDT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 
 
@@ -101,6 +102,57 @@ def test_qn_structure_mismatch_rejected(h):
     assert e.value.name == "ITN_E_SHAPE"
 
 
+def _sector_refs(L, w1, w2, R, psi, chosen):
+    """The oracle's output blocks of the a'-sectors in `chosen` (L restricted
+    to those rows), and the same for the absolute values of every operand."""
+    def restrict(Lt):
+        return Q.BlockTensor(Lt.inds, Lt.flux, {k: v for k, v in Lt.blocks.items() if k[0] in chosen})
+    ref = Q.heff_apply_blocks(restrict(L), w1, w2, R, psi)
+    aref = Q.heff_apply_blocks(restrict(U.abs_blocks(L)), U.abs_blocks(w1), U.abs_blocks(w2),
+                               U.abs_blocks(R), U.abs_blocks(psi))
+    return ref, aref
+
+
+def _check_sectors(got, psi, ref, aref, chosen, prec, c, what):
+    """Every output block of the chosen a'-sectors: relative error per block
+    (blocks of 16+ elements), element-wise rounding bound, 16-element runs."""
+    keys, offs, _ = psi.packed()
+    g_all, r_all, a_all = [], [], []
+    worst_blk = 0.0
+    for k, o in zip(keys, offs):
+        if k[0] not in chosen:
+            continue
+        n = psi.blocks[k].size
+        r = ref.blocks[k].ravel() if k in ref.blocks else np.zeros(n)
+        a = aref.blocks[k].ravel() if k in aref.blocks else np.zeros(n)
+        g = got[o:o + n]
+        if n >= 16:
+            worst_blk = max(worst_blk, rel_err(g, r))
+        g_all.append(g)
+        r_all.append(r)
+        a_all.append(a)
+        # runs of 16 inside the block (the last axis is b, rows are (a', s1', s2'))
+        assert group_rel_err(g.reshape(-1, psi.blocks[k].shape[-1]),
+                             r.reshape(-1, psi.blocks[k].shape[-1])) <= GTOL[prec], (what, k)
+    g_all, r_all, a_all = map(np.concatenate, (g_all, r_all, a_all))
+    e = rel_err(g_all, r_all)
+    q = elementwise_ratio(g_all, r_all, a_all, c)
+    print("qn", what, prec, "rel %.2e  worst block %.2e  elementwise %.3f of bound"
+          % (e, worst_blk, q))
+    assert e <= TOL[prec], (what, e)
+    assert worst_blk <= 5 * TOL[prec], (what, worst_blk)
+    assert q <= 1.0, (what, q)
+
+
+def _qn_factor(prec, L, w1, R, psi):
+    """Rounding-error factor of a QN apply: the dense bound's stages with
+    the full bond dimensions as the sum lengths (upper bounds of every
+    block sum), X stored in the operand type (five rounded operands)."""
+    chil, w, chir = L.inds[0].dim, w1.inds[0].dim, R.inds[0].dim
+    d2 = psi.inds[1].dim * psi.inds[2].dim
+    return heff_error_factor(prec, chil, w * d2, w * chir, op_roundings=5, w=w)
+
+
 @pytest.mark.parametrize("prec", ["f64", "bf16"])
 def test_c3_full_size_sampled_sectors(h, prec):
     """U(1) chi=4096 in 25 sectors (the benchmark workload): every output
@@ -108,16 +160,45 @@ def test_c3_full_size_sampled_sectors(h, prec):
     ops, W1, W2 = U.c3_operands()
     L, w1, w2, R, psi = ops
     _, _, got = _run(h, ops, W1, W2, prec, 1, [psi])
-    keys, offs, _ = psi.packed()
     chosen = {0, 7, 17}  # dims 8, 35, 107
-    Lr = Q.BlockTensor(L.inds, L.flux, {k: v for k, v in L.blocks.items() if k[0] in chosen})
-    ref = Q.heff_apply_blocks(Lr, w1, w2, R, psi)
-    for k, o in zip(keys, offs):
-        if k[0] not in chosen:
-            continue
-        n = psi.blocks[k].size
-        r = ref.blocks[k].ravel() if k in ref.blocks else np.zeros(n)
-        assert rel_err(got[o:o + n], r) <= TOL[prec], (k, prec)
+    ref, aref = _sector_refs(L, w1, w2, R, psi, chosen)
+    _check_sectors(got, psi, ref, aref, chosen, prec, _qn_factor(prec, L, w1, R, psi), "c3")
+
+
+@pytest.mark.parametrize("which", ["c4", "c4w38", "c4z4"])
+def test_c4_full_size_sampled_sectors(h, which):
+    """The Hubbard cylinder bond at full size and nv = 4, as the benchmark
+    launches it (chi = 4096 in 81 (dN, 2Sz) sectors with w = 18 or the
+    w = 38 shape; or 272 sectors with a Z_4 momentum label): every output
+    block of four a'-sectors of the first and last vector against the oracle
+    restricted to those rows, in FP64 and bf16."""
+    ops, W1, W2 = U.c4_operands(which, nv=4)
+    L, w1, w2, R, psis = ops
+    nsec = L.inds[0].nsec
+    if which == "c4z4":
+        chosen = {134, 79, 102, 10}  # (0,0,0): 81, (-2,-2,1): 30, (-1,-3,1): 23, (-5,-5,0): 1
+    else:
+        chosen = {40, 24, 31, 5}  # (0,0): 324, (-2,-2): 120, (-1,-3): 93, (-5,-5): 1
+    assert max(chosen) < nsec
+    refs = {v: _sector_refs(L, w1, w2, R, psis[v], chosen) for v in (0, 3)}
+    n1 = sum(b.size for b in psis[0].blocks.values())
+    for prec in ("f64", "bf16"):
+        _, _, got = _run(h, (L, w1, w2, R, psis[0]), W1, W2, prec, 4, psis)
+        c = _qn_factor(prec, L, w1, R, psis[0])
+        for v in (0, 3):
+            _check_sectors(got[v * n1:(v + 1) * n1], psis[v], *refs[v], chosen, prec, c,
+                           (which, v))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nv", [1, 2])
+def test_zn_three_component_parity(h, prec, nv):
+    """U(1) x U(1) x Z_4 QNs ((dN, 2Sz, momentum mod 4), the cylinder's
+    three-component structure at small size) with a synthetic symmetric W."""
+    ops, W1, W2 = U.small_u1u1z4()
+    psis = [ops[4]] + [_perturbed(ops[4], 60 + v) for v in range(nv - 1)]
+    _, _, got = _run(h, ops, W1, W2, prec, nv, psis)
+    assert rel_err(got, _ref(ops, psis)) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])

@@ -146,3 +146,48 @@ def test_zn_plan_out_blocks_match_oracle(host):
     keys, offs = plan.out_blocks()
     pk, po, _ = psi.packed()
     assert [tuple(k) for k in keys] == [tuple(k) for k in pk] and offs == po
+
+
+@pytest.mark.parametrize("which,flops", [("c4", 3.75e11), ("c4w38", 7.85e11), ("c4z4", None)])
+def test_c4_structure_bit_exact(host, which, flops):
+    """The Hubbard cylinder bonds of the benchmark (81 (dN, 2Sz) sectors with
+    w = 18 and the w = 38 shape; 272 sectors with a Z_4 momentum label): the
+    library's allowed blocks and offsets of every operand, and the plan's
+    output block table at nv = 4, equal the oracle's bit for bit; the
+    planner's block-sparse flop count matches the independently computed
+    figure of the workload (nv = 4)."""
+    ops, W1, W2 = U.c4_operands(which, nv=1)
+    L, w1, w2, R, psis = ops
+    psi = psis[0]
+    for bt in (L, w1, R, psi):
+        spaces = [U.space(i) for i in bt.inds]
+        blocks, offs, tot = host.qn_allowed_blocks(spaces)
+        keys, roffs, flat = bt.packed()
+        assert blocks == [tuple(k) for k in keys]
+        assert offs == roffs and tot == flat.size
+    plan = _plan(host, (L, w1, w2, R, psi), W1, W2, nv=4)
+    blocks, offs = plan.out_blocks()
+    keys, roffs, flat = psi.packed()
+    assert blocks == [tuple(k) for k in keys] and offs == roffs
+    info = plan.info()
+    assert info["out_elems"] == flat.size
+    if which != "c4z4":
+        assert len(blocks) == 1030 and L.inds[0].nsec == 81
+    else:
+        assert L.inds[0].nsec == 272
+    if flops is not None:
+        assert abs(info["flops"] - flops) / flops < 0.01, info["flops"]
+
+
+def test_three_component_plan_matches_oracle(host):
+    """U(1) x U(1) x Z_4: plan output blocks equal the oracle's blockwise
+    H_eff output blocks (which equal psi's)."""
+    ops, W1, W2 = U.small_u1u1z4()
+    L, w1, w2, R, psi = ops
+    plan = _plan(host, ops, W1, W2)
+    blocks, offs = plan.out_blocks()
+    ref = Q.heff_apply_blocks(L, w1, w2, R, psi)
+    keys, roffs, _ = ref.packed()
+    pk, po, _ = psi.packed()
+    assert blocks == [tuple(k) for k in keys] == [tuple(k) for k in pk]
+    assert offs == roffs == po
