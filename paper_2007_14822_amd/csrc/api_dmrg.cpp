@@ -532,10 +532,14 @@ itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdi
     std::memcpy(&info, pin + n * 8, sizeof(info));
   }
   if (info != 0) return fail(c.h, ITN_E_NOT_CONVERGED, "symmetric eigensolver info=%d at bond %d", (int)info, i);
-  // weights, descending
-  std::vector<double> pd(n);
+  // Weights, descending.  The n x n density matrix of the nl x nr matrix M
+  // has rank at most min(nl, nr): its spectrum beyond that is structurally
+  // zero (rounding noise of either sign), and the truncated SVD of Sec. 5 has
+  // only min(nl, nr) singular values to keep, so only those enter.
+  const int64_t nsv = std::min(nl, nr);
+  std::vector<double> pd(nsv);
   double tot = 0.0;
-  for (int64_t j = 0; j < n; ++j) {
+  for (int64_t j = 0; j < nsv; ++j) {
     pd[j] = std::max(ev[n - 1 - j], 0.0);
     tot += pd[j];
   }

@@ -92,6 +92,27 @@ def test_truncation_respects_maxdim(h):
     assert recs[-1]["max_trunc"] > 0.0
 
 
+@pytest.mark.parametrize("sched", [[(4, 0.0), (8, 0.0), (8, 0.0)], [(16, 1e-6), (16, 1e-8), (32, 1e-10)]])
+def test_truncating_sweeps_match_oracle(h, sched):
+    """Sweeps that truncate (N = 12 S=1/2 chain; maxdim 4 then 8, and cutoffs
+    1e-6 .. 1e-10): per sweep, the largest bond dimension equals the
+    oracle's, the largest discarded weight agrees to 1e-8 relative, and the
+    energies agree to 1e-10 relative; the final bond dimensions match site
+    by site."""
+    N = 12
+    As0 = inp.random_product_state(N, 2, np.random.default_rng(3))
+    ref = odmrg.dmrg(inp.heisenberg_mpo(N), As0, sched)
+    recs, mps = run(h, inp.heisenberg_mpo(N), As0, sched, eig_tol=1e-13, krylovdim=12,
+                    maxiter=800, allow_unconverged=True)
+    for r, o in zip(recs, ref.records):
+        print("sweep", o.sweep, r["max_bond"], o.max_bond, r["max_trunc"], o.max_trunc,
+              r["energy"], o.energy)
+        assert r["max_bond"] == o.max_bond
+        assert abs(r["max_trunc"] - o.max_trunc) <= 1e-8 * o.max_trunc + 1e-14
+        assert abs(r["energy"] - o.energy) <= 1e-10 * abs(o.energy)
+    assert h.mps_bonds(mps) == [1] + [A.shape[2] for A in ref.mps]
+
+
 def test_mismatched_mpo_rejected(h):
     As0 = inp.random_product_state(6, 2, np.random.default_rng(1))
     mps = h.mps(As0)
