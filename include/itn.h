@@ -181,6 +181,24 @@ itn_status itn_heff_apply_sum(itn_handle* h, int32_t nterms, const itn_tensor* c
                               const itn_tensor* const* R, const itn_tensor* psi, int32_t nv,
                               itn_tensor* out, itn_prec prec, void* hip_stream);
 
+/* itn_heff_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and results (bit-identical to itn_heff_apply), but
+ * every scratch buffer of the call -- psi transposed, the W-stage output,
+ * converted environments, the W-stage tables -- is carved from one fixed
+ * device array of the library (itn_heff_noalloc_max_bytes, 64 MiB; enough
+ * for chi_l = chi_r = 1024 at d = 2, w = 5, nv = 1 in bf16).  A request
+ * needing more returns ITN_E_WORKSPACE with the size it needs, before any
+ * work is queued.  The call allocates nothing: the W-stage tables are copied
+ * into the array on the stream.  Each device holds its own array, shared by
+ * every call on that device: calls that overlap on one device (other
+ * streams, threads or handles) race and must be serialised by the caller. */
+itn_status itn_heff_apply_noalloc(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
+                                  const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
+                                  int32_t nv, itn_tensor* out, itn_prec prec, void* hip_stream);
+/* Size in bytes of that fixed scratch array. */
+itn_status itn_heff_noalloc_max_bytes(size_t* bytes);
+
 /* Bytes of library workspace itn_heff_apply uses for these extents. */
 itn_status itn_heff_workspace_size(itn_handle* h, int64_t chi_l, int64_t chi_r, int32_t d,
                                    int32_t w, int32_t nv, itn_prec prec, size_t* bytes);

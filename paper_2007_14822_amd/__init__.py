@@ -237,6 +237,32 @@ class Handle:
                                             PREC[prec], self._sp(stream)))
         return out
 
+    def heff_apply_noalloc(self, Lenv, W1: np.ndarray, W2: np.ndarray, Renv, psi, out,
+                           nv: int = 1, prec: str = "f64", stream=None):
+        """heff_apply whose scratch is the library's fixed device array
+        (itn_heff_apply_noalloc: no device allocation; calls overlapping on
+        one device race)."""
+        cl, cr = Lenv.shape[0], Renv.shape[0]
+        d = W1.shape[2]
+        shp = (cl, d, d, cr)
+        self._check_vectors(psi, out, cl * d * d * cr, int(nv))
+        k = _Keep()
+        tl, tr = _dense(k, Lenv), _dense(k, Renv)
+        W1c = np.ascontiguousarray(W1, np.float64)
+        W2c = np.ascontiguousarray(W2, np.float64)
+        k.items += [W1c, W2c]
+        t1, t2 = _dense(k, W1c), _dense(k, W2c)
+        tp, to = _dense(k, psi, shape=shp), _dense(k, out, shape=shp)
+        self._check(self.lib.itn_heff_apply_noalloc(self.h, C.byref(tl), C.byref(t1), C.byref(t2),
+                                                    C.byref(tr), C.byref(tp), int(nv), C.byref(to),
+                                                    PREC[prec], self._sp(stream)))
+        return out
+
+    def heff_noalloc_max_bytes(self) -> int:
+        b = C.c_size_t()
+        self._check(self.lib.itn_heff_noalloc_max_bytes(C.byref(b)))
+        return b.value
+
     def heff_apply_sum(self, terms, psi, out, nv: int = 1, prec: str = "f64", stream=None):
         """out = sum of H_eff,k psi over terms [(Lenv, W1, W2, Renv), ...]."""
         cl, cr = terms[0][0].shape[0], terms[0][3].shape[0]

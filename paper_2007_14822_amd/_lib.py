@@ -76,6 +76,8 @@ SIGNATURES = {
     "itn_contract": (S, [P, T, T, T, C.c_int, P]),
     "itn_heff_apply": (S, [P, T, T, T, T, T, C.c_int32, T, C.c_int, P]),
     "itn_heff_apply_sum": (S, [P, C.c_int32, P, P, P, P, T, C.c_int32, T, C.c_int, P]),
+    "itn_heff_apply_noalloc": (S, [P, T, T, T, T, T, C.c_int32, T, C.c_int, P]),
+    "itn_heff_noalloc_max_bytes": (S, [C.POINTER(C.c_size_t)]),
     "itn_heff_workspace_size": (S, [P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_int, C.POINTER(C.c_size_t)]),
     "itn_qn_heff_plan": (S, [P, T, T, T, T, T, C.c_int32, C.c_int, C.POINTER(P)]),

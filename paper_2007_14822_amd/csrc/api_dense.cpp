@@ -242,6 +242,7 @@ itn_status itn_create(itn_handle** out, int device) {
       delete h;
       return ITN_E_HIP;
     }
+    noalloc_scratch_init(device);
   }
   *out = h;
   return ITN_OK;
@@ -466,6 +467,8 @@ itn_status itn_contract(itn_handle* h, const itn_tensor* A, const itn_tensor* B,
   return ITN_OK;
 }
 
+}  // extern "C"
+
 // -------------------------------------------------------------- dense H_eff
 static size_t heff_ws_bytes(int64_t cl, int64_t cr, int d, int w, int nv, int P, bool castL,
                             bool castR) {
@@ -481,8 +484,9 @@ static size_t heff_ws_bytes(int64_t cl, int64_t cr, int d, int w, int nv, int P,
   return b + 256;
 }
 
-itn_status itn_heff_workspace_size(itn_handle* h, int64_t chi_l, int64_t chi_r, int32_t d,
-                                   int32_t w, int32_t nv, itn_prec prec, size_t* bytes) {
+extern "C" itn_status itn_heff_workspace_size(itn_handle* h, int64_t chi_l, int64_t chi_r,
+                                              int32_t d, int32_t w, int32_t nv, itn_prec prec,
+                                              size_t* bytes) {
   if (!h || !bytes) return ITN_E_ARG;
   if (!valid_prec(prec) || chi_l < 0 || chi_r < 0 || d < 1 || w < 1 || nv < 1)
     return fail(h, ITN_E_ARG, "bad arguments");
@@ -511,13 +515,52 @@ static itn_status check_term(itn_handle* h, const itn_tensor* L, const itn_tenso
   return ITN_OK;
 }
 
+// Device bytes of a W-stage table held in a fixed scratch region.
+static size_t table_bytes(const CSR& c) {
+  const size_t nz = std::max<size_t>(1, c.coef.size());
+  return round256(c.row_ptr.size() * 4) + round256(std::max<size_t>(1, c.row_off.size()) * 8) +
+         round256(nz * 8) * 2 + round256(nz * 4) * 2;
+}
+
+// Copy a W-stage table into a fixed scratch region (stream-ordered before the
+// kernels that read it); the returned WTable points into the region.
+static itn_status table_to_scratch(itn_handle* h, const CSR& c, Carver& cv, hipStream_t s, WTable* t) {
+  const size_t nz = std::max<size_t>(1, c.coef.size());
+  t->nrows = (int32_t)c.row_off.size();
+  t->nnz = (int64_t)c.coef.size();
+  t->row_ptr = static_cast<int32_t*>(cv.take(c.row_ptr.size() * 4));
+  t->row_off = static_cast<int64_t*>(cv.take(std::max<size_t>(1, c.row_off.size()) * 8));
+  t->col_off = static_cast<int64_t*>(cv.take(nz * 8));
+  t->coef = static_cast<double*>(cv.take(nz * 8));
+  t->col_idx = static_cast<int32_t*>(cv.take(nz * 4));
+  t->coef32 = static_cast<float*>(cv.take(nz * 4));
+  ITN_HIP(h, hipMemcpyAsync(t->row_ptr, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice, s));
+  if (!c.row_off.empty())
+    ITN_HIP(h, hipMemcpyAsync(t->row_off, c.row_off.data(), c.row_off.size() * 8, hipMemcpyHostToDevice, s));
+  if (!c.coef.empty()) {
+    std::vector<int32_t> ci(c.col_off.begin(), c.col_off.end());
+    std::vector<float> cf(c.coef.begin(), c.coef.end());
+    ITN_HIP(h, hipMemcpyAsync(t->col_off, c.col_off.data(), c.col_off.size() * 8, hipMemcpyHostToDevice, s));
+    ITN_HIP(h, hipMemcpyAsync(t->coef, c.coef.data(), c.coef.size() * 8, hipMemcpyHostToDevice, s));
+    ITN_HIP(h, hipMemcpyAsync(t->col_idx, ci.data(), ci.size() * 4, hipMemcpyHostToDevice, s));
+    ITN_HIP(h, hipMemcpyAsync(t->coef32, cf.data(), cf.size() * 4, hipMemcpyHostToDevice, s));
+  }
+  return ITN_OK;
+}
+
+namespace itn {
+
 // out = sum over the n terms of H_eff,k psi (Sec. 7.2 sums of MPOs).  psi is
 // transposed and cast once; every term runs stage 1 (+ W-stage) and its
-// stage-4 GEMM adds into out from the second term on.
-static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const* Ls,
-                                   const itn_tensor* const* W1s, const itn_tensor* const* W2s,
-                                   const itn_tensor* const* Rs, const itn_tensor* psi, int32_t nv,
-                                   itn_tensor* out, itn_prec prec, void* hip_stream) {
+// stage-4 GEMM adds into out from the second term on.  Scratch comes from the
+// handle's workspace (grown on demand) with W-stage tables from the handle's
+// content-keyed cache, or, when `fixed` is given, from that region alone
+// (tables copied into it on the stream; nothing is allocated).
+itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const* Ls,
+                            const itn_tensor* const* W1s, const itn_tensor* const* W2s,
+                            const itn_tensor* const* Rs, const itn_tensor* psi, int32_t nv,
+                            itn_tensor* out, itn_prec prec, void* hip_stream,
+                            const FixedScratch* fixed) {
   if (!h) return ITN_E_ARG;
   if (n < 1 || !Ls || !W1s || !W2s || !Rs) return fail(h, ITN_E_ARG, "need at least one term");
   ITN_TRY(check_dense(h, psi, "psi", 4));
@@ -549,20 +592,65 @@ static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const
   const int pt = P == ITN_P_F64 ? D_F64 : (P == ITN_P_F32 ? D_F32 : D_BF16);
   const int es = dtype_size(pt);
   const int xt = xtype_of(P);
-  int64_t wmax = 0;
+  const int64_t N1 = d2 * nv * cr;
+  int64_t wmax = 0, wmax_unfused = 0;
   bool anyL = false, anyR = false;
+  // Per term: fused stage 1 or not, and the W-stage table it reads.
+  //   fused:   CSR with input index m0*d2 + c and output row c'*w + m2
+  //   unfused: CSR over X[a'][m0][c][v][b] -> Z[v][a'][c'][m2][b]
+  std::vector<char> fused(n, 0);
+  std::vector<CSR> csrs(n);
+  // The fused stage-1 kernel loads L rows straight into LDS: whole 128-byte
+  // K steps and 16-byte aligned rows (a converted L lands in aligned scratch).
+  const int64_t bk = 128 / es;
   for (int k = 0; k < n; ++k) {
-    wmax = std::max<int64_t>(wmax, Ls[k]->dims[1]);
+    const int64_t w = Ls[k]->dims[1];
+    wmax = std::max(wmax, w);
     anyL |= Ls[k]->dtype != pt;
     anyR |= Rs[k]->dtype != pt;
+    const double* w1 = static_cast<const double*>(W1s[k]->data);
+    const double* w2 = static_cast<const double*>(W2s[k]->data);
+    const bool aligned = Ls[k]->dtype != pt || (reinterpret_cast<uintptr_t>(Ls[k]->data) & 15) == 0;
+    bool f = heff_fused_supported(P, (int)w, (int)d2) && cl % bk == 0 && cl > 0 && aligned &&
+             heff_fused_fits(P, cl, cr, (int)w, (int)d2, (int)nv);
+    if (f) {
+      csrs[k] = heff_w_csr(w1, w2, (int)w, (int)d, d2, 1, w, 1);
+      f = heff_fused_table_fits((int)csrs[k].row_off.size(), (int64_t)csrs[k].coef.size());
+    }
+    if (!f) {
+      csrs[k] = heff_w_csr(w1, w2, (int)w, (int)d, /*in_m*/ N1, /*in_c*/ (int64_t)nv * cr,
+                           /*out_c*/ w * cr, /*out_m*/ cr);
+      wmax_unfused = std::max(wmax_unfused, w);
+    }
+    fused[k] = f;
   }
-  ITN_TRY(ensure_workspace(h, heff_ws_bytes(cl, cr, (int)d, (int)wmax, nv, P, anyL, anyR)));
-  Carver cv(h->ws.ptr);
-  void* Lcast = anyL ? cv.take((size_t)(cl * wmax * cl) * es) : nullptr;
-  void* Rcast = anyR ? cv.take((size_t)(cr * wmax * cr) * es) : nullptr;
-  void* psiT = cv.take((size_t)(d2 * nv * cr * cl) * es);
-  void* Z = cv.take((size_t)(nv * cl * d2 * wmax * cr) * es);
-  void* Xbuf = cv.take((size_t)(cl * wmax * d2 * nv * cr) * dtype_size(xt));
+  const size_t bLc = anyL ? round256((size_t)(cl * wmax * cl) * es) : 0;
+  const size_t bRc = anyR ? round256((size_t)(cr * wmax * cr) * es) : 0;
+  const size_t bPT = round256((size_t)(d2 * nv * cr * cl) * es);
+  const size_t bZ = round256((size_t)(nv * cl * d2 * wmax * cr) * es);
+  const size_t bX = round256((size_t)(cl * wmax_unfused * d2 * nv * cr) * dtype_size(xt));
+  size_t need = bLc + bRc + bPT + bZ + bX;
+  void* base = nullptr;
+  if (fixed) {
+    for (int k = 0; k < n; ++k) need += table_bytes(csrs[k]);
+    if (need > fixed->bytes)
+      return fail(h, ITN_E_WORKSPACE,
+                  "this H_eff needs %zu bytes of scratch; the fixed scratch region holds %zu", need,
+                  fixed->bytes);
+    base = fixed->base;
+  } else {
+    ITN_TRY(ensure_workspace(h, need + 256));
+    base = h->ws.ptr;
+  }
+  Carver cv(base);
+  void* Lcast = anyL ? cv.take(bLc) : nullptr;
+  void* Rcast = anyR ? cv.take(bRc) : nullptr;
+  void* psiT = cv.take(bPT);
+  void* Z = cv.take(bZ);
+  void* Xbuf = bX ? cv.take(bX) : nullptr;
+  std::vector<WTable> fixed_tabs(fixed ? n : 0);
+  if (fixed)
+    for (int k = 0; k < n; ++k) ITN_TRY(table_to_scratch(h, csrs[k], cv, s, &fixed_tabs[k]));
   // psi[v][a][c][b] -> psiT[c][v][b][a]
   TransposeArgs ta{};
   ta.rows = cl;
@@ -581,12 +669,9 @@ static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const
     Prof pf(h, "heff_psi_transpose", s);
     ITN_HIP(h, transpose_cast(psi->dtype, psi->data, pt, psiT, ta, s));
   }
-  const int64_t N1 = d2 * nv * cr;
   for (int term = 0; term < n; ++term) {
     const itn_tensor* L = Ls[term];
     const itn_tensor* R = Rs[term];
-    const itn_tensor* W1 = W1s[term];
-    const itn_tensor* W2 = W2s[term];
     const int64_t w = L->dims[1];
     const void* Lp = L->data;
     const void* Rp = R->data;
@@ -600,23 +685,13 @@ static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const
       ITN_HIP(h, cast(R->dtype, R->data, pt, Rcast, cr * w * cr, s));
       Rp = Rcast;
     }
-    // The fused stage-1 kernel loads L rows straight into LDS: whole 128-byte
-    // K steps and 16-byte aligned rows.
-    const int64_t bk = 128 / es;
-    CSR fcsr;
-    bool fused = heff_fused_supported(P, (int)w, (int)d2) && cl % bk == 0 && cl > 0 &&
-                 (reinterpret_cast<uintptr_t>(Lp) & 15) == 0 &&
-                 heff_fused_fits(P, cl, cr, (int)w, (int)d2, (int)nv);
-    if (fused) {
-      // CSR with input index m0*d2 + c and output row c'*w + m2.
-      fcsr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),
-                        (int)w, (int)d, d2, 1, w, 1);
-      fused = heff_fused_table_fits((int)fcsr.row_off.size(), (int64_t)fcsr.coef.size());
-    }
-    if (fused) {
-      const CSR& csr = fcsr;
-      const WTable* tab = nullptr;
-      ITN_TRY(get_wtable(h, "fused" + csr.key(), csr.row_ptr, csr.row_off, csr.col_off, csr.coef, &tab));
+    const CSR& csr = csrs[term];
+    const WTable* tab = nullptr;
+    if (fixed) tab = &fixed_tabs[term];
+    else
+      ITN_TRY(get_wtable(h, (fused[term] ? "fused" : "") + csr.key(), csr.row_ptr, csr.row_off,
+                         csr.col_off, csr.coef, &tab));
+    if (fused[term]) {
       HeffFusedArgs fa{};
       fa.L = Lp;
       fa.psiT = psiT;
@@ -652,11 +727,6 @@ static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const
         ITN_HIP(h, gemm_nt(P, xt, g1, s));
       }
       // W-stage: Z[v][a'][c'][m2][b] = sum W12 X[a'][m0][c][v][b]
-      CSR csr = heff_w_csr(static_cast<const double*>(W1->data), static_cast<const double*>(W2->data),
-                           (int)w, (int)d, /*in_m*/ N1, /*in_c*/ (int64_t)nv * cr,
-                           /*out_c*/ w * cr, /*out_m*/ cr);
-      const WTable* tab = nullptr;
-      ITN_TRY(get_wtable(h, csr.key(), csr.row_ptr, csr.row_off, csr.col_off, csr.coef, &tab));
       WStageArgs wa{};
       wa.X = cl;
       wa.Z = nv;
@@ -691,17 +761,21 @@ static itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const
   return ITN_OK;
 }
 
+}  // namespace itn
+
+extern "C" {
+
 itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
                           const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
                           int32_t nv, itn_tensor* out, itn_prec prec, void* hip_stream) {
-  return heff_apply_terms(h, 1, &L, &W1, &W2, &R, psi, nv, out, prec, hip_stream);
+  return heff_apply_terms(h, 1, &L, &W1, &W2, &R, psi, nv, out, prec, hip_stream, nullptr);
 }
 
 itn_status itn_heff_apply_sum(itn_handle* h, int32_t nterms, const itn_tensor* const* L,
                               const itn_tensor* const* W1, const itn_tensor* const* W2,
                               const itn_tensor* const* R, const itn_tensor* psi, int32_t nv,
                               itn_tensor* out, itn_prec prec, void* hip_stream) {
-  return heff_apply_terms(h, nterms, L, W1, W2, R, psi, nv, out, prec, hip_stream);
+  return heff_apply_terms(h, nterms, L, W1, W2, R, psi, nv, out, prec, hip_stream, nullptr);
 }
 
 // --------------------------------------------------------- environment step

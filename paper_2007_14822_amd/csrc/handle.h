@@ -104,6 +104,24 @@ struct Prof {
   ~Prof();
 };
 
+// A device region that scratch is carved from instead of the handle's
+// workspace (nothing is allocated when one is given).
+struct FixedScratch {
+  void* base = nullptr;
+  size_t bytes = 0;
+};
+
+// Dense H_eff of a sum of n terms (itn_heff_apply, itn_heff_apply_sum and
+// the allocation-free variant); fixed = nullptr uses the handle's workspace.
+itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const* Ls,
+                            const itn_tensor* const* W1s, const itn_tensor* const* W2s,
+                            const itn_tensor* const* Rs, const itn_tensor* psi, int32_t nv,
+                            itn_tensor* out, itn_prec prec, void* hip_stream,
+                            const FixedScratch* fixed);
+
+// Looks up the allocation-free entry point's scratch on `device` (current).
+void noalloc_scratch_init(int device);
+
 // Host-side CSR builders.
 struct CSR {
   std::vector<int32_t> row_ptr{0};
