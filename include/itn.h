@@ -322,7 +322,10 @@ typedef struct {
   int32_t maxiter;        /* matvecs per local eigensolve                      */
   double eig_tol;         /* residual tolerance, relative to |theta|           */
   itn_prec prec;          /* matvec precision of the Davidson expansion        */
-  int32_t refine;         /* 1: finish every local solve with FP64 matvecs     */
+  int32_t refine;         /* with prec below F64, 1: apply the first vector of
+                             every restart cycle in FP64 (exact couplings to
+                             the low-precision corrections; the solve converges
+                             to the FP64 eigenpair), 0: every matvec at prec  */
   double energy_tol;      /* stop early when |dE| < energy_tol*|E| (0: never)  */
   int32_t timing;         /* 1: synchronise at phase boundaries and report the
                              per-phase times below (adds host waits)           */
@@ -334,6 +337,10 @@ typedef struct {
   int32_t northo;
   const itn_mps* const* ortho;
   double weight;
+  /* Block size of the Davidson expansion: each step adds the residuals of
+   * the `block` lowest Ritz pairs and applies H_eff to them in one batched
+   * itn_heff_apply (nv = block).  0 or 1: one vector per step. */
+  int32_t block;
 } itn_sweep_params;
 
 /* Per-sweep results, arrays of nsweeps entries owned by the caller (any may
@@ -353,6 +360,7 @@ typedef struct {
   double* t_solver;
   double* t_split;
   double* t_env;
+  int64_t* matvecs_f64; /* of `matvecs`, those applied in FP64                 */
 } itn_sweep_result;
 
 /* Run the schedule: per sweep, left->right over bonds (0,1)..(N-2,N-1) then

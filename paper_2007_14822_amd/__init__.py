@@ -345,11 +345,12 @@ class Handle:
 
     def dmrg_sweep(self, mps, mpo, sweeps, prec="f64", mindim=1, krylovdim=8, maxiter=100,
                    eig_tol=1e-10, refine=True, energy_tol=0.0, allow_unconverged=False,
-                   timing=False, ortho=(), weight=0.0):
+                   timing=False, ortho=(), weight=0.0, block=1):
         """Run a schedule [(maxdim, cutoff), ...]; returns per-sweep records
         (with per-phase seconds t_matvec/t_solver/t_split/t_env if timing).
         ortho: previously found MPS whose projectors, times `weight`, are
-        added to H (excited states)."""
+        added to H (excited states).  block: Davidson vectors per batched
+        matvec."""
         ns = len(sweeps)
         md = (C.c_int32 * max(1, ns))(*[int(m) for m, _ in sweeps])
         co = (C.c_double * max(1, ns))(*[float(c) for _, c in sweeps])
@@ -361,12 +362,15 @@ class Handle:
         prm.northo = len(ortho)
         prm.ortho = C.cast(optrs, C.POINTER(C.c_void_p)) if ortho else None
         prm.weight = float(weight)
+        prm.block = int(block)
         fields = [("energy", C.c_double), ("max_trunc", C.c_double), ("max_bond", C.c_int32),
-                  ("seconds", C.c_double), ("matvecs", C.c_int64), ("residual", C.c_double)]
+                  ("seconds", C.c_double), ("matvecs", C.c_int64), ("residual", C.c_double),
+                  ("matvecs_f64", C.c_int64)]
         if timing:
             fields += [(k, C.c_double) for k in ("t_matvec", "t_solver", "t_split", "t_env")]
         arrs = {k: (t * max(1, ns))() for k, t in fields}
         res = L.itn_sweep_result(0, *[arrs[k] for k, _ in fields[:6]])
+        res.matvecs_f64 = arrs["matvecs_f64"]
         if timing:
             res.t_matvec, res.t_solver, res.t_split, res.t_env = (arrs[k] for k in
                                                                    ("t_matvec", "t_solver", "t_split", "t_env"))

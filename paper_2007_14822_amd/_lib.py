@@ -46,7 +46,7 @@ class itn_sweep_params(C.Structure):
                 ("krylovdim", C.c_int32), ("maxiter", C.c_int32), ("eig_tol", C.c_double),
                 ("prec", C.c_int), ("refine", C.c_int32), ("energy_tol", C.c_double),
                 ("timing", C.c_int32), ("northo", C.c_int32), ("ortho", C.POINTER(C.c_void_p)),
-                ("weight", C.c_double)]
+                ("weight", C.c_double), ("block", C.c_int32)]
 
 
 class itn_sweep_result(C.Structure):
@@ -55,7 +55,7 @@ class itn_sweep_result(C.Structure):
                 ("seconds", C.POINTER(C.c_double)), ("matvecs", C.POINTER(C.c_int64)),
                 ("residual", C.POINTER(C.c_double)), ("t_matvec", C.POINTER(C.c_double)),
                 ("t_solver", C.POINTER(C.c_double)), ("t_split", C.POINTER(C.c_double)),
-                ("t_env", C.POINTER(C.c_double))]
+                ("t_env", C.POINTER(C.c_double)), ("matvecs_f64", C.POINTER(C.c_int64))]
 
 
 P = C.c_void_p

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 
 #include "common.h"
 #include "handle.h"
@@ -96,6 +97,7 @@ struct itn_mps {
   DBuf psi, tmp, rho, evec, eval, einfo, V, AV, Lp, Rp, partial, dots, ev_host_stage;
   DBuf ovec, ot1, ot2, ot3, odots;
   DBuf hh, hscr;  // bond split: Householder reflectors [n][n]; tridiagonal and barrier scratch
+  DBuf hdiag, wdiag;  // block Davidson: diagonal of H_eff, and its W1 W2 factor
   HostPin pin;    // pinned host staging for small reads
   ~itn_mps() {
     for (auto& b : site) b.release();
@@ -105,7 +107,7 @@ struct itn_mps {
       for (auto& row : *v)
         for (auto& b : row) b.release();
     for (DBuf* b : {&psi, &tmp, &rho, &evec, &eval, &einfo, &V, &AV, &Lp, &Rp, &partial, &dots,
-                    &ev_host_stage, &ovec, &ot1, &ot2, &ot3, &odots, &hh, &hscr})
+                    &ev_host_stage, &ovec, &ot1, &ot2, &ot3, &odots, &hh, &hscr, &hdiag, &wdiag})
       b->release();
     pin.release();
   }
@@ -217,7 +219,8 @@ struct Ctx {
   const itn_mpo* mpo;
   const itn_sweep_params* p;
   hipStream_t s = nullptr;
-  int64_t matvecs = 0;
+  int64_t matvecs = 0;      // H_eff applications (vectors), all precisions
+  int64_t matvecs64 = 0;    // of which in FP64
   double max_resid = 0.0;
   bool unconverged = false;
   // per-phase seconds of the current sweep (params->timing only)
@@ -247,8 +250,10 @@ struct PhaseTimer {
   }
 };
 
-// y = H_eff x at precision `prec` (FP64 vectors), through the public entry point.
-itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl, int64_t cr) {
+// y = H_eff x for nv vectors stored one after another (FP64), at precision
+// `prec`, through the public entry point: one launch sequence for all nv.
+itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl, int64_t cr,
+                int nv = 1) {
   PhaseTimer pt(c, &c.t_mv);
   const int w = c.mpo->w, d = c.mpo->d;
   const int64_t dl[3] = {cl, w, cl}, dr[3] = {cr, w, cr}, dw[4] = {w, w, d, d};
@@ -261,14 +266,19 @@ itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl,
   itn_tensor W2 = dense_t(4, dw, ITN_F64, const_cast<double*>(c.mpo->site(i + 1)));
   itn_tensor P = dense_t(4, dp, ITN_F64, const_cast<double*>(x));
   itn_tensor O = dense_t(4, dp, ITN_F64, y);
-  c.matvecs++;
-  ITN_TRY(itn_heff_apply(c.h, &L, &W1, &W2, &R, &P, 1, &O, (itn_prec)prec, c.s));
+  c.matvecs += nv;
+  if (!low) c.matvecs64 += nv;
+  ITN_TRY(itn_heff_apply(c.h, &L, &W1, &W2, &R, &P, nv, &O, (itn_prec)prec, c.s));
   if (c.northo > 0) {  // + weight * sum_j |v_j><v_j| x  (Sec. 7.2 energy penalty)
     const int64_t n = cl * d * d * cr;
     ITN_TRY(c.m->partial.ensure(c.h, (size_t)c.northo * dot_blocks(n) * 8));
     ITN_TRY(c.m->odots.ensure(c.h, (size_t)c.northo * 8 + 8));
-    ITN_HIP(c.h, multi_dot(c.pen_v, n, c.northo, x, n, c.m->partial.d(), c.m->odots.d(), c.s));
-    ITN_HIP(c.h, lincomb_dev(c.pen_v, n, c.northo, c.m->odots.d(), c.p->weight, y, n, c.s));
+    for (int v = 0; v < nv; ++v) {
+      ITN_HIP(c.h, multi_dot(c.pen_v, n, c.northo, x + (size_t)v * n, n, c.m->partial.d(),
+                             c.m->odots.d(), c.s));
+      ITN_HIP(c.h, lincomb_dev(c.pen_v, n, c.northo, c.m->odots.d(), c.p->weight, y + (size_t)v * n,
+                               n, c.s));
+    }
   }
   return ITN_OK;
 }
@@ -285,117 +295,319 @@ itn_status dots(Ctx& c, const double* V, int64_t n, int k, const double* w, doub
   return ITN_OK;
 }
 
-// Lowest eigenpair of H_eff at bond i by Davidson (identity preconditioner,
-// full re-orthogonalisation, thick restart), FP64 vectors.  psi (in/out,
-// length n) is the start vector and the result.  *converged is false only
-// when maxiter matvecs ended above the tolerance; a residual already inside
-// the Krylov space (no new direction) is at the arithmetic's noise floor and
-// counts as converged.
+// Dot products of groups of vectors, read back with one host round trip:
+// each add(V, k, w) queues <V_a, w> for a < k (V_a at stride n) into the
+// next k slots of the result.
+struct DotBatch {
+  Ctx& c;
+  int64_t n;
+  int total = 0;
+  std::vector<std::pair<int, int>> spans;  // (offset, count) per add
+  DotBatch(Ctx& ctx, int64_t len) : c(ctx), n(len) {}
+  itn_status add(const double* V, int k, const double* w, int* off) {
+    ITN_TRY(c.m->partial.ensure(c.h, (size_t)std::max(k, 1) * dot_blocks(n) * 8));
+    ITN_TRY(c.m->dots.ensure(c.h, (size_t)(total + k) * 8 + 8));
+    ITN_HIP(c.h, multi_dot(V, n, k, w, n, c.m->partial.d(), c.m->dots.d() + total, c.s));
+    *off = total;
+    total += k;
+    return ITN_OK;
+  }
+  itn_status read(std::vector<double>& out) {
+    out.assign(std::max(total, 1), 0.0);
+    if (total == 0) return ITN_OK;
+    ITN_TRY(c.m->pin.ensure(c.h, (size_t)total * 8 + 8));
+    ITN_HIP(c.h, hipMemcpyAsync(c.m->pin.p, c.m->dots.p, (size_t)total * 8, hipMemcpyDeviceToHost, c.s));
+    ITN_HIP(c.h, hipStreamSynchronize(c.s));
+    std::memcpy(out.data(), c.m->pin.p, (size_t)total * 8);
+    return ITN_OK;
+  }
+};
+
+// Lowest eigenpair of H_eff at bond i by Davidson (full
+// re-orthogonalisation, restarts), FP64 basis.  psi (in/out, length n) is the
+// start vector and the result.
 //
-// Host round trips per expansion step: two, sometimes three.  (1) the new
-// column V^T A v_k of the projected matrix; (2) V^T r and r.r in one
-// reduction, the residual being formed in the next basis slot; (3) only when
-// the first Gram-Schmidt pass removed most of r (DGKS test): the same pair
-// after that pass, from which the norm after the second pass follows as
-// |r'|^2 - |c2|^2 (V orthonormal).
+// One vector per step (params->block <= 1): the residual of the lowest Ritz
+// pair with the identity preconditioner (Lanczos-equivalent).  Host round
+// trips per step: the residual's projections and norm, the new column of
+// the projected matrix, and a second Gram-Schmidt pass only when the first
+// removed more than half the residual's norm (Daniel-Gragg-Kaufman-Stewart).
+//
+// Block (params->block = B > 1): each step adds the residuals of the B
+// lowest Ritz pairs, preconditioned with the diagonal of H_eff (Davidson's
+// original correction (D - theta)^-1 r; with the identity all residuals of
+// one Krylov space would be parallel), orthonormalised against the basis
+// and each other by two rounds of Cholesky QR, and applies H_eff to the
+// block in one batched launch (nv = accepted vectors, contiguous slots).
+//
+// Precision: matvecs of expansion vectors run at `prec`.  When prec is below
+// FP64 and refinement is on, the first vector of every restart cycle (the
+// start vector, then each restart's Ritz vector) is applied in FP64 instead:
+// its row and column of the projected matrix are then exact, so the
+// corrections found with low-precision matvecs enter the Ritz vector with
+// first-order-exact couplings and the iteration converges to the FP64
+// eigenpair (the low-precision error enters only through the corrections'
+// own block, second order in their size).  A restart then keeps that one
+// Ritz vector (with a block, the B lowest), so a cycle is one FP64 matvec
+// and kmax - 1 low-precision ones.  Without refinement every matvec runs at
+// `prec`.  The returned energy is the Ritz value; with `exact_final` (mixed
+// mode) the result is applied once more in FP64 and its Rayleigh quotient
+// and residual are returned instead.
+//
+// *converged is false only when maxiter matvecs ended above the tolerance;
+// a residual with no new direction left (the basis spans the invariant
+// subspace up to rounding) counts as converged.
 itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* psi, int64_t n,
-                    int64_t cl, int64_t cr, double* energy, double* resid, bool* converged) {
-  const int kmax = std::max(4, std::min(c.p->krylovdim, 32));
-  constexpr int KEEP = 3;  // Ritz vectors kept at a restart (thick restart)
-  ITN_TRY(c.m->V.ensure(c.h, (size_t)(kmax + KEEP) * n * 8));
-  ITN_TRY(c.m->AV.ensure(c.h, (size_t)(kmax + KEEP) * n * 8));
+                    int64_t cl, int64_t cr, const double* diag, bool exact_final, double* energy,
+                    double* resid, bool* converged) {
+  const bool mixed = prec != ITN_P_F64 && c.p->refine;
+  const int B = diag ? std::max(1, std::min(c.p->block > 0 ? c.p->block : 1, 8)) : 1;
+  const int keep_base = mixed ? 1 : 3;  // Ritz vectors kept at a restart
+  int kmax = std::max(4, std::min(c.p->krylovdim, 32));
+  kmax = std::max(kmax, std::max(keep_base, B) + B);
+  // slots: basis [0, kmax), staged block [kmax, kmax + B), orthonormalisation
+  // staging [kmax + B, kmax + 2B), restart staging, one spare
+  const int s_orth = kmax + B, s_rest = kmax + 2 * B, s_spare = s_rest + std::max(keep_base, B);
+  const int cap = s_spare + 1;
+  ITN_TRY(c.m->V.ensure(c.h, (size_t)cap * n * 8));
+  ITN_TRY(c.m->AV.ensure(c.h, (size_t)cap * n * 8));
   double* V = c.m->V.d();
   double* AV = c.m->AV.d();
-  std::vector<double> Hk((size_t)kmax * kmax, 0.0), tmp(kmax + 2);
-  double nrm2;
-  ITN_TRY(dots(c, psi, n, 1, psi, &nrm2));
+  auto Vs = [&](int a) { return V + (size_t)a * n; };
+  auto AVs = [&](int a) { return AV + (size_t)a * n; };
+  std::vector<double> Hk((size_t)kmax * kmax, 0.0), got;
+  auto H = [&](int a, int b) -> double& { return Hk[(size_t)a * kmax + b]; };
+  int used = 0;  // matvecs of this solve
+  {
+    DotBatch db(c, n);
+    int o;
+    ITN_TRY(db.add(psi, 1, psi, &o));
+    ITN_TRY(db.read(got));
+  }
+  const double nrm2 = got[0];
   if (!(nrm2 > 0)) return fail(c.h, ITN_E_ARG, "zero start vector at bond %d", i);
   ITN_HIP(c.h, hipMemcpyAsync(V, psi, n * 8, hipMemcpyDeviceToDevice, c.s));
   ITN_HIP(c.h, scale(V, 1.0 / std::sqrt(nrm2), n, c.s));
-  ITN_TRY(heff(c, i, prec, V, AV, cl, cr));
+  ITN_TRY(heff(c, i, mixed ? ITN_P_F64 : prec, V, AV, cl, cr));
+  ++used;
+  {
+    DotBatch db(c, n);
+    int o;
+    ITN_TRY(db.add(V, 1, AV, &o));
+    ITN_TRY(db.read(got));
+    H(0, 0) = got[0];
+  }
   int k = 1;
-  double theta = 0.0, rn = 0.0;
+  double theta = H(0, 0), rn = 0.0;
   bool conv = false;
-  std::vector<double> w, Y, y;
-  for (int it = 0;; ++it) {
-    // (1) new column k-1 of the projected matrix
-    ITN_TRY(dots(c, V, n, k, AV + (size_t)(k - 1) * n, tmp.data()));
-    for (int a = 0; a < k; ++a) {
-      Hk[a * kmax + (k - 1)] = tmp[a];
-      Hk[(k - 1) * kmax + a] = tmp[a];
+  std::vector<double> w, Y, y0(1, 1.0);
+  // Orthonormalise the nin vectors in slots [k, k + nin) against the basis
+  // and each other, from their projections P(j, a) = <V_a, t_j> (a < k) and
+  // Gram matrix P(j, k + l): subtract the projections, Cholesky of the
+  // block's Gram (directions whose pivot is below drop * ref[j] are left out),
+  // accepted vectors written back to [k, k + *nout).
+  auto cholqr = [&](int nin, const std::function<double(int, int)>& P, double drop,
+                    const std::vector<double>& ref, int* nout) -> itn_status {
+    for (int j = 0; j < nin; ++j) {
+      std::vector<double> cj(k);
+      for (int a = 0; a < k; ++a) cj[a] = -P(j, a);
+      ITN_HIP(c.h, lincomb(V, n, k, cj.data(), 1.0, Vs(k + j), n, c.s));
     }
+    std::vector<double> Gb((size_t)nin * nin), Lc((size_t)nin * nin, 0.0);
+    for (int j = 0; j < nin; ++j)
+      for (int l = 0; l < nin; ++l) {
+        double v = P(j, k + l);
+        for (int a = 0; a < k; ++a) v -= P(j, a) * P(l, a);
+        Gb[(size_t)j * nin + l] = v;
+      }
+    std::vector<int> idx;
+    for (int j = 0; j < nin; ++j) {
+      double piv = Gb[(size_t)j * nin + j];
+      for (int q : idx) piv -= Lc[(size_t)j * nin + q] * Lc[(size_t)j * nin + q];
+      if (!(piv > drop * ref[j])) continue;
+      const double lj = std::sqrt(piv);
+      Lc[(size_t)j * nin + j] = lj;
+      for (int l = j + 1; l < nin; ++l) {
+        double v = Gb[(size_t)l * nin + j];
+        for (int q : idx) v -= Lc[(size_t)l * nin + q] * Lc[(size_t)j * nin + q];
+        Lc[(size_t)l * nin + j] = v / lj;
+      }
+      idx.push_back(j);
+    }
+    const int na = (int)idx.size();
+    // t_q = sum_j T[q][j] r_j: forward substitution over the accepted columns
+    std::vector<double> T((size_t)std::max(na, 1) * nin, 0.0);
+    for (int q = 0; q < na; ++q) {
+      const int j = idx[q];
+      std::vector<double> cf(nin, 0.0);
+      cf[j] = 1.0;
+      for (int p = 0; p < q; ++p) {
+        const double lij = Lc[(size_t)j * nin + idx[p]];
+        for (int jj = 0; jj < nin; ++jj) cf[jj] -= lij * T[(size_t)p * nin + jj];
+      }
+      for (int jj = 0; jj < nin; ++jj) T[(size_t)q * nin + jj] = cf[jj] / Lc[(size_t)j * nin + j];
+    }
+    for (int q = 0; q < na; ++q)
+      ITN_HIP(c.h, lincomb(Vs(k), n, nin, &T[(size_t)q * nin], 0.0, Vs(s_orth + q), n, c.s));
+    if (na > 0)
+      ITN_HIP(c.h, hipMemcpyAsync(Vs(k), Vs(s_orth), (size_t)na * n * 8, hipMemcpyDeviceToDevice, c.s));
+    *nout = na;
+    return ITN_OK;
+  };
+  for (;;) {
+    // Ritz pairs of the projected problem
     std::vector<double> Hs((size_t)k * k);
     for (int a = 0; a < k; ++a)
-      for (int b = 0; b < k; ++b) Hs[a * k + b] = 0.5 * (Hk[a * kmax + b] + Hk[b * kmax + a]);
+      for (int b = 0; b < k; ++b) Hs[a * k + b] = 0.5 * (H(a, b) + H(b, a));
     jacobi_eigh(k, Hs, w, Y);
     theta = w[0];
-    y.assign(k, 0.0);
-    for (int a = 0; a < k; ++a) y[a] = Y[a * k + 0];
-    if (k == kmax) {  // thick restart from the lowest KEEP Ritz vectors
-      const int keep = std::min(KEEP, k - 1);
-      for (int j = 0; j < keep; ++j) {
-        std::vector<double> yj(k);
-        for (int a = 0; a < k; ++a) yj[a] = Y[a * k + j];
-        ITN_HIP(c.h, lincomb(V, n, k, yj.data(), 0.0, V + (size_t)(kmax + j) * n, n, c.s));
-        ITN_HIP(c.h, lincomb(AV, n, k, yj.data(), 0.0, AV + (size_t)(kmax + j) * n, n, c.s));
+    y0.assign(k, 0.0);
+    for (int a = 0; a < k; ++a) y0[a] = Y[a * k + 0];
+    const int nb = std::min(B, k);
+    // residuals of the nb lowest pairs, staged in slots k .. k+nb-1
+    for (int j = 0; j < nb; ++j) {
+      std::vector<double> yj(k), ny(k);
+      for (int a = 0; a < k; ++a) {
+        yj[a] = Y[a * k + j];
+        ny[a] = -w[j] * yj[a];
       }
-      ITN_HIP(c.h, hipMemcpyAsync(V, V + (size_t)kmax * n, (size_t)keep * n * 8,
-                                  hipMemcpyDeviceToDevice, c.s));
-      ITN_HIP(c.h, hipMemcpyAsync(AV, AV + (size_t)kmax * n, (size_t)keep * n * 8,
-                                  hipMemcpyDeviceToDevice, c.s));
-      std::fill(Hk.begin(), Hk.end(), 0.0);
-      for (int j = 0; j < keep; ++j) Hk[j * kmax + j] = w[j];
-      k = keep;
-      y.assign(k, 0.0);
-      y[0] = 1.0;
+      ITN_HIP(c.h, lincomb(AV, n, k, yj.data(), 0.0, Vs(k + j), n, c.s));
+      ITN_HIP(c.h, lincomb(V, n, k, ny.data(), 1.0, Vs(k + j), n, c.s));
     }
-    // r = AV y - theta V y, in slot k (the next basis vector if r is kept)
-    double* r = V + (size_t)k * n;
-    std::vector<double> ny(k);
-    for (int a = 0; a < k; ++a) ny[a] = -theta * y[a];
-    ITN_HIP(c.h, lincomb(AV, n, k, y.data(), 0.0, r, n, c.s));
-    ITN_HIP(c.h, lincomb(V, n, k, ny.data(), 1.0, r, n, c.s));
-    // (2) V^T r and r.r
-    ITN_TRY(dots(c, V, n, k + 1, r, tmp.data()));
-    const double r2 = tmp[k];
-    rn = std::sqrt(std::max(r2, 0.0));
+    if (B > 1) {  // keep the lowest pair's residual for the convergence test, precondition all
+      ITN_HIP(c.h, hipMemcpyAsync(Vs(s_spare), Vs(k), n * 8, hipMemcpyDeviceToDevice, c.s));
+      for (int j = 0; j < nb; ++j)
+        ITN_HIP(c.h, precond_diag(Vs(k + j), diag, w[j], 1e-2 * std::max(1.0, std::fabs(w[j])), n, c.s));
+    }
+    // projections on the basis and the block's Gram matrix: G(j, a) = <V_a, t_j>, a < k + nb
+    std::vector<int> off(nb);
+    int orr = 0;
+    {
+      DotBatch db(c, n);
+      for (int j = 0; j < nb; ++j) ITN_TRY(db.add(V, k + nb, Vs(k + j), &off[j]));
+      if (B > 1) ITN_TRY(db.add(Vs(s_spare), 1, Vs(s_spare), &orr));
+      ITN_TRY(db.read(got));
+    }
+    std::vector<double> G0 = got;
+    auto G = [&](int j, int a) { return G0[off[j] + a]; };
+    rn = std::sqrt(std::max(B > 1 ? G0[orr] : G(0, k), 0.0));
     if (rn <= tol * std::max(1.0, std::fabs(theta))) {
       conv = true;
       break;
     }
-    if (it + 1 >= maxiter) break;
-    // Gram-Schmidt against V.  With V orthonormal the projected norm is
-    // r.r - |V^T r|^2; a second pass (and its reduction) is needed only when
-    // the projection removed much of r (Daniel-Gragg-Kaufman-Stewart test:
-    // kept norm below 1/sqrt(2)).  The Galerkin residual is orthogonal to V
-    // up to rounding, so one pass is the common case.
-    double p2 = 0.0;
-    for (int a = 0; a < k; ++a) {
-      p2 += tmp[a] * tmp[a];
-      tmp[a] = -tmp[a];
-    }
-    ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, r, n, c.s));
-    double t2 = r2 - p2;
-    if (!(t2 > 0.5 * r2)) {
-      ITN_TRY(dots(c, V, n, k + 1, r, tmp.data()));  // (3) second pass
-      double c2 = 0.0;
-      for (int a = 0; a < k; ++a) {
-        c2 += tmp[a] * tmp[a];
-        tmp[a] = -tmp[a];
+    if (used >= maxiter) break;
+    if (k + nb > kmax) {
+      // restart from the m lowest Ritz vectors (staged, then moved to the front)
+      const int m = std::min(k, std::max(keep_base, nb));
+      for (int j = 0; j < m; ++j) {
+        std::vector<double> yj(k);
+        for (int a = 0; a < k; ++a) yj[a] = Y[a * k + j];
+        ITN_HIP(c.h, lincomb(V, n, k, yj.data(), 0.0, Vs(s_rest + j), n, c.s));
+        ITN_HIP(c.h, lincomb(AV, n, k, yj.data(), 0.0, AVs(s_rest + j), n, c.s));
       }
-      t2 = tmp[k] - c2;
-      if (!(t2 > 1e-28 * std::max(1.0, r2))) {  // no new direction
-        conv = true;
-        break;
+      ITN_HIP(c.h, hipMemcpyAsync(V, Vs(s_rest), (size_t)m * n * 8, hipMemcpyDeviceToDevice, c.s));
+      ITN_HIP(c.h, hipMemcpyAsync(AV, AVs(s_rest), (size_t)m * n * 8, hipMemcpyDeviceToDevice, c.s));
+      std::fill(Hk.begin(), Hk.end(), 0.0);
+      for (int j = 0; j < m; ++j) H(j, j) = w[j];
+      k = m;
+      if (mixed) {  // the new cycle's first vector applied in FP64: exact row and column 0
+        ITN_TRY(heff(c, i, ITN_P_F64, V, AV, cl, cr));
+        ++used;
+        DotBatch db(c, n);
+        int o;
+        ITN_TRY(db.add(V, k, AV, &o));
+        ITN_TRY(db.read(got));
+        for (int a = 0; a < k; ++a) H(a, 0) = H(0, a) = got[o + a];
       }
-      ITN_HIP(c.h, lincomb(V, n, k, tmp.data(), 1.0, r, n, c.s));
+      continue;
     }
-    ITN_HIP(c.h, scale(r, 1.0 / std::sqrt(t2), n, c.s));
-    ITN_TRY(heff(c, i, prec, r, AV + (size_t)k * n, cl, cr));
-    ++k;
+    const int nbb = std::min(nb, maxiter - used);
+    int na = 0;
+    if (B == 1) {
+      // one residual: classical Gram-Schmidt, a second pass when the first
+      // removed more than half of its norm; no new direction left when the
+      // second pass keeps less than 1e-28 of it
+      const double r2 = G(0, k);
+      std::vector<double> ref(1, r2);
+      double t2 = r2;
+      for (int a = 0; a < k; ++a) t2 -= G(0, a) * G(0, a);
+      if (!(t2 > 0.5 * r2)) {
+        std::vector<double> cj(k);
+        for (int a = 0; a < k; ++a) cj[a] = -G(0, a);
+        ITN_HIP(c.h, lincomb(V, n, k, cj.data(), 1.0, Vs(k), n, c.s));
+        DotBatch db(c, n);
+        int o;
+        ITN_TRY(db.add(V, k + 1, Vs(k), &o));
+        ITN_TRY(db.read(got));
+        std::vector<double> G1(got.begin() + o, got.begin() + o + k + 1);
+        ITN_TRY(cholqr(1, [&](int, int a) { return G1[a]; }, 1e-28, ref, &na));
+      } else {
+        ITN_TRY(cholqr(1, [&](int j, int a) { return G(j, a); }, 1e-28, ref, &na));
+      }
+    } else {
+      // a block: two rounds of Cholesky QR (the second from fresh products,
+      // on vectors already close to orthonormal)
+      std::vector<double> ref(nbb);
+      for (int j = 0; j < nbb; ++j) ref[j] = G(j, k + j);
+      ITN_TRY(cholqr(nbb, [&](int j, int a) { return G(j, a); }, 1e-20, ref, &na));
+      if (na > 0) {
+        std::vector<int> o2(na);
+        DotBatch db(c, n);
+        for (int q = 0; q < na; ++q) ITN_TRY(db.add(V, k + na, Vs(k + q), &o2[q]));
+        ITN_TRY(db.read(got));
+        std::vector<double> G2 = got, ones(na, 1.0);
+        const int na1 = na;
+        ITN_TRY(cholqr(na1, [&](int j, int a) { return G2[o2[j] + a]; }, 1e-10, ones, &na));
+      }
+    }
+    if (na == 0) {  // the basis holds the invariant subspace up to rounding
+      conv = true;
+      break;
+    }
+    // one batched matvec for the accepted vectors
+    ITN_TRY(heff(c, i, prec, Vs(k), AVs(k), cl, cr, na));
+    used += na;
+    // new columns of the projected matrix; in mixed mode row 0 from the exact AV_0
+    {
+      DotBatch db(c, n);
+      std::vector<int> oc(na), o0(na);
+      for (int q = 0; q < na; ++q) ITN_TRY(db.add(V, k + na, AVs(k + q), &oc[q]));
+      if (mixed)
+        for (int q = 0; q < na; ++q) ITN_TRY(db.add(AV, 1, Vs(k + q), &o0[q]));
+      ITN_TRY(db.read(got));
+      for (int q = 0; q < na; ++q)
+        for (int a = 0; a <= k + q; ++a) H(a, k + q) = H(k + q, a) = got[oc[q] + a];
+      for (int q = 0; q < na; ++q)
+        for (int l = q + 1; l < na; ++l)  // symmetric average inside the block
+          H(k + q, k + l) = H(k + l, k + q) = 0.5 * (got[oc[l] + k + q] + got[oc[q] + k + l]);
+      if (mixed)
+        for (int q = 0; q < na; ++q) H(0, k + q) = H(k + q, 0) = got[o0[q]];
+    }
+    k += na;
   }
   // the Ritz vector of the last projected problem
-  ITN_HIP(c.h, lincomb(V, n, k, y.data(), 0.0, psi, n, c.s));
+  ITN_HIP(c.h, lincomb(V, n, k, y0.data(), 0.0, psi, n, c.s));
+  if (mixed && exact_final) {
+    // FP64 Rayleigh quotient and residual of the result
+    double* ax = AVs(s_spare);
+    ITN_TRY(heff(c, i, ITN_P_F64, psi, ax, cl, cr));
+    DotBatch db(c, n);
+    int o1, o2;
+    ITN_TRY(db.add(psi, 1, ax, &o1));
+    ITN_TRY(db.add(psi, 1, psi, &o2));
+    ITN_TRY(db.read(got));
+    const double xx = got[o2];
+    theta = got[o1] / xx;
+    double* r = Vs(s_spare);
+    const double cf[2] = {1.0, -theta};
+    ITN_HIP(c.h, lincomb(ax, n, 1, cf, 0.0, r, n, c.s));
+    ITN_HIP(c.h, lincomb(psi, n, 1, cf + 1, 1.0, r, n, c.s));
+    DotBatch db2(c, n);
+    ITN_TRY(db2.add(r, 1, r, &o1));
+    ITN_TRY(db2.read(got));
+    rn = std::sqrt(std::max(got[o1], 0.0) / xx);
+    conv = rn <= tol * std::max(1.0, std::fabs(theta));
+  }
   *energy = theta;
   *resid = rn;
   *converged = conv;
@@ -661,8 +873,8 @@ itn_status ov_project(Ctx& c, const double* LO, const double* B1, const double* 
 }
 
 // One bond: form psi, eigensolve, split, extend the environment.
-itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, double* energy,
-                     double* trunc) {
+itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, bool last,
+                     double* energy, double* trunc) {
   itn_mps* m = c.m;
   const int d = m->d;
   const int64_t cl = m->bond[i], cm = m->bond[i + 1], cr = m->bond[i + 2];
@@ -695,17 +907,31 @@ itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, do
   const int maxiter = c.p->maxiter > 0 ? c.p->maxiter : 100;
   double e = 0.0, r = 0.0;
   bool conv = true;
+  const double* diag = nullptr;
+  if (c.p->block > 1) {  // the diagonal of H_eff for the block expansion's preconditioner
+    const int w = c.mpo->w, d2 = d * d;
+    std::vector<double> wd((size_t)w * w * d2, 0.0);
+    const double* W1 = c.mpo->site(i);
+    const double* W2 = c.mpo->site(i + 1);
+    for (int m0 = 0; m0 < w; ++m0)
+      for (int m2 = 0; m2 < w; ++m2)
+        for (int s1 = 0; s1 < d; ++s1)
+          for (int s2 = 0; s2 < d; ++s2) {
+            double v = 0.0;
+            for (int m1 = 0; m1 < w; ++m1)
+              v += W1[((m0 * w + m1) * d + s1) * d + s1] * W2[((m1 * w + m2) * d + s2) * d + s2];
+            wd[((size_t)m0 * w + m2) * d2 + s1 * d + s2] = v;
+          }
+    ITN_TRY(m->wdiag.ensure(c.h, wd.size() * 8));
+    ITN_TRY(m->hdiag.ensure(c.h, (size_t)n * 8));
+    ITN_HIP(c.h, hipMemcpyAsync(m->wdiag.p, wd.data(), wd.size() * 8, hipMemcpyHostToDevice, c.s));
+    ITN_HIP(c.h, heff_diag(m->Lenv[i].d(), m->Renv[i + 2].d(), m->wdiag.d(), w, d2, cl, cr,
+                           m->hdiag.d(), c.s));
+    diag = m->hdiag.d();
+  }
   {
     PhaseTimer pt(c, &c.t_solve);
-    if (prec == ITN_P_F64) {
-      ITN_TRY(davidson(c, i, ITN_P_F64, tol, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
-    } else {
-      // low-precision phase to its own noise floor, then FP64 refinement
-      const double tol_lo = std::max(tol, prec == ITN_P_BF16 ? 2e-2 : 2e-5);
-      ITN_TRY(davidson(c, i, prec, tol_lo, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
-      if (c.p->refine)
-        ITN_TRY(davidson(c, i, ITN_P_F64, tol, maxiter, m->psi.d(), n, cl, cr, &e, &r, &conv));
-    }
+    ITN_TRY(davidson(c, i, prec, tol, maxiter, m->psi.d(), n, cl, cr, diag, last, &e, &r, &conv));
   }
   c.max_resid = std::max(c.max_resid, r);
   if (!conv && (prec == ITN_P_F64 || c.p->refine)) c.unconverged = true;
@@ -871,15 +1097,16 @@ itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
   for (int sw = 0; sw < p->nsweeps; ++sw) {
     auto t0 = std::chrono::steady_clock::now();
     c.matvecs = 0;
+    c.matvecs64 = 0;
     c.max_resid = 0.0;
     c.t_mv = c.t_solve = c.t_split = c.t_env = 0.0;
     double E = 0.0, maxtr = 0.0, tr = 0.0;
     for (int i = 0; i <= N - 2; ++i) {
-      ITN_TRY(bond_step(c, i, true, p->maxdim[sw], p->cutoff[sw], &E, &tr));
+      ITN_TRY(bond_step(c, i, true, p->maxdim[sw], p->cutoff[sw], false, &E, &tr));
       maxtr = std::max(maxtr, tr);
     }
     for (int i = N - 2; i >= 0; --i) {
-      ITN_TRY(bond_step(c, i, false, p->maxdim[sw], p->cutoff[sw], &E, &tr));
+      ITN_TRY(bond_step(c, i, false, p->maxdim[sw], p->cutoff[sw], i == 0, &E, &tr));
       maxtr = std::max(maxtr, tr);
     }
     ITN_HIP(h, hipStreamSynchronize(c.s));
@@ -890,6 +1117,7 @@ itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
       if (res->max_bond) res->max_bond[sw] = *std::max_element(mps->bond.begin(), mps->bond.end());
       if (res->seconds) res->seconds[sw] = secs;
       if (res->matvecs) res->matvecs[sw] = c.matvecs;
+      if (res->matvecs_f64) res->matvecs_f64[sw] = c.matvecs64;
       if (res->residual) res->residual[sw] = c.max_resid;
       if (p->timing) {
         if (res->t_matvec) res->t_matvec[sw] = c.t_mv;

@@ -362,6 +362,52 @@ hipError_t scale(double* x, double a, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Diagonal of H_eff (FP64): D[a][c][b] = sum_{m0, m2} L[a][m0][a] Wd[m0][m2][c]
+// R[b][m2][b], with Wd[m0][m2][c = s1*d + s2] = sum_m1 W1[m0,m1,s1,s1]
+// W2[m1,m2,s2,s2].  A thread per (a, b).
+__global__ void heff_diag_kernel(const double* __restrict__ L, const double* __restrict__ R,
+                                 const double* __restrict__ Wd, int w, int d2, int64_t cl,
+                                 int64_t cr, double* __restrict__ D) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cl * cr;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = t / cr, b = t % cr;
+    for (int c = 0; c < d2; ++c) {
+      double acc = 0.0;
+      for (int m0 = 0; m0 < w; ++m0) {
+        const double l = L[(a * w + m0) * cl + a];
+        if (l == 0.0) continue;
+        for (int m2 = 0; m2 < w; ++m2) acc += l * Wd[(m0 * w + m2) * d2 + c] * R[(b * w + m2) * cr + b];
+      }
+      D[(a * d2 + c) * cr + b] = acc;
+    }
+  }
+}
+hipError_t heff_diag(const double* L, const double* R, const double* Wd, int w, int d2, int64_t cl,
+                     int64_t cr, double* D, hipStream_t s) {
+  if (cl * cr == 0) return hipSuccess;
+  hipLaunchKernelGGL(heff_diag_kernel, dim3(grid_for(cl * cr, 256, 8192)), dim3(256), 0, s, L, R, Wd,
+                     w, d2, cl, cr, D);
+  return hipGetLastError();
+}
+
+// r[i] /= (D[i] - theta), denominators of magnitude below eps clipped to eps
+// (Davidson's diagonal preconditioner).
+__global__ void precond_diag_kernel(double* __restrict__ r, const double* __restrict__ D, double theta,
+                                    double eps, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double den = D[i] - theta;
+    if (fabs(den) < eps) den = den < 0.0 ? -eps : eps;
+    r[i] /= den;
+  }
+}
+hipError_t precond_diag(double* r, const double* D, double theta, double eps, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(precond_diag_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, r, D, theta,
+                     eps, n);
+  return hipGetLastError();
+}
+
 template <typename T> __global__ void fill_kernel(T* x, T v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

@@ -221,6 +221,12 @@ hipError_t scale(double* x, double a, int64_t n, hipStream_t s);
 hipError_t lincomb_dev(const double* V, int64_t ldv, int k, const double* c, double scale, double* y,
                        int64_t n, hipStream_t s);
 hipError_t fill(void* x, int dtype, double v, int64_t n, hipStream_t s);
+// Diagonal of the dense H_eff (FP64): L [cl, w, cl], R [cr, w, cr], Wd [w][w][d2]
+// (Wd[m0][m2][s1*d + s2] = sum_m1 W1[m0,m1,s1,s1] W2[m1,m2,s2,s2]), D [cl, d2, cr].
+hipError_t heff_diag(const double* L, const double* R, const double* Wd, int w, int d2, int64_t cl,
+                     int64_t cr, double* D, hipStream_t s);
+// r /= (D - theta) element-wise, denominators clipped to magnitude >= eps.
+hipError_t precond_diag(double* r, const double* D, double theta, double eps, int64_t n, hipStream_t s);
 
 // Householder tridiagonalisation of a symmetric FP64 n x n matrix A (rows of
 // length n at stride lda; read only) in one cooperative launch of nwg

@@ -27,15 +27,20 @@ def run(h, Ws, As0, sweeps, **kw):
     return recs, mps
 
 
+@pytest.mark.parametrize("block", [1, 4])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-def test_c0_heisenberg_matches_ed(h, e_ed10, prec):
+def test_c0_heisenberg_matches_ed(h, e_ed10, prec, block):
     """N=10 S=1/2, maxdim 32 (an exact representation), 5 sweeps, random
     product start: |E - E_ED| / |E_ED| <= 1e-10 (FP64), and the same for the
-    mixed-precision runs after their FP64 refinement."""
+    mixed-precision runs (low-precision expansions, each restart vector
+    applied in FP64); single-vector and block (4 vectors per batched matvec)
+    Davidson."""
     N = 10
     As0 = inp.random_product_state(N, 2, inp.rng_for(0, 32))
     recs, mps = run(h, inp.heisenberg_mpo(N), As0, [(32, 1e-14)] * 5, prec=prec, eig_tol=1e-12,
-                    krylovdim=12, maxiter=400)
+                    krylovdim=12, maxiter=400, block=block)
+    print("c0", prec, block, recs[-1]["energy"] - e_ed10, recs[-1]["matvecs"],
+          recs[-1]["matvecs_f64"])
     E = recs[-1]["energy"]
     assert abs(E - e_ed10) / abs(e_ed10) <= 1e-10, (prec, E, e_ed10)
     bonds = h.mps_bonds(mps)
@@ -43,8 +48,12 @@ def test_c0_heisenberg_matches_ed(h, e_ed10, prec):
     # the returned state carries that energy
     sites = h.mps_sites(mps)
     assert abs(hf.mps_energy(sites, inp.heisenberg_mpo(N)) - E) / abs(E) <= 1e-9
+    tot = sum(r["matvecs"] for r in recs)
+    f64 = sum(r["matvecs_f64"] for r in recs)
     if prec != "f64":
-        assert recs[-1]["matvecs"] > 0
+        assert tot > f64 > 0
+    else:
+        assert tot == f64
 
 
 def test_c0_matches_oracle_dmrg_per_converged_sweep(h):
@@ -203,3 +212,28 @@ def test_bond_split_eigensolvers_agree(h, monkeypatch, maxdim):
         assert abs(a["energy"] - b["energy"]) <= 1e-10 * abs(a["energy"]), (a, b)
         assert a["max_bond"] == b["max_bond"], (a, b)
         assert abs(a["max_trunc"] - b["max_trunc"]) <= 1e-12, (a, b)
+
+
+@pytest.mark.parametrize("block", [1, 4])
+def test_mixed_precision_sweeps_mostly_low_precision(h, block):
+    """Spin-1 chain (N = 20, maxdim 64), bf16 expansions with FP64 restart
+    vectors and a small Davidson budget per bond (4 vectors, 8 matvecs; four
+    times that with blocks of 4): at least 70 % of the matvecs run in bf16,
+    at most 2.5 FP64 matvecs per bond on average (3.5 with blocks), and the
+    converged energy agrees with the FP64 run to 1e-9 relative."""
+    N = 20
+    As0 = inp.random_product_state(N, 3, inp.rng_for(2, 64))
+    sched = [(64, 1e-10)] * 6
+    kw = dict(eig_tol=1e-9, krylovdim=4 * block, maxiter=8 * block, allow_unconverged=True,
+              block=block)
+    r64, _ = run(h, inp.heisenberg_mpo(N, 2), As0, sched, prec="f64", **kw)
+    rbf, _ = run(h, inp.heisenberg_mpo(N, 2), As0, sched, prec="bf16", **kw)
+    bonds = 2 * (N - 1)
+    tot = sum(r["matvecs"] for r in rbf)
+    f64 = sum(r["matvecs_f64"] for r in rbf)
+    print("mixed", block, tot, f64, f64 / (len(rbf) * bonds), rbf[-1]["energy"], r64[-1]["energy"])
+    assert (tot - f64) / tot >= 0.70
+    # single-vector: a restart cycle is one FP64 and three bf16 matvecs; the
+    # block solve runs more (batched) matvecs per bond and more cycles
+    assert f64 / (len(rbf) * bonds) <= (2.5 if block == 1 else 3.5)
+    assert abs(rbf[-1]["energy"] - r64[-1]["energy"]) <= 1e-9 * abs(r64[-1]["energy"])
