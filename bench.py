@@ -174,6 +174,45 @@ def time_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def size_leg(h, torch, np, inp, chi, d, steps, warmup, precs=("bf16", "f32", "f64")):
+    """The dense matvec at another bond dimension / local dimension (same
+    workload recipe as the headline): ms, TFLOP/s and fraction of the
+    precision's MFMA peak per precision, per-kernel times, error vs FP64."""
+    L64, W1, W2, R64, psi = build_workload(h, chi, d, torch, np, inp)
+    w = W1.shape[0]
+    flops = heff_flops(chi, chi, d, w)
+    work = kernel_work(chi, chi, d, w)
+    tdt = {"bf16": torch.bfloat16, "f32": torch.float32, "f64": torch.float64}
+    res, outs = {}, {}
+    for prec in precs:
+        if prec == "f64":
+            Lp, Rp = L64, R64
+        else:
+            Lp = torch.empty(L64.shape, dtype=tdt[prec], device="cuda:0")
+            Rp = torch.empty(R64.shape, dtype=tdt[prec], device="cuda:0")
+            h.cast(L64, Lp)
+            h.cast(R64, Rp)
+        out = torch.zeros_like(psi)
+        st = steps if prec != "f64" else max(2, steps // 4)
+        ms = time_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, st, warmup)
+        prof = profile_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, max(2, st // 2))
+        for k, v in prof.items():
+            if k in work:
+                v["tflops"] = work[k] / (v["avg_ms"] * 1e-3) / 1e12
+                v["frac_of_peak"] = v["tflops"] / PEAK_TFLOPS[prec]
+        tf = flops / (ms * 1e-3) / 1e12
+        res[prec] = {"ms_per_step": ms, "tflops": tf, "frac_of_peak": tf / PEAK_TFLOPS[prec],
+                     "steps": st, "kernels": prof}
+        outs[prec] = out
+        del Lp, Rp
+    if "f64" in outs:
+        for prec in outs:
+            if prec != "f64":
+                res[prec]["rel_err_vs_f64"] = float(torch.linalg.vector_norm(outs[prec] - outs["f64"]) /
+                                                    torch.linalg.vector_norm(outs["f64"]))
+    return {"chi": chi, "d": d, "w": w, "flop_per_step": flops, "by_precision": res}
+
+
 def profile_heff(h, torch, Lp, W1, W2, Rp, psi, out, prec, steps):
     h.profile(True)
     for _ in range(steps):
@@ -381,15 +420,38 @@ def time_qn(h, torch, np, inp, which, prec, nv, steps, warmup):
     h.profile(False)
     out = Od["data"].clone()
     del Ld, Rd, Pd, Od
+    kern = {k: {"avg_ms": v[0] / max(1, v[1]), "launches": v[1]} for k, v in rep.items()}
+    # roofline of each stage: block-sparse flops of the grouped GEMMs against
+    # the MFMA peak of the precision; the W-stage's compulsory bytes (read X
+    # once, write Z once, in their stored types) against HBM
+    es = {"bf16": 2, "f32": 4, "f64": 8}[prec]
+    xs = es  # X is stored in the operand type (bf16 applies accumulate it in f32)
+    work = {"qn_stage1_grouped": ("mfma", info["flops_stage1"]),
+            "qn_stage4_grouped": ("mfma", info["flops"] - info["flops_stage1"]),
+            "qn_wstage": ("hbm", nv * (info["x_elems"] * xs + info["z_elems"] * es))}
+    roof = {}
+    for k, (bound, amount) in work.items():
+        if k not in kern:
+            continue
+        t = kern[k]["avg_ms"] * 1e-3
+        if bound == "mfma":
+            ach = amount / t / 1e12
+            roof[k] = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec],
+                       "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[prec], "flop_per_launch": amount}
+        else:
+            ach = amount / t / 1e9
+            roof[k] = {"bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s",
+                       "frac": ach / 8000.0, "bytes_per_launch": amount}
     return {"ms_per_apply": ms, "tflops": info["flops"] / (ms * 1e-3) / 1e12,
+            "frac_of_peak": info["flops"] / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+            "roofline": roof,
             "ms_per_apply_prepared_env": ms_pe,
             "tflops_prepared_env": info["flops"] / (ms_pe * 1e-3) / 1e12,
             "flop_per_apply": info["flops"], "out_blocks": info["out_nblocks"],
             "stage1_groups": info["n_groups_stage1"], "stage4_segments": info["n_pairs_stage4"],
             "plan_seconds": tplan, "nv": nv,
             "launch_modes": [info["mode_stage1"], info["mode_stage4"]],
-            "wstage_tile": info["wstage_tile"],
-            "kernels": {k: {"avg_ms": v[0] / max(1, v[1]), "launches": v[1]} for k, v in rep.items()}}, out
+            "wstage_tile": info["wstage_tile"], "kernels": kern}, out
 
 
 # ---------------------------------------------------------------- DMRG leg
@@ -400,16 +462,29 @@ DAVIDSON = {"krylovdim": 4, "maxiter": 8}
 DAVIDSON_TIGHT = {"krylovdim": 8, "maxiter": 60}
 
 
-def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=DAVIDSON):
+def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=DAVIDSON, block=1):
     """Spin-1 Heisenberg chain (d=3, w=5), random product start, the given
-    (maxdim, cutoff) schedule; per-sweep time, energy, matvecs (and, with
-    timing, the per-phase split, which adds stream waits)."""
+    (maxdim, cutoff) schedule; per-sweep time, energy, matvecs (all, and
+    those in FP64), and with timing the per-phase split (adds stream
+    waits).  block > 1: block Davidson, `block` vectors per batched matvec
+    (the Krylov budget scaled by the block)."""
     mpo = h.mpo(inp.heisenberg_mpo(N, 2))
     mps = h.mps(inp.random_product_state(N, 3, inp.rng_for(2, 64)))
+    dv = dict(davidson)
+    if block > 1:
+        dv = {"krylovdim": dv["krylovdim"] * block, "maxiter": dv["maxiter"] * block}
     t0 = time.perf_counter()
     recs = h.dmrg_sweep(mps, mpo, sweeps, prec=prec, eig_tol=1e-9, refine=True,
-                        allow_unconverged=True, timing=timing, **davidson)
-    return {"total_seconds": time.perf_counter() - t0, "sweeps": recs}
+                        allow_unconverged=True, timing=timing, block=block, **dv)
+    secs = time.perf_counter() - t0
+    mps.close()
+    mpo.close()
+    tot = sum(r["matvecs"] for r in recs)
+    f64 = sum(r["matvecs_f64"] for r in recs)
+    bonds = 2 * (N - 1) * len(recs)
+    return {"total_seconds": secs, "sweeps": recs, "block": block, "davidson": dv,
+            "matvecs": tot, "matvecs_f64": f64, "low_precision_fraction": (tot - f64) / tot,
+            "f64_matvecs_per_bond": f64 / bonds}
 
 
 def main():
@@ -426,6 +501,8 @@ def main():
     ap.add_argument("--no-qn", action="store_true")
     ap.add_argument("--no-dmrg", action="store_true")
     ap.add_argument("--no-sum", action="store_true")
+    ap.add_argument("--no-sizes", action="store_true",
+                    help="skip the other dense sizes (chi 256/512/1024 at d=2, chi 2048 at d=3)")
     ap.add_argument("--dmrg-maxdim", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed work, copy a buffer of this many bytes 3 times "
@@ -513,6 +590,19 @@ def main():
     }
     if "f64" in results and head != "f64":
         line["speedup_vs_fp64_gpu"] = results["f64"]["ms_per_step"] / r["ms_per_step"]
+    if not args.only and not args.no_sizes:
+        sizes = {}
+        for cs, ds in ((256, 2), (512, 2), (1024, 2), (2048, 3)):
+            if (cs, ds) == (chi, d):
+                continue
+            log("[bench] dense chi=%d d=%d" % (cs, ds))
+            sizes["chi%d_d%d" % (cs, ds)] = size_leg(h, torch, np, inp, cs, ds, args.steps,
+                                                     args.warmup)
+            b = sizes["chi%d_d%d" % (cs, ds)]["by_precision"]
+            log("[bench]   " + ", ".join("%s %.3f ms (%.1f%% of peak)" % (p, v["ms_per_step"],
+                                                                        100 * v["frac_of_peak"])
+                                        for p, v in b.items()))
+        line["dense_sizes"] = sizes
     if not args.only:
         log("[bench] TTGT comparators (library GEMMs + permutes, FP64)")
         line["ttgt_gpu_f64"] = ttgt_gpu(torch, L64, W1, W2, R64, psi, flops, args.steps // 4 + 2)
@@ -540,11 +630,13 @@ def main():
         md = args.dmrg_maxdim
         sched = [(min(64, md), 1e-10), (min(128, md), 1e-10)] + [(md, 1e-10)] * 4
         dm = {}
-        for prec in ("f64", "bf16"):
-            log("[bench] DMRG spin-1 N=100 %s, maxdim up to %d" % (prec, md))
-            dm[prec] = dmrg_leg(h, np, inp, prec, sched)
-            log("[bench]   %.1f s, E=%.12f" % (dm[prec]["total_seconds"],
-                                               dm[prec]["sweeps"][-1]["energy"]))
+        for prec, blk in (("f64", 1), ("bf16", 1), ("f64", 4), ("bf16", 4)):
+            key = prec if blk == 1 else "%s_block%d" % (prec, blk)
+            log("[bench] DMRG spin-1 N=100 %s, block %d, maxdim up to %d" % (prec, blk, md))
+            dm[key] = dmrg_leg(h, np, inp, prec, sched, block=blk)
+            log("[bench]   %.1f s, E=%.12f, %d matvecs (%d FP64)" % (
+                dm[key]["total_seconds"], dm[key]["sweeps"][-1]["energy"], dm[key]["matvecs"],
+                dm[key]["matvecs_f64"]))
         log("[bench] DMRG reference: FP64, tight Davidson budget %s" % DAVIDSON_TIGHT)
         ref_run = dmrg_leg(h, np, inp, "f64", sched, davidson=DAVIDSON_TIGHT)
         e_conv = ref_run["sweeps"][-1]["energy"]
@@ -571,7 +663,7 @@ def main():
         log("[bench] DMRG bf16 time split (phase-timed run)")
         sp = dmrg_leg(h, np, inp, "bf16", sched, timing=True)["sweeps"][-1]
         split = {k: sp[k] for k in ("seconds", "t_matvec", "t_solver", "t_split", "t_env", "matvecs",
-                                    "max_bond")}
+                                    "matvecs_f64", "max_bond")}
         line["dmrg"] = {"model": "spin-1 Heisenberg chain, N=100, d=3, w=5",
                         "schedule": sched, **dm, "bf16_last_sweep_split": split}
     if not args.no_dmrg and not args.only:
@@ -591,6 +683,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         line["copy_probe_bytes"] = n * 4
+    h.close()
     print(json.dumps(line), flush=True)
 
 

@@ -237,6 +237,8 @@ typedef struct {
   int32_t mode_stage4;     /* itn_qn_heff_apply); -1 before the first apply       */
   int32_t wstage_tile;     /* W-stage kernel: 0 streaming, else LDS-staged with   */
                            /* this many positions per block; -1 before the first apply */
+  double flops_stage1;     /* the part of `flops` in the L*psi stage (the rest is   */
+                           /* the Z*R stage)                                         */
 } itn_plan_info;
 itn_status itn_plan_query(const itn_plan* plan, itn_plan_info* info);
 /* Copy the output block table: block_sec[out_nblocks*4], block_off[out_nblocks]. */

@@ -37,7 +37,8 @@ class itn_plan_info(C.Structure):
                 ("n_pairs_stage1", C.c_int64), ("n_groups_stage1", C.c_int64),
                 ("n_pairs_stage4", C.c_int64), ("n_tiles", C.c_int64), ("flops", C.c_double),
                 ("x_elems", C.c_int64), ("z_elems", C.c_int64), ("flops_wstage", C.c_double),
-                ("mode_stage1", C.c_int32), ("mode_stage4", C.c_int32), ("wstage_tile", C.c_int32)]
+                ("mode_stage1", C.c_int32), ("mode_stage4", C.c_int32), ("wstage_tile", C.c_int32),
+                ("flops_stage1", C.c_double)]
 
 
 class itn_sweep_params(C.Structure):

@@ -302,7 +302,7 @@ struct itn_plan {
   int64_t max_db = 0;  // widest right bond sector
   int64_t max_nin = 0; // most distinct X inputs of one W-stage pair
   int64_t pairs1 = 0;
-  double flops_gemm = 0.0, flops_w = 0.0;
+  double flops_gemm = 0.0, flops_w = 0.0, flops_s1 = 0.0;
   // device state
   int device = -1;
   char* dtab = nullptr;  // all tables
@@ -590,6 +590,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       xgroup[{ia, im}] = {xacc, iap};
       xacc += M * N_ia[ia];
       pl.flops_gemm += 2.0 * M * N_ia[ia] * SA.dim[ia];
+      pl.flops_s1 += 2.0 * M * N_ia[ia] * SA.dim[ia];
       for (size_t b = 0; b < P.blocks.size(); ++b) pl.pairs1 += P.blocks[b][0] == ia;
     }
   }
@@ -1088,6 +1089,7 @@ itn_status itn_plan_query(const itn_plan* pl, itn_plan_info* info) {
   info->x_elems = pl->X_elems;
   info->z_elems = pl->Z_elems;
   info->flops_wstage = pl->flops_w * pl->nv;
+  info->flops_stage1 = pl->flops_s1 * pl->nv;
   info->mode_stage1 = pl->tuned ? pl->cfg1 : -1;
   info->mode_stage4 = pl->tuned ? pl->cfg4 : -1;
   info->wstage_tile = pl->tuned ? itn_plan::kWCand[pl->wsel] : -1;
