@@ -144,9 +144,20 @@ itn_status itn_cast(itn_handle* h, const itn_tensor* src, itn_tensor* dst, void*
  * interface of Sec. 9.1): labels shared by A and B are summed; C's labels
  * must be exactly the remaining ones, in any order (the caller fixes the
  * output order).  No shared label is an outer product, all shared (rank-0
- * C) an inner product.  Dense operands only; dtypes F64 or F32 for A, B, C
- * (ITN_P_BF16 rounds operands to bf16).  Errors: ITN_E_LABEL,
- * ITN_E_SHAPE, ITN_E_DTYPE. */
+ * C) an inner product.  Dtypes F64 or F32 for A, B, C (ITN_P_BF16 rounds
+ * operands to bf16).  Errors: ITN_E_LABEL, ITN_E_SHAPE, ITN_E_DTYPE.
+ *
+ * Block-sparse operands (all three carry `space`; Sec. 8, 9.4): every pair
+ * of an A block and a B block whose contracted sectors agree is a dense
+ * block product; pairs landing on one C block are summed in ascending
+ * (A block, B block) order.  Contracted indices must have opposite arrows
+ * (ITN_E_ARROW) and equal sectors (ITN_E_SHAPE); each C index keeps the
+ * arrow and sectors of the index it comes from; every given block must obey
+ * its tensor's flux rule and flux(C) must equal flux(A) + flux(B)
+ * (ITN_E_FLUX).  C's block list must hold every block a contributing pair
+ * reaches (ITN_E_FLUX otherwise); C blocks no pair reaches are set to zero.
+ * All block products run as one grouped launch.  Mixing dense and
+ * block-sparse operands is ITN_E_ARG. */
 itn_status itn_contract(itn_handle* h, const itn_tensor* A, const itn_tensor* B, itn_tensor* C,
                         itn_prec prec, void* hip_stream);
 

@@ -425,8 +425,12 @@ def _qn(keep: _Keep, desc) -> L.itn_tensor:
         tt.nblocks = len(blocks)
         tt.block_sec = keep.arr(C.c_int32, [int(x) for b in blocks for x in b])
         tt.block_off = keep.arr(C.c_int64, [int(x) for x in desc["offsets"]])
-        nq = len(spaces[0][0][0]) if isinstance(spaces[0][0][0], (tuple, list)) else 1
-        tt.flux = keep.arr(C.c_int32, [0] * nq)
+        nq = len(spaces[0][0][0]) if spaces and isinstance(spaces[0][0][0], (tuple, list)) else 1
+        flux = desc.get("flux")
+        tt.flux = keep.arr(C.c_int32, [int(x) for x in flux] if flux is not None else [0] * nq)
+    labels = desc.get("labels")
+    if labels is not None:
+        tt.label = keep.arr(C.c_int32, [int(x) for x in labels])
     return tt
 
 
@@ -438,6 +442,17 @@ def _qn_handle_methods():
         self._check(self.lib.itn_qn_heff_plan(self.h, *[C.byref(t) for t in ts], int(nv),
                                               PREC[prec], C.byref(out)))
         return Plan(self, out)
+
+    def contract_blocks(self, Ad, la, Bd, lb, Cd, lc, prec: str = "f64", stream=None):
+        """Block-sparse C = A * B over labels (itn_contract with QN
+        operands).  Ad, Bd, Cd: QN descriptors (spaces, blocks, offsets,
+        flux, data); C's block list must hold every block a contributing
+        pair reaches, its other blocks are zeroed."""
+        k = _Keep()
+        ts = [_qn(k, dict(d, labels=list(l))) for d, l in ((Ad, la), (Bd, lb), (Cd, lc))]
+        self._check(self.lib.itn_contract(self.h, *[C.byref(t) for t in ts], PREC[prec],
+                                          self._sp(stream)))
+        return Cd
 
     def qn_allowed_blocks(self, spaces, flux=None):
         """(blocks, offsets, total) of the zero-flux (or `flux`) blocks."""
@@ -462,7 +477,7 @@ def _qn_handle_methods():
         k = _Keep()
         refs = [None if x is None else C.byref(_qn(k, x)) for x in (Ld, Rd, Pd, Od)]
         self._check(self.lib.itn_qn_heff_apply(self.h, plan.ptr, *refs, self._sp(stream)))
-    return qn_plan, qn_allowed_blocks, qn_apply
+    return qn_plan, qn_allowed_blocks, qn_apply, contract_blocks
 
 
 class Plan:
@@ -525,7 +540,8 @@ class Plan:
             pass
 
 
-Handle.qn_plan, Handle.qn_allowed_blocks, Handle.qn_apply = _qn_handle_methods()
+(Handle.qn_plan, Handle.qn_allowed_blocks, Handle.qn_apply,
+ Handle.contract_blocks) = _qn_handle_methods()
 
 
 class _Owned:

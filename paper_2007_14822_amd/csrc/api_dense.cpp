@@ -332,6 +332,8 @@ itn_status itn_cast(itn_handle* h, const itn_tensor* src, itn_tensor* dst, void*
 itn_status itn_contract(itn_handle* h, const itn_tensor* A, const itn_tensor* B, itn_tensor* C,
                         itn_prec prec, void* hip_stream) {
   if (!h) return ITN_E_ARG;
+  if (!A || !B || !C) return fail(h, ITN_E_ARG, "A, B and C are required");
+  if (A->space || B->space || C->space) return contract_qn(h, A, B, C, prec, hip_stream);
   ITN_TRY(check_dense(h, A, "A", -1));
   ITN_TRY(check_dense(h, B, "B", -1));
   ITN_TRY(check_dense(h, C, "C", -1));

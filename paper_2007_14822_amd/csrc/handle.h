@@ -119,6 +119,10 @@ itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const* Ls,
                             itn_tensor* out, itn_prec prec, void* hip_stream,
                             const FixedScratch* fixed);
 
+// itn_contract for operands with QN index spaces (block-sparse).
+itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, itn_tensor* C,
+                       itn_prec prec, void* hip_stream);
+
 // Looks up the allocation-free entry point's scratch on `device` (current).
 void noalloc_scratch_init(int device);
 

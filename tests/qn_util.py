@@ -12,7 +12,8 @@ def space(ind: Q.QNIndex):
 
 def desc(bt: Q.BlockTensor, data=None, with_data=True):
     keys, offs, flat = bt.packed()
-    d = {"spaces": [space(i) for i in bt.inds], "blocks": keys, "offsets": offs}
+    d = {"spaces": [space(i) for i in bt.inds], "blocks": keys, "offsets": offs,
+         "flux": list(bt.flux)}
     if with_data:
         d["data"] = flat if data is None else data
     return d, flat
