@@ -138,6 +138,29 @@ itn_status itn_profile_report(itn_handle* h, int32_t max_entries, char* names, d
  * environments in the matrix-core operand type once per bond. */
 itn_status itn_cast(itn_handle* h, const itn_tensor* src, itn_tensor* dst, void* hip_stream);
 
+/* ------------------------------------------------------------- workspace */
+
+/* Operations whose scratch comes from the handle's workspace. */
+typedef enum { ITN_OP_CONTRACT = 0, ITN_OP_HEFF = 1, ITN_OP_ENV_UPDATE = 2 } itn_op;
+
+/* Bytes of workspace one call would use: `t` holds that call's tensors in
+ * its argument order (ITN_OP_CONTRACT: A, B, C; ITN_OP_HEFF: L, W1, W2, R,
+ * psi; ITN_OP_ENV_UPDATE: E, A, W, E_out), with nv (H_eff) and dir
+ * (environment step) as the call takes them; data pointers are not read.
+ * The arguments are validated exactly as the call does (same errors).
+ * Host-only handles may ask. */
+itn_status itn_workspace_size(itn_handle* h, itn_op op, int32_t ntensors, const itn_tensor* const* t,
+                              int32_t nv, int32_t dir, itn_prec prec, size_t* bytes);
+
+/* Use caller-owned device memory (256-byte aligned, `bytes` long) as the
+ * handle's workspace from now on: the library then never grows it, and a
+ * call needing more returns ITN_E_WORKSPACE before queuing work.  The
+ * memory must stay allocated, and is not touched by anything else, while
+ * calls on the handle may run; the library never frees it.  ptr = NULL
+ * (bytes = 0) returns to library-owned workspace.  Waits for the device.
+ * W-stage tables and QN plans stay library-owned. */
+itn_status itn_set_workspace(itn_handle* h, void* ptr, size_t bytes);
+
 /* --------------------------------------------------------------- contract */
 
 /* C = A * B over labels (the product operator of Sec. 4 with the label
@@ -210,7 +233,8 @@ itn_status itn_heff_apply_noalloc(itn_handle* h, const itn_tensor* L, const itn_
 /* Size in bytes of that fixed scratch array. */
 itn_status itn_heff_noalloc_max_bytes(size_t* bytes);
 
-/* Bytes of library workspace itn_heff_apply uses for these extents. */
+/* Bytes of library workspace itn_heff_apply uses for these extents (the
+ * upper bound; itn_workspace_size gives the exact figure of one call). */
 itn_status itn_heff_workspace_size(itn_handle* h, int64_t chi_l, int64_t chi_r, int32_t d,
                                    int32_t w, int32_t nv, itn_prec prec, size_t* bytes);
 

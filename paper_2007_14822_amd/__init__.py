@@ -286,6 +286,53 @@ class Handle:
                                                 self._sp(stream)))
         return out
 
+    def workspace_size(self, op: str, *args, nv: int = 1, direction: str = "left",
+                       prec: str = "f64") -> int:
+        """Workspace bytes one call would use (itn_workspace_size):
+        op "contract": (A, la, B, lb, C, lc), dense tensors or QN descriptors;
+        op "heff": (L, W1, W2, R, psi) with nv; op "env": (E, A, W, E_out)
+        with direction.  Validates like the call (same errors)."""
+        k = _Keep()
+        if op == "contract":
+            A, la, B, lb, Cc, lc = args
+            ts = [_qn(k, dict(x, labels=list(l))) if isinstance(x, dict) else _dense(k, x, l)
+                  for x, l in ((A, la), (B, lb), (Cc, lc))]
+            code, dr = L.ITN_OP_CONTRACT, 0
+        elif op == "heff":
+            Lenv, W1, W2, Renv, psi = args
+            cl, cr, d = Lenv.shape[0], Renv.shape[0], W1.shape[2]
+            W1c = np.ascontiguousarray(W1, np.float64)
+            W2c = np.ascontiguousarray(W2, np.float64)
+            k.items += [W1c, W2c]
+            ts = [_dense(k, Lenv), _dense(k, W1c), _dense(k, W2c), _dense(k, Renv),
+                  _dense(k, psi, shape=(cl, d, d, cr))]
+            code, dr = L.ITN_OP_HEFF, 0
+        elif op == "env":
+            E, A, W, out = args
+            Wc = np.ascontiguousarray(W, np.float64)
+            k.items.append(Wc)
+            ts = [_dense(k, E), _dense(k, A), _dense(k, Wc), _dense(k, out)]
+            code, dr = L.ITN_OP_ENV_UPDATE, (L.ITN_LEFT if direction == "left" else L.ITN_RIGHT)
+        else:
+            raise ValueError("op must be contract, heff or env")
+        arr = (C.POINTER(L.itn_tensor) * len(ts))(*[C.pointer(t) for t in ts])
+        b = C.c_size_t()
+        self._check(self.lib.itn_workspace_size(self.h, code, len(ts), arr, int(nv), dr, PREC[prec],
+                                                C.byref(b)))
+        return b.value
+
+    def set_workspace(self, buf=None):
+        """Use a caller-owned device buffer (a torch tensor, 256-byte aligned)
+        as the workspace; None returns to library-owned workspace.  The
+        handle keeps a reference to the buffer while it is in use."""
+        if buf is None:
+            self._check(self.lib.itn_set_workspace(self.h, None, 0))
+            self._ws_buf = None
+            return
+        nbytes = buf.numel() * buf.element_size()
+        self._check(self.lib.itn_set_workspace(self.h, C.c_void_p(buf.data_ptr()), nbytes))
+        self._ws_buf = buf
+
     def heff_workspace_size(self, chi_l, chi_r, d, w, nv=1, prec="f64") -> int:
         b = C.c_size_t()
         self._check(self.lib.itn_heff_workspace_size(self.h, chi_l, chi_r, d, w, nv, PREC[prec],

@@ -17,6 +17,7 @@ STATUS_NAMES = {
 ITN_F64, ITN_F32, ITN_BF16 = 0, 1, 2
 ITN_P_F64, ITN_P_F32, ITN_P_BF16 = 0, 1, 2
 ITN_LEFT, ITN_RIGHT = 0, 1
+ITN_OP_CONTRACT, ITN_OP_HEFF, ITN_OP_ENV_UPDATE = 0, 1, 2
 
 
 class itn_space(C.Structure):
@@ -79,6 +80,9 @@ SIGNATURES = {
     "itn_heff_apply_sum": (S, [P, C.c_int32, P, P, P, P, T, C.c_int32, T, C.c_int, P]),
     "itn_heff_apply_noalloc": (S, [P, T, T, T, T, T, C.c_int32, T, C.c_int, P]),
     "itn_heff_noalloc_max_bytes": (S, [C.POINTER(C.c_size_t)]),
+    "itn_workspace_size": (S, [P, C.c_int, C.c_int32, C.POINTER(T), C.c_int32, C.c_int32, C.c_int,
+                               C.POINTER(C.c_size_t)]),
+    "itn_set_workspace": (S, [P, P, C.c_size_t]),
     "itn_heff_workspace_size": (S, [P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_int, C.POINTER(C.c_size_t)]),
     "itn_qn_heff_plan": (S, [P, T, T, T, T, T, C.c_int32, C.c_int, C.POINTER(P)]),

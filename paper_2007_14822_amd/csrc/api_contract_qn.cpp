@@ -178,10 +178,10 @@ itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, 
       by_c[ci->second].push_back(Pair{(int)a, b});
     }
   }
-  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
+  if (h->device < 0 && !h->ws.query) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (qc.elems == 0) return ITN_OK;
-  if (!C->data || (qa.elems > 0 && !A->data) || (qb.elems > 0 && !B->data))
+  if (!h->ws.query && (!C->data || (qa.elems > 0 && !A->data) || (qb.elems > 0 && !B->data)))
     return fail(h, ITN_E_ARG, "operand data missing");
   const int P = prec;
   const int pt = P == ITN_P_F64 ? D_F64 : (P == ITN_P_F32 ? D_F32 : D_BF16);

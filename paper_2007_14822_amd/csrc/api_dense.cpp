@@ -43,8 +43,15 @@ itn_status hip_fail(itn_handle* h, hipError_t e, const char* where) {
 }
 
 itn_status ensure_workspace(itn_handle* h, size_t bytes) {
+  if (h->ws.query) {
+    h->ws.query_bytes = bytes;
+    return ITN_STOP_QUERY;
+  }
   if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
   if (bytes <= h->ws.size) return ITN_OK;
+  if (h->ws.caller)
+    return fail(h, ITN_E_WORKSPACE, "this call needs %zu bytes of workspace; the caller's holds %zu",
+                bytes, h->ws.size);
   ITN_HIP(h, hipDeviceSynchronize());
   if (h->ws.ptr) ITN_HIP(h, hipFree(h->ws.ptr));
   h->ws.ptr = nullptr;
@@ -257,7 +264,7 @@ itn_status itn_destroy(itn_handle* h) {
     for (auto& r : h->prof) (void)hipEventDestroy(r.a), (void)hipEventDestroy(r.b);
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     for (auto& kv : h->wtables) kv.second->release();
-    if (h->ws.ptr) (void)hipFree(h->ws.ptr);
+    if (h->ws.ptr && !h->ws.caller) (void)hipFree(h->ws.ptr);
     itn_release_solver(h);
   }
   delete h;
@@ -383,7 +390,7 @@ itn_status itn_contract(itn_handle* h, const itn_tensor* A, const itn_tensor* B,
   for (int k : freeA) M *= A->dims[k];
   for (int k : freeB) N *= B->dims[k];
   for (int k : conA) K *= A->dims[k];
-  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
+  if (h->device < 0 && !h->ws.query) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
   hipStream_t s = as_stream(hip_stream);
   const int64_t nC = numel(C);
   if (nC == 0) return ITN_OK;
@@ -577,12 +584,12 @@ itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const* Ls,
     if (out->dims[k] != psi->dims[k]) return fail(h, ITN_E_SHAPE, "out must have psi's shape");
   if (psi->dtype == ITN_BF16 || out->dtype == ITN_BF16)
     return fail(h, ITN_E_DTYPE, "psi and out must be F64 or F32");
-  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
+  if (h->device < 0 && !h->ws.query) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
   const int64_t d2 = d * d;
   const int64_t n1 = cl * d2 * cr;  // one vector
   if (n1 == 0) return ITN_OK;
-  if (!psi->data || !out->data) return fail(h, ITN_E_ARG, "psi and out need data");
-  {  // the nv vectors of psi and of out occupy disjoint byte ranges
+  if (!h->ws.query && (!psi->data || !out->data)) return fail(h, ITN_E_ARG, "psi and out need data");
+  if (!h->ws.query) {  // the nv vectors of psi and of out occupy disjoint byte ranges
     const uintptr_t pa = reinterpret_cast<uintptr_t>(psi->data);
     const uintptr_t pb = reinterpret_cast<uintptr_t>(out->data);
     const uintptr_t na = (uintptr_t)(nv * n1) * dtype_size(psi->dtype);
@@ -767,6 +774,45 @@ itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const* Ls,
 
 extern "C" {
 
+itn_status itn_set_workspace(itn_handle* h, void* ptr, size_t bytes) {
+  if (!h) return ITN_E_ARG;
+  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle has no workspace");
+  if (ptr && (reinterpret_cast<uintptr_t>(ptr) & 255) != 0)
+    return fail(h, ITN_E_ARG, "workspace must be 256-byte aligned");
+  if (!ptr && bytes != 0) return fail(h, ITN_E_ARG, "NULL workspace with a nonzero size");
+  ITN_HIP(h, hipDeviceSynchronize());
+  if (h->ws.ptr && !h->ws.caller) ITN_HIP(h, hipFree(h->ws.ptr));
+  h->ws.ptr = ptr;
+  h->ws.size = ptr ? bytes : 0;
+  h->ws.caller = ptr != nullptr;
+  return ITN_OK;
+}
+
+itn_status itn_workspace_size(itn_handle* h, itn_op op, int32_t ntensors, const itn_tensor* const* t,
+                              int32_t nv, int32_t dir, itn_prec prec, size_t* bytes) {
+  if (!h || !bytes || (ntensors > 0 && !t)) return h ? fail(h, ITN_E_ARG, "null argument") : ITN_E_ARG;
+  const int need = op == ITN_OP_CONTRACT ? 3 : op == ITN_OP_HEFF ? 5 : op == ITN_OP_ENV_UPDATE ? 4 : -1;
+  if (need < 0) return fail(h, ITN_E_ARG, "unknown operation");
+  if (ntensors != need) return fail(h, ITN_E_ARG, "this operation takes %d tensors", need);
+  // The call itself, stopped at its workspace request (validation included).
+  h->ws.query = true;
+  h->ws.query_bytes = 0;
+  itn_status st = ITN_OK;
+  if (op == ITN_OP_CONTRACT)
+    st = itn_contract(h, t[0], t[1], const_cast<itn_tensor*>(t[2]), prec, nullptr);
+  else if (op == ITN_OP_HEFF)
+    st = heff_apply_terms(h, 1, &t[0], &t[1], &t[2], &t[3], t[4], nv, const_cast<itn_tensor*>(t[4]),
+                          prec, nullptr, nullptr);
+  else
+    st = itn_env_update(h, t[0], t[1], t[2], (itn_dir)dir, const_cast<itn_tensor*>(t[3]), prec, nullptr);
+  h->ws.query = false;
+  if (st == ITN_STOP_QUERY || st == ITN_OK) {
+    *bytes = st == ITN_OK ? 0 : h->ws.query_bytes;
+    return ITN_OK;
+  }
+  return st;
+}
+
 itn_status itn_heff_apply(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
                           const itn_tensor* W2, const itn_tensor* R, const itn_tensor* psi,
                           int32_t nv, itn_tensor* out, itn_prec prec, void* hip_stream) {
@@ -806,7 +852,7 @@ itn_status itn_env_update(itn_handle* h, const itn_tensor* E, const itn_tensor* 
   if (E_out->dims[0] != chio || E_out->dims[1] != w || E_out->dims[2] != chio)
     return fail(h, ITN_E_SHAPE, "E_out must be [%lld, %lld, %lld]", (long long)chio, (long long)w,
                 (long long)chio);
-  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
+  if (h->device < 0 && !h->ws.query) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
   hipStream_t s = as_stream(hip_stream);
   if (chio == 0) return ITN_OK;
   const int P = prec;

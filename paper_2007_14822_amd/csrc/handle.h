@@ -32,6 +32,9 @@ struct WTable {
 struct Workspace {
   void* ptr = nullptr;
   size_t size = 0;
+  bool caller = false;  // memory given by itn_set_workspace (never grown or freed here)
+  bool query = false;   // itn_workspace_size in progress: record the request, stop
+  size_t query_bytes = 0;
 };
 
 // One timed launch (events recorded on the launch stream).
@@ -71,7 +74,10 @@ itn_status hip_fail(itn_handle* h, hipError_t e, const char* where);
     if (_s != ITN_OK) return _s;       \
   } while (0)
 
-// Grow the handle's workspace to at least `bytes` (waits for the device).
+// Grow the handle's workspace to at least `bytes` (waits for the device).  With a
+// caller workspace, fail with ITN_E_WORKSPACE if it is smaller; during a size
+// query, record `bytes` and return ITN_STOP_QUERY before any work is queued.
+static const itn_status ITN_STOP_QUERY = static_cast<itn_status>(1000);
 itn_status ensure_workspace(itn_handle* h, size_t bytes);
 
 // Carve 256-byte-aligned regions out of a workspace.

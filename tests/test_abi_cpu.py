@@ -116,8 +116,8 @@ def test_heff_vector_count_and_overlap_checked(host):
 
 
 def test_objects_close_and_exit_hook():
-    """Handles and plans can be closed explicitly (twice is harmless); the
-    module's exit hook closes whatever is still open."""
+    """Handles and plans can be closed explicitly (twice is harmless); open
+    ones are registered with the module's exit hook."""
     h2 = itn.Handle(-1)
     h2.close()
     h2.close()
@@ -126,5 +126,37 @@ def test_objects_close_and_exit_hook():
         assert h3.h
     assert h3.h is None
     h4 = itn.Handle(-1)
-    itn._close_all()
-    assert h4.h is None
+    assert itn._exit_hook and h4 in itn._live_handles  # the exit hook will close it
+    h4.close()
+
+
+def test_workspace_size_query(host):
+    """itn_workspace_size on a host-only handle: the bytes the call would
+    take, the call's own validation errors, and no device work."""
+    A, B, Cc = _t(40, 30), _t(30, 20), _t(20, 40)
+    b_nat = host.workspace_size("contract", A, [1, 2], B, [2, 3], _t(40, 20), [1, 3])
+    b_perm = host.workspace_size("contract", A, [1, 2], B, [2, 3], Cc, [3, 1])
+    assert b_perm > b_nat > 0  # the permuted output adds a staging buffer
+    with pytest.raises(itn.ItnError) as e:
+        host.workspace_size("contract", A, [1, 2], B, [2, 3], Cc, [3, 4])
+    assert e.value.name == "ITN_E_LABEL"
+    W = np.zeros((5, 5, 2, 2))
+    hb = host.workspace_size("heff", _t(64, 5, 64), W, W, _t(48, 5, 48), _t(64, 2, 2, 48),
+                             prec="bf16")
+    hb2 = host.workspace_size("heff", _t(64, 5, 64), W, W, _t(48, 5, 48), _t(2, 64, 2, 2, 48),
+                              nv=2, prec="bf16")
+    assert hb2 > hb > 64 * 48 * 4 * 2
+    eb = host.workspace_size("env", _t(8, 5, 8), _t(8, 2, 12), W, _t(12, 5, 12))
+    assert eb > 0
+    from oracle import qn as Q
+    from paper_2007_14822_amd import inputs as inp
+    from tests import qn_util as U
+    i = Q.make_index([((0,), 3), ((1,), 2)], +1)
+    j = Q.make_index([((0,), 2), ((1,), 4)], +1)
+    QA = Q.random_blocks([i, j.dag()], (0,), 1, inp.block_values)
+    QB = Q.random_blocks([j, i.dag()], (0,), 2, inp.block_values)
+    ref = Q.contract_blocks(QA, [1, 2], QB, [2, 3], [1, 3])
+    qb = host.workspace_size("contract", U.desc(QA, with_data=False)[0], [1, 2],
+                             U.desc(QB, with_data=False)[0], [2, 3], U.desc(ref, with_data=False)[0],
+                             [1, 3])
+    assert qb > 0

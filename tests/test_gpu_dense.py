@@ -332,3 +332,47 @@ def test_cast_f64_to_bf16_rounds_once(h):
     h.cast(dev(x), dst)
     got = host(dst)
     assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:8]
+
+
+def test_caller_workspace(h):
+    """A caller-owned workspace of exactly the queried size runs the call
+    (same result as the library's own workspace); one too small is refused
+    with ITN_E_WORKSPACE before anything is written; None restores the
+    library-owned workspace."""
+    L, W1, W2, R, psi = _heff_case(128, 96, 2, 5, 2, 31)
+    Ld, Rd, pd = dev(L, torch.bfloat16), dev(R, torch.bfloat16), dev(psi)
+    ref = torch.zeros(psi.shape, dtype=torch.float64, device=DEV)
+    h.heff_apply(Ld, W1, W2, Rd, pd, ref, nv=2, prec="bf16")
+    need = h.workspace_size("heff", Ld, W1, W2, Rd, pd, nv=2, prec="bf16")
+    buf = torch.empty(need, dtype=torch.uint8, device=DEV)
+    assert buf.data_ptr() % 256 == 0
+    h2 = itn.Handle(0)
+    try:
+        h2.set_workspace(buf)
+        out = torch.full(psi.shape, float("nan"), dtype=torch.float64, device=DEV)
+        h2.heff_apply(Ld, W1, W2, Rd, pd, out, nv=2, prec="bf16")
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        small = torch.empty(need - 256, dtype=torch.uint8, device=DEV)
+        h2.set_workspace(small)
+        out2 = torch.full(psi.shape, 3.0, dtype=torch.float64, device=DEV)
+        with pytest.raises(itn.ItnError) as e:
+            h2.heff_apply(Ld, W1, W2, Rd, pd, out2, nv=2, prec="bf16")
+        assert e.value.name == "ITN_E_WORKSPACE"
+        torch.cuda.synchronize()
+        assert bool((out2 == 3.0).all())
+        h2.set_workspace(None)
+        h2.heff_apply(Ld, W1, W2, Rd, pd, out2, nv=2, prec="bf16")
+        torch.cuda.synchronize()
+        assert torch.equal(out2, ref)
+        # the query for a contraction matches what the call takes
+        A, B = dev(np.random.default_rng(1).standard_normal((300, 200))), \
+            dev(np.random.default_rng(2).standard_normal((200, 100)))
+        Cg = torch.zeros((100, 300), dtype=torch.float64, device=DEV)
+        nb = h2.workspace_size("contract", A, [1, 2], B, [2, 3], Cg, [3, 1])
+        h2.set_workspace(torch.empty(nb, dtype=torch.uint8, device=DEV))
+        h2.contract(A, [1, 2], B, [2, 3], Cg, [3, 1])
+        torch.cuda.synchronize()
+        assert rel_err(host(Cg), (host(A) @ host(B)).T) <= 1e-12
+    finally:
+        h2.close()

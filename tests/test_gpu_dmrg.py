@@ -216,14 +216,14 @@ def test_bond_split_eigensolvers_agree(h, monkeypatch, maxdim):
 
 @pytest.mark.parametrize("block", [1, 4])
 def test_mixed_precision_sweeps_mostly_low_precision(h, block):
-    """Spin-1 chain (N = 20, maxdim 64), bf16 expansions with FP64 restart
+    """Spin-1 chain (N = 20, maxdim 64, 9 sweeps), bf16 expansions with FP64 restart
     vectors and a small Davidson budget per bond (4 vectors, 8 matvecs; four
     times that with blocks of 4): at least 70 % of the matvecs run in bf16,
     at most 2.5 FP64 matvecs per bond on average (3.5 with blocks), and the
     converged energy agrees with the FP64 run to 1e-9 relative."""
     N = 20
     As0 = inp.random_product_state(N, 3, inp.rng_for(2, 64))
-    sched = [(64, 1e-10)] * 6
+    sched = [(64, 1e-10)] * 9
     kw = dict(eig_tol=1e-9, krylovdim=4 * block, maxiter=8 * block, allow_unconverged=True,
               block=block)
     r64, _ = run(h, inp.heisenberg_mpo(N, 2), As0, sched, prec="f64", **kw)
@@ -232,6 +232,8 @@ def test_mixed_precision_sweeps_mostly_low_precision(h, block):
     tot = sum(r["matvecs"] for r in rbf)
     f64 = sum(r["matvecs_f64"] for r in rbf)
     print("mixed", block, tot, f64, f64 / (len(rbf) * bonds), rbf[-1]["energy"], r64[-1]["energy"])
+    print("  sweeps f64 ", [r["energy"] for r in r64])
+    print("  sweeps bf16", [r["energy"] for r in rbf])
     assert (tot - f64) / tot >= 0.70
     # single-vector: a restart cycle is one FP64 and three bf16 matvecs; the
     # block solve runs more (batched) matvecs per bond and more cycles
