@@ -409,6 +409,40 @@ typedef struct {
 itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
                           const itn_sweep_params* params, itn_sweep_result* result);
 
+/* ------------------------------------------------- block-sparse DMRG sweeps */
+
+/* A block-sparse MPS (Sec. 8, 9.2): every site tensor A[a:Out, s:Out, a':In]
+ * holds only its flux-allowed blocks; the link charge is the total QN of the
+ * sites to its left, so the state has the definite total QN of its last link.
+ * Created as the product state state[i] (basis index per site; Neel states
+ * fix the sector).  site_qn[d*nq] gives the QN of each basis state (runs of
+ * equal QN form one sector), mod[nq] the addition rules (NULL: integer). */
+typedef struct itn_qn_mps itn_qn_mps;
+itn_status itn_qn_mps_create(itn_handle* h, int32_t N, int32_t d, int32_t nq, const int32_t* site_qn,
+                             const int32_t* mod, const int32_t* state, itn_qn_mps** mps);
+itn_status itn_qn_mps_destroy(itn_qn_mps* mps);
+/* Total link dimensions (N+1 entries). */
+itn_status itn_qn_mps_bonds(const itn_qn_mps* mps, int32_t* bond);
+/* Link k's sectors: on entry *nsec is the capacity of qn[*nsec*nq] and
+ * dim[*nsec] (NULL arrays: query only); on return the number of sectors. */
+itn_status itn_qn_mps_link(const itn_qn_mps* mps, int32_t k, int32_t* nsec, int32_t* qn, int32_t* dim);
+/* Site i as a dense host array [bond[i], d, bond[i+1]] (blocks embedded at
+ * their sector offsets, zero elsewhere). */
+itn_status itn_qn_mps_get_site(itn_handle* h, const itn_qn_mps* mps, int32_t i, double* host);
+
+/* Two-site DMRG sweeps on a block-sparse MPS (Sec. 7.2 with Sec. 8):
+ * link_qn[w*nq] gives the QN each MPO channel carries (W[m_in:Out, m_out:In,
+ * s':Out, s:In] with zero flux; a nonzero MPO entry outside the allowed
+ * blocks is ITN_E_FLUX).  At each bond the local problem is the planned
+ * block-sparse H_eff (itn_qn_heff_plan), the eigensolver that of
+ * itn_dmrg_sweep (precision and refinement as there; block must be <= 1,
+ * no excited states), and the bond is split per charge sector of the new
+ * link: each sector's density matrix is diagonalised and the truncation of
+ * Sec. 5 is applied to the weights of all sectors together; environments are
+ * block-sparse contractions.  The total QN is conserved exactly. */
+itn_status itn_qn_dmrg_sweep(itn_handle* h, itn_qn_mps* mps, const itn_mpo* mpo, const int32_t* link_qn,
+                             const itn_sweep_params* params, itn_sweep_result* result);
+
 #ifdef __cplusplus
 }
 #endif

@@ -140,11 +140,10 @@ class Handle:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
-        if sys.is_finalizing():
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
         try:
-            self.close()
+            if not _finalizing():
+                self.close()
         except Exception:
             pass
 
@@ -390,14 +389,8 @@ class Handle:
             out.append(a)
         return out
 
-    def dmrg_sweep(self, mps, mpo, sweeps, prec="f64", mindim=1, krylovdim=8, maxiter=100,
-                   eig_tol=1e-10, refine=True, energy_tol=0.0, allow_unconverged=False,
-                   timing=False, ortho=(), weight=0.0, block=1):
-        """Run a schedule [(maxdim, cutoff), ...]; returns per-sweep records
-        (with per-phase seconds t_matvec/t_solver/t_split/t_env if timing).
-        ortho: previously found MPS whose projectors, times `weight`, are
-        added to H (excited states).  block: Davidson vectors per batched
-        matvec."""
+    def _sweep_call(self, fn, sweeps, prec, mindim, krylovdim, maxiter, eig_tol, refine, energy_tol,
+                    allow_unconverged, timing, ortho, weight, block):
         ns = len(sweeps)
         md = (C.c_int32 * max(1, ns))(*[int(m) for m, _ in sweeps])
         co = (C.c_double * max(1, ns))(*[float(c) for _, c in sweeps])
@@ -421,10 +414,72 @@ class Handle:
         if timing:
             res.t_matvec, res.t_solver, res.t_split, res.t_env = (arrs[k] for k in
                                                                    ("t_matvec", "t_solver", "t_split", "t_env"))
-        st = self.lib.itn_dmrg_sweep(self.h, mps.ptr, mpo.ptr, C.byref(prm), C.byref(res))
+        st = fn(C.byref(prm), C.byref(res))
         if not (allow_unconverged and st == 9):
             self._check(st)
         return [{k: arrs[k][i] for k in arrs} for i in range(res.sweeps_done)]
+
+    def dmrg_sweep(self, mps, mpo, sweeps, prec="f64", mindim=1, krylovdim=8, maxiter=100,
+                   eig_tol=1e-10, refine=True, energy_tol=0.0, allow_unconverged=False,
+                   timing=False, ortho=(), weight=0.0, block=1):
+        """Run a schedule [(maxdim, cutoff), ...]; returns per-sweep records
+        (with per-phase seconds t_matvec/t_solver/t_split/t_env if timing).
+        ortho: previously found MPS whose projectors, times `weight`, are
+        added to H (excited states).  block: Davidson vectors per batched
+        matvec."""
+        return self._sweep_call(
+            lambda prm, res: self.lib.itn_dmrg_sweep(self.h, mps.ptr, mpo.ptr, prm, res), sweeps, prec,
+            mindim, krylovdim, maxiter, eig_tol, refine, energy_tol, allow_unconverged, timing, ortho,
+            weight, block)
+
+    # ------------------------------------------------- block-sparse sweeps
+    def qn_mps(self, site_qn, state, mod=None):
+        """Block-sparse MPS, the product state `state` (basis index per site);
+        site_qn: QN tuple of each basis state."""
+        sq = [tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,))) for q in site_qn]
+        d, nq, N = len(sq), len(sq[0]), len(state)
+        qarr = (C.c_int32 * (d * nq))(*[x for q in sq for x in q])
+        marr = (C.c_int32 * nq)(*[int(m) for m in mod]) if mod else None
+        st = (C.c_int32 * N)(*[int(s) for s in state])
+        out = C.c_void_p()
+        self._check(self.lib.itn_qn_mps_create(self.h, N, d, nq, qarr, marr, st, C.byref(out)))
+        return _Owned(self, self.lib.itn_qn_mps_destroy, out, N=N, d=d, nq=nq)
+
+    def qn_mps_bonds(self, mps):
+        b = (C.c_int32 * (mps.N + 1))()
+        self._check(self.lib.itn_qn_mps_bonds(mps.ptr, b))
+        return list(b)
+
+    def qn_mps_link(self, mps, k):
+        """[(QN tuple, dim)] of link k."""
+        n = C.c_int32(0)
+        self._check(self.lib.itn_qn_mps_link(mps.ptr, int(k), C.byref(n), None, None))
+        q = (C.c_int32 * max(1, n.value * mps.nq))()
+        dm = (C.c_int32 * max(1, n.value))()
+        self._check(self.lib.itn_qn_mps_link(mps.ptr, int(k), C.byref(n), q, dm))
+        return [(tuple(q[s * mps.nq:(s + 1) * mps.nq]), dm[s]) for s in range(n.value)]
+
+    def qn_mps_sites(self, mps):
+        bond = self.qn_mps_bonds(mps)
+        out = []
+        for i in range(mps.N):
+            a = np.zeros((bond[i], mps.d, bond[i + 1]))
+            self._check(self.lib.itn_qn_mps_get_site(self.h, mps.ptr, i,
+                                                     a.ctypes.data_as(C.POINTER(C.c_double))))
+            out.append(a)
+        return out
+
+    def qn_dmrg_sweep(self, mps, mpo, link_qn, sweeps, prec="f64", mindim=1, krylovdim=8,
+                      maxiter=100, eig_tol=1e-10, refine=True, energy_tol=0.0,
+                      allow_unconverged=False, timing=False):
+        """Two-site sweeps on a block-sparse MPS; link_qn: QN tuple of each MPO
+        channel."""
+        lq = [tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,))) for q in link_qn]
+        larr = (C.c_int32 * (len(lq) * len(lq[0])))(*[x for q in lq for x in q])
+        return self._sweep_call(
+            lambda prm, res: self.lib.itn_qn_dmrg_sweep(self.h, mps.ptr, mpo.ptr, larr, prm, res), sweeps,
+            prec, mindim, krylovdim, maxiter, eig_tol, refine, energy_tol, allow_unconverged, timing, (),
+            0.0, 1)
 
 
 def _qn(keep: _Keep, desc) -> L.itn_tensor:
@@ -578,11 +633,10 @@ class Plan:
             self.lib.itn_plan_destroy(self.ptr)
             self.ptr = None
 
-    def __del__(self):
-        if sys.is_finalizing():
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
         try:
-            self.close()
+            if not _finalizing():
+                self.close()
         except Exception:
             pass
 
@@ -608,10 +662,9 @@ class _Owned:
             self._destroy(self.ptr)
             self.ptr = None
 
-    def __del__(self):
-        if sys.is_finalizing():
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
         try:
-            self.close()
+            if not _finalizing():
+                self.close()
         except Exception:
             pass

@@ -103,6 +103,15 @@ SIGNATURES = {
     "itn_mps_bonds": (S, [P, C.POINTER(C.c_int32)]),
     "itn_mps_get_site": (S, [P, P, C.c_int32, C.POINTER(C.c_double)]),
     "itn_dmrg_sweep": (S, [P, P, P, C.POINTER(itn_sweep_params), C.POINTER(itn_sweep_result)]),
+    "itn_qn_mps_create": (S, [P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(P)]),
+    "itn_qn_mps_destroy": (S, [P]),
+    "itn_qn_mps_bonds": (S, [P, C.POINTER(C.c_int32)]),
+    "itn_qn_mps_link": (S, [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                            C.POINTER(C.c_int32)]),
+    "itn_qn_mps_get_site": (S, [P, P, C.c_int32, C.POINTER(C.c_double)]),
+    "itn_qn_dmrg_sweep": (S, [P, P, P, C.POINTER(C.c_int32), C.POINTER(itn_sweep_params),
+                              C.POINTER(itn_sweep_result)]),
 }
 
 _lib = None

@@ -12,75 +12,11 @@
 #include <functional>
 
 #include "common.h"
+#include "dmrg_common.h"
 #include "handle.h"
 
 using namespace itn;
 
-struct itn_mpo {
-  int32_t N = 0, w = 0, d = 0;
-  std::vector<double> W;  // host, N * w*w*d*d
-  const double* site(int i) const { return W.data() + (size_t)i * w * w * d * d; }
-};
-
-namespace {
-
-// Device buffer that only grows.
-struct DBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  itn_status ensure(itn_handle* h, size_t b) {
-    if (b <= bytes) return ITN_OK;
-    if (p) {
-      ITN_HIP(h, hipDeviceSynchronize());
-      ITN_HIP(h, hipFree(p));
-    }
-    p = nullptr;
-    bytes = 0;
-    if (hipMalloc(&p, b) != hipSuccess) {
-      p = nullptr;
-      return fail(h, ITN_E_WORKSPACE, "allocation of %zu bytes failed", b);
-    }
-    bytes = b;
-    return ITN_OK;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  double* d() const { return static_cast<double*>(p); }
-};
-
-// Pinned host staging for the small device-to-host reads of the sweep
-// (Davidson reductions, eigenvalues of the bond split): a read into pinned
-// memory completes without the staging copy of a pageable destination.
-struct HostPin {
-  void* p = nullptr;
-  size_t bytes = 0;
-  itn_status ensure(itn_handle* h, size_t b) {
-    if (b <= bytes) return ITN_OK;
-    if (p) {
-      ITN_HIP(h, hipDeviceSynchronize());
-      ITN_HIP(h, hipHostFree(p));
-    }
-    p = nullptr;
-    bytes = 0;
-    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
-      p = nullptr;
-      return fail(h, ITN_E_WORKSPACE, "pinned allocation of %zu bytes failed", b);
-    }
-    bytes = b;
-    return ITN_OK;
-  }
-  void release() {
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  double* d() const { return static_cast<double*>(p); }
-};
-
-}  // namespace
 
 struct itn_mps {
   int32_t N = 0, d = 0;
@@ -94,11 +30,11 @@ struct itn_mps {
   // OL[j][k] = <psi|phi_j> over sites [0, k), OR[j][k] over [k, N)
   std::vector<std::vector<DBuf>> OL, OR;
   // driver scratch
-  DBuf psi, tmp, rho, evec, eval, einfo, V, AV, Lp, Rp, partial, dots, ev_host_stage;
+  SolverBufs sb;  // eigensolver scratch
+  DBuf psi, tmp, rho, evec, eval, einfo, Lp, Rp, ev_host_stage;
   DBuf ovec, ot1, ot2, ot3, odots;
   DBuf hh, hscr;  // bond split: Householder reflectors [n][n]; tridiagonal and barrier scratch
   DBuf hdiag, wdiag;  // block Davidson: diagonal of H_eff, and its W1 W2 factor
-  HostPin pin;    // pinned host staging for small reads
   ~itn_mps() {
     for (auto& b : site) b.release();
     for (auto& b : Lenv) b.release();
@@ -106,10 +42,10 @@ struct itn_mps {
     for (auto* v : {&OL, &OR})
       for (auto& row : *v)
         for (auto& b : row) b.release();
-    for (DBuf* b : {&psi, &tmp, &rho, &evec, &eval, &einfo, &V, &AV, &Lp, &Rp, &partial, &dots,
-                    &ev_host_stage, &ovec, &ot1, &ot2, &ot3, &odots, &hh, &hscr, &hdiag, &wdiag})
+    for (DBuf* b : {&psi, &tmp, &rho, &evec, &eval, &einfo, &Lp, &Rp, &ev_host_stage, &ovec, &ot1,
+                    &ot2, &ot3, &odots, &hh, &hscr, &hdiag, &wdiag})
       b->release();
-    pin.release();
+    sb.release();
   }
 };
 
@@ -120,7 +56,7 @@ extern "C" void itn_release_solver(itn_handle* h) {
   }
 }
 
-namespace {
+namespace itn {
 
 // ------------------------------------------------------------ small eigh
 // Cyclic Jacobi for a symmetric k x k matrix (row-major); eigenvalues
@@ -173,6 +109,29 @@ void jacobi_eigh(int k, std::vector<double> A, std::vector<double>& w, std::vect
   V.swap(V2);
 }
 
+// Keep count per Sec. 5: discard the smallest weights while their running sum
+// stays within the cutoff, cap at maxdim, keep at least mindim (and one).
+int truncation_keep(const std::vector<double>& p_desc, double cutoff, int maxdim, int mindim,
+                    double* discarded) {
+  const int n = (int)p_desc.size();
+  int keep = n;
+  double disc = 0.0;
+  while (keep > 1 && disc + p_desc[keep - 1] <= cutoff) {
+    disc += p_desc[keep - 1];
+    --keep;
+  }
+  keep = std::min(keep, maxdim);
+  keep = std::max(keep, std::min(std::max(mindim, 1), n));
+  double d = 0.0;
+  for (int j = keep; j < n; ++j) d += p_desc[j];
+  *discarded = d;
+  return keep;
+}
+
+}  // namespace itn
+
+namespace {
+
 itn_tensor dense_t(int rank, const int64_t* dims, itn_dtype dt, void* data) {
   itn_tensor t{};
   t.rank = rank;
@@ -213,48 +172,18 @@ hipError_t transpose64(const double* in, double* out, int64_t rows, int64_t cols
   return transpose_cast(D_F64, in, D_F64, out, t, s);
 }
 
-struct Ctx {
-  itn_handle* h;
-  itn_mps* m;
-  const itn_mpo* mpo;
-  const itn_sweep_params* p;
-  hipStream_t s = nullptr;
-  int64_t matvecs = 0;      // H_eff applications (vectors), all precisions
-  int64_t matvecs64 = 0;    // of which in FP64
-  double max_resid = 0.0;
-  bool unconverged = false;
-  // per-phase seconds of the current sweep (params->timing only)
-  double t_mv = 0.0, t_solve = 0.0, t_split = 0.0, t_env = 0.0;
+struct Ctx : SolveCtx {
+  itn_mps* m = nullptr;
+  const itn_mpo* mpo = nullptr;
   // excited states: projected previous states at the current bond
   int northo = 0;
   const double* pen_v = nullptr;  // northo vectors of the bond's length
-};
-
-// Adds the wall time of a scope to *acc when timing is on; the stream is
-// drained at both ends so that the time belongs to the phase.
-struct PhaseTimer {
-  Ctx& c;
-  double* acc;
-  std::chrono::steady_clock::time_point t0;
-  PhaseTimer(Ctx& ctx, double* a) : c(ctx), acc(a) {
-    if (c.p->timing) {
-      (void)hipStreamSynchronize(c.s);
-      t0 = std::chrono::steady_clock::now();
-    }
-  }
-  ~PhaseTimer() {
-    if (c.p->timing) {
-      (void)hipStreamSynchronize(c.s);
-      *acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
-  }
 };
 
 // y = H_eff x for nv vectors stored one after another (FP64), at precision
 // `prec`, through the public entry point: one launch sequence for all nv.
 itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl, int64_t cr,
                 int nv = 1) {
-  PhaseTimer pt(c, &c.t_mv);
   const int w = c.mpo->w, d = c.mpo->d;
   const int64_t dl[3] = {cl, w, cl}, dr[3] = {cr, w, cr}, dw[4] = {w, w, d, d};
   const int64_t dp[4] = {cl, d, d, cr};
@@ -266,15 +195,13 @@ itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl,
   itn_tensor W2 = dense_t(4, dw, ITN_F64, const_cast<double*>(c.mpo->site(i + 1)));
   itn_tensor P = dense_t(4, dp, ITN_F64, const_cast<double*>(x));
   itn_tensor O = dense_t(4, dp, ITN_F64, y);
-  c.matvecs += nv;
-  if (!low) c.matvecs64 += nv;
   ITN_TRY(itn_heff_apply(c.h, &L, &W1, &W2, &R, &P, nv, &O, (itn_prec)prec, c.s));
   if (c.northo > 0) {  // + weight * sum_j |v_j><v_j| x  (Sec. 7.2 energy penalty)
     const int64_t n = cl * d * d * cr;
-    ITN_TRY(c.m->partial.ensure(c.h, (size_t)c.northo * dot_blocks(n) * 8));
+    ITN_TRY(c.sb->partial.ensure(c.h, (size_t)c.northo * dot_blocks(n) * 8));
     ITN_TRY(c.m->odots.ensure(c.h, (size_t)c.northo * 8 + 8));
     for (int v = 0; v < nv; ++v) {
-      ITN_HIP(c.h, multi_dot(c.pen_v, n, c.northo, x + (size_t)v * n, n, c.m->partial.d(),
+      ITN_HIP(c.h, multi_dot(c.pen_v, n, c.northo, x + (size_t)v * n, n, c.sb->partial.d(),
                              c.m->odots.d(), c.s));
       ITN_HIP(c.h, lincomb_dev(c.pen_v, n, c.northo, c.m->odots.d(), c.p->weight, y + (size_t)v * n,
                                n, c.s));
@@ -283,31 +210,23 @@ itn_status heff(Ctx& c, int i, int prec, const double* x, double* y, int64_t cl,
   return ITN_OK;
 }
 
-// <V_j, w> for j < k, to host.
-itn_status dots(Ctx& c, const double* V, int64_t n, int k, const double* w, double* out) {
-  ITN_TRY(c.m->partial.ensure(c.h, (size_t)k * dot_blocks(n) * 8));
-  ITN_TRY(c.m->dots.ensure(c.h, (size_t)k * 8 + 8));
-  ITN_TRY(c.m->pin.ensure(c.h, (size_t)k * 8 + 8));
-  ITN_HIP(c.h, multi_dot(V, n, k, w, n, c.m->partial.d(), c.m->dots.d(), c.s));
-  ITN_HIP(c.h, hipMemcpyAsync(c.m->pin.p, c.m->dots.p, (size_t)k * 8, hipMemcpyDeviceToHost, c.s));
-  ITN_HIP(c.h, hipStreamSynchronize(c.s));
-  std::memcpy(out, c.m->pin.p, (size_t)k * 8);
-  return ITN_OK;
-}
+}  // namespace
+
+namespace itn {
 
 // Dot products of groups of vectors, read back with one host round trip:
 // each add(V, k, w) queues <V_a, w> for a < k (V_a at stride n) into the
 // next k slots of the result.
 struct DotBatch {
-  Ctx& c;
+  SolveCtx& c;
   int64_t n;
   int total = 0;
   std::vector<std::pair<int, int>> spans;  // (offset, count) per add
-  DotBatch(Ctx& ctx, int64_t len) : c(ctx), n(len) {}
+  DotBatch(SolveCtx& ctx, int64_t len) : c(ctx), n(len) {}
   itn_status add(const double* V, int k, const double* w, int* off) {
-    ITN_TRY(c.m->partial.ensure(c.h, (size_t)std::max(k, 1) * dot_blocks(n) * 8));
-    ITN_TRY(c.m->dots.ensure(c.h, (size_t)(total + k) * 8 + 8));
-    ITN_HIP(c.h, multi_dot(V, n, k, w, n, c.m->partial.d(), c.m->dots.d() + total, c.s));
+    ITN_TRY(c.sb->partial.ensure(c.h, (size_t)std::max(k, 1) * dot_blocks(n) * 8));
+    ITN_TRY(c.sb->dots.ensure(c.h, (size_t)(total + k) * 8 + 8));
+    ITN_HIP(c.h, multi_dot(V, n, k, w, n, c.sb->partial.d(), c.sb->dots.d() + total, c.s));
     *off = total;
     total += k;
     return ITN_OK;
@@ -315,10 +234,10 @@ struct DotBatch {
   itn_status read(std::vector<double>& out) {
     out.assign(std::max(total, 1), 0.0);
     if (total == 0) return ITN_OK;
-    ITN_TRY(c.m->pin.ensure(c.h, (size_t)total * 8 + 8));
-    ITN_HIP(c.h, hipMemcpyAsync(c.m->pin.p, c.m->dots.p, (size_t)total * 8, hipMemcpyDeviceToHost, c.s));
+    ITN_TRY(c.sb->pin.ensure(c.h, (size_t)total * 8 + 8));
+    ITN_HIP(c.h, hipMemcpyAsync(c.sb->pin.p, c.sb->dots.p, (size_t)total * 8, hipMemcpyDeviceToHost, c.s));
     ITN_HIP(c.h, hipStreamSynchronize(c.s));
-    std::memcpy(out.data(), c.m->pin.p, (size_t)total * 8);
+    std::memcpy(out.data(), c.sb->pin.p, (size_t)total * 8);
     return ITN_OK;
   }
 };
@@ -357,9 +276,16 @@ struct DotBatch {
 // *converged is false only when maxiter matvecs ended above the tolerance;
 // a residual with no new direction left (the basis spans the invariant
 // subspace up to rounding) counts as converged.
-itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* psi, int64_t n,
-                    int64_t cl, int64_t cr, const double* diag, bool exact_final, double* energy,
-                    double* resid, bool* converged) {
+itn_status davidson(SolveCtx& c, const Matvec& mv, int prec, double tol, int maxiter, double* psi,
+                    int64_t n, const double* diag, bool exact_final, double* energy, double* resid,
+                    bool* converged) {
+  // every H_eff application of the solve: counted, and timed as the matvec phase
+  auto heff = [&](int p, const double* x, double* y, int nv) -> itn_status {
+    PhaseTimer pt(c, &c.t_mv);
+    c.matvecs += nv;
+    if (p == ITN_P_F64) c.matvecs64 += nv;
+    return mv(p, x, y, nv);
+  };
   const bool mixed = prec != ITN_P_F64 && c.p->refine;
   const int B = diag ? std::max(1, std::min(c.p->block > 0 ? c.p->block : 1, 8)) : 1;
   const int keep_base = mixed ? 1 : 3;  // Ritz vectors kept at a restart
@@ -369,10 +295,10 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
   // staging [kmax + B, kmax + 2B), restart staging, one spare
   const int s_orth = kmax + B, s_rest = kmax + 2 * B, s_spare = s_rest + std::max(keep_base, B);
   const int cap = s_spare + 1;
-  ITN_TRY(c.m->V.ensure(c.h, (size_t)cap * n * 8));
-  ITN_TRY(c.m->AV.ensure(c.h, (size_t)cap * n * 8));
-  double* V = c.m->V.d();
-  double* AV = c.m->AV.d();
+  ITN_TRY(c.sb->V.ensure(c.h, (size_t)cap * n * 8));
+  ITN_TRY(c.sb->AV.ensure(c.h, (size_t)cap * n * 8));
+  double* V = c.sb->V.d();
+  double* AV = c.sb->AV.d();
   auto Vs = [&](int a) { return V + (size_t)a * n; };
   auto AVs = [&](int a) { return AV + (size_t)a * n; };
   std::vector<double> Hk((size_t)kmax * kmax, 0.0), got;
@@ -385,10 +311,10 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
     ITN_TRY(db.read(got));
   }
   const double nrm2 = got[0];
-  if (!(nrm2 > 0)) return fail(c.h, ITN_E_ARG, "zero start vector at bond %d", i);
+  if (!(nrm2 > 0)) return fail(c.h, ITN_E_ARG, "zero start vector");
   ITN_HIP(c.h, hipMemcpyAsync(V, psi, n * 8, hipMemcpyDeviceToDevice, c.s));
   ITN_HIP(c.h, scale(V, 1.0 / std::sqrt(nrm2), n, c.s));
-  ITN_TRY(heff(c, i, mixed ? ITN_P_F64 : prec, V, AV, cl, cr));
+  ITN_TRY(heff(mixed ? ITN_P_F64 : prec, V, AV, 1));
   ++used;
   {
     DotBatch db(c, n);
@@ -399,7 +325,7 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
   }
   int k = 1;
   double theta = H(0, 0), rn = 0.0;
-  bool conv = false;
+  bool conv = false, force_restart = false;
   std::vector<double> w, Y, y0(1, 1.0);
   // Orthonormalise the nin vectors in slots [k, k + nin) against the basis
   // and each other, from their projections P(j, a) = <V_a, t_j> (a < k) and
@@ -496,7 +422,8 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
       break;
     }
     if (used >= maxiter) break;
-    if (k + nb > kmax) {
+    if (k + nb > kmax || force_restart) {
+      force_restart = false;
       // restart from the m lowest Ritz vectors (staged, then moved to the front)
       const int m = std::min(k, std::max(keep_base, nb));
       for (int j = 0; j < m; ++j) {
@@ -511,7 +438,7 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
       for (int j = 0; j < m; ++j) H(j, j) = w[j];
       k = m;
       if (mixed) {  // the new cycle's first vector applied in FP64: exact row and column 0
-        ITN_TRY(heff(c, i, ITN_P_F64, V, AV, cl, cr));
+        ITN_TRY(heff(ITN_P_F64, V, AV, 1));
         ++used;
         DotBatch db(c, n);
         int o;
@@ -560,12 +487,20 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
         ITN_TRY(cholqr(na1, [&](int j, int a) { return G2[o2[j] + a]; }, 1e-10, ones, &na));
       }
     }
-    if (na == 0) {  // the basis holds the invariant subspace up to rounding
+    if (na == 0) {
+      // the basis holds the invariant subspace up to rounding.  In mixed
+      // precision the residual above was formed with low-precision products:
+      // restart from the Ritz vector (its FP64 product makes the next
+      // residual exact) unless the basis is that single vector already.
+      if (mixed && k > 1) {
+        force_restart = true;
+        continue;
+      }
       conv = true;
       break;
     }
     // one batched matvec for the accepted vectors
-    ITN_TRY(heff(c, i, prec, Vs(k), AVs(k), cl, cr, na));
+    ITN_TRY(heff(prec, Vs(k), AVs(k), na));
     used += na;
     // new columns of the projected matrix; in mixed mode row 0 from the exact AV_0
     {
@@ -590,7 +525,7 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
   if (mixed && exact_final) {
     // FP64 Rayleigh quotient and residual of the result
     double* ax = AVs(s_spare);
-    ITN_TRY(heff(c, i, ITN_P_F64, psi, ax, cl, cr));
+    ITN_TRY(heff(ITN_P_F64, psi, ax, 1));
     DotBatch db(c, n);
     int o1, o2;
     ITN_TRY(db.add(psi, 1, ax, &o1));
@@ -614,6 +549,10 @@ itn_status davidson(Ctx& c, int i, int prec, double tol, int maxiter, double* ps
   return ITN_OK;
 }
 
+}  // namespace itn
+
+namespace {
+
 rocblas_handle solver(Ctx& c) {
   if (!c.h->solver) {
     rocblas_handle r = nullptr;
@@ -623,25 +562,6 @@ rocblas_handle solver(Ctx& c) {
   rocblas_handle r = static_cast<rocblas_handle>(c.h->solver);
   rocblas_set_stream(r, c.s);
   return r;
-}
-
-// Keep count per Sec. 5: discard the smallest weights while their running sum
-// stays within the cutoff, cap at maxdim, keep at least mindim (and one).
-int truncation_keep(const std::vector<double>& p_desc, double cutoff, int maxdim, int mindim,
-                    double* discarded) {
-  const int n = (int)p_desc.size();
-  int keep = n;
-  double disc = 0.0;
-  while (keep > 1 && disc + p_desc[keep - 1] <= cutoff) {
-    disc += p_desc[keep - 1];
-    --keep;
-  }
-  keep = std::min(keep, maxdim);
-  keep = std::max(keep, std::min(std::max(mindim, 1), n));
-  double d = 0.0;
-  for (int j = keep; j < n; ++j) d += p_desc[j];
-  *discarded = d;
-  return keep;
 }
 
 // ITN_EIG=library selects rocSOLVER's full symmetric eigensolver for every
@@ -715,8 +635,8 @@ itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdi
                                          (rocblas_int)n, static_cast<rocblas_int*>(m->einfo.p));
     if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dstedc failed (%d)", (int)st);
     int err = 0;
-    ITN_TRY(m->pin.ensure(c.h, (size_t)(n + 2) * 8));
-    char* pin = static_cast<char*>(m->pin.p);
+    ITN_TRY(m->sb.pin.ensure(c.h, (size_t)(n + 2) * 8));
+    char* pin = static_cast<char*>(m->sb.pin.p);
     ITN_HIP(c.h, hipMemcpyAsync(pin, D, n * 8, hipMemcpyDeviceToHost, c.s));
     ITN_HIP(c.h, hipMemcpyAsync(pin + n * 8, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
     ITN_HIP(c.h, hipMemcpyAsync(pin + (n + 1) * 8, coop_err, sizeof(err), hipMemcpyDeviceToHost, c.s));
@@ -735,8 +655,8 @@ itn_status split(Ctx& c, int i, bool to_right, int64_t cl, int64_t cr, int maxdi
                                          rho, (rocblas_int)n, D, E,
                                          static_cast<rocblas_int*>(m->einfo.p));
     if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd failed (%d)", (int)st);
-    ITN_TRY(m->pin.ensure(c.h, (size_t)(n + 2) * 8));
-    char* pin = static_cast<char*>(m->pin.p);
+    ITN_TRY(m->sb.pin.ensure(c.h, (size_t)(n + 2) * 8));
+    char* pin = static_cast<char*>(m->sb.pin.p);
     ITN_HIP(c.h, hipMemcpyAsync(pin, D, n * 8, hipMemcpyDeviceToHost, c.s));
     ITN_HIP(c.h, hipMemcpyAsync(pin + n * 8, m->einfo.p, sizeof(info), hipMemcpyDeviceToHost, c.s));
     ITN_HIP(c.h, hipStreamSynchronize(c.s));
@@ -931,7 +851,10 @@ itn_status bond_step(Ctx& c, int i, bool to_right, int maxdim, double cutoff, bo
   }
   {
     PhaseTimer pt(c, &c.t_solve);
-    ITN_TRY(davidson(c, i, prec, tol, maxiter, m->psi.d(), n, cl, cr, diag, last, &e, &r, &conv));
+    const Matvec mv = [&](int p, const double* x, double* y, int nv) {
+      return heff(c, i, p, x, y, cl, cr, nv);
+    };
+    ITN_TRY(davidson(c, mv, prec, tol, maxiter, m->psi.d(), n, diag, last, &e, &r, &conv));
   }
   c.max_resid = std::max(c.max_resid, r);
   if (!conv && (prec == ITN_P_F64 || c.p->refine)) c.unconverged = true;
@@ -1052,6 +975,7 @@ itn_status itn_dmrg_sweep(itn_handle* h, itn_mps* mps, const itn_mpo* mpo,
   if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot run sweeps");
   Ctx c;
   c.h = h;
+  c.sb = &mps->sb;
   c.m = mps;
   c.mpo = mpo;
   c.p = p;

@@ -86,28 +86,6 @@ itn_status read_qtensor(itn_handle* h, const itn_tensor* t, int rank, const int*
   return ITN_OK;
 }
 
-// Every allowed (zero-flux) sector tuple of a tensor's indices, lexicographic.
-std::vector<std::vector<int32_t>> allowed_blocks(const QTensor& t) {
-  std::vector<std::vector<int32_t>> out;
-  std::vector<int32_t> blk(t.rank, 0);
-  const int nq = t.sp[0].nq;
-  std::function<void(int)> rec = [&](int i) {
-    if (i == t.rank) {
-      auto f = block_flux(t, blk);
-      bool zero = true;
-      for (int c = 0; c < nq; ++c) zero &= f[c] == 0;
-      if (zero) out.push_back(blk);
-      return;
-    }
-    for (int k = 0; k < t.sp[i].nsec; ++k) {
-      blk[i] = k;
-      rec(i + 1);
-    }
-  };
-  rec(0);
-  return out;
-}
-
 bool distinct_qns(const QSpace& s) {
   for (int i = 0; i < s.nsec; ++i)
     for (int j = i + 1; j < s.nsec; ++j)
@@ -250,6 +228,7 @@ struct itn_plan {
   void* zero = nullptr;  // zero page for K tails of direct-to-LDS tiles
   int cfg1 = 0, cfg4 = 0;
   bool tuned = false;
+  bool direct = false;  // launch without graph capture (plans used for a few applies only)
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1001,6 +980,27 @@ itn_status itn_plan_destroy(itn_plan* plan) {
   return ITN_OK;
 }
 
+}  // extern "C"
+
+namespace itn {
+// Fix a plan's launch modes (no autotuning) and launch it without graph
+// capture: for plans that serve a handful of applies, as in a sweep.
+itn_status qn_plan_set_direct(itn_plan* pl, int mode_stage1, int mode_stage4) {
+  if (!pl || mode_stage1 < 0 || mode_stage1 >= itn_plan::kModes || mode_stage4 < 0 ||
+      mode_stage4 >= itn_plan::kModes)
+    return ITN_E_ARG;
+  if (!pl->tl1.usable(mode_stage1) || !pl->tl4.usable(mode_stage4)) return ITN_E_ARG;
+  pl->cfg1 = mode_stage1;
+  pl->cfg4 = mode_stage4;
+  pl->wsel = 0;
+  pl->tuned = true;
+  pl->direct = true;
+  return ITN_OK;
+}
+}  // namespace itn
+
+extern "C" {
+
 itn_status itn_plan_query(const itn_plan* pl, itn_plan_info* info) {
   if (!pl || !info) return ITN_E_ARG;
   info->out_nblocks = (int64_t)pl->out_blocks.size();
@@ -1121,7 +1121,7 @@ itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, c
     pl->env_ready = true;
   }
   if (!pl->tuned) ITN_TRY(autotune(h, *pl, s));
-  if (h->prof_on) {  // per-kernel timing: run the launches directly
+  if (h->prof_on || pl->direct) {  // per-kernel timing, or a short-lived plan: launch directly
     ITN_TRY(launch_all(h, *pl, s, pl->cfg1, pl->cfg4, !prepared));
     return ITN_OK;
   }

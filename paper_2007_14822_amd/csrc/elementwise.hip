@@ -408,6 +408,29 @@ hipError_t precond_diag(double* r, const double* D, double theta, double eps, in
   return hipGetLastError();
 }
 
+// x[i] += eps * u_i with u_i uniform in [-1, 1) from the splitmix64 hash of
+// (seed, i) (Steele, Lea and Flood's SplitMix64 finaliser): a reproducible
+// perturbation that touches every element.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void add_noise_kernel(double* __restrict__ x, int64_t n, double eps, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = splitmix64(seed ^ splitmix64((uint64_t)i));
+    const double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
+    x[i] += eps * (2.0 * u - 1.0);
+  }
+}
+hipError_t add_noise(double* x, int64_t n, double eps, uint64_t seed, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(add_noise_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, x, n, eps, seed);
+  return hipGetLastError();
+}
+
 template <typename T> __global__ void fill_kernel(T* x, T v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

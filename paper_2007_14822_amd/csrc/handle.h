@@ -129,6 +129,9 @@ itn_status heff_apply_terms(itn_handle* h, int n, const itn_tensor* const* Ls,
 itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, itn_tensor* C,
                        itn_prec prec, void* hip_stream);
 
+// Fix a QN plan's launch modes and launch it without a graph (sweeps).
+itn_status qn_plan_set_direct(itn_plan* pl, int mode_stage1, int mode_stage4);
+
 // Looks up the allocation-free entry point's scratch on `device` (current).
 void noalloc_scratch_init(int device);
 

@@ -225,6 +225,8 @@ hipError_t fill(void* x, int dtype, double v, int64_t n, hipStream_t s);
 // (Wd[m0][m2][s1*d + s2] = sum_m1 W1[m0,m1,s1,s1] W2[m1,m2,s2,s2]), D [cl, d2, cr].
 hipError_t heff_diag(const double* L, const double* R, const double* Wd, int w, int d2, int64_t cl,
                      int64_t cr, double* D, hipStream_t s);
+// x[i] += eps * (uniform in [-1, 1) from a counter-based hash of (seed, i)).
+hipError_t add_noise(double* x, int64_t n, double eps, uint64_t seed, hipStream_t s);
 // r /= (D - theta) element-wise, denominators clipped to magnitude >= eps.
 hipError_t precond_diag(double* r, const double* D, double theta, double eps, int64_t n, hipStream_t s);
 

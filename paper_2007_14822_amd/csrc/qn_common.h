@@ -4,6 +4,7 @@
 #pragma once
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -88,6 +89,30 @@ inline std::vector<int32_t> qadd(const int32_t* a, const int32_t* b, const std::
   std::vector<int32_t> r(nq);
   for (int c = 0; c < nq; ++c) r[c] = qn_red((int64_t)a[c] + sb * (int64_t)b[c], mod[c]);
   return r;
+}
+
+// Every allowed sector tuple of a tensor's indices (flux `flux`, empty =
+// zero), lexicographic.
+inline std::vector<std::vector<int32_t>> allowed_blocks(const QTensor& t,
+                                                       const std::vector<int32_t>& flux = {}) {
+  std::vector<std::vector<int32_t>> out;
+  std::vector<int32_t> blk(t.rank, 0);
+  const int nq = t.sp[0].nq;
+  std::function<void(int)> rec = [&](int i) {
+    if (i == t.rank) {
+      auto f = block_flux(t, blk);
+      bool zero = true;
+      for (int c = 0; c < nq; ++c) zero &= f[c] == (flux.empty() ? 0 : flux[c]);
+      if (zero) out.push_back(blk);
+      return;
+    }
+    for (int k = 0; k < t.sp[i].nsec; ++k) {
+      blk[i] = k;
+      rec(i + 1);
+    }
+  };
+  rec(0);
+  return out;
 }
 
 }  // namespace qn
