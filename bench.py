@@ -26,28 +26,34 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = ("H_eff·psi TFLOP/s (% MFMA peak), mixed vs FP64; DMRG sweep time at 1e-8 ΔE")
 PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
-# the sources heff_stage1_fused is compiled from (its HBM-traffic record is
+# the sources each timed kernel is compiled from (its HBM-traffic record is
 # valid only for this code); of the shared declarations header only the
 # kernel's argument struct counts
-KERNEL_SOURCES = ["paper_2007_14822_amd/csrc/heff_fused.hip", "paper_2007_14822_amd/csrc/gemm_core.h",
-                  "paper_2007_14822_amd/csrc/common.h"]
-KERNEL_DECLS = ("paper_2007_14822_amd/csrc/kernels.h", "struct HeffFusedArgs")
+KERNEL_SOURCES = {
+    "heff_stage1_fused": (["paper_2007_14822_amd/csrc/heff_fused.hip",
+                           "paper_2007_14822_amd/csrc/gemm_core.h",
+                           "paper_2007_14822_amd/csrc/common.h"], "struct HeffFusedArgs"),
+    "heff_stage4_gemm": (["paper_2007_14822_amd/csrc/gemm.hip", "paper_2007_14822_amd/csrc/gemm_core.h",
+                          "paper_2007_14822_amd/csrc/common.h"], "struct GemmArgs"),
+}
+KERNEL_DECLS = "paper_2007_14822_amd/csrc/kernels.h"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str = "heff_stage1_fused") -> str:
+    srcs, decl = KERNEL_SOURCES[kernel]
     hsh = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in srcs:
         fp = os.path.join(ROOT, p)
         if os.path.exists(fp):
             hsh.update(open(fp, "rb").read())
-    fp = os.path.join(ROOT, KERNEL_DECLS[0])
+    fp = os.path.join(ROOT, KERNEL_DECLS)
     if os.path.exists(fp):
         text = open(fp, "rb").read().decode()
-        i = text.find(KERNEL_DECLS[1])
+        i = text.find(decl)
         if i >= 0:
             hsh.update(text[i:text.index("};", i)].encode())
     return hsh.hexdigest()[:16]
@@ -230,7 +236,7 @@ def traffic_record(kernel: str, workload: str):
     if not os.path.exists(fp):
         return None
     rec = json.load(open(fp))
-    if rec.get("source_hash") != kernel_source_hash():
+    if kernel not in KERNEL_SOURCES or rec.get("source_hash") != kernel_source_hash(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -501,6 +507,13 @@ def main():
     ap.add_argument("--no-qn", action="store_true")
     ap.add_argument("--no-dmrg", action="store_true")
     ap.add_argument("--no-sum", action="store_true")
+    ap.add_argument("--qn-only", action="store_true",
+                    help="run the block-sparse legs only (profiling runs; prints their JSON)")
+    ap.add_argument("--qn-which", default="c3,c4,c4w38,c4z4",
+                    help="block-sparse workloads of --qn-only (comma list)")
+    ap.add_argument("--qn-prec", default="bf16,f64", help="precisions of --qn-only (comma list)")
+    ap.add_argument("--dmrg-only", action="store_true",
+                    help="run the DMRG legs only (profiling runs; prints their JSON)")
     ap.add_argument("--no-sizes", action="store_true",
                     help="skip the other dense sizes (chi 256/512/1024 at d=2, chi 2048 at d=3)")
     ap.add_argument("--dmrg-maxdim", type=int, default=256)
@@ -521,6 +534,24 @@ def main():
 
     chi, d = args.chi, args.d
     h = itn.Handle(0)
+    if args.qn_only or args.dmrg_only:
+        out = {}
+        if args.qn_only:
+            nvs = {"c3": 1, "c4": 4, "c4w38": 4, "c4z4": 4}
+            for which in args.qn_which.split(","):
+                nv = nvs[which]
+                for prec in args.qn_prec.split(","):
+                    log("[bench] QN %s %s nv=%d" % (which, prec, nv))
+                    out["%s_%s" % (which, prec)] = time_qn(h, torch, np, inp, which, prec, nv, 10, 3)[0]
+        if args.dmrg_only:
+            md = args.dmrg_maxdim
+            sched = [(min(64, md), 1e-10), (min(128, md), 1e-10)] + [(md, 1e-10)] * 4
+            for prec in ("f64", "bf16"):
+                log("[bench] DMRG spin-1 N=100 %s" % prec)
+                out["dmrg_" + prec] = dmrg_leg(h, np, inp, prec, sched)
+        h.close()
+        print(json.dumps(out), flush=True)
+        return
     log("[bench] building chi=%d workload" % chi)
     t0 = time.perf_counter()
     L64, W1, W2, R64, psi = build_workload(h, chi, d, torch, np, inp)
