@@ -302,9 +302,12 @@ def cpu_baseline(L, W1, W2, R, psi, chi, d, w, budget_s):
 
 
 # ----------------------------------------------------------------- QN legs
-def qn_workload(h, torch, np, inp, which, prec, nv):
+def qn_workload(h, torch, np, inp, which, prec, nv, split_mpo=False):
     """Block-sparse H_eff operands.  Structure from the library's block
-    enumeration, values from the seeded per-block generator.
+    enumeration, values from the seeded per-block generator.  split_mpo:
+    every MPO channel its own link sector (the sparse-MPO "splitblocks"
+    form: zero W blocks between channels of equal charge are never formed;
+    the same operator, finer groups).
       c3: U(1) S=1/2 chain bond, chi=4096 in 25 binomial-shaped sectors, w=5
       c4: U(1)xU(1) Hubbard 4x32 cylinder bond, chi=4096 in 81 sectors,
           w=18 (column-major snake) or the synthetic w=38 shape"""
@@ -340,7 +343,11 @@ def qn_workload(h, torch, np, inp, which, prec, nv):
     bq = [tuple(q) if isinstance(q, tuple) else (q,) for q, _ in bond]
     bd = [n for _, n in bond]
     sq, sd = inp.sectors_from_basis_qns(site_q)
-    lq, ld = inp.sectors_from_basis_qns(link_q)
+    if split_mpo:
+        lq = [tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,))) for q in link_q]
+        ld = [1] * len(lq)
+    else:
+        lq, ld = inp.sectors_from_basis_qns(link_q)
     spaces = {
         "L": [(bq, bd, +1), (lq, ld, -1), (bq, bd, -1)],
         "R": [(bq, bd, -1), (lq, ld, +1), (bq, bd, +1)],
@@ -390,8 +397,8 @@ def qn_workload(h, torch, np, inp, which, prec, nv):
     return Ld, W1d, W2d, Rd, Pd, Od
 
 
-def time_qn(h, torch, np, inp, which, prec, nv, steps, warmup):
-    Ld, W1d, W2d, Rd, Pd, Od = qn_workload(h, torch, np, inp, which, prec, nv)
+def time_qn(h, torch, np, inp, which, prec, nv, steps, warmup, split_mpo=False):
+    Ld, W1d, W2d, Rd, Pd, Od = qn_workload(h, torch, np, inp, which, prec, nv, split_mpo)
     t0 = time.perf_counter()
     plan = h.qn_plan(Ld, W1d, W2d, Rd, Pd, nv=nv, prec=prec)
     tplan = time.perf_counter() - t0
@@ -512,6 +519,9 @@ def main():
     ap.add_argument("--qn-which", default="c3,c4,c4w38,c4z4",
                     help="block-sparse workloads of --qn-only (comma list)")
     ap.add_argument("--qn-prec", default="bf16,f64", help="precisions of --qn-only (comma list)")
+    ap.add_argument("--dmrg-large", action="store_true",
+                    help="with --dmrg-only: spin-1 chain N=40, cutoff 0, maxdim 256 then 1024 x 3 "
+                         "(density matrices of up to 3072 rows)")
     ap.add_argument("--dmrg-only", action="store_true",
                     help="run the DMRG legs only (profiling runs; prints their JSON)")
     ap.add_argument("--no-sizes", action="store_true",
@@ -543,7 +553,17 @@ def main():
                 for prec in args.qn_prec.split(","):
                     log("[bench] QN %s %s nv=%d" % (which, prec, nv))
                     out["%s_%s" % (which, prec)] = time_qn(h, torch, np, inp, which, prec, nv, 10, 3)[0]
-        if args.dmrg_only:
+                if which in ("c3", "c4") and "bf16" in args.qn_prec:
+                    log("[bench] QN %s bf16, one link sector per MPO channel" % which)
+                    out["%s_bf16_splitblocks" % which] = time_qn(h, torch, np, inp, which, "bf16", nv, 10,
+                                                                 3, split_mpo=True)[0]
+        if args.dmrg_only and args.dmrg_large:
+            sched = [(256, 0.0), (1024, 0.0), (1024, 0.0), (1024, 0.0)]
+            for prec in ("bf16", "f64"):
+                log("[bench] DMRG spin-1 N=40 %s, cutoff 0, maxdim up to 1024" % prec)
+                out["dmrg_large_" + prec] = dmrg_leg(h, np, inp, prec, sched, N=40, timing=True)
+                log("[bench]   %.1f s" % out["dmrg_large_" + prec]["total_seconds"])
+        elif args.dmrg_only:
             md = args.dmrg_maxdim
             sched = [(min(64, md), 1e-10), (min(128, md), 1e-10)] + [(md, 1e-10)] * 4
             for prec in ("f64", "bf16"):
@@ -654,6 +674,12 @@ def main():
                 else:
                     lo_out = out
                 log("[bench]   %.3f ms, %.1f TFLOP/s" % (r_qn["ms_per_apply"], r_qn["tflops"]))
+        for which in ("c3", "c4"):  # the same operators with every MPO channel its own sector
+            log("[bench] QN %s bf16, one link sector per MPO channel" % which)
+            r_qn, _ = time_qn(h, torch, np, inp, which, "bf16", 1 if which == "c3" else 4, 10, 3,
+                              split_mpo=True)
+            qn["%s_bf16_splitblocks" % which] = r_qn
+            log("[bench]   %.3f ms, %.1f TFLOP/s" % (r_qn["ms_per_apply"], r_qn["tflops"]))
         line["qn"] = qn
     if not args.no_sum and not args.only:
         line["mpo_sum"] = sum_leg(h, torch, np, inp, chi, args.steps, args.warmup)

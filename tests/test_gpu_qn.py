@@ -286,3 +286,26 @@ def test_qn_prepared_environments(h, prec):
             # (0.5 L, 2 R): exact power-of-two scalings, the same H_eff
             ref = Q.heff_apply_blocks(L, w1, w2, R, p2).packed()[2]
             assert rel_err(a, ref) <= TOL[prec], (prec, seed)
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_splitblocks_mpo_sectors_parity(h, prec):
+    """The sparse-MPO form (every MPO channel its own link sector, so equal
+    charges repeat): the planner and grouped launches against the oracle on
+    the Hubbard MPO."""
+    from oracle import qn as Qn
+    from paper_2007_14822_amd import inputs as inp
+    Ws = inp.hubbard_mpo(2, 4)
+    link_q = inp.hubbard_mpo_link_qn(Ws[0].shape[0])
+    link = Qn.make_index([(q, 1) for q in link_q], +1)
+    site = Qn.index_from_basis_qns(inp.hubbard_site_qn())
+    bl = [((0, 0), 2), ((1, 1), 3), ((1, -1), 2), ((2, 0), 4)]
+    br = [((1, 1), 2), ((2, 0), 3), ((3, 1), 2), ((2, 2), 1), ((3, -1), 2)]
+    al, ar = Qn.make_index(bl, +1), Qn.make_index(br, +1)
+    L, R, psi = Qn._env_and_psi(al, ar, site, link, 99, inp.block_values, None)
+    w1 = Qn.mpo_blocks(Ws[5], link, link, site)
+    w2 = Qn.mpo_blocks(Ws[6], link, link, site)
+    ops = (L, w1, w2, R, psi)
+    assert link.nsec == Ws[0].shape[0]
+    _, _, got = _run(h, ops, Ws[5], Ws[6], prec, 2, [psi, _perturbed(psi, 3)])
+    assert rel_err(got, _ref(ops, [psi, _perturbed(psi, 3)])) <= TOL[prec]
