@@ -261,17 +261,20 @@ typedef struct {
   int64_t out_nblocks;     /* number of output blocks (equals psi's)              */
   int64_t out_elems;       /* elements per vector                                 */
   int64_t n_pairs_stage1;  /* block pairs L x psi                                 */
-  int64_t n_groups_stage1; /* GEMM groups after combining by (q_a, q_m0)          */
-  int64_t n_pairs_stage4;  /* block pairs Z x R                                   */
+  int64_t n_groups_stage1; /* L x psi products: one per a-sector (all m0 stacked) */
+  int64_t n_pairs_stage4;  /* K segments of the Z x R products (one product per   */
+                           /* b'-sector, one segment per (m2, b) sector pair)      */
   int64_t n_tiles;         /* work items of the grouped launches                  */
   double flops;            /* 2*M*N*K summed over contributing block products, x nv */
-  int64_t x_elems;         /* stage-1 intermediate X, elements per vector         */
-  int64_t z_elems;         /* W-stage output Z (stage-4 operand), per vector      */
+  int64_t x_elems;         /* stage-1 intermediate X, elements per vector (not    */
+                           /* counting the zero columns that pad each b-sector    */
+                           /* to a multiple of 8)                                 */
+  int64_t z_elems;         /* W-stage output Z (stage-4 operand), per vector, ditto */
   double flops_wstage;     /* 2 * W12 terms * positions, x nv (not in flops)      */
   int32_t mode_stage1;     /* grouped launch modes of stages 1 and 4 (0..5, see   */
   int32_t mode_stage4;     /* itn_qn_heff_apply); -1 before the first apply       */
-  int32_t wstage_tile;     /* W-stage kernel: 0 streaming, else LDS-staged with   */
-                           /* this many positions per block; -1 before the first apply */
+  int32_t wstage_tile;     /* W-stage work item: 16-byte vectors per workgroup    */
+                           /* (64, 128, 256 or 512); -1 before the first apply    */
   double flops_stage1;     /* the part of `flops` in the L*psi stage (the rest is   */
                            /* the Z*R stage)                                         */
 } itn_plan_info;

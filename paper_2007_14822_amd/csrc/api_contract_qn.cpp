@@ -236,6 +236,7 @@ itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, 
     pr.seg0 = (int32_t)segs.size();
     pr.nseg = (int32_t)kv.second.size();
     pr.tiles_n = (int32_t)((N + TC - 1) / TC);
+    pr.row0 = -1;
     for (const Pair& q : kv.second) {
       const int64_t K = dims_of(qa, q.a, conA);
       GSeg sg{};
@@ -311,6 +312,7 @@ itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, 
   gb.B = Bp;
   gb.C = natural ? C->data : T;
   gb.zero = nullptr;
+  gb.rows = nullptr;
   ITN_HIP(h, hipMemcpyAsync(dprob, probs.data(), probs.size() * sizeof(GProb), hipMemcpyHostToDevice, s));
   ITN_HIP(h, hipMemcpyAsync(dseg, segs.data(), segs.size() * sizeof(GSeg), hipMemcpyHostToDevice, s));
   ITN_HIP(h, hipMemcpyAsync(dtile, tiles.data(), tiles.size() * sizeof(GTile), hipMemcpyHostToDevice, s));

@@ -270,8 +270,10 @@ struct DotBatch {
 // Ritz vector (with a block, the B lowest), so a cycle is one FP64 matvec
 // and kmax - 1 low-precision ones.  Without refinement every matvec runs at
 // `prec`.  The returned energy is the Ritz value; with `exact_final` (mixed
-// mode) the result is applied once more in FP64 and its Rayleigh quotient
-// and residual are returned instead.
+// mode) a residual test passed with low-precision products is confirmed
+// from a restart (one FP64 product, then the exact residual), and a result
+// that does not end on such a restart is applied once more in FP64: the
+// returned energy and residual are then FP64 figures.
 //
 // *converged is false only when maxiter matvecs ended above the tolerance;
 // a residual with no new direction left (the basis spans the invariant
@@ -418,8 +420,15 @@ itn_status davidson(SolveCtx& c, const Matvec& mv, int prec, double tol, int max
     auto G = [&](int j, int a) { return G0[off[j] + a]; };
     rn = std::sqrt(std::max(B > 1 ? G0[orr] : G(0, k), 0.0));
     if (rn <= tol * std::max(1.0, std::fabs(theta))) {
-      conv = true;
-      break;
+      // In mixed mode a residual formed from low-precision products (k > 1)
+      // can pass the test while the FP64 residual does not.  Where the
+      // result must hold in FP64 (exact_final), confirm it from a restart:
+      // its single vector's product is FP64, so the next residual is exact.
+      if (!(mixed && exact_final && B == 1 && k > 1 && used < maxiter)) {
+        conv = true;
+        break;
+      }
+      force_restart = true;
     }
     if (used >= maxiter) break;
     if (k + nb > kmax || force_restart) {
@@ -522,7 +531,10 @@ itn_status davidson(SolveCtx& c, const Matvec& mv, int prec, double tol, int max
   }
   // the Ritz vector of the last projected problem
   ITN_HIP(c.h, lincomb(V, n, k, y0.data(), 0.0, psi, n, c.s));
-  if (mixed && exact_final) {
+  // A single-vector basis after a restart (or the start) holds the FP64
+  // product already: theta and rn above are the FP64 figures.
+  const bool exact_now = mixed && B == 1 && k == 1;
+  if (mixed && exact_final && !exact_now) {
     // FP64 Rayleigh quotient and residual of the result
     double* ax = AVs(s_spare);
     ITN_TRY(heff(ITN_P_F64, psi, ax, 1));

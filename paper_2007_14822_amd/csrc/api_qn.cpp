@@ -189,20 +189,19 @@ struct itn_plan {
   std::vector<int32_t> tbi;  // block of every transpose tile
   int64_t tb_tiles = 0;
   std::vector<QnWPair> wp;
-  std::vector<QnWIn> win;
   std::vector<QnWEnt> we;
-  // W-stage kernel candidates: streaming, or inputs staged in LDS for
-  // chunks of 64 / 128 / 256 positions (if the largest pair's inputs fit);
-  // one item list each, the autotuner picks wsel.
-  static constexpr int kWCand[4] = {0, 64, 128, 256};
-  std::vector<QnWItem> wi[4];
-  bool wok[4] = {true, false, false, false};
+  // W-stage kernel candidates: work items of 256, 512 (two per thread), 128
+  // or 64 vectors; one item list each, the autotuner picks wsel.
+  static constexpr int kWNum = 4;
+  static constexpr int kWCand[kWNum] = {256, 512, 128, 64};
+  std::vector<QnWItem> wi[kWNum];
   int wsel = 0;
+  std::vector<int64_t> rows4;  // stage-4 row table: output offset of every product row
   std::vector<QnCopy> cp;  // L / R repacks into padded, aligned blocks
   std::vector<int64_t> zoff, zsize;
   int64_t psiT_elems = 0, X_elems = 0, Z_elems = 0, Lp_elems = 0, Rp_elems = 0;
-  int64_t max_db = 0;  // widest right bond sector
-  int64_t max_nin = 0; // most distinct X inputs of one W-stage pair
+  int64_t max_db = 0;  // widest right bond sector (padded)
+  int64_t X_real = 0, Z_real = 0;  // X and Z elements without the b padding
   int64_t pairs1 = 0;
   double flops_gemm = 0.0, flops_w = 0.0, flops_s1 = 0.0;
   // device state
@@ -214,9 +213,9 @@ struct itn_plan {
   QnTBlock* dtb = nullptr;
   int32_t* dtbi = nullptr;
   QnWPair* dwp = nullptr;
-  QnWIn* dwin = nullptr;
   QnWEnt* dwe = nullptr;
-  QnWItem* dwi[4] = {nullptr, nullptr, nullptr, nullptr};
+  QnWItem* dwi[kWNum] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t* drows4 = nullptr;
   QnCopy* dcp = nullptr;
   int64_t* dzoff = nullptr;
   int64_t* dzsize = nullptr;
@@ -340,6 +339,51 @@ void build_tiles(TL& tl, const std::vector<GProb>& probs, const std::vector<GSeg
   tl.rest_midall = make_tiles(probs, segs, 64, 64, rest_midall);
 }
 
+// Every access the plan's tables describe stays inside its buffer, and the
+// W-stage vectors are 16-byte aligned: checked once per plan, on the host,
+// before any table reaches the device.
+bool layout_ok(const itn_plan& pl, int64_t psi_elems) {
+  for (const QnTBlock& t : pl.tb) {
+    if (t.rows <= 0 || t.cols <= 0 || t.in_ld < t.cols || t.ld_out < t.rows) return false;
+    if (t.in_off + (int64_t)(t.rows - 1) * t.in_ld + t.cols > psi_elems) return false;
+    if (t.out_off + (int64_t)(t.cols - 1) * t.ld_out + t.rows > pl.psiT_elems) return false;
+  }
+  for (const QnCopy& c : pl.cp) {
+    const int64_t lim = c.src ? pl.Rp_elems : pl.Lp_elems;
+    if (c.cols > c.ld_out || c.out_off + (int64_t)(c.rows - 1) * c.ld_out + c.cols > lim) return false;
+  }
+  auto seg_ok = [](const GProb& pr, const GSeg& g, int64_t a_lim, int64_t b_lim) {
+    return g.K <= g.lda && g.K <= g.ldb && g.a_off + (int64_t)pr.M * g.lda <= a_lim &&
+           g.b_off + (int64_t)pr.N * g.ldb <= b_lim;
+  };
+  for (const GProb& pr : pl.p1) {
+    if (pr.row0 >= 0 || pr.c_off + (int64_t)pr.M * pr.ldc > pl.X_elems || pr.N > pr.ldc) return false;
+    for (int k = 0; k < pr.nseg; ++k)
+      if (!seg_ok(pr, pl.s1[pr.seg0 + k], pl.Lp_elems, pl.psiT_elems)) return false;
+  }
+  for (const GProb& pr : pl.p4) {
+    if (pr.row0 < 0 || pr.row0 + (int64_t)pr.M > (int64_t)pl.rows4.size()) return false;
+    for (int64_t r = 0; r < pr.M; ++r)
+      if (pl.rows4[pr.row0 + r] < 0 || pl.rows4[pr.row0 + r] + pr.N > psi_elems) return false;
+    for (int k = 0; k < pr.nseg; ++k)
+      if (!seg_ok(pr, pl.s4[pr.seg0 + k], pl.Z_elems, pl.Rp_elems)) return false;
+  }
+  for (const QnWPair& wp : pl.wp) {
+    if (wp.da <= 0 || wp.db <= 0 || wp.db % 8 || wp.ne <= 0) return false;
+    for (int e = wp.e0; e < wp.e0 + wp.ne; ++e) {
+      const QnWEnt& en = pl.we[e];
+      if ((en.off | en.astride) % 8) return false;
+      if (en.off < 0 || en.off + (int64_t)(wp.da - 1) * en.astride + wp.db > pl.X_elems + pl.max_db) return false;
+      if (en.end) {
+        if ((en.zoff | en.zastride) % 8) return false;
+        if (en.zoff < 0 || en.zoff + (int64_t)(wp.da - 1) * en.zastride + wp.db > pl.Z_elems) return false;
+      }
+    }
+    if (!pl.we[wp.e0 + wp.ne - 1].end) return false;
+  }
+  return pl.X_elems % 8 == 0 && pl.Z_elems % 8 == 0;
+}
+
 itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t,
                       const itn_tensor* W2t, const itn_tensor* Rt, const itn_tensor* Pt, int nv,
                       int prec, itn_plan& pl) {
@@ -427,13 +471,20 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
            std::to_string(prec);
   pl.sig_hash = std::hash<std::string>()(pl.sig);
 
+  // Every b-sector is padded to a multiple of 8 columns in psiT, X, Z and
+  // the R copies (zero padding), so the W-stage moves aligned 16-byte
+  // vectors; the padded K columns of the Z x R products multiply zeros.
+  auto dbp = [&](int ib) -> int64_t { return pad8(SB.dim[ib]); };
+
   // ---- psiT layout: groups by a-sector (psi blocks are a-major already)
   const int nA = SA.nsec;
-  std::vector<int64_t> N_ia(nA, 0), psiT_off(nA, 0), colbase(P.blocks.size(), 0);
+  std::vector<int64_t> N_ia(nA, 0), N_real(nA, 0), psiT_off(nA, 0), colbase(P.blocks.size(), 0);
   for (size_t b = 0; b < P.blocks.size(); ++b) {
     const auto& k = P.blocks[b];
+    const int64_t ss = (int64_t)S1.dim[k[1]] * S2.dim[k[2]];
     colbase[b] = N_ia[k[0]];
-    N_ia[k[0]] += (int64_t)S1.dim[k[1]] * S2.dim[k[2]] * SB.dim[k[3]];
+    N_ia[k[0]] += ss * dbp(k[3]);
+    N_real[k[0]] += ss * SB.dim[k[3]];
   }
   std::vector<int64_t> ldT(nA);
   int64_t acc = 0;
@@ -444,28 +495,59 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   }
   pl.psiT_elems = acc;
   int64_t tiles = 0;
-  for (size_t b = 0; b < P.blocks.size(); ++b) {
-    const auto& k = P.blocks[b];
+  auto add_tblock = [&](int64_t in_off, int64_t out_off, int rows, int64_t cols, int64_t in_ld,
+                        int64_t ld_out) {
     QnTBlock t{};
-    t.in_off = P.off[b];
-    t.rows = SA.dim[k[0]];
-    t.cols = S1.dim[k[1]] * S2.dim[k[2]] * SB.dim[k[3]];
-    t.ld_out = (int32_t)ldT[k[0]];
-    t.out_off = psiT_off[k[0]] + colbase[b] * ldT[k[0]];
+    t.in_off = in_off;
+    t.rows = rows;
+    t.cols = (int32_t)cols;
+    t.in_ld = (int32_t)in_ld;
+    t.ld_out = (int32_t)ld_out;
+    t.out_off = out_off;
     t.tiles_c = (t.cols + 63) / 64;
     t.tile0 = (int32_t)tiles;
     const int64_t nt = (int64_t)((t.rows + 63) / 64) * t.tiles_c;
     tiles += nt;
     pl.tbi.insert(pl.tbi.end(), (size_t)nt, (int32_t)pl.tb.size());
     pl.tb.push_back(t);
+  };
+  for (size_t b = 0; b < P.blocks.size(); ++b) {
+    const auto& k = P.blocks[b];
+    const int64_t ss = (int64_t)S1.dim[k[1]] * S2.dim[k[2]], db = SB.dim[k[3]];
+    const int64_t base = psiT_off[k[0]] + colbase[b] * ldT[k[0]];
+    if (db == dbp(k[3])) {
+      add_tblock(P.off[b], base, SA.dim[k[0]], ss * db, ss * db, ldT[k[0]]);
+    } else {  // one transpose per (s1, s2): the padded columns stay zero
+      for (int64_t j = 0; j < ss; ++j)
+        add_tblock(P.off[b] + j * db, base + j * dbp(k[3]) * ldT[k[0]], SA.dim[k[0]], db, ss * db,
+                   ldT[k[0]]);
+    }
   }
   pl.tb_tiles = tiles;
 
-  // ---- stage 1 groups (a-sector, m0-sector)
+  // ---- stage 1: one product per a-sector over all its m0-sectors
+  // X[(a', m0), (s1, s2, b)] = sum_a L[(a', m0), a] psiT[(s1, s2, b), a]: the
+  // L blocks (a'(m0), m0, a) of one a-sector stack along the rows (their
+  // padded copies are consecutive), so they share the psiT operand in one
+  // product; X group (a, m0) is the row range of its L block.
   std::map<std::pair<int, int>, std::pair<int64_t, int>> xgroup;  // -> (X offset, a'-sector)
   int64_t xacc = 0;
   for (int ia = 0; ia < nA; ++ia) {
     if (N_ia[ia] == 0) continue;
+    GProb pr{};
+    pr.c_off = xacc;
+    pr.N = (int32_t)N_ia[ia];
+    pr.ldc = (int32_t)N_ia[ia];
+    pr.seg0 = (int32_t)pl.s1.size();
+    pr.nseg = 1;
+    pr.row0 = -1;
+    GSeg sg{};
+    sg.a_off = pl.Lp_elems;
+    sg.b_off = psiT_off[ia];
+    sg.lda = (int32_t)ldT[ia];
+    sg.ldb = (int32_t)ldT[ia];
+    sg.K = (int32_t)ldT[ia];
+    int64_t Mtot = 0;
     for (int im = 0; im < SM.nsec; ++im) {
       // L[a':Out, m:In, a:In], zero flux: q(a') = q(m) + q(a)
       const int iap = SA.find(qadd(SM.q(im), SA.q(ia), qmod, +1));
@@ -473,80 +555,102 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       auto it = L.index.find({iap, im, ia});
       if (it == L.index.end()) continue;
       const int64_t M = (int64_t)SA.dim[iap] * SM.dim[im];
-      GSeg sg{};
-      sg.a_off = pl.Lp_elems;
       add_copy(pl.cp, L.off[it->second], pl.Lp_elems, (int)M, SA.dim[ia], (int)ldT[ia], 0);
-      pl.Lp_elems += pad8(M * ldT[ia]);
-      sg.b_off = psiT_off[ia];
-      sg.lda = (int32_t)ldT[ia];
-      sg.ldb = (int32_t)ldT[ia];
-      sg.K = (int32_t)ldT[ia];
-      GProb pr{};
-      pr.c_off = xacc;
-      pr.M = (int32_t)M;
-      pr.N = (int32_t)N_ia[ia];
-      pr.ldc = (int32_t)N_ia[ia];
-      pr.seg0 = (int32_t)pl.s1.size();
-      pr.nseg = 1;
-      pl.s1.push_back(sg);
-      pl.p1.push_back(pr);
+      pl.Lp_elems += M * ldT[ia];  // a multiple of 8: the next block follows directly
       xgroup[{ia, im}] = {xacc, iap};
       xacc += M * N_ia[ia];
-      pl.flops_gemm += 2.0 * M * N_ia[ia] * SA.dim[ia];
-      pl.flops_s1 += 2.0 * M * N_ia[ia] * SA.dim[ia];
+      pl.X_real += M * N_real[ia];
+      Mtot += M;
+      pl.flops_gemm += 2.0 * M * N_real[ia] * SA.dim[ia];
+      pl.flops_s1 += 2.0 * M * N_real[ia] * SA.dim[ia];
       for (size_t b = 0; b < P.blocks.size(); ++b) pl.pairs1 += P.blocks[b][0] == ia;
     }
+    if (Mtot == 0) continue;
+    pr.M = (int32_t)Mtot;
+    pl.s1.push_back(sg);
+    pl.p1.push_back(pr);
   }
   pl.X_elems = xacc;
 
-  // ---- stage 4 problems and the Z blocks they need
+  // ---- stage 4: one product per b'-sector over all output blocks with it
+  // out[(a', s1', s2'), b'] = sum_{m2, b} Z[(a', s1', s2'), (m2, b)] R[b', (m2, b)]:
+  // the output blocks of one b' share the segments (m2, b) of R, so their Z
+  // blocks stack along the rows of one Z matrix per segment and the product
+  // writes its rows to the blocks through a row table.
   std::map<std::vector<int32_t>, int64_t> zblock;  // (ia', is1', is2', im2, ib) -> Z offset
   std::map<int, int64_t> rpad;                      // R block -> padded copy offset
   int64_t zacc = 0;
-  for (size_t ob = 0; ob < P.blocks.size(); ++ob) {
-    const auto& k = P.blocks[ob];
-    const int iap = k[0], i1 = k[1], i2 = k[2], ibp = k[3];
-    GProb pr{};
-    pr.c_off = P.off[ob];
-    pr.M = SA.dim[iap] * S1.dim[i1] * S2.dim[i2];
-    pr.N = SB.dim[ibp];
-    pr.ldc = SB.dim[ibp];
-    pr.seg0 = (int32_t)pl.s4.size();
-    pr.nseg = 0;
+  std::map<int, std::vector<size_t>> by_bp;  // b'-sector -> output blocks (psi order)
+  for (size_t ob = 0; ob < P.blocks.size(); ++ob) by_bp[P.blocks[ob][3]].push_back(ob);
+  for (auto& kv : by_bp) {
+    const int ibp = kv.first;
+    const std::vector<size_t>& obs = kv.second;
+    struct Seg {
+      int im2, ib;
+      int rb;  // R block
+    };
+    std::vector<Seg> segs;
     for (int im2 = 0; im2 < SM2.nsec; ++im2) {
       // R[b':In, m:Out, b:Out], zero flux: q(b) = q(b') - q(m)
       const int ib = SB.find(qadd(SB.q(ibp), SM2.q(im2), qmod, -1));
       if (ib < 0) continue;
       auto it = R.index.find({ibp, im2, ib});
       if (it == R.index.end()) continue;
-      std::vector<int32_t> zk = {iap, i1, i2, im2, ib};
-      const int64_t K = (int64_t)SM2.dim[im2] * SB.dim[ib];
-      const int64_t ldK = pad8(K);
-      if (!zblock.count(zk)) {
-        zblock[zk] = zacc;
-        zacc += pad8((int64_t)pr.M * ldK);
+      segs.push_back(Seg{im2, ib, it->second});
+    }
+    if (segs.empty()) {  // no R block: these output blocks are zero
+      for (size_t ob : obs) {
+        const auto& k = P.blocks[ob];
+        pl.zoff.push_back(P.off[ob]);
+        pl.zsize.push_back((int64_t)SA.dim[k[0]] * S1.dim[k[1]] * S2.dim[k[2]] * SB.dim[ibp]);
       }
-      if (!rpad.count(it->second)) {
-        rpad[it->second] = pl.Rp_elems;
-        add_copy(pl.cp, R.off[it->second], pl.Rp_elems, SB.dim[ibp], (int)K, (int)ldK, 1);
-        pl.Rp_elems += pad8((int64_t)SB.dim[ibp] * ldK);
+      continue;
+    }
+    const int64_t N = SB.dim[ibp];
+    GProb pr{};
+    pr.c_off = 0;
+    pr.N = (int32_t)N;
+    pr.ldc = (int32_t)N;
+    pr.seg0 = (int32_t)pl.s4.size();
+    pr.nseg = (int32_t)segs.size();
+    pr.row0 = (int32_t)pl.rows4.size();
+    std::vector<int64_t> rowstart;
+    int64_t Mtot = 0;
+    for (size_t ob : obs) {
+      const auto& k = P.blocks[ob];
+      const int64_t M = (int64_t)SA.dim[k[0]] * S1.dim[k[1]] * S2.dim[k[2]];
+      rowstart.push_back(Mtot);
+      for (int64_t r = 0; r < M; ++r) pl.rows4.push_back(P.off[ob] + r * N);
+      Mtot += M;
+    }
+    pr.M = (int32_t)Mtot;
+    for (const Seg& sgm : segs) {
+      const int64_t ldK = (int64_t)SM2.dim[sgm.im2] * dbp(sgm.ib);
+      const int64_t base = zacc;
+      zacc += Mtot * ldK;
+      for (size_t i = 0; i < obs.size(); ++i) {
+        const auto& k = P.blocks[obs[i]];
+        zblock[{k[0], k[1], k[2], sgm.im2, sgm.ib}] = base + rowstart[i] * ldK;
+      }
+      if (!rpad.count(sgm.rb)) {
+        // R block [b'][m2][b] -> rows (b', m2) of dbp(b) columns
+        rpad[sgm.rb] = pl.Rp_elems;
+        add_copy(pl.cp, R.off[sgm.rb], pl.Rp_elems, (int)(N * SM2.dim[sgm.im2]), SB.dim[sgm.ib],
+                 (int)dbp(sgm.ib), 1);
+        pl.Rp_elems += N * ldK;
       }
       GSeg sg{};
-      sg.a_off = zblock[zk];
+      sg.a_off = base;
       sg.lda = (int32_t)ldK;
-      sg.b_off = rpad[it->second];
+      sg.b_off = rpad[sgm.rb];
       sg.ldb = (int32_t)ldK;
       sg.K = (int32_t)ldK;
       pl.s4.push_back(sg);
-      pr.nseg++;
-      pl.flops_gemm += 2.0 * pr.M * pr.N * K;  // algorithmic (unpadded) work
+      const int64_t K = (int64_t)SM2.dim[sgm.im2] * SB.dim[sgm.ib];
+      pl.Z_real += Mtot * K;
+      pl.flops_gemm += 2.0 * Mtot * N * K;  // algorithmic (unpadded) work
     }
-    if (pr.nseg == 0) {
-      pl.zoff.push_back(P.off[ob]);
-      pl.zsize.push_back((int64_t)pr.M * pr.N);
-    } else {
-      pl.p4.push_back(pr);
-    }
+    pl.p4.push_back(pr);
   }
   pl.Z_elems = zacc;
 
@@ -575,21 +679,20 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   for (auto& kv : pairs) {
     const int iap = kv.first.first, ib = kv.first.second;
     QnWPair wpair{};
-    std::map<std::pair<int64_t, int64_t>, int32_t> pair_inputs;  // distinct X inputs -> index
     wpair.e0 = (int32_t)pl.we.size();
     wpair.da = SA.dim[iap];
-    wpair.db = SB.dim[ib];
-    const int64_t db = SB.dim[ib];
-    pl.max_db = std::max<int64_t>(pl.max_db, db);
+    const int64_t db = SB.dim[ib], dbw = dbp(ib);  // true and padded widths
+    wpair.db = (int32_t)dbw;
+    pl.max_db = std::max<int64_t>(pl.max_db, dbw);
     for (auto& zk : kv.second) {
       const int i1p = zk[1], i2p = zk[2], im2 = zk[3];
       const int64_t zoff = zblock[zk];
       const int64_t ds1p = S1.dim[i1p], ds2p = S2.dim[i2p], dm2 = SM2.dim[im2];
-      const int64_t ldZ = pad8(dm2 * db);
+      const int64_t ldZ = dm2 * dbw;
       for (int s1l = 0; s1l < ds1p; ++s1l)
         for (int s2l = 0; s2l < ds2p; ++s2l)
           for (int m2l = 0; m2l < dm2; ++m2l) {
-            const int64_t row_off = zoff + (s1l * ds2p + s2l) * ldZ + m2l * db;
+            const int64_t row_off = zoff + (s1l * ds2p + s2l) * ldZ + m2l * dbw;
             const int64_t row_astride = ds1p * ds2p * ldZ;
             const size_t row_e0 = pl.we.size();
             const int g_m2 = (int)SM2.off[im2] + m2l;
@@ -613,11 +716,9 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
                         if (cf == 0.0) continue;
                         QnWEnt e{};
                         e.off = xg->second.first + m0l * N_ia[ia] + colbase[pb->second] +
-                                (s1l2 * ds2 + s2l2) * db;
+                                (s1l2 * ds2 + s2l2) * dbw;
                         e.astride = (int64_t)SM.dim[im0] * N_ia[ia];
                         e.coef = cf;
-                        e.in = pair_inputs.emplace(std::make_pair(e.off, e.astride),
-                                                   (int32_t)pair_inputs.size()).first->second;
                         pl.we.push_back(e);
                       }
                 }
@@ -625,6 +726,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
             pl.flops_w += 2.0 * (double)(pl.we.size() - row_e0) * wpair.da * db;
             if (pl.we.size() == row_e0) {
               // no W12 term reaches this row: a zero-weight read of X[b] writes the zeros
+              // (X is allocated max_db elements beyond its last vector)
               QnWEnt e{};
               pl.we.push_back(e);
             }
@@ -635,26 +737,21 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
           }
     }
     wpair.ne = (int32_t)(pl.we.size() - wpair.e0);
-    wpair.in0 = (int32_t)pl.win.size();
-    wpair.nin = (int32_t)pair_inputs.size();
-    pl.win.resize(pl.win.size() + pair_inputs.size());
-    for (auto& kv : pair_inputs) pl.win[wpair.in0 + kv.second] = QnWIn{kv.first.first, kv.first.second};
-    pl.max_nin = std::max<int64_t>(pl.max_nin, (int64_t)pair_inputs.size());
     pl.wp.push_back(wpair);
   }
-  // W-stage item lists, one per kernel candidate
+  // W-stage item lists, one per kernel candidate (vectors per item)
   {
-    const int64_t xsz = pl.xt == D_F64 ? 8 : 4;  // LDS holds X in the accumulation type
-    for (int c = 0; c < 4; ++c) {
-      const int t = itn_plan::kWCand[c];
-      pl.wok[c] = t == 0 || pl.max_nin * t * xsz <= 144 * 1024;
-      if (!pl.wok[c]) continue;
-      const int64_t chunk = t ? t : QN_WSTAGE_POS;
-      for (size_t pid = 0; pid < pl.wp.size(); ++pid)
-        for (int64_t p0 = 0; p0 < (int64_t)pl.wp[pid].da * pl.wp[pid].db; p0 += chunk)
-          pl.wi[c].push_back(QnWItem{(int32_t)pid, (int32_t)p0});
+    const int64_t V = 16 / dtype_size(pl.xt);
+    for (int c = 0; c < itn_plan::kWNum; ++c) {
+      const int64_t chunk = itn_plan::kWCand[c];
+      for (size_t pid = 0; pid < pl.wp.size(); ++pid) {
+        const int64_t nvec = (int64_t)pl.wp[pid].da * pl.wp[pid].db / V;
+        for (int64_t v0 = 0; v0 < nvec; v0 += chunk)
+          pl.wi[c].push_back(QnWItem{(int32_t)pid, (int32_t)v0});
+      }
     }
   }
+  if (!layout_ok(pl, P.elems)) return fail(h, ITN_E_SHAPE, "internal plan layout check failed");
   build_tiles(pl.tl1, pl.p1, pl.s1, pl.prec, pl.pt);
   build_tiles(pl.tl4, pl.p4, pl.s4, pl.prec, pl.pt);
   return ITN_OK;
@@ -686,9 +783,9 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   add(pl.tb.size() * sizeof(QnTBlock));
   add(pl.tbi.size() * sizeof(int32_t));
   add(pl.wp.size() * sizeof(QnWPair));
-  add(pl.win.size() * sizeof(QnWIn));
   add(pl.we.size() * sizeof(QnWEnt));
-  for (int c = 0; c < 4; ++c) add(pl.wi[c].size() * sizeof(QnWItem));
+  for (int c = 0; c < itn_plan::kWNum; ++c) add(pl.wi[c].size() * sizeof(QnWItem));
+  add(pl.rows4.size() * sizeof(int64_t));
   add(pl.cp.size() * sizeof(QnCopy));
   add(pl.zoff.size() * 8);
   add(pl.zsize.size() * 8);
@@ -719,9 +816,9 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   ITN_HIP(h, put(pl.dtb, pl.tb));
   ITN_HIP(h, put(pl.dtbi, pl.tbi));
   ITN_HIP(h, put(pl.dwp, pl.wp));
-  ITN_HIP(h, put(pl.dwin, pl.win));
   ITN_HIP(h, put(pl.dwe, pl.we));
-  for (int c = 0; c < 4; ++c) ITN_HIP(h, put(pl.dwi[c], pl.wi[c]));
+  for (int c = 0; c < itn_plan::kWNum; ++c) ITN_HIP(h, put(pl.dwi[c], pl.wi[c]));
+  ITN_HIP(h, put(pl.drows4, pl.rows4));
   ITN_HIP(h, put(pl.dcp, pl.cp));
   ITN_HIP(h, put(pl.dzoff, pl.zoff));
   ITN_HIP(h, put(pl.dzsize, pl.zsize));
@@ -748,8 +845,8 @@ constexpr int MAX_WG = 1024;  // persistent grouped launches: at most 4 workgrou
 // The launches of one apply (after the operand pointers are set).
 // The W-stage with kernel candidate c.
 hipError_t wstage_launch(itn_plan& pl, int c, hipStream_t s) {
-  return qn_wstage(pl.xt, pl.X, pl.pt, pl.Z, pl.dwp, pl.dwin, pl.dwe, pl.dwi[c], (int64_t)pl.wi[c].size(),
-                   pl.X_elems, pl.Z_elems, pl.nv, itn_plan::kWCand[c], (int)pl.max_nin, s);
+  return qn_wstage(pl.xt, pl.X, pl.Z, pl.dwp, pl.dwe, pl.dwi[c], (int64_t)pl.wi[c].size(),
+                   pl.X_elems, pl.Z_elems, pl.nv, itn_plan::kWCand[c], s);
 }
 
 // One grouped stage (0: stage 1, 1: stage 4) in launch mode `mode`.
@@ -816,12 +913,12 @@ itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int 
 
 // Pick the faster tile per grouped stage by timing both on the real operands.
 itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
-  // ITN_QN_WSTAGE=0|64|128|256 fixes the W-stage kernel (if it fits)
+  // ITN_QN_WSTAGE=64|128|256|512 fixes the W-stage work item (vectors)
   int wforce = -1;
   if (const char* f = std::getenv("ITN_QN_WSTAGE")) {
     const int t = std::atoi(f);
-    for (int c = 0; c < 4; ++c)
-      if (itn_plan::kWCand[c] == t && pl.wok[c]) wforce = c;
+    for (int c = 0; c < itn_plan::kWNum; ++c)
+      if (itn_plan::kWCand[c] == t) wforce = c;
     if (wforce < 0) return fail(h, ITN_E_ARG, "ITN_QN_WSTAGE=%s is not an applicable W-stage kernel", f);
     pl.wsel = wforce;
   }
@@ -844,7 +941,7 @@ itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
     auto it = g_tune.find(pl.sig_hash);
     if (it != g_tune.end() && it->second[0] >= 0 && it->second[0] < itn_plan::kModes &&
         it->second[1] >= 0 && it->second[1] < itn_plan::kModes && it->second[2] >= 0 &&
-        it->second[2] < 4 && pl.wok[it->second[2]]) {
+        it->second[2] < itn_plan::kWNum) {
       pl.cfg1 = it->second[0];
       pl.cfg4 = it->second[1];
       if (wforce < 0) pl.wsel = it->second[2];
@@ -875,8 +972,7 @@ itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
   }
   if (wforce < 0) {  // W-stage kernel candidates
     float bestw = 1e30f;
-    for (int c = 0; c < 4; ++c) {
-      if (!pl.wok[c]) continue;
+    for (int c = 0; c < itn_plan::kWNum; ++c) {
       float tot = 0.f;
       for (int rep = 0; rep < 3; ++rep) {
         ITN_HIP(h, hipEventRecord(e0, s));
@@ -1010,8 +1106,8 @@ itn_status itn_plan_query(const itn_plan* pl, itn_plan_info* info) {
   info->n_pairs_stage4 = (int64_t)pl->s4.size();
   info->n_tiles = (int64_t)(pl->tl1.count(pl->cfg1) + pl->tl4.count(pl->cfg4));
   info->flops = pl->flops_gemm * pl->nv;
-  info->x_elems = pl->X_elems;
-  info->z_elems = pl->Z_elems;
+  info->x_elems = pl->X_real;
+  info->z_elems = pl->Z_real;
   info->flops_wstage = pl->flops_w * pl->nv;
   info->flops_stage1 = pl->flops_s1 * pl->nv;
   info->mode_stage1 = pl->tuned ? pl->cfg1 : -1;
@@ -1062,8 +1158,8 @@ itn_status itn_qn_prepare_env(itn_handle* h, itn_plan* pl, const itn_tensor* L, 
   QnDevPtrs v{};
   v.p.L = L->data;
   v.p.R = R->data;
-  v.g1 = GBases{pl->Lp, pl->psiT, pl->X, pl->zero};
-  v.g4 = GBases{pl->Z, pl->Rp, nullptr, pl->zero};
+  v.g1 = GBases{pl->Lp, pl->psiT, pl->X, pl->zero, nullptr};
+  v.g4 = GBases{pl->Z, pl->Rp, nullptr, pl->zero, pl->drows4};
   ITN_HIP(h, qn_set_ptrs(pl->dptrs, v, s));
   {
     Prof pf(h, "qn_env_repack", s);
@@ -1108,8 +1204,8 @@ itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* pl, const itn_tensor* L, c
   v.p.R = prepared ? pl->envR : R->data;
   v.p.psi = psi->data;
   v.p.out = out->data;
-  v.g1 = GBases{pl->Lp, pl->psiT, pl->X, pl->zero};
-  v.g4 = GBases{pl->Z, pl->Rp, out->data, pl->zero};
+  v.g1 = GBases{pl->Lp, pl->psiT, pl->X, pl->zero, nullptr};
+  v.g4 = GBases{pl->Z, pl->Rp, out->data, pl->zero, pl->drows4};
   {
     Prof pf(h, "qn_set_ptrs", s);
     ITN_HIP(h, qn_set_ptrs(pl->dptrs, v, s));

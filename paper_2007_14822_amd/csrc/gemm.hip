@@ -79,8 +79,9 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(
         gemm_accum<P, BM, BN, false>(A, sg.lda, pr.M, B, sg.ldb, pr.N, sg.K, (int64_t)t.tm * BM,
                                      (int64_t)t.tn * BN, acc, lds);
     }
-    store_tile<P, BM, BN, TOut>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc, pr.M, pr.N,
-                                (int64_t)t.tm * BM, (int64_t)t.tn * BN, false);
+    const int64_t* rows = pr.row0 >= 0 ? bases->rows + pr.row0 : nullptr;
+    store_tile<P, BM, BN, TOut>(acc, Cbase + (rows ? 0 : pr.c_off) + batch * c_bs, pr.ldc, pr.M,
+                                pr.N, (int64_t)t.tm * BM, (int64_t)t.tn * BN, false, rows);
   }
 }
 
@@ -114,9 +115,19 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_grouped_direct_kernel(
                                                  Bbase + sg.b_off + batch * b_bs, sg.ldb, pr.N, sg.K,
                                                  (int64_t)t.tm * BM, (int64_t)t.tn * BN, acc, lds, zero);
     }
-    store_tile_direct<P, BM, BN, WM, WN, TOut, 0>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc,
-                                                       pr.M, pr.N, (int64_t)t.tm * BM,
-                                                       (int64_t)t.tn * BN);
+    const int64_t* rows = pr.row0 >= 0 ? bases->rows + pr.row0 : nullptr;
+    if constexpr (sizeof(TOut) == 2) {
+      // whole-row 16-byte stores through LDS where C's rows are aligned (uniform per problem)
+      if (!rows && ((pr.c_off | pr.ldc | pr.N | c_bs) & 7) == 0 &&
+          (reinterpret_cast<uintptr_t>(Cbase) & 15) == 0) {
+        store_tile_lds<P, BM, BN, WM, WN, TOut>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc, pr.M,
+                                                pr.N, (int64_t)t.tm * BM, (int64_t)t.tn * BN, lds);
+        continue;
+      }
+    }
+    store_tile_direct<P, BM, BN, WM, WN, TOut, 0>(acc, Cbase + (rows ? 0 : pr.c_off) + batch * c_bs,
+                                                       pr.ldc, pr.M, pr.N, (int64_t)t.tm * BM,
+                                                       (int64_t)t.tn * BN, rows);
   }
 }
 
@@ -273,11 +284,12 @@ static hipError_t launch_grouped_direct(const GBases* bases, const GProb* probs,
   int64_t g = ntiles;
   if (max_wg > 0 && g > max_wg) g = max_wg;
   dim3 grid((unsigned)g, (unsigned)nbatch);
-  static const hipError_t attr =
-      allow_lds(gemm_grouped_direct_kernel<P, BM, BN, WM, WN, TOut>, Cfg::LDS_BYTES);
+  constexpr int lds = sizeof(TOut) == 2 && epi_bytes<BM, BN>() > Cfg::LDS_BYTES ? epi_bytes<BM, BN>()
+                                                                                 : Cfg::LDS_BYTES;
+  static const hipError_t attr = allow_lds(gemm_grouped_direct_kernel<P, BM, BN, WM, WN, TOut>, lds);
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL((gemm_grouped_direct_kernel<P, BM, BN, WM, WN, TOut>), grid, dim3(Cfg::THREADS),
-                     Cfg::LDS_BYTES, s, bases, probs, segs, tiles, ntiles, a_bs, b_bs, c_bs);
+                     lds, s, bases, probs, segs, tiles, ntiles, a_bs, b_bs, c_bs);
   return hipGetLastError();
 }
 

@@ -291,7 +291,8 @@ __device__ __forceinline__ void gemm_accum_direct(
 template <int P, int BM, int BN, int WM, int WN, typename TOut, int MODE>
 __device__ __forceinline__ void store_tile_direct(
     const typename PT<P>::AccV (&acc)[DirectCfg<P, BM, BN, WM, WN>::FM][DirectCfg<P, BM, BN, WM, WN>::FN],
-    TOut* __restrict__ Cp, int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0) {
+    TOut* __restrict__ Cp, int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0,
+    const int64_t* __restrict__ rows = nullptr) {
   using C = DirectCfg<P, BM, BN, WM, WN>;
   using Acc = typename PT<P>::Acc;
   const int tid = threadIdx.x;
@@ -309,7 +310,7 @@ __device__ __forceinline__ void store_tile_direct(
         const int64_t col = n0 + wn * C::TN + j * 16 + (lane & 15);
         if (full || (row < M && col < N)) {
           Acc v = acc[i][j][e];
-          TOut* p = Cp + row * ldc + col;
+          TOut* p = Cp + (rows ? rows[row] : row * ldc) + col;
           if constexpr (MODE == 1) {
             v += cvt<Acc>(*p);
             *p = cvt<TOut>(v);
@@ -322,11 +323,60 @@ __device__ __forceinline__ void store_tile_direct(
       }
 }
 
+// Store of a 2-byte direct tile through LDS: the accumulators are converted
+// into an LDS copy of the tile (rows padded by 16 bytes so that the four
+// row groups of a lane's column start in different banks), then every
+// thread writes whole 16-byte vectors of a row, so each row of the tile
+// leaves as one contiguous run instead of 32-byte pieces from several
+// waves.  Needs C rows 16-byte aligned (C, ldc and the column origin
+// multiples of 8) and N a multiple of 8; `lds` holds at least
+// EpiBytes<BM, BN> bytes and is free on entry and on return.
+template <int BM, int BN> constexpr int epi_bytes() { return BM * (BN + 8) * 2; }
+template <int P, int BM, int BN, int WM, int WN, typename TOut>
+__device__ __forceinline__ void store_tile_lds(
+    const typename PT<P>::AccV (&acc)[DirectCfg<P, BM, BN, WM, WN>::FM][DirectCfg<P, BM, BN, WM, WN>::FN],
+    TOut* __restrict__ Cp, int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0, char* lds) {
+  static_assert(sizeof(TOut) == 2, "2-byte outputs only");
+  using C = DirectCfg<P, BM, BN, WM, WN>;
+  constexpr int LD = BN + 8;
+  TOut* t = reinterpret_cast<TOut*>(lds);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  __syncthreads();  // every wave is done with the K loop's LDS stages
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = wm * C::TM + i * 16 + acc_row<P>(lane, e);
+        const int col = wn * C::TN + j * 16 + (lane & 15);
+        t[row * LD + col] = cvt<TOut>(acc[i][j][e]);
+      }
+  __syncthreads();
+  constexpr int VPR = BN / 8;               // 16-byte vectors per tile row
+  constexpr int RPP = C::THREADS / VPR;     // rows per pass
+  static_assert(C::THREADS % VPR == 0 && BM % RPP == 0, "epilogue passes");
+  const int rr = tid / VPR, cv = (tid % VPR) * 8;
+  const int64_t gc = n0 + cv;
+#pragma unroll 4
+  for (int r0 = 0; r0 < BM; r0 += RPP) {
+    const int r = r0 + rr;
+    const int64_t gr = m0 + r;
+    if (gr < M && gc < N)
+      *reinterpret_cast<uint4*>(Cp + gr * ldc + gc) = *reinterpret_cast<const uint4*>(t + r * LD + cv);
+  }
+  __syncthreads();  // the next tile's loads overwrite the LDS
+}
+
 // Write (or add to) the BM x BN tile at (m0, n0) of C (rows >= M or cols >= N skipped).
 template <int P, int BM, int BN, typename TOut>
 __device__ __forceinline__ void store_tile(
     const typename TileCfg<P, BM, BN>::AccV (&acc)[BM / 32][BN / 32], TOut* __restrict__ Cp,
-    int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0, bool accumulate) {
+    int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0, bool accumulate,
+    const int64_t* __restrict__ rows = nullptr) {
   using Acc = typename PT<P>::Acc;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -342,7 +392,7 @@ __device__ __forceinline__ void store_tile(
         const int64_t col = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
         if (row < M && col < N) {
           Acc v = acc[i][j][e];
-          TOut* p = Cp + row * ldc + col;
+          TOut* p = Cp + (rows ? rows[row] : row * ldc) + col;
           if (accumulate) v += cvt<Acc>(*p);
           *p = cvt<TOut>(v);
         }

@@ -44,6 +44,8 @@ struct GProb {     // one output problem (an output block, or a group of them)
   int32_t seg0;    // first segment index
   int32_t nseg;
   int32_t tiles_n; // column tiles
+  int32_t row0;    // >= 0: row r of C starts at bases->rows[row0 + r] (c_off, ldc unused)
+  int32_t pad;
 };
 struct GTile {     // one work item
   int32_t prob;
@@ -55,7 +57,8 @@ struct GBases {
   const void* A;
   const void* B;
   void* C;
-  const void* zero;  // >= 16 zero bytes (K tails of direct-to-LDS tiles)
+  const void* zero;    // >= 16 zero bytes (K tails of direct-to-LDS tiles)
+  const int64_t* rows; // row offsets of C for problems with row0 >= 0 (else unused)
 };
 // Persistent grouped launch: at most max_wg workgroups (0: one per tile)
 // stride over the tile list.  Tile config: 0 = 64x64, 1 = 128x128 (register
@@ -87,15 +90,15 @@ struct QnDevPtrs {
 };
 hipError_t qn_set_ptrs(QnDevPtrs* dst, QnDevPtrs v, hipStream_t s);
 // Per-block transpose with conversion: item i moves block `in` [rows][cols]
-// (row-major at in_off of psi + v * in_bs) to out_off of `out` + v * out_bs
-// as [cols][rows] with row stride ld_out (elements).
+// (row stride in_ld, at in_off of psi + v * in_bs) to out_off of `out` +
+// v * out_bs as [cols][rows] with row stride ld_out (elements).
 struct QnTBlock {
   int64_t in_off, out_off;
   int32_t rows, cols;
   int32_t ld_out;
   int32_t tiles_c;  // column tiles of 64
   int32_t tile0;    // first tile index of this block in the flat tile space
-  int32_t pad;
+  int32_t in_ld;
 };
 hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, void* out,
                               const QnTBlock* blocks, const int32_t* tile_block, int64_t ntiles,
@@ -111,22 +114,16 @@ struct QnCopy {
 };
 hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
                          const QnCopy* items, int64_t nitems, hipStream_t s);
-// Block-sparse W-stage: work item = (pair, first position of 256); positions
-// p = a' * db + b of the pair; rows and entries carry their own offsets and
-// a'-strides.
 // Block-sparse W-stage.  The entries of one (a'-sector, b-sector) pair are
 // stored row after row; the last entry of a row carries the row's Z offset,
 // and rows without W12 terms have one zero-weight entry, so every Z element
-// of the pair is written.  Each entry names its X input both directly (off,
-// astride) and as an index into the pair's list of distinct inputs.
+// of the pair is written.  The planner pads every b-sector of X and Z to a
+// multiple of 8 columns (db below is the padded width; X padding is zero)
+// and keeps every offset and stride a multiple of 8 elements, so the kernel
+// moves whole 16-byte vectors of V = 16 / sizeof(T) positions (a', b..b+V-1).
 struct QnWPair {
   int32_t e0, ne;       // entries of this pair
-  int32_t da, db;       // positions a' < da, b < db
-  int32_t in0, nin;     // distinct X inputs of this pair
-};
-struct QnWIn {
-  int64_t off;          // X offset of (a' = 0, b = 0)
-  int64_t astride;
+  int32_t da, db;       // positions a' < da, b < db (db a multiple of 8)
 };
 struct QnWEnt {
   int64_t off;          // X offset of (a' = 0, b = 0)
@@ -135,19 +132,18 @@ struct QnWEnt {
   int64_t zoff;         // Z offset of (a' = 0, b = 0) of the row (last entry of a row)
   int64_t zastride;     // 0 on entries that do not end a row
   int32_t end;          // 1 on the last entry of a row
-  int32_t in;           // index into the pair's inputs
+  int32_t pad;
 };
-constexpr int QN_WSTAGE_POS = 512;  // positions per item of the streaming kernel (2 per thread)
 struct QnWItem {
   int32_t pair;
-  int32_t p0;  // first position
+  int32_t v0;  // first vector (position v0 * V in a' * db + b order)
 };
-// staged = 64/128/256: items of that many positions; the pair's inputs for
-// them are loaded once into LDS (max_nin inputs at most); staged = 0: the
-// streaming kernel (QN_WSTAGE_POS positions per item, X read per entry).
-hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnWPair* pairs,
-                     const QnWIn* ins, const QnWEnt* ents, const QnWItem* items, int64_t nitems,
-                     int64_t x_bs, int64_t z_bs, int nv, int staged, int max_nin, hipStream_t s);
+// Work items of `per_item` vectors (64, 128, 256 or 512: up to 256 threads,
+// one or two vectors each); X and Z of batch v at v * x_bs, v * z_bs.
+// dtype: F64, F32 or BF16 (X and Z alike).
+hipError_t qn_wstage(int dtype, const void* X, void* Z, const QnWPair* pairs, const QnWEnt* ents,
+                     const QnWItem* items, int64_t nitems, int64_t x_bs, int64_t z_bs, int nv,
+                     int per_item, hipStream_t s);
 // Zero the listed output blocks (offsets, sizes) of out + v * bs.
 hipError_t qn_zero_blocks(int dtype, const QnPtrs* ptrs, const int64_t* offs, const int64_t* sizes,
                           int nblocks, int64_t bs, int nv, hipStream_t s);

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restr
 #pragma unroll 4
   for (int i = ty; i < 64; i += 4) {
     const int64_t r = r0 + i, c = c0 + tx;
-    if (r < bk.rows && c < bk.cols) tile[i][tx] = (TS)ip[r * bk.cols + c];
+    if (r < bk.rows && c < bk.cols) tile[i][tx] = (TS)ip[r * bk.in_ld + c];
   }
   __syncthreads();
 #pragma unroll 4
@@ -81,160 +81,115 @@ hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, v
 }
 
 // -------------------------------------------------------------- W-stage
-// Streaming variant (pairs with too many inputs for LDS): one workgroup per
-// item of QN_WSTAGE_POS positions (a', b) of a pair, two
-// per thread; the pair's entries are taken eight at a time, so every thread
-// has sixteen independent X loads in flight before it accumulates.
-template <typename TX, typename TZ>
-__global__ __launch_bounds__(256) void qn_wstage_kernel(const TX* __restrict__ X, TZ* __restrict__ Z,
-                                                         const QnWPair* __restrict__ pairs,
-                                                         const QnWEnt* __restrict__ ents,
-                                                         const QnWItem* __restrict__ items,
-                                                         int64_t x_bs, int64_t z_bs) {
-  using A = typename std::conditional<sizeof(TX) == 8, double, float>::type;
-  constexpr int NP = QN_WSTAGE_POS / 256;
+// Z[a', s1', s2', m2, b] = sum of coef * X[a', m0, s1, s2, b] over the W12
+// terms of the row (s1', s2', m2), one (a'-sector, b-sector) pair per work
+// item.  Thread t of an item takes vectors v0 + t + k * NT (k < NPV): V
+// consecutive b of one a', a 16-byte load per entry (the planner's padding
+// keeps every such vector aligned and inside its row).  Entries are taken
+// eight at a time, so every thread has 8 * NPV independent 16-byte loads in
+// flight before it accumulates; Z is written one 16-byte vector per row end.
+template <typename T> union QnVec {
+  static constexpr int V = 16 / (int)sizeof(T);
+  uint4 u;
+  T e[V];
+};
+
+template <typename T, int NT, int NPV>
+__global__ __launch_bounds__(NT) void qn_wstage_kernel(const T* __restrict__ X, T* __restrict__ Z,
+                                                        const QnWPair* __restrict__ pairs,
+                                                        const QnWEnt* __restrict__ ents,
+                                                        const QnWItem* __restrict__ items,
+                                                        int64_t x_bs, int64_t z_bs) {
+  using A = typename std::conditional<sizeof(T) == 8, double, float>::type;
+  constexpr int V = QnVec<T>::V;
   constexpr int NE = 8;
   const QnWItem it = items[blockIdx.x];
   const QnWPair pr = pairs[it.pair];
-  const int npos = pr.da * pr.db;
-  int64_t a[NP], b[NP];
-  bool ok[NP];
+  const int vrow = pr.db / V;  // vectors per a'-row
+  const int nvec = pr.da * vrow;
+  int64_t a[NPV], b[NPV];
+  bool ok[NPV];
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const int p = it.p0 + k * 256 + (int)threadIdx.x;
-    ok[k] = p < npos;
-    const int pp = ok[k] ? p : 0;  // position (0, 0) exists in every pair
-    a[k] = pp / pr.db;
-    b[k] = pp - a[k] * pr.db;
+  for (int k = 0; k < NPV; ++k) {
+    const int vi = it.v0 + k * NT + (int)threadIdx.x;
+    ok[k] = vi < nvec;
+    const int vv = ok[k] ? vi : 0;  // vector 0 exists in every pair
+    a[k] = vv / vrow;
+    b[k] = (int64_t)(vv - (int)a[k] * vrow) * V;
   }
   const int64_t v = blockIdx.y;
-  const TX* xv = X + v * x_bs;
-  TZ* zv = Z + v * z_bs;
+  const T* xv = X + v * x_bs;
+  T* zv = Z + v * z_bs;
   const QnWEnt* en = ents + pr.e0;
   const int ne = pr.ne;
-  A z[NP];
+  A z[NPV][V];
 #pragma unroll
-  for (int k = 0; k < NP; ++k) z[k] = 0;
+  for (int k = 0; k < NPV; ++k)
+#pragma unroll
+    for (int i = 0; i < V; ++i) z[k][i] = 0;
   for (int e0 = 0; e0 < ne; e0 += NE) {
     QnWEnt ec[NE];
-    A x[NE][NP];
+    QnVec<T> x[NE][NPV];
 #pragma unroll
     for (int j = 0; j < NE; ++j) ec[j] = en[e0 + j < ne ? e0 + j : ne - 1];
 #pragma unroll
     for (int j = 0; j < NE; ++j)
 #pragma unroll
-      for (int k = 0; k < NP; ++k) x[j][k] = (A)xv[ec[j].off + a[k] * ec[j].astride + b[k]];
+      for (int k = 0; k < NPV; ++k)
+        x[j][k].u = *reinterpret_cast<const uint4*>(xv + ec[j].off + a[k] * ec[j].astride + b[k]);
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
       if (e0 + j >= ne) break;
-      if (ec[j].coef != 0.0)  // zero-weight entries of rows without W12 terms add nothing
+      if (ec[j].coef != 0.0) {  // zero-weight entries of rows without W12 terms add nothing
+        const A c = (A)ec[j].coef;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) z[k] += (A)ec[j].coef * x[j][k];
+        for (int k = 0; k < NPV; ++k)
+#pragma unroll
+          for (int i = 0; i < V; ++i) z[k][i] += c * (A)x[j][k].e[i];
+      }
       if (ec[j].end) {
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          if (ok[k]) zv[ec[j].zoff + a[k] * ec[j].zastride + b[k]] = qconv<TZ>((double)z[k]);
-          z[k] = 0;
+        for (int k = 0; k < NPV; ++k) {
+          QnVec<T> o;
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            o.e[i] = (T)z[k][i];
+            z[k][i] = 0;
+          }
+          if (ok[k]) *reinterpret_cast<uint4*>(zv + ec[j].zoff + a[k] * ec[j].zastride + b[k]) = o.u;
         }
       }
     }
   }
 }
 
-// Staged variant: one workgroup of T threads per item of T positions.  The
-// pair's distinct X inputs for these positions are loaded once into LDS
-// ([input][position], each thread its own column, so no barrier), then the
-// entries index them; a dense W12 no longer re-reads X per entry.
-template <typename TX, typename TZ, int T>
-__global__ __launch_bounds__(T) void qn_wstage_staged_kernel(const TX* __restrict__ X,
-                                                              TZ* __restrict__ Z,
-                                                              const QnWPair* __restrict__ pairs,
-                                                              const QnWIn* __restrict__ ins,
-                                                              const QnWEnt* __restrict__ ents,
-                                                              const QnWItem* __restrict__ items,
-                                                              int64_t x_bs, int64_t z_bs) {
-  using A = typename std::conditional<sizeof(TX) == 8, double, float>::type;
-  constexpr int NE = 8;
-  extern __shared__ __align__(16) char lds_raw[];
-  A* xs = reinterpret_cast<A*>(lds_raw);
-  const int tid = threadIdx.x;
-  const QnWItem it = items[blockIdx.x];
-  const QnWPair pr = pairs[it.pair];
-  const int npos = pr.da * pr.db;
-  const int p = it.p0 + tid;
-  const bool ok = p < npos;
-  const int pp = ok ? p : 0;  // position (0, 0) exists in every pair
-  const int64_t a = pp / pr.db, b = pp - a * pr.db;
-  const int64_t v = blockIdx.y;
-  const TX* xv = X + v * x_bs;
-  TZ* zv = Z + v * z_bs;
-  const QnWIn* in = ins + pr.in0;
-#pragma unroll 4
-  for (int k = 0; k < pr.nin; ++k) xs[k * T + tid] = (A)xv[in[k].off + a * in[k].astride + b];
-  const QnWEnt* en = ents + pr.e0;
-  const int ne = pr.ne;
-  A z = 0;
-  for (int e0 = 0; e0 < ne; e0 += NE) {
-    QnWEnt ec[NE];
-    A x[NE];
-#pragma unroll
-    for (int j = 0; j < NE; ++j) ec[j] = en[e0 + j < ne ? e0 + j : ne - 1];
-#pragma unroll
-    for (int j = 0; j < NE; ++j) x[j] = xs[ec[j].in * T + tid];
-#pragma unroll
-    for (int j = 0; j < NE; ++j) {
-      if (e0 + j >= ne) break;
-      if (ec[j].coef != 0.0) z += (A)ec[j].coef * x[j];  // zero-weight entries add nothing
-      if (ec[j].end) {
-        if (ok) zv[ec[j].zoff + a * ec[j].zastride + b] = qconv<TZ>((double)z);
-        z = 0;
-      }
-    }
-  }
-}
-
-template <typename TX, typename TZ, int T>
-static hipError_t qn_wstage_staged_t(const void* X, void* Z, const QnWPair* pairs, const QnWIn* ins,
-                                     const QnWEnt* ents, const QnWItem* items, int64_t nitems,
-                                     int64_t x_bs, int64_t z_bs, int nv, int max_nin, hipStream_t s) {
-  const int lds = std::max(1, max_nin) * T * (int)sizeof(typename std::conditional<sizeof(TX) == 8, double, float>::type);
-  auto kern = qn_wstage_staged_kernel<TX, TZ, T>;
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, dim3((unsigned)nitems, (unsigned)nv), dim3(T), lds, s,
-                     static_cast<const TX*>(X), static_cast<TZ*>(Z), pairs, ins, ents, items, x_bs, z_bs);
-  return hipGetLastError();
-}
-
-template <typename TX, typename TZ>
-static hipError_t qn_wstage_t(const void* X, void* Z, const QnWPair* pairs, const QnWIn* ins,
-                              const QnWEnt* ents, const QnWItem* items, int64_t nitems, int64_t x_bs,
-                              int64_t z_bs, int nv, int staged, int max_nin, hipStream_t s) {
+template <typename T>
+static hipError_t qn_wstage_t(const void* X, void* Z, const QnWPair* pairs, const QnWEnt* ents,
+                              const QnWItem* items, int64_t nitems, int64_t x_bs, int64_t z_bs,
+                              int nv, int per_item, hipStream_t s) {
   if (nitems == 0 || nv == 0) return hipSuccess;
-  switch (staged) {
-    case 256: return qn_wstage_staged_t<TX, TZ, 256>(X, Z, pairs, ins, ents, items, nitems, x_bs, z_bs, nv, max_nin, s);
-    case 128: return qn_wstage_staged_t<TX, TZ, 128>(X, Z, pairs, ins, ents, items, nitems, x_bs, z_bs, nv, max_nin, s);
-    case 64: return qn_wstage_staged_t<TX, TZ, 64>(X, Z, pairs, ins, ents, items, nitems, x_bs, z_bs, nv, max_nin, s);
-    case 0: break;
+  const dim3 grid((unsigned)nitems, (unsigned)nv);
+  const T* x = static_cast<const T*>(X);
+  T* z = static_cast<T*>(Z);
+  switch (per_item) {
+    case 512: hipLaunchKernelGGL((qn_wstage_kernel<T, 256, 2>), grid, dim3(256), 0, s, x, z, pairs, ents, items, x_bs, z_bs); break;
+    case 256: hipLaunchKernelGGL((qn_wstage_kernel<T, 256, 1>), grid, dim3(256), 0, s, x, z, pairs, ents, items, x_bs, z_bs); break;
+    case 128: hipLaunchKernelGGL((qn_wstage_kernel<T, 128, 1>), grid, dim3(128), 0, s, x, z, pairs, ents, items, x_bs, z_bs); break;
+    case 64: hipLaunchKernelGGL((qn_wstage_kernel<T, 64, 1>), grid, dim3(64), 0, s, x, z, pairs, ents, items, x_bs, z_bs); break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL((qn_wstage_kernel<TX, TZ>), dim3((unsigned)nitems, (unsigned)nv), dim3(256), 0,
-                     s, static_cast<const TX*>(X), static_cast<TZ*>(Z), pairs, ents, items, x_bs, z_bs);
   return hipGetLastError();
 }
 
-hipError_t qn_wstage(int x_dtype, const void* X, int z_dtype, void* Z, const QnWPair* pairs,
-                     const QnWIn* ins, const QnWEnt* ents, const QnWItem* items, int64_t nitems,
-                     int64_t x_bs, int64_t z_bs, int nv, int staged, int max_nin, hipStream_t s) {
-#define ITN_QW(TX, TZ) return qn_wstage_t<TX, TZ>(X, Z, pairs, ins, ents, items, nitems, x_bs, z_bs, nv, staged, max_nin, s)
-  if (x_dtype == D_F64 && z_dtype == D_F64) ITN_QW(double, double);
-  if (x_dtype == D_F32 && z_dtype == D_F32) ITN_QW(float, float);
-  if (x_dtype == D_F32 && z_dtype == D_BF16) ITN_QW(float, bf16_t);
-  if (x_dtype == D_BF16 && z_dtype == D_BF16) ITN_QW(bf16_t, bf16_t);
-#undef ITN_QW
+hipError_t qn_wstage(int dtype, const void* X, void* Z, const QnWPair* pairs, const QnWEnt* ents,
+                     const QnWItem* items, int64_t nitems, int64_t x_bs, int64_t z_bs, int nv,
+                     int per_item, hipStream_t s) {
+  if ((x_bs | z_bs) & 7) return hipErrorInvalidValue;  // batch strides keep the 16-byte alignment
+  switch (dtype) {
+    case D_F64: return qn_wstage_t<double>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, s);
+    case D_F32: return qn_wstage_t<float>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, s);
+    case D_BF16: return qn_wstage_t<bf16_t>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, s);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -74,6 +74,20 @@ def zn_u1z4(seed=41, scale=1):
     return (L, w1, w2, R, psi), W1, W2
 
 
+def u1_degenerate_site(seed=67):
+    """U(1) (particle number only) operands whose site sectors hold more than
+    one state (the two singly occupied states share N = 1), so a psi block
+    has several (s1, s2) column runs per b; bond sectors are not multiples of
+    8.  Synthetic symmetric W (Gaussian on every allowed block)."""
+    bl = [((0,), 3), ((1,), 5), ((2,), 4)]
+    br = [((1,), 2), ((2,), 5), ((3,), 3), ((4,), 2)]
+    site = [(0,), (1,), (1,), (2,)]
+    link = [(0,), (1,), (-1,), (1,), (-1,), (0,)]
+    L, w1, w2, R, psi, W1, W2 = Q.heff_qn_operands_random_w(bl, br, site, link, (0,), seed,
+                                                            inp.block_values)
+    return (L, w1, w2, R, psi), W1, W2
+
+
 def small_u1u1z4(seed=53):
     """U(1) x U(1) x Z_4 operands: (dN, 2Sz, momentum mod 4) sectors of a
     small bond, the Hubbard momentum site basis, the w = 6 channel charges of
