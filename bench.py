@@ -519,6 +519,8 @@ def main():
     ap.add_argument("--qn-which", default="c3,c4,c4w38,c4z4",
                     help="block-sparse workloads of --qn-only (comma list)")
     ap.add_argument("--qn-prec", default="bf16,f64", help="precisions of --qn-only (comma list)")
+    ap.add_argument("--no-splitblocks", action="store_true",
+                    help="--qn-only without the one-sector-per-channel MPO legs")
     ap.add_argument("--dmrg-large", action="store_true",
                     help="with --dmrg-only: spin-1 chain N=40, cutoff 0, maxdim 256 then 1024 x 3 "
                          "(density matrices of up to 3072 rows)")
@@ -553,7 +555,7 @@ def main():
                 for prec in args.qn_prec.split(","):
                     log("[bench] QN %s %s nv=%d" % (which, prec, nv))
                     out["%s_%s" % (which, prec)] = time_qn(h, torch, np, inp, which, prec, nv, 10, 3)[0]
-                if which in ("c3", "c4") and "bf16" in args.qn_prec:
+                if which in ("c3", "c4") and "bf16" in args.qn_prec and not args.no_splitblocks:
                     log("[bench] QN %s bf16, one link sector per MPO channel" % which)
                     out["%s_bf16_splitblocks" % which] = time_qn(h, torch, np, inp, which, "bf16", nv, 10,
                                                                  3, split_mpo=True)[0]

@@ -167,23 +167,24 @@ static hipError_t launch_nt(const GemmArgs& g, hipStream_t s) {
 template <int P, int BM, int BN, int WM, int WN, typename TOut>
 static hipError_t launch_nt_direct(const GemmArgs& g, hipStream_t s) {
   using Cfg = DirectCfg<P, BM, BN, WM, WN>;
+  constexpr int LDS = Cfg::LDS_BYTES;
   const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
   dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)g.batch);
   static const hipError_t attr =
-      (allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 0>, Cfg::LDS_BYTES) != hipSuccess ||
-       allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 1>, Cfg::LDS_BYTES) != hipSuccess)
+      (allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 0>, LDS) != hipSuccess ||
+       allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 1>, LDS) != hipSuccess)
           ? hipErrorInvalidValue
-          : allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 2>, Cfg::LDS_BYTES);
+          : allow_lds(gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 2>, LDS);
   if (attr != hipSuccess) return attr;
   if (g.accumulate)
     hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 1>), grid,
-                       dim3(Cfg::THREADS), Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
+                       dim3(Cfg::THREADS), LDS, s, g, tiles_m, tiles_n);
   else if (g.stream)
     hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 2>), grid,
-                       dim3(Cfg::THREADS), Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
+                       dim3(Cfg::THREADS), LDS, s, g, tiles_m, tiles_n);
   else
     hipLaunchKernelGGL((gemm_nt_direct_kernel<P, BM, BN, WM, WN, TOut, 0>), grid,
-                       dim3(Cfg::THREADS), Cfg::LDS_BYTES, s, g, tiles_m, tiles_n);
+                       dim3(Cfg::THREADS), LDS, s, g, tiles_m, tiles_n);
   return hipGetLastError();
 }
 
@@ -284,8 +285,8 @@ static hipError_t launch_grouped_direct(const GBases* bases, const GProb* probs,
   int64_t g = ntiles;
   if (max_wg > 0 && g > max_wg) g = max_wg;
   dim3 grid((unsigned)g, (unsigned)nbatch);
-  constexpr int lds = sizeof(TOut) == 2 && epi_bytes<BM, BN>() > Cfg::LDS_BYTES ? epi_bytes<BM, BN>()
-                                                                                 : Cfg::LDS_BYTES;
+  constexpr int main_lds = Cfg::LDS_BYTES;
+  constexpr int lds = sizeof(TOut) == 2 && epi_bytes<BM, BN>() > main_lds ? epi_bytes<BM, BN>() : main_lds;
   static const hipError_t attr = allow_lds(gemm_grouped_direct_kernel<P, BM, BN, WM, WN, TOut>, lds);
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL((gemm_grouped_direct_kernel<P, BM, BN, WM, WN, TOut>), grid, dim3(Cfg::THREADS),
@@ -304,6 +305,7 @@ static hipError_t grouped_cfg(int cfg, const GBases* bases, const GProb* probs, 
     else return launch_grouped_direct<P, 256, 256, 2, 4, TOut>(ITN_GROUPED_ARGS);
   }
   if (cfg == 3) return launch_grouped_direct<P, 128, 128, 2, 2, TOut>(ITN_GROUPED_ARGS);
+  if (cfg == 4) return launch_grouped_direct<P, 256, 64, 4, 1, TOut>(ITN_GROUPED_ARGS);
   if (cfg == 1) return launch_grouped<P, 128, 128, TOut>(ITN_GROUPED_ARGS);
   return launch_grouped<P, 64, 64, TOut>(ITN_GROUPED_ARGS);
 }
@@ -333,9 +335,12 @@ hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const GBases* bases
 }
 #undef ITN_GROUPED_ARGS
 
-int grouped_tile_rows(int tile_cfg) { return tile_cfg == 2 ? 256 : (tile_cfg == 1 || tile_cfg == 3) ? 128 : 64; }
+int grouped_tile_rows(int tile_cfg) {
+  return (tile_cfg == 2 || tile_cfg == 4) ? 256 : (tile_cfg == 1 || tile_cfg == 3) ? 128 : 64;
+}
 int grouped_tile_cols(int prec, int tile_cfg) {
   if (tile_cfg == 2) return prec == P_F64 ? 128 : 256;
+  if (tile_cfg == 4) return 64;
   return grouped_tile_rows(tile_cfg);
 }
 

@@ -63,9 +63,9 @@ struct GBases {
 // Persistent grouped launch: at most max_wg workgroups (0: one per tile)
 // stride over the tile list.  Tile config: 0 = 64x64, 1 = 128x128 (register
 // staged, any alignment); 2 = direct-to-LDS 8-wave tiles (256x256, FP64
-// 256x128), 3 = direct-to-LDS 4-wave 128x128 tiles; 2 and 3 need 16-byte
-// aligned operand rows that are zero up to K rounded to 16 bytes, and
-// bases->zero.  Batch b (grid.y) offsets A, B and
+// 256x128), 3 = direct-to-LDS 4-wave 128x128 tiles, 4 = direct-to-LDS
+// 4-wave 256x64 tiles (narrow products); 2, 3 and 4 need 16-byte aligned
+// operand rows that are zero up to K rounded to 16 bytes, and bases->zero.  Batch b (grid.y) offsets A, B and
 // C by b times their batch strides.
 hipError_t gemm_grouped(int prec, int c_dtype, int tile_cfg, const GBases* bases, const GProb* probs,
                         const GSeg* segs, const GTile* tiles, int64_t ntiles, int64_t a_batch_stride,

@@ -202,12 +202,15 @@ def test_zn_three_component_parity(h, prec, nv):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-def test_qn_launch_modes_parity(h, monkeypatch, prec):
-    """Every grouped launch mode, forced, against the oracle on sectors of a
-    few hundred states (ragged M, N, K: the 256-tile path with K tails)."""
-    ops, W1, W2 = U.large_u1()
+@pytest.mark.parametrize("which", ["large_u1", "zn_u1z4_x20"])
+def test_qn_launch_modes_parity(h, monkeypatch, prec, which):
+    """Every grouped launch mode, forced, against the oracle: sectors of a
+    few hundred states (ragged M, N, K: the 256-tile path with K tails), and
+    U(1) x Z_4 sectors of 20-60 states, whose Z x R products are narrow
+    (N < 96 on the 256 x 64 tiles of mode 6)."""
+    ops, W1, W2 = U.large_u1() if which == "large_u1" else U.zn_u1z4(scale=20)
     ref = _ref(ops, [ops[4]])
-    for mode in ("0,0", "1,1", "2,2", "3,3", "2,3", "3,2", "4,4", "5,5", "4,5"):
+    for mode in ("0,0", "1,1", "2,2", "3,3", "2,3", "3,2", "4,4", "5,5", "4,5", "6,6", "5,6"):
         monkeypatch.setenv("ITN_QN_TILE_MODE", mode)
         plan, _, got = _run(h, ops, W1, W2, prec, 1, [ops[4]])
         assert plan.info()["n_tiles"] > 0
