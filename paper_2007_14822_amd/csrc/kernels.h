@@ -59,6 +59,8 @@ struct GBases {
   void* C;
   const void* zero;    // >= 16 zero bytes (K tails of direct-to-LDS tiles)
   const int64_t* rows; // row offsets of C for problems with row0 >= 0 (else unused)
+  int32_t stream;      // non-zero: C (2-byte) is written with nontemporal stores
+  int32_t pad;
 };
 // Persistent grouped launch: at most max_wg workgroups (0: one per tile)
 // stride over the tile list.  Tile config: 0 = 64x64, 1 = 128x128 (register

@@ -156,7 +156,8 @@ __global__ __launch_bounds__(NT) void qn_wstage_kernel(const T* __restrict__ X, 
             o.e[i] = (T)z[k][i];
             z[k][i] = 0;
           }
-          if (ok[k]) *reinterpret_cast<uint4*>(zv + ec[j].zoff + a[k] * ec[j].zastride + b[k]) = o.u;
+          if (ok[k])
+            *reinterpret_cast<uint4*>(zv + ec[j].zoff + a[k] * ec[j].zastride + b[k]) = o.u;
         }
       }
     }
