@@ -273,8 +273,8 @@ typedef struct {
   double flops_wstage;     /* 2 * W12 terms * positions, x nv (not in flops)      */
   int32_t mode_stage1;     /* grouped launch modes of stages 1 and 4 (0..6, see   */
   int32_t mode_stage4;     /* itn_qn_heff_apply); -1 before the first apply       */
-  int32_t wstage_tile;     /* W-stage work item: 16-byte vectors per workgroup    */
-                           /* (64, 128, 256 or 512); -1 before the first apply    */
+  int32_t wstage_tile;     /* W-stage work item: 16-byte vectors per wave (64,    */
+                           /* 128 or 256); -1 before the first apply              */
   double flops_stage1;     /* the part of `flops` in the L*psi stage (the rest is   */
                            /* the Z*R stage)                                         */
 } itn_plan_info;

@@ -196,10 +196,10 @@ struct itn_plan {
   int64_t tb_tiles = 0;
   std::vector<QnWPair> wp;
   std::vector<QnWEnt> we;
-  // W-stage kernel candidates: work items of 256, 512 (two per thread), 128
-  // or 64 vectors; one item list each, the autotuner picks wsel.
-  static constexpr int kWNum = 4;
-  static constexpr int kWCand[kWNum] = {256, 512, 128, 64};
+  // W-stage kernel candidates: work items (one wave each) of 64, 128 or 256
+  // vectors; one item list each, the autotuner picks wsel.
+  static constexpr int kWNum = 3;
+  static constexpr int kWCand[kWNum] = {64, 128, 256};
   std::vector<QnWItem> wi[kWNum];
   int wsel = 0;
   std::vector<int64_t> rows4;  // stage-4 row table: output offset of every product row
@@ -220,7 +220,7 @@ struct itn_plan {
   int32_t* dtbi = nullptr;
   QnWPair* dwp = nullptr;
   QnWEnt* dwe = nullptr;
-  QnWItem* dwi[kWNum] = {nullptr, nullptr, nullptr, nullptr};
+  QnWItem* dwi[kWNum] = {nullptr, nullptr, nullptr};
   int64_t* drows4 = nullptr;
   QnCopy* dcp = nullptr;
   int64_t* dzoff = nullptr;
@@ -865,21 +865,24 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
 
 constexpr int MAX_WG = 1024;  // persistent grouped launches: at most 4 workgroups per CU
 
-// X goes out with nontemporal stores when it is larger than half of the
-// 256 MiB last-level cache: then the W-stage reads it from HBM anyway, and
-// the stores should not displace stage 1's operands (measured on the
-// cylinder bond, 1 GiB of X: stage 1 0.58 -> 0.52 ms; on the 86 MB chain
-// bond X stays cached for the W-stage).
+// X and Z go out with nontemporal stores when they are larger than half of
+// the 256 MiB last-level cache: the next pass reads them from HBM anyway,
+// and the stores then do not displace the operands that stay cached
+// between applies (L, R, psi).  Smaller ones (the 86 MB chain bond) stay
+// cached for the pass that reads them.
+int32_t big_for_cache(double bytes) { return bytes > 128.0 * 1024 * 1024 ? 1 : 0; }
 int32_t x_stream(const itn_plan& pl) {
-  const double bytes = (double)pl.nv * (double)pl.X_elems * dtype_size(pl.xt);
-  return bytes > 128.0 * 1024 * 1024 ? 1 : 0;
+  return big_for_cache((double)pl.nv * (double)pl.X_elems * dtype_size(pl.xt));
+}
+int32_t z_stream(const itn_plan& pl) {
+  return big_for_cache((double)pl.nv * (double)pl.Z_elems * dtype_size(pl.pt));
 }
 
 // The launches of one apply (after the operand pointers are set).
 // The W-stage with kernel candidate c.
 hipError_t wstage_launch(itn_plan& pl, int c, hipStream_t s) {
   return qn_wstage(pl.xt, pl.X, pl.Z, pl.dwp, pl.dwe, pl.dwi[c], (int64_t)pl.wi[c].size(),
-                   pl.X_elems, pl.Z_elems, pl.nv, itn_plan::kWCand[c], s);
+                   pl.X_elems, pl.Z_elems, pl.nv, itn_plan::kWCand[c], z_stream(pl), s);
 }
 
 // One grouped stage (0: stage 1, 1: stage 4) in launch mode `mode`.
@@ -950,7 +953,7 @@ itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int 
 
 // Pick the faster tile per grouped stage by timing both on the real operands.
 itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
-  // ITN_QN_WSTAGE=64|128|256|512 fixes the W-stage work item (vectors)
+  // ITN_QN_WSTAGE=64|128|256 fixes the W-stage work item (vectors)
   int wforce = -1;
   if (const char* f = std::getenv("ITN_QN_WSTAGE")) {
     const int t = std::atoi(f);

@@ -120,9 +120,14 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_grouped_direct_kernel(
       // whole-row 16-byte stores through LDS where C's rows are aligned (uniform per problem)
       if (!rows && ((pr.c_off | pr.ldc | pr.N | c_bs) & 7) == 0 &&
           (reinterpret_cast<uintptr_t>(Cbase) & 15) == 0) {
-        store_tile_lds<P, BM, BN, WM, WN, TOut>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc, pr.M,
-                                                pr.N, (int64_t)t.tm * BM, (int64_t)t.tn * BN, lds,
-                                                bases->stream != 0);
+        if (bases->stream)
+          store_tile_lds<P, BM, BN, WM, WN, TOut, true>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc,
+                                                        pr.M, pr.N, (int64_t)t.tm * BM,
+                                                        (int64_t)t.tn * BN, lds);
+        else
+          store_tile_lds<P, BM, BN, WM, WN, TOut, false>(acc, Cbase + pr.c_off + batch * c_bs, pr.ldc,
+                                                         pr.M, pr.N, (int64_t)t.tm * BM,
+                                                         (int64_t)t.tn * BN, lds);
         continue;
       }
     }

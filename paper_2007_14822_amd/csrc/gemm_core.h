@@ -330,16 +330,15 @@ __device__ __forceinline__ void store_tile_direct(
 // leaves as one contiguous run instead of 32-byte pieces from several
 // waves.  Needs C rows 16-byte aligned (C, ldc and the column origin
 // multiples of 8) and N a multiple of 8; `lds` holds at least
-// EpiBytes<BM, BN> bytes and is free on entry and on return.  `stream`:
+// EpiBytes<BM, BN> bytes and is free on entry and on return.  STREAM:
 // nontemporal stores (C is read once by a later pass and does not fit the
 // caches; the stores then do not displace the operands' lines).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <int BM, int BN> constexpr int epi_bytes() { return BM * (BN + 8) * 2; }
-template <int P, int BM, int BN, int WM, int WN, typename TOut>
+template <int P, int BM, int BN, int WM, int WN, typename TOut, bool STREAM>
 __device__ __forceinline__ void store_tile_lds(
     const typename PT<P>::AccV (&acc)[DirectCfg<P, BM, BN, WM, WN>::FM][DirectCfg<P, BM, BN, WM, WN>::FN],
-    TOut* __restrict__ Cp, int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0, char* lds,
-    bool stream) {
+    TOut* __restrict__ Cp, int64_t ldc, int64_t M, int64_t N, int64_t m0, int64_t n0, char* lds) {
   static_assert(sizeof(TOut) == 2, "2-byte outputs only");
   using C = DirectCfg<P, BM, BN, WM, WN>;
   constexpr int LD = BN + 8;
@@ -372,7 +371,7 @@ __device__ __forceinline__ void store_tile_lds(
     if (gr < M && gc < N) {
       const u32x4 v = *reinterpret_cast<const u32x4*>(t + r * LD + cv);
       u32x4* dst = reinterpret_cast<u32x4*>(Cp + gr * ldc + gc);
-      if (stream) __builtin_nontemporal_store(v, dst);
+      if constexpr (STREAM) __builtin_nontemporal_store(v, dst);
       else *dst = v;
     }
   }

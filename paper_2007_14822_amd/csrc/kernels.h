@@ -140,12 +140,13 @@ struct QnWItem {
   int32_t pair;
   int32_t v0;  // first vector (position v0 * V in a' * db + b order)
 };
-// Work items of `per_item` vectors (64, 128, 256 or 512: up to 256 threads,
-// one or two vectors each); X and Z of batch v at v * x_bs, v * z_bs.
+// Work items of `per_item` vectors (64, 128 or 256), one wave each (one,
+// two or four vectors per lane), four per workgroup; X and Z of batch v at
+// v * x_bs, v * z_bs; stream != 0: Z written with nontemporal stores.
 // dtype: F64, F32 or BF16 (X and Z alike).
 hipError_t qn_wstage(int dtype, const void* X, void* Z, const QnWPair* pairs, const QnWEnt* ents,
                      const QnWItem* items, int64_t nitems, int64_t x_bs, int64_t z_bs, int nv,
-                     int per_item, hipStream_t s);
+                     int per_item, int stream, hipStream_t s);
 // Zero the listed output blocks (offsets, sizes) of out + v * bs.
 hipError_t qn_zero_blocks(int dtype, const QnPtrs* ptrs, const int64_t* offs, const int64_t* sizes,
                           int nblocks, int64_t bs, int nv, hipStream_t s);

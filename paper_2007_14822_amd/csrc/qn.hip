@@ -82,28 +82,36 @@ hipError_t qn_block_transpose(int in_dtype, const QnPtrs* ptrs, int out_dtype, v
 
 // -------------------------------------------------------------- W-stage
 // Z[a', s1', s2', m2, b] = sum of coef * X[a', m0, s1, s2, b] over the W12
-// terms of the row (s1', s2', m2), one (a'-sector, b-sector) pair per work
-// item.  Thread t of an item takes vectors v0 + t + k * NT (k < NPV): V
-// consecutive b of one a', a 16-byte load per entry (the planner's padding
-// keeps every such vector aligned and inside its row).  Entries are taken
-// eight at a time, so every thread has 8 * NPV independent 16-byte loads in
-// flight before it accumulates; Z is written one 16-byte vector per row end.
+// terms of the row (s1', s2', m2), for one (a'-sector, b-sector) pair per
+// work item.  A work item is one wave: lane l takes vectors v0 + l + 64 k
+// (k < NPV), each V consecutive b of one a' (the planner's padding keeps
+// every such vector aligned and inside its row), one 16-byte load per entry.
+// A workgroup runs four independent items, so a pair of a few dozen vectors
+// occupies one wave instead of a whole workgroup.  Entries are taken NE at
+// a time, so every lane has NE * NPV independent 16-byte loads in flight
+// before it accumulates; Z is written one 16-byte vector per row end, with
+// nontemporal stores when `stream` is set (Z larger than the caches).
+typedef unsigned int qn_u32x4 __attribute__((ext_vector_type(4)));
 template <typename T> union QnVec {
   static constexpr int V = 16 / (int)sizeof(T);
   uint4 u;
   T e[V];
 };
 
-template <typename T, int NT, int NPV>
-__global__ __launch_bounds__(NT) void qn_wstage_kernel(const T* __restrict__ X, T* __restrict__ Z,
+template <typename T, int NPV, int NE, bool STREAM>
+__global__ __launch_bounds__(256) void qn_wstage_kernel(const T* __restrict__ X, T* __restrict__ Z,
                                                         const QnWPair* __restrict__ pairs,
                                                         const QnWEnt* __restrict__ ents,
                                                         const QnWItem* __restrict__ items,
-                                                        int64_t x_bs, int64_t z_bs) {
+                                                        int64_t nitems, int64_t x_bs, int64_t z_bs) {
   using A = typename std::conditional<sizeof(T) == 8, double, float>::type;
   constexpr int V = QnVec<T>::V;
-  constexpr int NE = 8;
-  const QnWItem it = items[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  // the item index is uniform over the wave: readfirstlane makes that
+  // explicit, so the item, pair and entry records are scalar loads
+  const int64_t item = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (item >= nitems) return;  // the whole wave
+  const QnWItem it = items[item];
   const QnWPair pr = pairs[it.pair];
   const int vrow = pr.db / V;  // vectors per a'-row
   const int nvec = pr.da * vrow;
@@ -111,7 +119,7 @@ __global__ __launch_bounds__(NT) void qn_wstage_kernel(const T* __restrict__ X, 
   bool ok[NPV];
 #pragma unroll
   for (int k = 0; k < NPV; ++k) {
-    const int vi = it.v0 + k * NT + (int)threadIdx.x;
+    const int vi = it.v0 + k * 64 + lane;
     ok[k] = vi < nvec;
     const int vv = ok[k] ? vi : 0;  // vector 0 exists in every pair
     a[k] = vv / vrow;
@@ -156,8 +164,13 @@ __global__ __launch_bounds__(NT) void qn_wstage_kernel(const T* __restrict__ X, 
             o.e[i] = (T)z[k][i];
             z[k][i] = 0;
           }
-          if (ok[k])
-            *reinterpret_cast<uint4*>(zv + ec[j].zoff + a[k] * ec[j].zastride + b[k]) = o.u;
+          if (ok[k]) {
+            T* dst = zv + ec[j].zoff + a[k] * ec[j].zastride + b[k];
+            if constexpr (STREAM)
+              __builtin_nontemporal_store(__builtin_bit_cast(qn_u32x4, o.u), reinterpret_cast<qn_u32x4*>(dst));
+            else
+              *reinterpret_cast<uint4*>(dst) = o.u;
+          }
         }
       }
     }
@@ -167,29 +180,38 @@ __global__ __launch_bounds__(NT) void qn_wstage_kernel(const T* __restrict__ X, 
 template <typename T>
 static hipError_t qn_wstage_t(const void* X, void* Z, const QnWPair* pairs, const QnWEnt* ents,
                               const QnWItem* items, int64_t nitems, int64_t x_bs, int64_t z_bs,
-                              int nv, int per_item, hipStream_t s) {
+                              int nv, int per_item, int stream, hipStream_t s) {
   if (nitems == 0 || nv == 0) return hipSuccess;
-  const dim3 grid((unsigned)nitems, (unsigned)nv);
+  const dim3 grid((unsigned)((nitems + 3) / 4), (unsigned)nv);
   const T* x = static_cast<const T*>(X);
   T* z = static_cast<T*>(Z);
+#define ITN_QW(NPV, NE)                                                                             \
+  do {                                                                                              \
+    if (stream)                                                                                     \
+      hipLaunchKernelGGL((qn_wstage_kernel<T, NPV, NE, true>), grid, dim3(256), 0, s, x, z, pairs,   \
+                         ents, items, nitems, x_bs, z_bs);                                          \
+    else                                                                                            \
+      hipLaunchKernelGGL((qn_wstage_kernel<T, NPV, NE, false>), grid, dim3(256), 0, s, x, z, pairs,  \
+                         ents, items, nitems, x_bs, z_bs);                                          \
+  } while (0)
   switch (per_item) {
-    case 512: hipLaunchKernelGGL((qn_wstage_kernel<T, 256, 2>), grid, dim3(256), 0, s, x, z, pairs, ents, items, x_bs, z_bs); break;
-    case 256: hipLaunchKernelGGL((qn_wstage_kernel<T, 256, 1>), grid, dim3(256), 0, s, x, z, pairs, ents, items, x_bs, z_bs); break;
-    case 128: hipLaunchKernelGGL((qn_wstage_kernel<T, 128, 1>), grid, dim3(128), 0, s, x, z, pairs, ents, items, x_bs, z_bs); break;
-    case 64: hipLaunchKernelGGL((qn_wstage_kernel<T, 64, 1>), grid, dim3(64), 0, s, x, z, pairs, ents, items, x_bs, z_bs); break;
+    case 64: ITN_QW(1, 8); break;
+    case 128: ITN_QW(2, 8); break;
+    case 256: ITN_QW(4, 4); break;
     default: return hipErrorInvalidValue;
   }
+#undef ITN_QW
   return hipGetLastError();
 }
 
 hipError_t qn_wstage(int dtype, const void* X, void* Z, const QnWPair* pairs, const QnWEnt* ents,
                      const QnWItem* items, int64_t nitems, int64_t x_bs, int64_t z_bs, int nv,
-                     int per_item, hipStream_t s) {
+                     int per_item, int stream, hipStream_t s) {
   if ((x_bs | z_bs) & 7) return hipErrorInvalidValue;  // batch strides keep the 16-byte alignment
   switch (dtype) {
-    case D_F64: return qn_wstage_t<double>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, s);
-    case D_F32: return qn_wstage_t<float>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, s);
-    case D_BF16: return qn_wstage_t<bf16_t>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, s);
+    case D_F64: return qn_wstage_t<double>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, stream, s);
+    case D_F32: return qn_wstage_t<float>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, stream, s);
+    case D_BF16: return qn_wstage_t<bf16_t>(X, Z, pairs, ents, items, nitems, x_bs, z_bs, nv, per_item, stream, s);
   }
   return hipErrorInvalidValue;
 }
