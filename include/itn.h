@@ -271,7 +271,7 @@ typedef struct {
                            /* to a multiple of 8)                                 */
   int64_t z_elems;         /* W-stage output Z (stage-4 operand), per vector, ditto */
   double flops_wstage;     /* 2 * W12 terms * positions, x nv (not in flops)      */
-  int32_t mode_stage1;     /* grouped launch modes of stages 1 and 4 (0..6, see   */
+  int32_t mode_stage1;     /* grouped launch modes of stages 1 and 4 (0..7, see   */
   int32_t mode_stage4;     /* itn_qn_heff_apply); -1 before the first apply       */
   int32_t wstage_tile;     /* W-stage work item: 16-byte vectors per wave (64,    */
                            /* 128 or 256); -1 before the first apply              */
@@ -302,9 +302,10 @@ itn_status itn_qn_allowed_blocks(itn_handle* h, const itn_tensor* t, int64_t* nb
  * on 64 / 128; 4: as 2, with the remaining products of both extents >= 96
  * on 128x128 direct-to-LDS tiles; 5: products of both extents >= 96 on
  * 128x128 direct-to-LDS tiles, the rest on 64; 6: as 5, with the products
- * of M >= 96 and N < 96 on 256x64 direct-to-LDS tiles).  The choice is
- * cached per operand structure (in the file ITN_AUTOTUNE_CACHE if set);
- * ITN_QN_TILE_MODE="m1,m4" (modes 0..6) fixes it instead.
+ * of M >= 96 and N < 96 on 256x64 direct-to-LDS tiles; 7: as 4, with those
+ * narrow products on 256x64 direct-to-LDS tiles).  The choice is cached per
+ * operand structure (in the file ITN_AUTOTUNE_CACHE if set);
+ * ITN_QN_TILE_MODE="m1,m4" (modes 0..7) fixes it instead.
  * L == NULL and R == NULL apply with the environments of the last
  * itn_qn_prepare_env (or of the last apply that passed them) without
  * repacking them again (ITN_E_ARG if there are none); passing only one of

@@ -165,10 +165,10 @@ struct itn_plan {
   // midall: every problem with both extents >= 96 on the 128x128 direct
   // tile, rest_midall: the others (64x64); narrow: problems with M >= 96
   // and N < 96 on the 4-wave 256x64 direct tile, rest_nar: what neither
-  // midall nor narrow takes (64x64).  Launch modes: 0, 1 = all[mode];
-  // 2, 3 = big then rest[mode - 2]; 4 = big, mid, rest_mid; 5 = midall,
-  // rest_midall; 6 = midall, narrow, rest_nar.
-  static constexpr int kModes = 7;
+  // midall (= big + mid) nor narrow takes (64x64).  Launch modes: 0, 1 = all[mode]; 2, 3 = big then
+  // rest[mode - 2]; 4 = big, mid, rest_mid; 5 = midall, rest_midall;
+  // 6 = midall, narrow, rest_nar; 7 = big, mid, narrow, rest_nar.
+  static constexpr int kModes = 8;
   struct Tiles {
     std::vector<GTile> all[2], big, rest[2], mid, rest_mid, midall, rest_midall, narrow, rest_nar;
     GTile *d_all[2] = {nullptr, nullptr}, *d_big = nullptr, *d_rest[2] = {nullptr, nullptr};
@@ -180,7 +180,8 @@ struct itn_plan {
         case 2: case 3: return big.size() + rest[mode - 2].size();
         case 4: return big.size() + mid.size() + rest_mid.size();
         case 5: return midall.size() + rest_midall.size();
-        default: return midall.size() + narrow.size() + rest_nar.size();
+        case 6: return midall.size() + narrow.size() + rest_nar.size();
+        default: return big.size() + mid.size() + narrow.size() + rest_nar.size();
       }
     }
     bool usable(int mode) const {
@@ -188,6 +189,7 @@ struct itn_plan {
       if (mode == 4) return !big.empty() && !mid.empty();
       if (mode == 5) return !midall.empty();
       if (mode == 6) return !narrow.empty();
+      if (mode == 7) return !big.empty() && !narrow.empty();
       return true;
     }
   } tl1, tl4;
@@ -281,30 +283,72 @@ void add_copy(std::vector<QnCopy>& v, int64_t in_off, int64_t out_off, int rows,
   }
 }
 
-// Tile list (bm x bn tiles) over the problems `use` selects, largest K-work
-// first, each problem's tiles row panel by row panel.  (Placing the column
-// tiles of a panel on one XCD, eight panels at a time, measured slower on
-// the cylinder bond: 1.97 against 1.92 ms per apply.)
+// Tile list (bm x bn tiles) over the problems `use` selects, each run of
+// row panels on one XCD.  The persistent launch runs list position i on XCD
+// i % 8 (workgroups go to the XCDs in turn; the grid and the list are
+// multiples of 8), so the list interleaves eight queues: products are cut
+// into runs of row panels of at most 1/32 of the total work, the runs are
+// dealt to the XCDs largest first, each to the least loaded one, and a
+// queue holds its runs' tiles row panel by row panel.  The tiles of a run
+// share one L2, which serves its operand panels to every tile after the
+// first instead of each XCD fetching them again (stage 1 of the cylinder
+// bond read its operands about ten times over from beyond the L2 with the
+// tiles spread over all XCDs).  Queues shorter than the longest are padded
+// with empty tiles (prob = -1).
 std::vector<GTile> make_tiles(const std::vector<GProb>& probs, const std::vector<GSeg>& segs, int bm,
                               int bn, const std::vector<char>& use) {
-  std::vector<std::pair<int64_t, int>> order;  // (K work, problem)
+  struct Job {
+    int64_t work;  // tiles x K
+    int p;
+  };
+  std::vector<Job> jobs;
   for (size_t p = 0; p < probs.size(); ++p) {
     if (!use[p]) continue;
     int64_t k = 0;
     for (int s = 0; s < probs[p].nseg; ++s) k += segs[probs[p].seg0 + s].K;
-    order.push_back({k, (int)p});
+    const int64_t t = (int64_t)((probs[p].M + bm - 1) / bm) * ((probs[p].N + bn - 1) / bn);
+    jobs.push_back({t * k, (int)p});
   }
-  std::stable_sort(order.begin(), order.end(),
-                   [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& b) {
-                     return a.first > b.first;
-                   });
+  constexpr int NX = 8;
+  // products larger than 1/32 of the total are cut into runs of row panels
+  // of at most that size (so that eight queues can balance), each run a job
+  int64_t total = 0;
+  for (const Job& j : jobs) total += j.work;
+  const int64_t cap = std::max<int64_t>(1, total / (4 * NX));
+  struct Run {
+    int64_t work;
+    int p, i0, i1;  // row panels [i0, i1)
+  };
+  std::vector<Run> runs;
+  for (const Job& j : jobs) {
+    const GProb& pr = probs[j.p];
+    const int tm = (pr.M + bm - 1) / bm;
+    const int64_t per_panel = j.work / tm;
+    const int step = (int)std::max<int64_t>(1, cap / std::max<int64_t>(1, per_panel));
+    for (int i0 = 0; i0 < tm; i0 += step) {
+      const int i1 = std::min(tm, i0 + step);
+      runs.push_back({per_panel * (i1 - i0), j.p, i0, i1});
+    }
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.work > b.work; });
+  std::vector<GTile> q[NX];
+  int64_t load[NX] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (const Run& r : runs) {
+    int x = 0;
+    for (int y = 1; y < NX; ++y)
+      if (load[y] < load[x]) x = y;
+    load[x] += r.work;
+    const int tn = (probs[r.p].N + bn - 1) / bn;
+    for (int i = r.i0; i < r.i1; ++i)
+      for (int c = 0; c < tn; ++c) q[x].push_back(GTile{r.p, i, c, 0});
+  }
+  size_t len = 0;
+  for (int x = 0; x < NX; ++x) len = std::max(len, q[x].size());
   std::vector<GTile> out;
-  for (auto& o : order) {
-    const GProb& pr = probs[o.second];
-    const int tm = (pr.M + bm - 1) / bm, tn = (pr.N + bn - 1) / bn;
-    for (int i = 0; i < tm; ++i)
-      for (int j = 0; j < tn; ++j) out.push_back(GTile{o.second, i, j, 0});
-  }
+  out.reserve(len * NX);
+  const GTile none{-1, 0, 0, 0};
+  for (size_t k = 0; k < len; ++k)
+    for (int x = 0; x < NX; ++x) out.push_back(k < q[x].size() ? q[x][k] : none);
   return out;
 }
 
@@ -915,6 +959,11 @@ hipError_t stage_launch(itn_plan& pl, int stage, int mode, hipStream_t s) {
       if ((e = run(3, T.d_midall, T.midall.size())) != hipSuccess) return e;
       if ((e = run(4, T.d_narrow, T.narrow.size())) != hipSuccess) return e;
       return run(0, T.d_rest_nar, T.rest_nar.size());
+    case 7:
+      if ((e = run(2, T.d_big, T.big.size())) != hipSuccess) return e;
+      if ((e = run(3, T.d_mid, T.mid.size())) != hipSuccess) return e;
+      if ((e = run(4, T.d_narrow, T.narrow.size())) != hipSuccess) return e;
+      return run(0, T.d_rest_nar, T.rest_nar.size());
   }
   return hipErrorInvalidValue;
 }
@@ -973,7 +1022,7 @@ itn_status autotune(itn_handle* h, itn_plan& pl, hipStream_t s) {
       pl.tuned = true;
       return ITN_OK;
     }
-    return fail(h, ITN_E_ARG, "ITN_QN_TILE_MODE must be \"m1,m4\" with modes 0..6");
+    return fail(h, ITN_E_ARG, "ITN_QN_TILE_MODE must be \"m1,m4\" with modes 0..7");
   }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -62,6 +62,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(
   const int64_t batch = blockIdx.y;
   for (int64_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
     const GTile t = tiles[ti];
+    if (t.prob < 0) continue;  // padding that keeps every list position on its XCD
     const GProb pr = probs[t.prob];
     typename Cfg::AccV acc[BM / 32][BN / 32];
     zero_acc<P, BM, BN>(acc);
@@ -101,6 +102,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_grouped_direct_kernel(
   const int64_t batch = blockIdx.y;
   for (int64_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
     const GTile t = tiles[ti];
+    if (t.prob < 0) continue;  // padding that keeps every list position on its XCD
     const GProb pr = probs[t.prob];
     typename Cfg::AccV acc[Cfg::FM][Cfg::FN];
 #pragma unroll

@@ -48,7 +48,7 @@ struct GProb {     // one output problem (an output block, or a group of them)
   int32_t pad;
 };
 struct GTile {     // one work item
-  int32_t prob;
+  int32_t prob;    // -1: no work (padding of the tile list)
   int32_t tm, tn;  // tile coordinates within the problem
   int32_t pad;
 };
@@ -63,7 +63,8 @@ struct GBases {
   int32_t pad;
 };
 // Persistent grouped launch: at most max_wg workgroups (0: one per tile)
-// stride over the tile list.  Tile config: 0 = 64x64, 1 = 128x128 (register
+// stride over the tile list; with max_wg and the list length multiples of
+// 8, list position i runs on XCD i % 8.  Tile config: 0 = 64x64, 1 = 128x128 (register
 // staged, any alignment); 2 = direct-to-LDS 8-wave tiles (256x256, FP64
 // 256x128), 3 = direct-to-LDS 4-wave 128x128 tiles, 4 = direct-to-LDS
 // 4-wave 256x64 tiles (narrow products); 2, 3 and 4 need 16-byte aligned

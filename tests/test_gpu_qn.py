@@ -210,7 +210,7 @@ def test_qn_launch_modes_parity(h, monkeypatch, prec, which):
     (N < 96 on the 256 x 64 tiles of mode 6)."""
     ops, W1, W2 = U.large_u1() if which == "large_u1" else U.zn_u1z4(scale=20)
     ref = _ref(ops, [ops[4]])
-    for mode in ("0,0", "1,1", "2,2", "3,3", "2,3", "3,2", "4,4", "5,5", "4,5", "6,6", "5,6"):
+    for mode in ("0,0", "1,1", "2,2", "3,3", "2,3", "3,2", "4,4", "5,5", "4,5", "6,6", "5,6", "7,7"):
         monkeypatch.setenv("ITN_QN_TILE_MODE", mode)
         plan, _, got = _run(h, ops, W1, W2, prec, 1, [ops[4]])
         assert plan.info()["n_tiles"] > 0
