@@ -260,18 +260,20 @@ struct DotBatch {
 // block in one batched launch (nv = accepted vectors, contiguous slots).
 //
 // Precision: matvecs of expansion vectors run at `prec`.  When prec is below
-// FP64 and refinement is on, the first vector of every restart cycle (the
-// start vector, then each restart's Ritz vector) is applied in FP64 instead:
-// its row and column of the projected matrix are then exact, so the
-// corrections found with low-precision matvecs enter the Ritz vector with
-// first-order-exact couplings and the iteration converges to the FP64
-// eigenpair (the low-precision error enters only through the corrections'
-// own block, second order in their size).  A restart then keeps that one
-// Ritz vector (with a block, the B lowest), so a cycle is one FP64 matvec
-// and kmax - 1 low-precision ones.  Without refinement every matvec runs at
+// FP64 and refinement is on, the vectors every restart cycle starts from
+// (the start vector, then each restart's Ritz vectors) are applied in FP64
+// instead: their rows and columns of the projected matrix are then exact,
+// so the corrections found with low-precision matvecs enter the Ritz
+// vectors with first-order-exact couplings and the iteration converges to
+// the FP64 eigenpair (the low-precision error enters only through the
+// corrections' own block, second order in their size).  A restart keeps one
+// Ritz vector (with a block, the B lowest, all applied in FP64: with only
+// the first exact, the others' low-precision couplings, of order u_bf16
+// times the norm of H_eff, left Ritz vectors with residuals of that size),
+// so a cycle is one (B) FP64 matvecs and the rest low-precision ones.  Without refinement every matvec runs at
 // `prec`.  The returned energy is the Ritz value; with `exact_final` (mixed
 // mode) a residual test passed with low-precision products is confirmed
-// from a restart (one FP64 product, then the exact residual), and a result
+// from a restart (FP64 products, then the exact residual), and a result
 // that does not end on such a restart is applied once more in FP64: the
 // returned energy and residual are then FP64 figures.
 //
@@ -326,6 +328,7 @@ itn_status davidson(SolveCtx& c, const Matvec& mv, int prec, double tol, int max
     H(0, 0) = got[0];
   }
   int k = 1;
+  int nexact = 1;  // leading basis vectors whose products are FP64 (mixed mode)
   double theta = H(0, 0), rn = 0.0;
   bool conv = false, force_restart = false;
   std::vector<double> w, Y, y0(1, 1.0);
@@ -424,7 +427,7 @@ itn_status davidson(SolveCtx& c, const Matvec& mv, int prec, double tol, int max
       // can pass the test while the FP64 residual does not.  Where the
       // result must hold in FP64 (exact_final), confirm it from a restart:
       // its single vector's product is FP64, so the next residual is exact.
-      if (!(mixed && exact_final && B == 1 && k > 1 && used < maxiter)) {
+      if (!(mixed && exact_final && k > nexact && used < maxiter)) {
         conv = true;
         break;
       }
@@ -446,14 +449,17 @@ itn_status davidson(SolveCtx& c, const Matvec& mv, int prec, double tol, int max
       std::fill(Hk.begin(), Hk.end(), 0.0);
       for (int j = 0; j < m; ++j) H(j, j) = w[j];
       k = m;
-      if (mixed) {  // the new cycle's first vector applied in FP64: exact row and column 0
-        ITN_TRY(heff(ITN_P_F64, V, AV, 1));
-        ++used;
+      if (mixed) {  // the kept vectors applied in FP64: their rows and columns are exact
+        ITN_TRY(heff(ITN_P_F64, V, AV, m));
+        used += m;
         DotBatch db(c, n);
-        int o;
-        ITN_TRY(db.add(V, k, AV, &o));
+        std::vector<int> o(m);
+        for (int b = 0; b < m; ++b) ITN_TRY(db.add(V, m, AVs(b), &o[b]));
         ITN_TRY(db.read(got));
-        for (int a = 0; a < k; ++a) H(a, 0) = H(0, a) = got[o + a];
+        for (int b = 0; b < m; ++b)
+          for (int a = 0; a <= b; ++a)
+            H(a, b) = H(b, a) = 0.5 * (got[o[b] + a] + got[o[a] + b]);
+        nexact = m;
       }
       continue;
     }
@@ -517,7 +523,7 @@ itn_status davidson(SolveCtx& c, const Matvec& mv, int prec, double tol, int max
       std::vector<int> oc(na), o0(na);
       for (int q = 0; q < na; ++q) ITN_TRY(db.add(V, k + na, AVs(k + q), &oc[q]));
       if (mixed)
-        for (int q = 0; q < na; ++q) ITN_TRY(db.add(AV, 1, Vs(k + q), &o0[q]));
+        for (int q = 0; q < na; ++q) ITN_TRY(db.add(AV, nexact, Vs(k + q), &o0[q]));
       ITN_TRY(db.read(got));
       for (int q = 0; q < na; ++q)
         for (int a = 0; a <= k + q; ++a) H(a, k + q) = H(k + q, a) = got[oc[q] + a];
@@ -525,15 +531,16 @@ itn_status davidson(SolveCtx& c, const Matvec& mv, int prec, double tol, int max
         for (int l = q + 1; l < na; ++l)  // symmetric average inside the block
           H(k + q, k + l) = H(k + l, k + q) = 0.5 * (got[oc[l] + k + q] + got[oc[q] + k + l]);
       if (mixed)
-        for (int q = 0; q < na; ++q) H(0, k + q) = H(k + q, 0) = got[o0[q]];
+        for (int q = 0; q < na; ++q)
+          for (int a = 0; a < nexact; ++a) H(a, k + q) = H(k + q, a) = got[o0[q] + a];
     }
     k += na;
   }
   // the Ritz vector of the last projected problem
   ITN_HIP(c.h, lincomb(V, n, k, y0.data(), 0.0, psi, n, c.s));
-  // A single-vector basis after a restart (or the start) holds the FP64
-  // product already: theta and rn above are the FP64 figures.
-  const bool exact_now = mixed && B == 1 && k == 1;
+  // A basis of only the vectors applied in FP64 (after a restart, or the
+  // start) holds the FP64 products already: theta and rn are FP64 figures.
+  const bool exact_now = mixed && k == nexact;
   if (mixed && exact_final && !exact_now) {
     // FP64 Rayleigh quotient and residual of the result
     double* ax = AVs(s_spare);

@@ -219,8 +219,9 @@ def test_mixed_precision_sweeps_mostly_low_precision(h, block):
     """Spin-1 chain (N = 20, maxdim 64, 9 sweeps), bf16 expansions with FP64 restart
     vectors and a small Davidson budget per bond (4 vectors, 8 matvecs; four
     times that with blocks of 4): at least 70 % of the matvecs run in bf16,
-    at most 2.5 FP64 matvecs per bond on average (3.5 with blocks), and the
-    converged energy agrees with the FP64 run to 1e-9 relative."""
+    at most 2.5 FP64 matvecs per bond on average (5 with blocks, whose
+    restarts apply all four kept vectors in FP64), and the converged energy
+    agrees with the FP64 run to 1e-9 relative."""
     N = 20
     As0 = inp.random_product_state(N, 3, inp.rng_for(2, 64))
     sched = [(64, 1e-10)] * 9
@@ -235,7 +236,7 @@ def test_mixed_precision_sweeps_mostly_low_precision(h, block):
     print("  sweeps f64 ", [r["energy"] for r in r64])
     print("  sweeps bf16", [r["energy"] for r in rbf])
     assert (tot - f64) / tot >= 0.70
-    # single-vector: a restart cycle is one FP64 and three bf16 matvecs; the
-    # block solve runs more (batched) matvecs per bond and more cycles
-    assert f64 / (len(rbf) * bonds) <= (2.5 if block == 1 else 3.5)
+    # single-vector: a restart cycle is one FP64 and three bf16 matvecs; a
+    # block cycle is four FP64 (the kept block) and twelve bf16 matvecs
+    assert f64 / (len(rbf) * bonds) <= (2.5 if block == 1 else 5.0)
     assert abs(rbf[-1]["energy"] - r64[-1]["energy"]) <= 1e-9 * abs(r64[-1]["energy"])
