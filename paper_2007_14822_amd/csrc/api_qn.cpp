@@ -399,10 +399,14 @@ void build_tiles(TL& tl, const std::vector<GProb>& probs, const std::vector<GSeg
 // W-stage vectors are 16-byte aligned: checked once per plan, on the host,
 // before any table reaches the device.
 bool layout_ok(const itn_plan& pl, int64_t psi_elems) {
+  // transposes: output rows of ld_out >= rows rounded up to 8, offsets multiples of 8
+  // elements (the kernel writes whole 16-byte vectors up to that rounding)
+  if (pl.psiT_elems % 8 != 0) return false;
   for (const QnTBlock& t : pl.tb) {
-    if (t.rows <= 0 || t.cols <= 0 || t.in_ld < t.cols || t.ld_out < t.rows) return false;
+    if (t.rows <= 0 || t.cols <= 0 || t.in_ld < t.cols || t.ld_out < pad8(t.rows)) return false;
+    if (t.ld_out % 8 != 0 || t.out_off % 8 != 0) return false;
     if (t.in_off + (int64_t)(t.rows - 1) * t.in_ld + t.cols > psi_elems) return false;
-    if (t.out_off + (int64_t)(t.cols - 1) * t.ld_out + t.rows > pl.psiT_elems) return false;
+    if (t.out_off + (int64_t)(t.cols - 1) * t.ld_out + pad8(t.rows) > pl.psiT_elems) return false;
   }
   for (const QnCopy& c : pl.cp) {
     const int64_t lim = c.src ? pl.Rp_elems : pl.Lp_elems;

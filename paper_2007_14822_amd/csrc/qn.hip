@@ -23,7 +23,10 @@ hipError_t qn_set_ptrs(QnDevPtrs* dst, QnDevPtrs v, hipStream_t s) {
 // ------------------------------------------------------------ transpose
 // One 64 x 64 tile per workgroup; tile -> block from a table built by the
 // planner.  The LDS tile holds FP64 only for FP64 output (bf16 from FP64
-// goes through FP32 either way).
+// goes through FP32 either way).  Output rows are padded to a multiple of 8
+// elements, 16-byte aligned and zero past `rows`, so the store phase writes
+// whole 16-byte vectors of consecutive r (zeros past `rows`): one store per
+// 8 bf16 instead of one per element.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restrict__ ptrs,
                                                             TO* __restrict__ out,
@@ -40,16 +43,32 @@ __global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restr
   const TI* ip = static_cast<const TI*>(ptrs->psi) + bk.in_off + v * in_bs;
   TO* op = out + bk.out_off + v * out_bs;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-#pragma unroll 4
-  for (int i = ty; i < 64; i += 4) {
-    const int64_t r = r0 + i, c = c0 + tx;
-    if (r < bk.rows && c < bk.cols) tile[i][tx] = (TS)ip[r * bk.in_ld + c];
+  // all 16 loads of a thread in flight before the first LDS write
+  TI in[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t r = r0 + ty + 4 * k, c = c0 + tx;
+    in[k] = r < bk.rows && c < bk.cols ? ip[r * bk.in_ld + c] : TI(0);
   }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) tile[ty + 4 * k][tx] = (TS)in[k];
   __syncthreads();
-#pragma unroll 4
-  for (int i = ty; i < 64; i += 4) {
-    const int64_t c = c0 + i, r = r0 + tx;
-    if (r < bk.rows && c < bk.cols) op[c * bk.ld_out + r] = qconv<TO>((double)tile[tx][i]);
+  constexpr int V = 16 / (int)sizeof(TO);  // elements per 16-byte vector
+  constexpr int CH = 64 / V;               // vectors per tile column
+  union Vec {
+    uint4 u;
+    TO e[V];
+  };
+#pragma unroll
+  for (int it = threadIdx.x; it < 64 * CH; it += 256) {
+    const int ci = it / CH, j = it % CH;
+    const int64_t c = c0 + ci, r = r0 + (int64_t)j * V;
+    if (c >= bk.cols || r >= bk.rows) continue;
+    Vec w;
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+      w.e[e] = r + e < bk.rows ? qconv<TO>((double)tile[j * V + e][ci]) : qconv<TO>(0.0);
+    *reinterpret_cast<uint4*>(op + c * bk.ld_out + r) = w.u;
   }
 }
 
