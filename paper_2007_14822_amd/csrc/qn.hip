@@ -22,19 +22,19 @@ hipError_t qn_set_ptrs(QnDevPtrs* dst, QnDevPtrs v, hipStream_t s) {
 
 // ------------------------------------------------------------ transpose
 // One 64 x 64 tile per workgroup; tile -> block from a table built by the
-// planner.  The LDS tile holds FP64 only for FP64 output (bf16 from FP64
-// goes through FP32 either way).  Output rows are padded to a multiple of 8
-// elements, 16-byte aligned and zero past `rows`, so the store phase writes
-// whole 16-byte vectors of consecutive r (zeros past `rows`): one store per
-// 8 bf16 instead of one per element.
+// planner.  Each element is converted once, as it is loaded, to the output
+// type (FP64 -> bf16 is a single rounding, not one to FP32 and another to
+// bf16), and the LDS tile holds the converted values.  Output rows are
+// padded to a multiple of 8 elements, 16-byte aligned and zero past `rows`,
+// so the store phase writes whole 16-byte vectors of consecutive r (zeros
+// past `rows`): one store per 8 bf16 instead of one per element.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restrict__ ptrs,
                                                             TO* __restrict__ out,
                                                             const QnTBlock* __restrict__ blocks,
                                                             const int32_t* __restrict__ tile_block,
                                                             int64_t in_bs, int64_t out_bs) {
-  using TS = typename std::conditional<sizeof(TO) == 8, double, float>::type;
-  __shared__ TS tile[64][65];
+  __shared__ TO tile[64][65];
   const int t = blockIdx.x;
   const QnTBlock bk = blocks[tile_block[t]];
   const int local = t - bk.tile0;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restr
     in[k] = r < bk.rows && c < bk.cols ? ip[r * bk.in_ld + c] : TI(0);
   }
 #pragma unroll
-  for (int k = 0; k < 16; ++k) tile[ty + 4 * k][tx] = (TS)in[k];
+  for (int k = 0; k < 16; ++k) tile[ty + 4 * k][tx] = qconv<TO>((double)in[k]);
   __syncthreads();
   constexpr int V = 16 / (int)sizeof(TO);  // elements per 16-byte vector
   constexpr int CH = 64 / V;               // vectors per tile column
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restr
     Vec w;
 #pragma unroll
     for (int e = 0; e < V; ++e)
-      w.e[e] = r + e < bk.rows ? qconv<TO>((double)tile[j * V + e][ci]) : qconv<TO>(0.0);
+      w.e[e] = r + e < bk.rows ? tile[j * V + e][ci] : qconv<TO>(0.0);
     *reinterpret_cast<uint4*>(op + c * bk.ld_out + r) = w.u;
   }
 }

@@ -6,6 +6,7 @@ import torch
 
 import paper_2007_14822_amd as itn
 from oracle import qn as Q
+from paper_2007_14822_amd import inputs as inp
 from tests import qn_util as U
 from tests.workloads import elementwise_ratio, group_rel_err, heff_error_factor, rel_err
 
@@ -216,6 +217,40 @@ def test_qn_launch_modes_parity(h, monkeypatch, prec, which):
         assert plan.info()["n_tiles"] > 0
         assert rel_err(got, ref) <= TOL[prec], (mode, prec)
         del plan
+
+
+def test_qn_bf16_operand_rounds_once(h):
+    """psi's FP64 -> bf16 conversion on the block-sparse path is one rounding
+    to nearest, ties to even.  With identity environments (L, R = 1 on every
+    diagonal block) and a one-channel identity MPO, H_eff psi = psi, and
+    every later step is exact in bf16 / f32 (products with 1, sums of one
+    term), so the output is psi rounded to bf16: values just above and below
+    bf16 midpoints (where rounding to FP32 first lands on the midpoint and
+    then ties to even) and random values, against the exact reference."""
+    bl = [((-2,), 3), ((0,), 5), ((2,), 4)]
+    br = [((-2,), 2), ((0,), 4), ((2,), 5), ((4,), 3)]
+    W = np.zeros((1, 1, 2, 2))
+    W[0, 0] = np.eye(2)
+    L, w1, w2, R, psi = Q.heff_qn_operands(bl, br, inp.heisenberg_site_qn(1), [0], W, W, 5,
+                                           inp.block_values)
+    for env in (L, R):
+        for k in env.blocks:
+            assert k[0] == k[2]
+            env.blocks[k] = np.eye(env.blocks[k].shape[0]).reshape(env.blocks[k].shape)
+    rng = np.random.default_rng(17)
+    ulp = 2.0 ** -7
+    for k, blk in psi.blocks.items():
+        base = (1.0 + rng.integers(0, 127, blk.shape) * ulp) * rng.choice([-1.0, 1.0], blk.shape)
+        kind = rng.integers(0, 4, blk.shape)
+        off = np.choose(kind, [0.5 * ulp, 0.5 * ulp + 2.0 ** -30, 0.5 * ulp - 2.0 ** -30,
+                               rng.random(blk.shape) * ulp])
+        psi.blocks[k] = (base + np.sign(base) * off) * 2.0 ** rng.integers(-4, 4, blk.shape)
+    flat = psi.packed()[2]
+    e = np.floor(np.log2(np.abs(flat)))
+    q = 2.0 ** (e - 7)
+    ref = np.rint(flat / q) * q
+    _, _, got = _run(h, (L, w1, w2, R, psi), W, W, "bf16", 1, [psi])
+    assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:8]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
