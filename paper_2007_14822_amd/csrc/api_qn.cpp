@@ -975,11 +975,11 @@ hipError_t stage_launch(itn_plan& pl, int stage, int mode, hipStream_t s) {
 itn_status launch_all(itn_handle* h, itn_plan& pl, hipStream_t s, int cfg1, int cfg4,
                       bool with_env = true) {
   QnPtrs* ptrs = &pl.dptrs->p;
-  if (with_env) {
-    Prof pf(h, "qn_env_repack", s);
-    ITN_HIP(h, qn_block_copy(pl.pt, ptrs, pl.Lp, pl.Rp, pl.dcp, (int64_t)pl.cp.size(), s));
-  }
-  {
+  if (with_env) {  // L/R repack and psi transpose in one launch
+    Prof pf(h, "qn_env_repack_psi_transpose", s);
+    ITN_HIP(h, qn_prepare(pl.psi_dt, ptrs, pl.pt, pl.psiT, pl.dtb, pl.dtbi, pl.tb_tiles, pl.out_elems,
+                          pl.psiT_elems, pl.nv, pl.Lp, pl.Rp, pl.dcp, (int64_t)pl.cp.size(), s));
+  } else {
     Prof pf(h, "qn_psi_transpose", s);
     ITN_HIP(h, qn_block_transpose(pl.psi_dt, ptrs, pl.pt, pl.psiT, pl.dtb, pl.dtbi, pl.tb_tiles,
                                   pl.out_elems, pl.psiT_elems, pl.nv, s));

@@ -117,6 +117,12 @@ struct QnCopy {
 };
 hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
                          const QnCopy* items, int64_t nitems, hipStream_t s);
+// qn_block_copy (ncopy items, in the transpose's output type) and
+// qn_block_transpose in one launch (independent passes of an apply).
+hipError_t qn_prepare(int in_dtype, const QnPtrs* ptrs, int out_dtype, void* psiT,
+                      const QnTBlock* blocks, const int32_t* tile_block, int64_t ntiles, int64_t in_bs,
+                      int64_t out_bs, int nv, void* outL, void* outR, const QnCopy* items,
+                      int64_t ncopy, hipStream_t s);
 // Block-sparse W-stage.  The entries of one (a'-sector, b-sector) pair are
 // stored row after row; the last entry of a row carries the row's Z offset,
 // and rows without W12 terms have one zero-weight entry, so every Z element

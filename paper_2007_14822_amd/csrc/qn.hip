@@ -29,17 +29,14 @@ hipError_t qn_set_ptrs(QnDevPtrs* dst, QnDevPtrs v, hipStream_t s) {
 // so the store phase writes whole 16-byte vectors of consecutive r (zeros
 // past `rows`): one store per 8 bf16 instead of one per element.
 template <typename TI, typename TO>
-__global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restrict__ ptrs,
-                                                            TO* __restrict__ out,
-                                                            const QnTBlock* __restrict__ blocks,
-                                                            const int32_t* __restrict__ tile_block,
-                                                            int64_t in_bs, int64_t out_bs) {
+__device__ __forceinline__ void transpose_tile(const QnPtrs* __restrict__ ptrs, TO* __restrict__ out,
+                                               const QnTBlock* __restrict__ blocks,
+                                               const int32_t* __restrict__ tile_block, int t,
+                                               int64_t v, int64_t in_bs, int64_t out_bs) {
   __shared__ TO tile[64][65];
-  const int t = blockIdx.x;
   const QnTBlock bk = blocks[tile_block[t]];
   const int local = t - bk.tile0;
   const int64_t r0 = (int64_t)(local / bk.tiles_c) * 64, c0 = (int64_t)(local % bk.tiles_c) * 64;
-  const int64_t v = blockIdx.y;
   const TI* ip = static_cast<const TI*>(ptrs->psi) + bk.in_off + v * in_bs;
   TO* op = out + bk.out_off + v * out_bs;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -70,6 +67,15 @@ __global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restr
       w.e[e] = r + e < bk.rows ? tile[j * V + e][ci] : qconv<TO>(0.0);
     *reinterpret_cast<uint4*>(op + c * bk.ld_out + r) = w.u;
   }
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void qn_transpose_kernel(const QnPtrs* __restrict__ ptrs,
+                                                            TO* __restrict__ out,
+                                                            const QnTBlock* __restrict__ blocks,
+                                                            const int32_t* __restrict__ tile_block,
+                                                            int64_t in_bs, int64_t out_bs) {
+  transpose_tile<TI, TO>(ptrs, out, blocks, tile_block, blockIdx.x, blockIdx.y, in_bs, out_bs);
 }
 
 template <typename TI, typename TO>
@@ -239,10 +245,8 @@ hipError_t qn_wstage(int dtype, const void* X, void* Z, const QnWPair* pairs, co
 // Rows of an item (at most 32) are spread over the four waves, columns over
 // the lanes; narrow blocks use a flat index instead.
 template <typename T>
-__global__ __launch_bounds__(256) void qn_copy_kernel(const QnPtrs* __restrict__ ptrs,
-                                                       T* __restrict__ outL, T* __restrict__ outR,
-                                                       const QnCopy* __restrict__ items) {
-  const QnCopy it = items[blockIdx.x];
+__device__ __forceinline__ void copy_item(const QnPtrs* __restrict__ ptrs, T* __restrict__ outL,
+                                          T* __restrict__ outR, const QnCopy& it) {
   const T* src = static_cast<const T*>(it.src ? ptrs->R : ptrs->L) + it.in_off;
   T* dst = (it.src ? outR : outL) + it.out_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -262,6 +266,12 @@ __global__ __launch_bounds__(256) void qn_copy_kernel(const QnPtrs* __restrict__
     }
   }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void qn_copy_kernel(const QnPtrs* __restrict__ ptrs,
+                                                       T* __restrict__ outL, T* __restrict__ outR,
+                                                       const QnCopy* __restrict__ items) {
+  copy_item<T>(ptrs, outL, outR, items[blockIdx.x]);
+}
 hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
                          const QnCopy* items, int64_t nitems, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
@@ -275,6 +285,61 @@ hipError_t qn_block_copy(int dtype, const QnPtrs* ptrs, void* outL, void* outR,
     hipLaunchKernelGGL(qn_copy_kernel<bf16_t>, dim3((unsigned)nitems), dim3(256), 0, s, ptrs,
                        static_cast<bf16_t*>(outL), static_cast<bf16_t*>(outR), items);
   return hipGetLastError();
+}
+
+// ------------------------------------------------ repack + transpose
+// The L/R repack and the psi transpose of an apply with environments in one
+// launch (they are independent): workgroups [0, ncopy) copy one repack item
+// each, the rest take the transpose tiles of every vector; one launch
+// instead of two dependent ones, and the two passes' tails overlap.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void qn_prep_kernel(const QnPtrs* __restrict__ ptrs,
+                                                       TO* __restrict__ psiT,
+                                                       const QnTBlock* __restrict__ blocks,
+                                                       const int32_t* __restrict__ tile_block,
+                                                       int64_t ntiles, int64_t in_bs, int64_t out_bs,
+                                                       TO* __restrict__ outL, TO* __restrict__ outR,
+                                                       const QnCopy* __restrict__ items, int64_t ncopy) {
+  const int64_t b = blockIdx.x;
+  if (b < ncopy) {
+    copy_item<TO>(ptrs, outL, outR, items[b]);
+    return;
+  }
+  const int64_t t = (b - ncopy) % ntiles, v = (b - ncopy) / ntiles;
+  transpose_tile<TI, TO>(ptrs, psiT, blocks, tile_block, (int)t, v, in_bs, out_bs);
+}
+
+template <typename TI, typename TO>
+static hipError_t qn_prep_t(const QnPtrs* ptrs, void* psiT, const QnTBlock* blocks,
+                            const int32_t* tile_block, int64_t ntiles, int64_t in_bs, int64_t out_bs,
+                            int nv, void* outL, void* outR, const QnCopy* items, int64_t ncopy,
+                            hipStream_t s) {
+  const int64_t n = ncopy + ntiles * nv;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((qn_prep_kernel<TI, TO>), dim3((unsigned)n), dim3(256), 0, s, ptrs,
+                     static_cast<TO*>(psiT), blocks, tile_block, ntiles > 0 ? ntiles : 1, in_bs, out_bs,
+                     static_cast<TO*>(outL), static_cast<TO*>(outR), items, ncopy);
+  return hipGetLastError();
+}
+
+hipError_t qn_prepare(int in_dtype, const QnPtrs* ptrs, int out_dtype, void* psiT,
+                      const QnTBlock* blocks, const int32_t* tile_block, int64_t ntiles, int64_t in_bs,
+                      int64_t out_bs, int nv, void* outL, void* outR, const QnCopy* items,
+                      int64_t ncopy, hipStream_t s) {
+  if (nv <= 0) ntiles = 0;
+#define ITN_QP(TI, TO) \
+  return qn_prep_t<TI, TO>(ptrs, psiT, blocks, tile_block, ntiles, in_bs, out_bs, nv, outL, outR, items, ncopy, s)
+  if (in_dtype == D_F64) {
+    if (out_dtype == D_F64) ITN_QP(double, double);
+    if (out_dtype == D_F32) ITN_QP(double, float);
+    if (out_dtype == D_BF16) ITN_QP(double, bf16_t);
+  } else if (in_dtype == D_F32) {
+    if (out_dtype == D_F64) ITN_QP(float, double);
+    if (out_dtype == D_F32) ITN_QP(float, float);
+    if (out_dtype == D_BF16) ITN_QP(float, bf16_t);
+  }
+#undef ITN_QP
+  return hipErrorInvalidValue;
 }
 
 // ----------------------------------------------------------- zero blocks
