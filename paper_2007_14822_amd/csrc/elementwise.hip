@@ -101,10 +101,11 @@ hipError_t permute_cast(int in_dtype, const void* in, int out_dtype, void* out, 
 
 // --------------------------------------------------------------- transpose
 // 64x64 tiles through LDS: coalesced reads along c, coalesced writes along r.
-// The tile holds FP64 only for FP64 output (bf16 conversion from FP64 goes
-// through FP32 either way), which keeps the LDS footprint, and so the
-// number of resident tiles, up for the common FP64 -> bf16/FP32 case.  Each
-// lane writes two consecutive r of an output row.
+// Each element is converted once, as it is loaded, to the output type
+// (FP64 -> bf16 is one rounding, not one to FP32 and another to bf16), and
+// the tile holds the converted values: for the common FP64 -> bf16 case a
+// quarter of the FP64 footprint, so more tiles stay resident.  Each lane
+// writes two consecutive r of an output row.
 constexpr int TT = 64;
 template <typename TO> struct alignas(2 * sizeof(TO)) Pair { TO v[2]; };
 template <typename TI> struct alignas(16) TW2 { TI v[2]; };
@@ -112,8 +113,7 @@ template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ in,
                                                          TO* __restrict__ out, TransposeArgs t,
                                                          int64_t tiles_r, int64_t tiles_c) {
-  using TS = typename std::conditional<sizeof(TO) == 8, double, float>::type;
-  __shared__ TS tile[TT][TT + 1];
+  __shared__ TO tile[TT][TT + 1];
   const int64_t z = blockIdx.y;
   const int64_t zb = z / t.nzc, zc = z % t.nzc;
   const int64_t tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
@@ -131,14 +131,14 @@ __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ i
 #pragma unroll
     for (int i = ry; i < TT; i += 8) {
       const TW2<TI> v2 = *reinterpret_cast<const TW2<TI>*>(ip + (r0 + i) * t.in_r + c0 + c2);
-      tile[i][c2] = (TS)(TW)v2.v[0];
-      tile[i][c2 + 1] = (TS)(TW)v2.v[1];
+      tile[i][c2] = conv<TO, TW>((TW)v2.v[0]);
+      tile[i][c2 + 1] = conv<TO, TW>((TW)v2.v[1]);
     }
   } else {
 #pragma unroll 4
     for (int i = ty; i < TT; i += 4) {
       const int64_t r = r0 + i, c = c0 + tx;
-      if (r < t.rows && c < t.cols) tile[i][tx] = (TS)(TW)ip[r * t.in_r + c * t.in_c];
+      if (r < t.rows && c < t.cols) tile[i][tx] = conv<TO, TW>((TW)ip[r * t.in_r + c * t.in_c]);
     }
   }
   __syncthreads();
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ i
           uint4 u;
         } pk;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) pk.v[q] = conv<TO, TS>(tile[g8 * 8 + q][i]);
+        for (int q = 0; q < 8; ++q) pk.v[q] = tile[g8 * 8 + q][i];
         *reinterpret_cast<uint4*>(op + (c0 + i) * t.out_c + r0 + g8 * 8) = pk.u;
       }
       return;
@@ -170,15 +170,15 @@ __global__ __launch_bounds__(256) void transpose_kernel(const TI* __restrict__ i
     const int64_t c = c0 + i;
     if (c >= t.cols || r >= t.rows) continue;
     TO* p = op + c * t.out_c + r * t.out_r;
-    const TO v0 = conv<TO, TS>(tile[2 * px][i]);
+    const TO v0 = tile[2 * px][i];
     if (pair_ok && (reinterpret_cast<uintptr_t>(p) % sizeof(Pair<TO>)) == 0) {
       Pair<TO> pr;
       pr.v[0] = v0;
-      pr.v[1] = conv<TO, TS>(tile[2 * px + 1][i]);
+      pr.v[1] = tile[2 * px + 1][i];
       *reinterpret_cast<Pair<TO>*>(p) = pr;
     } else {
       p[0] = v0;
-      if (r + 1 < t.rows) p[t.out_r] = conv<TO, TS>(tile[2 * px + 1][i]);
+      if (r + 1 < t.rows) p[t.out_r] = tile[2 * px + 1][i];
     }
   }
 }

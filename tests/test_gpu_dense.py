@@ -334,6 +334,39 @@ def test_cast_f64_to_bf16_rounds_once(h):
     assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:8]
 
 
+@pytest.mark.parametrize("w", [1, 5])
+def test_heff_bf16_psi_rounds_once(h, w):
+    """The bf16 H_eff's transpose-cast of psi is one rounding to nearest,
+    ties to even.  With identity environments on MPO channel 0 (zero on the
+    others) and an MPO that is the identity on channel 0 only, H_eff psi =
+    psi, and every later step is exact (products with 1, sums of one term),
+    so the output is psi rounded to bf16: values just above and below bf16
+    midpoints and random ones, ragged tiles (chi 130 and 70), against the
+    exact reference.  w = 5 takes the fused stage-1 kernel, w = 1 the
+    unfused stages."""
+    cl, d, cr = 130, 2, 70
+    W = np.zeros((w, w, d, d))
+    W[0, 0] = np.eye(d)
+    L = np.zeros((cl, w, cl))
+    L[:, 0, :] = np.eye(cl)
+    R = np.zeros((cr, w, cr))
+    R[:, 0, :] = np.eye(cr)
+    rng = np.random.default_rng(23)
+    ulp = 2.0 ** -7
+    shape = (cl, d, d, cr)
+    base = (1.0 + rng.integers(0, 127, shape) * ulp) * rng.choice([-1.0, 1.0], shape)
+    off = np.choose(rng.integers(0, 4, shape), [0.5 * ulp, 0.5 * ulp + 2.0 ** -30,
+                                                 0.5 * ulp - 2.0 ** -30, rng.random(shape) * ulp])
+    psi = (base + np.sign(base) * off) * 2.0 ** rng.integers(-4, 4, shape)
+    e = np.floor(np.log2(np.abs(psi)))
+    q = 2.0 ** (e - 7)
+    ref = np.rint(psi / q) * q
+    out = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    h.heff_apply(dev(L, torch.bfloat16), W, W, dev(R, torch.bfloat16), dev(psi), out, prec="bf16")
+    got = host(out)
+    assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:8]
+
+
 def test_caller_workspace(h):
     """A caller-owned workspace of exactly the queried size runs the call
     (same result as the library's own workspace); one too small is refused
