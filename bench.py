@@ -500,6 +500,31 @@ def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=DAVIDSON, b
             "f64_matvecs_per_bond": f64 / bonds}
 
 
+def qn_dmrg_leg(h, inp, prec, Lx=8, Ly=4, maxdims=(64, 128, 256, 512, 512)):
+    """Block-sparse two-site sweeps on the U(1) x U(1) Hubbard cylinder
+    (Lx x Ly, U/t = 8, half filling from a Neel product state, cutoff 1e-8),
+    the bench's small Davidson budget; per sweep energy, time and the
+    phase split."""
+    Ws = inp.hubbard_mpo(Lx, Ly, U=8.0)
+    N = Lx * Ly
+    mps = h.qn_mps(inp.hubbard_site_qn(), [1 + (k % 2) for k in range(N)])
+    mpo = h.mpo(Ws)
+    t0 = time.perf_counter()
+    recs = h.qn_dmrg_sweep(mps, mpo, inp.hubbard_mpo_link_qn(Ws[0].shape[0]),
+                           [(m, 1e-8) for m in maxdims], prec=prec, eig_tol=1e-10,
+                           allow_unconverged=True, timing=True, **DAVIDSON)
+    secs = time.perf_counter() - t0
+    total_qn = h.qn_mps_link(mps, N)  # the last link carries the state's (N, 2Sz)
+    mps.close()
+    mpo.close()
+    tot = sum(r["matvecs"] for r in recs)
+    f64 = sum(r["matvecs_f64"] for r in recs)
+    return {"model": "Hubbard %dx%d cylinder, U/t=8, U(1)xU(1) (N, 2Sz), w=%d" % (Lx, Ly, Ws[0].shape[0]),
+            "schedule": [(m, 1e-8) for m in maxdims], "total_seconds": secs, "sweeps": recs,
+            "matvecs": tot, "matvecs_f64": f64, "low_precision_fraction": (tot - f64) / tot,
+            "total_qn": [list(q) for q, _ in total_qn]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -726,6 +751,14 @@ def main():
         line["dmrg"] = {"model": "spin-1 Heisenberg chain, N=100, d=3, w=5",
                         "schedule": sched, **dm, "bf16_last_sweep_split": split}
     if not args.no_dmrg and not args.only:
+        qd = {}
+        for prec in ("f64", "bf16"):
+            log("[bench] block-sparse DMRG, Hubbard 8x4 cylinder %s, maxdim up to 512" % prec)
+            qd[prec] = qn_dmrg_leg(h, inp, prec)
+            log("[bench]   %.1f s, E=%.10f" % (qd[prec]["total_seconds"], qd[prec]["sweeps"][-1]["energy"]))
+        e64 = qd["f64"]["sweeps"][-1]["energy"]
+        qd["bf16"]["rel_err_vs_f64_run"] = abs(qd["bf16"]["sweeps"][-1]["energy"] - e64) / abs(e64)
+        line["qn_dmrg"] = qd
         log("[bench] excited state by energy penalty, S=1/2 chain N=40")
         line["excited_state"] = excited_leg(h, np, inp)
     if not args.no_cpu_baseline:

@@ -164,12 +164,13 @@ struct itn_qn_mps {
   std::vector<int32_t> env_link_qn;  // MPO channel QNs the environments were built with
   const itn_mpo* env_mpo = nullptr;
   SolverBufs sb;
-  DBuf psi, Lp, Rp, mat, matT, rho, ut, prod, ev, info;
+  DBuf psi, Lp, Rp, mat, matT, rho, ut, prod, ev, info, bat, batw, bmeta;
   HostPin pin;
   ~itn_qn_mps() {
     for (auto* v : {&A, &L, &R})
       for (auto& t : *v) t.data.release();
-    for (DBuf* b : {&psi, &Lp, &Rp, &mat, &matT, &rho, &ut, &prod, &ev, &info}) b->release();
+    for (DBuf* b : {&psi, &Lp, &Rp, &mat, &matT, &rho, &ut, &prod, &ev, &info, &bat, &batw, &bmeta})
+      b->release();
     sb.release();
     pin.release();
   }
@@ -396,12 +397,46 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
       ITN_HIP(c.h, transpose_sub(M, S.nc, MT, S.nr, S.nc, c.s));
       ITN_HIP(c.h, gemm_nt64(MT, S.nr, MT, S.nr, rho, n, n, n, S.nr, c.s));  // M^T M
     }
-    double* D = m->ev.d() + evo;
-    rocblas_status st = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n,
-                                         rho, (rocblas_int)n, D, D + n,
-                                         static_cast<rocblas_int*>(m->info.p) + e);
-    if (st != rocblas_status_success) return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd failed (%d)", (int)st);
-    evo += 2 * n;
+  }
+  // All sectors' eigenproblems in one batched divide-and-conquer call: each
+  // density matrix padded to the largest dimension (the padding is a -1
+  // diagonal block, below every weight; its eigenvectors stay in the
+  // padding), then each sector's eigenvalues and eigenvectors copied out.
+  // One call instead of one per sector: a bond of the Hubbard cylinder has
+  // tens of sectors, and the per-call cost dominated the split.
+  {
+    int64_t nmax = 0;
+    std::vector<int64_t> meta;
+    for (const Eig& g : eig) {
+      nmax = std::max(nmax, g.n);
+      meta.push_back(g.n);
+      meta.push_back(g.rho_off);
+    }
+    const int nb = (int)eig.size();
+    ITN_TRY(m->bmeta.ensure(c.h, meta.size() * 8));
+    ITN_TRY(m->bat.ensure(c.h, (size_t)nb * nmax * nmax * 8));
+    ITN_TRY(m->batw.ensure(c.h, (size_t)nb * nmax * 2 * 8));
+    ITN_HIP(c.h, hipMemcpy(m->bmeta.p, meta.data(), meta.size() * 8, hipMemcpyHostToDevice));
+    double* Ab = m->bat.d();
+    double* Wb = m->batw.d();
+    double* Eb = Wb + (size_t)nb * nmax;
+    ITN_HIP(c.h, pad_batch(m->rho.d(), static_cast<const int64_t*>(m->bmeta.p), Ab, nmax, nb, c.s));
+    rocblas_status st = rocsolver_dsyevd_strided_batched(
+        rb, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)nmax, Ab, (rocblas_int)nmax,
+        (rocblas_stride)(nmax * nmax), Wb, (rocblas_stride)nmax, Eb, (rocblas_stride)nmax,
+        static_cast<rocblas_int*>(m->info.p), (rocblas_int)nb);
+    if (st != rocblas_status_success)
+      return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd_strided_batched failed (%d)", (int)st);
+    for (int b = 0; b < nb; ++b) {
+      const int64_t n = eig[b].n, lo = nmax - n;  // the sector's eigenpairs are the top n
+      ITN_HIP(c.h, hipMemcpyAsync(m->ev.d() + evo, Wb + (size_t)b * nmax + lo, n * 8,
+                                  hipMemcpyDeviceToDevice, c.s));
+      // column lo + j of the padded matrix (rows < n) -> row j of the sector's eigenvectors
+      ITN_HIP(c.h, hipMemcpy2DAsync(m->rho.d() + eig[b].rho_off, n * 8,
+                                    Ab + (size_t)b * nmax * nmax + lo * nmax, nmax * 8, n * 8, n,
+                                    hipMemcpyDeviceToDevice, c.s));
+      evo += 2 * n;
+    }
   }
   // eigenvalues and solver status to host
   ITN_TRY(m->pin.ensure(c.h, ev_tot * 8 + eig.size() * sizeof(rocblas_int) + 64));

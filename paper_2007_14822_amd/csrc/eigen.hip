@@ -12,6 +12,8 @@
 // workgroups, through global memory and one grid barrier.  One launch
 // replaces the per-column launches of a library reduction, whose cost at
 // n of a few hundred is launch latency.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -330,6 +332,25 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 
 }  // namespace
 
+// Per-sector density matrices padded into one batch of nmax x nmax matrices
+// (meta[2b] = n, meta[2b + 1] = element offset of sector b's n x n matrix in
+// rho): rho_b in the leading block, -1 on the rest of the diagonal, 0
+// elsewhere.  The padding is a separate diagonal block whose eigenvalues
+// (-1) lie below every density-matrix weight, so the eigenpairs of rho_b are
+// those of the padded matrix with the padding rows zero.
+__global__ void pad_batch_kernel(const double* __restrict__ rho, const int64_t* __restrict__ meta,
+                                 double* __restrict__ A, int64_t nmax) {
+  const int64_t b = blockIdx.y;
+  const int64_t n = meta[2 * b], off = meta[2 * b + 1];
+  double* Ab = A + b * nmax * nmax;
+  const int64_t tot = nmax * nmax;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = idx / nmax, r = idx - c * nmax;
+    Ab[idx] = (r < n && c < n) ? rho[off + r * n + c] : (r == c ? -1.0 : 0.0);
+  }
+}
+
 int sytrd_coop_groups(int n) {
   if (n < 3 || n > 1 + 8 * EIG_THREADS) return 0;
   // rows of A plus three n-vectors must fit the LDS of one workgroup
@@ -365,6 +386,15 @@ hipError_t sytrd_coop(const SytrdArgs& a0, hipStream_t s) {
   void* args[] = {&a};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(sytrd_coop_kernel), dim3(a.nwg),
                                     dim3(EIG_THREADS), args, (unsigned)lds, s);
+}
+
+hipError_t pad_batch(const double* rho, const int64_t* meta, double* A, int64_t nmax, int nbatch,
+                     hipStream_t s) {
+  if (nmax <= 0 || nbatch <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((nmax * nmax + 255) / 256, 1024);
+  hipLaunchKernelGGL(pad_batch_kernel, dim3((unsigned)blocks, (unsigned)nbatch), dim3(256), 0, s, rho,
+                     meta, A, nmax);
+  return hipGetLastError();
 }
 
 bool tridiag_back_supported(int n) {

@@ -258,5 +258,10 @@ hipError_t sytrd_coop(const SytrdArgs& a, hipStream_t s);
 hipError_t tridiag_back(const double* V, const double* tau, const double* ZT, int64_t ldz, int cols0,
                         double* out, int n, int k, hipStream_t s);
 bool tridiag_back_supported(int n);
+// Batch of nbatch symmetric nmax x nmax matrices A (column-major, stride
+// nmax^2) from per-matrix n x n blocks of rho (meta[2b] = n, meta[2b + 1] =
+// offset in rho): rho_b leading, -1 on the rest of the diagonal, 0 elsewhere.
+hipError_t pad_batch(const double* rho, const int64_t* meta, double* A, int64_t nmax, int nbatch,
+                     hipStream_t s);
 
 }  // namespace itn
