@@ -752,6 +752,25 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     const int64_t db = SB.dim[ib], dbw = dbp(ib);  // true and padded widths
     wpair.db = (int32_t)dbw;
     pl.max_db = std::max<int64_t>(pl.max_db, dbw);
+    // the X inputs of this pair, in entry order (they do not depend on the Z row)
+    struct InBlock {
+      int im0, ia, i1, i2;
+      int64_t xbase, colbase;
+    };
+    std::vector<InBlock> inputs;
+    for (int im0 = 0; im0 < SM.nsec; ++im0) {
+      // X group (ia, im0) with q(a) = q(a') - q(m0)
+      const int ia = SA.find(qadd(SA.q(iap), SM.q(im0), qmod, -1));
+      if (ia < 0) continue;
+      auto xg = xgroup.find({ia, im0});
+      if (xg == xgroup.end() || xg->second.second != iap) continue;
+      for (int i1 = 0; i1 < S1.nsec; ++i1)
+        for (int i2 = 0; i2 < S2.nsec; ++i2) {
+          auto pb = P.index.find({ia, i1, i2, ib});
+          if (pb == P.index.end()) continue;
+          inputs.push_back({im0, ia, i1, i2, xg->second.first, colbase[pb->second]});
+        }
+    }
     for (auto& zk : kv.second) {
       const int i1p = zk[1], i2p = zk[2], im2 = zk[3];
       const int64_t zoff = zblock[zk];
@@ -765,31 +784,20 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
             const size_t row_e0 = pl.we.size();
             const int g_m2 = (int)SM2.off[im2] + m2l;
             const int g_s1p = (int)S1.off[i1p] + s1l, g_s2p = (int)S2.off[i2p] + s2l;
-            for (int im0 = 0; im0 < SM.nsec; ++im0) {
-              // X group (ia, im0) with q(a) = q(a') - q(m0)
-              const int ia = SA.find(qadd(SA.q(iap), SM.q(im0), qmod, -1));
-              if (ia < 0) continue;
-              auto xg = xgroup.find({ia, im0});
-              if (xg == xgroup.end() || xg->second.second != iap) continue;
-              for (int i1 = 0; i1 < S1.nsec; ++i1)
-                for (int i2 = 0; i2 < S2.nsec; ++i2) {
-                  auto pb = P.index.find({ia, i1, i2, ib});
-                  if (pb == P.index.end()) continue;
-                  const int64_t ds1 = S1.dim[i1], ds2 = S2.dim[i2];
-                  for (int m0l = 0; m0l < SM.dim[im0]; ++m0l)
-                    for (int s1l2 = 0; s1l2 < ds1; ++s1l2)
-                      for (int s2l2 = 0; s2l2 < ds2; ++s2l2) {
-                        const double cf = w12((int)SM.off[im0] + m0l, g_m2, g_s1p, g_s2p,
-                                              (int)S1.off[i1] + s1l2, (int)S2.off[i2] + s2l2);
-                        if (cf == 0.0) continue;
-                        QnWEnt e{};
-                        e.off = xg->second.first + m0l * N_ia[ia] + colbase[pb->second] +
-                                (s1l2 * ds2 + s2l2) * dbw;
-                        e.astride = (int64_t)SM.dim[im0] * N_ia[ia];
-                        e.coef = cf;
-                        pl.we.push_back(e);
-                      }
-                }
+            for (const InBlock& in : inputs) {
+              const int64_t ds1 = S1.dim[in.i1], ds2 = S2.dim[in.i2];
+              for (int m0l = 0; m0l < SM.dim[in.im0]; ++m0l)
+                for (int s1l2 = 0; s1l2 < ds1; ++s1l2)
+                  for (int s2l2 = 0; s2l2 < ds2; ++s2l2) {
+                    const double cf = w12((int)SM.off[in.im0] + m0l, g_m2, g_s1p, g_s2p,
+                                          (int)S1.off[in.i1] + s1l2, (int)S2.off[in.i2] + s2l2);
+                    if (cf == 0.0) continue;
+                    QnWEnt e{};
+                    e.off = in.xbase + m0l * N_ia[in.ia] + in.colbase + (s1l2 * ds2 + s2l2) * dbw;
+                    e.astride = (int64_t)SM.dim[in.im0] * N_ia[in.ia];
+                    e.coef = cf;
+                    pl.we.push_back(e);
+                  }
             }
             pl.flops_w += 2.0 * (double)(pl.we.size() - row_e0) * wpair.da * db;
             if (pl.we.size() == row_e0) {
