@@ -165,10 +165,12 @@ struct itn_qn_mps {
   const itn_mpo* env_mpo = nullptr;
   SolverBufs sb;
   DBuf psi, Lp, Rp, mat, matT, rho, ut, prod, ev, info, bat, batw, bmeta;
+  QBT theta, T1, T2;  // two-site tensor and environment intermediates (buffers reused)
   HostPin pin;
   ~itn_qn_mps() {
     for (auto* v : {&A, &L, &R})
       for (auto& t : *v) t.data.release();
+    for (QBT* t : {&theta, &T1, &T2}) t->data.release();
     for (DBuf* b : {&psi, &Lp, &Rp, &mat, &matT, &rho, &ut, &prod, &ev, &info, &bat, &batw, &bmeta})
       b->release();
     sb.release();
@@ -260,7 +262,7 @@ itn_status contract(QCtx& c, const QBT& A, const std::vector<int32_t>& la, bool 
 // R_i from R_{i+1} and site i:  R'[b', m, b] = sum A[b', s', b''] W[m, m', s', s] A[b, s, b'''] R[b'', m', b''']
 itn_status env_step(QCtx& c, int i, bool left) {
   itn_qn_mps* m = c.m;
-  QBT T1, T2;
+  QBT &T1 = m->T1, &T2 = m->T2;  // buffers kept between steps (stream order protects them)
   if (left) {
     ITN_TRY(contract(c, m->L[i], {1, 2, 3}, false, m->A[i], {1, 4, 5}, true, {2, 3, 4, 5}, T1));
     ITN_TRY(contract(c, T1, {2, 3, 4, 5}, false, c.W[i], {2, 6, 4, 7}, false, {3, 5, 6, 7}, T2));
@@ -270,9 +272,6 @@ itn_status env_step(QCtx& c, int i, bool left) {
     ITN_TRY(contract(c, T1, {1, 4, 6, 7}, false, c.W[i], {8, 6, 4, 9}, false, {1, 7, 8, 9}, T2));
     ITN_TRY(contract(c, T2, {1, 7, 8, 9}, false, m->A[i], {10, 9, 7}, false, {1, 8, 10}, m->R[i]));
   }
-  ITN_HIP(c.h, hipStreamSynchronize(c.s));  // T1, T2 are released at return
-  T1.data.release();
-  T2.data.release();
   return ITN_OK;
 }
 
@@ -612,7 +611,7 @@ itn_status make_plan(QCtx& c, int i, const QBT& psi, int prec, BondPlan& bp) {
 itn_status bond_step(QCtx& c, int i, bool to_right, int maxdim, double cutoff, bool last, double* energy,
                      double* trunc) {
   itn_qn_mps* m = c.m;
-  QBT psi;
+  QBT& psi = m->theta;  // buffer kept between bonds
   ITN_TRY(contract(c, m->A[i], {1, 2, 3}, false, m->A[i + 1], {3, 4, 5}, false, {1, 2, 4, 5}, psi, true));
   const int64_t n = psi.q.elems;
   const int prec = c.p->prec;
@@ -650,8 +649,6 @@ itn_status bond_step(QCtx& c, int i, bool to_right, int maxdim, double cutoff, b
     ITN_TRY(split(c, i, to_right, psi, maxdim, cutoff, trunc));
   }
   PhaseTimer pt(c, &c.t_env);
-  ITN_HIP(c.h, hipStreamSynchronize(c.s));
-  psi.data.release();
   if (to_right) return env_step(c, i, true);
   return env_step(c, i + 1, false);
 }
