@@ -252,37 +252,27 @@ itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, 
     for (int tm = 0; tm < (M + TR - 1) / TR; ++tm)
       for (int tn = 0; tn < pr.tiles_n; ++tn) tiles.push_back(GTile{pi, tm, tn, 0});
   }
-  // workspace: Ap, Bp, T, tables
-  const size_t bAp = round256((size_t)std::max<int64_t>(ap_elems, 1) * es);
-  const size_t bBp = round256((size_t)std::max<int64_t>(bp_elems, 1) * es);
-  const size_t bT = round256((size_t)std::max<int64_t>(t_elems, 1) * dtype_size(acc_dt));
-  const size_t bP = round256(std::max<size_t>(probs.size(), 1) * sizeof(GProb));
-  const size_t bS = round256(std::max<size_t>(segs.size(), 1) * sizeof(GSeg));
-  const size_t bTl = round256(std::max<size_t>(tiles.size(), 1) * sizeof(GTile));
-  const size_t bB = round256(sizeof(GBases));
-  ITN_TRY(ensure_workspace(h, bAp + bBp + bT + bP + bS + bTl + bB + 256));
-  Carver cv(h->ws.ptr);
-  void* Ap = cv.take(bAp);
-  void* Bp = cv.take(bBp);
-  void* T = cv.take(bT);
-  GProb* dprob = static_cast<GProb*>(cv.take(bP));
-  GSeg* dseg = static_cast<GSeg*>(cv.take(bS));
-  GTile* dtile = static_cast<GTile*>(cv.take(bTl));
-  GBases* dbase = static_cast<GBases*>(cv.take(bB));
-  Prof pf(h, "qn_contract", s);
-  // zero every C block no pair reaches (and all of C when there are none)
-  for (size_t cb = 0; cb < qc.blocks.size(); ++cb)
-    if (!by_c.count((int)cb)) {
-      int64_t sz = 1;
-      for (int k = 0; k < C->rank; ++k) sz *= qc.sp[k].dim[qc.blocks[cb][k]];
-      ITN_HIP(h, fill(static_cast<char*>(C->data) + qc.off[cb] * dtype_size(C->dtype), C->dtype, 0.0, sz, s));
-    }
-  if (probs.empty()) return ITN_OK;
-  // operand blocks permuted (and converted) into K-contiguous matrices
-  auto permute_blocks = [&](const itn_tensor* t, const QTensor& q, const std::vector<int>& fr,
-                            const std::vector<int>& cn, void* dst, const std::vector<int64_t>& doff,
-                            const std::set<int>& used) -> itn_status {
-    const int esz = dtype_size(t->dtype);
+  // the block permutations (operand blocks into K-contiguous matrices, and
+  // the result blocks into C's label order), each set in one launch
+  std::set<int> usedA, usedB;
+  for (auto& kv : by_c)
+    for (const Pair& q : kv.second) usedA.insert(q.a), usedB.insert(q.b);
+  std::vector<PermItem> items;
+  std::vector<PermChunk> chunks;
+  auto add_item = [&](int64_t src, int64_t dst, const std::vector<int64_t>& od,
+                      const std::vector<int64_t>& is) {
+    PermItem it{};
+    it.src = src;
+    it.dst = dst;
+    it.rank = (int32_t)od.size();
+    it.n = 1;
+    for (size_t k = 0; k < od.size(); ++k) it.dims[k] = od[k], it.istr[k] = is[k], it.n *= od[k];
+    for (int64_t f = 0; f < it.n; f += PERM_CHUNK) chunks.push_back(PermChunk{(int32_t)items.size(), 0, f});
+    items.push_back(it);
+  };
+  auto block_items = [&](const itn_tensor* t, const QTensor& q, const std::vector<int>& fr,
+                         const std::vector<int>& cn, const std::vector<int64_t>& doff,
+                         const std::set<int>& used) {
     for (size_t b = 0; b < q.blocks.size(); ++b) {
       if (!used.count((int)b)) continue;
       std::vector<int64_t> dims(t->rank), st(t->rank);
@@ -296,31 +286,15 @@ itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, 
       for (int k : fr) od.push_back(dims[k]), is.push_back(st[k]);
       for (int k : cn) od.push_back(dims[k]), is.push_back(st[k]);
       if (od.empty()) od.push_back(1), is.push_back(0);
-      ITN_HIP(h, permute_cast(t->dtype, static_cast<const char*>(t->data) + q.off[b] * esz, pt,
-                              static_cast<char*>(dst) + doff[b] * es, (int)od.size(), od.data(),
-                              is.data(), s));
+      add_item(q.off[b], doff[b], od, is);
     }
-    return ITN_OK;
   };
-  std::set<int> usedA, usedB;
-  for (auto& kv : by_c)
-    for (const Pair& q : kv.second) usedA.insert(q.a), usedB.insert(q.b);
-  ITN_TRY(permute_blocks(A, qa, freeA, conA, Ap, aoff, usedA));
-  ITN_TRY(permute_blocks(B, qb, freeB, conB, Bp, boff, usedB));
-  GBases gb{};
-  gb.A = Ap;
-  gb.B = Bp;
-  gb.C = natural ? C->data : T;
-  gb.zero = nullptr;
-  gb.rows = nullptr;
-  ITN_HIP(h, hipMemcpyAsync(dprob, probs.data(), probs.size() * sizeof(GProb), hipMemcpyHostToDevice, s));
-  ITN_HIP(h, hipMemcpyAsync(dseg, segs.data(), segs.size() * sizeof(GSeg), hipMemcpyHostToDevice, s));
-  ITN_HIP(h, hipMemcpyAsync(dtile, tiles.data(), tiles.size() * sizeof(GTile), hipMemcpyHostToDevice, s));
-  ITN_HIP(h, hipMemcpyAsync(dbase, &gb, sizeof(GBases), hipMemcpyHostToDevice, s));
-  ITN_HIP(h, gemm_grouped(P, natural ? C->dtype : acc_dt, tile_cfg, dbase, dprob, dseg, dtile,
-                          (int64_t)tiles.size(), 0, 0, 0, 1, 0, s));
+  block_items(A, qa, freeA, conA, aoff, usedA);
+  const int64_t nchA = (int64_t)chunks.size();
+  block_items(B, qb, freeB, conB, boff, usedB);
+  const int64_t nchB = (int64_t)chunks.size() - nchA;
   if (!natural) {
-    // T[cb] is [freeA..., freeB...]; gather each into C's label order
+    // T[cb] is [freeA..., freeB...]; each gathered into C's label order
     for (auto& kv : by_c) {
       const int cb = kv.first;
       const int a0 = kv.second[0].a, b0 = kv.second[0].b;
@@ -340,11 +314,60 @@ itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, 
         od[k] = qc.sp[k].dim[qc.blocks[cb][k]];
         is[k] = tstr[pos];
       }
-      ITN_HIP(h, permute_cast(acc_dt, static_cast<const char*>(T) + toff[cb] * dtype_size(acc_dt),
-                              C->dtype, static_cast<char*>(C->data) + qc.off[cb] * dtype_size(C->dtype),
-                              C->rank, od.data(), is.data(), s));
+      if (od.empty()) od.push_back(1), is.push_back(0);
+      add_item(toff[cb], qc.off[cb], od, is);
     }
   }
+  const int64_t nchC = (int64_t)chunks.size() - nchA - nchB;
+  // workspace: Ap, Bp, T, tables
+  const size_t bAp = round256((size_t)std::max<int64_t>(ap_elems, 1) * es);
+  const size_t bBp = round256((size_t)std::max<int64_t>(bp_elems, 1) * es);
+  const size_t bT = round256((size_t)std::max<int64_t>(t_elems, 1) * dtype_size(acc_dt));
+  const size_t bP = round256(std::max<size_t>(probs.size(), 1) * sizeof(GProb));
+  const size_t bS = round256(std::max<size_t>(segs.size(), 1) * sizeof(GSeg));
+  const size_t bTl = round256(std::max<size_t>(tiles.size(), 1) * sizeof(GTile));
+  const size_t bB = round256(sizeof(GBases));
+  const size_t bIt = round256(std::max<size_t>(items.size(), 1) * sizeof(PermItem));
+  const size_t bCh = round256(std::max<size_t>(chunks.size(), 1) * sizeof(PermChunk));
+  ITN_TRY(ensure_workspace(h, bAp + bBp + bT + bP + bS + bTl + bB + bIt + bCh + 256));
+  Carver cv(h->ws.ptr);
+  void* Ap = cv.take(bAp);
+  void* Bp = cv.take(bBp);
+  void* T = cv.take(bT);
+  GProb* dprob = static_cast<GProb*>(cv.take(bP));
+  GSeg* dseg = static_cast<GSeg*>(cv.take(bS));
+  GTile* dtile = static_cast<GTile*>(cv.take(bTl));
+  GBases* dbase = static_cast<GBases*>(cv.take(bB));
+  PermItem* ditem = static_cast<PermItem*>(cv.take(bIt));
+  PermChunk* dchunk = static_cast<PermChunk*>(cv.take(bCh));
+  Prof pf(h, "qn_contract", s);
+  // zero every C block no pair reaches (and all of C when there are none)
+  for (size_t cb = 0; cb < qc.blocks.size(); ++cb)
+    if (!by_c.count((int)cb)) {
+      int64_t sz = 1;
+      for (int k = 0; k < C->rank; ++k) sz *= qc.sp[k].dim[qc.blocks[cb][k]];
+      ITN_HIP(h, fill(static_cast<char*>(C->data) + qc.off[cb] * dtype_size(C->dtype), C->dtype, 0.0, sz, s));
+    }
+  if (probs.empty()) return ITN_OK;
+  // operand blocks permuted (and converted) into K-contiguous matrices
+  ITN_HIP(h, hipMemcpyAsync(ditem, items.data(), items.size() * sizeof(PermItem), hipMemcpyHostToDevice, s));
+  ITN_HIP(h, hipMemcpyAsync(dchunk, chunks.data(), chunks.size() * sizeof(PermChunk),
+                            hipMemcpyHostToDevice, s));
+  ITN_HIP(h, permute_batch(A->dtype, A->data, pt, Ap, ditem, dchunk, nchA, s));
+  ITN_HIP(h, permute_batch(B->dtype, B->data, pt, Bp, ditem, dchunk + nchA, nchB, s));
+  GBases gb{};
+  gb.A = Ap;
+  gb.B = Bp;
+  gb.C = natural ? C->data : T;
+  gb.zero = nullptr;
+  gb.rows = nullptr;
+  ITN_HIP(h, hipMemcpyAsync(dprob, probs.data(), probs.size() * sizeof(GProb), hipMemcpyHostToDevice, s));
+  ITN_HIP(h, hipMemcpyAsync(dseg, segs.data(), segs.size() * sizeof(GSeg), hipMemcpyHostToDevice, s));
+  ITN_HIP(h, hipMemcpyAsync(dtile, tiles.data(), tiles.size() * sizeof(GTile), hipMemcpyHostToDevice, s));
+  ITN_HIP(h, hipMemcpyAsync(dbase, &gb, sizeof(GBases), hipMemcpyHostToDevice, s));
+  ITN_HIP(h, gemm_grouped(P, natural ? C->dtype : acc_dt, tile_cfg, dbase, dprob, dseg, dtile,
+                          (int64_t)tiles.size(), 0, 0, 0, 1, 0, s));
+  if (!natural) ITN_HIP(h, permute_batch(acc_dt, T, C->dtype, C->data, ditem, dchunk + nchA + nchB, nchC, s));
   return ITN_OK;
 }
 

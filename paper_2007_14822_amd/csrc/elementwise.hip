@@ -99,6 +99,39 @@ hipError_t permute_cast(int in_dtype, const void* in, int out_dtype, void* out, 
   ITN_DISPATCH2(in_dtype, out_dtype, permute_t, in, out, a, s);
 }
 
+// ----------------------------------------------------------- permute batch
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void permute_batch_kernel(const TI* __restrict__ in,
+                                                             TO* __restrict__ out,
+                                                             const PermItem* __restrict__ items,
+                                                             const PermChunk* __restrict__ chunks) {
+  const PermChunk ch = chunks[blockIdx.x];
+  const PermItem& it = items[ch.item];
+  const int rank = it.rank;
+  const int64_t end = ch.first + PERM_CHUNK < it.n ? ch.first + PERM_CHUNK : it.n;
+  for (int64_t j = ch.first + threadIdx.x; j < end; j += blockDim.x) {
+    int64_t rem = j, off = 0;
+    for (int k = rank - 1; k >= 0; --k) {
+      const int64_t c = rem % it.dims[k];
+      rem /= it.dims[k];
+      off += c * it.istr[k];
+    }
+    out[it.dst + j] = conv<TO, TI>(in[it.src + off]);
+  }
+}
+template <typename TI, typename TO>
+static hipError_t permute_batch_t(const void* in, void* out, const PermItem* items,
+                                  const PermChunk* chunks, int64_t nchunks, hipStream_t s) {
+  if (nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL((permute_batch_kernel<TI, TO>), dim3((unsigned)nchunks), dim3(256), 0, s,
+                     static_cast<const TI*>(in), static_cast<TO*>(out), items, chunks);
+  return hipGetLastError();
+}
+hipError_t permute_batch(int in_dtype, const void* in, int out_dtype, void* out, const PermItem* items,
+                         const PermChunk* chunks, int64_t nchunks, hipStream_t s) {
+  ITN_DISPATCH2(in_dtype, out_dtype, permute_batch_t, in, out, items, chunks, nchunks, s);
+}
+
 // --------------------------------------------------------------- transpose
 // 64x64 tiles through LDS: coalesced reads along c, coalesced writes along r.
 // Each element is converted once, as it is loaded, to the output type

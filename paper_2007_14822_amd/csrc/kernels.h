@@ -163,6 +163,24 @@ hipError_t qn_zero_blocks(int dtype, const QnPtrs* ptrs, const int64_t* offs, co
 hipError_t permute_cast(int in_dtype, const void* in, int out_dtype, void* out, int rank,
                         const int64_t* out_dims, const int64_t* in_strides, hipStream_t s);
 
+// Many permutations in one launch (the blocks of a block-sparse operand):
+// item i moves out[dst + j] = in[src + sum_k j_k * istr[k]] for the n
+// elements j (row-major over dims[0..rank)); the launch runs one workgroup
+// per chunk {item, first element} of at most PERM_CHUNK elements.
+constexpr int PERM_CHUNK = 4096;
+struct PermItem {
+  int64_t src, dst, n;
+  int32_t rank, pad;
+  int64_t dims[8];
+  int64_t istr[8];
+};
+struct PermChunk {
+  int32_t item, pad;
+  int64_t first;
+};
+hipError_t permute_batch(int in_dtype, const void* in, int out_dtype, void* out, const PermItem* items,
+                         const PermChunk* chunks, int64_t nchunks, hipStream_t s);
+
 // Batched 2-D transpose with conversion: for each batch z (two levels zb, zc):
 //   out[zb][zc][c][r] = in[zb][zc][r][c]  with explicit strides.
 struct TransposeArgs {
