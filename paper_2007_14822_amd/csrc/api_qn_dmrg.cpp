@@ -397,44 +397,66 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
       ITN_HIP(c.h, gemm_nt64(MT, S.nr, MT, S.nr, rho, n, n, n, S.nr, c.s));  // M^T M
     }
   }
-  // All sectors' eigenproblems in one batched divide-and-conquer call: each
-  // density matrix padded to the largest dimension (the padding is a -1
-  // diagonal block, below every weight; its eigenvectors stay in the
-  // padding), then each sector's eigenvalues and eigenvectors copied out.
-  // One call instead of one per sector: a bond of the Hubbard cylinder has
-  // tens of sectors, and the per-call cost dominated the split.
+  // The sectors' eigenproblems in a few batched divide-and-conquer calls:
+  // sectors sorted by dimension and grouped so that a group's largest is at
+  // most 4 times its smallest, each density matrix padded to its group's
+  // largest dimension (the padding is a -1 diagonal block, below every
+  // weight; its eigenvectors stay in the padding), then each sector's
+  // eigenvalues and eigenvectors copied out.  A bond of the Hubbard cylinder
+  // has tens of sectors; one solver call each cost more than the solves.
+  const int nb = (int)eig.size();
+  std::vector<int> order(nb), pos_of(nb);
+  std::vector<int64_t> evo_of(nb);
+  for (int e = 0; e < nb; ++e) order[e] = e, evo_of[e] = evo, evo += 2 * eig[e].n;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return eig[a].n < eig[b].n; });
   {
-    int64_t nmax = 0;
     std::vector<int64_t> meta;
-    for (const Eig& g : eig) {
-      nmax = std::max(nmax, g.n);
-      meta.push_back(g.n);
-      meta.push_back(g.rho_off);
+    std::vector<std::pair<int, int>> groups;  // [p0, p1) in `order`
+    size_t abytes = 0, wbytes = 0;
+    for (int p = 0; p < nb;) {
+      int q = p + 1;
+      while (q < nb && eig[order[q]].n <= eig[order[p]].n * 4) ++q;
+      groups.push_back({p, q});
+      const int64_t nmax = eig[order[q - 1]].n;
+      abytes += (size_t)(q - p) * nmax * nmax * 8;
+      wbytes += (size_t)(q - p) * nmax * 2 * 8;
+      p = q;
     }
-    const int nb = (int)eig.size();
+    for (int p = 0; p < nb; ++p) {
+      pos_of[order[p]] = p;
+      meta.push_back(eig[order[p]].n);
+      meta.push_back(eig[order[p]].rho_off);
+    }
     ITN_TRY(m->bmeta.ensure(c.h, meta.size() * 8));
-    ITN_TRY(m->bat.ensure(c.h, (size_t)nb * nmax * nmax * 8));
-    ITN_TRY(m->batw.ensure(c.h, (size_t)nb * nmax * 2 * 8));
+    ITN_TRY(m->bat.ensure(c.h, abytes));
+    ITN_TRY(m->batw.ensure(c.h, wbytes));
     ITN_HIP(c.h, hipMemcpy(m->bmeta.p, meta.data(), meta.size() * 8, hipMemcpyHostToDevice));
     double* Ab = m->bat.d();
     double* Wb = m->batw.d();
-    double* Eb = Wb + (size_t)nb * nmax;
-    ITN_HIP(c.h, pad_batch(m->rho.d(), static_cast<const int64_t*>(m->bmeta.p), Ab, nmax, nb, c.s));
-    rocblas_status st = rocsolver_dsyevd_strided_batched(
-        rb, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)nmax, Ab, (rocblas_int)nmax,
-        (rocblas_stride)(nmax * nmax), Wb, (rocblas_stride)nmax, Eb, (rocblas_stride)nmax,
-        static_cast<rocblas_int*>(m->info.p), (rocblas_int)nb);
-    if (st != rocblas_status_success)
-      return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd_strided_batched failed (%d)", (int)st);
-    for (int b = 0; b < nb; ++b) {
-      const int64_t n = eig[b].n, lo = nmax - n;  // the sector's eigenpairs are the top n
-      ITN_HIP(c.h, hipMemcpyAsync(m->ev.d() + evo, Wb + (size_t)b * nmax + lo, n * 8,
-                                  hipMemcpyDeviceToDevice, c.s));
-      // column lo + j of the padded matrix (rows < n) -> row j of the sector's eigenvectors
-      ITN_HIP(c.h, hipMemcpy2DAsync(m->rho.d() + eig[b].rho_off, n * 8,
-                                    Ab + (size_t)b * nmax * nmax + lo * nmax, nmax * 8, n * 8, n,
+    for (const auto& g : groups) {
+      const int cnt = g.second - g.first;
+      const int64_t nmax = eig[order[g.second - 1]].n;
+      double* Eb = Wb + (size_t)cnt * nmax;
+      ITN_HIP(c.h, pad_batch(m->rho.d(), static_cast<const int64_t*>(m->bmeta.p) + 2 * g.first, Ab, nmax,
+                             cnt, c.s));
+      rocblas_status st = rocsolver_dsyevd_strided_batched(
+          rb, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)nmax, Ab, (rocblas_int)nmax,
+          (rocblas_stride)(nmax * nmax), Wb, (rocblas_stride)nmax, Eb, (rocblas_stride)nmax,
+          static_cast<rocblas_int*>(m->info.p) + g.first, (rocblas_int)cnt);
+      if (st != rocblas_status_success)
+        return fail(c.h, ITN_E_HIP, "rocsolver_dsyevd_strided_batched failed (%d)", (int)st);
+      for (int k = 0; k < cnt; ++k) {
+        const int e = order[g.first + k];
+        const int64_t n = eig[e].n, lo = nmax - n;  // the sector's eigenpairs are the top n
+        ITN_HIP(c.h, hipMemcpyAsync(m->ev.d() + evo_of[e], Wb + (size_t)k * nmax + lo, n * 8,
                                     hipMemcpyDeviceToDevice, c.s));
-      evo += 2 * n;
+        // column lo + j of the padded matrix (rows < n) -> row j of the sector's eigenvectors
+        ITN_HIP(c.h, hipMemcpy2DAsync(m->rho.d() + eig[e].rho_off, n * 8,
+                                      Ab + (size_t)k * nmax * nmax + lo * nmax, nmax * 8, n * 8, n,
+                                      hipMemcpyDeviceToDevice, c.s));
+      }
+      Ab += (size_t)cnt * nmax * nmax;
+      Wb += (size_t)cnt * nmax * 2;
     }
   }
   // eigenvalues and solver status to host
@@ -446,8 +468,8 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
   ITN_HIP(c.h, hipStreamSynchronize(c.s));
   evo = 0;
   for (size_t e = 0; e < eig.size(); ++e) {
-    rocblas_int inf = 0;
-    std::memcpy(&inf, pin + ev_tot * 8 + e * sizeof(rocblas_int), sizeof(inf));
+    rocblas_int inf = 0;  // the solver status of sector e is at its position in the sorted order
+    std::memcpy(&inf, pin + ev_tot * 8 + pos_of[e] * sizeof(rocblas_int), sizeof(inf));
     if (inf != 0) return fail(c.h, ITN_E_NOT_CONVERGED, "symmetric eigensolver info=%d at bond %d", (int)inf, i);
     const int64_t n = eig[e].n;
     const double* D = reinterpret_cast<const double*>(pin) + evo;
