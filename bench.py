@@ -500,7 +500,7 @@ def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=DAVIDSON, b
             "f64_matvecs_per_bond": f64 / bonds}
 
 
-def qn_dmrg_leg(h, inp, prec, Lx=8, Ly=4, maxdims=(64, 128, 256, 512, 512)):
+def qn_dmrg_leg(h, inp, prec, Lx=8, Ly=4, maxdims=(128, 512, 1024, 2048, 2048)):
     """Block-sparse two-site sweeps on the U(1) x U(1) Hubbard cylinder
     (Lx x Ly, U/t = 8, half filling from a Neel product state, cutoff 1e-8),
     the bench's small Davidson budget; per sweep energy, time and the
@@ -753,7 +753,7 @@ def main():
     if not args.no_dmrg and not args.only:
         qd = {}
         for prec in ("f64", "bf16"):
-            log("[bench] block-sparse DMRG, Hubbard 8x4 cylinder %s, maxdim up to 512" % prec)
+            log("[bench] block-sparse DMRG, Hubbard 8x4 cylinder %s, maxdim up to 2048" % prec)
             qd[prec] = qn_dmrg_leg(h, inp, prec)
             log("[bench]   %.1f s, E=%.10f" % (qd[prec]["total_seconds"], qd[prec]["sweeps"][-1]["energy"]))
         e64 = qd["f64"]["sweeps"][-1]["energy"]
