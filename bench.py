@@ -500,19 +500,23 @@ def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=DAVIDSON, b
             "f64_matvecs_per_bond": f64 / bonds}
 
 
-def qn_dmrg_leg(h, inp, prec, Lx=8, Ly=4, maxdims=(128, 512, 1024, 2048, 2048)):
+def qn_dmrg_leg(h, inp, prec, Lx=8, Ly=4, maxdims=(128, 512, 1024, 2048, 2048), block=1):
     """Block-sparse two-site sweeps on the U(1) x U(1) Hubbard cylinder
     (Lx x Ly, U/t = 8, half filling from a Neel product state, cutoff 1e-8),
     the bench's small Davidson budget; per sweep energy, time and the
-    phase split."""
+    phase split.  block > 1: block Davidson, `block` vectors per batched
+    matvec (the Krylov budget scaled by the block)."""
     Ws = inp.hubbard_mpo(Lx, Ly, U=8.0)
     N = Lx * Ly
     mps = h.qn_mps(inp.hubbard_site_qn(), [1 + (k % 2) for k in range(N)])
     mpo = h.mpo(Ws)
+    dv = dict(DAVIDSON)
+    if block > 1:
+        dv = {"krylovdim": dv["krylovdim"] * block, "maxiter": dv["maxiter"] * block}
     t0 = time.perf_counter()
     recs = h.qn_dmrg_sweep(mps, mpo, inp.hubbard_mpo_link_qn(Ws[0].shape[0]),
                            [(m, 1e-8) for m in maxdims], prec=prec, eig_tol=1e-10,
-                           allow_unconverged=True, timing=True, **DAVIDSON)
+                           allow_unconverged=True, timing=True, block=block, **dv)
     secs = time.perf_counter() - t0
     total_qn = h.qn_mps_link(mps, N)  # the last link carries the state's (N, 2Sz)
     mps.close()
@@ -520,7 +524,8 @@ def qn_dmrg_leg(h, inp, prec, Lx=8, Ly=4, maxdims=(128, 512, 1024, 2048, 2048)):
     tot = sum(r["matvecs"] for r in recs)
     f64 = sum(r["matvecs_f64"] for r in recs)
     return {"model": "Hubbard %dx%d cylinder, U/t=8, U(1)xU(1) (N, 2Sz), w=%d" % (Lx, Ly, Ws[0].shape[0]),
-            "schedule": [(m, 1e-8) for m in maxdims], "total_seconds": secs, "sweeps": recs,
+            "schedule": [(m, 1e-8) for m in maxdims], "block": block, "davidson": dv,
+            "total_seconds": secs, "sweeps": recs,
             "matvecs": tot, "matvecs_f64": f64, "low_precision_fraction": (tot - f64) / tot,
             "total_qn": [list(q) for q, _ in total_qn]}
 

@@ -471,15 +471,15 @@ class Handle:
 
     def qn_dmrg_sweep(self, mps, mpo, link_qn, sweeps, prec="f64", mindim=1, krylovdim=8,
                       maxiter=100, eig_tol=1e-10, refine=True, energy_tol=0.0,
-                      allow_unconverged=False, timing=False):
+                      allow_unconverged=False, timing=False, block=1):
         """Two-site sweeps on a block-sparse MPS; link_qn: QN tuple of each MPO
-        channel."""
+        channel.  block: Davidson vectors per batched matvec."""
         lq = [tuple(int(x) for x in (q if isinstance(q, (tuple, list)) else (q,))) for q in link_qn]
         larr = (C.c_int32 * (len(lq) * len(lq[0])))(*[x for q in lq for x in q])
         return self._sweep_call(
             lambda prm, res: self.lib.itn_qn_dmrg_sweep(self.h, mps.ptr, mpo.ptr, larr, prm, res), sweeps,
             prec, mindim, krylovdim, maxiter, eig_tol, refine, energy_tol, allow_unconverged, timing, (),
-            0.0, 1)
+            0.0, block)
 
 
 def _qn(keep: _Keep, desc) -> L.itn_tensor:

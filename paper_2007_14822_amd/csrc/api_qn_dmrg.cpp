@@ -165,13 +165,15 @@ struct itn_qn_mps {
   const itn_mpo* env_mpo = nullptr;
   SolverBufs sb;
   DBuf psi, Lp, Rp, mat, matT, rho, ut, prod, ev, info, bat, batw, bmeta;
+  DBuf hdiag, envd, dtab, bx, by;  // block Davidson: H_eff diagonal, its tables, padded batches
   QBT theta, T1, T2;  // two-site tensor and environment intermediates (buffers reused)
   HostPin pin;
   ~itn_qn_mps() {
     for (auto* v : {&A, &L, &R})
       for (auto& t : *v) t.data.release();
     for (QBT* t : {&theta, &T1, &T2}) t->data.release();
-    for (DBuf* b : {&psi, &Lp, &Rp, &mat, &matT, &rho, &ut, &prod, &ev, &info, &bat, &batw, &bmeta})
+    for (DBuf* b : {&psi, &Lp, &Rp, &mat, &matT, &rho, &ut, &prod, &ev, &info, &bat, &batw, &bmeta,
+                    &hdiag, &envd, &dtab, &bx, &by})
       b->release();
     sb.release();
     pin.release();
@@ -599,7 +601,7 @@ struct BondPlan {
   }
 };
 
-itn_status make_plan(QCtx& c, int i, const QBT& psi, int prec, BondPlan& bp) {
+itn_status make_plan(QCtx& c, int i, const QBT& psi, int prec, int nv, BondPlan& bp) {
   itn_qn_mps* m = c.m;
   const int w = c.mpo->w, d = c.mpo->d;
   const int64_t dw[4] = {w, w, d, d};
@@ -624,9 +626,95 @@ itn_status make_plan(QCtx& c, int i, const QBT& psi, int prec, BondPlan& bp) {
   }
   View vl(L.q, L.flux, low ? m->Lp.p : L.d(), et), vr(R.q, R.flux, low ? m->Rp.p : R.d(), et);
   View vp(psi.q, psi.flux, psi.d(), ITN_F64);
-  ITN_TRY(itn_qn_heff_plan(c.h, &vl.t, &w1.t, &w2.t, &vr.t, &vp.t, 1, (itn_prec)prec, &bp.pl));
+  ITN_TRY(itn_qn_heff_plan(c.h, &vl.t, &w1.t, &w2.t, &vr.t, &vp.t, nv, (itn_prec)prec, &bp.pl));
   ITN_TRY(qn_plan_set_direct(bp.pl, 0, 0));
   ITN_TRY(itn_qn_prepare_env(c.h, bp.pl, &vl.t, &vr.t, c.s));
+  return ITN_OK;
+}
+
+// The diagonal of the two-site H_eff at bond i for the block expansion's
+// preconditioner, into m->hdiag (psi's block layout).  A diagonal entry
+// pairs L[a, m0, a] and R[b, m2, b]: charge conservation leaves only the
+// zero-charge MPO channels m0, m2, whose environment diagonals are gathered
+// into dense [chi][wz] tables; Wd[i][j][s1][s2] = sum_m1 W1[m0,m1,s1,s1]
+// W2[m1,m2,s2,s2] over those channels is formed on the host.  The tables
+// are copied from `keep`, which must outlive the stream's next host wait.
+itn_status qn_diag(QCtx& c, int i, const QBT& psi, std::vector<char>& keep) {
+  itn_qn_mps* m = c.m;
+  const int w = c.mpo->w, d = c.mpo->d;
+  const QBT &L = m->L[i], &R = m->R[i + 2];
+  if (!psi.q.sp[0].same_sectors(L.q.sp[0]) || !psi.q.sp[3].same_sectors(R.q.sp[0]))
+    return fail(c.h, ITN_E_SHAPE, "environment and two-site tensor links differ at bond %d", i);
+  std::vector<int32_t> zpos(w, -1);
+  int wz = 0;
+  for (int k = 0; k < c.mlink.nsec; ++k) {
+    const int32_t* q = c.mlink.q(k);
+    if (std::all_of(q, q + c.mlink.nq, [](int32_t v) { return v == 0; }))
+      for (int y = 0; y < c.mlink.dim[k]; ++y) zpos[c.mlink.off[k] + y] = wz++;
+  }
+  const int wzs = std::max(wz, 1);
+  std::vector<double> wd((size_t)wzs * wzs * d * d, 0.0);
+  const double* W1 = c.mpo->site(i);
+  const double* W2 = c.mpo->site(i + 1);
+  for (int m0 = 0; m0 < w; ++m0)
+    for (int m2 = 0; m2 < w; ++m2) {
+      if (zpos[m0] < 0 || zpos[m2] < 0) continue;
+      for (int s1 = 0; s1 < d; ++s1)
+        for (int s2 = 0; s2 < d; ++s2) {
+          double v = 0.0;
+          for (int m1 = 0; m1 < w; ++m1)
+            v += W1[((m0 * w + m1) * d + s1) * d + s1] * W2[((m1 * w + m2) * d + s2) * d + s2];
+          wd[(((size_t)zpos[m0] * wzs + zpos[m2]) * d + s1) * d + s2] = v;
+        }
+    }
+  auto items = [&](const QBT& E, std::vector<EnvDiagItem>& out) -> itn_status {
+    for (size_t b = 0; b < E.q.blocks.size(); ++b) {
+      const auto& k = E.q.blocks[b];
+      if (k[0] != k[2]) continue;
+      const int64_t mg = E.q.sp[1].off[k[1]];
+      if (zpos[mg] < 0)
+        return fail(c.h, ITN_E_FLUX, "environment block on a charged channel has equal link sectors");
+      out.push_back({E.q.off[b], E.q.sp[0].dim[k[0]], E.q.sp[1].dim[k[1]], E.q.sp[0].off[k[0]], zpos[mg]});
+    }
+    return ITN_OK;
+  };
+  std::vector<EnvDiagItem> li, ri;
+  ITN_TRY(items(L, li));
+  ITN_TRY(items(R, ri));
+  std::vector<DiagBlock> db;
+  int64_t most = 0;
+  for (size_t b = 0; b < psi.q.blocks.size(); ++b) {
+    const auto& k = psi.q.blocks[b];
+    DiagBlock q{psi.q.off[b],
+                psi.q.sp[0].dim[k[0]], psi.q.sp[1].dim[k[1]], psi.q.sp[2].dim[k[2]], psi.q.sp[3].dim[k[3]],
+                psi.q.sp[0].off[k[0]], psi.q.sp[1].off[k[1]], psi.q.sp[2].off[k[2]], psi.q.sp[3].off[k[3]]};
+    most = std::max(most, q.da * q.d1 * q.d2 * q.db);
+    db.push_back(q);
+  }
+  const int64_t cl = psi.q.sp[0].total, cr = psi.q.sp[3].total, n = psi.q.elems;
+  // one host block: Wd, the two item lists, the psi block list (8-byte aligned parts)
+  const size_t o_li = wd.size() * 8, o_ri = o_li + li.size() * sizeof(EnvDiagItem),
+               o_db = o_ri + ri.size() * sizeof(EnvDiagItem), bytes = o_db + db.size() * sizeof(DiagBlock);
+  keep.resize(bytes);
+  std::memcpy(keep.data(), wd.data(), wd.size() * 8);
+  if (!li.empty()) std::memcpy(keep.data() + o_li, li.data(), li.size() * sizeof(EnvDiagItem));
+  if (!ri.empty()) std::memcpy(keep.data() + o_ri, ri.data(), ri.size() * sizeof(EnvDiagItem));
+  if (!db.empty()) std::memcpy(keep.data() + o_db, db.data(), db.size() * sizeof(DiagBlock));
+  ITN_TRY(m->dtab.ensure(c.h, bytes));
+  ITN_TRY(m->envd.ensure(c.h, (size_t)(cl + cr) * wzs * 8));
+  ITN_TRY(m->hdiag.ensure(c.h, (size_t)std::max<int64_t>(n, 1) * 8));
+  char* dt = static_cast<char*>(m->dtab.p);
+  double* Ld = m->envd.d();
+  double* Rd = Ld + (size_t)cl * wzs;
+  ITN_HIP(c.h, hipMemcpyAsync(dt, keep.data(), bytes, hipMemcpyHostToDevice, c.s));
+  ITN_HIP(c.h, hipMemsetAsync(Ld, 0, (size_t)(cl + cr) * wzs * 8, c.s));
+  ITN_HIP(c.h, env_diag_gather(L.d(), reinterpret_cast<const EnvDiagItem*>(dt + o_li), (int)li.size(), wzs,
+                               Ld, c.s));
+  ITN_HIP(c.h, env_diag_gather(R.d(), reinterpret_cast<const EnvDiagItem*>(dt + o_ri), (int)ri.size(), wzs,
+                               Rd, c.s));
+  ITN_HIP(c.h, qn_heff_diag(Ld, Rd, reinterpret_cast<const double*>(dt), wzs, d,
+                            reinterpret_cast<const DiagBlock*>(dt + o_db), (int)db.size(), (most + 255) / 256,
+                            m->hdiag.d(), c.s));
   return ITN_OK;
 }
 
@@ -637,18 +725,40 @@ itn_status bond_step(QCtx& c, int i, bool to_right, int maxdim, double cutoff, b
   ITN_TRY(contract(c, m->A[i], {1, 2, 3}, false, m->A[i + 1], {3, 4, 5}, false, {1, 2, 4, 5}, psi, true));
   const int64_t n = psi.q.elems;
   const int prec = c.p->prec;
+  // block Davidson: plans for B vectors per launch; calls with fewer are padded with zero vectors
+  const int B = c.p->block > 1 ? std::min(c.p->block, 8) : 1;
   BondPlan p64, plo;
-  ITN_TRY(make_plan(c, i, psi, ITN_P_F64, p64));
-  if (prec != ITN_P_F64) ITN_TRY(make_plan(c, i, psi, prec, plo));
+  ITN_TRY(make_plan(c, i, psi, ITN_P_F64, B, p64));
+  if (prec != ITN_P_F64) ITN_TRY(make_plan(c, i, psi, prec, B, plo));
+  if (B > 1) {
+    ITN_TRY(m->bx.ensure(c.h, (size_t)B * std::max<int64_t>(n, 1) * 8));
+    ITN_TRY(m->by.ensure(c.h, (size_t)B * std::max<int64_t>(n, 1) * 8));
+  }
   View vp(psi.q, psi.flux, nullptr, ITN_F64), vo(psi.q, psi.flux, nullptr, ITN_F64);
   const Matvec mv = [&](int p, const double* x, double* y, int nv) -> itn_status {
-    for (int v = 0; v < nv; ++v) {
-      vp.t.data = const_cast<double*>(x + (size_t)v * n);
-      vo.t.data = y + (size_t)v * n;
+    for (int v0 = 0; v0 < nv; v0 += B) {
+      const int k = std::min(B, nv - v0);
+      const double* xs = x + (size_t)v0 * n;
+      double* ys = y + (size_t)v0 * n;
+      if (k < B) {
+        ITN_HIP(c.h, hipMemcpyAsync(m->bx.p, xs, (size_t)k * n * 8, hipMemcpyDeviceToDevice, c.s));
+        ITN_HIP(c.h, hipMemsetAsync(m->bx.d() + (size_t)k * n, 0, (size_t)(B - k) * n * 8, c.s));
+        xs = m->bx.d();
+      }
+      vp.t.data = const_cast<double*>(xs);
+      vo.t.data = k < B ? m->by.d() : ys;
       ITN_TRY(itn_qn_heff_apply(c.h, p == ITN_P_F64 ? p64.pl : plo.pl, nullptr, nullptr, &vp.t, &vo.t, c.s));
+      if (k < B)
+        ITN_HIP(c.h, hipMemcpyAsync(ys, m->by.p, (size_t)k * n * 8, hipMemcpyDeviceToDevice, c.s));
     }
     return ITN_OK;
   };
+  std::vector<char> diag_tables;  // read by the diagonal's launches; alive until the solve's host waits
+  const double* diag = nullptr;
+  if (B > 1) {
+    ITN_TRY(qn_diag(c, i, psi, diag_tables));
+    diag = m->hdiag.d();
+  }
   const double tol = c.p->eig_tol > 0 ? c.p->eig_tol : 1e-10;
   const int maxiter = c.p->maxiter > 0 ? c.p->maxiter : 100;
   double e = 0.0, r = 0.0;
@@ -661,7 +771,7 @@ itn_status bond_step(QCtx& c, int i, bool to_right, int maxdim, double cutoff, b
     ITN_HIP(c.h, add_noise(psi.d(), n, 1e-7 / std::sqrt((double)std::max<int64_t>(n, 1)),
                            0x5eedull * 1000003ull + (uint64_t)(c.sweep * 4096 + i * 2 + (to_right ? 0 : 1)),
                            c.s));
-    ITN_TRY(davidson(c, mv, prec, tol, maxiter, psi.d(), n, nullptr, last, &e, &r, &conv));
+    ITN_TRY(davidson(c, mv, prec, tol, maxiter, psi.d(), n, diag, last, &e, &r, &conv));
   }
   c.max_resid = std::max(c.max_resid, r);
   if (!conv && (prec == ITN_P_F64 || c.p->refine)) c.unconverged = true;
@@ -781,7 +891,6 @@ itn_status itn_qn_dmrg_sweep(itn_handle* h, itn_qn_mps* mps, const itn_mpo* mpo,
   if (p->prec != ITN_P_F64 && p->prec != ITN_P_F32 && p->prec != ITN_P_BF16)
     return fail(h, ITN_E_ARG, "unknown precision");
   if (p->northo > 0) return fail(h, ITN_E_UNSUPPORTED, "excited states are not supported on QN sweeps");
-  if (p->block > 1) return fail(h, ITN_E_UNSUPPORTED, "block Davidson is not supported on QN sweeps");
   for (int k = 0; k < p->nsweeps; ++k)
     if (p->maxdim[k] < 1 || p->cutoff[k] < 0) return fail(h, ITN_E_ARG, "bad maxdim/cutoff");
   if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot run sweeps");

@@ -423,6 +423,64 @@ hipError_t heff_diag(const double* L, const double* R, const double* Wd, int w, 
   return hipGetLastError();
 }
 
+// Diagonal entries of one block-sparse environment, E[x][m][x] for the blocks
+// whose two link sectors coincide (their channel sector then carries zero
+// charge): out[(g + x) * wz + zb + y] = E_block[(x * dm + y) * dd + x].
+__global__ void env_diag_gather_kernel(const double* __restrict__ E, const EnvDiagItem* __restrict__ it,
+                                       int nitems, int wz, double* __restrict__ out) {
+  for (int k = blockIdx.y; k < nitems; k += gridDim.y) {
+    const EnvDiagItem e = it[k];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < e.dd * e.dm;
+         t += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t x = t / e.dm, y = t % e.dm;
+      out[(e.g + x) * wz + e.zb + y] = E[e.src + (x * e.dm + y) * e.dd + x];
+    }
+  }
+}
+hipError_t env_diag_gather(const double* E, const EnvDiagItem* items, int nitems, int wz, double* out,
+                           hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  hipLaunchKernelGGL(env_diag_gather_kernel, dim3(4, std::min(nitems, 65535)), dim3(256), 0, s, E, items,
+                     nitems, wz, out);
+  return hipGetLastError();
+}
+
+// Diagonal of the block-sparse two-site H_eff, block by block of psi:
+// D[a, s1, s2, b] = sum_{i, j} Ld[a][i] Wd[i][j][s1][s2] Rd[b][j] over the
+// zero-charge channels i, j (indices global within each space).
+__global__ void qn_heff_diag_kernel(const double* __restrict__ Ld, const double* __restrict__ Rd,
+                                    const double* __restrict__ Wd, int wz, int d,
+                                    const DiagBlock* __restrict__ blk, int nblk, double* __restrict__ D) {
+  for (int k = blockIdx.y; k < nblk; k += gridDim.y) {
+    const DiagBlock q = blk[k];
+    const int64_t cnt = q.da * q.d1 * q.d2 * q.db;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cnt;
+         t += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t z = t % q.db, r = t / q.db;
+      const int64_t y2 = r % q.d2, r2 = r / q.d2;
+      const int64_t y1 = r2 % q.d1, x = r2 / q.d1;
+      const double* la = Ld + (q.ga + x) * wz;
+      const double* rb = Rd + (q.gb + z) * wz;
+      const int64_t c = (q.g1 + y1) * d + (q.g2 + y2);
+      double acc = 0.0;
+      for (int i = 0; i < wz; ++i) {
+        if (la[i] == 0.0) continue;
+        double u = 0.0;
+        for (int j = 0; j < wz; ++j) u += Wd[((int64_t)i * wz + j) * d * d + c] * rb[j];
+        acc += la[i] * u;
+      }
+      D[q.off + t] = acc;
+    }
+  }
+}
+hipError_t qn_heff_diag(const double* Ld, const double* Rd, const double* Wd, int wz, int d,
+                        const DiagBlock* blocks, int nblk, int64_t chunks, double* D, hipStream_t s) {
+  if (nblk == 0) return hipSuccess;
+  hipLaunchKernelGGL(qn_heff_diag_kernel, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(chunks, 64)),
+                     std::min(nblk, 65535)), dim3(256), 0, s, Ld, Rd, Wd, wz, d, blocks, nblk, D);
+  return hipGetLastError();
+}
+
 // r[i] /= (D[i] - theta), denominators of magnitude below eps clipped to eps
 // (Davidson's diagonal preconditioner).
 __global__ void precond_diag_kernel(double* __restrict__ r, const double* __restrict__ D, double theta,

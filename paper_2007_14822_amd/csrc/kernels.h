@@ -249,6 +249,23 @@ hipError_t fill(void* x, int dtype, double v, int64_t n, hipStream_t s);
 // (Wd[m0][m2][s1*d + s2] = sum_m1 W1[m0,m1,s1,s1] W2[m1,m2,s2,s2]), D [cl, d2, cr].
 hipError_t heff_diag(const double* L, const double* R, const double* Wd, int w, int d2, int64_t cl,
                      int64_t cr, double* D, hipStream_t s);
+// Block-sparse H_eff diagonal.  EnvDiagItem: one environment block whose two
+// link sectors coincide, data at `src` as [dd][dm][dd]; its diagonal goes to
+// out[(g + x) * wz + zb + y] (g: the link sector's global offset, zb: the
+// channel sector's first position among the wz zero-charge channels).
+struct EnvDiagItem {
+  int64_t src, dd, dm, g, zb;
+};
+hipError_t env_diag_gather(const double* E, const EnvDiagItem* items, int nitems, int wz, double* out,
+                           hipStream_t s);
+// DiagBlock: one psi block at element offset `off`, extents [da][d1][d2][db],
+// global offsets of its sectors ga, g1, g2, gb.  D = sum_{i,j} Ld[a][i]
+// Wd[i][j][s1][s2] Rd[b][j] (Ld [chi_l][wz], Rd [chi_r][wz], Wd [wz][wz][d][d]).
+struct DiagBlock {
+  int64_t off, da, d1, d2, db, ga, g1, g2, gb;
+};
+hipError_t qn_heff_diag(const double* Ld, const double* Rd, const double* Wd, int wz, int d,
+                        const DiagBlock* blocks, int nblk, int64_t chunks, double* D, hipStream_t s);
 // x[i] += eps * (uniform in [-1, 1) from a counter-based hash of (seed, i)).
 hipError_t add_noise(double* x, int64_t n, double eps, uint64_t seed, hipStream_t s);
 // r /= (D - theta) element-wise, denominators clipped to magnitude >= eps.
