@@ -473,6 +473,9 @@ def time_qn(h, torch, np, inp, which, prec, nv, steps, warmup, split_mpo=False):
 # that fixes the converged energy.
 DAVIDSON = {"krylovdim": 4, "maxiter": 8}
 DAVIDSON_TIGHT = {"krylovdim": 8, "maxiter": 60}
+# block Davidson on the block-sparse sweeps: 4 residuals per step, two steps
+# between restarts (8 basis vectors), 12 vectors applied per bond
+DAVIDSON_BLOCK4 = {"krylovdim": 8, "maxiter": 12}
 
 
 def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=DAVIDSON, block=1):
@@ -500,18 +503,19 @@ def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=DAVIDSON, b
             "f64_matvecs_per_bond": f64 / bonds}
 
 
-def qn_dmrg_leg(h, inp, prec, Lx=8, Ly=4, maxdims=(128, 512, 1024, 2048, 2048), block=1):
+def qn_dmrg_leg(h, inp, prec, Lx=8, Ly=4, maxdims=(128, 512, 1024, 2048, 2048), block=1, davidson=None):
     """Block-sparse two-site sweeps on the U(1) x U(1) Hubbard cylinder
     (Lx x Ly, U/t = 8, half filling from a Neel product state, cutoff 1e-8),
     the bench's small Davidson budget; per sweep energy, time and the
     phase split.  block > 1: block Davidson, `block` vectors per batched
-    matvec (the Krylov budget scaled by the block)."""
+    matvec (the Krylov budget `davidson`, else the small one scaled by the
+    block)."""
     Ws = inp.hubbard_mpo(Lx, Ly, U=8.0)
     N = Lx * Ly
     mps = h.qn_mps(inp.hubbard_site_qn(), [1 + (k % 2) for k in range(N)])
     mpo = h.mpo(Ws)
-    dv = dict(DAVIDSON)
-    if block > 1:
+    dv = dict(davidson or DAVIDSON)
+    if block > 1 and davidson is None:
         dv = {"krylovdim": dv["krylovdim"] * block, "maxiter": dv["maxiter"] * block}
     t0 = time.perf_counter()
     recs = h.qn_dmrg_sweep(mps, mpo, inp.hubbard_mpo_link_qn(Ws[0].shape[0]),
@@ -763,6 +767,10 @@ def main():
             log("[bench]   %.1f s, E=%.10f" % (qd[prec]["total_seconds"], qd[prec]["sweeps"][-1]["energy"]))
         e64 = qd["f64"]["sweeps"][-1]["energy"]
         qd["bf16"]["rel_err_vs_f64_run"] = abs(qd["bf16"]["sweeps"][-1]["energy"] - e64) / abs(e64)
+        log("[bench] block-sparse DMRG, Hubbard 8x4 cylinder bf16, block Davidson (4 vectors per launch)")
+        qd["bf16_block4"] = qn_dmrg_leg(h, inp, "bf16", block=4, davidson=DAVIDSON_BLOCK4)
+        log("[bench]   %.1f s, E=%.10f" % (qd["bf16_block4"]["total_seconds"],
+                                          qd["bf16_block4"]["sweeps"][-1]["energy"]))
         line["qn_dmrg"] = qd
         log("[bench] excited state by energy penalty, S=1/2 chain N=40")
         line["excited_state"] = excited_leg(h, np, inp)

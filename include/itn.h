@@ -381,7 +381,8 @@ typedef struct {
   double weight;
   /* Block size of the Davidson expansion: each step adds the residuals of
    * the `block` lowest Ritz pairs and applies H_eff to them in one batched
-   * itn_heff_apply (nv = block).  0 or 1: one vector per step. */
+   * itn_heff_apply (itn_qn_heff_apply on block-sparse sweeps; nv = block,
+ * at most 8).  0 or 1: one vector per step. */
   int32_t block;
 } itn_sweep_params;
 
@@ -440,8 +441,10 @@ itn_status itn_qn_mps_get_site(itn_handle* h, const itn_qn_mps* mps, int32_t i, 
  * s':Out, s:In] with zero flux; a nonzero MPO entry outside the allowed
  * blocks is ITN_E_FLUX).  At each bond the local problem is the planned
  * block-sparse H_eff (itn_qn_heff_plan), the eigensolver that of
- * itn_dmrg_sweep (precision and refinement as there; block must be <= 1,
- * no excited states), and the bond is split per charge sector of the new
+ * itn_dmrg_sweep (precision, refinement and block as there: with block > 1
+ * the plans carry `block` vectors per launch and the preconditioner is the
+ * block-sparse H_eff diagonal; no excited states: ITN_E_UNSUPPORTED), and
+ * the bond is split per charge sector of the new
  * link: each sector's density matrix is diagonalised and the truncation of
  * Sec. 5 is applied to the weights of all sectors together; environments are
  * block-sparse contractions.  The total QN is conserved exactly. */
