@@ -166,12 +166,14 @@ struct itn_qn_mps {
   SolverBufs sb;
   DBuf psi, Lp, Rp, mat, matT, rho, ut, prod, ev, info, bat, batw, bmeta;
   DBuf hdiag, envd, dtab, bx, by;  // block Davidson: H_eff diagonal, its tables, padded batches
+  DBuf ctab[4];                    // bond split: tables of its batched copies
   QBT theta, T1, T2;  // two-site tensor and environment intermediates (buffers reused)
   HostPin pin;
   ~itn_qn_mps() {
     for (auto* v : {&A, &L, &R})
       for (auto& t : *v) t.data.release();
     for (QBT* t : {&theta, &T1, &T2}) t->data.release();
+    for (DBuf& b : ctab) b.release();
     for (DBuf* b : {&psi, &Lp, &Rp, &mat, &matT, &rho, &ut, &prod, &ev, &info, &bat, &batw, &bmeta,
                     &hdiag, &envd, &dtab, &bx, &by})
       b->release();
@@ -313,6 +315,36 @@ hipError_t transpose_sub(const double* in, int64_t ld, double* out, int64_t rows
 
 // Split psi (block-sparse [a, s1, s2, b]) at bond i into sites i, i+1, sector
 // by sector of the new link charge q = q(a) + q(s1).
+// Strided copies collected and run as one launch.  The table goes up with a
+// blocking copy: each table buffer is read by one phase of the bond split,
+// and a host wait on the stream separates its last readers from the next
+// upload (the split's own wait for the eigenvalues, the eigensolver's).
+struct CopyList {
+  std::vector<Copy2D> items;
+  std::vector<PermChunk> chunks;
+  void add(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols) {
+    if (rows <= 0 || cols <= 0) return;
+    items.push_back(Copy2D{src, dst, rows, cols, lds, ldd});
+    for (int64_t f = 0; f < rows * cols; f += PERM_CHUNK)
+      chunks.push_back(PermChunk{(int32_t)items.size() - 1, 0, f});
+  }
+  itn_status run(QCtx& c, DBuf& tab) {
+    if (chunks.empty()) return ITN_OK;
+    const size_t bi = items.size() * sizeof(Copy2D), bc = chunks.size() * sizeof(PermChunk);
+    std::vector<char> host(bi + bc);
+    std::memcpy(host.data(), items.data(), bi);
+    std::memcpy(host.data() + bi, chunks.data(), bc);
+    ITN_TRY(tab.ensure(c.h, bi + bc));
+    ITN_HIP(c.h, hipMemcpy(tab.p, host.data(), bi + bc, hipMemcpyHostToDevice));
+    const char* d = static_cast<const char*>(tab.p);
+    ITN_HIP(c.h, copy2d_batch(reinterpret_cast<const Copy2D*>(d), reinterpret_cast<const PermChunk*>(d + bi),
+                              (int64_t)chunks.size(), c.s));
+    items.clear();
+    chunks.clear();
+    return ITN_OK;
+  }
+};
+
 itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, double cutoff, double* trunc) {
   itn_qn_mps* m = c.m;
   const QSpace &sa = psi.q.sp[0], &s1 = psi.q.sp[1], &s2 = psi.q.sp[2], &sb = psi.q.sp[3];
@@ -373,10 +405,10 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
   ITN_TRY(m->ev.ensure(c.h, ev_tot * 8));
   ITN_TRY(m->info.ensure(c.h, 64 + eig.size() * sizeof(rocblas_int)));
   int64_t evo = 0;
-  for (size_t e = 0; e < eig.size(); ++e) {
+  CopyList cpy;
+  for (size_t e = 0; e < eig.size(); ++e) {  // gather psi blocks into M_q [nr][nc]
     Sec& S = *eig[e].S;
     double* M = m->mat.d() + eig[e].mat_off;
-    // gather psi blocks into M_q [nr][nc]
     for (size_t r = 0; r < S.rows.size(); ++r)
       for (size_t cc = 0; cc < S.cols.size(); ++cc) {
         const std::vector<int32_t> blk = {S.rows[r].first, S.rows[r].second, S.cols[cc].first,
@@ -385,10 +417,13 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
         if (it == psi.q.index.end()) return fail(c.h, ITN_E_FLUX, "internal: psi block missing");
         const int64_t br = (int64_t)sa.dim[blk[0]] * s1.dim[blk[1]];
         const int64_t bc = (int64_t)s2.dim[blk[2]] * sb.dim[blk[3]];
-        ITN_HIP(c.h, hipMemcpy2DAsync(M + S.roff[r] * S.nc + S.coff[cc], S.nc * 8,
-                                      psi.d() + psi.q.off[it->second], bc * 8, bc * 8, br,
-                                      hipMemcpyDeviceToDevice, c.s));
+        cpy.add(psi.d() + psi.q.off[it->second], bc, M + S.roff[r] * S.nc + S.coff[cc], S.nc, br, bc);
       }
+  }
+  ITN_TRY(cpy.run(c, m->ctab[0]));
+  for (size_t e = 0; e < eig.size(); ++e) {
+    Sec& S = *eig[e].S;
+    double* M = m->mat.d() + eig[e].mat_off;
     double* rho = m->rho.d() + eig[e].rho_off;
     const int64_t n = eig[e].n;
     if (to_right) {
@@ -450,16 +485,15 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
       for (int k = 0; k < cnt; ++k) {
         const int e = order[g.first + k];
         const int64_t n = eig[e].n, lo = nmax - n;  // the sector's eigenpairs are the top n
-        ITN_HIP(c.h, hipMemcpyAsync(m->ev.d() + evo_of[e], Wb + (size_t)k * nmax + lo, n * 8,
-                                    hipMemcpyDeviceToDevice, c.s));
+        cpy.add(Wb + (size_t)k * nmax + lo, 0, m->ev.d() + evo_of[e], 0, 1, n);
         // column lo + j of the padded matrix (rows < n) -> row j of the sector's eigenvectors
-        ITN_HIP(c.h, hipMemcpy2DAsync(m->rho.d() + eig[e].rho_off, n * 8,
-                                      Ab + (size_t)k * nmax * nmax + lo * nmax, nmax * 8, n * 8, n,
-                                      hipMemcpyDeviceToDevice, c.s));
+        cpy.add(Ab + (size_t)k * nmax * nmax + lo * nmax, nmax, m->rho.d() + eig[e].rho_off, n, n, n);
       }
       Ab += (size_t)cnt * nmax * nmax;
       Wb += (size_t)cnt * nmax * 2;
     }
+    // after every group's solve: the copies write over density matrices the padding read
+    ITN_TRY(cpy.run(c, m->ctab[1]));
   }
   // eigenvalues and solver status to host
   ITN_TRY(m->pin.ensure(c.h, ev_tot * 8 + eig.size() * sizeof(rocblas_int) + 64));
@@ -542,14 +576,19 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
   for (int k = 0; k < nl.nsec; ++k) ut_tot += (int64_t)kq[e_of_sector[k]] * eig[e_of_sector[k]].n;
   ITN_TRY(m->ut.ensure(c.h, std::max<int64_t>(ut_tot, 1) * 8));
   int64_t uo = 0;
+  for (int k = 0; k < nl.nsec; ++k) {  // Ut [kk][n]: kept eigenvectors, largest first (rows reversed)
+    const Eig& E = eig[e_of_sector[k]];
+    const int64_t n = E.n, kk = kq[e_of_sector[k]];
+    cpy.add(m->rho.d() + E.rho_off + (n - 1) * n, -n, m->ut.d() + uo, n, kk, n);
+    uo += kk * n;
+  }
+  ITN_TRY(cpy.run(c, m->ctab[2]));
+  uo = 0;
   for (int k = 0; k < nl.nsec; ++k) {
     const Eig& E = eig[e_of_sector[k]];
     const Sec& S = *E.S;
     const int64_t n = E.n, kk = kq[e_of_sector[k]];
-    const double* rho = m->rho.d() + E.rho_off;
-    double* Ut = m->ut.d() + uo;  // [kk][n]: kept eigenvectors, largest first
-    for (int64_t j = 0; j < kk; ++j)
-      ITN_HIP(c.h, hipMemcpyAsync(Ut + j * n, rho + (n - 1 - j) * n, n * 8, hipMemcpyDeviceToDevice, c.s));
+    double* Ut = m->ut.d() + uo;
     const double* M = m->mat.d() + E.mat_off;
     double* P = m->prod.d() + E.mat_off;  // kk x nc (right) or nr x kk (left)
     if (to_right) {
@@ -566,8 +605,7 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
       for (size_t cc = 0; cc < S.cols.size(); ++cc) {
         const std::vector<int32_t> blk = {k, S.cols[cc].first, S.cols[cc].second};
         const int64_t bc = (int64_t)s2.dim[blk[1]] * sb.dim[blk[2]];
-        ITN_HIP(c.h, hipMemcpy2DAsync(Aj.d() + Aj.q.off[Aj.q.index.at(blk)], bc * 8, P + S.coff[cc],
-                                      S.nc * 8, bc * 8, kk, hipMemcpyDeviceToDevice, c.s));
+        cpy.add(P + S.coff[cc], S.nc, Aj.d() + Aj.q.off[Aj.q.index.at(blk)], bc, kk, bc);
       }
     } else {
       // A_{i+1} rows of V^T (right-orthonormal); A_i = M V / |S_kept|
@@ -576,18 +614,17 @@ itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, doub
       for (size_t r = 0; r < S.rows.size(); ++r) {
         const std::vector<int32_t> blk = {S.rows[r].first, S.rows[r].second, k};
         const int64_t br = (int64_t)sa.dim[blk[0]] * s1.dim[blk[1]];
-        ITN_HIP(c.h, hipMemcpyAsync(Ai.d() + Ai.q.off[Ai.q.index.at(blk)], P + S.roff[r] * kk,
-                                    br * kk * 8, hipMemcpyDeviceToDevice, c.s));
+        cpy.add(P + S.roff[r] * kk, kk, Ai.d() + Ai.q.off[Ai.q.index.at(blk)], kk, br, kk);
       }
       for (size_t cc = 0; cc < S.cols.size(); ++cc) {
         const std::vector<int32_t> blk = {k, S.cols[cc].first, S.cols[cc].second};
         const int64_t bc = (int64_t)s2.dim[blk[1]] * sb.dim[blk[2]];
-        ITN_HIP(c.h, hipMemcpy2DAsync(Aj.d() + Aj.q.off[Aj.q.index.at(blk)], bc * 8, Ut + S.coff[cc], n * 8,
-                                      bc * 8, kk, hipMemcpyDeviceToDevice, c.s));
+        cpy.add(Ut + S.coff[cc], n, Aj.d() + Aj.q.off[Aj.q.index.at(blk)], bc, kk, bc);
       }
     }
     uo += kk * n;
   }
+  ITN_TRY(cpy.run(c, m->ctab[3]));
   m->link[i + 1] = nl;
   return ITN_OK;
 }

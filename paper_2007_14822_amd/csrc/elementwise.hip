@@ -132,6 +132,23 @@ hipError_t permute_batch(int in_dtype, const void* in, int out_dtype, void* out,
   ITN_DISPATCH2(in_dtype, out_dtype, permute_batch_t, in, out, items, chunks, nchunks, s);
 }
 
+__global__ __launch_bounds__(256) void copy2d_batch_kernel(const Copy2D* __restrict__ items,
+                                                            const PermChunk* __restrict__ chunks) {
+  const PermChunk ch = chunks[blockIdx.x];
+  const Copy2D it = items[ch.item];
+  const int64_t n = it.rows * it.cols;
+  const int64_t end = ch.first + PERM_CHUNK < n ? ch.first + PERM_CHUNK : n;
+  for (int64_t j = ch.first + threadIdx.x; j < end; j += blockDim.x) {
+    const int64_t r = j / it.cols, c = j - r * it.cols;
+    it.dst[r * it.ldd + c] = it.src[r * it.lds + c];
+  }
+}
+hipError_t copy2d_batch(const Copy2D* items, const PermChunk* chunks, int64_t nchunks, hipStream_t s) {
+  if (nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy2d_batch_kernel, dim3((unsigned)nchunks), dim3(256), 0, s, items, chunks);
+  return hipGetLastError();
+}
+
 // --------------------------------------------------------------- transpose
 // 64x64 tiles through LDS: coalesced reads along c, coalesced writes along r.
 // Each element is converted once, as it is loaded, to the output type

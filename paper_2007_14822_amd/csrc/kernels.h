@@ -180,6 +180,16 @@ struct PermChunk {
 };
 hipError_t permute_batch(int in_dtype, const void* in, int out_dtype, void* out, const PermItem* items,
                          const PermChunk* chunks, int64_t nchunks, hipStream_t s);
+// Many strided FP64 2D copies in one launch: item i copies rows x cols
+// elements, dst[r * ldd + c] = src[r * lds + c] (lds < 0 walks the source
+// rows backwards); one workgroup per chunk {item, first element} of at most
+// PERM_CHUNK elements.  Items must not overlap in their destinations.
+struct Copy2D {
+  const double* src;
+  double* dst;
+  int64_t rows, cols, lds, ldd;
+};
+hipError_t copy2d_batch(const Copy2D* items, const PermChunk* chunks, int64_t nchunks, hipStream_t s);
 
 // Batched 2-D transpose with conversion: for each batch z (two levels zb, zc):
 //   out[zb][zc][c][r] = in[zb][zc][r][c]  with explicit strides.
