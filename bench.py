@@ -553,6 +553,9 @@ def main():
     ap.add_argument("--qn-which", default="c3,c4,c4w38,c4z4",
                     help="block-sparse workloads of --qn-only (comma list)")
     ap.add_argument("--qn-prec", default="bf16,f64", help="precisions of --qn-only (comma list)")
+    ap.add_argument("--qn-dmrg-only", action="store_true",
+                    help="run the block-sparse Hubbard sweeps only, precisions of --qn-prec (profiling runs)")
+    ap.add_argument("--qn-dmrg-block", type=int, default=1, help="Davidson block of --qn-dmrg-only")
     ap.add_argument("--no-splitblocks", action="store_true",
                     help="--qn-only without the one-sector-per-channel MPO legs")
     ap.add_argument("--dmrg-large", action="store_true",
@@ -580,8 +583,15 @@ def main():
 
     chi, d = args.chi, args.d
     h = itn.Handle(0)
-    if args.qn_only or args.dmrg_only:
+    if args.qn_only or args.dmrg_only or args.qn_dmrg_only:
         out = {}
+        if args.qn_dmrg_only:  # the block-sparse Hubbard sweeps alone (profiling runs)
+            for prec in args.qn_prec.split(","):
+                log("[bench] block-sparse DMRG, Hubbard 8x4 cylinder %s, block %d" % (prec, args.qn_dmrg_block))
+                out["qn_dmrg_" + prec] = qn_dmrg_leg(
+                    h, inp, prec, block=args.qn_dmrg_block,
+                    davidson=DAVIDSON_BLOCK4 if args.qn_dmrg_block == 4 else None)
+                log("[bench]   %.1f s" % out["qn_dmrg_" + prec]["total_seconds"])
         if args.qn_only:
             nvs = {"c3": 1, "c4": 4, "c4w38": 4, "c4z4": 4}
             for which in args.qn_which.split(","):

@@ -255,8 +255,7 @@ struct itn_plan {
       if (exec_pe) (void)hipGraphExecDestroy(exec_pe);
       if (graph_pe) (void)hipGraphDestroy(graph_pe);
       if (cap) (void)hipStreamDestroy(cap);
-      for (void* p : {(void*)dtab, psiT, X, Z, Lp, Rp, zero})
-        if (p) (void)hipFree(p);
+      if (dtab) (void)hipFree(dtab);  // tables and work buffers: one allocation
     }
   }
 };
@@ -866,14 +865,32 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   add(pl.cp.size() * sizeof(QnCopy));
   add(pl.zoff.size() * 8);
   add(pl.zsize.size() * 8);
-  ITN_HIP(h, hipMalloc(&pl.dtab, bytes + 256));
+  // The work buffers follow the tables in the same allocation, each 256-byte
+  // aligned; their padding must read as zero (never rewritten).
+  const int es = dtype_size(pl.pt), xs = dtype_size(pl.xt);
+  size_t wbytes = 0;
+  auto wadd = [&](size_t n) {
+    const size_t o = wbytes;
+    wbytes += (std::max<size_t>(256, n) + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t o_psiT = wadd((size_t)pl.nv * pl.psiT_elems * es);
+  // + max b-sector width: zero-weight W-stage entries read X[v * X_elems + b]
+  const size_t o_X = wadd(((size_t)pl.nv * pl.X_elems + (size_t)pl.max_db) * xs);
+  const size_t o_Z = wadd((size_t)pl.nv * pl.Z_elems * es);
+  const size_t o_Lp = wadd((size_t)pl.Lp_elems * es), o_Rp = wadd((size_t)pl.Rp_elems * es);
+  const size_t o_zero = wadd(256);
+  ITN_HIP(h, hipMalloc(&pl.dtab, bytes + wbytes));
+  // tables laid out in a host mirror, then one copy
+  std::vector<char> host(bytes, 0);
   char* p = pl.dtab;
   pl.dptrs = carve<QnDevPtrs>(p, 1);
   auto put = [&](auto*& dst, const auto& vec) -> hipError_t {
     using E = typename std::remove_reference<decltype(vec)>::type::value_type;
     dst = carve<E>(p, vec.size());
-    if (vec.empty()) return hipSuccess;
-    return hipMemcpy(dst, vec.data(), vec.size() * sizeof(E), hipMemcpyHostToDevice);
+    if (!vec.empty())
+      std::memcpy(host.data() + (reinterpret_cast<char*>(dst) - pl.dtab), vec.data(), vec.size() * sizeof(E));
+    return hipSuccess;
   };
   ITN_HIP(h, put(pl.dp1, pl.p1));
   ITN_HIP(h, put(pl.dp4, pl.p4));
@@ -901,20 +918,16 @@ itn_status upload(itn_handle* h, itn_plan& pl) {
   ITN_HIP(h, put(pl.dcp, pl.cp));
   ITN_HIP(h, put(pl.dzoff, pl.zoff));
   ITN_HIP(h, put(pl.dzsize, pl.zsize));
-  const int es = dtype_size(pl.pt), xs = dtype_size(pl.xt);
-  auto zalloc = [&](void** p, size_t bytes) -> hipError_t {
-    bytes = std::max<size_t>(256, bytes);
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return e;
-    return hipMemset(*p, 0, bytes);  // padding must read as zero (never rewritten)
-  };
-  ITN_HIP(h, zalloc(&pl.psiT, (size_t)pl.nv * pl.psiT_elems * es));
-  // + max b-sector width: zero-weight W-stage entries read X[v * X_elems + b]
-  ITN_HIP(h, zalloc(&pl.X, ((size_t)pl.nv * pl.X_elems + (size_t)pl.max_db) * xs));
-  ITN_HIP(h, zalloc(&pl.Z, (size_t)pl.nv * pl.Z_elems * es));
-  ITN_HIP(h, zalloc(&pl.Lp, (size_t)pl.Lp_elems * es));
-  ITN_HIP(h, zalloc(&pl.Rp, (size_t)pl.Rp_elems * es));
-  ITN_HIP(h, zalloc(&pl.zero, 256));
+  if (p - pl.dtab > (std::ptrdiff_t)bytes) return fail(h, ITN_E_WORKSPACE, "internal: plan tables overrun");
+  ITN_HIP(h, hipMemcpy(pl.dtab, host.data(), bytes, hipMemcpyHostToDevice));
+  char* w0 = pl.dtab + bytes;
+  pl.psiT = w0 + o_psiT;
+  pl.X = w0 + o_X;
+  pl.Z = w0 + o_Z;
+  pl.Lp = w0 + o_Lp;
+  pl.Rp = w0 + o_Rp;
+  pl.zero = w0 + o_zero;
+  ITN_HIP(h, hipMemset(w0, 0, wbytes));
   ITN_HIP(h, hipDeviceSynchronize());
   return ITN_OK;
 }
