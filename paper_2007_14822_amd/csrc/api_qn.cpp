@@ -26,6 +26,7 @@
 #include <functional>
 #include <map>
 #include <tuple>
+#include <unordered_map>
 #include <mutex>
 #include <sstream>
 
@@ -85,6 +86,42 @@ itn_status read_qtensor(itn_handle* h, const itn_tensor* t, int rank, const int*
   }
   out.elems = expect;
   return ITN_OK;
+}
+
+// Number of flux-allowed blocks (zero flux) of t: the charge sums of the
+// first half of the indices tallied, then matched against the second half's.
+int64_t count_allowed(const QTensor& t) {
+  const int nq = t.sp[0].nq, h = t.rank / 2;
+  const std::vector<int32_t>& mod = t.sp[0].mod;
+  auto sums = [&](int i0, int i1, const std::function<void(const std::vector<int64_t>&)>& f) {
+    std::vector<int64_t> acc(nq, 0);
+    std::function<void(int)> rec = [&](int i) {
+      if (i == i1) {
+        f(acc);
+        return;
+      }
+      for (int k = 0; k < t.sp[i].nsec; ++k) {
+        for (int c = 0; c < nq; ++c) acc[c] += t.sp[i].arrow * (int64_t)t.sp[i].q(k)[c];
+        rec(i + 1);
+        for (int c = 0; c < nq; ++c) acc[c] -= t.sp[i].arrow * (int64_t)t.sp[i].q(k)[c];
+      }
+    };
+    rec(i0);
+  };
+  std::map<std::vector<int32_t>, int64_t> left;
+  sums(0, h, [&](const std::vector<int64_t>& a) {
+    std::vector<int32_t> r(nq);
+    for (int c = 0; c < nq; ++c) r[c] = qn_red(a[c], mod[c]);
+    ++left[r];
+  });
+  int64_t n = 0;
+  sums(h, t.rank, [&](const std::vector<int64_t>& a) {
+    std::vector<int32_t> r(nq);
+    for (int c = 0; c < nq; ++c) r[c] = qn_red(-a[c], mod[c]);
+    auto it = left.find(r);
+    if (it != left.end()) n += it->second;
+  });
+  return n;
 }
 
 bool distinct_qns(const QSpace& s) {
@@ -474,8 +511,9 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     return fail(h, ITN_E_SHAPE, "W2's site indices and psi's s2 differ");
   if (!distinct_qns(P.sp[0]) || !distinct_qns(P.sp[3]))
     return fail(h, ITN_E_UNSUPPORTED, "bond indices must have distinct sector QNs");
-  // psi must hold every allowed block (the output block set is psi's)
-  if (allowed_blocks(P) != P.blocks)
+  // psi must hold every allowed block (the output block set is psi's); its
+  // stored blocks are unique and allowed, so counting the allowed ones suffices
+  if (count_allowed(P) != (int64_t)P.blocks.size())
     return fail(h, ITN_E_SHAPE, "psi must store every flux-allowed block");
   const int w = (int)W1.sp[0].total, d1 = (int)P.sp[1].total, d2 = (int)P.sp[2].total;
   if (W2.sp[0].total != w) return fail(h, ITN_E_SHAPE, "W1 and W2 bond dimensions differ");
@@ -483,27 +521,34 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     return fail(h, ITN_E_DTYPE, "W1, W2 must be host F64 dense arrays");
   const double* w1 = static_cast<const double*>(W1t->data);
   const double* w2 = static_cast<const double*>(W2t->data);
-  // the MPO tensors must respect their own charges
-  auto sector_of = [](const QSpace& s, int g) {
-    int k = 0;
-    while (k + 1 < s.nsec && s.off[k + 1] <= g) ++k;
-    return k;
+  // the MPO tensors must respect their own charges (each block's flux
+  // computed once, then looked up per nonzero entry)
+  auto sectors_of = [](const QSpace& s) {
+    std::vector<int> r((size_t)s.total);
+    for (int k = 0; k < s.nsec; ++k)
+      for (int64_t g = s.off[k]; g < s.off[k] + s.dim[k]; ++g) r[(size_t)g] = k;
+    return r;
   };
   for (int which = 0; which < 2; ++which) {
     const QTensor& Wt = which ? W2 : W1;
     const double* wd = which ? w2 : w1;
     const int d = which ? d2 : d1;
+    const std::vector<int> k0 = sectors_of(Wt.sp[0]), k1 = sectors_of(Wt.sp[1]), k2 = sectors_of(Wt.sp[2]),
+                           k3 = sectors_of(Wt.sp[3]);
+    const int n1 = Wt.sp[1].nsec, n2 = Wt.sp[2].nsec, n3 = Wt.sp[3].nsec;
+    std::vector<int8_t> ok((size_t)Wt.sp[0].nsec * n1 * n2 * n3, -1);  // -1: not yet computed
     for (int a = 0; a < w; ++a)
       for (int b = 0; b < w; ++b)
         for (int sp = 0; sp < d; ++sp)
           for (int s = 0; s < d; ++s) {
             if (wd[((a * w + b) * d + sp) * d + s] == 0.0) continue;
-            std::vector<int32_t> blk = {sector_of(Wt.sp[0], a), sector_of(Wt.sp[1], b),
-                                        sector_of(Wt.sp[2], sp), sector_of(Wt.sp[3], s)};
-            for (int c = 0; c < nq; ++c)
-              if (block_flux(Wt, blk)[c] != 0)
-                return fail(h, ITN_E_FLUX, "W%d has a nonzero entry outside its allowed blocks",
-                            which + 1);
+            int8_t& f = ok[(((size_t)k0[a] * n1 + k1[b]) * n2 + k2[sp]) * n3 + k3[s]];
+            if (f < 0) {
+              const auto fl = block_flux(Wt, {k0[a], k1[b], k2[sp], k3[s]});
+              f = std::all_of(fl.begin(), fl.end(), [](int32_t v) { return v == 0; }) ? 1 : 0;
+            }
+            if (!f)
+              return fail(h, ITN_E_FLUX, "W%d has a nonzero entry outside its allowed blocks", which + 1);
           }
   }
   const QSpace& SA = P.sp[0];
@@ -741,6 +786,57 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
                 if (b != 0.0) w12(m0, m2, s1p, s2p, s1, s2) += a * b;
               }
         }
+  // The nonzeros of W12 for each output (m2, s1', s2'), in the order the
+  // entries of a Z row are emitted: by input block (m0, s1, s2 sectors),
+  // then m0, s1, s2 within it.
+  struct W12nz {
+    int m0, s1, s2, in;  // in: the input block's (m0, s1, s2) sector triple, flattened
+    double c;
+  };
+  std::vector<std::vector<W12nz>> wcol((size_t)w * d1 * d2);
+  {
+    std::vector<int> km(w), k1(d1), k2(d2);
+    for (int k = 0; k < SM.nsec; ++k)
+      for (int64_t g = SM.off[k]; g < SM.off[k] + SM.dim[k]; ++g) km[(size_t)g] = k;
+    for (int k = 0; k < S1.nsec; ++k)
+      for (int64_t g = S1.off[k]; g < S1.off[k] + S1.dim[k]; ++g) k1[(size_t)g] = k;
+    for (int k = 0; k < S2.nsec; ++k)
+      for (int64_t g = S2.off[k]; g < S2.off[k] + S2.dim[k]; ++g) k2[(size_t)g] = k;
+    for (int m0 = 0; m0 < w; ++m0)
+      for (int m2 = 0; m2 < w; ++m2)
+        for (int s1p = 0; s1p < d1; ++s1p)
+          for (int s2p = 0; s2p < d2; ++s2p)
+            for (int s1 = 0; s1 < d1; ++s1)
+              for (int s2 = 0; s2 < d2; ++s2) {
+                const double cf = w12(m0, m2, s1p, s2p, s1, s2);
+                if (cf == 0.0) continue;
+                const int in = (km[m0] * S1.nsec + k1[s1]) * S2.nsec + k2[s2];
+                wcol[((size_t)m2 * d1 + s1p) * d2 + s2p].push_back(W12nz{m0, s1, s2, in, cf});
+              }
+    for (auto& col : wcol)
+      std::stable_sort(col.begin(), col.end(), [](const W12nz& x, const W12nz& y) {
+        if (x.in != y.in) return x.in < y.in;
+        if (x.m0 != y.m0) return x.m0 < y.m0;
+        if (x.s1 != y.s1) return x.s1 < y.s1;
+        return x.s2 < y.s2;
+      });
+  }
+  std::vector<int> in_of((size_t)SM.nsec * S1.nsec * S2.nsec, -1);  // input block per sector triple
+  // lookups: psi's block number per flattened sector quadruple, and the
+  // a-sector with q(a) = q(a') - q(m0) per (a', m0) (-1: none)
+  auto pkey = [&](int ia, int i1, int i2, int ib) {
+    return (((int64_t)ia * S1.nsec + i1) * S2.nsec + i2) * SB.nsec + ib;
+  };
+  std::unordered_map<int64_t, int> pblk;
+  pblk.reserve(P.blocks.size() * 2);
+  for (size_t b = 0; b < P.blocks.size(); ++b) {
+    const auto& k = P.blocks[b];
+    pblk[pkey(k[0], k[1], k[2], k[3])] = (int)b;
+  }
+  std::vector<int> ia_of((size_t)SA.nsec * SM.nsec);
+  for (int iap = 0; iap < SA.nsec; ++iap)
+    for (int im0 = 0; im0 < SM.nsec; ++im0)
+      ia_of[(size_t)iap * SM.nsec + im0] = SA.find(qadd(SA.q(iap), SM.q(im0), qmod, -1));
   std::map<std::pair<int, int>, std::vector<std::vector<int32_t>>> pairs;
   for (auto& kv : zblock) pairs[{kv.first[0], kv.first[4]}].push_back(kv.first);
   for (auto& kv : pairs) {
@@ -759,17 +855,19 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     std::vector<InBlock> inputs;
     for (int im0 = 0; im0 < SM.nsec; ++im0) {
       // X group (ia, im0) with q(a) = q(a') - q(m0)
-      const int ia = SA.find(qadd(SA.q(iap), SM.q(im0), qmod, -1));
+      const int ia = ia_of[(size_t)iap * SM.nsec + im0];
       if (ia < 0) continue;
       auto xg = xgroup.find({ia, im0});
       if (xg == xgroup.end() || xg->second.second != iap) continue;
       for (int i1 = 0; i1 < S1.nsec; ++i1)
         for (int i2 = 0; i2 < S2.nsec; ++i2) {
-          auto pb = P.index.find({ia, i1, i2, ib});
-          if (pb == P.index.end()) continue;
+          const auto pb = pblk.find(pkey(ia, i1, i2, ib));
+          if (pb == pblk.end()) continue;
           inputs.push_back({im0, ia, i1, i2, xg->second.first, colbase[pb->second]});
         }
     }
+    for (size_t k = 0; k < inputs.size(); ++k)
+      in_of[((size_t)inputs[k].im0 * S1.nsec + inputs[k].i1) * S2.nsec + inputs[k].i2] = (int)k;
     for (auto& zk : kv.second) {
       const int i1p = zk[1], i2p = zk[2], im2 = zk[3];
       const int64_t zoff = zblock[zk];
@@ -783,20 +881,17 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
             const size_t row_e0 = pl.we.size();
             const int g_m2 = (int)SM2.off[im2] + m2l;
             const int g_s1p = (int)S1.off[i1p] + s1l, g_s2p = (int)S2.off[i2p] + s2l;
-            for (const InBlock& in : inputs) {
-              const int64_t ds1 = S1.dim[in.i1], ds2 = S2.dim[in.i2];
-              for (int m0l = 0; m0l < SM.dim[in.im0]; ++m0l)
-                for (int s1l2 = 0; s1l2 < ds1; ++s1l2)
-                  for (int s2l2 = 0; s2l2 < ds2; ++s2l2) {
-                    const double cf = w12((int)SM.off[in.im0] + m0l, g_m2, g_s1p, g_s2p,
-                                          (int)S1.off[in.i1] + s1l2, (int)S2.off[in.i2] + s2l2);
-                    if (cf == 0.0) continue;
-                    QnWEnt e{};
-                    e.off = in.xbase + m0l * N_ia[in.ia] + in.colbase + (s1l2 * ds2 + s2l2) * dbw;
-                    e.astride = (int64_t)SM.dim[in.im0] * N_ia[in.ia];
-                    e.coef = cf;
-                    pl.we.push_back(e);
-                  }
+            for (const W12nz& z : wcol[((size_t)g_m2 * d1 + g_s1p) * d2 + g_s2p]) {
+              const int k = in_of[(size_t)z.in];
+              if (k < 0) continue;
+              const InBlock& in = inputs[(size_t)k];
+              const int64_t ds2 = S2.dim[in.i2];
+              const int64_t m0l = z.m0 - SM.off[in.im0], s1l2 = z.s1 - S1.off[in.i1], s2l2 = z.s2 - S2.off[in.i2];
+              QnWEnt e{};
+              e.off = in.xbase + m0l * N_ia[in.ia] + in.colbase + (s1l2 * ds2 + s2l2) * dbw;
+              e.astride = (int64_t)SM.dim[in.im0] * N_ia[in.ia];
+              e.coef = z.c;
+              pl.we.push_back(e);
             }
             pl.flops_w += 2.0 * (double)(pl.we.size() - row_e0) * wpair.da * db;
             if (pl.we.size() == row_e0) {
@@ -811,6 +906,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
             last.end = 1;
           }
     }
+    for (const InBlock& in : inputs) in_of[((size_t)in.im0 * S1.nsec + in.i1) * S2.nsec + in.i2] = -1;
     wpair.ne = (int32_t)(pl.we.size() - wpair.e0);
     pl.wp.push_back(wpair);
   }
