@@ -480,6 +480,39 @@ bool layout_ok(const itn_plan& pl, int64_t psi_elems) {
   return pl.X_elems % 8 == 0 && pl.Z_elems % 8 == 0;
 }
 
+// The compute precision and the signature that includes it.
+void set_prec(itn_plan& pl, int prec) {
+  pl.prec = prec;
+  pl.pt = prec == ITN_P_F64 ? D_F64 : (prec == ITN_P_F32 ? D_F32 : D_BF16);
+  // X (stage 1's output) is the W-stage's operand: stored at the operand
+  // precision (bf16 for bf16 applies: half the bytes of the HBM-bound
+  // W-stage), accumulated in f32 by the W-stage.
+  pl.xt = pl.pt;
+  pl.sig = pl.sigL + "|" + pl.sigR + "|" + pl.sigP + "|" + std::to_string(pl.nv) + "|" +
+           std::to_string(prec);
+  pl.sig_hash = std::hash<std::string>()(pl.sig);
+}
+
+// The precision-dependent lists of a plan whose structure is built: the
+// W-stage items (16-byte vectors of X's type), one list per kernel candidate,
+// and the tile lists of both grouped stages; then the layout check.
+itn_status finish_plan(itn_handle* h, itn_plan& pl) {
+  const int64_t V = 16 / dtype_size(pl.xt);
+  for (int c = 0; c < itn_plan::kWNum; ++c) {
+    pl.wi[c].clear();
+    const int64_t chunk = itn_plan::kWCand[c];
+    for (size_t pid = 0; pid < pl.wp.size(); ++pid) {
+      const int64_t nvec = (int64_t)pl.wp[pid].da * pl.wp[pid].db / V;
+      for (int64_t v0 = 0; v0 < nvec; v0 += chunk)
+        pl.wi[c].push_back(QnWItem{(int32_t)pid, (int32_t)v0});
+    }
+  }
+  if (!layout_ok(pl, pl.out_elems)) return fail(h, ITN_E_SHAPE, "internal plan layout check failed");
+  build_tiles(pl.tl1, pl.p1, pl.s1, pl.prec, pl.pt);
+  build_tiles(pl.tl4, pl.p4, pl.s4, pl.prec, pl.pt);
+  return ITN_OK;
+}
+
 itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t,
                       const itn_tensor* W2t, const itn_tensor* Rt, const itn_tensor* Pt, int nv,
                       int prec, itn_plan& pl) {
@@ -557,12 +590,6 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   const QSpace& SB = P.sp[3];
   const QSpace& SM = L.sp[1];   // m0 sectors
   const QSpace& SM2 = R.sp[1];  // m2 sectors
-  pl.prec = prec;
-  pl.pt = prec == ITN_P_F64 ? D_F64 : (prec == ITN_P_F32 ? D_F32 : D_BF16);
-  // X (stage 1's output) is the W-stage's operand: stored at the operand
-  // precision (bf16 for bf16 applies: half the bytes of the HBM-bound
-  // W-stage), accumulated in f32 by the W-stage.
-  pl.xt = pl.pt;
   pl.psi_dt = Pt->dtype;
   pl.nv = nv;
   pl.out_elems = P.elems;
@@ -571,9 +598,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   pl.sigL = sig_of(L);
   pl.sigR = sig_of(R);
   pl.sigP = sig_of(P);
-  pl.sig = pl.sigL + "|" + pl.sigR + "|" + pl.sigP + "|" + std::to_string(nv) + "|" +
-           std::to_string(prec);
-  pl.sig_hash = std::hash<std::string>()(pl.sig);
+  set_prec(pl, prec);
 
   // Every b-sector is padded to a multiple of 8 columns in psiT, X, Z and
   // the R copies (zero padding), so the W-stage moves aligned 16-byte
@@ -910,22 +935,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
     wpair.ne = (int32_t)(pl.we.size() - wpair.e0);
     pl.wp.push_back(wpair);
   }
-  // W-stage item lists, one per kernel candidate (vectors per item)
-  {
-    const int64_t V = 16 / dtype_size(pl.xt);
-    for (int c = 0; c < itn_plan::kWNum; ++c) {
-      const int64_t chunk = itn_plan::kWCand[c];
-      for (size_t pid = 0; pid < pl.wp.size(); ++pid) {
-        const int64_t nvec = (int64_t)pl.wp[pid].da * pl.wp[pid].db / V;
-        for (int64_t v0 = 0; v0 < nvec; v0 += chunk)
-          pl.wi[c].push_back(QnWItem{(int32_t)pid, (int32_t)v0});
-      }
-    }
-  }
-  if (!layout_ok(pl, P.elems)) return fail(h, ITN_E_SHAPE, "internal plan layout check failed");
-  build_tiles(pl.tl1, pl.p1, pl.s1, pl.prec, pl.pt);
-  build_tiles(pl.tl4, pl.p4, pl.s4, pl.prec, pl.pt);
-  return ITN_OK;
+  return finish_plan(h, pl);
 }
 
 template <typename T> T* carve(char*& p, size_t n) {
@@ -1291,6 +1301,23 @@ itn_status itn_plan_destroy(itn_plan* plan) {
 namespace itn {
 // Fix a plan's launch modes (no autotuning) and launch it without graph
 // capture: for plans that serve a handful of applies, as in a sweep.
+itn_status qn_plan_at_prec(itn_handle* h, const itn_plan* src, int prec, itn_plan** out) {
+  if (!h || !src || !out) return h ? fail(h, ITN_E_ARG, "null argument") : ITN_E_ARG;
+  *out = nullptr;
+  if (prec != ITN_P_F64 && prec != ITN_P_F32 && prec != ITN_P_BF16)
+    return fail(h, ITN_E_ARG, "unknown precision");
+  if (src->device >= 0 || src->dtab) return fail(h, ITN_E_ARG, "the source plan is already on a device");
+  auto* pl = new itn_plan(*src);  // host tables only: no device state to share
+  set_prec(*pl, prec);
+  itn_status st = finish_plan(h, *pl);
+  if (st != ITN_OK) {
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return ITN_OK;
+}
+
 itn_status qn_plan_set_direct(itn_plan* pl, int mode_stage1, int mode_stage4) {
   if (!pl || mode_stage1 < 0 || mode_stage1 >= itn_plan::kModes || mode_stage4 < 0 ||
       mode_stage4 >= itn_plan::kModes)

@@ -638,11 +638,11 @@ struct BondPlan {
   }
 };
 
-itn_status make_plan(QCtx& c, int i, const QBT& psi, int prec, int nv, BondPlan& bp) {
+// The bond's H_eff plans: FP64 (restarts, refinement) and, below FP64, one at
+// `prec` derived from the same structure tables; each applied with its
+// environments prepared once (the low-precision ones cast first).
+itn_status make_plans(QCtx& c, int i, const QBT& psi, int prec, int nv, BondPlan& p64, BondPlan& plo) {
   itn_qn_mps* m = c.m;
-  const int w = c.mpo->w, d = c.mpo->d;
-  const int64_t dw[4] = {w, w, d, d};
-  (void)dw;
   const QSpace wl = c.mlink, ws = m->site;
   QTensor wq;
   wq.rank = 4;
@@ -651,21 +651,25 @@ itn_status make_plan(QCtx& c, int i, const QBT& psi, int prec, int nv, BondPlan&
   w1.t.nblocks = w2.t.nblocks = 0;
   w1.t.block_sec = w2.t.block_sec = nullptr;
   w1.t.block_off = w2.t.block_off = nullptr;
-  const itn_dtype et = prec == ITN_P_BF16 ? ITN_BF16 : (prec == ITN_P_F32 ? ITN_F32 : ITN_F64);
-  const bool low = prec != ITN_P_F64;
   const QBT &L = m->L[i], &R = m->R[i + 2];
+  View vl(L.q, L.flux, L.d(), ITN_F64), vr(R.q, R.flux, R.d(), ITN_F64);
+  View vp(psi.q, psi.flux, psi.d(), ITN_F64);
+  const bool low = prec != ITN_P_F64;
+  ITN_TRY(itn_qn_heff_plan(c.h, &vl.t, &w1.t, &w2.t, &vr.t, &vp.t, nv, ITN_P_F64, &p64.pl));
+  if (low) ITN_TRY(qn_plan_at_prec(c.h, p64.pl, prec, &plo.pl));
+  ITN_TRY(qn_plan_set_direct(p64.pl, 0, 0));
+  ITN_TRY(itn_qn_prepare_env(c.h, p64.pl, &vl.t, &vr.t, c.s));
   if (low) {
+    const itn_dtype et = prec == ITN_P_BF16 ? ITN_BF16 : ITN_F32;
     const int dt = prec == ITN_P_BF16 ? D_BF16 : D_F32;
     ITN_TRY(m->Lp.ensure(c.h, std::max<int64_t>(L.q.elems, 1) * 4 + 256));
     ITN_TRY(m->Rp.ensure(c.h, std::max<int64_t>(R.q.elems, 1) * 4 + 256));
     ITN_HIP(c.h, cast(D_F64, L.d(), dt, m->Lp.p, L.q.elems, c.s));
     ITN_HIP(c.h, cast(D_F64, R.d(), dt, m->Rp.p, R.q.elems, c.s));
+    View ll(L.q, L.flux, m->Lp.p, et), lr(R.q, R.flux, m->Rp.p, et);
+    ITN_TRY(qn_plan_set_direct(plo.pl, 0, 0));
+    ITN_TRY(itn_qn_prepare_env(c.h, plo.pl, &ll.t, &lr.t, c.s));
   }
-  View vl(L.q, L.flux, low ? m->Lp.p : L.d(), et), vr(R.q, R.flux, low ? m->Rp.p : R.d(), et);
-  View vp(psi.q, psi.flux, psi.d(), ITN_F64);
-  ITN_TRY(itn_qn_heff_plan(c.h, &vl.t, &w1.t, &w2.t, &vr.t, &vp.t, nv, (itn_prec)prec, &bp.pl));
-  ITN_TRY(qn_plan_set_direct(bp.pl, 0, 0));
-  ITN_TRY(itn_qn_prepare_env(c.h, bp.pl, &vl.t, &vr.t, c.s));
   return ITN_OK;
 }
 
@@ -765,8 +769,7 @@ itn_status bond_step(QCtx& c, int i, bool to_right, int maxdim, double cutoff, b
   // block Davidson: plans for B vectors per launch; calls with fewer are padded with zero vectors
   const int B = c.p->block > 1 ? std::min(c.p->block, 8) : 1;
   BondPlan p64, plo;
-  ITN_TRY(make_plan(c, i, psi, ITN_P_F64, B, p64));
-  if (prec != ITN_P_F64) ITN_TRY(make_plan(c, i, psi, prec, B, plo));
+  ITN_TRY(make_plans(c, i, psi, prec, B, p64, plo));
   if (B > 1) {
     ITN_TRY(m->bx.ensure(c.h, (size_t)B * std::max<int64_t>(n, 1) * 8));
     ITN_TRY(m->by.ensure(c.h, (size_t)B * std::max<int64_t>(n, 1) * 8));

@@ -131,6 +131,11 @@ itn_status contract_qn(itn_handle* h, const itn_tensor* A, const itn_tensor* B, 
 
 // Fix a QN plan's launch modes and launch it without a graph (sweeps).
 itn_status qn_plan_set_direct(itn_plan* pl, int mode_stage1, int mode_stage4);
+// A QN plan for the same operands at another precision, derived from `src`
+// before its first apply or environment preparation (src holds no device
+// state yet; ITN_E_ARG otherwise): the structure tables are copied, the
+// precision-dependent lists rebuilt.  The caller owns *out.
+itn_status qn_plan_at_prec(itn_handle* h, const itn_plan* src, int prec, itn_plan** out);
 
 // Looks up the allocation-free entry point's scratch on `device` (current).
 void noalloc_scratch_init(int device);
