@@ -239,3 +239,28 @@ def test_block_sparse_contract_errors(host):
                       torch.zeros(6, 5, dtype=torch.float64), [2, 3],
                       torch.zeros(5, 5, dtype=torch.float64), [1, 3])
     assert e.value.name == "ITN_E_NODEVICE"
+
+
+@pytest.mark.parametrize("make", [U.small_u1, U.small_u1u1, U.zn_u1z4])
+@pytest.mark.parametrize("drop", ["first", "middle", "last"])
+def test_psi_missing_one_allowed_block_is_rejected(host, make, drop):
+    """psi with one flux-allowed block left out (offsets kept consistent, so
+    every remaining block is valid) fails the completeness check with
+    ITN_E_SHAPE, under integer and Z_N addition rules; the full block list
+    plans."""
+    ops, W1, W2 = make()[:3]
+    L, w1, w2, R, psi = ops
+    Ld, _ = U.desc(L, with_data=False)
+    Rd, _ = U.desc(R, with_data=False)
+    Pd, _ = U.desc(psi, with_data=False)
+    m1, m2 = U.mpo_desc(W1, w1), U.mpo_desc(W2, w2)
+    host.qn_plan(Ld, m1, m2, Rd, Pd)
+    bad = copy.deepcopy(Pd)
+    k = {"first": 0, "middle": len(bad["blocks"]) // 2, "last": len(bad["blocks"]) - 1}[drop]
+    bad["blocks"] = bad["blocks"][:k] + bad["blocks"][k + 1:]
+    dims = [sp[1] for sp in bad["spaces"]]
+    sizes = [int(np.prod([dims[i][s] for i, s in enumerate(b)])) for b in bad["blocks"]]
+    bad["offsets"] = [int(x) for x in np.cumsum([0] + sizes[:-1])]
+    with pytest.raises(itn.ItnError) as e:
+        host.qn_plan(Ld, m1, m2, Rd, bad)
+    assert e.value.name == "ITN_E_SHAPE"
