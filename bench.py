@@ -473,22 +473,28 @@ def time_qn(h, torch, np, inp, which, prec, nv, steps, warmup, split_mpo=False):
 # that fixes the converged energy.
 DAVIDSON = {"krylovdim": 4, "maxiter": 8}
 DAVIDSON_TIGHT = {"krylovdim": 8, "maxiter": 60}
-# block Davidson on the block-sparse sweeps: 4 residuals per step, two steps
-# between restarts (8 basis vectors), 12 vectors applied per bond
+# block Davidson (dense and block-sparse sweeps): 4 residuals per step, two
+# steps between restarts (8 basis vectors), 12 vectors applied per bond
 DAVIDSON_BLOCK4 = {"krylovdim": 8, "maxiter": 12}
 
 
-def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=DAVIDSON, block=1):
+def dmrg_leg(h, np, inp, prec, sweeps, N=100, timing=False, davidson=None, block=1):
     """Spin-1 Heisenberg chain (d=3, w=5), random product start, the given
     (maxdim, cutoff) schedule; per-sweep time, energy, matvecs (all, and
     those in FP64), and with timing the per-phase split (adds stream
     waits).  block > 1: block Davidson, `block` vectors per batched matvec
-    (the Krylov budget scaled by the block)."""
+    (Krylov budget `davidson`, else DAVIDSON_BLOCK4 for block 4 and the
+    small budget scaled by the block otherwise)."""
     mpo = h.mpo(inp.heisenberg_mpo(N, 2))
     mps = h.mps(inp.random_product_state(N, 3, inp.rng_for(2, 64)))
-    dv = dict(davidson)
-    if block > 1:
-        dv = {"krylovdim": dv["krylovdim"] * block, "maxiter": dv["maxiter"] * block}
+    if davidson is not None:
+        dv = dict(davidson)
+    elif block == 4:
+        dv = dict(DAVIDSON_BLOCK4)
+    elif block > 1:
+        dv = {"krylovdim": DAVIDSON["krylovdim"] * block, "maxiter": DAVIDSON["maxiter"] * block}
+    else:
+        dv = dict(DAVIDSON)
     t0 = time.perf_counter()
     recs = h.dmrg_sweep(mps, mpo, sweeps, prec=prec, eig_tol=1e-9, refine=True,
                         allow_unconverged=True, timing=timing, block=block, **dv)
