@@ -314,6 +314,21 @@ itn_status itn_qn_heff_apply(itn_handle* h, itn_plan* plan, const itn_tensor* L,
                              const itn_tensor* R, const itn_tensor* psi, itn_tensor* out,
                              void* hip_stream);
 
+/* Diagonal of the block-sparse two-site H_eff (the operands of
+ * itn_qn_heff_plan, Sec. 7.2 with Sec. 8): out[a, s1, s2, b] = sum over m0,
+ * m1, m2 of L[a, m0, a] W1[m0, m1, s1, s1] W2[m1, m2, s2, s2] R[b, m2, b],
+ * the preconditioner of block Davidson.  L, R: device F64 block-sparse (any
+ * flux-allowed block lists); W1, W2: host F64 dense with their QN spaces;
+ * out: device F64, psi's index spaces and arrows, every listed block written.
+ * Only zero-charge MPO channels reach the diagonal (the environments' flux
+ * rule).  Uses the handle's workspace (small: the environments' diagonals
+ * and the block tables) and returns after the work on hip_stream has
+ * finished.  Errors: ITN_E_ARROW, ITN_E_SHAPE (sectors differ), ITN_E_DTYPE,
+ * ITN_E_FLUX, ITN_E_WORKSPACE, ITN_E_NODEVICE. */
+itn_status itn_qn_heff_diag(itn_handle* h, const itn_tensor* L, const itn_tensor* W1,
+                            const itn_tensor* W2, const itn_tensor* R, itn_tensor* out,
+                            void* hip_stream);
+
 /* Repack the environments L, R (the plan's structure and compute type:
  * ITN_E_SHAPE / ITN_E_DTYPE otherwise) into the plan's layouts on
  * hip_stream, for applies with L = R = NULL.  The eigensolver at a bond of

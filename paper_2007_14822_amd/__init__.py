@@ -545,6 +545,13 @@ def _qn_handle_methods():
                                               PREC[prec], C.byref(out)))
         return Plan(self, out)
 
+    def qn_heff_diag(self, Ld, W1d, W2d, Rd, Od, stream=None):
+        """Diagonal of the block-sparse two-site H_eff into Od's data (psi's
+        block layout, F64); descriptors as for qn_plan, L/R/out with data."""
+        k = _Keep()
+        ts = [_qn(k, x) for x in (Ld, W1d, W2d, Rd, Od)]
+        self._check(self.lib.itn_qn_heff_diag(self.h, *[C.byref(t) for t in ts], self._sp(stream)))
+
     def contract_blocks(self, Ad, la, Bd, lb, Cd, lc, prec: str = "f64", stream=None):
         """Block-sparse C = A * B over labels (itn_contract with QN
         operands).  Ad, Bd, Cd: QN descriptors (spaces, blocks, offsets,
@@ -579,7 +586,7 @@ def _qn_handle_methods():
         k = _Keep()
         refs = [None if x is None else C.byref(_qn(k, x)) for x in (Ld, Rd, Pd, Od)]
         self._check(self.lib.itn_qn_heff_apply(self.h, plan.ptr, *refs, self._sp(stream)))
-    return qn_plan, qn_allowed_blocks, qn_apply, contract_blocks
+    return qn_plan, qn_allowed_blocks, qn_apply, contract_blocks, qn_heff_diag
 
 
 class Plan:
@@ -642,7 +649,7 @@ class Plan:
 
 
 (Handle.qn_plan, Handle.qn_allowed_blocks, Handle.qn_apply,
- Handle.contract_blocks) = _qn_handle_methods()
+ Handle.contract_blocks, Handle.qn_heff_diag) = _qn_handle_methods()
 
 
 class _Owned:

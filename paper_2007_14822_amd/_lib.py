@@ -93,6 +93,7 @@ SIGNATURES = {
     "itn_plan_out_blocks": (S, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "itn_qn_heff_apply": (S, [P, P, T, T, T, T, P]),
     "itn_qn_prepare_env": (S, [P, P, T, T, P]),
+    "itn_qn_heff_diag": (S, [P, T, T, T, T, T, P]),
     "itn_env_update": (S, [P, T, T, T, C.c_int, T, C.c_int, P]),
     "itn_mpo_create": (S, [P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                            C.POINTER(P)]),

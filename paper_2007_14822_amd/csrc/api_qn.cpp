@@ -1334,6 +1334,47 @@ itn_status qn_plan_set_direct(itn_plan* pl, int mode_stage1, int mode_stage4) {
 
 extern "C" {
 
+itn_status itn_qn_heff_diag(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t, const itn_tensor* W2t,
+                            const itn_tensor* Rt, itn_tensor* out, void* hip_stream) {
+  if (!h) return ITN_E_ARG;
+  static const int aL[3] = {+1, -1, -1}, aR[3] = {-1, +1, +1}, aP[4] = {+1, +1, +1, -1},
+                   aW[4] = {+1, -1, +1, -1};
+  QTensor L, R, P, W1, W2;
+  ITN_TRY(read_qtensor(h, Lt, 3, aL, L, "L", true));
+  ITN_TRY(read_qtensor(h, Rt, 3, aR, R, "R", true));
+  ITN_TRY(read_qtensor(h, out, 4, aP, P, "out", true));
+  ITN_TRY(read_qtensor(h, W1t, 4, aW, W1, "W1", false));
+  ITN_TRY(read_qtensor(h, W2t, 4, aW, W2, "W2", false));
+  if (!L.sp[0].same_sectors(P.sp[0]) || !L.sp[2].same_sectors(P.sp[0]))
+    return fail(h, ITN_E_SHAPE, "L's a', a and out's a differ");
+  if (!R.sp[0].same_sectors(P.sp[3]) || !R.sp[2].same_sectors(P.sp[3]))
+    return fail(h, ITN_E_SHAPE, "R's b', b and out's b differ");
+  if (!L.sp[1].same_sectors(W1.sp[0])) return fail(h, ITN_E_SHAPE, "L's m and W1's m_in differ");
+  if (!W1.sp[1].same_sectors(W2.sp[0])) return fail(h, ITN_E_SHAPE, "W1's m_out and W2's m_in differ");
+  if (!W2.sp[1].same_sectors(R.sp[1])) return fail(h, ITN_E_SHAPE, "W2's m_out and R's m differ");
+  if (!W1.sp[2].same_sectors(P.sp[1]) || !W1.sp[3].same_sectors(P.sp[1]))
+    return fail(h, ITN_E_SHAPE, "W1's site indices and out's s1 differ");
+  if (!W2.sp[2].same_sectors(P.sp[2]) || !W2.sp[3].same_sectors(P.sp[2]))
+    return fail(h, ITN_E_SHAPE, "W2's site indices and out's s2 differ");
+  if (!W1t->data || !W2t->data || W1t->dtype != ITN_F64 || W2t->dtype != ITN_F64)
+    return fail(h, ITN_E_DTYPE, "W1, W2 must be host F64 dense arrays");
+  if (Lt->dtype != ITN_F64 || Rt->dtype != ITN_F64 || out->dtype != ITN_F64)
+    return fail(h, ITN_E_DTYPE, "L, R and out must be F64");
+  if (h->device < 0) return fail(h, ITN_E_NODEVICE, "host-only handle cannot launch work");
+  if (P.elems == 0) return ITN_OK;
+  if (!out->data || (!Lt->data && L.elems > 0) || (!Rt->data && R.elems > 0))
+    return fail(h, ITN_E_ARG, "L, R and out need device data");
+  HeffDiag dg;
+  ITN_TRY(heff_diag_build(h, L, R, static_cast<const double*>(W1t->data), static_cast<const double*>(W2t->data),
+                          (int)W1.sp[1].total, P, dg));
+  ITN_TRY(ensure_workspace(h, dg.device_bytes()));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  ITN_HIP(h, heff_diag_launch(dg, static_cast<const double*>(Lt->data), static_cast<const double*>(Rt->data),
+                              h->ws.ptr, static_cast<double*>(out->data), s));
+  ITN_HIP(h, hipStreamSynchronize(s));  // the host tables go out of scope here
+  return ITN_OK;
+}
+
 itn_status itn_plan_query(const itn_plan* pl, itn_plan_info* info) {
   if (!pl || !info) return ITN_E_ARG;
   info->out_nblocks = (int64_t)pl->out_blocks.size();

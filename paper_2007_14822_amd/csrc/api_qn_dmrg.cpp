@@ -165,7 +165,7 @@ struct itn_qn_mps {
   const itn_mpo* env_mpo = nullptr;
   SolverBufs sb;
   DBuf psi, Lp, Rp, mat, matT, rho, ut, prod, ev, info, bat, batw, bmeta;
-  DBuf hdiag, envd, dtab, bx, by;  // block Davidson: H_eff diagonal, its tables, padded batches
+  DBuf hdiag, dtab, bx, by;  // block Davidson: H_eff diagonal, its tables, padded batches
   DBuf ctab[4];                    // bond split: tables of its batched copies
   QBT theta, T1, T2;  // two-site tensor and environment intermediates (buffers reused)
   HostPin pin;
@@ -175,12 +175,111 @@ struct itn_qn_mps {
     for (QBT* t : {&theta, &T1, &T2}) t->data.release();
     for (DBuf& b : ctab) b.release();
     for (DBuf* b : {&psi, &Lp, &Rp, &mat, &matT, &rho, &ut, &prod, &ev, &info, &bat, &batw, &bmeta,
-                    &hdiag, &envd, &dtab, &bx, &by})
+                    &hdiag, &dtab, &bx, &by})
       b->release();
     sb.release();
     pin.release();
   }
 };
+
+namespace itn {
+namespace qn {
+
+itn_status heff_diag_build(itn_handle* h, const QTensor& L, const QTensor& R, const double* W1,
+                           const double* W2, int wm, const QTensor& P, HeffDiag& out) {
+  if (!P.sp[0].same_sectors(L.sp[0]) || !P.sp[3].same_sectors(R.sp[0]))
+    return fail(h, ITN_E_SHAPE, "the environments' link sectors differ from psi's");
+  const QSpace &ML = L.sp[1], &MR = R.sp[1];
+  const int wl = (int)ML.total, wr = (int)MR.total, d1 = (int)P.sp[1].total, d2 = (int)P.sp[2].total;
+  // zero-charge channels of each environment (only these reach the diagonal)
+  auto zeros = [](const QSpace& sp, std::vector<int32_t>& zpos) {
+    zpos.assign((size_t)sp.total, -1);
+    int n = 0;
+    for (int k = 0; k < sp.nsec; ++k) {
+      bool zero = true;
+      for (int c = 0; c < sp.nq; ++c) zero &= qn_red(sp.q(k)[c], sp.mod[c]) == 0;
+      if (zero)
+        for (int y = 0; y < sp.dim[k]; ++y) zpos[(size_t)(sp.off[k] + y)] = n++;
+    }
+    return std::max(n, 1);
+  };
+  std::vector<int32_t> zl, zr;
+  out.wzl = zeros(ML, zl);
+  out.wzr = zeros(MR, zr);
+  out.d1 = d1;
+  out.d2 = d2;
+  std::vector<double> wd((size_t)out.wzl * out.wzr * d1 * d2, 0.0);
+  for (int m0 = 0; m0 < wl; ++m0)
+    for (int m2 = 0; m2 < wr; ++m2) {
+      if (zl[(size_t)m0] < 0 || zr[(size_t)m2] < 0) continue;
+      for (int s1 = 0; s1 < d1; ++s1)
+        for (int s2 = 0; s2 < d2; ++s2) {
+          double v = 0.0;
+          for (int m1 = 0; m1 < wm; ++m1)
+            v += W1[(((size_t)m0 * wm + m1) * d1 + s1) * d1 + s1] *
+                 W2[(((size_t)m1 * wr + m2) * d2 + s2) * d2 + s2];
+          wd[(((size_t)zl[(size_t)m0] * out.wzr + zr[(size_t)m2]) * d1 + s1) * d2 + s2] = v;
+        }
+    }
+  auto items = [&](const QTensor& E, const std::vector<int32_t>& zpos,
+                   std::vector<EnvDiagItem>& v) -> itn_status {
+    for (size_t b = 0; b < E.blocks.size(); ++b) {
+      const auto& k = E.blocks[b];
+      if (k[0] != k[2]) continue;
+      const int64_t mg = E.sp[1].off[k[1]];
+      if (zpos[(size_t)mg] < 0)
+        return fail(h, ITN_E_FLUX, "environment block with equal link sectors on a charged channel");
+      v.push_back({E.off[b], E.sp[0].dim[k[0]], E.sp[1].dim[k[1]], E.sp[0].off[k[0]], zpos[(size_t)mg]});
+    }
+    return ITN_OK;
+  };
+  std::vector<EnvDiagItem> li, ri;
+  ITN_TRY(items(L, zl, li));
+  ITN_TRY(items(R, zr, ri));
+  std::vector<DiagBlock> db;
+  out.most = 0;
+  for (size_t b = 0; b < P.blocks.size(); ++b) {
+    const auto& k = P.blocks[b];
+    DiagBlock q{P.off[b],          P.sp[0].dim[k[0]], P.sp[1].dim[k[1]], P.sp[2].dim[k[2]], P.sp[3].dim[k[3]],
+                P.sp[0].off[k[0]], P.sp[1].off[k[1]], P.sp[2].off[k[2]], P.sp[3].off[k[3]]};
+    out.most = std::max(out.most, q.da * q.d1 * q.d2 * q.db);
+    db.push_back(q);
+  }
+  out.cl = P.sp[0].total;
+  out.cr = P.sp[3].total;
+  out.nli = (int)li.size();
+  out.nri = (int)ri.size();
+  out.ndb = (int)db.size();
+  out.o_li = wd.size() * 8;
+  out.o_ri = out.o_li + li.size() * sizeof(EnvDiagItem);
+  out.o_db = out.o_ri + ri.size() * sizeof(EnvDiagItem);
+  out.host.assign(out.o_db + db.size() * sizeof(DiagBlock), 0);
+  std::memcpy(out.host.data(), wd.data(), wd.size() * 8);
+  if (!li.empty()) std::memcpy(out.host.data() + out.o_li, li.data(), li.size() * sizeof(EnvDiagItem));
+  if (!ri.empty()) std::memcpy(out.host.data() + out.o_ri, ri.data(), ri.size() * sizeof(EnvDiagItem));
+  if (!db.empty()) std::memcpy(out.host.data() + out.o_db, db.data(), db.size() * sizeof(DiagBlock));
+  return ITN_OK;
+}
+
+hipError_t heff_diag_launch(const HeffDiag& q, const double* Ldata, const double* Rdata, void* dev, double* D,
+                            hipStream_t s) {
+  char* dt = static_cast<char*>(dev);
+  double* Ld = reinterpret_cast<double*>(dt + round256(q.host.size()));
+  double* Rd = Ld + (size_t)q.cl * q.wzl;
+  hipError_t e = hipMemcpyAsync(dt, q.host.data(), q.host.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(Ld, 0, (size_t)(q.cl * q.wzl + q.cr * q.wzr) * 8, s);
+  if (e == hipSuccess)
+    e = env_diag_gather(Ldata, reinterpret_cast<const EnvDiagItem*>(dt + q.o_li), q.nli, q.wzl, Ld, s);
+  if (e == hipSuccess)
+    e = env_diag_gather(Rdata, reinterpret_cast<const EnvDiagItem*>(dt + q.o_ri), q.nri, q.wzr, Rd, s);
+  if (e == hipSuccess)
+    e = qn_heff_diag(Ld, Rd, reinterpret_cast<const double*>(dt), q.wzl, q.wzr, q.d1, q.d2,
+                     reinterpret_cast<const DiagBlock*>(dt + q.o_db), q.ndb, (q.most + 255) / 256, D, s);
+  return e;
+}
+
+}  // namespace qn
+}  // namespace itn
 
 namespace {
 
@@ -313,8 +412,6 @@ hipError_t transpose_sub(const double* in, int64_t ld, double* out, int64_t rows
   return permute_cast(D_F64, in, D_F64, out, 2, dims, st, s);
 }
 
-// Split psi (block-sparse [a, s1, s2, b]) at bond i into sites i, i+1, sector
-// by sector of the new link charge q = q(a) + q(s1).
 // Strided copies collected and run as one launch.  The table goes up with a
 // blocking copy: each table buffer is read by one phase of the bond split,
 // and a host wait on the stream separates its last readers from the next
@@ -345,6 +442,8 @@ struct CopyList {
   }
 };
 
+// Split psi (block-sparse [a, s1, s2, b]) at bond i into sites i, i+1, sector
+// by sector of the new link charge q = q(a) + q(s1).
 itn_status split(QCtx& c, int i, bool to_right, const QBT& psi, int maxdim, double cutoff, double* trunc) {
   itn_qn_mps* m = c.m;
   const QSpace &sa = psi.q.sp[0], &s1 = psi.q.sp[1], &s2 = psi.q.sp[2], &sb = psi.q.sp[3];
@@ -674,88 +773,15 @@ itn_status make_plans(QCtx& c, int i, const QBT& psi, int prec, int nv, BondPlan
 }
 
 // The diagonal of the two-site H_eff at bond i for the block expansion's
-// preconditioner, into m->hdiag (psi's block layout).  A diagonal entry
-// pairs L[a, m0, a] and R[b, m2, b]: charge conservation leaves only the
-// zero-charge MPO channels m0, m2, whose environment diagonals are gathered
-// into dense [chi][wz] tables; Wd[i][j][s1][s2] = sum_m1 W1[m0,m1,s1,s1]
-// W2[m1,m2,s2,s2] over those channels is formed on the host.  The tables
-// are copied from `keep`, which must outlive the stream's next host wait.
-itn_status qn_diag(QCtx& c, int i, const QBT& psi, std::vector<char>& keep) {
+// preconditioner, into m->hdiag (psi's block layout); `diag` holds the host
+// tables until the solve's first host wait.
+itn_status qn_diag(QCtx& c, int i, const QBT& psi, HeffDiag& diag) {
   itn_qn_mps* m = c.m;
-  const int w = c.mpo->w, d = c.mpo->d;
   const QBT &L = m->L[i], &R = m->R[i + 2];
-  if (!psi.q.sp[0].same_sectors(L.q.sp[0]) || !psi.q.sp[3].same_sectors(R.q.sp[0]))
-    return fail(c.h, ITN_E_SHAPE, "environment and two-site tensor links differ at bond %d", i);
-  std::vector<int32_t> zpos(w, -1);
-  int wz = 0;
-  for (int k = 0; k < c.mlink.nsec; ++k) {
-    const int32_t* q = c.mlink.q(k);
-    if (std::all_of(q, q + c.mlink.nq, [](int32_t v) { return v == 0; }))
-      for (int y = 0; y < c.mlink.dim[k]; ++y) zpos[c.mlink.off[k] + y] = wz++;
-  }
-  const int wzs = std::max(wz, 1);
-  std::vector<double> wd((size_t)wzs * wzs * d * d, 0.0);
-  const double* W1 = c.mpo->site(i);
-  const double* W2 = c.mpo->site(i + 1);
-  for (int m0 = 0; m0 < w; ++m0)
-    for (int m2 = 0; m2 < w; ++m2) {
-      if (zpos[m0] < 0 || zpos[m2] < 0) continue;
-      for (int s1 = 0; s1 < d; ++s1)
-        for (int s2 = 0; s2 < d; ++s2) {
-          double v = 0.0;
-          for (int m1 = 0; m1 < w; ++m1)
-            v += W1[((m0 * w + m1) * d + s1) * d + s1] * W2[((m1 * w + m2) * d + s2) * d + s2];
-          wd[(((size_t)zpos[m0] * wzs + zpos[m2]) * d + s1) * d + s2] = v;
-        }
-    }
-  auto items = [&](const QBT& E, std::vector<EnvDiagItem>& out) -> itn_status {
-    for (size_t b = 0; b < E.q.blocks.size(); ++b) {
-      const auto& k = E.q.blocks[b];
-      if (k[0] != k[2]) continue;
-      const int64_t mg = E.q.sp[1].off[k[1]];
-      if (zpos[mg] < 0)
-        return fail(c.h, ITN_E_FLUX, "environment block on a charged channel has equal link sectors");
-      out.push_back({E.q.off[b], E.q.sp[0].dim[k[0]], E.q.sp[1].dim[k[1]], E.q.sp[0].off[k[0]], zpos[mg]});
-    }
-    return ITN_OK;
-  };
-  std::vector<EnvDiagItem> li, ri;
-  ITN_TRY(items(L, li));
-  ITN_TRY(items(R, ri));
-  std::vector<DiagBlock> db;
-  int64_t most = 0;
-  for (size_t b = 0; b < psi.q.blocks.size(); ++b) {
-    const auto& k = psi.q.blocks[b];
-    DiagBlock q{psi.q.off[b],
-                psi.q.sp[0].dim[k[0]], psi.q.sp[1].dim[k[1]], psi.q.sp[2].dim[k[2]], psi.q.sp[3].dim[k[3]],
-                psi.q.sp[0].off[k[0]], psi.q.sp[1].off[k[1]], psi.q.sp[2].off[k[2]], psi.q.sp[3].off[k[3]]};
-    most = std::max(most, q.da * q.d1 * q.d2 * q.db);
-    db.push_back(q);
-  }
-  const int64_t cl = psi.q.sp[0].total, cr = psi.q.sp[3].total, n = psi.q.elems;
-  // one host block: Wd, the two item lists, the psi block list (8-byte aligned parts)
-  const size_t o_li = wd.size() * 8, o_ri = o_li + li.size() * sizeof(EnvDiagItem),
-               o_db = o_ri + ri.size() * sizeof(EnvDiagItem), bytes = o_db + db.size() * sizeof(DiagBlock);
-  keep.resize(bytes);
-  std::memcpy(keep.data(), wd.data(), wd.size() * 8);
-  if (!li.empty()) std::memcpy(keep.data() + o_li, li.data(), li.size() * sizeof(EnvDiagItem));
-  if (!ri.empty()) std::memcpy(keep.data() + o_ri, ri.data(), ri.size() * sizeof(EnvDiagItem));
-  if (!db.empty()) std::memcpy(keep.data() + o_db, db.data(), db.size() * sizeof(DiagBlock));
-  ITN_TRY(m->dtab.ensure(c.h, bytes));
-  ITN_TRY(m->envd.ensure(c.h, (size_t)(cl + cr) * wzs * 8));
-  ITN_TRY(m->hdiag.ensure(c.h, (size_t)std::max<int64_t>(n, 1) * 8));
-  char* dt = static_cast<char*>(m->dtab.p);
-  double* Ld = m->envd.d();
-  double* Rd = Ld + (size_t)cl * wzs;
-  ITN_HIP(c.h, hipMemcpyAsync(dt, keep.data(), bytes, hipMemcpyHostToDevice, c.s));
-  ITN_HIP(c.h, hipMemsetAsync(Ld, 0, (size_t)(cl + cr) * wzs * 8, c.s));
-  ITN_HIP(c.h, env_diag_gather(L.d(), reinterpret_cast<const EnvDiagItem*>(dt + o_li), (int)li.size(), wzs,
-                               Ld, c.s));
-  ITN_HIP(c.h, env_diag_gather(R.d(), reinterpret_cast<const EnvDiagItem*>(dt + o_ri), (int)ri.size(), wzs,
-                               Rd, c.s));
-  ITN_HIP(c.h, qn_heff_diag(Ld, Rd, reinterpret_cast<const double*>(dt), wzs, d,
-                            reinterpret_cast<const DiagBlock*>(dt + o_db), (int)db.size(), (most + 255) / 256,
-                            m->hdiag.d(), c.s));
+  ITN_TRY(heff_diag_build(c.h, L.q, R.q, c.mpo->site(i), c.mpo->site(i + 1), c.mpo->w, psi.q, diag));
+  ITN_TRY(m->dtab.ensure(c.h, diag.device_bytes()));
+  ITN_TRY(m->hdiag.ensure(c.h, (size_t)std::max<int64_t>(psi.q.elems, 1) * 8));
+  ITN_HIP(c.h, heff_diag_launch(diag, L.d(), R.d(), m->dtab.p, m->hdiag.d(), c.s));
   return ITN_OK;
 }
 
@@ -793,7 +819,7 @@ itn_status bond_step(QCtx& c, int i, bool to_right, int maxdim, double cutoff, b
     }
     return ITN_OK;
   };
-  std::vector<char> diag_tables;  // read by the diagonal's launches; alive until the solve's host waits
+  HeffDiag diag_tables;  // read by the diagonal's upload; alive until the solve's host waits
   const double* diag = nullptr;
   if (B > 1) {
     ITN_TRY(qn_diag(c, i, psi, diag_tables));

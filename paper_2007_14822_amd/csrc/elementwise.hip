@@ -464,9 +464,10 @@ hipError_t env_diag_gather(const double* E, const EnvDiagItem* items, int nitems
 
 // Diagonal of the block-sparse two-site H_eff, block by block of psi:
 // D[a, s1, s2, b] = sum_{i, j} Ld[a][i] Wd[i][j][s1][s2] Rd[b][j] over the
-// zero-charge channels i, j (indices global within each space).
+// zero-charge channels i (wzl of them) and j (wzr); indices global within
+// each space.
 __global__ void qn_heff_diag_kernel(const double* __restrict__ Ld, const double* __restrict__ Rd,
-                                    const double* __restrict__ Wd, int wz, int d,
+                                    const double* __restrict__ Wd, int wzl, int wzr, int d1, int d2,
                                     const DiagBlock* __restrict__ blk, int nblk, double* __restrict__ D) {
   for (int k = blockIdx.y; k < nblk; k += gridDim.y) {
     const DiagBlock q = blk[k];
@@ -476,25 +477,25 @@ __global__ void qn_heff_diag_kernel(const double* __restrict__ Ld, const double*
       const int64_t z = t % q.db, r = t / q.db;
       const int64_t y2 = r % q.d2, r2 = r / q.d2;
       const int64_t y1 = r2 % q.d1, x = r2 / q.d1;
-      const double* la = Ld + (q.ga + x) * wz;
-      const double* rb = Rd + (q.gb + z) * wz;
-      const int64_t c = (q.g1 + y1) * d + (q.g2 + y2);
+      const double* la = Ld + (q.ga + x) * wzl;
+      const double* rb = Rd + (q.gb + z) * wzr;
+      const int64_t c = (q.g1 + y1) * d2 + (q.g2 + y2);
       double acc = 0.0;
-      for (int i = 0; i < wz; ++i) {
+      for (int i = 0; i < wzl; ++i) {
         if (la[i] == 0.0) continue;
         double u = 0.0;
-        for (int j = 0; j < wz; ++j) u += Wd[((int64_t)i * wz + j) * d * d + c] * rb[j];
+        for (int j = 0; j < wzr; ++j) u += Wd[((int64_t)i * wzr + j) * d1 * d2 + c] * rb[j];
         acc += la[i] * u;
       }
       D[q.off + t] = acc;
     }
   }
 }
-hipError_t qn_heff_diag(const double* Ld, const double* Rd, const double* Wd, int wz, int d,
+hipError_t qn_heff_diag(const double* Ld, const double* Rd, const double* Wd, int wzl, int wzr, int d1, int d2,
                         const DiagBlock* blocks, int nblk, int64_t chunks, double* D, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
   hipLaunchKernelGGL(qn_heff_diag_kernel, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(chunks, 64)),
-                     std::min(nblk, 65535)), dim3(256), 0, s, Ld, Rd, Wd, wz, d, blocks, nblk, D);
+                     std::min(nblk, 65535)), dim3(256), 0, s, Ld, Rd, Wd, wzl, wzr, d1, d2, blocks, nblk, D);
   return hipGetLastError();
 }
 

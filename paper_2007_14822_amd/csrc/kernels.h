@@ -270,11 +270,12 @@ hipError_t env_diag_gather(const double* E, const EnvDiagItem* items, int nitems
                            hipStream_t s);
 // DiagBlock: one psi block at element offset `off`, extents [da][d1][d2][db],
 // global offsets of its sectors ga, g1, g2, gb.  D = sum_{i,j} Ld[a][i]
-// Wd[i][j][s1][s2] Rd[b][j] (Ld [chi_l][wz], Rd [chi_r][wz], Wd [wz][wz][d][d]).
+// Wd[i][j][s1][s2] Rd[b][j] (Ld [chi_l][wzl], Rd [chi_r][wzr],
+// Wd [wzl][wzr][d1][d2]).
 struct DiagBlock {
   int64_t off, da, d1, d2, db, ga, g1, g2, gb;
 };
-hipError_t qn_heff_diag(const double* Ld, const double* Rd, const double* Wd, int wz, int d,
+hipError_t qn_heff_diag(const double* Ld, const double* Rd, const double* Wd, int wzl, int wzr, int d1, int d2,
                         const DiagBlock* blocks, int nblk, int64_t chunks, double* D, hipStream_t s);
 // x[i] += eps * (uniform in [-1, 1) from a counter-based hash of (seed, i)).
 hipError_t add_noise(double* x, int64_t n, double eps, uint64_t seed, hipStream_t s);

@@ -115,5 +115,29 @@ inline std::vector<std::vector<int32_t>> allowed_blocks(const QTensor& t,
   return out;
 }
 
+// Diagonal of the two-site block-sparse H_eff (the block Davidson
+// preconditioner), psi's block layout.  An entry pairs L[a, m0, a] with
+// R[b, m2, b]: the environments' flux rule leaves only their blocks whose two
+// link sectors coincide, all on zero-charge MPO channels, whose diagonals
+// are gathered into dense [chi][zero-charge channels] tables; Wd[i][j][s1][s2]
+// = sum_m1 W1[m0, m1, s1, s1] W2[m1, m2, s2, s2] over those channels.
+// heff_diag_build lays out the host tables (integer and FP64 host work);
+// heff_diag_launch uploads them to `dev` (device_bytes() of device memory,
+// 256-byte aligned) on stream s and launches; the host tables must stay alive
+// until the stream has passed the upload.
+struct HeffDiag {
+  std::vector<char> host;  // Wd, the two environment item lists, psi's block list
+  size_t o_li = 0, o_ri = 0, o_db = 0;
+  int nli = 0, nri = 0, ndb = 0, wzl = 1, wzr = 1, d1 = 0, d2 = 0;
+  int64_t cl = 0, cr = 0, most = 0;
+  size_t device_bytes() const { return round256(host.size()) + (size_t)(cl * wzl + cr * wzr) * 8; }
+};
+// W1 [wl][wm][d1][d1], W2 [wm][wr][d2][d2] host FP64 (wl = L's channel total,
+// wr = R's); L [a', m0, a], R [b', m2, b], P [a, s1, s2, b] structures.
+itn_status heff_diag_build(itn_handle* h, const QTensor& L, const QTensor& R, const double* W1,
+                           const double* W2, int wm, const QTensor& P, HeffDiag& out);
+hipError_t heff_diag_launch(const HeffDiag& q, const double* Ldata, const double* Rdata, void* dev, double* D,
+                            hipStream_t s);
+
 }  // namespace qn
 }  // namespace itn

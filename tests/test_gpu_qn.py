@@ -348,3 +348,33 @@ def test_splitblocks_mpo_sectors_parity(h, prec):
     assert link.nsec == Ws[0].shape[0]
     _, _, got = _run(h, ops, Ws[5], Ws[6], prec, 2, [psi, _perturbed(psi, 3)])
     assert rel_err(got, _ref(ops, [psi, _perturbed(psi, 3)])) <= TOL[prec]
+
+
+@pytest.mark.parametrize("make", [U.small_u1, U.small_u1u1, U.zn_u1z4, U.small_u1u1z4])
+def test_qn_heff_diag_matches_oracle_unit_vectors(h, make):
+    """itn_qn_heff_diag (block Davidson's preconditioner) equals the diagonal
+    of the oracle's block-sparse H_eff, read off entry by entry by applying
+    it to every unit vector of psi's block layout (brute force), to 1e-12
+    relative; under U(1), U(1) x U(1), U(1) x Z_4 and three-component rules."""
+    ops, W1, W2 = make()[:3]
+    L, w1, w2, R, psi = ops
+    Ld, Rd = _gpu_desc(L, torch.float64), _gpu_desc(R, torch.float64)
+    Pd, _ = U.desc(psi, with_data=False)
+    keys, offs, flat = psi.packed()
+    Od = dict(Pd)
+    Od["data"] = torch.full((flat.size,), float("nan"), dtype=torch.float64, device=DEV)
+    h.qn_heff_diag(Ld, U.mpo_desc(W1, w1), U.mpo_desc(W2, w2), Rd, Od)
+    torch.cuda.synchronize()
+    got = Od["data"].cpu().numpy()
+    ref = np.empty(flat.size)
+    for k, o in zip(keys, offs):
+        shape = psi.blocks[k].shape
+        for j in range(int(np.prod(shape))):
+            e = Q.BlockTensor(psi.inds, psi.flux, {kk: np.zeros(v.shape) for kk, v in psi.blocks.items()})
+            e.blocks[k].flat[j] = 1.0
+            out = Q.heff_apply_blocks(L, w1, w2, R, e).blocks.get(k)
+            ref[o + j] = 0.0 if out is None else out.flat[j]
+    assert np.all(np.isfinite(got))
+    scale = np.abs(ref).max()
+    assert scale > 0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)

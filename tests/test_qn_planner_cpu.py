@@ -264,3 +264,29 @@ def test_psi_missing_one_allowed_block_is_rejected(host, make, drop):
     with pytest.raises(itn.ItnError) as e:
         host.qn_plan(Ld, m1, m2, Rd, bad)
     assert e.value.name == "ITN_E_SHAPE"
+
+
+def test_qn_heff_diag_errors(host):
+    """itn_qn_heff_diag validates like the plan: arrows (ITN_E_ARROW), sectors
+    (ITN_E_SHAPE), and a host-only handle cannot launch (ITN_E_NODEVICE)."""
+    ops, W1, W2 = U.small_u1()
+    L, w1, w2, R, psi = ops
+    Ld, _ = U.desc(L, with_data=False)
+    Rd, _ = U.desc(R, with_data=False)
+    Pd, _ = U.desc(psi, with_data=False)
+    m1, m2 = U.mpo_desc(W1, w1), U.mpo_desc(W2, w2)
+
+    def err(*a):
+        with pytest.raises(itn.ItnError) as e:
+            host.qn_heff_diag(*a)
+        return e.value.name
+
+    bad = copy.deepcopy(Ld)
+    q, d, a = bad["spaces"][2]
+    bad["spaces"][2] = (q, d, +1)
+    assert err(bad, m1, m2, Rd, Pd) == "ITN_E_ARROW"
+    bad = copy.deepcopy(Rd)
+    q, d, a = bad["spaces"][2]
+    bad["spaces"][2] = (q, [x + 1 for x in d], a)
+    assert err(Ld, m1, m2, bad, Pd) in ("ITN_E_SHAPE", "ITN_E_ARG")
+    assert err(Ld, m1, m2, Rd, Pd) == "ITN_E_NODEVICE"
