@@ -714,7 +714,8 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
   // the output blocks of one b' share the segments (m2, b) of R, so their Z
   // blocks stack along the rows of one Z matrix per segment and the product
   // writes its rows to the blocks through a row table.
-  std::map<std::vector<int32_t>, int64_t> zblock;  // (ia', is1', is2', im2, ib) -> Z offset
+  // Z blocks: key (ia', is1', is2', im2, ib) and Z offset; sorted by key after stage 4
+  std::vector<std::pair<std::array<int32_t, 5>, int64_t>> zblock;
   std::map<int, int64_t> rpad;                      // R block -> padded copy offset
   int64_t zacc = 0;
   std::map<int, std::vector<size_t>> by_bp;  // b'-sector -> output blocks (psi order)
@@ -767,7 +768,7 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       zacc += Mtot * ldK;
       for (size_t i = 0; i < obs.size(); ++i) {
         const auto& k = P.blocks[obs[i]];
-        zblock[{k[0], k[1], k[2], sgm.im2, sgm.ib}] = base + rowstart[i] * ldK;
+        zblock.push_back({{k[0], k[1], k[2], sgm.im2, sgm.ib}, base + rowstart[i] * ldK});
       }
       if (!rpad.count(sgm.rb)) {
         // R block [b'][m2][b] -> rows (b', m2) of dbp(b) columns
@@ -847,23 +848,26 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       });
   }
   std::vector<int> in_of((size_t)SM.nsec * S1.nsec * S2.nsec, -1);  // input block per sector triple
-  // lookups: psi's block number per flattened sector quadruple, and the
-  // a-sector with q(a) = q(a') - q(m0) per (a', m0) (-1: none)
-  auto pkey = [&](int ia, int i1, int i2, int ib) {
-    return (((int64_t)ia * S1.nsec + i1) * S2.nsec + i2) * SB.nsec + ib;
+  // lookups: psi's blocks per (a, b) sector pair as (s1, s2, block) in
+  // ascending (s1, s2) order (psi's block list is sorted); the a-sector with
+  // q(a) = q(a') - q(m0) per (a', m0) (-1: none); X group per (a, m0)
+  struct PB {
+    int i1, i2, b;
   };
-  std::unordered_map<int64_t, int> pblk;
-  pblk.reserve(P.blocks.size() * 2);
+  std::unordered_map<int64_t, std::vector<PB>> pab;
   for (size_t b = 0; b < P.blocks.size(); ++b) {
     const auto& k = P.blocks[b];
-    pblk[pkey(k[0], k[1], k[2], k[3])] = (int)b;
+    pab[(int64_t)k[0] * SB.nsec + k[3]].push_back(PB{k[1], k[2], (int)b});
   }
+  std::vector<std::pair<int64_t, int>> xg_of((size_t)SA.nsec * SM.nsec, {0, -1});  // (X offset, a'-sector)
+  for (const auto& kv : xgroup) xg_of[(size_t)kv.first.first * SM.nsec + kv.first.second] = kv.second;
   std::vector<int> ia_of((size_t)SA.nsec * SM.nsec);
   for (int iap = 0; iap < SA.nsec; ++iap)
     for (int im0 = 0; im0 < SM.nsec; ++im0)
       ia_of[(size_t)iap * SM.nsec + im0] = SA.find(qadd(SA.q(iap), SM.q(im0), qmod, -1));
-  std::map<std::pair<int, int>, std::vector<std::vector<int32_t>>> pairs;
-  for (auto& kv : zblock) pairs[{kv.first[0], kv.first[4]}].push_back(kv.first);
+  std::sort(zblock.begin(), zblock.end());  // keys are unique
+  std::map<std::pair<int, int>, std::vector<size_t>> pairs;  // (a', b) -> Z blocks, in key order
+  for (size_t z = 0; z < zblock.size(); ++z) pairs[{zblock[z].first[0], zblock[z].first[4]}].push_back(z);
   for (auto& kv : pairs) {
     const int iap = kv.first.first, ib = kv.first.second;
     QnWPair wpair{};
@@ -882,20 +886,18 @@ itn_status build_plan(itn_handle* h, const itn_tensor* Lt, const itn_tensor* W1t
       // X group (ia, im0) with q(a) = q(a') - q(m0)
       const int ia = ia_of[(size_t)iap * SM.nsec + im0];
       if (ia < 0) continue;
-      auto xg = xgroup.find({ia, im0});
-      if (xg == xgroup.end() || xg->second.second != iap) continue;
-      for (int i1 = 0; i1 < S1.nsec; ++i1)
-        for (int i2 = 0; i2 < S2.nsec; ++i2) {
-          const auto pb = pblk.find(pkey(ia, i1, i2, ib));
-          if (pb == pblk.end()) continue;
-          inputs.push_back({im0, ia, i1, i2, xg->second.first, colbase[pb->second]});
-        }
+      const auto& xg = xg_of[(size_t)ia * SM.nsec + im0];
+      if (xg.second != iap) continue;
+      const auto pl_ab = pab.find((int64_t)ia * SB.nsec + ib);
+      if (pl_ab == pab.end()) continue;
+      for (const PB& pb : pl_ab->second) inputs.push_back({im0, ia, pb.i1, pb.i2, xg.first, colbase[pb.b]});
     }
     for (size_t k = 0; k < inputs.size(); ++k)
       in_of[((size_t)inputs[k].im0 * S1.nsec + inputs[k].i1) * S2.nsec + inputs[k].i2] = (int)k;
-    for (auto& zk : kv.second) {
+    for (size_t zi : kv.second) {
+      const auto& zk = zblock[zi].first;
       const int i1p = zk[1], i2p = zk[2], im2 = zk[3];
-      const int64_t zoff = zblock[zk];
+      const int64_t zoff = zblock[zi].second;
       const int64_t ds1p = S1.dim[i1p], ds2p = S2.dim[i2p], dm2 = SM2.dim[im2];
       const int64_t ldZ = dm2 * dbw;
       for (int s1l = 0; s1l < ds1p; ++s1l)
